@@ -1,0 +1,260 @@
+"""Python face of the CPU oracle (test infrastructure only).
+
+Thin ctypes marshalling around ``ppcg_oracle.c`` plus the few steps that are
+plain library calls (a symmetric tridiagonal eigensolve for the Lanczos
+bounds).  Arrays are numpy float64 / int64 / int32 on the host.
+
+Only tests, the smoke check and the CPU-baseline leg of the benchmark may use
+this module; the GPU library never does.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import time
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ppcg_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+OK, NOT_CONVERGED, BREAKDOWN, ERR_ARG = 0, 1, 2, -1
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no FMA contraction, no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+               "-shared", "-o", _LIB + ".tmp", _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = C.CDLL(_LIB)
+        P = C.c_void_p
+        L.orc_dot.restype = C.c_double
+        L.orc_dot.argtypes = [C.c_int64, P, P]
+        L.orc_csr_matvec.argtypes = [C.c_int64, P, P, P, P, P]
+        L.orc_op_apply.argtypes = [P, P, P]
+        L.orc_op_diag.argtypes = [P, P]
+        L.orc_cheb_coeffs.restype = C.c_int
+        L.orc_cheb_coeffs.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, P, P, P, P]
+        L.orc_cheb_apply.restype = C.c_int
+        L.orc_cheb_apply.argtypes = [P, C.c_int, C.c_double, C.c_double, C.c_double, P, P, P]
+        L.orc_newton_apply.restype = C.c_int
+        L.orc_newton_apply.argtypes = [P, C.c_int, C.c_double, C.c_double, C.c_double, P, P]
+        L.orc_pcg.restype = C.c_int
+        L.orc_pcg.argtypes = [P, C.c_int, C.c_double, C.c_double, C.c_double, P, P, C.c_double,
+                              C.c_int, P]
+        L.orc_lanczos.restype = C.c_int
+        L.orc_lanczos.argtypes = [P, C.c_int, P, P]
+        L.orc_fmix32_start.argtypes = [C.c_int64, P]
+        _lib = L
+    return _lib
+
+
+class _OpStruct(C.Structure):
+    _fields_ = [
+        ("kind", C.c_int32), ("pad0", C.c_int32), ("n", C.c_int64),
+        ("arp", C.c_void_p), ("aci", C.c_void_p), ("av", C.c_void_p),
+        ("nt", C.c_int64), ("crp", C.c_void_p), ("cci", C.c_void_p), ("cv", C.c_void_p),
+        ("m", C.c_void_p), ("dis", C.c_void_p), ("work_n", C.c_void_p), ("work_nt", C.c_void_p),
+        ("n_apply", C.c_int64),
+    ]
+
+
+class _PcgStats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("relres", C.c_double),
+                ("n_apply", C.c_int64), ("n_dot", C.c_int64)]
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class Operator:
+    """A CSR matrix or the Schur-shaped operator A_ff + C^T M^{-1} C.
+
+    ``a`` is any object with ``rowptr``, ``col``, ``val`` (CSR, n x n); for the
+    Schur shape pass ``c`` (nt x n CSR) and ``m`` (nt).  With ``jacobi`` the
+    operator seen by every routine is D^{-1/2} op D^{-1/2}, D = diag(op)
+    (section 3 with W = D^{-1/2}; section 4.2 for the Schur case).
+    """
+
+    def __init__(self, a, c=None, m=None, jacobi: bool = False):
+        self.n = int(len(a.rowptr) - 1)
+        self._arp = np.ascontiguousarray(a.rowptr, dtype=np.int64)
+        self._aci = np.ascontiguousarray(a.col, dtype=np.int32)
+        self._av = _f64(a.val)
+        self.kind = 0 if c is None else 1
+        self._work_n = np.zeros(self.n)
+        s = _OpStruct()
+        s.kind = self.kind
+        s.n = self.n
+        s.arp, s.aci, s.av = _p(self._arp), _p(self._aci), _p(self._av)
+        s.work_n = _p(self._work_n)
+        if c is not None:
+            self.nt = int(len(c.rowptr) - 1)
+            self._crp = np.ascontiguousarray(c.rowptr, dtype=np.int64)
+            self._cci = np.ascontiguousarray(c.col, dtype=np.int32)
+            self._cv = _f64(c.val)
+            self._m = _f64(m)
+            self._work_nt = np.zeros(self.nt)
+            s.nt = self.nt
+            s.crp, s.cci, s.cv = _p(self._crp), _p(self._cci), _p(self._cv)
+            s.m, s.work_nt = _p(self._m), _p(self._work_nt)
+        else:
+            self.nt = 0
+        self._s = s
+        self.jacobi = bool(jacobi)
+        self.dis = None
+        if jacobi:
+            d = self.diag_raw()
+            if not np.all(d > 0):
+                raise ValueError("Jacobi scaling needs a positive diagonal")
+            self.dis = 1.0 / np.sqrt(d)
+            s.dis = _p(self.dis)
+
+    @property
+    def n_apply(self) -> int:
+        return int(self._s.n_apply)
+
+    def reset_count(self):
+        self._s.n_apply = 0
+
+    def diag_raw(self) -> np.ndarray:
+        """diag(op) of the unscaled operator."""
+        d = np.zeros(self.n)
+        lib().orc_op_diag(C.byref(self._s), _p(d))
+        return d
+
+    def apply(self, x) -> np.ndarray:
+        """op-hat x (scaled when jacobi)."""
+        x = _f64(x)
+        y = np.empty(self.n)
+        lib().orc_op_apply(C.byref(self._s), _p(x), _p(y))
+        return y
+
+    def apply_raw(self, x) -> np.ndarray:
+        """op x, unscaled, whatever the jacobi flag."""
+        saved = self._s.dis
+        self._s.dis = None
+        try:
+            return self.apply(x)
+        finally:
+            self._s.dis = saved
+
+
+def csr_matvec(a, x) -> np.ndarray:
+    x = _f64(x)
+    n = len(a.rowptr) - 1
+    y = np.empty(n)
+    rp = np.ascontiguousarray(a.rowptr, dtype=np.int64)
+    ci = np.ascontiguousarray(a.col, dtype=np.int32)
+    v = _f64(a.val)
+    lib().orc_csr_matvec(n, _p(rp), _p(ci), _p(v), _p(x), _p(y))
+    return y
+
+
+def cheb_coeffs(k: int, lmin: float, lmax: float, xi: float):
+    """(theta_bar, delta, sigma, rho[0..k]) of the xi-modified Chebyshev polynomial."""
+    rho = np.zeros(k + 1)
+    th, de, si = C.c_double(), C.c_double(), C.c_double()
+    st = lib().orc_cheb_coeffs(k, lmin, lmax, xi, C.byref(th), C.byref(de), C.byref(si), _p(rho))
+    if st != OK:
+        raise ValueError("invalid polynomial parameters")
+    return th.value, de.value, si.value, rho
+
+
+def cheb_apply_hat(op: Operator, k: int, lmin: float, lmax: float, xi: float, r) -> np.ndarray:
+    """p_k(op-hat) r by Algorithm 2 (scaled space when op.jacobi)."""
+    r = _f64(r)
+    z = np.empty(op.n)
+    work = np.empty(3 * op.n)
+    st = lib().orc_cheb_apply(C.byref(op._s), k, lmin, lmax, xi, _p(r), _p(z), _p(work))
+    if st != OK:
+        raise ValueError("invalid polynomial parameters")
+    return z
+
+
+def cheb_apply(op: Operator, k: int, lmin: float, lmax: float, xi: float, r) -> np.ndarray:
+    """Effective preconditioner applied to r: D^{-1/2} p_k(op-hat) D^{-1/2} r (or p_k(op) r)."""
+    r = _f64(r)
+    if op.dis is None:
+        return cheb_apply_hat(op, k, lmin, lmax, xi, r)
+    return op.dis * cheb_apply_hat(op, k, lmin, lmax, xi, op.dis * r)
+
+
+def newton_apply_hat(op: Operator, nlev: int, lmin: float, lmax: float, xi: float, r) -> np.ndarray:
+    """P_nlev r by Algorithm 1 (degree 2^nlev - 1), scaled space when op.jacobi."""
+    r = _f64(r)
+    z = np.empty(op.n)
+    st = lib().orc_newton_apply(C.byref(op._s), nlev, lmin, lmax, xi, _p(r), _p(z))
+    if st != OK:
+        raise ValueError("invalid polynomial parameters")
+    return z
+
+
+def pcg(op: Operator, k: int, lmin: float, lmax: float, xi: float, b, x0=None, tol: float = 1e-8,
+        maxit: int = 1000):
+    """CG on op x = b preconditioned by p_k; returns (x, stats)."""
+    b = _f64(b)
+    x = np.zeros(op.n) if x0 is None else _f64(x0).copy()
+    st = _PcgStats()
+    t0 = time.perf_counter()
+    ret = lib().orc_pcg(C.byref(op._s), k, lmin, lmax, xi, _p(b), _p(x), tol, maxit, C.byref(st))
+    dt = time.perf_counter() - t0
+    if ret == ERR_ARG:
+        raise ValueError("invalid PCG arguments")
+    return x, dict(iters=int(st.iters), status=int(st.status), relres=float(st.relres),
+                   n_apply=int(st.n_apply), n_dot=int(st.n_dot), seconds=dt)
+
+
+def fmix32_start(n: int) -> np.ndarray:
+    v = np.empty(n)
+    lib().orc_fmix32_start(n, _p(v))
+    return v
+
+
+def lanczos(op: Operator, m: int = 20):
+    """alpha_1..alpha_j, beta_1..beta_j of j <= m Lanczos steps on op-hat."""
+    a = np.zeros(m)
+    b = np.zeros(m)
+    done = lib().orc_lanczos(C.byref(op._s), m, _p(a), _p(b))
+    return a[:done], b[:done]
+
+
+def lanczos_bounds(op: Operator, m: int = 20):
+    """Spectral bounds for the polynomial from m Lanczos steps.
+
+    lambda_min = smallest Ritz value; lambda_max = largest Ritz value plus the
+    Ritz residual |beta_m s_{m,max}| (s = eigenvector of T_m for the largest
+    Ritz value), which makes lambda_max an upper bound of the closest
+    eigenvalue of op-hat.
+    """
+    from scipy.linalg import eigh_tridiagonal
+
+    a, b = lanczos(op, m)
+    j = len(a)
+    if j == 1:
+        w = a.copy()
+        s = np.ones((1, 1))
+    else:
+        w, s = eigh_tridiagonal(a, b[: j - 1])
+    pad = abs(b[j - 1] * s[j - 1, -1])
+    return float(w[0]), float(w[-1] + pad)

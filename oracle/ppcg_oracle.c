@@ -1,0 +1,412 @@
+/*
+ * CPU oracle for polynomial-preconditioned Conjugate Gradient.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, FP64 reference that
+ * the GPU library is checked against.  Only the tests, the smoke check and the
+ * CPU-baseline leg of the benchmark load it; the GPU library never does, and
+ * the two share no code.  Everything here is written for a reader to compare
+ * by eye with the paper: plain loops, left-to-right sums, no blocking, no
+ * fusion, no threads.  Build with -ffp-contract=off so that no FMA changes the
+ * rounding of the printed formulas.
+ *
+ * Paper: Bergamaschi, Ferronato, Isotton, Janna, Martinez, "Parallel
+ * matrix-free polynomial preconditioners with application to flow simulations
+ * in discrete fracture networks" (arXiv 2208.01339).
+ *
+ * Contents and the passage each follows:
+ *   orc_op_apply     y = A x for a CSR matrix, or for the Schur-shaped
+ *                    operator y = A_ff x + C^T (M^{-1} (C x)) (the
+ *                    G - W^T M^{-1} Z pattern of section 4.1, eq. (schur),
+ *                    with a diagonal middle block), optionally symmetrically
+ *                    scaled by D^{-1/2} (section 3, W = D^{-1/2}; section 4.2).
+ *   orc_op_diag      diag of that operator without forming it (the analogue
+ *                    of Algorithm 4 for the Schur shape).
+ *   orc_cheb_coeffs  theta-bar, delta, sigma and rho_j: section 2.2 eqs.
+ *                    (polycheb)/(rhocheb) with theta replaced by
+ *                    theta-bar = (beta+alpha)/2 (1+xi), eq. (thetamod).
+ *   orc_cheb_apply   z = p_k(A) r, Algorithm 2.
+ *   orc_newton_apply z = P_nlev r, Algorithm 1 (degree 2^nlev - 1).
+ *   orc_pcg          CG preconditioned by p_k(A), standard Hestenes-Stiefel
+ *                    loop; counts operator applications and dot products as
+ *                    reported in Table tab11.
+ *   orc_lanczos      plain Lanczos tridiagonalisation (no
+ *                    reorthogonalisation) used to estimate the extremal
+ *                    eigenvalues alpha, beta that section 2 assumes known.
+ *   orc_fmix32_start Lanczos start vector from the MurmurHash3 32-bit
+ *                    finaliser of the row index.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    int32_t kind;          /* 0 = CSR matrix, 1 = Schur-shaped operator          */
+    int32_t pad0;
+    int64_t n;             /* order of the operator                              */
+    const int64_t *arp;    /* A (or A_ff): CSR row pointers, n + 1               */
+    const int32_t *aci;    /* A: column indices                                  */
+    const double *av;      /* A: values                                          */
+    int64_t nt;            /* Schur: rows of C (trace cell pairs)                */
+    const int64_t *crp;    /* Schur: C row pointers, nt + 1                      */
+    const int32_t *cci;    /* Schur: C column indices (cells)                    */
+    const double *cv;      /* Schur: C values                                    */
+    const double *m;       /* Schur: diagonal of M, nt                           */
+    const double *dis;     /* D^{-1/2} for symmetric scaling, or NULL            */
+    double *work_n;        /* scratch, n doubles                                 */
+    double *work_nt;       /* scratch, nt doubles (Schur only)                   */
+    int64_t n_apply;       /* operator applications performed (counter)          */
+} orc_op;
+
+enum { ORC_OK = 0, ORC_NOT_CONVERGED = 1, ORC_BREAKDOWN = 2, ORC_ERR_ARG = -1 };
+
+/* ------------------------------------------------------------------------ */
+/* vectors                                                                   */
+/* ------------------------------------------------------------------------ */
+
+double orc_dot(int64_t n, const double *x, const double *y)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s += x[i] * y[i];
+    return s;
+}
+
+/* ------------------------------------------------------------------------ */
+/* operators                                                                 */
+/* ------------------------------------------------------------------------ */
+
+/* y = A x for a CSR matrix. */
+void orc_csr_matvec(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
+                    const double *x, double *y)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p) s += v[p] * x[ci[p]];
+        y[i] = s;
+    }
+}
+
+/* y = op x (unscaled).  Schur: y = A_ff x + C^T (M^{-1} (C x)). */
+static void op_apply_raw(const orc_op *op, const double *x, double *y)
+{
+    orc_csr_matvec(op->n, op->arp, op->aci, op->av, x, y);
+    if (op->kind == 1) {
+        double *w = op->work_nt;
+        /* w = C x */
+        orc_csr_matvec(op->nt, op->crp, op->cci, op->cv, x, w);
+        /* w = M^{-1} w */
+        for (int64_t t = 0; t < op->nt; ++t) w[t] = w[t] / op->m[t];
+        /* y += C^T w, one row of C at a time */
+        for (int64_t t = 0; t < op->nt; ++t)
+            for (int64_t p = op->crp[t]; p < op->crp[t + 1]; ++p)
+                y[op->cci[p]] += op->cv[p] * w[t];
+    }
+}
+
+/* y = op-hat x, with op-hat = D^{-1/2} op D^{-1/2} when dis is set. */
+void orc_op_apply(orc_op *op, const double *x, double *y)
+{
+    op->n_apply += 1;
+    if (op->dis == NULL) {
+        op_apply_raw(op, x, y);
+        return;
+    }
+    double *t = op->work_n;
+    for (int64_t i = 0; i < op->n; ++i) t[i] = op->dis[i] * x[i];
+    op_apply_raw(op, t, y);
+    for (int64_t i = 0; i < op->n; ++i) y[i] = op->dis[i] * y[i];
+}
+
+/* d = diag(op), unscaled.  CSR: a_ii.  Schur: (A_ff)_ii + sum_t C_ti^2 / M_t. */
+void orc_op_diag(const orc_op *op, double *d)
+{
+    for (int64_t i = 0; i < op->n; ++i) {
+        double s = 0.0;
+        for (int64_t p = op->arp[i]; p < op->arp[i + 1]; ++p)
+            if (op->aci[p] == i) s += op->av[p];
+        d[i] = s;
+    }
+    if (op->kind == 1) {
+        for (int64_t t = 0; t < op->nt; ++t)
+            for (int64_t p = op->crp[t]; p < op->crp[t + 1]; ++p)
+                d[op->cci[p]] += op->cv[p] * op->cv[p] / op->m[t];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Chebyshev polynomial preconditioner                                       */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * theta-bar = (lmax + lmin)/2 * (1 + xi)   (eq. thetamod: xi moves the centre)
+ * delta     = (lmax - lmin)/2              (unchanged by xi)
+ * sigma     = theta-bar / delta
+ * rho_0 = 1/sigma, rho_j = 1/(2 sigma - rho_{j-1})   (eq. rhocheb)
+ * rho must have room for k + 1 entries (k >= 0).
+ */
+int orc_cheb_coeffs(int k, double lmin, double lmax, double xi,
+                    double *theta_bar, double *delta, double *sigma, double *rho)
+{
+    if (k < 0 || !(lmin > 0.0) || !(lmax > lmin) || !(xi >= 0.0)) return ORC_ERR_ARG;
+    double th = (lmax + lmin) / 2.0 * (1.0 + xi);
+    double de = (lmax - lmin) / 2.0;
+    double si = th / de;
+    *theta_bar = th;
+    *delta = de;
+    *sigma = si;
+    rho[0] = 1.0 / si;
+    for (int j = 1; j <= k; ++j) rho[j] = 1.0 / (2.0 * si - rho[j - 1]);
+    return ORC_OK;
+}
+
+/*
+ * z = p_k(op-hat) r by Algorithm 2: k operator applications.
+ *   x_old = r / theta
+ *   x     = (2 rho_1 / delta) (2 r - A r / theta)
+ *   for j = 2..k:  t = (2/delta)(r - A x);  r_hat = rho_j (2 sigma x - rho_{j-1} x_old + t)
+ *                  x_old = x;  x = r_hat
+ * work must hold 3 n doubles.
+ */
+int orc_cheb_apply(orc_op *op, int k, double lmin, double lmax, double xi,
+                   const double *r, double *z, double *work)
+{
+    int64_t n = op->n;
+    double th, de, si;
+    double *rho = (double *)malloc(sizeof(double) * (size_t)(k + 1));
+    if (!rho) return ORC_ERR_ARG;
+    int st = orc_cheb_coeffs(k, lmin, lmax, xi, &th, &de, &si, rho);
+    if (st != ORC_OK) { free(rho); return st; }
+    if (k == 0) {
+        for (int64_t i = 0; i < n; ++i) z[i] = r[i] / th;
+        free(rho);
+        return ORC_OK;
+    }
+    double *xold = work, *x = work + n, *ax = work + 2 * n;
+    for (int64_t i = 0; i < n; ++i) xold[i] = r[i] / th;
+    orc_op_apply(op, r, ax);
+    for (int64_t i = 0; i < n; ++i) x[i] = (2.0 * rho[1] / de) * (2.0 * r[i] - ax[i] / th);
+    for (int j = 2; j <= k; ++j) {
+        orc_op_apply(op, x, ax);
+        for (int64_t i = 0; i < n; ++i) {
+            double t = (2.0 / de) * (r[i] - ax[i]);
+            double rh = rho[j] * (2.0 * si * x[i] - rho[j - 1] * xold[i] + t);
+            xold[i] = x[i];
+            x[i] = rh;
+        }
+    }
+    memcpy(z, x, sizeof(double) * (size_t)n);
+    free(rho);
+    return ORC_OK;
+}
+
+/*
+ * Algorithm 1 (Newton form), applied recursively:
+ *   P_0 r = zeta_0 r,   P_{j+1} r = zeta_{j+1} (2 P_j r - P_j A P_j r).
+ * zeta_0 = 1/theta-bar (= 2/(alpha+beta) when xi = 0);
+ * zeta_1 = 2 / (1 + 2 a zeta_0 - (a zeta_0)^2) with a the left end of the
+ * interval [theta-bar - delta, theta-bar + delta] (a = alpha when xi = 0);
+ * zeta_i = 2 / (1 + 2 zeta_{i-1} - zeta_{i-1}^2), i >= 2  (eq. zetaNewt).
+ */
+static void newton_level(orc_op *op, int j, const double *zeta, const double *r, double *out,
+                         double *ws)
+{
+    int64_t n = op->n;
+    if (j == 0) {
+        for (int64_t i = 0; i < n; ++i) out[i] = zeta[0] * r[i];
+        return;
+    }
+    double *u = ws, *au = ws + n, *pau = ws + 2 * n, *next = ws + 3 * n;
+    newton_level(op, j - 1, zeta, r, u, next);
+    orc_op_apply(op, u, au);
+    newton_level(op, j - 1, zeta, au, pau, next);
+    for (int64_t i = 0; i < n; ++i) out[i] = zeta[j] * (2.0 * u[i] - pau[i]);
+}
+
+int orc_newton_apply(orc_op *op, int nlev, double lmin, double lmax, double xi,
+                     const double *r, double *z)
+{
+    if (nlev < 0 || nlev > 20 || !(lmin > 0.0) || !(lmax > lmin) || !(xi >= 0.0)) return ORC_ERR_ARG;
+    double th = (lmax + lmin) / 2.0 * (1.0 + xi);
+    double de = (lmax - lmin) / 2.0;
+    double a = th - de;
+    double zeta[21];
+    zeta[0] = 1.0 / th;
+    if (nlev >= 1) {
+        double az = a * zeta[0];
+        zeta[1] = 2.0 / (1.0 + 2.0 * az - az * az);
+    }
+    for (int i = 2; i <= nlev; ++i) zeta[i] = 2.0 / (1.0 + 2.0 * zeta[i - 1] - zeta[i - 1] * zeta[i - 1]);
+    double *ws = (double *)malloc(sizeof(double) * (size_t)op->n * (size_t)(3 * nlev + 1));
+    if (!ws) return ORC_ERR_ARG;
+    newton_level(op, nlev, zeta, r, z, ws);
+    free(ws);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* PCG                                                                       */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t iters;
+    int32_t status;
+    double relres;      /* ||r_hat|| / ||b_hat|| of the recursive residual */
+    int64_t n_apply;    /* operator applications, preconditioner included  */
+    int64_t n_dot;      /* dot products, excluding ||b_hat||              */
+} orc_pcg_stats;
+
+/*
+ * Solve op x = b by CG preconditioned with p_k(op-hat) (op-hat = scaled op when
+ * op->dis is set: the system solved is D^{-1/2} A D^{-1/2} x_hat = D^{-1/2} b,
+ * x = D^{-1/2} x_hat; the tolerance applies to ||r_hat|| / ||b_hat||).
+ * On entry x holds x0; on exit the last iterate.
+ *
+ *   r = b - A x0;  z = P r;  p = z;  rho = r.z
+ *   for it = 1..maxit:
+ *     q = A p;  gamma = p.q;  alpha = rho / gamma
+ *     x += alpha p;  r -= alpha q
+ *     if ||r|| <= tol ||b|| : converged after it iterations
+ *     z = P r;  rho' = r.z;  beta = rho' / rho;  p = z + beta p;  rho = rho'
+ */
+int orc_pcg(orc_op *op, int k, double lmin, double lmax, double xi, const double *b, double *x,
+            double tol, int maxit, orc_pcg_stats *st)
+{
+    int64_t n = op->n;
+    memset(st, 0, sizeof(*st));
+    double *bh = (double *)malloc(sizeof(double) * (size_t)n * 9);
+    if (!bh) return ORC_ERR_ARG;
+    double *xh = bh + n, *r = bh + 2 * n, *z = bh + 3 * n, *p = bh + 4 * n, *q = bh + 5 * n;
+    double *cw = bh + 6 * n;
+    int64_t apply0 = op->n_apply;
+    int ret = ORC_OK;
+
+    int x0_zero = 1;
+    for (int64_t i = 0; i < n; ++i) {
+        double di = op->dis ? op->dis[i] : 1.0;
+        bh[i] = di * b[i];
+        xh[i] = x[i] / di;
+        if (x[i] != 0.0) x0_zero = 0;
+    }
+    double bnorm = sqrt(orc_dot(n, bh, bh));
+    if (bnorm == 0.0) {
+        for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+        st->status = ORC_OK;
+        free(bh);
+        return ORC_OK;
+    }
+    if (x0_zero) {
+        memcpy(r, bh, sizeof(double) * (size_t)n);
+    } else {
+        orc_op_apply(op, xh, q);
+        for (int64_t i = 0; i < n; ++i) r[i] = bh[i] - q[i];
+        double rr0 = orc_dot(n, r, r);
+        if (sqrt(rr0) <= tol * bnorm) {
+            st->relres = sqrt(rr0) / bnorm;
+            goto done;
+        }
+    }
+    ret = orc_cheb_apply(op, k, lmin, lmax, xi, r, z, cw);
+    if (ret != ORC_OK) goto done;
+    double rho = orc_dot(n, r, z);
+    st->n_dot += 1;
+    if (!(rho > 0.0) || !isfinite(rho)) { ret = ORC_BREAKDOWN; goto done; }
+    memcpy(p, z, sizeof(double) * (size_t)n);
+    double rr = 0.0;
+    ret = ORC_NOT_CONVERGED;
+    for (int it = 1; it <= maxit; ++it) {
+        orc_op_apply(op, p, q);
+        double gamma = orc_dot(n, p, q);
+        st->n_dot += 1;
+        if (!(gamma > 0.0) || !isfinite(gamma)) { ret = ORC_BREAKDOWN; break; }
+        double alpha = rho / gamma;
+        for (int64_t i = 0; i < n; ++i) {
+            xh[i] = xh[i] + alpha * p[i];
+            r[i] = r[i] - alpha * q[i];
+        }
+        st->iters = it;
+        rr = orc_dot(n, r, r);
+        st->n_dot += 1;
+        st->relres = sqrt(rr) / bnorm;
+        if (!isfinite(rr)) { ret = ORC_BREAKDOWN; break; }
+        if (sqrt(rr) <= tol * bnorm) { ret = ORC_OK; break; }
+        if (it == maxit) { ret = ORC_NOT_CONVERGED; break; }
+        orc_cheb_apply(op, k, lmin, lmax, xi, r, z, cw);
+        double rho_new = orc_dot(n, r, z);
+        st->n_dot += 1;
+        if (!(rho_new > 0.0) || !isfinite(rho_new)) { ret = ORC_BREAKDOWN; break; }
+        double beta = rho_new / rho;
+        for (int64_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+        rho = rho_new;
+    }
+done:
+    for (int64_t i = 0; i < n; ++i) {
+        double di = op->dis ? op->dis[i] : 1.0;
+        x[i] = di * xh[i];
+    }
+    st->status = ret;
+    st->n_apply = op->n_apply - apply0;
+    free(bh);
+    return ret;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Lanczos                                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* MurmurHash3 32-bit finaliser (fmix32). */
+static uint32_t fmix32(uint32_t h)
+{
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+
+/* v_i = fmix32(i) / 2^32 - 0.5, i = 0..n-1 (0-based row index, low 32 bits). */
+void orc_fmix32_start(int64_t n, double *v)
+{
+    for (int64_t i = 0; i < n; ++i) v[i] = (double)fmix32((uint32_t)i) / 4294967296.0 - 0.5;
+}
+
+/*
+ * m steps of Lanczos on op-hat from the fmix32 start vector, no
+ * reorthogonalisation:
+ *   v_1 = v / ||v||,  beta_0 v_0 = 0
+ *   w = A v_j - beta_{j-1} v_{j-1};  alpha_j = v_j.w;  w -= alpha_j v_j
+ *   beta_j = ||w||;  v_{j+1} = w / beta_j
+ * Outputs alpha_1..alpha_m and beta_1..beta_m (beta_m couples T_m to the
+ * next Lanczos vector).  Returns the number of steps done (< m on an exact
+ * invariant subspace, beta_j == 0).
+ */
+int orc_lanczos(orc_op *op, int m, double *alpha, double *beta)
+{
+    int64_t n = op->n;
+    double *v = (double *)malloc(sizeof(double) * (size_t)n * 3);
+    if (!v) return -1;
+    double *vprev = v + n, *w = v + 2 * n;
+    orc_fmix32_start(n, v);
+    double nv = sqrt(orc_dot(n, v, v));
+    for (int64_t i = 0; i < n; ++i) { v[i] = v[i] / nv; vprev[i] = 0.0; }
+    double bprev = 0.0;
+    int done = 0;
+    for (int j = 0; j < m; ++j) {
+        orc_op_apply(op, v, w);
+        for (int64_t i = 0; i < n; ++i) w[i] = w[i] - bprev * vprev[i];
+        double a = orc_dot(n, v, w);
+        for (int64_t i = 0; i < n; ++i) w[i] = w[i] - a * v[i];
+        double b = sqrt(orc_dot(n, w, w));
+        alpha[j] = a;
+        beta[j] = b;
+        done = j + 1;
+        if (b == 0.0) break;
+        for (int64_t i = 0; i < n; ++i) {
+            vprev[i] = v[i];
+            v[i] = w[i] / b;
+        }
+        bprev = b;
+    }
+    free(v);
+    return done;
+}
