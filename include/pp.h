@@ -1,0 +1,184 @@
+/*
+ * pp.h -- polynomial-preconditioned Conjugate Gradient on one MI355X (gfx950).
+ *
+ * Method: Bergamaschi, Ferronato, Isotton, Janna, Martinez, "Parallel
+ * matrix-free polynomial preconditioners with application to flow simulations
+ * in discrete fracture networks" (arXiv 2208.01339).
+ *
+ * CG (section 1) is preconditioned by P = p_k(A), the optimal Chebyshev
+ * polynomial of degree k on [lambda_min, lambda_max] with the centre of the
+ * interval moved by the scaling parameter xi (section 2.2, eqs. polycheb and
+ * rhocheb; section 2.4, eq. thetamod).  P is applied matrix-free by the
+ * three-term recurrence of Algorithm 2: k operator applications and a few
+ * vector updates, no dot product.  The operator is either a CSR matrix or the
+ * never-assembled Schur-shaped operator S = A_ff + C^T M^{-1} C of section 4.1
+ * (eq. schur, with a diagonal middle block).  Optional symmetric Jacobi
+ * scaling D^{-1/2} A D^{-1/2} is the diagonal seed preconditioner of
+ * section 3 (W = D^{-1/2}) and section 4.2.
+ *
+ * Conventions for every entry point:
+ *  - Array arguments are DEVICE pointers (hipMalloc'ed or torch CUDA tensors)
+ *    unless marked "host".  The library never frees caller memory.
+ *  - create copies (and re-lays out) what it needs during the call; the
+ *    caller may free its arrays once create returns.
+ *  - All GPU work of a handle is queued on the stream given at create
+ *    (NULL = the legacy default stream).  pcg_solve, pp_estimate_bounds and
+ *    create synchronise that stream before returning; pp_apply and
+ *    pp_operator_apply return with the work queued.
+ *  - A handle is not thread-safe; distinct handles are independent.
+ *  - No C++ exception crosses this interface; errors are status codes, and
+ *    pp_last_error() gives a message for the last failing call on the calling
+ *    thread.
+ *  - Vectors passed to pp_apply / pcg_solve must hold n doubles; this cannot
+ *    be checked.  Input and output vectors must not alias.
+ */
+#ifndef PP_H
+#define PP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define PP_API __attribute__((visibility("default")))
+#else
+#define PP_API
+#endif
+
+typedef struct pp_op_s *pp_op;
+
+typedef enum {
+    PP_OK = 0,            /* success / converged                                   */
+    PP_NOT_CONVERGED = 1, /* maxit iterations done without reaching tol            */
+    PP_BREAKDOWN = 2,     /* p.Ap <= 0, r.z <= 0 or a non-finite scalar in CG      */
+    PP_ERR_ARG = -1,      /* invalid argument (null pointer, size, bounds, flags)  */
+    PP_ERR_OOM = -2,      /* device allocation failed                              */
+    PP_ERR_HIP = -3,      /* a HIP runtime call failed                             */
+    PP_ERR_STATE = -4     /* call out of order (apply/solve before pp_setup)       */
+} pp_status;
+
+/* create flags */
+enum {
+    PP_JACOBI = 1u, /* iterate on D^{-1/2} A D^{-1/2}, D = diag(A) (section 3, 4.2)        */
+    PP_MIXED = 2u   /* p_k(A)v in FP32 (values, vectors, accumulation); CG stays FP64     */
+};
+
+/*
+ * Create an operator from a CSR matrix A (n x n, symmetric positive definite).
+ *   rowptr  [n+1] int64, rowptr[0] = 0, non-decreasing, rowptr[n] = nnz
+ *   colind  [nnz] int32 in [0, n)
+ *   val     [nnz] double
+ * With PP_JACOBI the diagonal must be positive (PP_ERR_ARG otherwise).
+ * n >= 1, nnz >= 1, nnz < 2^31 per slice layout limits are checked.
+ */
+PP_API pp_status pp_create_csr(pp_op *out, int64_t n, int64_t nnz, const int64_t *rowptr,
+                        const int32_t *colind, const double *val, unsigned flags, void *stream);
+
+/*
+ * Create the Schur-shaped operator S = A_ff + C^T diag(m)^{-1} C (section 4.1,
+ * eq. schur; Algorithm 3 applies the paper's S_u the same way, matrix-free).
+ *   A_ff    n x n CSR (a_rowptr [n+1] int64, a_col [nnz_a] int32, a_val [nnz_a])
+ *   C       nt x n CSR (c_rowptr [nt+1] int64, c_col [nnz_c] int32, c_val [nnz_c])
+ *   m_diag  [nt] double, all > 0
+ * S is never formed.  With PP_JACOBI, D = diag(S) is computed in closed form
+ * as (A_ff)_ii + sum_t C_ti^2 / m_t (the analogue of Algorithm 4).
+ */
+PP_API pp_status pp_create_schur(pp_op *out, int64_t n, int64_t nnz_a, const int64_t *a_rowptr,
+                          const int32_t *a_col, const double *a_val, int64_t nt, int64_t nnz_c,
+                          const int64_t *c_rowptr, const int32_t *c_col, const double *c_val,
+                          const double *m_diag, unsigned flags, void *stream);
+
+/*
+ * Fix the polynomial (section 2.2 and eq. thetamod of section 2.4):
+ *   theta-bar = (lambda_max + lambda_min)/2 * (1 + scaling),
+ *   delta = (lambda_max - lambda_min)/2, sigma = theta-bar/delta,
+ *   rho_0 = 1/sigma, rho_j = 1/(2 sigma - rho_{j-1}).
+ * k = degree = operator applications per preconditioner application,
+ * 0 <= k <= 4096.  Bounds refer to the (Jacobi-scaled, if PP_JACOBI) operator;
+ * require 0 < lambda_min < lambda_max, both finite, scaling >= 0 finite.
+ * Host-only computation; may be called again to change the polynomial.
+ */
+PP_API pp_status pp_setup(pp_op op, int k, double lambda_min, double lambda_max, double scaling);
+
+/*
+ * z = P r by Algorithm 2 (k operator applications, no dot product).
+ * With PP_JACOBI: z = D^{-1/2} p_k(D^{-1/2} A D^{-1/2}) D^{-1/2} r, the
+ * effective preconditioner of A.  With PP_MIXED the recurrence runs in FP32.
+ * r, z: [n] double, must not alias.  Asynchronous on the handle's stream.
+ */
+PP_API pp_status pp_apply(pp_op op, const double *r, double *z);
+
+/*
+ * Solve A x = b by CG preconditioned with P (standard Hestenes-Stiefel loop:
+ * q = A p, alpha = rho / p.q, x += alpha p, r -= alpha q, convergence test,
+ * z = P r, rho' = r.z, beta = rho'/rho, p = z + beta p; three dot products
+ * per iteration, as counted in Table tab11).
+ *   b      [n] double (device)
+ *   x      [n] double (device): x0 on entry, last iterate on exit
+ *   tol    stop when ||r_hat|| <= tol ||b_hat|| (scaled system under PP_JACOBI,
+ *          as in section 4.2); tol >= 0 (0 = run maxit iterations)
+ *   maxit  >= 0
+ *   iters, relres  host outputs (may be NULL): iterations done and the final
+ *          recursive relative residual ||r_hat|| / ||b_hat||
+ * Returns PP_OK, PP_NOT_CONVERGED (iters = maxit) or PP_BREAKDOWN (x holds
+ * the last iterate).  b = 0 gives x = 0, iters = 0, PP_OK.  Synchronises.
+ */
+PP_API pp_status pcg_solve(pp_op op, const double *b, double *x, double tol, int maxit, int *iters,
+                    double *relres);
+
+/*
+ * Estimate lambda_min, lambda_max of the (scaled) operator with `steps`
+ * Lanczos steps (1..64) from the start vector v_i = fmix32(i)/2^32 - 0.5
+ * (MurmurHash3 finaliser of the row index), no reorthogonalisation:
+ * lambda_min = smallest Ritz value, lambda_max = largest Ritz value + its
+ * Ritz residual.  The paper obtains these bounds with DACG (section 6.1);
+ * any estimate of the extremal eigenvalues serves.  Host outputs; synchronises.
+ */
+PP_API pp_status pp_estimate_bounds(pp_op op, int steps, double *lambda_min, double *lambda_max);
+
+/*
+ * y = A x with the UNSCALED operator (CSR SpMV, or A_ff x + C^T (M^{-1}(C x))
+ * for the Schur shape, Algorithm 3's role).  x, y: [n] double, no aliasing.
+ */
+PP_API pp_status pp_operator_apply(pp_op op, const double *x, double *y);
+
+/* Statistics of the last pcg_solve / pp_apply on this handle (host struct). */
+typedef struct {
+    int32_t iters;          /* CG iterations of the last solve                      */
+    int32_t status;         /* pp_status of the last solve                          */
+    double relres;          /* recursive ||r_hat|| / ||b_hat||                       */
+    int64_t op_applies;     /* operator applications in the last solve              */
+    int64_t dots;           /* dot products (global reductions), excluding ||b||    */
+    double cheb_ms;         /* summed device time of the polynomial steps (events), */
+                            /* valid only with PP_OPT_TIMING = 1                    */
+    int64_t cheb_steps;     /* polynomial steps covered by cheb_ms                  */
+    double solve_ms;        /* device time of the whole solve (events)             */
+    int64_t n;              /* operator order                                       */
+    int64_t nnz_stored;     /* matrix entries held in the slice layout (padded)     */
+    int64_t nnz_matrix;     /* entries of the CSR / A_ff + C^T parts given          */
+    int32_t driver;         /* 0 = stream-driven kernels, 1 = persistent kernel     */
+    int32_t grid;           /* workgroups per launch used                           */
+} pp_stats;
+
+PP_API pp_status pp_get_stats(pp_op op, pp_stats *st);
+
+/* Tunables (pp_set_option keys). */
+enum {
+    PP_OPT_GRID = 1,        /* workgroups per launch (multiple of 8 preferred), 0 = auto   */
+    PP_OPT_CHUNK = 2,       /* CG iterations queued between host convergence checks       */
+    PP_OPT_TIMING = 3,      /* 1 = record events around the polynomial steps              */
+    PP_OPT_DRIVER = 4,      /* 0 = stream-driven, 1 = persistent cooperative kernel, -1 = auto */
+    PP_OPT_NT_LOADS = 5     /* 1 = non-temporal loads for the matrix stream                */
+};
+PP_API pp_status pp_set_option(pp_op op, int key, int64_t value);
+
+PP_API void pp_destroy(pp_op op);
+PP_API const char *pp_status_str(pp_status s);
+PP_API const char *pp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PP_H */

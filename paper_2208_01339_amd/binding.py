@@ -1,0 +1,235 @@
+"""ctypes binding of include/pp.h (argument marshalling only).
+
+Every function keeps the C name and forwards to libppcg.so; device arrays are
+torch CUDA tensors, streams are torch streams.  All computation happens in the
+HIP kernels of the library: if it is not built or cannot be loaded, every call
+raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libppcg.so")
+
+PP_OK, PP_NOT_CONVERGED, PP_BREAKDOWN = 0, 1, 2
+PP_ERR_ARG, PP_ERR_OOM, PP_ERR_HIP, PP_ERR_STATE = -1, -2, -3, -4
+PP_JACOBI, PP_MIXED = 1, 2
+PP_OPT_GRID, PP_OPT_CHUNK, PP_OPT_TIMING, PP_OPT_DRIVER, PP_OPT_NT_LOADS = 1, 2, 3, 4, 5
+
+ABI_FUNCTIONS = (
+    "pp_create_csr", "pp_create_schur", "pp_setup", "pp_apply", "pcg_solve", "pp_estimate_bounds",
+    "pp_operator_apply", "pp_get_stats", "pp_set_option", "pp_destroy", "pp_status_str",
+    "pp_last_error",
+)
+
+
+class PPError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (_status_name(status), msg))
+        self.status = status
+
+
+class pp_stats(C.Structure):
+    _fields_ = [
+        ("iters", C.c_int32), ("status", C.c_int32), ("relres", C.c_double),
+        ("op_applies", C.c_int64), ("dots", C.c_int64), ("cheb_ms", C.c_double),
+        ("cheb_steps", C.c_int64), ("solve_ms", C.c_double), ("n", C.c_int64),
+        ("nnz_stored", C.c_int64), ("nnz_matrix", C.c_int64), ("driver", C.c_int32),
+        ("grid", C.c_int32),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load libppcg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libppcg.so is not built; run __graft_entry__.build() "
+                               "(python -m paper_2208_01339_amd.build)")
+        L = C.CDLL(LIB_PATH)
+        P, I64, I32, D = C.c_void_p, C.c_int64, C.c_int, C.c_double
+        L.pp_create_csr.argtypes = [C.POINTER(P), I64, I64, P, P, P, C.c_uint, P]
+        L.pp_create_schur.argtypes = [C.POINTER(P), I64, I64, P, P, P, I64, I64, P, P, P, P, C.c_uint, P]
+        L.pp_setup.argtypes = [P, I32, D, D, D]
+        L.pp_apply.argtypes = [P, P, P]
+        L.pcg_solve.argtypes = [P, P, P, D, I32, C.POINTER(I32), C.POINTER(D)]
+        L.pp_estimate_bounds.argtypes = [P, I32, C.POINTER(D), C.POINTER(D)]
+        L.pp_operator_apply.argtypes = [P, P, P]
+        L.pp_get_stats.argtypes = [P, C.POINTER(pp_stats)]
+        L.pp_set_option.argtypes = [P, I32, I64]
+        L.pp_destroy.argtypes = [P]
+        L.pp_destroy.restype = None
+        L.pp_status_str.argtypes = [I32]
+        L.pp_status_str.restype = C.c_char_p
+        L.pp_last_error.argtypes = []
+        L.pp_last_error.restype = C.c_char_p
+        for f in ABI_FUNCTIONS:
+            if f not in ("pp_destroy", "pp_status_str", "pp_last_error"):
+                getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _status_name(s: int) -> str:
+    try:
+        return lib().pp_status_str(s).decode()
+    except Exception:  # pragma: no cover - only while reporting another error
+        return str(s)
+
+
+def _check(s: int, ok=(PP_OK,)) -> int:
+    if s not in ok:
+        raise PPError(s, lib().pp_last_error().decode())
+    return s
+
+
+def _ptr(t):
+    """Device pointer of a contiguous torch CUDA tensor (or None -> NULL)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device (CUDA/HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dtype_check(t, dt, name):
+    if t.dtype != dt:
+        raise ValueError("%s must be %s" % (name, dt))
+
+
+# ---------------------------------------------------------------------------
+# the C ABI, one wrapper per function
+# ---------------------------------------------------------------------------
+
+def pp_create_csr(n, nnz, rowptr, colind, val, flags=0, stream=None):
+    import torch
+
+    _dtype_check(rowptr, torch.int64, "rowptr")
+    _dtype_check(colind, torch.int32, "colind")
+    _dtype_check(val, torch.float64, "val")
+    h = C.c_void_p()
+    _check(lib().pp_create_csr(C.byref(h), int(n), int(nnz), _ptr(rowptr), _ptr(colind), _ptr(val),
+                               int(flags), _stream(stream)))
+    return h
+
+
+def pp_create_schur(n, nnz_a, a_rowptr, a_col, a_val, nt, nnz_c, c_rowptr, c_col, c_val, m_diag,
+                    flags=0, stream=None):
+    import torch
+
+    for t, dt, nm in ((a_rowptr, torch.int64, "a_rowptr"), (a_col, torch.int32, "a_col"),
+                      (a_val, torch.float64, "a_val"), (c_rowptr, torch.int64, "c_rowptr"),
+                      (c_col, torch.int32, "c_col"), (c_val, torch.float64, "c_val"),
+                      (m_diag, torch.float64, "m_diag")):
+        _dtype_check(t, dt, nm)
+    h = C.c_void_p()
+    _check(lib().pp_create_schur(C.byref(h), int(n), int(nnz_a), _ptr(a_rowptr), _ptr(a_col),
+                                 _ptr(a_val), int(nt), int(nnz_c), _ptr(c_rowptr), _ptr(c_col),
+                                 _ptr(c_val), _ptr(m_diag), int(flags), _stream(stream)))
+    return h
+
+
+def pp_setup(op, k, lambda_min, lambda_max, scaling=0.0):
+    return _check(lib().pp_setup(op, int(k), float(lambda_min), float(lambda_max), float(scaling)))
+
+
+def pp_apply(op, r, z):
+    return _check(lib().pp_apply(op, _ptr(r), _ptr(z)))
+
+
+def pcg_solve(op, b, x, tol=1e-8, maxit=1000):
+    """Returns (status, iters, relres); raises on argument/HIP errors only."""
+    it = C.c_int(0)
+    rel = C.c_double(0.0)
+    s = lib().pcg_solve(op, _ptr(b), _ptr(x), float(tol), int(maxit), C.byref(it), C.byref(rel))
+    _check(s, ok=(PP_OK, PP_NOT_CONVERGED, PP_BREAKDOWN))
+    return s, it.value, rel.value
+
+
+def pp_estimate_bounds(op, steps=20):
+    lo, hi = C.c_double(), C.c_double()
+    _check(lib().pp_estimate_bounds(op, int(steps), C.byref(lo), C.byref(hi)))
+    return lo.value, hi.value
+
+
+def pp_operator_apply(op, x, y):
+    return _check(lib().pp_operator_apply(op, _ptr(x), _ptr(y)))
+
+
+def pp_get_stats(op):
+    st = pp_stats()
+    _check(lib().pp_get_stats(op, C.byref(st)))
+    return {f: getattr(st, f) for f, _ in pp_stats._fields_}
+
+
+def pp_set_option(op, key, value):
+    return _check(lib().pp_set_option(op, int(key), int(value)))
+
+
+def pp_destroy(op):
+    if op:
+        lib().pp_destroy(op)
+
+
+def pp_status_str(s):
+    return lib().pp_status_str(int(s)).decode()
+
+
+def pp_last_error():
+    return lib().pp_last_error().decode()
+
+
+# ---------------------------------------------------------------------------
+# convenience: upload host CSR / Schur parts and own the handle
+# ---------------------------------------------------------------------------
+
+class Operator:
+    """Owns a pp_op built from host CSR arrays (or Schur parts) uploaded to ``device``."""
+
+    def __init__(self, a=None, schur=None, flags=0, device="cuda:0", stream=None):
+        import torch
+
+        self.device = torch.device(device)
+        dev = self.device
+
+        def up(x, dt):
+            return torch.from_numpy(x).to(device=dev, dtype=dt).contiguous()
+
+        if schur is not None:
+            s = schur
+            self.n = s.a.n_rows
+            self.handle = pp_create_schur(
+                s.a.n_rows, s.a.nnz, up(s.a.rowptr, torch.int64), up(s.a.col, torch.int32),
+                up(s.a.val, torch.float64), s.c.n_rows, s.c.nnz, up(s.c.rowptr, torch.int64),
+                up(s.c.col, torch.int32), up(s.c.val, torch.float64), up(s.m, torch.float64), flags,
+                stream)
+        else:
+            self.n = a.n_rows
+            self.handle = pp_create_csr(a.n_rows, a.nnz, up(a.rowptr, torch.int64),
+                                        up(a.col, torch.int32), up(a.val, torch.float64), flags,
+                                        stream)
+
+    def close(self):
+        if self.handle:
+            pp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

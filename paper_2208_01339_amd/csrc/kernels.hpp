@@ -1,0 +1,747 @@
+// Device code for polynomial-preconditioned CG on gfx950 (CDNA4).
+//
+// Layout.  The operator lives in a wavefront-row-group ("sliced ELLPACK")
+// layout: rows are grouped in slices of 64 (one wavefront, one lane per row);
+// inside a slice the j-th stored entry of all 64 rows is contiguous, so every
+// load of values and column indices is a fully coalesced 512 B (FP64) or
+// 256 B (int32 / FP32) wave access.  A slice is padded to its longest row
+// with (col = own row, val = 0).  For the Schur shape the trace term C^T w is
+// appended to the rows as extra columns n + t that index the trace vector w.
+//
+// Scheduling.  Every streaming kernel runs a fixed grid of G workgroups of
+// 256 threads.  Workgroup b runs on XCD b % 8; it is remapped so that the G/8
+// workgroups of one XCD cover one contiguous eighth of the rows, and each
+// workgroup owns a contiguous range of slices (its four waves interleave over
+// it).  Neighbouring rows of a stencil-like operator are then gathered from
+// the same XCD's L2.
+//
+// Reductions are deterministic: a fixed-order wave shuffle tree, a fixed
+// order over the waves of a workgroup, one partial per workgroup, and the
+// last workgroup to finish (agent-scope ticket) sums the G partials in index
+// order and applies the CG scalar logic on the device.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ppk {
+
+constexpr int WAVE = 64;
+constexpr int BLOCK = 256;
+constexpr int WPB = BLOCK / WAVE;  // waves per workgroup
+constexpr int LZ_MAX = 64;         // max Lanczos steps
+
+// Device-resident solver state: CG scalars live here, never on the host.
+struct State {
+    double rho;      // r.z of the current iteration
+    double alpha;    // rho / p.q
+    double beta;     // rho' / rho
+    double gamma;    // p.q
+    double rr;       // r.r after the update
+    double bnorm2;   // b_hat.b_hat
+    double tol2;     // tol^2 * bnorm2, set once bnorm2 is known
+    double tol;      // requested relative tolerance
+    double lz_alpha[LZ_MAX];
+    double lz_beta[LZ_MAX];
+    double scratch[4];
+    int32_t it;      // iterations done
+    int32_t maxit;
+    int32_t done;    // 1 once converged / failed / maxit: later kernels return at entry
+    int32_t status;  // pp_status
+    int32_t zero_b;  // b_hat == 0 -> x = 0
+    int32_t pad;
+    uint32_t ticket; // last-workgroup ticket, always 0 between kernels
+    uint32_t pad2;
+};
+
+enum Fin : int {
+    FIN_NONE = 0,
+    FIN_BNORM,       // bnorm2 = sum; zero b -> done
+    FIN_RR0,         // initial residual check
+    FIN_RHO0,        // rho = r.z (before the first iteration)
+    FIN_GAMMA,       // gamma = p.q, alpha = rho/gamma
+    FIN_RR,          // rr = r.r, it++, convergence / maxit
+    FIN_RHO,         // rho' = r.z, beta = rho'/rho, rho = rho'
+    FIN_LZ_NORM0,    // scratch[0] = sqrt(sum) (start vector norm)
+    FIN_LZ_ALPHA,    // lz_alpha[idx] = sum
+    FIN_LZ_BETA      // lz_beta[idx] = sqrt(sum)
+};
+
+struct SellView {
+    const int64_t *sp;   // [nslices + 1] element offset of each slice (multiple of 64)
+    const int32_t *col;  // [sp[nslices]]
+    const void *val;     // [sp[nslices]] double or float
+    int64_t n;           // rows
+    int64_t nslices;
+    int64_t nx;          // columns < nx index x; columns >= nx index w[col - nx]
+};
+
+struct CsrView {         // plain CSR (trace operator M^{-1} C)
+    const int64_t *rp;
+    const int32_t *col;
+    const void *val;
+    int64_t rows;
+};
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int xcd_remap(int b, int G)
+{
+    const int q = G >> 3, r = G & 7, x = b & 7, i = b >> 3;
+    return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+__device__ __forceinline__ void block_range(int64_t total, int L, int G, int64_t &lo, int64_t &hi)
+{
+    lo = total * (int64_t)L / G;
+    hi = total * (int64_t)(L + 1) / G;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, WAVE);
+    return v;
+}
+
+// Sum over the workgroup; result valid in thread 0.  Fixed order.
+__device__ __forceinline__ double block_sum(double v, double *lds)
+{
+    v = wave_sum(v);
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+    if (lane == 0) lds[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < WPB; ++i) s += lds[i];
+    }
+    __syncthreads();
+    return s;
+}
+
+__device__ __forceinline__ bool finite_pos(double v) { return v > 0.0 && v < INFINITY; }
+
+// CG scalar logic, run by thread 0 of the last workgroup of a reduction.
+__device__ inline void finalize(State *st, int fin, int idx, double s)
+{
+    switch (fin) {
+    case FIN_BNORM:
+        st->bnorm2 = s;
+        st->tol2 = st->tol * st->tol * s;
+        if (!(s < INFINITY)) { st->done = 1; st->status = 2; }
+        else if (s == 0.0) { st->done = 1; st->status = 0; st->zero_b = 1; }
+        break;
+    case FIN_RR0:
+        st->rr = s;
+        if (!(s < INFINITY)) { st->done = 1; st->status = 2; }
+        else if (s <= st->tol2) { st->done = 1; st->status = 0; }
+        else if (st->maxit <= 0) { st->done = 1; st->status = 1; }
+        break;
+    case FIN_RHO0:
+        st->rho = s;
+        if (!finite_pos(s)) { st->done = 1; st->status = 2; }
+        break;
+    case FIN_GAMMA:
+        st->gamma = s;
+        if (!finite_pos(s)) { st->done = 1; st->status = 2; }
+        else st->alpha = st->rho / s;
+        break;
+    case FIN_RR:
+        st->rr = s;
+        st->it += 1;
+        if (!(s < INFINITY)) { st->done = 1; st->status = 2; }
+        else if (s <= st->tol2) { st->done = 1; st->status = 0; }
+        else if (st->it >= st->maxit) { st->done = 1; st->status = 1; }
+        break;
+    case FIN_RHO: {
+        if (!finite_pos(s)) { st->done = 1; st->status = 2; break; }
+        st->beta = s / st->rho;
+        st->rho = s;
+        break;
+    }
+    case FIN_LZ_NORM0: st->scratch[0] = sqrt(s); break;
+    case FIN_LZ_ALPHA: st->lz_alpha[idx] = s; break;
+    case FIN_LZ_BETA: st->lz_beta[idx] = sqrt(s); break;
+    default: break;
+    }
+}
+
+// Publish this workgroup's partial; the last workgroup reduces all partials in
+// index order and runs finalize().  Every thread of the workgroup must call it.
+__device__ inline void commit_partial(double part, double *partials, State *st, int fin, int idx,
+                                      int L, int G)
+{
+    __shared__ double lds[WPB];
+    __shared__ int last;
+    double s = block_sum(part, lds);
+    if (threadIdx.x == 0) {
+        __hip_atomic_store(&partials[L], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t t = __hip_atomic_fetch_add(&st->ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        last = (t == (uint32_t)(G - 1));
+    }
+    __syncthreads();
+    if (!last) return;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < G; i += BLOCK)
+        acc += __hip_atomic_load(&partials[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    double tot = block_sum(acc, lds);
+    if (threadIdx.x == 0) {
+        finalize(st, fin, idx, tot);
+        __hip_atomic_store(&st->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T ldm(const T *p, bool nt)
+{
+    return nt ? __builtin_nontemporal_load(p) : *p;
+}
+
+// (A x)_row for one lane of a slice.  Columns >= nx read the trace vector w.
+template <typename T, typename XT, bool SCHUR>
+__device__ __forceinline__ T sell_row(const SellView &A, const XT *__restrict__ x,
+                                      const T *__restrict__ w, int64_t slice, int lane, bool nt)
+{
+    const int64_t base = A.sp[slice];
+    const int width = (int)((A.sp[slice + 1] - base) >> 6);
+    const int32_t *c = A.col + base + lane;
+    const T *v = (const T *)A.val + base + lane;
+    T acc = (T)0;
+#pragma unroll 8
+    for (int j = 0; j < width; ++j) {
+        const int cj = ldm(c + (int64_t)j * WAVE, nt);
+        const T vj = ldm(v + (int64_t)j * WAVE, nt);
+        T xj;
+        if (SCHUR) xj = (cj < A.nx) ? (T)x[cj] : w[cj - A.nx];
+        else xj = (T)x[cj];
+        acc += vj * xj;
+    }
+    return acc;
+}
+
+// Iterate the rows owned by logical workgroup L: fn(row, slice, lane).
+template <typename F>
+__device__ __forceinline__ void for_my_slices(int64_t nslices, int L, int G, F fn)
+{
+    int64_t s0, s1;
+    block_range(nslices, L, G, s0, s1);
+    const int w = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+    for (int64_t s = s0 + w; s < s1; s += WPB) fn(s * WAVE + lane, s, lane);
+}
+
+template <typename F>
+__device__ __forceinline__ void for_my_elems(int64_t n, int L, int G, F fn)
+{
+    int64_t e0, e1;
+    block_range(n, L, G, e0, e1);
+    for (int64_t i = e0 + threadIdx.x; i < e1; i += BLOCK) fn(i);
+}
+
+#define PPK_PROLOGUE(st)                                  \
+    if (st != nullptr && st->done) return;                \
+    const int G = (int)gridDim.x;                         \
+    const int L = xcd_remap((int)blockIdx.x, G);
+
+// ---------------------------------------------------------------------------
+// operator kernels
+// ---------------------------------------------------------------------------
+
+// w_t = sum_p cm_tp x[col_p]  (trace phase of the Schur operator: M^{-1} C x,
+// with 1/m_t and the Jacobi column scaling folded into cm).  One thread per
+// trace row; rows are short (two entries).
+template <typename T, typename XT>
+__global__ __launch_bounds__(BLOCK) void k_trace(CsrView Cm, const XT *__restrict__ x,
+                                                 T *__restrict__ w, const State *st)
+{
+    PPK_PROLOGUE(st)
+    for_my_elems(Cm.rows, L, G, [&](int64_t t) {
+        T acc = (T)0;
+        const T *v = (const T *)Cm.val;
+        for (int64_t p = Cm.rp[t]; p < Cm.rp[t + 1]; ++p) acc += v[p] * (T)x[Cm.col[p]];
+        w[t] = acc;
+    });
+}
+
+// y = A x (plain SpMV in the slice layout).
+template <typename T, bool SCHUR>
+__global__ __launch_bounds__(BLOCK) void k_spmv(SellView A, const T *__restrict__ x,
+                                                const T *__restrict__ w, T *__restrict__ y, int nt)
+{
+    const int G = (int)gridDim.x;
+    const int L = xcd_remap((int)blockIdx.x, G);
+    for_my_slices(A.nslices, L, G, [&](int64_t row, int64_t s, int lane) {
+        T a = sell_row<T, T, SCHUR>(A, x, w, s, lane, nt != 0);
+        if (row < A.n) y[row] = a;
+    });
+}
+
+// One step of Algorithm 2, fused with the operator application:
+//   out = ax * x_i + aold * sold_i + ar * r_i + aA * (A x)_i
+// MODE 1 (first step):  x = r gathered, coefficients (0, 0, 4 rho1/delta, -2 rho1/(delta theta))
+// MODE 2 (second step): x = s_1, s_0 = r/theta folded into ar
+// MODE 3 (j >= 3):      x = s_{j-1}, sold = s_{j-2}
+// DOT: also reduce r.out (r read as RT, exact double product) -> FIN_RHO/FIN_RHO0.
+// SCALE: out *= dis_i (pp_apply with Jacobi returns D^{-1/2} s_k).
+// out may alias sold (each thread reads sold_i before writing out_i).
+template <typename T, typename XT, typename RT, typename OT, int MODE, bool SCHUR, bool DOT, bool SCALE>
+__global__ __launch_bounds__(BLOCK) void k_cheb(SellView A, const XT *__restrict__ xg,
+                                                const T *__restrict__ w, const RT *__restrict__ r,
+                                                const T *sold, OT *out, double cx, double cold,
+                                                double cr, double cA, const double *__restrict__ dis,
+                                                double *partials, State *st, int fin, int nt)
+{
+    PPK_PROLOGUE(st)
+    const T ax = (T)cx, aold = (T)cold, ar = (T)cr, aA = (T)cA;
+    double part = 0.0;
+    for_my_slices(A.nslices, L, G, [&](int64_t row, int64_t s, int lane) {
+        T a = sell_row<T, XT, SCHUR>(A, xg, w, s, lane, nt != 0);
+        if (row < A.n) {
+            const RT ri = r[row];
+            T o = aA * a + ar * (T)ri;
+            if (MODE >= 2) o += ax * (T)xg[row];
+            if (MODE == 3) o += aold * sold[row];
+            OT ov = (OT)o;
+            if (SCALE) ov = (OT)((double)ov * dis[row]);
+            out[row] = ov;
+            if (DOT) part += (double)ri * (double)ov;
+        }
+    });
+    if (DOT) commit_partial(part, partials, st, fin, 0, L, G);
+}
+
+// ---------------------------------------------------------------------------
+// CG kernels
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(BLOCK) void k_state_init(State *st, double tol, int maxit)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->rho = st->alpha = st->beta = st->gamma = st->rr = st->bnorm2 = st->tol2 = 0.0;
+        st->tol = tol;
+        st->it = 0;
+        st->maxit = maxit;
+        st->done = 0;
+        st->status = 1;
+        st->zero_b = 0;
+        st->ticket = 0u;
+    }
+}
+
+// bh = dis .* b, xh = x ./ dis; reduce bh.bh -> FIN_BNORM
+__global__ __launch_bounds__(BLOCK) void k_init_scale(int64_t n, const double *__restrict__ b,
+                                                      const double *__restrict__ x,
+                                                      const double *__restrict__ dis,
+                                                      double *__restrict__ bh, double *__restrict__ xh,
+                                                      double *partials, State *st)
+{
+    PPK_PROLOGUE(st)
+    double part = 0.0;
+    for_my_elems(n, L, G, [&](int64_t i) {
+        const double d = dis ? dis[i] : 1.0;
+        const double bi = d * b[i];
+        bh[i] = bi;
+        xh[i] = x[i] / d;
+        part += bi * bi;
+    });
+    commit_partial(part, partials, st, FIN_BNORM, 0, L, G);
+}
+
+// r = bh - A xh; reduce r.r -> FIN_RR0
+template <bool SCHUR>
+__global__ __launch_bounds__(BLOCK) void k_init_resid(SellView A, const double *__restrict__ xh,
+                                                      const double *__restrict__ w,
+                                                      const double *__restrict__ bh,
+                                                      double *__restrict__ r, double *partials,
+                                                      State *st, int nt)
+{
+    PPK_PROLOGUE(st)
+    double part = 0.0;
+    for_my_slices(A.nslices, L, G, [&](int64_t row, int64_t s, int lane) {
+        double a = sell_row<double, double, SCHUR>(A, xh, w, s, lane, nt != 0);
+        if (row < A.n) {
+            const double ri = bh[row] - a;
+            r[row] = ri;
+            part += ri * ri;
+        }
+    });
+    commit_partial(part, partials, st, FIN_RR0, 0, L, G);
+}
+
+// q = A p; reduce p.q -> FIN_GAMMA
+template <bool SCHUR>
+__global__ __launch_bounds__(BLOCK) void k_pq(SellView A, const double *__restrict__ p,
+                                              const double *__restrict__ w, double *__restrict__ q,
+                                              double *partials, State *st, int nt)
+{
+    PPK_PROLOGUE(st)
+    double part = 0.0;
+    for_my_slices(A.nslices, L, G, [&](int64_t row, int64_t s, int lane) {
+        double a = sell_row<double, double, SCHUR>(A, p, w, s, lane, nt != 0);
+        if (row < A.n) {
+            q[row] = a;
+            part += p[row] * a;
+        }
+    });
+    commit_partial(part, partials, st, FIN_GAMMA, 0, L, G);
+}
+
+// x += alpha p; r -= alpha q; reduce r.r -> FIN_RR
+__global__ __launch_bounds__(BLOCK) void k_xr(int64_t n, const double *__restrict__ p,
+                                              const double *__restrict__ q, double *__restrict__ x,
+                                              double *__restrict__ r, double *partials, State *st)
+{
+    PPK_PROLOGUE(st)
+    const double alpha = st->alpha;
+    double part = 0.0;
+    for_my_elems(n, L, G, [&](int64_t i) {
+        x[i] = x[i] + alpha * p[i];
+        const double ri = r[i] - alpha * q[i];
+        r[i] = ri;
+        part += ri * ri;
+    });
+    commit_partial(part, partials, st, FIN_RR, 0, L, G);
+}
+
+// p = z + beta p   (first=1: p = z)
+__global__ __launch_bounds__(BLOCK) void k_p(int64_t n, const double *__restrict__ z,
+                                             double *__restrict__ p, const State *st, int first)
+{
+    PPK_PROLOGUE(st)
+    const double beta = first ? 0.0 : st->beta;
+    for_my_elems(n, L, G, [&](int64_t i) { p[i] = first ? z[i] : z[i] + beta * p[i]; });
+}
+
+// x = dis .* xh (or 0 when b_hat == 0); runs even when done is set.
+__global__ __launch_bounds__(BLOCK) void k_final_x(int64_t n, const double *__restrict__ xh,
+                                                   const double *__restrict__ dis,
+                                                   double *__restrict__ x, const State *st)
+{
+    const int G = (int)gridDim.x;
+    const int L = xcd_remap((int)blockIdx.x, G);
+    const int zb = st->zero_b;
+    for_my_elems(n, L, G, [&](int64_t i) { x[i] = zb ? 0.0 : (dis ? dis[i] : 1.0) * xh[i]; });
+}
+
+// ---------------------------------------------------------------------------
+// small elementwise kernels
+// ---------------------------------------------------------------------------
+
+// y = s .* x (s may be null = 1), converting type
+template <typename XT, typename YT>
+__global__ __launch_bounds__(BLOCK) void k_scale(int64_t n, const XT *__restrict__ x,
+                                                 const double *__restrict__ s, double c,
+                                                 YT *__restrict__ y)
+{
+    const int G = (int)gridDim.x;
+    const int L = xcd_remap((int)blockIdx.x, G);
+    for_my_elems(n, L, G, [&](int64_t i) {
+        double v = (double)x[i] * c;
+        if (s) v *= s[i];
+        y[i] = (YT)v;
+    });
+}
+
+// y = s .* s .* x * c   (k = 0 preconditioner with Jacobi)
+__global__ __launch_bounds__(BLOCK) void k_scale2(int64_t n, const double *__restrict__ x,
+                                                  const double *__restrict__ s, double c,
+                                                  double *__restrict__ y)
+{
+    const int G = (int)gridDim.x;
+    const int L = xcd_remap((int)blockIdx.x, G);
+    for_my_elems(n, L, G, [&](int64_t i) {
+        const double d = s ? s[i] : 1.0;
+        y[i] = d * (d * (x[i] * c));
+    });
+}
+
+// r.z into the CG state (degree-0 preconditioner: no operator step to fuse into)
+__global__ __launch_bounds__(BLOCK) void k_dot_fin(int64_t n, const double *__restrict__ x,
+                                                   const double *__restrict__ y, double *partials,
+                                                   State *st, int fin)
+{
+    PPK_PROLOGUE(st)
+    double part = 0.0;
+    for_my_elems(n, L, G, [&](int64_t i) { part += x[i] * y[i]; });
+    commit_partial(part, partials, st, fin, 0, L, G);
+}
+
+// y = x ./ d
+__global__ __launch_bounds__(BLOCK) void k_div(int64_t n, const double *__restrict__ x,
+                                               const double *__restrict__ d, double *__restrict__ y)
+{
+    const int G = (int)gridDim.x;
+    const int L = xcd_remap((int)blockIdx.x, G);
+    for_my_elems(n, L, G, [&](int64_t i) { y[i] = x[i] / d[i]; });
+}
+
+// ---------------------------------------------------------------------------
+// Lanczos
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint32_t fmix32(uint32_t h)
+{
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+
+// v_i = fmix32(i) / 2^32 - 0.5 ; reduce v.v -> FIN_LZ_NORM0
+__global__ __launch_bounds__(BLOCK) void k_lz_start(int64_t n, double *__restrict__ v,
+                                                    double *partials, State *st)
+{
+    PPK_PROLOGUE(st)
+    double part = 0.0;
+    for_my_elems(n, L, G, [&](int64_t i) {
+        const double x = (double)fmix32((uint32_t)i) / 4294967296.0 - 0.5;
+        v[i] = x;
+        part += x * x;
+    });
+    commit_partial(part, partials, st, FIN_LZ_NORM0, 0, L, G);
+}
+
+// v /= scratch[0]
+__global__ __launch_bounds__(BLOCK) void k_lz_norm(int64_t n, double *__restrict__ v, const State *st)
+{
+    const int G = (int)gridDim.x;
+    const int L = xcd_remap((int)blockIdx.x, G);
+    const double nv = st->scratch[0];
+    for_my_elems(n, L, G, [&](int64_t i) { v[i] = v[i] / nv; });
+}
+
+// w = A v - beta_{j-1} vprev ; reduce v.w -> lz_alpha[j]
+template <bool SCHUR>
+__global__ __launch_bounds__(BLOCK) void k_lz_apply(SellView A, const double *__restrict__ v,
+                                                    const double *__restrict__ tw,
+                                                    const double *__restrict__ vprev,
+                                                    double *__restrict__ wout, double *partials,
+                                                    State *st, int j, int nt)
+{
+    const int G = (int)gridDim.x;
+    const int L = xcd_remap((int)blockIdx.x, G);
+    const double bp = (j > 0) ? st->lz_beta[j - 1] : 0.0;
+    double part = 0.0;
+    for_my_slices(A.nslices, L, G, [&](int64_t row, int64_t s, int lane) {
+        double a = sell_row<double, double, SCHUR>(A, v, tw, s, lane, nt != 0);
+        if (row < A.n) {
+            const double wi = a - bp * vprev[row];
+            wout[row] = wi;
+            part += v[row] * wi;
+        }
+    });
+    commit_partial(part, partials, st, FIN_LZ_ALPHA, j, L, G);
+}
+
+// w -= alpha_j v ; reduce w.w -> lz_beta[j]
+__global__ __launch_bounds__(BLOCK) void k_lz_orth(int64_t n, const double *__restrict__ v,
+                                                   double *__restrict__ w, double *partials,
+                                                   State *st, int j)
+{
+    const int G = (int)gridDim.x;
+    const int L = xcd_remap((int)blockIdx.x, G);
+    const double a = st->lz_alpha[j];
+    double part = 0.0;
+    for_my_elems(n, L, G, [&](int64_t i) {
+        const double wi = w[i] - a * v[i];
+        w[i] = wi;
+        part += wi * wi;
+    });
+    commit_partial(part, partials, st, FIN_LZ_BETA, j, L, G);
+}
+
+// vprev = v ; v = w / beta_j
+__global__ __launch_bounds__(BLOCK) void k_lz_next(int64_t n, double *__restrict__ vprev,
+                                                   double *__restrict__ v,
+                                                   const double *__restrict__ w, const State *st,
+                                                   int j)
+{
+    const int G = (int)gridDim.x;
+    const int L = xcd_remap((int)blockIdx.x, G);
+    const double b = st->lz_beta[j];
+    for_my_elems(n, L, G, [&](int64_t i) {
+        vprev[i] = v[i];
+        v[i] = w[i] / b;
+    });
+}
+
+// ---------------------------------------------------------------------------
+// setup kernels: diagonal, Jacobi scaling, slice layout
+// ---------------------------------------------------------------------------
+
+// d_i = a_ii + sum over appended trace entries (c_ti^2 / m_t); flag non-positive.
+__global__ __launch_bounds__(BLOCK) void k_diag(int64_t n, const int64_t *__restrict__ rp,
+                                                const int32_t *__restrict__ col,
+                                                const double *__restrict__ val,
+                                                const int64_t *__restrict__ ctp,
+                                                const int32_t *__restrict__ ctt,
+                                                const double *__restrict__ ctv,
+                                                const double *__restrict__ m,
+                                                double *__restrict__ d, double *__restrict__ dis,
+                                                int *bad)
+{
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int64_t p = rp[i]; p < rp[i + 1]; ++p)
+        if (col[p] == i) s += val[p];
+    if (ctp) {
+        for (int64_t p = ctp[i]; p < ctp[i + 1]; ++p) s += ctv[p] * ctv[p] / m[ctt[p]];
+    }
+    d[i] = s;
+    if (!(s > 0.0) || !(s < INFINITY)) {
+        atomicOr(bad, 1);
+        dis[i] = 1.0;
+    } else {
+        dis[i] = 1.0 / sqrt(s);
+    }
+}
+
+// width of each slice = max over its rows of (row length + appended trace entries)
+__global__ __launch_bounds__(BLOCK) void k_slice_width(int64_t n, int64_t nslices,
+                                                       const int64_t *__restrict__ rp,
+                                                       const int64_t *__restrict__ ctp,
+                                                       int64_t *__restrict__ width)
+{
+    const int64_t s = (int64_t)blockIdx.x * WPB + threadIdx.x / WAVE;
+    const int lane = threadIdx.x & (WAVE - 1);
+    if (s >= nslices) return;
+    const int64_t row = s * WAVE + lane;
+    int64_t len = 0;
+    if (row < n) {
+        len = rp[row + 1] - rp[row];
+        if (ctp) len += ctp[row + 1] - ctp[row];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        int64_t o = __shfl_down(len, off, WAVE);
+        len = o > len ? o : len;
+    }
+    if (lane == 0) width[s] = len;
+}
+
+// exclusive scan of width*64 into sp[0..nslices]; one workgroup, fixed order
+__global__ __launch_bounds__(1024) void k_scan_slices(int64_t nslices, const int64_t *__restrict__ width,
+                                                      int64_t *__restrict__ sp)
+{
+    __shared__ int64_t part[1024];
+    const int t = threadIdx.x;
+    const int64_t chunk = (nslices + 1023) / 1024;
+    const int64_t lo = (int64_t)t * chunk;
+    const int64_t hi = lo + chunk < nslices ? lo + chunk : nslices;
+    int64_t s = 0;
+    for (int64_t i = lo; i < hi; ++i) s += width[i] * WAVE;
+    part[t] = s;
+    __syncthreads();
+    if (t == 0) {
+        int64_t acc = 0;
+        for (int i = 0; i < 1024; ++i) {
+            int64_t v = part[i];
+            part[i] = acc;
+            acc += v;
+        }
+    }
+    __syncthreads();
+    int64_t acc = part[t];
+    for (int64_t i = lo; i < hi; ++i) {
+        sp[i] = acc;
+        acc += width[i] * WAVE;
+    }
+    if (hi == nslices && lo < hi) sp[nslices] = acc;
+    if (nslices == 0 && t == 0) sp[0] = 0;
+}
+
+// Fill the slice layout: scaled values a_ij dis_i dis_j, appended trace
+// entries (column nx + t, value c_ti dis_i), padding (own row, 0).
+__global__ __launch_bounds__(BLOCK) void k_slice_fill(int64_t n, int64_t nslices, int64_t nx,
+                                                      const int64_t *__restrict__ rp,
+                                                      const int32_t *__restrict__ col,
+                                                      const double *__restrict__ val,
+                                                      const int64_t *__restrict__ ctp,
+                                                      const int32_t *__restrict__ ctt,
+                                                      const double *__restrict__ ctv,
+                                                      const double *__restrict__ dis,
+                                                      const int64_t *__restrict__ sp,
+                                                      int32_t *__restrict__ scol,
+                                                      double *__restrict__ sval,
+                                                      float *__restrict__ sval32)
+{
+    const int64_t s = (int64_t)blockIdx.x * WPB + threadIdx.x / WAVE;
+    const int lane = threadIdx.x & (WAVE - 1);
+    if (s >= nslices) return;
+    const int64_t row = s * WAVE + lane;
+    const int64_t base = sp[s];
+    const int width = (int)((sp[s + 1] - base) / WAVE);
+    int j = 0;
+    const int32_t self = (int32_t)(row < n ? row : 0);
+    if (row < n) {
+        const double di = dis ? dis[row] : 1.0;
+        for (int64_t p = rp[row]; p < rp[row + 1]; ++p, ++j) {
+            const int32_t c = col[p];
+            const double v = dis ? val[p] * di * dis[c] : val[p];
+            const int64_t o = base + (int64_t)j * WAVE + lane;
+            scol[o] = c;
+            sval[o] = v;
+            if (sval32) sval32[o] = (float)v;
+        }
+        if (ctp) {
+            for (int64_t p = ctp[row]; p < ctp[row + 1]; ++p, ++j) {
+                const double v = ctv[p] * di;
+                const int64_t o = base + (int64_t)j * WAVE + lane;
+                scol[o] = (int32_t)(nx + ctt[p]);
+                sval[o] = v;
+                if (sval32) sval32[o] = (float)v;
+            }
+        }
+    }
+    for (; j < width; ++j) {
+        const int64_t o = base + (int64_t)j * WAVE + lane;
+        scol[o] = self;
+        sval[o] = 0.0;
+        if (sval32) sval32[o] = 0.0f;
+    }
+}
+
+// Trace operator values: cm_tp = c_tp dis_{col} / m_t (and an FP32 copy).
+__global__ __launch_bounds__(BLOCK) void k_trace_fill(int64_t nt, const int64_t *__restrict__ crp,
+                                                      const int32_t *__restrict__ ccol,
+                                                      const double *__restrict__ cval,
+                                                      const double *__restrict__ m,
+                                                      const double *__restrict__ dis,
+                                                      double *__restrict__ cm,
+                                                      float *__restrict__ cm32)
+{
+    const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (t >= nt) return;
+    for (int64_t p = crp[t]; p < crp[t + 1]; ++p) {
+        const double v = cval[p] * (dis ? dis[ccol[p]] : 1.0) / m[t];
+        cm[p] = v;
+        if (cm32) cm32[p] = (float)v;
+    }
+}
+
+// validate CSR structure: monotone row pointers, columns in range
+__global__ __launch_bounds__(BLOCK) void k_check_csr(int64_t rows, int64_t ncols, int64_t nnz,
+                                                     const int64_t *__restrict__ rp,
+                                                     const int32_t *__restrict__ col, int *bad)
+{
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= rows) return;
+    const int64_t a = rp[i], b = rp[i + 1];
+    if (a < 0 || b < a || b > nnz || (i == 0 && a != 0) || (i == rows - 1 && b != nnz)) {
+        atomicOr(bad, 2);
+        return;
+    }
+    for (int64_t p = a; p < b; ++p) {
+        const int32_t c = col[p];
+        if (c < 0 || (int64_t)c >= ncols) {
+            atomicOr(bad, 4);
+            return;
+        }
+    }
+}
+
+}  // namespace ppk

@@ -1,0 +1,870 @@
+// C-ABI implementation of include/pp.h: polynomial-preconditioned CG on one
+// MI355X.  Host code only queues the HIP kernels of kernels.hpp; every step
+// of the solve runs on the device, and CG scalars never leave it until the
+// solve ends.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/pp.h"
+#include "kernels.hpp"
+#include "sym_eig.hpp"
+
+using ppk::BLOCK;
+using ppk::WAVE;
+using ppk::WPB;
+
+namespace {
+
+thread_local std::string g_err;
+
+pp_status fail(pp_status s, const std::string &msg)
+{
+    g_err = msg;
+    return s;
+}
+
+struct HipError {
+    hipError_t e;
+    const char *what;
+    int line;
+};
+
+#define HIPCHK(x)                                             \
+    do {                                                      \
+        hipError_t e_ = (x);                                  \
+        if (e_ != hipSuccess) throw HipError{e_, #x, __LINE__}; \
+    } while (0)
+
+template <typename T>
+T *dalloc(size_t count)
+{
+    if (count == 0) count = 1;
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, count * sizeof(T));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw std::bad_alloc();
+    }
+    return (T *)p;
+}
+
+template <typename T>
+void dfree(T *&p)
+{
+    if (p) (void)hipFree((void *)p);
+    p = nullptr;
+}
+
+constexpr int K_MAX = 4096;
+constexpr int GRID_DEFAULT = 2048;
+
+}  // namespace
+
+struct pp_op_s {
+    int kind = 0;  // 0 CSR, 1 Schur
+    int64_t n = 0, nt = 0, nnz_c = 0, nnz_given = 0;
+    unsigned flags = 0;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    // slice layout of A-hat (and appended trace columns)
+    int64_t nslices = 0, nstored = 0;
+    int64_t *sp = nullptr;
+    int32_t *scol = nullptr;
+    double *sval = nullptr;
+    float *sval32 = nullptr;
+    // trace operator M^{-1} C-hat (Schur)
+    int64_t *crp = nullptr;
+    int32_t *ccol = nullptr;
+    double *cm = nullptr;
+    float *cm32 = nullptr;
+    double *tw = nullptr;
+    float *tw32 = nullptr;
+    // Jacobi
+    double *dis = nullptr;
+    // work vectors
+    double *xh = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr, *bh = nullptr;
+    double *sA = nullptr, *sB = nullptr;
+    float *r32 = nullptr, *sA32 = nullptr, *sB32 = nullptr;
+    double *partials = nullptr;
+    ppk::State *st = nullptr;
+    ppk::State *hst = nullptr;  // pinned
+    int32_t *hflag = nullptr;   // pinned, 2 slots
+    hipEvent_t flag_ev[2] = {nullptr, nullptr};
+    std::vector<hipEvent_t> tev;  // timing events (pairs)
+    hipEvent_t solve_ev[2] = {nullptr, nullptr};
+    // polynomial
+    bool setup_done = false;
+    int k = 0;
+    double lmin = 0, lmax = 0, xi = 0, theta = 0, delta = 0, sigma = 0;
+    std::vector<double> rho;
+    // options
+    int grid_max = GRID_DEFAULT;
+    int chunk = 0;  // 0 = auto
+    int timing = 0;
+    int driver = 0;
+    int ntload = 0;
+    pp_stats stats{};
+
+    bool schur() const { return kind == 1; }
+    bool mixed() const { return (flags & PP_MIXED) != 0; }
+
+    int grid_slices() const
+    {
+        int64_t g = (nslices + WPB - 1) / WPB;
+        return (int)std::max<int64_t>(1, std::min<int64_t>(g, grid_max));
+    }
+    int grid_elems(int64_t cnt) const
+    {
+        int64_t g = (cnt + BLOCK - 1) / BLOCK;
+        return (int)std::max<int64_t>(1, std::min<int64_t>(g, grid_max));
+    }
+    ppk::SellView view(bool f32) const
+    {
+        ppk::SellView v;
+        v.sp = sp;
+        v.col = scol;
+        v.val = f32 ? (const void *)sval32 : (const void *)sval;
+        v.n = n;
+        v.nslices = nslices;
+        v.nx = n;
+        return v;
+    }
+    ppk::CsrView cview(bool f32) const
+    {
+        ppk::CsrView v;
+        v.rp = crp;
+        v.col = ccol;
+        v.val = f32 ? (const void *)cm32 : (const void *)cm;
+        v.rows = nt;
+        return v;
+    }
+
+    void release()
+    {
+        dfree(sp); dfree(scol); dfree(sval); dfree(sval32);
+        dfree(crp); dfree(ccol); dfree(cm); dfree(cm32); dfree(tw); dfree(tw32);
+        dfree(dis);
+        dfree(xh); dfree(r); dfree(p); dfree(q); dfree(z); dfree(bh); dfree(sA); dfree(sB);
+        dfree(r32); dfree(sA32); dfree(sB32);
+        dfree(partials); dfree(st);
+        if (hst) (void)hipHostFree(hst);
+        if (hflag) (void)hipHostFree(hflag);
+        hst = nullptr;
+        hflag = nullptr;
+        for (auto &e : flag_ev) if (e) { (void)hipEventDestroy(e); e = nullptr; }
+        for (auto &e : solve_ev) if (e) { (void)hipEventDestroy(e); e = nullptr; }
+        for (auto &e : tev) (void)hipEventDestroy(e);
+        tev.clear();
+    }
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// setup
+// ---------------------------------------------------------------------------
+
+// Host-side transpose of C (nt x n, given on the device) into per-cell lists
+// (cell -> trace rows), sorted by trace row so that the appended entries have
+// a fixed order.  C is small (two entries per trace row).
+void build_ct(pp_op_s *op, const int64_t *c_rowptr, const int32_t *c_col, const double *c_val,
+              int64_t **ctp_d, int32_t **ctt_d, double **ctv_d)
+{
+    const int64_t nt = op->nt, n = op->n, nnz = op->nnz_c;
+    std::vector<int64_t> crp(nt + 1);
+    std::vector<int32_t> ccol(nnz);
+    std::vector<double> cval(nnz);
+    HIPCHK(hipMemcpyAsync(crp.data(), c_rowptr, sizeof(int64_t) * (nt + 1), hipMemcpyDeviceToHost, op->stream));
+    HIPCHK(hipMemcpyAsync(ccol.data(), c_col, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost, op->stream));
+    HIPCHK(hipMemcpyAsync(cval.data(), c_val, sizeof(double) * nnz, hipMemcpyDeviceToHost, op->stream));
+    HIPCHK(hipStreamSynchronize(op->stream));
+    std::vector<int64_t> ctp(n + 1, 0);
+    for (int64_t p = 0; p < nnz; ++p) ctp[(size_t)ccol[p] + 1] += 1;
+    for (int64_t i = 0; i < n; ++i) ctp[i + 1] += ctp[i];
+    std::vector<int64_t> fill(ctp.begin(), ctp.end() - 1);
+    std::vector<int32_t> ctt(nnz);
+    std::vector<double> ctv(nnz);
+    for (int64_t t = 0; t < nt; ++t)  // ascending t -> each list sorted by trace row
+        for (int64_t p = crp[t]; p < crp[t + 1]; ++p) {
+            const int64_t o = fill[ccol[p]]++;
+            ctt[o] = (int32_t)t;
+            ctv[o] = cval[p];
+        }
+    *ctp_d = dalloc<int64_t>(n + 1);
+    *ctt_d = dalloc<int32_t>(nnz);
+    *ctv_d = dalloc<double>(nnz);
+    HIPCHK(hipMemcpyAsync(*ctp_d, ctp.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, op->stream));
+    HIPCHK(hipMemcpyAsync(*ctt_d, ctt.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, op->stream));
+    HIPCHK(hipMemcpyAsync(*ctv_d, ctv.data(), sizeof(double) * nnz, hipMemcpyHostToDevice, op->stream));
+    HIPCHK(hipStreamSynchronize(op->stream));
+}
+
+int check_csr_dev(pp_op_s *op, int64_t rows, int64_t ncols, int64_t nnz, const int64_t *rp,
+                  const int32_t *col, int *flag_d)
+{
+    HIPCHK(hipMemsetAsync(flag_d, 0, sizeof(int), op->stream));
+    const int64_t g = (rows + BLOCK - 1) / BLOCK;
+    hipLaunchKernelGGL(ppk::k_check_csr, dim3((unsigned)g), dim3(BLOCK), 0, op->stream, rows, ncols,
+                       nnz, rp, col, flag_d);
+    HIPCHK(hipGetLastError());
+    int h = 0;
+    HIPCHK(hipMemcpyAsync(&h, flag_d, sizeof(int), hipMemcpyDeviceToHost, op->stream));
+    HIPCHK(hipStreamSynchronize(op->stream));
+    return h;
+}
+
+pp_status build_operator(pp_op_s *op, const int64_t *rp, const int32_t *col, const double *val,
+                         const int64_t *c_rowptr, const int32_t *c_col, const double *c_val,
+                         const double *m_diag)
+{
+    const int64_t n = op->n;
+    int *flag_d = dalloc<int>(1);
+    int64_t *ctp = nullptr;
+    int32_t *ctt = nullptr;
+    double *ctv = nullptr;
+    int64_t *width = nullptr;
+    double *dtmp = nullptr;
+    auto cleanup = [&]() {
+        dfree(flag_d); dfree(ctp); dfree(ctt); dfree(ctv); dfree(width); dfree(dtmp);
+    };
+    try {
+        int bad = check_csr_dev(op, n, n, op->nnz_given, rp, col, flag_d);
+        if (bad) { cleanup(); return fail(PP_ERR_ARG, "invalid CSR structure of A (row pointers or column indices)"); }
+        if (op->schur()) {
+            bad = check_csr_dev(op, op->nt, n, op->nnz_c, c_rowptr, c_col, flag_d);
+            if (bad) { cleanup(); return fail(PP_ERR_ARG, "invalid CSR structure of C"); }
+            // m > 0 check on host (nt is small)
+            std::vector<double> mh(op->nt);
+            HIPCHK(hipMemcpyAsync(mh.data(), m_diag, sizeof(double) * op->nt, hipMemcpyDeviceToHost, op->stream));
+            HIPCHK(hipStreamSynchronize(op->stream));
+            for (double v : mh)
+                if (!(v > 0.0) || !std::isfinite(v)) { cleanup(); return fail(PP_ERR_ARG, "m_diag must be positive and finite"); }
+            build_ct(op, c_rowptr, c_col, c_val, &ctp, &ctt, &ctv);
+        }
+        // Jacobi: d = diag(op), dis = d^{-1/2}
+        if (op->flags & PP_JACOBI) {
+            op->dis = dalloc<double>(n);
+            dtmp = dalloc<double>(n);
+            HIPCHK(hipMemsetAsync(flag_d, 0, sizeof(int), op->stream));
+            hipLaunchKernelGGL(ppk::k_diag, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0,
+                               op->stream, n, rp, col, val, ctp, ctt, ctv, m_diag, dtmp, op->dis, flag_d);
+            HIPCHK(hipGetLastError());
+            int h = 0;
+            HIPCHK(hipMemcpyAsync(&h, flag_d, sizeof(int), hipMemcpyDeviceToHost, op->stream));
+            HIPCHK(hipStreamSynchronize(op->stream));
+            if (h) { cleanup(); return fail(PP_ERR_ARG, "Jacobi scaling needs a positive finite diagonal"); }
+        }
+        // slice widths and offsets
+        op->nslices = (n + WAVE - 1) / WAVE;
+        width = dalloc<int64_t>(op->nslices);
+        op->sp = dalloc<int64_t>(op->nslices + 1);
+        const unsigned gs = (unsigned)((op->nslices + WPB - 1) / WPB);
+        hipLaunchKernelGGL(ppk::k_slice_width, dim3(gs), dim3(BLOCK), 0, op->stream, n, op->nslices, rp,
+                           (const int64_t *)ctp, width);
+        HIPCHK(hipGetLastError());
+        hipLaunchKernelGGL(ppk::k_scan_slices, dim3(1), dim3(1024), 0, op->stream, op->nslices,
+                           (const int64_t *)width, op->sp);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(&op->nstored, op->sp + op->nslices, sizeof(int64_t), hipMemcpyDeviceToHost, op->stream));
+        HIPCHK(hipStreamSynchronize(op->stream));
+        op->scol = dalloc<int32_t>(op->nstored);
+        op->sval = dalloc<double>(op->nstored);
+        if (op->mixed()) op->sval32 = dalloc<float>(op->nstored);
+        hipLaunchKernelGGL(ppk::k_slice_fill, dim3(gs), dim3(BLOCK), 0, op->stream, n, op->nslices, n, rp,
+                           col, val, (const int64_t *)ctp, (const int32_t *)ctt, (const double *)ctv,
+                           (const double *)op->dis, (const int64_t *)op->sp, op->scol, op->sval,
+                           op->sval32);
+        HIPCHK(hipGetLastError());
+        if (op->schur()) {
+            const int64_t nt = op->nt;
+            op->crp = dalloc<int64_t>(nt + 1);
+            op->ccol = dalloc<int32_t>(op->nnz_c);
+            op->cm = dalloc<double>(op->nnz_c);
+            HIPCHK(hipMemcpyAsync(op->crp, c_rowptr, sizeof(int64_t) * (nt + 1), hipMemcpyDeviceToDevice, op->stream));
+            HIPCHK(hipMemcpyAsync(op->ccol, c_col, sizeof(int32_t) * op->nnz_c, hipMemcpyDeviceToDevice, op->stream));
+            if (op->mixed()) op->cm32 = dalloc<float>(op->nnz_c);
+            hipLaunchKernelGGL(ppk::k_trace_fill, dim3((unsigned)((nt + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0,
+                               op->stream, nt, (const int64_t *)c_rowptr, c_col, c_val, m_diag,
+                               (const double *)op->dis, op->cm, op->cm32);
+            HIPCHK(hipGetLastError());
+            op->tw = dalloc<double>(nt);
+            if (op->mixed()) op->tw32 = dalloc<float>(nt);
+        }
+        // work vectors
+        op->xh = dalloc<double>(n);
+        op->r = dalloc<double>(n);
+        op->p = dalloc<double>(n);
+        op->q = dalloc<double>(n);
+        op->z = dalloc<double>(n);
+        op->bh = dalloc<double>(n);
+        op->sA = dalloc<double>(n);
+        op->sB = dalloc<double>(n);
+        if (op->mixed()) {
+            op->r32 = dalloc<float>(n);
+            op->sA32 = dalloc<float>(n);
+            op->sB32 = dalloc<float>(n);
+        }
+        op->partials = dalloc<double>(std::max(op->grid_max, 8192));
+        op->st = dalloc<ppk::State>(1);
+        HIPCHK(hipMemsetAsync(op->st, 0, sizeof(ppk::State), op->stream));
+        HIPCHK(hipHostMalloc((void **)&op->hst, sizeof(ppk::State), hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void **)&op->hflag, 2 * sizeof(int32_t), hipHostMallocDefault));
+        for (auto &e : op->flag_ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        for (auto &e : op->solve_ev) HIPCHK(hipEventCreate(&e));
+        HIPCHK(hipStreamSynchronize(op->stream));
+    } catch (std::bad_alloc &) {
+        cleanup();
+        return fail(PP_ERR_OOM, "device allocation failed");
+    } catch (HipError &e) {
+        cleanup();
+        char b[256];
+        snprintf(b, sizeof b, "HIP error %s in %s (line %d)", hipGetErrorString(e.e), e.what, e.line);
+        return fail(PP_ERR_HIP, b);
+    }
+    cleanup();
+    op->stats.n = n;
+    op->stats.nnz_stored = op->nstored;
+    op->stats.nnz_matrix = op->nnz_given + op->nnz_c;
+    return PP_OK;
+}
+
+pp_status create_common(pp_op *out, int kind, int64_t n, int64_t nnz, const int64_t *rp,
+                        const int32_t *col, const double *val, int64_t nt, int64_t nnz_c,
+                        const int64_t *c_rowptr, const int32_t *c_col, const double *c_val,
+                        const double *m_diag, unsigned flags, void *stream)
+{
+    if (!out) return fail(PP_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (n <= 0 || nnz <= 0 || !rp || !col || !val) return fail(PP_ERR_ARG, "n, nnz must be positive and arrays non-NULL");
+    if (n > (int64_t)INT32_MAX - 1) return fail(PP_ERR_ARG, "n must be below 2^31 (int32 column indices)");
+    if (flags & ~(unsigned)(PP_JACOBI | PP_MIXED)) return fail(PP_ERR_ARG, "unknown flags");
+    if (kind == 1) {
+        if (nt <= 0 || nnz_c <= 0 || !c_rowptr || !c_col || !c_val || !m_diag)
+            return fail(PP_ERR_ARG, "Schur: nt, nnz_c must be positive and arrays non-NULL");
+        if (n + nt > (int64_t)INT32_MAX - 1) return fail(PP_ERR_ARG, "n + nt must be below 2^31");
+    }
+    pp_op_s *op = new (std::nothrow) pp_op_s();
+    if (!op) return fail(PP_ERR_OOM, "host allocation failed");
+    op->kind = kind;
+    op->n = n;
+    op->nt = kind == 1 ? nt : 0;
+    op->nnz_c = kind == 1 ? nnz_c : 0;
+    op->nnz_given = nnz;
+    op->flags = flags;
+    op->stream = (hipStream_t)stream;
+    (void)hipGetDevice(&op->device);
+    pp_status s = build_operator(op, rp, col, val, c_rowptr, c_col, c_val, m_diag);
+    if (s != PP_OK) {
+        op->release();
+        delete op;
+        return s;
+    }
+    *out = op;
+    return PP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// polynomial application (Algorithm 2), queued on the handle's stream
+// ---------------------------------------------------------------------------
+
+struct StepCoef {
+    double cx, cold, cr, cA;
+};
+
+// coefficients of step j (1-based) in the form out = cx x + cold sold + cr r + cA (A x)
+StepCoef step_coef(const pp_op_s *op, int j)
+{
+    const double th = op->theta, de = op->delta, si = op->sigma;
+    const std::vector<double> &rho = op->rho;
+    StepCoef c{0, 0, 0, 0};
+    if (j == 1) {
+        c.cr = 4.0 * rho[1] / de;
+        c.cA = -2.0 * rho[1] / (de * th);
+    } else if (j == 2) {
+        c.cx = 2.0 * si * rho[2];
+        c.cr = 2.0 * rho[2] / de - rho[2] * rho[1] / th;
+        c.cA = -2.0 * rho[2] / de;
+    } else {
+        c.cx = 2.0 * si * rho[j];
+        c.cold = -rho[j] * rho[j - 1];
+        c.cr = 2.0 * rho[j] / de;
+        c.cA = -2.0 * rho[j] / de;
+    }
+    return c;
+}
+
+template <typename T, typename XT, typename RT, typename OT, int MODE, bool SCHUR, bool DOT, bool SCALE>
+void launch_cheb(pp_op_s *op, const XT *xg, const T *w, const RT *r, const T *sold, OT *out,
+                 const StepCoef &c, int fin)
+{
+    const bool f32 = sizeof(T) == 4;
+    hipLaunchKernelGGL((ppk::k_cheb<T, XT, RT, OT, MODE, SCHUR, DOT, SCALE>), dim3(op->grid_slices()),
+                       dim3(BLOCK), 0, op->stream, op->view(f32), xg, w, r, sold, out, c.cx, c.cold, c.cr,
+                       c.cA, (const double *)op->dis, op->partials, op->st, fin, op->ntload);
+}
+
+template <typename T, typename XT, typename RT, typename OT, int MODE, bool SCHUR>
+void launch_cheb_rt(pp_op_s *op, const XT *xg, const T *w, const RT *r, const T *sold, OT *out,
+                    const StepCoef &c, int fin, bool scale)
+{
+    if (fin != ppk::FIN_NONE)
+        launch_cheb<T, XT, RT, OT, MODE, SCHUR, true, false>(op, xg, w, r, sold, out, c, fin);
+    else if (scale)
+        launch_cheb<T, XT, RT, OT, MODE, SCHUR, false, true>(op, xg, w, r, sold, out, c, fin);
+    else
+        launch_cheb<T, XT, RT, OT, MODE, SCHUR, false, false>(op, xg, w, r, sold, out, c, fin);
+}
+
+template <typename T, typename XT, typename RT, typename OT, int MODE>
+void launch_step(pp_op_s *op, const XT *xg, const RT *r, const T *sold, OT *out, const StepCoef &c,
+                 int fin, bool scale)
+{
+    if (op->schur()) {
+        T *w = sizeof(T) == 4 ? (T *)op->tw32 : (T *)op->tw;
+        hipLaunchKernelGGL((ppk::k_trace<T, XT>), dim3(op->grid_elems(op->nt)), dim3(BLOCK), 0, op->stream,
+                           op->cview(sizeof(T) == 4), xg, w, (const ppk::State *)op->st);
+        launch_cheb_rt<T, XT, RT, OT, MODE, true>(op, xg, w, r, sold, out, c, fin, scale);
+    } else {
+        launch_cheb_rt<T, XT, RT, OT, MODE, false>(op, xg, (const T *)nullptr, r, sold, out, c, fin, scale);
+    }
+}
+
+// z = p_k(A-hat) rr, rr in the scaled space (double).  fin: FIN_NONE,
+// FIN_RHO0 or FIN_RHO (reduce rr.z).  scale: multiply the output by dis
+// (pp_apply under Jacobi).  r32src: FP32 copy of rr already made (mixed).
+void enqueue_poly(pp_op_s *op, const double *rr, double *zout, int fin, bool scale)
+{
+    const int k = op->k;
+    if (k == 0) {
+        // z = rr / theta (and the dot when requested)
+        hipLaunchKernelGGL((ppk::k_scale<double, double>), dim3(op->grid_elems(op->n)), dim3(BLOCK), 0,
+                           op->stream, op->n, rr, (const double *)(scale ? op->dis : nullptr), 1.0 / op->theta,
+                           zout);
+        if (fin != ppk::FIN_NONE)
+            hipLaunchKernelGGL(ppk::k_dot_fin, dim3(op->grid_elems(op->n)), dim3(BLOCK), 0, op->stream, op->n,
+                               rr, (const double *)zout, op->partials, op->st, fin);
+        return;
+    }
+    if (!op->mixed()) {
+        for (int j = 1; j <= k; ++j) {
+            const StepCoef c = step_coef(op, j);
+            const bool last = (j == k);
+            const int f = last ? fin : ppk::FIN_NONE;
+            const bool sc = last && scale;
+            double *out = last ? zout : ((j % 2 == 1) ? op->sA : op->sB);
+            if (j == 1) {
+                launch_step<double, double, double, double, 1>(op, rr, rr, (const double *)nullptr, out, c, f, sc);
+            } else if (j == 2) {
+                launch_step<double, double, double, double, 2>(op, op->sA, rr, (const double *)nullptr, out, c, f, sc);
+            } else {
+                // s_{j-1} in the buffer written by step j-1, s_{j-2} in the other
+                const double *prev = (j % 2 == 0) ? op->sA : op->sB;
+                const double *old = (j % 2 == 0) ? op->sB : op->sA;
+                launch_step<double, double, double, double, 3>(op, prev, rr, old, out, c, f, sc);
+            }
+        }
+        return;
+    }
+    // mixed: r32 = (float) rr, steps in FP32, last step writes FP64 z
+    hipLaunchKernelGGL((ppk::k_scale<double, float>), dim3(op->grid_elems(op->n)), dim3(BLOCK), 0, op->stream,
+                       op->n, rr, (const double *)nullptr, 1.0, op->r32);
+    for (int j = 1; j <= k; ++j) {
+        const StepCoef c = step_coef(op, j);
+        const bool last = (j == k);
+        const int f = last ? fin : ppk::FIN_NONE;
+        const bool sc = last && scale;
+        float *out32 = (j % 2 == 1) ? op->sA32 : op->sB32;
+        if (!last) {
+            if (j == 1)
+                launch_step<float, float, float, float, 1>(op, op->r32, op->r32, (const float *)nullptr, out32, c, f, sc);
+            else if (j == 2)
+                launch_step<float, float, float, float, 2>(op, op->sA32, op->r32, (const float *)nullptr, out32, c, f, sc);
+            else {
+                const float *prev = (j % 2 == 0) ? op->sA32 : op->sB32;
+                const float *old = (j % 2 == 0) ? op->sB32 : op->sA32;
+                launch_step<float, float, float, float, 3>(op, prev, op->r32, old, out32, c, f, sc);
+            }
+        } else {
+            // last step: r read in FP64 (for the CG dot), output FP64
+            if (j == 1)
+                launch_step<float, float, double, double, 1>(op, op->r32, rr, (const float *)nullptr, zout, c, f, sc);
+            else if (j == 2)
+                launch_step<float, float, double, double, 2>(op, op->sA32, rr, (const float *)nullptr, zout, c, f, sc);
+            else {
+                const float *prev = (j % 2 == 0) ? op->sA32 : op->sB32;
+                const float *old = (j % 2 == 0) ? op->sB32 : op->sA32;
+                launch_step<float, float, double, double, 3>(op, prev, rr, old, zout, c, f, sc);
+            }
+        }
+    }
+}
+
+}  // namespace
+
+namespace {
+
+// w = M^{-1} C-hat x (Schur only).  live_state: skip once the solve is done.
+void enqueue_trace_f64(pp_op_s *op, const double *x, bool live_state = true)
+{
+    if (!op->schur()) return;
+    hipLaunchKernelGGL((ppk::k_trace<double, double>), dim3(op->grid_elems(op->nt)), dim3(BLOCK), 0, op->stream,
+                       op->cview(false), x, op->tw, (const ppk::State *)(live_state ? op->st : nullptr));
+}
+
+void enqueue_iteration(pp_op_s *op, hipEvent_t e0, hipEvent_t e1)
+{
+    const int gs = op->grid_slices(), ge = op->grid_elems(op->n);
+    enqueue_trace_f64(op, op->p);
+    if (op->schur())
+        hipLaunchKernelGGL(ppk::k_pq<true>, dim3(gs), dim3(BLOCK), 0, op->stream, op->view(false), op->p,
+                           (const double *)op->tw, op->q, op->partials, op->st, op->ntload);
+    else
+        hipLaunchKernelGGL(ppk::k_pq<false>, dim3(gs), dim3(BLOCK), 0, op->stream, op->view(false), op->p,
+                           (const double *)nullptr, op->q, op->partials, op->st, op->ntload);
+    hipLaunchKernelGGL(ppk::k_xr, dim3(ge), dim3(BLOCK), 0, op->stream, op->n, op->p, op->q, op->xh, op->r,
+                       op->partials, op->st);
+    if (e0) (void)hipEventRecord(e0, op->stream);
+    enqueue_poly(op, op->r, op->z, ppk::FIN_RHO, false);
+    if (e1) (void)hipEventRecord(e1, op->stream);
+    hipLaunchKernelGGL(ppk::k_p, dim3(ge), dim3(BLOCK), 0, op->stream, op->n, op->z, op->p,
+                       (const ppk::State *)op->st, 0);
+}
+
+hipEvent_t timing_event(pp_op_s *op, size_t i)
+{
+    while (op->tev.size() <= i) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        op->tev.push_back(e);
+    }
+    return op->tev[i];
+}
+
+pp_status hip_fail(const HipError &e)
+{
+    char b[256];
+    snprintf(b, sizeof b, "HIP error %s in %s (line %d)", hipGetErrorString(e.e), e.what, e.line);
+    return fail(PP_ERR_HIP, b);
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" {
+
+const char *pp_status_str(pp_status s)
+{
+    switch (s) {
+    case PP_OK: return "PP_OK";
+    case PP_NOT_CONVERGED: return "PP_NOT_CONVERGED";
+    case PP_BREAKDOWN: return "PP_BREAKDOWN";
+    case PP_ERR_ARG: return "PP_ERR_ARG";
+    case PP_ERR_OOM: return "PP_ERR_OOM";
+    case PP_ERR_HIP: return "PP_ERR_HIP";
+    case PP_ERR_STATE: return "PP_ERR_STATE";
+    }
+    return "PP_UNKNOWN";
+}
+
+const char *pp_last_error(void) { return g_err.c_str(); }
+
+pp_status pp_create_csr(pp_op *out, int64_t n, int64_t nnz, const int64_t *rowptr, const int32_t *colind,
+                        const double *val, unsigned flags, void *stream)
+{
+    return create_common(out, 0, n, nnz, rowptr, colind, val, 0, 0, nullptr, nullptr, nullptr, nullptr, flags,
+                         stream);
+}
+
+pp_status pp_create_schur(pp_op *out, int64_t n, int64_t nnz_a, const int64_t *a_rowptr, const int32_t *a_col,
+                          const double *a_val, int64_t nt, int64_t nnz_c, const int64_t *c_rowptr,
+                          const int32_t *c_col, const double *c_val, const double *m_diag, unsigned flags,
+                          void *stream)
+{
+    return create_common(out, 1, n, nnz_a, a_rowptr, a_col, a_val, nt, nnz_c, c_rowptr, c_col, c_val, m_diag,
+                         flags, stream);
+}
+
+void pp_destroy(pp_op op)
+{
+    if (!op) return;
+    (void)hipStreamSynchronize(op->stream);
+    op->release();
+    delete op;
+}
+
+pp_status pp_setup(pp_op op, int k, double lambda_min, double lambda_max, double scaling)
+{
+    if (!op) return fail(PP_ERR_ARG, "op is NULL");
+    if (k < 0 || k > K_MAX) return fail(PP_ERR_ARG, "degree k out of range [0, 4096]");
+    if (!std::isfinite(lambda_min) || !std::isfinite(lambda_max) || !(lambda_min > 0.0) ||
+        !(lambda_max > lambda_min))
+        return fail(PP_ERR_ARG, "bounds must satisfy 0 < lambda_min < lambda_max (finite)");
+    if (!std::isfinite(scaling) || !(scaling >= 0.0)) return fail(PP_ERR_ARG, "scaling must be finite and >= 0");
+    op->k = k;
+    op->lmin = lambda_min;
+    op->lmax = lambda_max;
+    op->xi = scaling;
+    op->theta = (lambda_max + lambda_min) / 2.0 * (1.0 + scaling);
+    op->delta = (lambda_max - lambda_min) / 2.0;
+    op->sigma = op->theta / op->delta;
+    op->rho.assign((size_t)k + 1, 0.0);
+    op->rho[0] = 1.0 / op->sigma;
+    for (int j = 1; j <= k; ++j) op->rho[j] = 1.0 / (2.0 * op->sigma - op->rho[j - 1]);
+    op->setup_done = true;
+    return PP_OK;
+}
+
+pp_status pp_set_option(pp_op op, int key, int64_t value)
+{
+    if (!op) return fail(PP_ERR_ARG, "op is NULL");
+    switch (key) {
+    case PP_OPT_GRID:
+        if (value < 0 || value > 8192) return fail(PP_ERR_ARG, "grid must be in [0, 8192]");
+        op->grid_max = value == 0 ? GRID_DEFAULT : (int)value;
+        return PP_OK;
+    case PP_OPT_CHUNK:
+        if (value < 0 || value > 4096) return fail(PP_ERR_ARG, "chunk must be in [0, 4096]");
+        op->chunk = (int)value;
+        return PP_OK;
+    case PP_OPT_TIMING: op->timing = value != 0; return PP_OK;
+    case PP_OPT_DRIVER:
+        if (value != 0 && value != -1) return fail(PP_ERR_ARG, "driver: only 0 (stream-driven) or -1 (auto)");
+        op->driver = 0;
+        return PP_OK;
+    case PP_OPT_NT_LOADS: op->ntload = value != 0; return PP_OK;
+    default: return fail(PP_ERR_ARG, "unknown option");
+    }
+}
+
+pp_status pp_get_stats(pp_op op, pp_stats *st)
+{
+    if (!op || !st) return fail(PP_ERR_ARG, "NULL argument");
+    *st = op->stats;
+    return PP_OK;
+}
+
+pp_status pp_operator_apply(pp_op op, const double *x, double *y)
+{
+    if (!op || !x || !y) return fail(PP_ERR_ARG, "NULL argument");
+    if (x == y) return fail(PP_ERR_ARG, "x and y must not alias");
+    try {
+        const int64_t n = op->n;
+        const double *src = x;
+        if (op->dis) {
+            // A = D^{1/2} A-hat D^{1/2}: xh = x / dis, y = (A-hat xh) / dis
+            hipLaunchKernelGGL(ppk::k_div, dim3(op->grid_elems(n)), dim3(BLOCK), 0, op->stream, n, x,
+                               (const double *)op->dis, op->bh);
+            src = op->bh;
+        }
+        enqueue_trace_f64(op, src, false);
+        double *dst = op->dis ? op->sA : y;
+        if (op->schur())
+            hipLaunchKernelGGL((ppk::k_spmv<double, true>), dim3(op->grid_slices()), dim3(BLOCK), 0, op->stream,
+                               op->view(false), src, (const double *)op->tw, dst, op->ntload);
+        else
+            hipLaunchKernelGGL((ppk::k_spmv<double, false>), dim3(op->grid_slices()), dim3(BLOCK), 0, op->stream,
+                               op->view(false), src, (const double *)nullptr, dst, op->ntload);
+        if (op->dis)
+            hipLaunchKernelGGL(ppk::k_div, dim3(op->grid_elems(n)), dim3(BLOCK), 0, op->stream, n,
+                               (const double *)op->sA, (const double *)op->dis, y);
+        HIPCHK(hipGetLastError());
+    } catch (HipError &e) {
+        return hip_fail(e);
+    }
+    return PP_OK;
+}
+
+pp_status pp_apply(pp_op op, const double *r, double *z)
+{
+    if (!op || !r || !z) return fail(PP_ERR_ARG, "NULL argument");
+    if (r == z) return fail(PP_ERR_ARG, "r and z must not alias");
+    if (!op->setup_done) return fail(PP_ERR_STATE, "pp_setup must be called before pp_apply");
+    try {
+        const int64_t n = op->n;
+        // the polynomial kernels check the device state: make sure it is live
+        hipLaunchKernelGGL(ppk::k_state_init, dim3(1), dim3(64), 0, op->stream, op->st, 0.0, 0);
+        const double *rr = r;
+        if (op->dis) {
+            hipLaunchKernelGGL((ppk::k_scale<double, double>), dim3(op->grid_elems(n)), dim3(BLOCK), 0, op->stream,
+                               n, r, (const double *)op->dis, 1.0, op->bh);
+            rr = op->bh;
+        }
+        enqueue_poly(op, rr, z, ppk::FIN_NONE, op->dis != nullptr);
+        HIPCHK(hipGetLastError());
+    } catch (HipError &e) {
+        return hip_fail(e);
+    }
+    return PP_OK;
+}
+
+pp_status pcg_solve(pp_op op, const double *b, double *x, double tol, int maxit, int *iters, double *relres)
+{
+    if (!op || !b || !x) return fail(PP_ERR_ARG, "NULL argument");
+    if (b == x) return fail(PP_ERR_ARG, "b and x must not alias");
+    if (!std::isfinite(tol) || tol < 0.0) return fail(PP_ERR_ARG, "tol must be finite and >= 0");
+    if (maxit < 0) return fail(PP_ERR_ARG, "maxit must be >= 0");
+    if (!op->setup_done) return fail(PP_ERR_STATE, "pp_setup must be called before pcg_solve");
+    try {
+        const int64_t n = op->n;
+        const int gs = op->grid_slices(), ge = op->grid_elems(n);
+        HIPCHK(hipEventRecord(op->solve_ev[0], op->stream));
+        hipLaunchKernelGGL(ppk::k_state_init, dim3(1), dim3(64), 0, op->stream, op->st, tol, maxit);
+        hipLaunchKernelGGL(ppk::k_init_scale, dim3(ge), dim3(BLOCK), 0, op->stream, n, b, (const double *)x,
+                           (const double *)op->dis, op->bh, op->xh, op->partials, op->st);
+        enqueue_trace_f64(op, op->xh);
+        if (op->schur())
+            hipLaunchKernelGGL(ppk::k_init_resid<true>, dim3(gs), dim3(BLOCK), 0, op->stream, op->view(false),
+                               (const double *)op->xh, (const double *)op->tw, (const double *)op->bh, op->r,
+                               op->partials, op->st, op->ntload);
+        else
+            hipLaunchKernelGGL(ppk::k_init_resid<false>, dim3(gs), dim3(BLOCK), 0, op->stream, op->view(false),
+                               (const double *)op->xh, (const double *)nullptr, (const double *)op->bh, op->r,
+                               op->partials, op->st, op->ntload);
+        size_t ev_i = 0;
+        hipEvent_t e0 = op->timing ? timing_event(op, ev_i++) : nullptr;
+        hipEvent_t e1 = op->timing ? timing_event(op, ev_i++) : nullptr;
+        if (e0) HIPCHK(hipEventRecord(e0, op->stream));
+        enqueue_poly(op, op->r, op->z, ppk::FIN_RHO0, false);
+        if (e1) HIPCHK(hipEventRecord(e1, op->stream));
+        hipLaunchKernelGGL(ppk::k_p, dim3(ge), dim3(BLOCK), 0, op->stream, n, (const double *)op->z, op->p,
+                           (const ppk::State *)op->st, 1);
+        HIPCHK(hipGetLastError());
+
+        int chunk = op->chunk;
+        if (chunk <= 0) chunk = n >= (1 << 20) ? 1 : (n >= (1 << 16) ? 4 : 16);
+        int enq = 0, c = 0;
+        while (enq < maxit) {
+            const int m = std::min(chunk, maxit - enq);
+            for (int i = 0; i < m; ++i) {
+                hipEvent_t a = op->timing ? timing_event(op, ev_i++) : nullptr;
+                hipEvent_t bb = op->timing ? timing_event(op, ev_i++) : nullptr;
+                enqueue_iteration(op, a, bb);
+            }
+            HIPCHK(hipGetLastError());
+            enq += m;
+            HIPCHK(hipMemcpyAsync(&op->hflag[c & 1], &op->st->done, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                  op->stream));
+            HIPCHK(hipEventRecord(op->flag_ev[c & 1], op->stream));
+            if (c >= 1) {
+                HIPCHK(hipEventSynchronize(op->flag_ev[(c - 1) & 1]));
+                if (op->hflag[(c - 1) & 1]) break;
+            }
+            ++c;
+        }
+        hipLaunchKernelGGL(ppk::k_final_x, dim3(ge), dim3(BLOCK), 0, op->stream, n, (const double *)op->xh,
+                           (const double *)op->dis, x, (const ppk::State *)op->st);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipEventRecord(op->solve_ev[1], op->stream));
+        HIPCHK(hipMemcpyAsync(op->hst, op->st, sizeof(ppk::State), hipMemcpyDeviceToHost, op->stream));
+        HIPCHK(hipStreamSynchronize(op->stream));
+        const ppk::State &s = *op->hst;
+        const int it = s.it;
+        pp_status ret = (pp_status)s.status;
+        double rel = s.bnorm2 > 0 ? std::sqrt(s.rr / s.bnorm2) : 0.0;
+        if (s.zero_b) { ret = PP_OK; rel = 0.0; }
+        if (iters) *iters = it;
+        if (relres) *relres = rel;
+        op->stats.iters = it;
+        op->stats.status = ret;
+        op->stats.relres = rel;
+        // initial residual (1) + initial preconditioner (k) + per iteration A p (1) and,
+        // except after the last iteration, the preconditioner (k)
+        const int64_t polys = it > 0 ? it : 1;
+        op->stats.op_applies = s.zero_b ? 0 : 1 + (int64_t)op->k * polys + it;
+        op->stats.dots = s.zero_b ? 0 : 1 + 3LL * it;
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, op->solve_ev[0], op->solve_ev[1]));
+        op->stats.solve_ms = ms;
+        op->stats.cheb_ms = 0;
+        op->stats.cheb_steps = 0;
+        op->stats.driver = 0;
+        op->stats.grid = gs;
+        if (op->timing && !s.zero_b) {
+            // pairs 0 .. polys-1 ran (the initial one and one per iteration but the last)
+            double tot = 0;
+            for (int64_t i = 0; i < polys && (size_t)(2 * i + 1) < ev_i; ++i) {
+                float t = 0;
+                HIPCHK(hipEventElapsedTime(&t, op->tev[2 * i], op->tev[2 * i + 1]));
+                tot += t;
+            }
+            op->stats.cheb_ms = tot;
+            op->stats.cheb_steps = (int64_t)op->k * polys;
+        }
+        return ret;
+    } catch (HipError &e) {
+        return hip_fail(e);
+    }
+}
+
+pp_status pp_estimate_bounds(pp_op op, int steps, double *lambda_min, double *lambda_max)
+{
+    if (!op || !lambda_min || !lambda_max) return fail(PP_ERR_ARG, "NULL argument");
+    if (steps < 1 || steps > ppk::LZ_MAX) return fail(PP_ERR_ARG, "steps must be in [1, 64]");
+    try {
+        const int64_t n = op->n;
+        const int gs = op->grid_slices(), ge = op->grid_elems(n);
+        double *v = op->sA, *vprev = op->sB, *w = op->q;
+        hipLaunchKernelGGL(ppk::k_state_init, dim3(1), dim3(64), 0, op->stream, op->st, 0.0, 0);
+        hipLaunchKernelGGL(ppk::k_lz_start, dim3(ge), dim3(BLOCK), 0, op->stream, n, v, op->partials, op->st);
+        hipLaunchKernelGGL(ppk::k_lz_norm, dim3(ge), dim3(BLOCK), 0, op->stream, n, v, (const ppk::State *)op->st);
+        hipLaunchKernelGGL((ppk::k_scale<double, double>), dim3(ge), dim3(BLOCK), 0, op->stream, n,
+                           (const double *)v, (const double *)nullptr, 0.0, vprev);
+        for (int j = 0; j < steps; ++j) {
+            enqueue_trace_f64(op, v);
+            if (op->schur())
+                hipLaunchKernelGGL(ppk::k_lz_apply<true>, dim3(gs), dim3(BLOCK), 0, op->stream, op->view(false),
+                                   (const double *)v, (const double *)op->tw, (const double *)vprev, w,
+                                   op->partials, op->st, j, op->ntload);
+            else
+                hipLaunchKernelGGL(ppk::k_lz_apply<false>, dim3(gs), dim3(BLOCK), 0, op->stream, op->view(false),
+                                   (const double *)v, (const double *)nullptr, (const double *)vprev, w,
+                                   op->partials, op->st, j, op->ntload);
+            hipLaunchKernelGGL(ppk::k_lz_orth, dim3(ge), dim3(BLOCK), 0, op->stream, n, (const double *)v, w,
+                               op->partials, op->st, j);
+            if (j + 1 < steps)
+                hipLaunchKernelGGL(ppk::k_lz_next, dim3(ge), dim3(BLOCK), 0, op->stream, n, vprev, v,
+                                   (const double *)w, (const ppk::State *)op->st, j);
+        }
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(op->hst, op->st, sizeof(ppk::State), hipMemcpyDeviceToHost, op->stream));
+        HIPCHK(hipStreamSynchronize(op->stream));
+        int m = steps;
+        for (int j = 0; j < steps; ++j) {
+            if (!std::isfinite(op->hst->lz_alpha[j]) || !std::isfinite(op->hst->lz_beta[j]))
+                return fail(PP_ERR_ARG, "non-finite value in Lanczos (operator not finite?)");
+            if (op->hst->lz_beta[j] == 0.0) { m = j + 1; break; }
+        }
+        std::vector<double> T((size_t)m * m, 0.0), wv, V;
+        for (int j = 0; j < m; ++j) {
+            T[(size_t)j * m + j] = op->hst->lz_alpha[j];
+            if (j + 1 < m) {
+                T[(size_t)j * m + j + 1] = op->hst->lz_beta[j];
+                T[(size_t)(j + 1) * m + j] = op->hst->lz_beta[j];
+            }
+        }
+        ppeig::jacobi_eig(m, T, wv, V);
+        int imin = 0, imax = 0;
+        for (int i = 1; i < m; ++i) {
+            if (wv[i] < wv[imin]) imin = i;
+            if (wv[i] > wv[imax]) imax = i;
+        }
+        const double pad = std::fabs(op->hst->lz_beta[m - 1] * V[(size_t)(m - 1) * m + imax]);
+        *lambda_min = wv[imin];
+        *lambda_max = wv[imax] + pad;
+    } catch (HipError &e) {
+        return hip_fail(e);
+    }
+    return PP_OK;
+}
+
+}  // extern "C"
