@@ -266,8 +266,13 @@ def test_lanczos_bounds(B, case, jacobi):
     lo_r, hi_r = O.lanczos_bounds(orc, 20)
     op = make_op(B, a, s, B.PP_JACOBI if jacobi else 0)
     lo, hi = B.pp_estimate_bounds(op.handle, 20)
-    assert lo == pytest.approx(lo_r, rel=1e-8)
-    assert hi == pytest.approx(hi_r, rel=1e-8)
+    # Ritz values are eigenvalues of T_20; two T_20 built with different
+    # rounding orders differ by O(eps ||A||) amplified by the loss of
+    # orthogonality of plain Lanczos, and by Weyl's theorem so do their
+    # eigenvalues: the tolerance is relative to ||A|| ~ lambda_max, not to
+    # an unconverged lambda_min.
+    assert abs(lo - lo_r) <= 1e-7 * hi_r
+    assert abs(hi - hi_r) <= 1e-7 * hi_r
     op.close()
 
 
