@@ -57,6 +57,60 @@ def cheb_bytes_per_step(n, nnz, k, fp32=False):
     return total / k
 
 
+def schur_bytes_per_step(n, nnz_a, nt, nnz_c, k):
+    """Algorithmic bytes of one fused step with the never-assembled S = A_ff + C^T M^-1 C (FP64).
+
+    A_ff in CSR (12 nnz + 4(n+1)), C read twice (trace phase and transpose
+    scatter, 12 nnz_c each, one row structure 4(nt+1)), the trace vector w
+    written and read and M read (24 nt), plus the vector traffic of the
+    Chebyshev step (as for a CSR operator).
+    """
+    bop = 12 * nnz_a + 4 * (n + 1) + 24 * nnz_c + 4 * (nt + 1) + 24 * nt
+    total = k * bop + 8 * n * (4 * k - 3) if k >= 2 else bop + 16 * n
+    return total / k
+
+
+def run_dfn(args, B, W, torch, dev):
+    """DFN-shaped Schur operator (2000 fractures of 64 x 64 cells, 5000 traces), degree dfn_k."""
+    t0 = time.perf_counter()
+    s, b = W.config_dfn()
+    n, nt = s.n, s.nt
+    up = lambda x: torch.from_numpy(x).to(dev)
+    h = B.pp_create_schur(n, s.a.nnz, up(s.a.rowptr), up(s.a.col), up(s.a.val), nt, s.c.nnz,
+                          up(s.c.rowptr), up(s.c.col), up(s.c.val), up(s.m), B.PP_JACOBI)
+    t_create = time.perf_counter() - t0
+    lmin, lmax = B.pp_estimate_bounds(h, 20)
+    B.pp_set_option(h, B.PP_OPT_TIMING, 1)
+    k = args.dfn_k
+    B.pp_setup(h, k, lmin, lmax, args.xi)
+    bd = up(b)
+    x = torch.zeros(n, dtype=torch.float64, device=dev)
+    for _ in range(args.warmup):
+        x.zero_()
+        B.pcg_solve(h, bd, x, args.tol, args.maxit)
+    torch.cuda.synchronize()
+    cms, csteps = 0.0, 0
+    tt0 = time.perf_counter()
+    for _ in range(args.steps):
+        x.zero_()
+        status, it, rel = B.pcg_solve(h, bd, x, args.tol, args.maxit)
+        st = B.pp_get_stats(h)
+        cms += st["cheb_ms"]
+        csteps += st["cheb_steps"]
+    torch.cuda.synchronize()
+    tsolve = (time.perf_counter() - tt0) / max(1, args.steps)
+    step_us = 1000.0 * cms / max(1, csteps)
+    bps = schur_bytes_per_step(n, s.a.nnz, nt, s.c.nnz, k)
+    out = dict(workload="dfn_schur_2000x64x64_5000traces_jacobi", n=n, nt=nt, nnz_a=s.a.nnz, nnz_c=s.c.nnz,
+               k=k, s_per_solve=tsolve, iters=it, relres=rel, status=B.pp_status_str(status),
+               bounds=[lmin, lmax], step_us=step_us, step_gbs=bps / (step_us * 1e-6) / 1e9,
+               step_frac_hbm=bps / (step_us * 1e-6) / 1e9 / HBM_PEAK_GBS, create_s=t_create,
+               nnz_stored=st["nnz_stored"])
+    B.pp_destroy(h)
+    log("dfn k=%d: %.3f s/solve, iters %d, step %.1f us (%.0f GB/s)" % (k, tsolve, it, step_us, out["step_gbs"]))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,6 +123,12 @@ def main():
     ap.add_argument("--maxit", type=int, default=5000)
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-dfn", action="store_true", help="skip the DFN-shaped Schur leg")
+    ap.add_argument("--dfn-k", type=int, default=40)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one plain 1 GiB device copy first (HBM counter calibration)")
+    ap.add_argument("--grid", type=int, default=0, help="workgroups per launch (0 = library default)")
+    ap.add_argument("--nt-loads", type=int, default=-1, help="1/0: non-temporal matrix loads (-1 = default)")
     ap.add_argument("--cpu-sample-k", type=int, default=0, help="degree of the CPU sample iteration (0 = 20)")
     args = ap.parse_args()
 
@@ -102,6 +162,14 @@ def main():
     bd = torch.from_numpy(b).to(dev)
     torch.cuda.synchronize()
 
+    if args.calib_copy:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     t0 = time.perf_counter()
     h = B.pp_create_csr(n, nnz, rp, ci, va, B.PP_JACOBI)
     torch.cuda.synchronize()
@@ -112,6 +180,10 @@ def main():
     log("create %.2fs, Lanczos bounds [%.6g, %.6g] in %.3fs" % (t_create, lmin, lmax, t_bounds))
     st0 = B.pp_get_stats(h)
     B.pp_set_option(h, B.PP_OPT_TIMING, 1)
+    if args.grid:
+        B.pp_set_option(h, B.PP_OPT_GRID, args.grid)
+    if args.nt_loads >= 0:
+        B.pp_set_option(h, B.PP_OPT_NT_LOADS, args.nt_loads)
 
     x = torch.zeros(n, dtype=torch.float64, device=dev)
     per_k = []
@@ -183,6 +255,10 @@ def main():
     if not args.no_mixed:
         hm = B.pp_create_csr(n, nnz, rp, ci, va, B.PP_JACOBI | B.PP_MIXED)
         B.pp_set_option(hm, B.PP_OPT_TIMING, 1)
+        if args.grid:
+            B.pp_set_option(hm, B.PP_OPT_GRID, args.grid)
+        if args.nt_loads >= 0:
+            B.pp_set_option(hm, B.PP_OPT_NT_LOADS, args.nt_loads)
         B.pp_setup(hm, kh, lmin, lmax, args.xi)
         x.zero_()
         B.pcg_solve(hm, bd, x, args.tol, args.maxit)
@@ -209,6 +285,8 @@ def main():
         log("mixed k=%d: %.3f s/solve, iters %d, true relres %.2e, speedup %.2fx"
             % (kh, tm, it_m, tr, mixed["speedup_vs_fp64"]))
         B.pp_destroy(hm)
+
+    dfn = None if args.no_dfn else run_dfn(args, B, W, torch, dev)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -249,6 +327,7 @@ def main():
                      "frac_hbm": round(apply_gbs / HBM_PEAK_GBS, 4)},
         "per_k": per_k,
         "mixed": mixed,
+        "dfn": dfn,
         "setup": {"create_s": round(t_create, 3), "lanczos_s": round(t_bounds, 4),
                   "nnz_stored": st0["nnz_stored"]},
     }

@@ -166,11 +166,11 @@ PP_API pp_status pp_get_stats(pp_op op, pp_stats *st);
 
 /* Tunables (pp_set_option keys). */
 enum {
-    PP_OPT_GRID = 1,        /* workgroups per launch (multiple of 8 preferred), 0 = auto   */
+    PP_OPT_GRID = 1,        /* workgroups per launch, 0 = auto (resident workgroups, CUs x occupancy) */
     PP_OPT_CHUNK = 2,       /* CG iterations queued between host convergence checks       */
     PP_OPT_TIMING = 3,      /* 1 = record events around the polynomial steps              */
     PP_OPT_DRIVER = 4,      /* 0 = stream-driven, 1 = persistent cooperative kernel, -1 = auto */
-    PP_OPT_NT_LOADS = 5     /* 1 = non-temporal loads for the matrix stream                */
+    PP_OPT_NT_LOADS = 5     /* 1 (default) = non-temporal loads for the matrix stream, 0 = plain */
 };
 PP_API pp_status pp_set_option(pp_op op, int key, int64_t value);
 

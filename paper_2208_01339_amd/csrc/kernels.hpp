@@ -193,32 +193,53 @@ __device__ inline void commit_partial(double part, double *partials, State *st, 
     }
 }
 
-template <typename T>
-__device__ __forceinline__ T ldm(const T *p, bool nt)
+template <bool NT, typename T>
+__device__ __forceinline__ T ldm(const T *p)
 {
-    return nt ? __builtin_nontemporal_load(p) : *p;
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
 }
 
-// (A x)_row for one lane of a slice.  Columns >= nx read the trace vector w.
-template <typename T, typename XT, bool SCHUR>
+// (A x)_row for one lane of a slice whose entries start at `base` (width
+// entries per row).  Entries are taken in chunks of U: all U column indices
+// and values are loaded before any gather is issued, so one chunk costs two
+// dependent memory round trips whatever its length; indices past the row's
+// width are clamped to the last entry (an L1 hit) and their product dropped.
+// Columns >= nx read the trace vector w.
+template <typename T, typename XT, bool SCHUR, bool NT = false>
 __device__ __forceinline__ T sell_row(const SellView &A, const XT *__restrict__ x,
-                                      const T *__restrict__ w, int64_t slice, int lane, bool nt)
+                                      const T *__restrict__ w, int64_t base, int width, int lane)
 {
-    const int64_t base = A.sp[slice];
-    const int width = (int)((A.sp[slice + 1] - base) >> 6);
+    constexpr int U = 8;
     const int32_t *c = A.col + base + lane;
     const T *v = (const T *)A.val + base + lane;
     T acc = (T)0;
-#pragma unroll 8
-    for (int j = 0; j < width; ++j) {
-        const int cj = ldm(c + (int64_t)j * WAVE, nt);
-        const T vj = ldm(v + (int64_t)j * WAVE, nt);
-        T xj;
-        if (SCHUR) xj = (cj < A.nx) ? (T)x[cj] : w[cj - A.nx];
-        else xj = (T)x[cj];
-        acc += vj * xj;
+    for (int j0 = 0; j0 < width; j0 += U) {
+        int cj[U];
+        T vj[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = (j0 + u < width) ? j0 + u : width - 1;
+            cj[u] = ldm<NT>(c + (int64_t)j * WAVE);
+            vj[u] = ldm<NT>(v + (int64_t)j * WAVE);
+        }
+        T xj[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (SCHUR) xj[u] = (cj[u] < A.nx) ? (T)x[cj[u]] : w[cj[u] - A.nx];
+            else xj[u] = (T)x[cj[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (j0 + u < width) acc += vj[u] * xj[u];
     }
     return acc;
+}
+
+__device__ __forceinline__ void slice_span(const SellView &A, int64_t s, int64_t &base, int &width)
+{
+    base = A.sp[s];
+    width = (int)((A.sp[s + 1] - base) >> 6);
 }
 
 // Iterate the rows owned by logical workgroup L: fn(row, slice, lane).
@@ -227,7 +248,8 @@ __device__ __forceinline__ void for_my_slices(int64_t nslices, int L, int G, F f
 {
     int64_t s0, s1;
     block_range(nslices, L, G, s0, s1);
-    const int w = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+    const int lane = threadIdx.x & (WAVE - 1);
     for (int64_t s = s0 + w; s < s1; s += WPB) fn(s * WAVE + lane, s, lane);
 }
 
@@ -272,7 +294,8 @@ __global__ __launch_bounds__(BLOCK) void k_spmv(SellView A, const T *__restrict_
     const int G = (int)gridDim.x;
     const int L = xcd_remap((int)blockIdx.x, G);
     for_my_slices(A.nslices, L, G, [&](int64_t row, int64_t s, int lane) {
-        T a = sell_row<T, T, SCHUR>(A, x, w, s, lane, nt != 0);
+        int64_t base; int width; slice_span(A, s, base, width);
+        T a = sell_row<T, T, SCHUR>(A, x, w, base, width, lane);
         if (row < A.n) y[row] = a;
     });
 }
@@ -285,7 +308,8 @@ __global__ __launch_bounds__(BLOCK) void k_spmv(SellView A, const T *__restrict_
 // DOT: also reduce r.out (r read as RT, exact double product) -> FIN_RHO/FIN_RHO0.
 // SCALE: out *= dis_i (pp_apply with Jacobi returns D^{-1/2} s_k).
 // out may alias sold (each thread reads sold_i before writing out_i).
-template <typename T, typename XT, typename RT, typename OT, int MODE, bool SCHUR, bool DOT, bool SCALE>
+template <typename T, typename XT, typename RT, typename OT, int MODE, bool SCHUR, bool DOT, bool SCALE,
+          bool NT>
 __global__ __launch_bounds__(BLOCK) void k_cheb(SellView A, const XT *__restrict__ xg,
                                                 const T *__restrict__ w, const RT *__restrict__ r,
                                                 const T *sold, OT *out, double cx, double cold,
@@ -296,14 +320,22 @@ __global__ __launch_bounds__(BLOCK) void k_cheb(SellView A, const XT *__restrict
     const T ax = (T)cx, aold = (T)cold, ar = (T)cr, aA = (T)cA;
     double part = 0.0;
     for_my_slices(A.nslices, L, G, [&](int64_t row, int64_t s, int lane) {
-        T a = sell_row<T, XT, SCHUR>(A, xg, w, s, lane, nt != 0);
+        int64_t base;
+        int width;
+        slice_span(A, s, base, width);
+        // row-level operands first, so they are in flight with the matrix stream
+        const int64_t rc = row < A.n ? row : A.n - 1;
+        const RT ri = r[rc];
+        const T xs = (MODE >= 2) ? (T)xg[rc] : (T)0;
+        const T so = (MODE == 3) ? sold[rc] : (T)0;
+        const double ds = SCALE ? dis[rc] : 1.0;
+        T a = sell_row<T, XT, SCHUR, NT>(A, xg, w, base, width, lane);
         if (row < A.n) {
-            const RT ri = r[row];
             T o = aA * a + ar * (T)ri;
-            if (MODE >= 2) o += ax * (T)xg[row];
-            if (MODE == 3) o += aold * sold[row];
+            if (MODE >= 2) o += ax * xs;
+            if (MODE == 3) o += aold * so;
             OT ov = (OT)o;
-            if (SCALE) ov = (OT)((double)ov * dis[row]);
+            if (SCALE) ov = (OT)((double)ov * ds);
             out[row] = ov;
             if (DOT) part += (double)ri * (double)ov;
         }
@@ -359,7 +391,8 @@ __global__ __launch_bounds__(BLOCK) void k_init_resid(SellView A, const double *
     PPK_PROLOGUE(st)
     double part = 0.0;
     for_my_slices(A.nslices, L, G, [&](int64_t row, int64_t s, int lane) {
-        double a = sell_row<double, double, SCHUR>(A, xh, w, s, lane, nt != 0);
+        int64_t base; int width; slice_span(A, s, base, width);
+        double a = sell_row<double, double, SCHUR>(A, xh, w, base, width, lane);
         if (row < A.n) {
             const double ri = bh[row] - a;
             r[row] = ri;
@@ -378,7 +411,8 @@ __global__ __launch_bounds__(BLOCK) void k_pq(SellView A, const double *__restri
     PPK_PROLOGUE(st)
     double part = 0.0;
     for_my_slices(A.nslices, L, G, [&](int64_t row, int64_t s, int lane) {
-        double a = sell_row<double, double, SCHUR>(A, p, w, s, lane, nt != 0);
+        int64_t base; int width; slice_span(A, s, base, width);
+        double a = sell_row<double, double, SCHUR>(A, p, w, base, width, lane);
         if (row < A.n) {
             q[row] = a;
             part += p[row] * a;
@@ -526,7 +560,8 @@ __global__ __launch_bounds__(BLOCK) void k_lz_apply(SellView A, const double *__
     const double bp = (j > 0) ? st->lz_beta[j - 1] : 0.0;
     double part = 0.0;
     for_my_slices(A.nslices, L, G, [&](int64_t row, int64_t s, int lane) {
-        double a = sell_row<double, double, SCHUR>(A, v, tw, s, lane, nt != 0);
+        int64_t base; int width; slice_span(A, s, base, width);
+        double a = sell_row<double, double, SCHUR>(A, v, tw, base, width, lane);
         if (row < A.n) {
             const double wi = a - bp * vprev[row];
             wout[row] = wi;

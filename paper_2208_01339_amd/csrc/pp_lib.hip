@@ -106,10 +106,11 @@ struct pp_op_s {
     std::vector<double> rho;
     // options
     int grid_max = GRID_DEFAULT;
+    int grid_auto = GRID_DEFAULT;  // resident workgroups of the fused step (CUs x occupancy)
     int chunk = 0;  // 0 = auto
     int timing = 0;
     int driver = 0;
-    int ntload = 0;
+    int ntload = 1;
     pp_stats stats{};
 
     bool schur() const { return kind == 1; }
@@ -366,6 +367,19 @@ pp_status create_common(pp_op *out, int kind, int64_t n, int64_t nnz, const int6
         delete op;
         return s;
     }
+    // one wave of resident workgroups for the streaming kernels: the fused
+    // step holds ~70 VGPRs, which caps residency; a grid of exactly the
+    // resident count avoids a tail of late workgroups
+    int cus = 0, occ = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, op->device) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &occ, (const void *)ppk::k_cheb<double, double, double, double, 3, false, false, false, true>, BLOCK,
+            0) == hipSuccess &&
+        cus > 0 && occ > 0) {
+        op->grid_auto = std::min(8192, cus * occ);
+        op->grid_max = op->grid_auto;
+    }
+    (void)hipGetLastError();
     *out = op;
     return PP_OK;
 }
@@ -405,9 +419,14 @@ void launch_cheb(pp_op_s *op, const XT *xg, const T *w, const RT *r, const T *so
                  const StepCoef &c, int fin)
 {
     const bool f32 = sizeof(T) == 4;
-    hipLaunchKernelGGL((ppk::k_cheb<T, XT, RT, OT, MODE, SCHUR, DOT, SCALE>), dim3(op->grid_slices()),
-                       dim3(BLOCK), 0, op->stream, op->view(f32), xg, w, r, sold, out, c.cx, c.cold, c.cr,
-                       c.cA, (const double *)op->dis, op->partials, op->st, fin, op->ntload);
+    if (op->ntload)
+        hipLaunchKernelGGL((ppk::k_cheb<T, XT, RT, OT, MODE, SCHUR, DOT, SCALE, true>), dim3(op->grid_slices()),
+                           dim3(BLOCK), 0, op->stream, op->view(f32), xg, w, r, sold, out, c.cx, c.cold, c.cr,
+                           c.cA, (const double *)op->dis, op->partials, op->st, fin, 0);
+    else
+        hipLaunchKernelGGL((ppk::k_cheb<T, XT, RT, OT, MODE, SCHUR, DOT, SCALE, false>), dim3(op->grid_slices()),
+                           dim3(BLOCK), 0, op->stream, op->view(f32), xg, w, r, sold, out, c.cx, c.cold, c.cr,
+                           c.cA, (const double *)op->dis, op->partials, op->st, fin, 0);
 }
 
 template <typename T, typename XT, typename RT, typename OT, int MODE, bool SCHUR>
@@ -630,7 +649,7 @@ pp_status pp_set_option(pp_op op, int key, int64_t value)
     switch (key) {
     case PP_OPT_GRID:
         if (value < 0 || value > 8192) return fail(PP_ERR_ARG, "grid must be in [0, 8192]");
-        op->grid_max = value == 0 ? GRID_DEFAULT : (int)value;
+        op->grid_max = value == 0 ? op->grid_auto : (int)value;
         return PP_OK;
     case PP_OPT_CHUNK:
         if (value < 0 || value > 4096) return fail(PP_ERR_ARG, "chunk must be in [0, 4096]");
