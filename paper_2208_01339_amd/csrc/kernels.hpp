@@ -270,14 +270,19 @@ __device__ __forceinline__ void for_my_elems(int64_t n, int L, int G, F fn)
 // operator kernels
 // ---------------------------------------------------------------------------
 
+// ---------------------------------------------------------------------------
+// phases: the body of each step of the solve for the rows owned by logical
+// workgroup L of G.  The stream-driven kernels below wrap one phase each; the
+// persistent driver chains them with grid-wide barriers.
+// ---------------------------------------------------------------------------
+
 // w_t = sum_p cm_tp x[col_p]  (trace phase of the Schur operator: M^{-1} C x,
 // with 1/m_t and the Jacobi column scaling folded into cm).  One thread per
 // trace row; rows are short (two entries).
 template <typename T, typename XT>
-__global__ __launch_bounds__(BLOCK) void k_trace(CsrView Cm, const XT *__restrict__ x,
-                                                 T *__restrict__ w, const State *st)
+__device__ __forceinline__ void ph_trace(const CsrView &Cm, const XT *__restrict__ x, T *__restrict__ w,
+                                         int L, int G)
 {
-    PPK_PROLOGUE(st)
     for_my_elems(Cm.rows, L, G, [&](int64_t t) {
         T acc = (T)0;
         const T *v = (const T *)Cm.val;
@@ -286,38 +291,21 @@ __global__ __launch_bounds__(BLOCK) void k_trace(CsrView Cm, const XT *__restric
     });
 }
 
-// y = A x (plain SpMV in the slice layout).
-template <typename T, bool SCHUR>
-__global__ __launch_bounds__(BLOCK) void k_spmv(SellView A, const T *__restrict__ x,
-                                                const T *__restrict__ w, T *__restrict__ y, int nt)
-{
-    const int G = (int)gridDim.x;
-    const int L = xcd_remap((int)blockIdx.x, G);
-    for_my_slices(A.nslices, L, G, [&](int64_t row, int64_t s, int lane) {
-        int64_t base; int width; slice_span(A, s, base, width);
-        T a = sell_row<T, T, SCHUR>(A, x, w, base, width, lane);
-        if (row < A.n) y[row] = a;
-    });
-}
-
 // One step of Algorithm 2, fused with the operator application:
 //   out = ax * x_i + aold * sold_i + ar * r_i + aA * (A x)_i
 // MODE 1 (first step):  x = r gathered, coefficients (0, 0, 4 rho1/delta, -2 rho1/(delta theta))
 // MODE 2 (second step): x = s_1, s_0 = r/theta folded into ar
 // MODE 3 (j >= 3):      x = s_{j-1}, sold = s_{j-2}
-// DOT: also reduce r.out (r read as RT, exact double product) -> FIN_RHO/FIN_RHO0.
+// DOT: return this workgroup's share of r.out (r read as RT, double products).
 // SCALE: out *= dis_i (pp_apply with Jacobi returns D^{-1/2} s_k).
 // out may alias sold (each thread reads sold_i before writing out_i).
 template <typename T, typename XT, typename RT, typename OT, int MODE, bool SCHUR, bool DOT, bool SCALE,
           bool NT>
-__global__ __launch_bounds__(BLOCK) void k_cheb(SellView A, const XT *__restrict__ xg,
-                                                const T *__restrict__ w, const RT *__restrict__ r,
-                                                const T *sold, OT *out, double cx, double cold,
-                                                double cr, double cA, const double *__restrict__ dis,
-                                                double *partials, State *st, int fin, int nt)
+__device__ __forceinline__ double ph_cheb(const SellView &A, const XT *__restrict__ xg,
+                                          const T *__restrict__ w, const RT *__restrict__ r,
+                                          const T *sold, OT *out, T ax, T aold, T ar, T aA,
+                                          const double *__restrict__ dis, int L, int G)
 {
-    PPK_PROLOGUE(st)
-    const T ax = (T)cx, aold = (T)cold, ar = (T)cr, aA = (T)cA;
     double part = 0.0;
     for_my_slices(A.nslices, L, G, [&](int64_t row, int64_t s, int lane) {
         int64_t base;
@@ -340,12 +328,148 @@ __global__ __launch_bounds__(BLOCK) void k_cheb(SellView A, const XT *__restrict
             if (DOT) part += (double)ri * (double)ov;
         }
     });
-    if (DOT) commit_partial(part, partials, st, fin, 0, L, G);
+    return part;
+}
+
+// bh = dis .* b, xh = x ./ dis; returns the share of bh.bh
+__device__ __forceinline__ double ph_init_scale(int64_t n, const double *__restrict__ b,
+                                                const double *__restrict__ x,
+                                                const double *__restrict__ dis, double *__restrict__ bh,
+                                                double *__restrict__ xh, int L, int G)
+{
+    double part = 0.0;
+    for_my_elems(n, L, G, [&](int64_t i) {
+        const double d = dis ? dis[i] : 1.0;
+        const double bi = d * b[i];
+        bh[i] = bi;
+        xh[i] = x[i] / d;
+        part += bi * bi;
+    });
+    return part;
+}
+
+// r = bh - A xh; returns the share of r.r
+template <bool SCHUR>
+__device__ __forceinline__ double ph_init_resid(const SellView &A, const double *__restrict__ xh,
+                                                const double *__restrict__ w, const double *__restrict__ bh,
+                                                double *__restrict__ r, int L, int G)
+{
+    double part = 0.0;
+    for_my_slices(A.nslices, L, G, [&](int64_t row, int64_t s, int lane) {
+        int64_t base; int width; slice_span(A, s, base, width);
+        double a = sell_row<double, double, SCHUR>(A, xh, w, base, width, lane);
+        if (row < A.n) {
+            const double ri = bh[row] - a;
+            r[row] = ri;
+            part += ri * ri;
+        }
+    });
+    return part;
+}
+
+// q = A p; returns the share of p.q
+template <bool SCHUR, bool NT>
+__device__ __forceinline__ double ph_pq(const SellView &A, const double *__restrict__ p,
+                                        const double *__restrict__ w, double *__restrict__ q, int L, int G)
+{
+    double part = 0.0;
+    for_my_slices(A.nslices, L, G, [&](int64_t row, int64_t s, int lane) {
+        int64_t base; int width; slice_span(A, s, base, width);
+        const int64_t rc = row < A.n ? row : A.n - 1;
+        const double pi = p[rc];
+        double a = sell_row<double, double, SCHUR, NT>(A, p, w, base, width, lane);
+        if (row < A.n) {
+            q[row] = a;
+            part += pi * a;
+        }
+    });
+    return part;
+}
+
+// x += alpha p; r -= alpha q; returns the share of r.r
+__device__ __forceinline__ double ph_xr(int64_t n, const double *__restrict__ p, const double *__restrict__ q,
+                                        double *__restrict__ x, double *__restrict__ r, double alpha, int L,
+                                        int G)
+{
+    double part = 0.0;
+    for_my_elems(n, L, G, [&](int64_t i) {
+        x[i] = x[i] + alpha * p[i];
+        const double ri = r[i] - alpha * q[i];
+        r[i] = ri;
+        part += ri * ri;
+    });
+    return part;
+}
+
+// p = z + beta p   (first: p = z)
+__device__ __forceinline__ void ph_p(int64_t n, const double *__restrict__ z, double *__restrict__ p,
+                                     double beta, bool first, int L, int G)
+{
+    for_my_elems(n, L, G, [&](int64_t i) { p[i] = first ? z[i] : z[i] + beta * p[i]; });
+}
+
+// x = dis .* xh (or 0 when b_hat == 0)
+__device__ __forceinline__ void ph_final_x(int64_t n, const double *__restrict__ xh,
+                                           const double *__restrict__ dis, double *__restrict__ x, bool zb,
+                                           int L, int G)
+{
+    for_my_elems(n, L, G, [&](int64_t i) { x[i] = zb ? 0.0 : (dis ? dis[i] : 1.0) * xh[i]; });
+}
+
+// y = c x (converting type); returns the share of x.y when DOT
+template <typename XT, typename YT, bool DOT>
+__device__ __forceinline__ double ph_scale(int64_t n, const XT *__restrict__ x, double c, YT *__restrict__ y,
+                                           int L, int G)
+{
+    double part = 0.0;
+    for_my_elems(n, L, G, [&](int64_t i) {
+        const double xi = (double)x[i];
+        const YT yi = (YT)(xi * c);
+        y[i] = yi;
+        if (DOT) part += xi * (double)yi;
+    });
+    return part;
 }
 
 // ---------------------------------------------------------------------------
-// CG kernels
+// stream-driven kernels: one phase per launch
 // ---------------------------------------------------------------------------
+
+template <typename T, typename XT>
+__global__ __launch_bounds__(BLOCK) void k_trace(CsrView Cm, const XT *__restrict__ x,
+                                                 T *__restrict__ w, const State *st)
+{
+    PPK_PROLOGUE(st)
+    ph_trace<T, XT>(Cm, x, w, L, G);
+}
+
+// y = A x (plain SpMV in the slice layout).
+template <typename T, bool SCHUR>
+__global__ __launch_bounds__(BLOCK) void k_spmv(SellView A, const T *__restrict__ x,
+                                                const T *__restrict__ w, T *__restrict__ y, int nt)
+{
+    const int G = (int)gridDim.x;
+    const int L = xcd_remap((int)blockIdx.x, G);
+    for_my_slices(A.nslices, L, G, [&](int64_t row, int64_t s, int lane) {
+        int64_t base; int width; slice_span(A, s, base, width);
+        T a = sell_row<T, T, SCHUR>(A, x, w, base, width, lane);
+        if (row < A.n) y[row] = a;
+    });
+}
+
+template <typename T, typename XT, typename RT, typename OT, int MODE, bool SCHUR, bool DOT, bool SCALE,
+          bool NT>
+__global__ __launch_bounds__(BLOCK) void k_cheb(SellView A, const XT *__restrict__ xg,
+                                                const T *__restrict__ w, const RT *__restrict__ r,
+                                                const T *sold, OT *out, double cx, double cold,
+                                                double cr, double cA, const double *__restrict__ dis,
+                                                double *partials, State *st, int fin, int nt)
+{
+    PPK_PROLOGUE(st)
+    const double part = ph_cheb<T, XT, RT, OT, MODE, SCHUR, DOT, SCALE, NT>(
+        A, xg, w, r, sold, out, (T)cx, (T)cold, (T)cr, (T)cA, dis, L, G);
+    if (DOT) commit_partial(part, partials, st, fin, 0, L, G);
+}
 
 __global__ __launch_bounds__(BLOCK) void k_state_init(State *st, double tol, int maxit)
 {
@@ -361,7 +485,6 @@ __global__ __launch_bounds__(BLOCK) void k_state_init(State *st, double tol, int
     }
 }
 
-// bh = dis .* b, xh = x ./ dis; reduce bh.bh -> FIN_BNORM
 __global__ __launch_bounds__(BLOCK) void k_init_scale(int64_t n, const double *__restrict__ b,
                                                       const double *__restrict__ x,
                                                       const double *__restrict__ dis,
@@ -369,18 +492,10 @@ __global__ __launch_bounds__(BLOCK) void k_init_scale(int64_t n, const double *_
                                                       double *partials, State *st)
 {
     PPK_PROLOGUE(st)
-    double part = 0.0;
-    for_my_elems(n, L, G, [&](int64_t i) {
-        const double d = dis ? dis[i] : 1.0;
-        const double bi = d * b[i];
-        bh[i] = bi;
-        xh[i] = x[i] / d;
-        part += bi * bi;
-    });
+    const double part = ph_init_scale(n, b, x, dis, bh, xh, L, G);
     commit_partial(part, partials, st, FIN_BNORM, 0, L, G);
 }
 
-// r = bh - A xh; reduce r.r -> FIN_RR0
 template <bool SCHUR>
 __global__ __launch_bounds__(BLOCK) void k_init_resid(SellView A, const double *__restrict__ xh,
                                                       const double *__restrict__ w,
@@ -389,73 +504,44 @@ __global__ __launch_bounds__(BLOCK) void k_init_resid(SellView A, const double *
                                                       State *st, int nt)
 {
     PPK_PROLOGUE(st)
-    double part = 0.0;
-    for_my_slices(A.nslices, L, G, [&](int64_t row, int64_t s, int lane) {
-        int64_t base; int width; slice_span(A, s, base, width);
-        double a = sell_row<double, double, SCHUR>(A, xh, w, base, width, lane);
-        if (row < A.n) {
-            const double ri = bh[row] - a;
-            r[row] = ri;
-            part += ri * ri;
-        }
-    });
+    const double part = ph_init_resid<SCHUR>(A, xh, w, bh, r, L, G);
     commit_partial(part, partials, st, FIN_RR0, 0, L, G);
 }
 
-// q = A p; reduce p.q -> FIN_GAMMA
 template <bool SCHUR>
 __global__ __launch_bounds__(BLOCK) void k_pq(SellView A, const double *__restrict__ p,
                                               const double *__restrict__ w, double *__restrict__ q,
                                               double *partials, State *st, int nt)
 {
     PPK_PROLOGUE(st)
-    double part = 0.0;
-    for_my_slices(A.nslices, L, G, [&](int64_t row, int64_t s, int lane) {
-        int64_t base; int width; slice_span(A, s, base, width);
-        double a = sell_row<double, double, SCHUR>(A, p, w, base, width, lane);
-        if (row < A.n) {
-            q[row] = a;
-            part += p[row] * a;
-        }
-    });
+    const double part = nt ? ph_pq<SCHUR, true>(A, p, w, q, L, G) : ph_pq<SCHUR, false>(A, p, w, q, L, G);
     commit_partial(part, partials, st, FIN_GAMMA, 0, L, G);
 }
 
-// x += alpha p; r -= alpha q; reduce r.r -> FIN_RR
 __global__ __launch_bounds__(BLOCK) void k_xr(int64_t n, const double *__restrict__ p,
                                               const double *__restrict__ q, double *__restrict__ x,
                                               double *__restrict__ r, double *partials, State *st)
 {
     PPK_PROLOGUE(st)
-    const double alpha = st->alpha;
-    double part = 0.0;
-    for_my_elems(n, L, G, [&](int64_t i) {
-        x[i] = x[i] + alpha * p[i];
-        const double ri = r[i] - alpha * q[i];
-        r[i] = ri;
-        part += ri * ri;
-    });
+    const double part = ph_xr(n, p, q, x, r, st->alpha, L, G);
     commit_partial(part, partials, st, FIN_RR, 0, L, G);
 }
 
-// p = z + beta p   (first=1: p = z)
 __global__ __launch_bounds__(BLOCK) void k_p(int64_t n, const double *__restrict__ z,
                                              double *__restrict__ p, const State *st, int first)
 {
     PPK_PROLOGUE(st)
-    const double beta = first ? 0.0 : st->beta;
-    for_my_elems(n, L, G, [&](int64_t i) { p[i] = first ? z[i] : z[i] + beta * p[i]; });
+    ph_p(n, z, p, first ? 0.0 : st->beta, first != 0, L, G);
 }
 
-// x = dis .* xh (or 0 when b_hat == 0); runs even when done is set.
+// runs even when done is set
 __global__ __launch_bounds__(BLOCK) void k_final_x(int64_t n, const double *__restrict__ xh,
                                                    const double *__restrict__ dis,
                                                    double *__restrict__ x, const State *st)
 {
     const int G = (int)gridDim.x;
     const int L = xcd_remap((int)blockIdx.x, G);
-    const int zb = st->zero_b;
-    for_my_elems(n, L, G, [&](int64_t i) { x[i] = zb ? 0.0 : (dis ? dis[i] : 1.0) * xh[i]; });
+    ph_final_x(n, xh, dis, x, st->zero_b != 0, L, G);
 }
 
 // ---------------------------------------------------------------------------

@@ -14,6 +14,7 @@
 
 #include "../../include/pp.h"
 #include "kernels.hpp"
+#include "persistent.hpp"
 #include "sym_eig.hpp"
 
 using ppk::BLOCK;
@@ -93,6 +94,10 @@ struct pp_op_s {
     double *sA = nullptr, *sB = nullptr;
     float *r32 = nullptr, *sA32 = nullptr, *sB32 = nullptr;
     double *partials = nullptr;
+    double *coef_d = nullptr;  // [k][4] step coefficients for the persistent driver
+    int coef_k = -1;           // degree the device coefficients were uploaded for
+    std::vector<double> coef_h;
+    int persist_occ[4] = {0, 0, 0, 0};
     ppk::State *st = nullptr;
     ppk::State *hst = nullptr;  // pinned
     int32_t *hflag = nullptr;   // pinned, 2 slots
@@ -109,7 +114,7 @@ struct pp_op_s {
     int grid_auto = GRID_DEFAULT;  // resident workgroups of the fused step (CUs x occupancy)
     int chunk = 0;  // 0 = auto
     int timing = 0;
-    int driver = 0;
+    int driver = -1;  // -1 auto, 0 stream-driven, 1 persistent
     int ntload = 1;
     pp_stats stats{};
 
@@ -154,7 +159,7 @@ struct pp_op_s {
         dfree(dis);
         dfree(xh); dfree(r); dfree(p); dfree(q); dfree(z); dfree(bh); dfree(sA); dfree(sB);
         dfree(r32); dfree(sA32); dfree(sB32);
-        dfree(partials); dfree(st);
+        dfree(partials); dfree(coef_d); dfree(st);
         if (hst) (void)hipHostFree(hst);
         if (hflag) (void)hipHostFree(hflag);
         hst = nullptr;
@@ -312,7 +317,7 @@ pp_status build_operator(pp_op_s *op, const int64_t *rp, const int32_t *col, con
             op->sA32 = dalloc<float>(n);
             op->sB32 = dalloc<float>(n);
         }
-        op->partials = dalloc<double>(std::max(op->grid_max, 8192));
+        op->partials = dalloc<double>(2 * 8192);
         op->st = dalloc<ppk::State>(1);
         HIPCHK(hipMemsetAsync(op->st, 0, sizeof(ppk::State), op->stream));
         HIPCHK(hipHostMalloc((void **)&op->hst, sizeof(ppk::State), hipHostMallocDefault));
@@ -575,6 +580,91 @@ pp_status hip_fail(const HipError &e)
 
 }  // namespace
 
+namespace {
+
+template <bool SCHUR, bool MIXED>
+const void *persistent_kernel()
+{
+    return (const void *)ppk::k_pcg_persistent<SCHUR, MIXED>;
+}
+
+const void *pick_persistent(const pp_op_s *op, int *slot)
+{
+    *slot = (op->schur() ? 2 : 0) + (op->mixed() ? 1 : 0);
+    switch (*slot) {
+    case 0: return persistent_kernel<false, false>();
+    case 1: return persistent_kernel<false, true>();
+    case 2: return persistent_kernel<true, false>();
+    default: return persistent_kernel<true, true>();
+    }
+}
+
+// Whole solve in one cooperative launch.  Returns false (nothing queued) when
+// the runtime refuses the cooperative grid; the caller then uses the
+// stream-driven kernels.
+bool persistent_solve(pp_op_s *op, const double *b, double *x, double tol, int maxit)
+{
+    int slot = 0;
+    const void *fn = pick_persistent(op, &slot);
+    if (op->persist_occ[slot] == 0) {
+        int occ = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, BLOCK, 0) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, op->device) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        op->persist_occ[slot] = std::max(0, occ) * std::max(0, cus);
+    }
+    int G = (int)std::min<int64_t>({(int64_t)op->persist_occ[slot], (op->nslices + WPB - 1) / WPB, 8192,
+                                    (int64_t)op->grid_max});
+    if (G < 1) return false;
+    const int k = op->k;
+    if (op->coef_k != k) {
+        op->coef_h.assign((size_t)std::max(1, 4 * k), 0.0);
+        for (int j = 1; j <= k; ++j) {
+            const StepCoef c = step_coef(op, j);
+            op->coef_h[4 * (j - 1) + 0] = c.cx;
+            op->coef_h[4 * (j - 1) + 1] = c.cold;
+            op->coef_h[4 * (j - 1) + 2] = c.cr;
+            op->coef_h[4 * (j - 1) + 3] = c.cA;
+        }
+        dfree(op->coef_d);
+        op->coef_d = dalloc<double>(op->coef_h.size());
+        HIPCHK(hipMemcpyAsync(op->coef_d, op->coef_h.data(), sizeof(double) * op->coef_h.size(),
+                              hipMemcpyHostToDevice, op->stream));
+        HIPCHK(hipStreamSynchronize(op->stream));
+        op->coef_k = k;
+    }
+    ppk::PersistArgs a;
+    a.A = op->view(false);
+    a.A32 = op->view(op->mixed());
+    a.Cm = op->cview(false);
+    a.Cm32 = op->cview(op->mixed());
+    a.b = b;
+    a.x = x;
+    a.dis = op->dis;
+    a.bh = op->bh; a.xh = op->xh; a.r = op->r; a.p = op->p; a.q = op->q; a.z = op->z;
+    a.sA = op->sA; a.sB = op->sB; a.tw = op->tw;
+    a.r32 = op->r32; a.sA32 = op->sA32; a.sB32 = op->sB32; a.tw32 = op->tw32;
+    a.coef = op->coef_d;
+    a.partials = op->partials;
+    a.st = op->st;
+    a.theta_inv = 1.0 / op->theta;
+    a.tol = tol;
+    a.k = k;
+    a.maxit = maxit;
+    void *args[] = {&a};
+    hipError_t e = hipLaunchCooperativeKernel(fn, dim3(G), dim3(BLOCK), args, 0, op->stream);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    op->stats.grid = G;
+    return true;
+}
+
+}  // namespace
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -657,8 +747,8 @@ pp_status pp_set_option(pp_op op, int key, int64_t value)
         return PP_OK;
     case PP_OPT_TIMING: op->timing = value != 0; return PP_OK;
     case PP_OPT_DRIVER:
-        if (value != 0 && value != -1) return fail(PP_ERR_ARG, "driver: only 0 (stream-driven) or -1 (auto)");
-        op->driver = 0;
+        if (value < -1 || value > 1) return fail(PP_ERR_ARG, "driver: 0 (stream-driven), 1 (persistent), -1 (auto)");
+        op->driver = (int)value;
         return PP_OK;
     case PP_OPT_NT_LOADS: op->ntload = value != 0; return PP_OK;
     default: return fail(PP_ERR_ARG, "unknown option");
@@ -738,50 +828,57 @@ pp_status pcg_solve(pp_op op, const double *b, double *x, double tol, int maxit,
         const int gs = op->grid_slices(), ge = op->grid_elems(n);
         HIPCHK(hipEventRecord(op->solve_ev[0], op->stream));
         hipLaunchKernelGGL(ppk::k_state_init, dim3(1), dim3(64), 0, op->stream, op->st, tol, maxit);
-        hipLaunchKernelGGL(ppk::k_init_scale, dim3(ge), dim3(BLOCK), 0, op->stream, n, b, (const double *)x,
-                           (const double *)op->dis, op->bh, op->xh, op->partials, op->st);
-        enqueue_trace_f64(op, op->xh);
-        if (op->schur())
-            hipLaunchKernelGGL(ppk::k_init_resid<true>, dim3(gs), dim3(BLOCK), 0, op->stream, op->view(false),
-                               (const double *)op->xh, (const double *)op->tw, (const double *)op->bh, op->r,
-                               op->partials, op->st, op->ntload);
-        else
-            hipLaunchKernelGGL(ppk::k_init_resid<false>, dim3(gs), dim3(BLOCK), 0, op->stream, op->view(false),
-                               (const double *)op->xh, (const double *)nullptr, (const double *)op->bh, op->r,
-                               op->partials, op->st, op->ntload);
+        // persistent driver on request only: its grid-wide barriers cost more
+        // than kernel boundaries on this chip at every size measured (each
+        // barrier serialises one same-address atomic per workgroup)
+        const bool want_persist = op->driver == 1;
+        bool persisted = want_persist && persistent_solve(op, b, x, tol, maxit);
         size_t ev_i = 0;
-        hipEvent_t e0 = op->timing ? timing_event(op, ev_i++) : nullptr;
-        hipEvent_t e1 = op->timing ? timing_event(op, ev_i++) : nullptr;
-        if (e0) HIPCHK(hipEventRecord(e0, op->stream));
-        enqueue_poly(op, op->r, op->z, ppk::FIN_RHO0, false);
-        if (e1) HIPCHK(hipEventRecord(e1, op->stream));
-        hipLaunchKernelGGL(ppk::k_p, dim3(ge), dim3(BLOCK), 0, op->stream, n, (const double *)op->z, op->p,
-                           (const ppk::State *)op->st, 1);
-        HIPCHK(hipGetLastError());
-
-        int chunk = op->chunk;
-        if (chunk <= 0) chunk = n >= (1 << 20) ? 1 : (n >= (1 << 16) ? 4 : 16);
-        int enq = 0, c = 0;
-        while (enq < maxit) {
-            const int m = std::min(chunk, maxit - enq);
-            for (int i = 0; i < m; ++i) {
-                hipEvent_t a = op->timing ? timing_event(op, ev_i++) : nullptr;
-                hipEvent_t bb = op->timing ? timing_event(op, ev_i++) : nullptr;
-                enqueue_iteration(op, a, bb);
-            }
+        if (!persisted) {
+            hipLaunchKernelGGL(ppk::k_init_scale, dim3(ge), dim3(BLOCK), 0, op->stream, n, b, (const double *)x,
+                               (const double *)op->dis, op->bh, op->xh, op->partials, op->st);
+            enqueue_trace_f64(op, op->xh);
+            if (op->schur())
+                hipLaunchKernelGGL(ppk::k_init_resid<true>, dim3(gs), dim3(BLOCK), 0, op->stream, op->view(false),
+                                   (const double *)op->xh, (const double *)op->tw, (const double *)op->bh, op->r,
+                                   op->partials, op->st, op->ntload);
+            else
+                hipLaunchKernelGGL(ppk::k_init_resid<false>, dim3(gs), dim3(BLOCK), 0, op->stream, op->view(false),
+                                   (const double *)op->xh, (const double *)nullptr, (const double *)op->bh, op->r,
+                                   op->partials, op->st, op->ntload);
+            hipEvent_t e0 = op->timing ? timing_event(op, ev_i++) : nullptr;
+            hipEvent_t e1 = op->timing ? timing_event(op, ev_i++) : nullptr;
+            if (e0) HIPCHK(hipEventRecord(e0, op->stream));
+            enqueue_poly(op, op->r, op->z, ppk::FIN_RHO0, false);
+            if (e1) HIPCHK(hipEventRecord(e1, op->stream));
+            hipLaunchKernelGGL(ppk::k_p, dim3(ge), dim3(BLOCK), 0, op->stream, n, (const double *)op->z, op->p,
+                               (const ppk::State *)op->st, 1);
             HIPCHK(hipGetLastError());
-            enq += m;
-            HIPCHK(hipMemcpyAsync(&op->hflag[c & 1], &op->st->done, sizeof(int32_t), hipMemcpyDeviceToHost,
-                                  op->stream));
-            HIPCHK(hipEventRecord(op->flag_ev[c & 1], op->stream));
-            if (c >= 1) {
-                HIPCHK(hipEventSynchronize(op->flag_ev[(c - 1) & 1]));
-                if (op->hflag[(c - 1) & 1]) break;
+
+            int chunk = op->chunk;
+            if (chunk <= 0) chunk = n >= (1 << 20) ? 1 : (n >= (1 << 16) ? 4 : 16);
+            int enq = 0, c = 0;
+            while (enq < maxit) {
+                const int m = std::min(chunk, maxit - enq);
+                for (int i = 0; i < m; ++i) {
+                    hipEvent_t a = op->timing ? timing_event(op, ev_i++) : nullptr;
+                    hipEvent_t bb = op->timing ? timing_event(op, ev_i++) : nullptr;
+                    enqueue_iteration(op, a, bb);
+                }
+                HIPCHK(hipGetLastError());
+                enq += m;
+                HIPCHK(hipMemcpyAsync(&op->hflag[c & 1], &op->st->done, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                      op->stream));
+                HIPCHK(hipEventRecord(op->flag_ev[c & 1], op->stream));
+                if (c >= 1) {
+                    HIPCHK(hipEventSynchronize(op->flag_ev[(c - 1) & 1]));
+                    if (op->hflag[(c - 1) & 1]) break;
+                }
+                ++c;
             }
-            ++c;
+            hipLaunchKernelGGL(ppk::k_final_x, dim3(ge), dim3(BLOCK), 0, op->stream, n, (const double *)op->xh,
+                               (const double *)op->dis, x, (const ppk::State *)op->st);
         }
-        hipLaunchKernelGGL(ppk::k_final_x, dim3(ge), dim3(BLOCK), 0, op->stream, n, (const double *)op->xh,
-                           (const double *)op->dis, x, (const ppk::State *)op->st);
         HIPCHK(hipGetLastError());
         HIPCHK(hipEventRecord(op->solve_ev[1], op->stream));
         HIPCHK(hipMemcpyAsync(op->hst, op->st, sizeof(ppk::State), hipMemcpyDeviceToHost, op->stream));
@@ -806,8 +903,8 @@ pp_status pcg_solve(pp_op op, const double *b, double *x, double tol, int maxit,
         op->stats.solve_ms = ms;
         op->stats.cheb_ms = 0;
         op->stats.cheb_steps = 0;
-        op->stats.driver = 0;
-        op->stats.grid = gs;
+        op->stats.driver = persisted ? 1 : 0;
+        if (!persisted) op->stats.grid = gs;
         if (op->timing && !s.zero_b) {
             // pairs 0 .. polys-1 ran (the initial one and one per iteration but the last)
             double tot = 0;

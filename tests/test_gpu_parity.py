@@ -150,8 +150,9 @@ PCG_CASES = [
 ]
 
 
+@pytest.mark.parametrize("driver", [0, 1], ids=["stream", "persistent"])
 @pytest.mark.parametrize("name,builder,jacobi,k,xi", PCG_CASES, ids=[c[0] for c in PCG_CASES])
-def test_pcg_parity(B, name, builder, jacobi, k, xi):
+def test_pcg_parity(B, name, builder, jacobi, k, xi, driver):
     a, s = builder()
     orc = make_oracle(a, s, jacobi)
     n = orc.n
@@ -160,10 +161,12 @@ def test_pcg_parity(B, name, builder, jacobi, k, xi):
     xo, sto = O.pcg(orc, k, lmin, lmax, xi, b, tol=1e-8, maxit=5000)
     assert sto["status"] == O.OK
     op = make_op(B, a, s, B.PP_JACOBI if jacobi else 0)
+    B.pp_set_option(op.handle, B.PP_OPT_DRIVER, driver)
     B.pp_setup(op.handle, k, lmin, lmax, xi)
     bd = dev(b)
     x = torch.zeros(n, dtype=torch.float64, device="cuda")
     status, it, rel = B.pcg_solve(op.handle, bd, x, 1e-8, 5000)
+    assert B.pp_get_stats(op.handle)["driver"] == driver
     assert status == B.PP_OK
     assert abs(it - sto["iters"]) <= 2, (it, sto["iters"])
     assert rel <= 1e-8
@@ -180,11 +183,13 @@ def test_pcg_parity(B, name, builder, jacobi, k, xi):
     op.close()
 
 
-def test_pcg_edge_cases(B):
+@pytest.mark.parametrize("driver", [0, 1], ids=["stream", "persistent"])
+def test_pcg_edge_cases(B, driver):
     a = W.poisson3d(10)
     orc = O.Operator(a)
     n = orc.n
     op = make_op(B, a, None, 0)
+    B.pp_set_option(op.handle, B.PP_OPT_DRIVER, driver)
     B.pp_setup(op.handle, 4, 0.2, 12.0, 0.0)
     # b = 0 -> x = 0, no iteration
     x = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -224,7 +229,8 @@ def test_pcg_edge_cases(B):
     op.close()
 
 
-def test_odd_degree_bad_bounds_breakdown(B):
+@pytest.mark.parametrize("driver", [0, 1], ids=["stream", "persistent"])
+def test_odd_degree_bad_bounds_breakdown(B, driver):
     """Odd k with lambda_max far too small makes P indefinite (p_k < 0 beyond 2 theta-bar)."""
     a = W.poisson3d(12)
     orc = O.Operator(a)
@@ -232,6 +238,7 @@ def test_odd_degree_bad_bounds_breakdown(B):
     lmin, lmax = 0.05, 2.0  # true lambda_max ~ 11.7 > 2 theta-bar
     xo, sto = O.pcg(orc, 9, lmin, lmax, 0.0, b, tol=1e-8, maxit=300)
     op = make_op(B, a, None, 0)
+    B.pp_set_option(op.handle, B.PP_OPT_DRIVER, driver)
     B.pp_setup(op.handle, 9, lmin, lmax, 0.0)
     x = torch.zeros(orc.n, dtype=torch.float64, device="cuda")
     s, it, rel = B.pcg_solve(op.handle, dev(b), x, 1e-8, 300)
@@ -285,6 +292,7 @@ def test_config0_end_to_end(B):
     op = make_op(B, a, None, 0)
     lo, hi = B.pp_estimate_bounds(op.handle, 20)
     B.pp_setup(op.handle, 10, lo, hi, 0.0)
+    assert abs(lo - lo_r) <= 1e-7 * hi_r and abs(hi - hi_r) <= 1e-7 * hi_r
     x = torch.zeros(orc.n, dtype=torch.float64, device="cuda")
     s, it, rel = B.pcg_solve(op.handle, dev(b), x, 1e-8, 1000)
     assert s == B.PP_OK and abs(it - sto["iters"]) <= 2
@@ -299,8 +307,9 @@ def test_config0_end_to_end(B):
 # mixed precision (FP32 polynomial, FP64 CG)
 # ---------------------------------------------------------------------------
 
+@pytest.mark.parametrize("driver", [0, 1], ids=["stream", "persistent"])
 @pytest.mark.parametrize("name,builder,jacobi,k,xi", PCG_CASES[:4] + PCG_CASES[5:], ids=[c[0] for c in PCG_CASES[:4] + PCG_CASES[5:]])
-def test_mixed_pcg_residual(B, name, builder, jacobi, k, xi):
+def test_mixed_pcg_residual(B, name, builder, jacobi, k, xi, driver):
     a, s = builder()
     orc = make_oracle(a, s, jacobi)
     n = orc.n
@@ -308,9 +317,11 @@ def test_mixed_pcg_residual(B, name, builder, jacobi, k, xi):
     lmin, lmax = O.lanczos_bounds(orc, 20)
     xo, sto = O.pcg(orc, k, lmin, lmax, xi, b, tol=1e-8, maxit=5000)
     op = make_op(B, a, s, (B.PP_JACOBI if jacobi else 0) | B.PP_MIXED)
+    B.pp_set_option(op.handle, B.PP_OPT_DRIVER, driver)
     B.pp_setup(op.handle, k, lmin, lmax, xi)
     x = torch.zeros(n, dtype=torch.float64, device="cuda")
     status, it, rel = B.pcg_solve(op.handle, dev(b), x, 1e-8, 5000)
+    assert B.pp_get_stats(op.handle)["driver"] == driver
     assert status == B.PP_OK and rel <= 1e-8
     assert abs(it - sto["iters"]) <= 2, (it, sto["iters"])
     got = host(x)
@@ -342,3 +353,24 @@ def test_mixed_pp_apply_close(B, jacobi):
         err = np.linalg.norm(host(z) - ref) / np.linalg.norm(ref)
         assert err <= 1e-4, (k, err)
     op.close()
+
+
+def test_drivers_agree_bitwise_iterations(B):
+    """Stream-driven and persistent drivers reduce in different partitions, so
+    iterates differ in the last bits; iteration counts may differ by one at most."""
+    a = W.hetero_diffusion(24, 2.0, 9)
+    orc = O.Operator(a, jacobi=True)
+    lmin, lmax = O.lanczos_bounds(orc, 20)
+    b = W.rhs_uniform(a.n_rows, 2)
+    res = []
+    for driver in (0, 1):
+        op = make_op(B, a, None, B.PP_JACOBI)
+        B.pp_set_option(op.handle, B.PP_OPT_DRIVER, driver)
+        B.pp_setup(op.handle, 12, lmin, lmax, 1e-3)
+        x = torch.zeros(a.n_rows, dtype=torch.float64, device="cuda")
+        s, it, rel = B.pcg_solve(op.handle, dev(b), x, 1e-10, 1000)
+        assert s == B.PP_OK
+        res.append((it, host(x)))
+        op.close()
+    assert abs(res[0][0] - res[1][0]) <= 1
+    assert np.linalg.norm(res[0][1] - res[1][1]) / np.linalg.norm(res[0][1]) < 1e-9
