@@ -175,6 +175,85 @@ enum {
 PP_API pp_status pp_set_option(pp_op op, int key, int64_t value);
 
 PP_API void pp_destroy(pp_op op);
+
+/* ------------------------------------------------------------------------
+ * Batches: many independent systems and/or a block of right-hand sides,
+ * solved together.  Each system keeps its own Jacobi scaling, bounds,
+ * polynomial and CG scalars; every right-hand side column runs its own CG
+ * (own alpha, beta, convergence test).  The matrix is read once per
+ * polynomial step for all columns (a sparse-matrix times block-of-vectors
+ * product), and one chunk of CG iterations is captured in a hipGraph and
+ * replayed until every (system, column) has finished.
+ * ------------------------------------------------------------------------ */
+typedef struct pp_batch_s *pp_batch;
+
+/*
+ * nsys systems given as ONE block-diagonal CSR matrix: the rows and columns of
+ * system s are sys_ptr[s] .. sys_ptr[s+1]-1 (sys_ptr: HOST array [nsys+1],
+ * sys_ptr[0] = 0, strictly increasing); an entry coupling two systems is
+ * rejected (PP_ERR_ARG).  rowptr [n+1] int64, colind [nnz] int32 (global
+ * column numbers), val [nnz] double, n = sys_ptr[nsys] (device arrays).
+ * nrhs in [1, 32]: width of the right-hand-side blocks (row-major [n][nrhs]).
+ * flags: PP_JACOBI, PP_MIXED (FP32 polynomial / SpMM, FP64 CG).
+ */
+PP_API pp_status pp_create_batch(pp_batch *out, int nsys, const int64_t *sys_ptr, int64_t nnz,
+                                 const int64_t *rowptr, const int32_t *colind, const double *val,
+                                 int nrhs, unsigned flags, void *stream);
+
+/* Lanczos bounds of every system (steps in [1, 64]); lambda_min, lambda_max:
+ * HOST arrays [nsys].  Same start vector and padding as pp_estimate_bounds. */
+PP_API pp_status pp_batch_estimate_bounds(pp_batch op, int steps, double *lambda_min,
+                                          double *lambda_max);
+
+/* Per-system polynomial (section 2.2 / eq. thetamod), degree k shared by all
+ * systems, bounds HOST arrays [nsys], one scaling for all. */
+PP_API pp_status pp_batch_setup(pp_batch op, int k, const double *lambda_min, const double *lambda_max,
+                                double scaling);
+
+/*
+ * Solve every system for every column: B, X device [n][nrhs] row-major
+ * (X: x0 in, solution out).  iters, relres, status: HOST arrays
+ * [nsys * nrhs] (index s * nrhs + c), may be NULL.  Returns PP_OK when every
+ * (system, column) converged, otherwise the worst status.  Synchronises.
+ */
+PP_API pp_status pcg_solve_batch(pp_batch op, const double *B, double *X, double tol, int maxit,
+                                 int *iters, double *relres, int *status);
+
+/* Z = P R for every system and column (device [n][nrhs]); asynchronous. */
+PP_API pp_status pp_batch_apply(pp_batch op, const double *R, double *Z);
+
+/*
+ * Layout of the block product: W lanes per row (64/W rows per wavefront),
+ * each lane handling (internal block width)/W columns.  W = 0 restores the
+ * default.  pp_batch_autotune times every supported W on a polynomial step
+ * and keeps the fastest (HOST output *best_w, *best_us).
+ */
+PP_API pp_status pp_batch_set_layout(pp_batch op, int w);
+PP_API pp_status pp_batch_autotune(pp_batch op, int *best_w, double *best_us);
+
+/* Batch options: PP_OPT_CHUNK (iterations per graph), PP_OPT_NT_LOADS, and
+ * PP_BOPT_GRAPH (1 = replay captured iteration chunks, 0 = launch eagerly). */
+enum { PP_BOPT_GRAPH = 100 };
+PP_API pp_status pp_batch_set_option(pp_batch op, int key, int64_t value);
+
+/* Sizes and last-solve timing: n rows, internal block width, stored matrix
+ * entries, workgroups per launch, solve device time (ms), polynomial steps. */
+typedef struct {
+    int64_t n;
+    int32_t nsys;
+    int32_t nb;
+    int32_t nrhs;
+    int32_t w;
+    int64_t nnz_stored;
+    int32_t grid;
+    int32_t graph;
+    double solve_ms;
+    int32_t max_iters;
+    int32_t pad;
+} pp_batch_stats;
+PP_API pp_status pp_batch_get_stats(pp_batch op, pp_batch_stats *st);
+
+PP_API void pp_destroy_batch(pp_batch op);
 PP_API const char *pp_status_str(pp_status s);
 PP_API const char *pp_last_error(void);
 

@@ -18,10 +18,14 @@ PP_ERR_ARG, PP_ERR_OOM, PP_ERR_HIP, PP_ERR_STATE = -1, -2, -3, -4
 PP_JACOBI, PP_MIXED = 1, 2
 PP_OPT_GRID, PP_OPT_CHUNK, PP_OPT_TIMING, PP_OPT_DRIVER, PP_OPT_NT_LOADS = 1, 2, 3, 4, 5
 
+PP_BOPT_GRAPH = 100
+
 ABI_FUNCTIONS = (
     "pp_create_csr", "pp_create_schur", "pp_setup", "pp_apply", "pcg_solve", "pp_estimate_bounds",
     "pp_operator_apply", "pp_get_stats", "pp_set_option", "pp_destroy", "pp_status_str",
-    "pp_last_error",
+    "pp_last_error", "pp_create_batch", "pp_batch_estimate_bounds", "pp_batch_setup",
+    "pcg_solve_batch", "pp_batch_apply", "pp_batch_set_layout", "pp_batch_autotune",
+    "pp_batch_set_option", "pp_batch_get_stats", "pp_destroy_batch",
 )
 
 
@@ -38,6 +42,14 @@ class pp_stats(C.Structure):
         ("cheb_steps", C.c_int64), ("solve_ms", C.c_double), ("n", C.c_int64),
         ("nnz_stored", C.c_int64), ("nnz_matrix", C.c_int64), ("driver", C.c_int32),
         ("grid", C.c_int32),
+    ]
+
+
+class pp_batch_stats(C.Structure):
+    _fields_ = [
+        ("n", C.c_int64), ("nsys", C.c_int32), ("nb", C.c_int32), ("nrhs", C.c_int32), ("w", C.c_int32),
+        ("nnz_stored", C.c_int64), ("grid", C.c_int32), ("graph", C.c_int32), ("solve_ms", C.c_double),
+        ("max_iters", C.c_int32), ("pad", C.c_int32),
     ]
 
 
@@ -68,8 +80,19 @@ def lib():
         L.pp_status_str.restype = C.c_char_p
         L.pp_last_error.argtypes = []
         L.pp_last_error.restype = C.c_char_p
+        L.pp_create_batch.argtypes = [C.POINTER(P), I32, P, I64, P, P, P, I32, C.c_uint, P]
+        L.pp_batch_estimate_bounds.argtypes = [P, I32, P, P]
+        L.pp_batch_setup.argtypes = [P, I32, P, P, D]
+        L.pcg_solve_batch.argtypes = [P, P, P, D, I32, P, P, P]
+        L.pp_batch_apply.argtypes = [P, P, P]
+        L.pp_batch_set_layout.argtypes = [P, I32]
+        L.pp_batch_autotune.argtypes = [P, C.POINTER(I32), C.POINTER(D)]
+        L.pp_batch_set_option.argtypes = [P, I32, I64]
+        L.pp_batch_get_stats.argtypes = [P, C.POINTER(pp_batch_stats)]
+        L.pp_destroy_batch.argtypes = [P]
+        L.pp_destroy_batch.restype = None
         for f in ABI_FUNCTIONS:
-            if f not in ("pp_destroy", "pp_status_str", "pp_last_error"):
+            if f not in ("pp_destroy", "pp_status_str", "pp_last_error", "pp_destroy_batch"):
                 getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -191,6 +214,120 @@ def pp_status_str(s):
 
 def pp_last_error():
     return lib().pp_last_error().decode()
+
+
+# ---------------------------------------------------------------------------
+# batches
+# ---------------------------------------------------------------------------
+
+def _hptr(a):
+    """Host pointer of a contiguous numpy array."""
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def pp_create_batch(nsys, sys_ptr, nnz, rowptr, colind, val, nrhs=1, flags=0, stream=None):
+    import numpy as np
+    import torch
+
+    sp = np.ascontiguousarray(sys_ptr, dtype=np.int64)
+    if sp.size != nsys + 1:
+        raise ValueError("sys_ptr must hold nsys + 1 entries")
+    _dtype_check(rowptr, torch.int64, "rowptr")
+    _dtype_check(colind, torch.int32, "colind")
+    _dtype_check(val, torch.float64, "val")
+    h = C.c_void_p()
+    _check(lib().pp_create_batch(C.byref(h), int(nsys), _hptr(sp), int(nnz), _ptr(rowptr), _ptr(colind),
+                                 _ptr(val), int(nrhs), int(flags), _stream(stream)))
+    return h
+
+
+def pp_batch_estimate_bounds(op, nsys, steps=20):
+    import numpy as np
+
+    lo = np.zeros(nsys)
+    hi = np.zeros(nsys)
+    _check(lib().pp_batch_estimate_bounds(op, int(steps), _hptr(lo), _hptr(hi)))
+    return lo, hi
+
+
+def pp_batch_setup(op, k, lambda_min, lambda_max, scaling=0.0):
+    import numpy as np
+
+    lo = np.ascontiguousarray(lambda_min, dtype=np.float64)
+    hi = np.ascontiguousarray(lambda_max, dtype=np.float64)
+    return _check(lib().pp_batch_setup(op, int(k), _hptr(lo), _hptr(hi), float(scaling)))
+
+
+def pcg_solve_batch(op, nsys, nrhs, B, X, tol=1e-8, maxit=1000):
+    """Returns (worst status, iters[nsys, nrhs], relres[nsys, nrhs], status[nsys, nrhs])."""
+    import numpy as np
+
+    it = np.zeros(nsys * nrhs, dtype=np.int32)
+    rel = np.zeros(nsys * nrhs)
+    stt = np.zeros(nsys * nrhs, dtype=np.int32)
+    s = lib().pcg_solve_batch(op, _ptr(B), _ptr(X), float(tol), int(maxit), _hptr(it), _hptr(rel), _hptr(stt))
+    _check(s, ok=(PP_OK, PP_NOT_CONVERGED, PP_BREAKDOWN))
+    return s, it.reshape(nsys, nrhs), rel.reshape(nsys, nrhs), stt.reshape(nsys, nrhs)
+
+
+def pp_batch_apply(op, R, Z):
+    return _check(lib().pp_batch_apply(op, _ptr(R), _ptr(Z)))
+
+
+def pp_batch_set_layout(op, w):
+    return _check(lib().pp_batch_set_layout(op, int(w)))
+
+
+def pp_batch_autotune(op):
+    w = C.c_int(0)
+    us = C.c_double(0.0)
+    _check(lib().pp_batch_autotune(op, C.byref(w), C.byref(us)))
+    return w.value, us.value
+
+
+def pp_batch_set_option(op, key, value):
+    return _check(lib().pp_batch_set_option(op, int(key), int(value)))
+
+
+def pp_batch_get_stats(op):
+    st = pp_batch_stats()
+    _check(lib().pp_batch_get_stats(op, C.byref(st)))
+    return {f: getattr(st, f) for f, _ in pp_batch_stats._fields_ if f != "pad"}
+
+
+def pp_destroy_batch(op):
+    if op:
+        lib().pp_destroy_batch(op)
+
+
+class BatchOperator:
+    """Owns a pp_batch built from a list of host CSR systems (block-diagonal stacking)."""
+
+    def __init__(self, systems, nrhs=1, flags=0, device="cuda:0", stream=None):
+        import torch
+
+        from .workloads import block_diag
+
+        a, sys_ptr = block_diag(systems)
+        dev = torch.device(device)
+        self.nsys = len(systems)
+        self.nrhs = nrhs
+        self.n = a.n_rows
+        self.sys_ptr = sys_ptr
+        self.handle = pp_create_batch(
+            self.nsys, sys_ptr, a.nnz, torch.from_numpy(a.rowptr).to(dev), torch.from_numpy(a.col).to(dev),
+            torch.from_numpy(a.val).to(dev), nrhs, flags, stream)
+
+    def close(self):
+        if self.handle:
+            pp_destroy_batch(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---------------------------------------------------------------------------

@@ -459,7 +459,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmv(SellView A, const T *__restrict_
 
 template <typename T, typename XT, typename RT, typename OT, int MODE, bool SCHUR, bool DOT, bool SCALE,
           bool NT>
-__global__ __launch_bounds__(BLOCK) void k_cheb(SellView A, const XT *__restrict__ xg,
+static __global__ __launch_bounds__(BLOCK) void k_cheb(SellView A, const XT *__restrict__ xg,
                                                 const T *__restrict__ w, const RT *__restrict__ r,
                                                 const T *sold, OT *out, double cx, double cold,
                                                 double cr, double cA, const double *__restrict__ dis,
@@ -471,7 +471,7 @@ __global__ __launch_bounds__(BLOCK) void k_cheb(SellView A, const XT *__restrict
     if (DOT) commit_partial(part, partials, st, fin, 0, L, G);
 }
 
-__global__ __launch_bounds__(BLOCK) void k_state_init(State *st, double tol, int maxit)
+static __global__ __launch_bounds__(BLOCK) void k_state_init(State *st, double tol, int maxit)
 {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->rho = st->alpha = st->beta = st->gamma = st->rr = st->bnorm2 = st->tol2 = 0.0;
@@ -485,7 +485,7 @@ __global__ __launch_bounds__(BLOCK) void k_state_init(State *st, double tol, int
     }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_init_scale(int64_t n, const double *__restrict__ b,
+static __global__ __launch_bounds__(BLOCK) void k_init_scale(int64_t n, const double *__restrict__ b,
                                                       const double *__restrict__ x,
                                                       const double *__restrict__ dis,
                                                       double *__restrict__ bh, double *__restrict__ xh,
@@ -518,7 +518,7 @@ __global__ __launch_bounds__(BLOCK) void k_pq(SellView A, const double *__restri
     commit_partial(part, partials, st, FIN_GAMMA, 0, L, G);
 }
 
-__global__ __launch_bounds__(BLOCK) void k_xr(int64_t n, const double *__restrict__ p,
+static __global__ __launch_bounds__(BLOCK) void k_xr(int64_t n, const double *__restrict__ p,
                                               const double *__restrict__ q, double *__restrict__ x,
                                               double *__restrict__ r, double *partials, State *st)
 {
@@ -527,7 +527,7 @@ __global__ __launch_bounds__(BLOCK) void k_xr(int64_t n, const double *__restric
     commit_partial(part, partials, st, FIN_RR, 0, L, G);
 }
 
-__global__ __launch_bounds__(BLOCK) void k_p(int64_t n, const double *__restrict__ z,
+static __global__ __launch_bounds__(BLOCK) void k_p(int64_t n, const double *__restrict__ z,
                                              double *__restrict__ p, const State *st, int first)
 {
     PPK_PROLOGUE(st)
@@ -535,7 +535,7 @@ __global__ __launch_bounds__(BLOCK) void k_p(int64_t n, const double *__restrict
 }
 
 // runs even when done is set
-__global__ __launch_bounds__(BLOCK) void k_final_x(int64_t n, const double *__restrict__ xh,
+static __global__ __launch_bounds__(BLOCK) void k_final_x(int64_t n, const double *__restrict__ xh,
                                                    const double *__restrict__ dis,
                                                    double *__restrict__ x, const State *st)
 {
@@ -564,7 +564,7 @@ __global__ __launch_bounds__(BLOCK) void k_scale(int64_t n, const XT *__restrict
 }
 
 // y = s .* s .* x * c   (k = 0 preconditioner with Jacobi)
-__global__ __launch_bounds__(BLOCK) void k_scale2(int64_t n, const double *__restrict__ x,
+static __global__ __launch_bounds__(BLOCK) void k_scale2(int64_t n, const double *__restrict__ x,
                                                   const double *__restrict__ s, double c,
                                                   double *__restrict__ y)
 {
@@ -577,7 +577,7 @@ __global__ __launch_bounds__(BLOCK) void k_scale2(int64_t n, const double *__res
 }
 
 // r.z into the CG state (degree-0 preconditioner: no operator step to fuse into)
-__global__ __launch_bounds__(BLOCK) void k_dot_fin(int64_t n, const double *__restrict__ x,
+static __global__ __launch_bounds__(BLOCK) void k_dot_fin(int64_t n, const double *__restrict__ x,
                                                    const double *__restrict__ y, double *partials,
                                                    State *st, int fin)
 {
@@ -588,7 +588,7 @@ __global__ __launch_bounds__(BLOCK) void k_dot_fin(int64_t n, const double *__re
 }
 
 // y = x ./ d
-__global__ __launch_bounds__(BLOCK) void k_div(int64_t n, const double *__restrict__ x,
+static __global__ __launch_bounds__(BLOCK) void k_div(int64_t n, const double *__restrict__ x,
                                                const double *__restrict__ d, double *__restrict__ y)
 {
     const int G = (int)gridDim.x;
@@ -611,7 +611,7 @@ __device__ __forceinline__ uint32_t fmix32(uint32_t h)
 }
 
 // v_i = fmix32(i) / 2^32 - 0.5 ; reduce v.v -> FIN_LZ_NORM0
-__global__ __launch_bounds__(BLOCK) void k_lz_start(int64_t n, double *__restrict__ v,
+static __global__ __launch_bounds__(BLOCK) void k_lz_start(int64_t n, double *__restrict__ v,
                                                     double *partials, State *st)
 {
     PPK_PROLOGUE(st)
@@ -625,7 +625,7 @@ __global__ __launch_bounds__(BLOCK) void k_lz_start(int64_t n, double *__restric
 }
 
 // v /= scratch[0]
-__global__ __launch_bounds__(BLOCK) void k_lz_norm(int64_t n, double *__restrict__ v, const State *st)
+static __global__ __launch_bounds__(BLOCK) void k_lz_norm(int64_t n, double *__restrict__ v, const State *st)
 {
     const int G = (int)gridDim.x;
     const int L = xcd_remap((int)blockIdx.x, G);
@@ -658,7 +658,7 @@ __global__ __launch_bounds__(BLOCK) void k_lz_apply(SellView A, const double *__
 }
 
 // w -= alpha_j v ; reduce w.w -> lz_beta[j]
-__global__ __launch_bounds__(BLOCK) void k_lz_orth(int64_t n, const double *__restrict__ v,
+static __global__ __launch_bounds__(BLOCK) void k_lz_orth(int64_t n, const double *__restrict__ v,
                                                    double *__restrict__ w, double *partials,
                                                    State *st, int j)
 {
@@ -675,7 +675,7 @@ __global__ __launch_bounds__(BLOCK) void k_lz_orth(int64_t n, const double *__re
 }
 
 // vprev = v ; v = w / beta_j
-__global__ __launch_bounds__(BLOCK) void k_lz_next(int64_t n, double *__restrict__ vprev,
+static __global__ __launch_bounds__(BLOCK) void k_lz_next(int64_t n, double *__restrict__ vprev,
                                                    double *__restrict__ v,
                                                    const double *__restrict__ w, const State *st,
                                                    int j)
@@ -694,7 +694,7 @@ __global__ __launch_bounds__(BLOCK) void k_lz_next(int64_t n, double *__restrict
 // ---------------------------------------------------------------------------
 
 // d_i = a_ii + sum over appended trace entries (c_ti^2 / m_t); flag non-positive.
-__global__ __launch_bounds__(BLOCK) void k_diag(int64_t n, const int64_t *__restrict__ rp,
+static __global__ __launch_bounds__(BLOCK) void k_diag(int64_t n, const int64_t *__restrict__ rp,
                                                 const int32_t *__restrict__ col,
                                                 const double *__restrict__ val,
                                                 const int64_t *__restrict__ ctp,
@@ -722,7 +722,7 @@ __global__ __launch_bounds__(BLOCK) void k_diag(int64_t n, const int64_t *__rest
 }
 
 // width of each slice = max over its rows of (row length + appended trace entries)
-__global__ __launch_bounds__(BLOCK) void k_slice_width(int64_t n, int64_t nslices,
+static __global__ __launch_bounds__(BLOCK) void k_slice_width(int64_t n, int64_t nslices,
                                                        const int64_t *__restrict__ rp,
                                                        const int64_t *__restrict__ ctp,
                                                        int64_t *__restrict__ width)
@@ -745,7 +745,7 @@ __global__ __launch_bounds__(BLOCK) void k_slice_width(int64_t n, int64_t nslice
 }
 
 // exclusive scan of width*64 into sp[0..nslices]; one workgroup, fixed order
-__global__ __launch_bounds__(1024) void k_scan_slices(int64_t nslices, const int64_t *__restrict__ width,
+static __global__ __launch_bounds__(1024) void k_scan_slices(int64_t nslices, const int64_t *__restrict__ width,
                                                       int64_t *__restrict__ sp)
 {
     __shared__ int64_t part[1024];
@@ -777,7 +777,7 @@ __global__ __launch_bounds__(1024) void k_scan_slices(int64_t nslices, const int
 
 // Fill the slice layout: scaled values a_ij dis_i dis_j, appended trace
 // entries (column nx + t, value c_ti dis_i), padding (own row, 0).
-__global__ __launch_bounds__(BLOCK) void k_slice_fill(int64_t n, int64_t nslices, int64_t nx,
+static __global__ __launch_bounds__(BLOCK) void k_slice_fill(int64_t n, int64_t nslices, int64_t nx,
                                                       const int64_t *__restrict__ rp,
                                                       const int32_t *__restrict__ col,
                                                       const double *__restrict__ val,
@@ -827,7 +827,7 @@ __global__ __launch_bounds__(BLOCK) void k_slice_fill(int64_t n, int64_t nslices
 }
 
 // Trace operator values: cm_tp = c_tp dis_{col} / m_t (and an FP32 copy).
-__global__ __launch_bounds__(BLOCK) void k_trace_fill(int64_t nt, const int64_t *__restrict__ crp,
+static __global__ __launch_bounds__(BLOCK) void k_trace_fill(int64_t nt, const int64_t *__restrict__ crp,
                                                       const int32_t *__restrict__ ccol,
                                                       const double *__restrict__ cval,
                                                       const double *__restrict__ m,
@@ -845,7 +845,7 @@ __global__ __launch_bounds__(BLOCK) void k_trace_fill(int64_t nt, const int64_t 
 }
 
 // validate CSR structure: monotone row pointers, columns in range
-__global__ __launch_bounds__(BLOCK) void k_check_csr(int64_t rows, int64_t ncols, int64_t nnz,
+static __global__ __launch_bounds__(BLOCK) void k_check_csr(int64_t rows, int64_t ncols, int64_t nnz,
                                                      const int64_t *__restrict__ rp,
                                                      const int32_t *__restrict__ col, int *bad)
 {

@@ -1,0 +1,818 @@
+// C-ABI implementation of the batch entry points of include/pp.h: many
+// independent systems and/or a block of right-hand sides per system.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <type_traits>
+#include <vector>
+
+#include "batch.hpp"
+#include "common.hpp"
+#include "sym_eig.hpp"
+
+using ppc::dalloc;
+using ppc::dfree;
+using ppc::fail;
+using ppc::hip_fail;
+using ppc::HipError;
+using ppk::BLOCK;
+using ppk::WAVE;
+using ppk::WPB;
+
+struct pp_batch_s {
+    int S = 0, NB = 1, nrhs = 1, W = 1, CPL = 1;
+    unsigned flags = 0;
+    hipStream_t ustream = nullptr;  // caller's stream
+    hipStream_t stream = nullptr;   // internal stream (capturable)
+    int device = 0;
+    int64_t n_ext = 0, nnz = 0, nslices = 0, n_int = 0, nstored = 0;
+    int G = 0;
+    std::vector<int64_t> sys_ptr, seg_row0_h, seg_n_h;
+    // maps
+    int32_t *blk_seg = nullptr, *seg_blk0 = nullptr, *slice_seg = nullptr;
+    int64_t *blk_s0 = nullptr, *blk_s1 = nullptr, *seg_row0 = nullptr, *seg_n = nullptr, *ext_row0 = nullptr;
+    // operator
+    int64_t *sp = nullptr;
+    int32_t *scol = nullptr;
+    double *sval = nullptr;
+    float *sval32 = nullptr;
+    double *dis = nullptr;
+    // vectors [n_int][NB]
+    double *Xh = nullptr, *R = nullptr, *P = nullptr, *Q = nullptr, *Z = nullptr, *Bh = nullptr;
+    double *SA64 = nullptr, *SB64 = nullptr;
+    float *R32 = nullptr, *SA = nullptr, *SB = nullptr;
+    double *partials = nullptr;
+    double *coef_d = nullptr, *thinv_d = nullptr;
+    // state
+    double *d_rho = nullptr, *d_alpha = nullptr, *d_beta = nullptr, *d_rr = nullptr, *d_bn2 = nullptr,
+           *d_tol2 = nullptr, *d_lz = nullptr;
+    int32_t *d_it = nullptr, *d_status = nullptr, *d_done = nullptr, *d_zero_b = nullptr, *d_seg_ndone = nullptr,
+            *d_seg_done = nullptr, *d_ndone = nullptr;
+    uint32_t *d_ticket = nullptr;
+    int32_t *h_ndone = nullptr;  // pinned [2]
+    hipEvent_t flag_ev[2] = {nullptr, nullptr};
+    hipEvent_t sync_ev = nullptr, solve_ev[2] = {nullptr, nullptr};
+    // polynomial
+    bool setup_done = false;
+    int k = 0;
+    double xi = 0;
+    std::vector<double> lmin, lmax;
+    // options
+    int chunk = 0, ntload = 1, use_graph = 1;
+    // captured iteration chunk
+    hipGraphExec_t gexec = nullptr;
+    int g_k = -1, g_chunk = -1, g_maxit = -1, g_W = -1;
+    double g_tol = -1.0;
+    pp_batch_stats stats{};
+
+    bool mixed() const { return (flags & PP_MIXED) != 0; }
+
+    ppb::Batch bt() const
+    {
+        ppb::Batch b;
+        b.blk_seg = blk_seg;
+        b.blk_s0 = blk_s0;
+        b.blk_s1 = blk_s1;
+        b.seg_blk0 = seg_blk0;
+        b.seg_row0 = seg_row0;
+        b.seg_n = seg_n;
+        b.ext_row0 = ext_row0;
+        b.S = S;
+        b.NB = NB;
+        b.nrhs = nrhs;
+        b.k = k;
+        return b;
+    }
+    ppb::BState bst(double tol, int maxit) const
+    {
+        ppb::BState s;
+        s.rho = d_rho; s.alpha = d_alpha; s.beta = d_beta; s.rr = d_rr; s.bn2 = d_bn2; s.tol2 = d_tol2;
+        s.lz = d_lz;
+        s.it = d_it; s.status = d_status; s.done = d_done; s.zero_b = d_zero_b;
+        s.seg_ndone = d_seg_ndone; s.seg_done = d_seg_done; s.ticket = d_ticket; s.ndone = d_ndone;
+        s.tol = tol;
+        s.maxit = maxit;
+        return s;
+    }
+    ppk::SellView view(bool f32) const
+    {
+        ppk::SellView v;
+        v.sp = sp;
+        v.col = scol;
+        v.val = f32 ? (const void *)sval32 : (const void *)sval;
+        v.n = n_int;
+        v.nslices = nslices;
+        v.nx = n_int;
+        return v;
+    }
+
+    void release()
+    {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        gexec = nullptr;
+        dfree(blk_seg); dfree(seg_blk0); dfree(slice_seg); dfree(blk_s0); dfree(blk_s1); dfree(seg_row0);
+        dfree(seg_n); dfree(ext_row0);
+        dfree(sp); dfree(scol); dfree(sval); dfree(sval32); dfree(dis);
+        dfree(Xh); dfree(R); dfree(P); dfree(Q); dfree(Z); dfree(Bh); dfree(SA64); dfree(SB64);
+        dfree(R32); dfree(SA); dfree(SB); dfree(partials); dfree(coef_d); dfree(thinv_d);
+        dfree(d_rho); dfree(d_alpha); dfree(d_beta); dfree(d_rr); dfree(d_bn2); dfree(d_tol2); dfree(d_lz);
+        dfree(d_it); dfree(d_status); dfree(d_done); dfree(d_zero_b); dfree(d_seg_ndone); dfree(d_seg_done);
+        dfree(d_ndone); dfree(d_ticket);
+        if (h_ndone) (void)hipHostFree(h_ndone);
+        h_ndone = nullptr;
+        for (auto &e : flag_ev) if (e) { (void)hipEventDestroy(e); e = nullptr; }
+        for (auto &e : solve_ev) if (e) { (void)hipEventDestroy(e); e = nullptr; }
+        if (sync_ev) (void)hipEventDestroy(sync_ev);
+        sync_ev = nullptr;
+        if (stream) (void)hipStreamDestroy(stream);
+        stream = nullptr;
+    }
+};
+
+namespace {
+
+template <int V>
+using IC = std::integral_constant<int, V>;
+
+// supported (W, CPL) layouts per internal block width NB
+bool layout_ok(int NB, int W)
+{
+    if (NB == 1) return W == 1;
+    if (NB == 8) return W == 8 || W == 4 || W == 2;
+    if (NB == 32) return W == 32 || W == 16 || W == 8;
+    return false;
+}
+
+template <class F>
+void with_layout(int W, int CPL, F &&f)
+{
+    if (W == 1 && CPL == 1) f(IC<1>{}, IC<1>{});
+    else if (W == 8 && CPL == 1) f(IC<8>{}, IC<1>{});
+    else if (W == 4 && CPL == 2) f(IC<4>{}, IC<2>{});
+    else if (W == 2 && CPL == 4) f(IC<2>{}, IC<4>{});
+    else if (W == 32 && CPL == 1) f(IC<32>{}, IC<1>{});
+    else if (W == 16 && CPL == 2) f(IC<16>{}, IC<2>{});
+    else if (W == 8 && CPL == 4) f(IC<8>{}, IC<4>{});
+}
+
+// caller stream -> internal stream ordering
+void begin_call(pp_batch_s *op)
+{
+    HIPCHK(hipEventRecord(op->sync_ev, op->ustream));
+    HIPCHK(hipStreamWaitEvent(op->stream, op->sync_ev, 0));
+}
+
+void end_call(pp_batch_s *op)
+{
+    HIPCHK(hipEventRecord(op->sync_ev, op->stream));
+    HIPCHK(hipStreamWaitEvent(op->ustream, op->sync_ev, 0));
+}
+
+pp_status build(pp_batch_s *op, const int64_t *rowptr, const int32_t *colind, const double *val)
+{
+    const int S = op->S;
+    int *flag_d = nullptr;
+    int64_t *width = nullptr;
+    auto cleanup = [&]() { dfree(flag_d); dfree(width); };
+    try {
+        HIPCHK(hipStreamCreateWithFlags(&op->stream, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&op->sync_ev, hipEventDisableTiming));
+        for (auto &e : op->flag_ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        for (auto &e : op->solve_ev) HIPCHK(hipEventCreate(&e));
+        begin_call(op);
+        // structure check of the whole CSR
+        flag_d = dalloc<int>(1);
+        HIPCHK(hipMemsetAsync(flag_d, 0, sizeof(int), op->stream));
+        hipLaunchKernelGGL(ppk::k_check_csr, dim3((unsigned)((op->n_ext + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0,
+                           op->stream, op->n_ext, op->n_ext, op->nnz, rowptr, colind, flag_d);
+        HIPCHK(hipGetLastError());
+        int h = 0;
+        HIPCHK(hipMemcpyAsync(&h, flag_d, sizeof(int), hipMemcpyDeviceToHost, op->stream));
+        HIPCHK(hipStreamSynchronize(op->stream));
+        if (h) { cleanup(); return fail(PP_ERR_ARG, "invalid CSR structure"); }
+
+        // segment layout: every system padded to whole slices
+        op->seg_row0_h.assign(S + 1, 0);
+        op->seg_n_h.assign(S, 0);
+        std::vector<int64_t> seg_sl0(S + 1, 0);
+        for (int s = 0; s < S; ++s) {
+            op->seg_n_h[s] = op->sys_ptr[s + 1] - op->sys_ptr[s];
+            const int64_t sl = (op->seg_n_h[s] + WAVE - 1) / WAVE;
+            seg_sl0[s + 1] = seg_sl0[s] + sl;
+            op->seg_row0_h[s + 1] = seg_sl0[s + 1] * WAVE;
+        }
+        op->nslices = seg_sl0[S];
+        op->n_int = op->nslices * WAVE;
+        if (op->n_int > (int64_t)INT32_MAX - 1) { cleanup(); return fail(PP_ERR_ARG, "padded rows exceed 2^31"); }
+        std::vector<int32_t> slice_seg(op->nslices);
+        for (int s = 0; s < S; ++s)
+            for (int64_t q = seg_sl0[s]; q < seg_sl0[s + 1]; ++q) slice_seg[q] = s;
+        // workgroups: proportional to slices, at least one per system, never two systems in one
+        int cus = 256;
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, op->device);
+        const int64_t target = (int64_t)cus * 8;
+        std::vector<int32_t> blk_seg, seg_blk0(S + 1, 0);
+        std::vector<int64_t> blk_s0, blk_s1;
+        for (int s = 0; s < S; ++s) {
+            const int64_t sl = seg_sl0[s + 1] - seg_sl0[s];
+            int64_t nb = (int64_t)std::llround((double)target * (double)sl / (double)op->nslices);
+            nb = std::max<int64_t>(1, std::min<int64_t>(nb, (sl + WPB - 1) / WPB));
+            for (int64_t i = 0; i < nb; ++i) {
+                blk_seg.push_back(s);
+                blk_s0.push_back(seg_sl0[s] + sl * i / nb);
+                blk_s1.push_back(seg_sl0[s] + sl * (i + 1) / nb);
+            }
+            seg_blk0[s + 1] = (int32_t)blk_seg.size();
+        }
+        op->G = (int)blk_seg.size();
+        auto upload = [&](auto *&dst, const auto &src) {
+            using T = typename std::remove_reference<decltype(src[0])>::type;
+            dst = dalloc<typename std::remove_const<T>::type>(src.size());
+            HIPCHK(hipMemcpyAsync(dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice, op->stream));
+        };
+        upload(op->blk_seg, blk_seg);
+        upload(op->blk_s0, blk_s0);
+        upload(op->blk_s1, blk_s1);
+        upload(op->seg_blk0, seg_blk0);
+        upload(op->seg_row0, op->seg_row0_h);
+        upload(op->seg_n, op->seg_n_h);
+        upload(op->ext_row0, op->sys_ptr);
+        upload(op->slice_seg, slice_seg);
+        HIPCHK(hipStreamSynchronize(op->stream));  // host vectors may go out of scope
+
+        // diagonal / Jacobi and block-diagonal check
+        op->dis = dalloc<double>(op->n_int);
+        HIPCHK(hipMemsetAsync(flag_d, 0, sizeof(int), op->stream));
+        hipLaunchKernelGGL(ppb::kb_diag, dim3((unsigned)((op->n_int + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, op->stream,
+                           op->nslices, (const int32_t *)op->slice_seg, (const int64_t *)op->seg_row0,
+                           (const int64_t *)op->seg_n, (const int64_t *)op->ext_row0, rowptr, colind, val, op->dis,
+                           (int)((op->flags & PP_JACOBI) != 0), flag_d);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(&h, flag_d, sizeof(int), hipMemcpyDeviceToHost, op->stream));
+        HIPCHK(hipStreamSynchronize(op->stream));
+        if (h & 8) { cleanup(); return fail(PP_ERR_ARG, "an entry couples two systems (matrix not block diagonal)"); }
+        if (h & 1) { cleanup(); return fail(PP_ERR_ARG, "Jacobi scaling needs a positive finite diagonal"); }
+
+        // slice layout
+        width = dalloc<int64_t>(op->nslices);
+        op->sp = dalloc<int64_t>(op->nslices + 1);
+        const unsigned gs = (unsigned)((op->nslices + WPB - 1) / WPB);
+        hipLaunchKernelGGL(ppb::kb_slice_width, dim3(gs), dim3(BLOCK), 0, op->stream, op->nslices,
+                           (const int32_t *)op->slice_seg, (const int64_t *)op->seg_row0, (const int64_t *)op->seg_n,
+                           (const int64_t *)op->ext_row0, rowptr, width);
+        hipLaunchKernelGGL(ppk::k_scan_slices, dim3(1), dim3(1024), 0, op->stream, op->nslices, (const int64_t *)width,
+                           op->sp);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(&op->nstored, op->sp + op->nslices, sizeof(int64_t), hipMemcpyDeviceToHost, op->stream));
+        HIPCHK(hipStreamSynchronize(op->stream));
+        op->scol = dalloc<int32_t>(op->nstored);
+        op->sval = dalloc<double>(op->nstored);
+        if (op->mixed()) op->sval32 = dalloc<float>(op->nstored);
+        hipLaunchKernelGGL(ppb::kb_slice_fill, dim3(gs), dim3(BLOCK), 0, op->stream, op->nslices,
+                           (const int32_t *)op->slice_seg, (const int64_t *)op->seg_row0, (const int64_t *)op->seg_n,
+                           (const int64_t *)op->ext_row0, rowptr, colind, val, (const double *)op->dis,
+                           (const int64_t *)op->sp, op->scol, op->sval, op->sval32,
+                           (int)((op->flags & PP_JACOBI) != 0));
+        HIPCHK(hipGetLastError());
+
+        // vectors (zeroed: padding rows and columns stay zero for good)
+        const size_t nv = (size_t)op->n_int * op->NB;
+        auto zalloc64 = [&](double *&p) {
+            p = dalloc<double>(nv);
+            HIPCHK(hipMemsetAsync(p, 0, nv * sizeof(double), op->stream));
+        };
+        auto zalloc32 = [&](float *&p) {
+            p = dalloc<float>(nv);
+            HIPCHK(hipMemsetAsync(p, 0, nv * sizeof(float), op->stream));
+        };
+        zalloc64(op->Xh); zalloc64(op->R); zalloc64(op->P); zalloc64(op->Q); zalloc64(op->Z); zalloc64(op->Bh);
+        if (op->mixed()) { zalloc32(op->R32); zalloc32(op->SA); zalloc32(op->SB); }
+        else { zalloc64(op->SA64); zalloc64(op->SB64); }
+        op->partials = dalloc<double>((size_t)op->G * op->NB);
+        const size_t sn = (size_t)S * op->NB;
+        op->d_rho = dalloc<double>(sn); op->d_alpha = dalloc<double>(sn); op->d_beta = dalloc<double>(sn);
+        op->d_rr = dalloc<double>(sn); op->d_bn2 = dalloc<double>(sn); op->d_tol2 = dalloc<double>(sn);
+        op->d_lz = dalloc<double>((size_t)S * (2 * ppk::LZ_MAX + 2));
+        op->d_it = dalloc<int32_t>(sn); op->d_status = dalloc<int32_t>(sn); op->d_done = dalloc<int32_t>(sn);
+        op->d_zero_b = dalloc<int32_t>(sn);
+        op->d_seg_ndone = dalloc<int32_t>(S); op->d_seg_done = dalloc<int32_t>(S);
+        op->d_ticket = dalloc<uint32_t>(S);
+        op->d_ndone = dalloc<int32_t>(1);
+        HIPCHK(hipMemsetAsync(op->d_ticket, 0, sizeof(uint32_t) * S, op->stream));
+        HIPCHK(hipHostMalloc((void **)&op->h_ndone, 2 * sizeof(int32_t), hipHostMallocDefault));
+        HIPCHK(hipStreamSynchronize(op->stream));
+        end_call(op);
+    } catch (std::bad_alloc &) {
+        cleanup();
+        return fail(PP_ERR_OOM, "device allocation failed");
+    } catch (HipError &e) {
+        cleanup();
+        return hip_fail(e);
+    }
+    cleanup();
+    return PP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// launches
+// ---------------------------------------------------------------------------
+
+void launch_state_init(pp_batch_s *op, double tol, int maxit)
+{
+    const int m = std::max(op->S * op->NB, op->S);
+    hipLaunchKernelGGL(ppb::kb_state_init, dim3((unsigned)((m + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, op->stream,
+                       op->bst(tol, maxit), op->S, op->NB);
+    hipLaunchKernelGGL(ppb::kb_pad_cols, dim3((unsigned)((op->S + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, op->stream,
+                       op->bst(tol, maxit), op->S, op->NB, op->nrhs);
+}
+
+// Z = p_k(A-hat) R for all columns; fin = BF_RHO0 / BF_RHO (reduce R.Z)
+template <int W, int CPL>
+void poly(pp_batch_s *op, const ppb::BState &st, int fin)
+{
+    const dim3 g(op->G), b(BLOCK);
+    const ppb::Batch bt = op->bt();
+    const int k = op->k;
+    if (k == 0) {
+        hipLaunchKernelGGL((ppb::kb_deg0<W, CPL>), g, b, 0, op->stream, bt, st, op->view(false), (const double *)op->R,
+                           op->Z, (const double *)op->thinv_d, op->partials, fin);
+        return;
+    }
+    const bool nt = op->ntload != 0;
+    if (!op->mixed()) {
+        const ppk::SellView A = op->view(false);
+        for (int j = 1; j <= k; ++j) {
+            const bool last = (j == k);
+            const double *X = j == 1 ? op->R : ((j % 2 == 0) ? op->SA64 : op->SB64);
+            const double *old = (j % 2 == 0) ? op->SB64 : op->SA64;
+            double *out = last ? op->Z : ((j % 2 == 1) ? op->SA64 : op->SB64);
+#define KB64(MODE, LAST, NT)                                                                                           \
+    hipLaunchKernelGGL((ppb::kb_cheb<double, double, double, W, CPL, MODE, LAST, NT>), g, b, 0, op->stream, bt, st, A, \
+                       X, (const double *)op->R, old, out, (const double *)op->coef_d, j, op->partials, fin)
+            const int mode = j == 1 ? 1 : (j == 2 ? 2 : 3);
+            if (last) {
+                if (mode == 1) { if (nt) KB64(1, true, true); else KB64(1, true, false); }
+                else if (mode == 2) { if (nt) KB64(2, true, true); else KB64(2, true, false); }
+                else { if (nt) KB64(3, true, true); else KB64(3, true, false); }
+            } else {
+                if (mode == 1) { if (nt) KB64(1, false, true); else KB64(1, false, false); }
+                else if (mode == 2) { if (nt) KB64(2, false, true); else KB64(2, false, false); }
+                else { if (nt) KB64(3, false, true); else KB64(3, false, false); }
+            }
+#undef KB64
+        }
+        return;
+    }
+    const ppk::SellView A = op->view(true);
+    hipLaunchKernelGGL((ppb::kb_conv<W, CPL>), g, b, 0, op->stream, bt, st, A, (const double *)op->R, op->R32);
+    for (int j = 1; j <= k; ++j) {
+        const bool last = (j == k);
+        const float *X = j == 1 ? op->R32 : ((j % 2 == 0) ? op->SA : op->SB);
+        const float *old = (j % 2 == 0) ? op->SB : op->SA;
+        float *out = (j % 2 == 1) ? op->SA : op->SB;
+        const int mode = j == 1 ? 1 : (j == 2 ? 2 : 3);
+#define KB32(MODE, NT)                                                                                                  \
+    hipLaunchKernelGGL((ppb::kb_cheb<float, float, float, W, CPL, MODE, false, NT>), g, b, 0, op->stream, bt, st, A,    \
+                       X, (const float *)op->R32, old, out, (const double *)op->coef_d, j, op->partials, fin)
+#define KB32L(MODE, NT)                                                                                                 \
+    hipLaunchKernelGGL((ppb::kb_cheb<float, double, double, W, CPL, MODE, true, NT>), g, b, 0, op->stream, bt, st, A,   \
+                       X, (const double *)op->R, old, op->Z, (const double *)op->coef_d, j, op->partials, fin)
+        if (last) {
+            if (mode == 1) { if (nt) KB32L(1, true); else KB32L(1, false); }
+            else if (mode == 2) { if (nt) KB32L(2, true); else KB32L(2, false); }
+            else { if (nt) KB32L(3, true); else KB32L(3, false); }
+        } else {
+            if (mode == 1) { if (nt) KB32(1, true); else KB32(1, false); }
+            else if (mode == 2) { if (nt) KB32(2, true); else KB32(2, false); }
+            else { if (nt) KB32(3, true); else KB32(3, false); }
+        }
+#undef KB32
+#undef KB32L
+    }
+}
+
+template <int W, int CPL>
+void iteration(pp_batch_s *op, const ppb::BState &st)
+{
+    const dim3 g(op->G), b(BLOCK);
+    const ppb::Batch bt = op->bt();
+    const ppk::SellView A = op->view(false);
+    if (op->ntload)
+        hipLaunchKernelGGL((ppb::kb_apply64<W, CPL, 1, true>), g, b, 0, op->stream, bt, st, A, (const double *)op->P,
+                           (const double *)nullptr, op->Q, op->partials);
+    else
+        hipLaunchKernelGGL((ppb::kb_apply64<W, CPL, 1, false>), g, b, 0, op->stream, bt, st, A, (const double *)op->P,
+                           (const double *)nullptr, op->Q, op->partials);
+    hipLaunchKernelGGL((ppb::kb_xr<W, CPL>), g, b, 0, op->stream, bt, st, A, (const double *)op->P,
+                       (const double *)op->Q, op->Xh, op->R, op->partials);
+    poly<W, CPL>(op, st, ppb::BF_RHO);
+    hipLaunchKernelGGL((ppb::kb_p<W, CPL>), g, b, 0, op->stream, bt, st, A, (const double *)op->Z, op->P, 0);
+}
+
+void upload_coefficients(pp_batch_s *op)
+{
+    const int S = op->S, k = op->k;
+    std::vector<double> coef((size_t)S * std::max(1, k) * 4, 0.0), thinv(S);
+    for (int s = 0; s < S; ++s) {
+        const double th = (op->lmax[s] + op->lmin[s]) / 2.0 * (1.0 + op->xi);
+        const double de = (op->lmax[s] - op->lmin[s]) / 2.0;
+        const double si = th / de;
+        std::vector<double> rho(k + 1);
+        rho[0] = 1.0 / si;
+        for (int j = 1; j <= k; ++j) rho[j] = 1.0 / (2.0 * si - rho[j - 1]);
+        thinv[s] = 1.0 / th;
+        for (int j = 1; j <= k; ++j) {
+            double *c = &coef[((size_t)s * k + (j - 1)) * 4];
+            if (j == 1) {
+                c[0] = 0; c[1] = 0; c[2] = 4.0 * rho[1] / de; c[3] = -2.0 * rho[1] / (de * th);
+            } else if (j == 2) {
+                c[0] = 2.0 * si * rho[2]; c[1] = 0; c[2] = 2.0 * rho[2] / de - rho[2] * rho[1] / th;
+                c[3] = -2.0 * rho[2] / de;
+            } else {
+                c[0] = 2.0 * si * rho[j]; c[1] = -rho[j] * rho[j - 1]; c[2] = 2.0 * rho[j] / de; c[3] = -2.0 * rho[j] / de;
+            }
+        }
+    }
+    dfree(op->coef_d);
+    dfree(op->thinv_d);
+    op->coef_d = dalloc<double>(coef.size());
+    op->thinv_d = dalloc<double>(S);
+    HIPCHK(hipMemcpyAsync(op->coef_d, coef.data(), sizeof(double) * coef.size(), hipMemcpyHostToDevice, op->stream));
+    HIPCHK(hipMemcpyAsync(op->thinv_d, thinv.data(), sizeof(double) * S, hipMemcpyHostToDevice, op->stream));
+    HIPCHK(hipStreamSynchronize(op->stream));
+}
+
+}  // namespace
+
+extern "C" {
+
+pp_status pp_create_batch(pp_batch *out, int nsys, const int64_t *sys_ptr, int64_t nnz, const int64_t *rowptr,
+                          const int32_t *colind, const double *val, int nrhs, unsigned flags, void *stream)
+{
+    if (!out) return fail(PP_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (nsys < 1 || !sys_ptr || nnz <= 0 || !rowptr || !colind || !val)
+        return fail(PP_ERR_ARG, "nsys >= 1, nnz > 0 and non-NULL arrays required");
+    if (nrhs < 1 || nrhs > ppb::NB_MAX) return fail(PP_ERR_ARG, "nrhs must be in [1, 32]");
+    if (flags & ~(unsigned)(PP_JACOBI | PP_MIXED)) return fail(PP_ERR_ARG, "unknown flags");
+    if (sys_ptr[0] != 0) return fail(PP_ERR_ARG, "sys_ptr[0] must be 0");
+    for (int s = 0; s < nsys; ++s)
+        if (sys_ptr[s + 1] <= sys_ptr[s]) return fail(PP_ERR_ARG, "sys_ptr must be strictly increasing");
+    if (sys_ptr[nsys] > (int64_t)INT32_MAX - 1) return fail(PP_ERR_ARG, "n must be below 2^31");
+    pp_batch_s *op = new (std::nothrow) pp_batch_s();
+    if (!op) return fail(PP_ERR_OOM, "host allocation failed");
+    op->S = nsys;
+    op->nrhs = nrhs;
+    op->NB = nrhs == 1 ? 1 : (nrhs <= 8 ? 8 : 32);
+    op->W = op->NB;
+    op->CPL = 1;
+    op->flags = flags;
+    op->ustream = (hipStream_t)stream;
+    op->sys_ptr.assign(sys_ptr, sys_ptr + nsys + 1);
+    op->n_ext = sys_ptr[nsys];
+    op->nnz = nnz;
+    (void)hipGetDevice(&op->device);
+    pp_status s = build(op, rowptr, colind, val);
+    if (s != PP_OK) {
+        op->release();
+        delete op;
+        return s;
+    }
+    op->stats.n = op->n_ext;
+    op->stats.nsys = nsys;
+    op->stats.nb = op->NB;
+    op->stats.nrhs = nrhs;
+    op->stats.w = op->W;
+    op->stats.nnz_stored = op->nstored;
+    op->stats.grid = op->G;
+    *out = op;
+    return PP_OK;
+}
+
+void pp_destroy_batch(pp_batch op)
+{
+    if (!op) return;
+    (void)hipStreamSynchronize(op->stream);
+    op->release();
+    delete op;
+}
+
+pp_status pp_batch_set_option(pp_batch op, int key, int64_t value)
+{
+    if (!op) return fail(PP_ERR_ARG, "op is NULL");
+    switch (key) {
+    case PP_OPT_CHUNK:
+        if (value < 0 || value > 256) return fail(PP_ERR_ARG, "chunk must be in [0, 256]");
+        op->chunk = (int)value;
+        return PP_OK;
+    case PP_OPT_NT_LOADS: op->ntload = value != 0; op->g_k = -1; return PP_OK;
+    case PP_BOPT_GRAPH: op->use_graph = value != 0; return PP_OK;
+    default: return fail(PP_ERR_ARG, "unknown batch option");
+    }
+}
+
+pp_status pp_batch_set_layout(pp_batch op, int w)
+{
+    if (!op) return fail(PP_ERR_ARG, "op is NULL");
+    if (w == 0) w = op->NB;
+    if (!layout_ok(op->NB, w)) return fail(PP_ERR_ARG, "unsupported lanes-per-row for this block width");
+    op->W = w;
+    op->CPL = op->NB / w;
+    op->stats.w = w;
+    return PP_OK;
+}
+
+pp_status pp_batch_get_stats(pp_batch op, pp_batch_stats *st)
+{
+    if (!op || !st) return fail(PP_ERR_ARG, "NULL argument");
+    *st = op->stats;
+    return PP_OK;
+}
+
+pp_status pp_batch_setup(pp_batch op, int k, const double *lambda_min, const double *lambda_max, double scaling)
+{
+    if (!op || !lambda_min || !lambda_max) return fail(PP_ERR_ARG, "NULL argument");
+    if (k < 0 || k > 4096) return fail(PP_ERR_ARG, "degree k out of range [0, 4096]");
+    if (!std::isfinite(scaling) || !(scaling >= 0.0)) return fail(PP_ERR_ARG, "scaling must be finite and >= 0");
+    for (int s = 0; s < op->S; ++s)
+        if (!std::isfinite(lambda_min[s]) || !std::isfinite(lambda_max[s]) || !(lambda_min[s] > 0.0) ||
+            !(lambda_max[s] > lambda_min[s]))
+            return fail(PP_ERR_ARG, "bounds must satisfy 0 < lambda_min < lambda_max (finite) for every system");
+    try {
+        op->k = k;
+        op->xi = scaling;
+        op->lmin.assign(lambda_min, lambda_min + op->S);
+        op->lmax.assign(lambda_max, lambda_max + op->S);
+        upload_coefficients(op);
+        op->g_k = -1;  // re-capture the iteration graph
+        op->setup_done = true;
+    } catch (std::bad_alloc &) {
+        return fail(PP_ERR_OOM, "device allocation failed");
+    } catch (HipError &e) {
+        return hip_fail(e);
+    }
+    return PP_OK;
+}
+
+pp_status pp_batch_estimate_bounds(pp_batch op, int steps, double *lambda_min, double *lambda_max)
+{
+    if (!op || !lambda_min || !lambda_max) return fail(PP_ERR_ARG, "NULL argument");
+    if (steps < 1 || steps > ppk::LZ_MAX) return fail(PP_ERR_ARG, "steps must be in [1, 64]");
+    try {
+        begin_call(op);
+        const dim3 g(op->G), b(BLOCK);
+        const ppb::Batch bt = op->bt();
+        const ppb::BState st = op->bst(0.0, 0);
+        const ppk::SellView A = op->view(false);
+        launch_state_init(op, 0.0, 0);
+        double *v = op->P, *vprev = op->Q, *w = op->Z;
+        hipLaunchKernelGGL(ppb::kb_lz_start, g, b, 0, op->stream, bt, st, A, v, op->partials);
+        hipLaunchKernelGGL(ppb::kb_lz_vec, g, b, 0, op->stream, bt, st, A, v, vprev, (const double *)w, 0, 0);
+        for (int j = 0; j < steps; ++j) {
+            hipLaunchKernelGGL(ppb::kb_lz_step<0>, g, b, 0, op->stream, bt, st, A, (const double *)v,
+                               (const double *)vprev, w, op->partials, j);
+            hipLaunchKernelGGL(ppb::kb_lz_step<1>, g, b, 0, op->stream, bt, st, A, (const double *)v,
+                               (const double *)vprev, w, op->partials, j);
+            if (j + 1 < steps)
+                hipLaunchKernelGGL(ppb::kb_lz_vec, g, b, 0, op->stream, bt, st, A, v, vprev, (const double *)w, 1, j);
+        }
+        HIPCHK(hipGetLastError());
+        const size_t lzn = (size_t)op->S * (2 * ppk::LZ_MAX + 2);
+        std::vector<double> lz(lzn);
+        HIPCHK(hipMemcpyAsync(lz.data(), op->d_lz, sizeof(double) * lzn, hipMemcpyDeviceToHost, op->stream));
+        // the Lanczos vectors used the CG buffers: restore their zero padding
+        const size_t nv = (size_t)op->n_int * op->NB;
+        HIPCHK(hipMemsetAsync(op->P, 0, nv * sizeof(double), op->stream));
+        HIPCHK(hipMemsetAsync(op->Q, 0, nv * sizeof(double), op->stream));
+        HIPCHK(hipMemsetAsync(op->Z, 0, nv * sizeof(double), op->stream));
+        HIPCHK(hipStreamSynchronize(op->stream));
+        end_call(op);
+        for (int s = 0; s < op->S; ++s) {
+            const double *al = &lz[(size_t)s * (2 * ppk::LZ_MAX + 2)];
+            const double *be = al + ppk::LZ_MAX;
+            int m = steps;
+            for (int j = 0; j < steps; ++j) {
+                if (!std::isfinite(al[j]) || !std::isfinite(be[j]))
+                    return fail(PP_ERR_ARG, "non-finite value in Lanczos");
+                if (be[j] == 0.0) { m = j + 1; break; }
+            }
+            std::vector<double> T((size_t)m * m, 0.0), wv, V;
+            for (int j = 0; j < m; ++j) {
+                T[(size_t)j * m + j] = al[j];
+                if (j + 1 < m) T[(size_t)j * m + j + 1] = T[(size_t)(j + 1) * m + j] = be[j];
+            }
+            ppeig::jacobi_eig(m, T, wv, V);
+            int imin = 0, imax = 0;
+            for (int i = 1; i < m; ++i) {
+                if (wv[i] < wv[imin]) imin = i;
+                if (wv[i] > wv[imax]) imax = i;
+            }
+            lambda_min[s] = wv[imin];
+            lambda_max[s] = wv[imax] + std::fabs(be[m - 1] * V[(size_t)(m - 1) * m + imax]);
+        }
+    } catch (HipError &e) {
+        return hip_fail(e);
+    }
+    return PP_OK;
+}
+
+pp_status pcg_solve_batch(pp_batch op, const double *B, double *X, double tol, int maxit, int *iters, double *relres,
+                          int *status)
+{
+    if (!op || !B || !X) return fail(PP_ERR_ARG, "NULL argument");
+    if (B == X) return fail(PP_ERR_ARG, "B and X must not alias");
+    if (!std::isfinite(tol) || tol < 0.0) return fail(PP_ERR_ARG, "tol must be finite and >= 0");
+    if (maxit < 0) return fail(PP_ERR_ARG, "maxit must be >= 0");
+    if (!op->setup_done) return fail(PP_ERR_STATE, "pp_batch_setup must be called before pcg_solve_batch");
+    try {
+        begin_call(op);
+        HIPCHK(hipEventRecord(op->solve_ev[0], op->stream));
+        const ppb::BState st = op->bst(tol, maxit);
+        const ppb::Batch bt = op->bt();
+        const dim3 g(op->G), b(BLOCK);
+        launch_state_init(op, tol, maxit);
+        const int total = op->S * op->NB;
+        int chunk = op->chunk > 0 ? op->chunk : (op->n_int * (int64_t)op->NB >= (1 << 22) ? 2 : 8);
+        with_layout(op->W, op->CPL, [&](auto wc, auto cc) {
+            constexpr int W = decltype(wc)::value;
+            constexpr int CPL = decltype(cc)::value;
+            const ppk::SellView A = op->view(false);
+            hipLaunchKernelGGL((ppb::kb_init_scale<W, CPL>), g, b, 0, op->stream, bt, st, A, B, (const double *)X,
+                               (const double *)op->dis, op->Bh, op->Xh, op->partials);
+            hipLaunchKernelGGL((ppb::kb_apply64<W, CPL, 0, false>), g, b, 0, op->stream, bt, st, A,
+                               (const double *)op->Xh, (const double *)op->Bh, op->R, op->partials);
+            poly<W, CPL>(op, st, ppb::BF_RHO0);
+            hipLaunchKernelGGL((ppb::kb_p<W, CPL>), g, b, 0, op->stream, bt, st, A, (const double *)op->Z, op->P, 1);
+            HIPCHK(hipGetLastError());
+            // one chunk of iterations, captured once and replayed
+            const bool graph = op->use_graph != 0;
+            if (graph && (op->g_k != op->k || op->g_chunk != chunk || op->g_tol != tol || op->g_maxit != maxit ||
+                          op->g_W != op->W || !op->gexec)) {
+                if (op->gexec) HIPCHK(hipGraphExecDestroy(op->gexec));
+                op->gexec = nullptr;
+                hipGraph_t gr;
+                HIPCHK(hipStreamBeginCapture(op->stream, hipStreamCaptureModeThreadLocal));
+                for (int i = 0; i < chunk; ++i) iteration<W, CPL>(op, st);
+                HIPCHK(hipStreamEndCapture(op->stream, &gr));
+                HIPCHK(hipGraphInstantiate(&op->gexec, gr, nullptr, nullptr, 0));
+                HIPCHK(hipGraphDestroy(gr));
+                op->g_k = op->k; op->g_chunk = chunk; op->g_tol = tol; op->g_maxit = maxit; op->g_W = op->W;
+            }
+            int enq = 0, c = 0;
+            while (enq < maxit) {
+                if (graph) HIPCHK(hipGraphLaunch(op->gexec, op->stream));
+                else
+                    for (int i = 0; i < chunk; ++i) iteration<W, CPL>(op, st);
+                HIPCHK(hipGetLastError());
+                enq += chunk;
+                HIPCHK(hipMemcpyAsync(&op->h_ndone[c & 1], op->d_ndone, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                      op->stream));
+                HIPCHK(hipEventRecord(op->flag_ev[c & 1], op->stream));
+                if (c >= 1) {
+                    HIPCHK(hipEventSynchronize(op->flag_ev[(c - 1) & 1]));
+                    if (op->h_ndone[(c - 1) & 1] >= total) break;
+                }
+                ++c;
+            }
+            hipLaunchKernelGGL((ppb::kb_final<W, CPL>), g, b, 0, op->stream, bt, st, A, (const double *)op->Xh,
+                               (const double *)op->dis, X);
+            HIPCHK(hipGetLastError());
+        });
+        HIPCHK(hipEventRecord(op->solve_ev[1], op->stream));
+        const size_t sn = (size_t)total;
+        std::vector<int32_t> it(sn), stt(sn), zb(sn);
+        std::vector<double> rr(sn), bn(sn);
+        HIPCHK(hipMemcpyAsync(it.data(), op->d_it, sizeof(int32_t) * sn, hipMemcpyDeviceToHost, op->stream));
+        HIPCHK(hipMemcpyAsync(stt.data(), op->d_status, sizeof(int32_t) * sn, hipMemcpyDeviceToHost, op->stream));
+        HIPCHK(hipMemcpyAsync(zb.data(), op->d_zero_b, sizeof(int32_t) * sn, hipMemcpyDeviceToHost, op->stream));
+        HIPCHK(hipMemcpyAsync(rr.data(), op->d_rr, sizeof(double) * sn, hipMemcpyDeviceToHost, op->stream));
+        HIPCHK(hipMemcpyAsync(bn.data(), op->d_bn2, sizeof(double) * sn, hipMemcpyDeviceToHost, op->stream));
+        HIPCHK(hipStreamSynchronize(op->stream));
+        end_call(op);
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, op->solve_ev[0], op->solve_ev[1]));
+        op->stats.solve_ms = ms;
+        op->stats.graph = op->use_graph;
+        pp_status worst = PP_OK;
+        int maxits = 0;
+        for (int s = 0; s < op->S; ++s)
+            for (int c = 0; c < op->nrhs; ++c) {
+                const size_t i = (size_t)s * op->NB + c, o = (size_t)s * op->nrhs + c;
+                const pp_status sc = zb[i] ? PP_OK : (pp_status)stt[i];
+                if (sc == PP_BREAKDOWN || (sc == PP_NOT_CONVERGED && worst == PP_OK)) worst = sc;
+                maxits = std::max(maxits, it[i]);
+                if (iters) iters[o] = it[i];
+                if (status) status[o] = sc;
+                if (relres) relres[o] = zb[i] ? 0.0 : (bn[i] > 0 ? std::sqrt(rr[i] / bn[i]) : 0.0);
+            }
+        op->stats.max_iters = maxits;
+        return worst;
+    } catch (std::bad_alloc &) {
+        return fail(PP_ERR_OOM, "device allocation failed");
+    } catch (HipError &e) {
+        return hip_fail(e);
+    }
+}
+
+pp_status pp_batch_apply(pp_batch op, const double *Rin, double *Zout)
+{
+    if (!op || !Rin || !Zout) return fail(PP_ERR_ARG, "NULL argument");
+    if (Rin == Zout) return fail(PP_ERR_ARG, "R and Z must not alias");
+    if (!op->setup_done) return fail(PP_ERR_STATE, "pp_batch_setup must be called before pp_batch_apply");
+    try {
+        begin_call(op);
+        const ppb::BState st = op->bst(0.0, 1);
+        const ppb::Batch bt = op->bt();
+        const dim3 g(op->G), b(BLOCK);
+        launch_state_init(op, 0.0, 1);
+        with_layout(op->W, op->CPL, [&](auto wc, auto cc) {
+            constexpr int W = decltype(wc)::value;
+            constexpr int CPL = decltype(cc)::value;
+            const ppk::SellView A = op->view(false);
+            // R = D^{-1/2} Rin in the internal layout (Bh holds it), polynomial, Z = D^{-1/2} z
+            hipLaunchKernelGGL((ppb::kb_init_scale<W, CPL>), g, b, 0, op->stream, bt, st, A, Rin, Rin,
+                               (const double *)op->dis, op->R, op->Xh, op->partials);
+            poly<W, CPL>(op, st, ppb::BF_NONE);
+            hipLaunchKernelGGL((ppb::kb_final<W, CPL>), g, b, 0, op->stream, bt, st, A, (const double *)op->Z,
+                               (const double *)op->dis, Zout);
+        });
+        HIPCHK(hipGetLastError());
+        end_call(op);
+    } catch (HipError &e) {
+        return hip_fail(e);
+    }
+    return PP_OK;
+}
+
+pp_status pp_batch_autotune(pp_batch op, int *best_w, double *best_us)
+{
+    if (!op || !best_w) return fail(PP_ERR_ARG, "NULL argument");
+    if (!op->setup_done || op->k < 3) return fail(PP_ERR_STATE, "autotune needs pp_batch_setup with k >= 3");
+    const int cands[3] = {op->NB, op->NB / 2, op->NB / 4};
+    double best = 1e300;
+    int bw = op->W;
+    try {
+        begin_call(op);
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        const ppb::BState st = op->bst(0.0, 1);
+        launch_state_init(op, 0.0, 1);
+        for (int w : cands) {
+            if (w < 1 || !layout_ok(op->NB, w)) continue;
+            const int cpl = op->NB / w;
+            double us = 0;
+            with_layout(w, cpl, [&](auto wc, auto cc) {
+                constexpr int W = decltype(wc)::value;
+                constexpr int CPL = decltype(cc)::value;
+                const dim3 g(op->G), b(BLOCK);
+                const ppb::Batch bt = op->bt();
+                const bool f32 = op->mixed();
+                const ppk::SellView A = op->view(f32);
+                auto step = [&]() {
+                    if (f32)
+                        hipLaunchKernelGGL((ppb::kb_cheb<float, float, float, W, CPL, 3, false, true>), g, b, 0,
+                                           op->stream, bt, st, A, (const float *)op->SA, (const float *)op->R32,
+                                           (const float *)op->SB, op->SB, (const double *)op->coef_d, 3, op->partials, 0);
+                    else
+                        hipLaunchKernelGGL((ppb::kb_cheb<double, double, double, W, CPL, 3, false, true>), g, b, 0,
+                                           op->stream, bt, st, A, (const double *)op->SA64, (const double *)op->R,
+                                           (const double *)op->SB64, op->SB64, (const double *)op->coef_d, 3,
+                                           op->partials, 0);
+                };
+                step();
+                HIPCHK(hipEventRecord(e0, op->stream));
+                for (int r = 0; r < 5; ++r) step();
+                HIPCHK(hipEventRecord(e1, op->stream));
+                HIPCHK(hipEventSynchronize(e1));
+                float ms = 0;
+                HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                us = 1000.0 * ms / 5;
+            });
+            if (us < best) {
+                best = us;
+                bw = w;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        // the timing steps wrote the step buffers: restore zero padding
+        const size_t nv = (size_t)op->n_int * op->NB;
+        if (op->mixed()) HIPCHK(hipMemsetAsync(op->SB, 0, nv * sizeof(float), op->stream));
+        else HIPCHK(hipMemsetAsync(op->SB64, 0, nv * sizeof(double), op->stream));
+        HIPCHK(hipStreamSynchronize(op->stream));
+        end_call(op);
+    } catch (HipError &e) {
+        return hip_fail(e);
+    }
+    op->W = bw;
+    op->CPL = op->NB / bw;
+    op->stats.w = bw;
+    *best_w = bw;
+    if (best_us) *best_us = best;
+    return PP_OK;
+}
+
+}  // extern "C"

@@ -21,47 +21,21 @@ using ppk::BLOCK;
 using ppk::WAVE;
 using ppk::WPB;
 
+#include "common.hpp"
+
+std::string &ppc::last_error()
+{
+    static thread_local std::string e;
+    return e;
+}
+
 namespace {
 
-thread_local std::string g_err;
-
-pp_status fail(pp_status s, const std::string &msg)
-{
-    g_err = msg;
-    return s;
-}
-
-struct HipError {
-    hipError_t e;
-    const char *what;
-    int line;
-};
-
-#define HIPCHK(x)                                             \
-    do {                                                      \
-        hipError_t e_ = (x);                                  \
-        if (e_ != hipSuccess) throw HipError{e_, #x, __LINE__}; \
-    } while (0)
-
-template <typename T>
-T *dalloc(size_t count)
-{
-    if (count == 0) count = 1;
-    void *p = nullptr;
-    hipError_t e = hipMalloc(&p, count * sizeof(T));
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        throw std::bad_alloc();
-    }
-    return (T *)p;
-}
-
-template <typename T>
-void dfree(T *&p)
-{
-    if (p) (void)hipFree((void *)p);
-    p = nullptr;
-}
+using ppc::dalloc;
+using ppc::dfree;
+using ppc::fail;
+using ppc::HipError;
+using ppc::hip_fail;
 
 constexpr int K_MAX = 4096;
 constexpr int GRID_DEFAULT = 2048;
@@ -571,12 +545,6 @@ hipEvent_t timing_event(pp_op_s *op, size_t i)
     return op->tev[i];
 }
 
-pp_status hip_fail(const HipError &e)
-{
-    char b[256];
-    snprintf(b, sizeof b, "HIP error %s in %s (line %d)", hipGetErrorString(e.e), e.what, e.line);
-    return fail(PP_ERR_HIP, b);
-}
 
 }  // namespace
 
@@ -685,7 +653,7 @@ const char *pp_status_str(pp_status s)
     return "PP_UNKNOWN";
 }
 
-const char *pp_last_error(void) { return g_err.c_str(); }
+const char *pp_last_error(void) { return ppc::last_error().c_str(); }
 
 pp_status pp_create_csr(pp_op *out, int64_t n, int64_t nnz, const int64_t *rowptr, const int32_t *colind,
                         const double *val, unsigned flags, void *stream)

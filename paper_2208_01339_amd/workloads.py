@@ -309,3 +309,23 @@ def block_rhs(n: int, width: int, first_seed: int = 3000) -> np.ndarray:
     for j in range(width):
         out[:, j] = rhs_uniform(n, first_seed + j)
     return out
+
+
+def block_diag(systems):
+    """Stack CSR systems into one block-diagonal CSR; returns (CSR, sys_ptr int64 [nsys+1])."""
+    n = [s.n_rows for s in systems]
+    sys_ptr = np.zeros(len(systems) + 1, dtype=np.int64)
+    np.cumsum(n, out=sys_ptr[1:])
+    nnz = [s.nnz for s in systems]
+    nz_ptr = np.zeros(len(systems) + 1, dtype=np.int64)
+    np.cumsum(nnz, out=nz_ptr[1:])
+    rowptr = np.empty(sys_ptr[-1] + 1, dtype=np.int64)
+    col = np.empty(nz_ptr[-1], dtype=np.int32)
+    val = np.empty(nz_ptr[-1], dtype=np.float64)
+    for i, s in enumerate(systems):
+        rowptr[sys_ptr[i]:sys_ptr[i + 1]] = s.rowptr[:-1] + nz_ptr[i]
+        col[nz_ptr[i]:nz_ptr[i + 1]] = s.col + np.int32(sys_ptr[i])
+        val[nz_ptr[i]:nz_ptr[i + 1]] = s.val
+    rowptr[-1] = nz_ptr[-1]
+    N = int(sys_ptr[-1])
+    return CSR(N, N, rowptr, col, val), sys_ptr

@@ -1,0 +1,228 @@
+"""GPU parity of the batched path: many systems and/or a block of right-hand sides.
+
+Every (system, column) is compared with its own single-system oracle solve
+on the same inputs; the bounds passed to both come from the oracle.
+FP64: equal iteration count (every member runs exactly m iterations, tol 0)
+-> relative solution error <= 1e-10; tol-driven iteration counts within +-2.
+FP32 polynomial (mixed): the scaled FP64 true residual <= 2e-8 and iteration
+counts within +-2 of the FP64 oracle (no iterate-level pin).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2208_01339_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2208_01339_amd import binding
+
+    binding.lib()
+    return binding
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+SIZES = [6, 9, 11, 14, 5, 17]
+
+
+def members():
+    return [W.hetero_diffusion(N, 2.0, 100 + i) for i, N in enumerate(SIZES)]
+
+
+def oracle_bounds(systems):
+    lo, hi = [], []
+    ops = []
+    for a in systems:
+        o = O.Operator(a, jacobi=True)
+        l, h = O.lanczos_bounds(o, 20)
+        lo.append(l)
+        hi.append(h)
+        ops.append(o)
+    return ops, np.array(lo), np.array(hi)
+
+
+def block_rhs(sys_ptr, nrhs, seed0):
+    n = int(sys_ptr[-1])
+    return W.block_rhs(n, nrhs, seed0)
+
+
+@pytest.mark.parametrize("nrhs", [1, 3, 8])
+def test_batch_bounds_match_oracle(B, nrhs):
+    systems = members()
+    ops, lo, hi = oracle_bounds(systems)
+    bo = B.BatchOperator(systems, nrhs=nrhs, flags=B.PP_JACOBI)
+    glo, ghi = B.pp_batch_estimate_bounds(bo.handle, len(systems), 20)
+    assert np.all(np.abs(glo - lo) <= 1e-7 * hi)
+    assert np.all(np.abs(ghi - hi) <= 1e-7 * hi)
+    bo.close()
+
+
+@pytest.mark.parametrize("nrhs,w", [(1, 1), (3, 8), (3, 4), (3, 2), (8, 8), (8, 2), (20, 32), (20, 16), (20, 8)])
+def test_batch_fp64_equal_iterations(B, nrhs, w):
+    systems = members()
+    ops, lo, hi = oracle_bounds(systems)
+    k, xi, m = 7, 1e-3, 9
+    bo = B.BatchOperator(systems, nrhs=nrhs, flags=B.PP_JACOBI)
+    B.pp_batch_set_layout(bo.handle, w)
+    B.pp_batch_setup(bo.handle, k, lo, hi, xi)
+    Bm = block_rhs(bo.sys_ptr, nrhs, 40)
+    X = torch.zeros(bo.n, nrhs, dtype=torch.float64, device="cuda")
+    s, it, rel, stt = B.pcg_solve_batch(bo.handle, len(systems), nrhs, dev(Bm), X, 0.0, m)
+    assert np.all(it == m) and np.all(stt == B.PP_NOT_CONVERGED)
+    Xg = host(X)
+    for i, o in enumerate(ops):
+        r0, r1 = bo.sys_ptr[i], bo.sys_ptr[i + 1]
+        for c in range(nrhs):
+            xo, sto = O.pcg(o, k, lo[i], hi[i], xi, Bm[r0:r1, c], tol=0.0, maxit=m)
+            err = np.linalg.norm(Xg[r0:r1, c] - xo) / np.linalg.norm(xo)
+            assert err <= 1e-10, (i, c, err)
+            assert abs(rel[i, c] - sto["relres"]) <= 1e-6 * sto["relres"]
+    bo.close()
+
+
+@pytest.mark.parametrize("nrhs", [1, 4])
+def test_batch_fp64_tol_driven(B, nrhs):
+    systems = members()
+    ops, lo, hi = oracle_bounds(systems)
+    k = 10
+    bo = B.BatchOperator(systems, nrhs=nrhs, flags=B.PP_JACOBI)
+    B.pp_batch_setup(bo.handle, k, lo, hi, 0.0)
+    Bm = block_rhs(bo.sys_ptr, nrhs, 7)
+    X = torch.zeros(bo.n, nrhs, dtype=torch.float64, device="cuda")
+    s, it, rel, stt = B.pcg_solve_batch(bo.handle, len(systems), nrhs, dev(Bm), X, 1e-9, 500)
+    assert s == B.PP_OK and np.all(stt == B.PP_OK) and np.all(rel <= 1e-9)
+    Xg = host(X)
+    for i, o in enumerate(ops):
+        r0, r1 = bo.sys_ptr[i], bo.sys_ptr[i + 1]
+        for c in range(nrhs):
+            xo, sto = O.pcg(o, k, lo[i], hi[i], 0.0, Bm[r0:r1, c], tol=1e-9, maxit=500)
+            assert abs(int(it[i, c]) - sto["iters"]) <= 2
+            assert np.linalg.norm(Xg[r0:r1, c] - xo) / np.linalg.norm(xo) <= 1e-6
+    bo.close()
+
+
+@pytest.mark.parametrize("nrhs", [1, 8])
+def test_batch_mixed_residual(B, nrhs):
+    systems = members()
+    ops, lo, hi = oracle_bounds(systems)
+    k = 12
+    bo = B.BatchOperator(systems, nrhs=nrhs, flags=B.PP_JACOBI | B.PP_MIXED)
+    B.pp_batch_setup(bo.handle, k, lo, hi, 0.0)
+    Bm = block_rhs(bo.sys_ptr, nrhs, 3)
+    X = torch.zeros(bo.n, nrhs, dtype=torch.float64, device="cuda")
+    s, it, rel, stt = B.pcg_solve_batch(bo.handle, len(systems), nrhs, dev(Bm), X, 1e-8, 500)
+    assert s == B.PP_OK and np.all(rel <= 1e-8)
+    Xg = host(X)
+    for i, o in enumerate(ops):
+        r0, r1 = bo.sys_ptr[i], bo.sys_ptr[i + 1]
+        for c in range(nrhs):
+            b = Bm[r0:r1, c]
+            x = Xg[r0:r1, c]
+            res = (o.apply_raw(x) - b) * o.dis
+            assert np.linalg.norm(res) / np.linalg.norm(b * o.dis) <= 2e-8
+            xo, sto = O.pcg(o, k, lo[i], hi[i], 0.0, b, tol=1e-8, maxit=500)
+            assert abs(int(it[i, c]) - sto["iters"]) <= 2
+    bo.close()
+
+
+def test_batch_apply_matches_oracle(B):
+    systems = members()
+    ops, lo, hi = oracle_bounds(systems)
+    nrhs, k = 3, 9
+    bo = B.BatchOperator(systems, nrhs=nrhs, flags=B.PP_JACOBI)
+    B.pp_batch_setup(bo.handle, k, lo, hi, 2e-3)
+    R = block_rhs(bo.sys_ptr, nrhs, 11)
+    Z = torch.empty(bo.n, nrhs, dtype=torch.float64, device="cuda")
+    B.pp_batch_apply(bo.handle, dev(R), Z)
+    Zg = host(Z)
+    for i, o in enumerate(ops):
+        r0, r1 = bo.sys_ptr[i], bo.sys_ptr[i + 1]
+        for c in range(nrhs):
+            ref = O.cheb_apply(o, k, lo[i], hi[i], 2e-3, R[r0:r1, c])
+            assert np.linalg.norm(Zg[r0:r1, c] - ref) / np.linalg.norm(ref) <= 1e-12
+    bo.close()
+
+
+def test_batch_graph_replays_match_eager(B):
+    """Captured iteration chunks replayed many times give the same iterates as eager launches,
+    with eager work and synchronisations between the replays."""
+    systems = members()
+    ops, lo, hi = oracle_bounds(systems)
+    nrhs = 8
+    bo = B.BatchOperator(systems, nrhs=nrhs, flags=B.PP_JACOBI)
+    B.pp_batch_setup(bo.handle, 6, lo, hi, 0.0)
+    B.pp_batch_set_option(bo.handle, B.PP_OPT_CHUNK, 3)
+    Bm = dev(block_rhs(bo.sys_ptr, nrhs, 21))
+    results = []
+    for graph in (0, 1, 1, 0, 1):
+        B.pp_batch_set_option(bo.handle, B.PP_BOPT_GRAPH, graph)
+        X = torch.zeros(bo.n, nrhs, dtype=torch.float64, device="cuda")
+        s, it, rel, stt = B.pcg_solve_batch(bo.handle, len(systems), nrhs, Bm, X, 1e-10, 400)
+        assert s == B.PP_OK
+        results.append((it.copy(), host(X)))
+        # unrelated eager work in between
+        y = torch.randn(1000, device="cuda").sum()
+        torch.cuda.synchronize()
+    for it, x in results[1:]:
+        assert np.array_equal(it, results[0][0])
+        assert np.array_equal(x, results[0][1])
+    bo.close()
+
+
+def test_batch_autotune_and_zero_rhs(B, tmp_path, monkeypatch):
+    from paper_2208_01339_amd import autotune
+
+    monkeypatch.setenv("PP_AUTOTUNE_CACHE", str(tmp_path / "cache.json"))
+    systems = members()
+    ops, lo, hi = oracle_bounds(systems)
+    nrhs = 20
+    bo = B.BatchOperator(systems, nrhs=nrhs, flags=B.PP_JACOBI | B.PP_MIXED)
+    B.pp_batch_setup(bo.handle, 8, lo, hi, 0.0)
+    r1 = autotune.tune(bo.handle, mixed=True)
+    assert r1["w"] in (32, 16, 8) and not r1["cached"]
+    r2 = autotune.tune(bo.handle, mixed=True)
+    assert r2["cached"] and r2["w"] == r1["w"]
+    Bm = block_rhs(bo.sys_ptr, nrhs, 5)
+    Bm[:, 3] = 0.0  # a zero right-hand side column: x = 0, zero iterations
+    X = torch.ones(bo.n, nrhs, dtype=torch.float64, device="cuda")
+    s, it, rel, stt = B.pcg_solve_batch(bo.handle, len(systems), nrhs, dev(Bm), X, 1e-8, 500)
+    assert s == B.PP_OK
+    Xg = host(X)
+    assert np.all(Xg[:, 3] == 0.0) and np.all(it[:, 3] == 0)
+    assert np.all(rel[:, [0, 1, 2, 4]] <= 1e-8)
+    bo.close()
+
+
+def test_batch_rejects_bad_input(B):
+    a = W.hetero_diffusion(5, 1.0, 0)
+    b2 = W.hetero_diffusion(4, 1.0, 1)
+    full, sp = W.block_diag([a, b2])
+    # couple the two systems
+    col = full.col.copy()
+    col[0] = int(sp[1]) + 1
+    with pytest.raises(B.PPError) as e:
+        B.pp_create_batch(2, sp, full.nnz, dev(full.rowptr), dev(col), dev(full.val), 1, B.PP_JACOBI)
+    assert e.value.status == B.PP_ERR_ARG
+    for nrhs in (0, 33):
+        with pytest.raises(B.PPError):
+            B.pp_create_batch(2, sp, full.nnz, dev(full.rowptr), dev(full.col), dev(full.val), nrhs)
+    h = B.pp_create_batch(2, sp, full.nnz, dev(full.rowptr), dev(full.col), dev(full.val), 2, B.PP_JACOBI)
+    X = torch.zeros(full.n_rows, 2, dtype=torch.float64, device="cuda")
+    with pytest.raises(B.PPError) as e:
+        B.pcg_solve_batch(h, 2, 2, X.clone(), X, 1e-8, 10)
+    assert e.value.status == B.PP_ERR_STATE
+    B.pp_destroy_batch(h)
