@@ -111,6 +111,90 @@ def run_dfn(args, B, W, torch, dev):
     return out
 
 
+def run_block(args, B, W, torch, dev, a, lmin, lmax, fp64_single):
+    """32 right-hand sides on the 256^3 operator: FP32 block polynomial, FP64 CG per column."""
+    from paper_2208_01339_amd import autotune
+
+    n, nnz = a.n_rows, a.nnz
+    nrhs, k = args.block_rhs, args.block_k
+    sp = np.array([0, n], dtype=np.int64)
+    h = B.pp_create_batch(1, sp, nnz, torch.from_numpy(a.rowptr).to(dev), torch.from_numpy(a.col).to(dev),
+                          torch.from_numpy(a.val).to(dev), nrhs, B.PP_JACOBI | B.PP_MIXED)
+    B.pp_batch_setup(h, k, np.array([lmin]), np.array([lmax]), args.xi)
+    tune = autotune.tune(h, mixed=True)
+    Bm = torch.from_numpy(W.block_rhs(n, nrhs, 3000)).to(dev)
+    X = torch.zeros(n, nrhs, dtype=torch.float64, device=dev)
+    B.pcg_solve_batch(h, 1, nrhs, Bm, X, args.tol, args.maxit)  # warm-up (captures the graph)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(max(1, args.steps)):
+        X.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s, it, rel, stt = B.pcg_solve_batch(h, 1, nrhs, Bm, X, args.tol, args.maxit)
+        times.append(time.perf_counter() - t0)
+    tb = sum(times) / len(times)
+    st = B.pp_batch_get_stats(h)
+    B.pp_destroy_batch(h)
+    single = fp64_single(k)
+    out = dict(workload="hetero_diffusion_256^3_%drhs_jacobi" % nrhs, nrhs=nrhs, k=k, dtype="f32 polynomial, f64 CG",
+               s_per_solve=tb, s_per_rhs=tb / nrhs, iters_max=int(it.max()), iters_min=int(it.min()),
+               relres_max=float(rel.max()), status=B.pp_status_str(s), layout_w=st["w"], autotune=tune,
+               fp64_single_s=single, fp64_sequential_s=single * nrhs,
+               speedup_vs_fp64_sequential=single * nrhs / tb)
+    log("block %d rhs k=%d: %.3f s (%.4f s per rhs), iters %d..%d, vs %d sequential FP64 solves %.2fx"
+        % (nrhs, k, tb, tb / nrhs, it.min(), it.max(), nrhs, out["speedup_vs_fp64_sequential"]))
+    return out
+
+
+def run_batch256(args, B, W, torch, dev):
+    """256 uneven heterogeneous systems (n ~ U[1e4, 2e6]) in one batched solve vs one-at-a-time FP64."""
+    t0 = time.perf_counter()
+    sides = W.batch_sizes()
+    systems, rhs = [], []
+    for i, N in enumerate(sides):
+        a_i, b_i = W.batch_system(i, int(N))
+        systems.append(a_i)
+        rhs.append(b_i)
+    full, sp = W.block_diag(systems)
+    bvec = np.concatenate(rhs)
+    log("batch256: generated n=%d nnz=%d in %.0fs" % (full.n_rows, full.nnz, time.perf_counter() - t0))
+    k = args.block_k
+    h = B.pp_create_batch(len(systems), sp, full.nnz, torch.from_numpy(full.rowptr).to(dev),
+                          torch.from_numpy(full.col).to(dev), torch.from_numpy(full.val).to(dev), 1,
+                          B.PP_JACOBI | B.PP_MIXED)
+    del full
+    lo, hi = B.pp_batch_estimate_bounds(h, len(systems), 20)
+    B.pp_batch_setup(h, k, lo, hi, args.xi)
+    bd = torch.from_numpy(bvec).to(dev).reshape(-1, 1)
+    X = torch.zeros_like(bd)
+    B.pcg_solve_batch(h, len(systems), 1, bd, X, args.tol, args.maxit)
+    X.zero_()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s, it, rel, stt = B.pcg_solve_batch(h, len(systems), 1, bd, X, args.tol, args.maxit)
+    tb = time.perf_counter() - t1
+    B.pp_destroy_batch(h)
+    # plain FP64, one system at a time, same bounds and degree
+    tseq = 0.0
+    for i, a_i in enumerate(systems):
+        op = B.Operator(a=a_i, flags=B.PP_JACOBI)
+        B.pp_setup(op.handle, k, lo[i], hi[i], args.xi)
+        bi = torch.from_numpy(rhs[i]).to(dev)
+        xi = torch.zeros_like(bi)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        B.pcg_solve(op.handle, bi, xi, args.tol, args.maxit)
+        tseq += time.perf_counter() - t2
+        op.close()
+    out = dict(workload="batch256_hetero_uneven", nsys=len(systems), n=int(sp[-1]), k=k,
+               dtype="f32 polynomial, f64 CG", s_per_solve=tb, iters_max=int(it.max()), iters_min=int(it.min()),
+               relres_max=float(rel.max()), status=B.pp_status_str(s), fp64_sequential_s=tseq,
+               speedup_vs_fp64_sequential=tseq / tb)
+    log("batch256: %.2f s batched vs %.2f s sequential FP64 (%.2fx)" % (tb, tseq, tseq / tb))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -125,6 +209,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dfn", action="store_true", help="skip the DFN-shaped Schur leg")
     ap.add_argument("--dfn-k", type=int, default=40)
+    ap.add_argument("--no-block", action="store_true", help="skip the 32-RHS block leg")
+    ap.add_argument("--block-rhs", type=int, default=32)
+    ap.add_argument("--block-k", type=int, default=60)
+    ap.add_argument("--batch256", action="store_true",
+                    help="also run the 256-system uneven batch (about 60 GB, slow to generate)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (HBM counter calibration)")
     ap.add_argument("--grid", type=int, default=0, help="workgroups per launch (0 = library default)")
@@ -288,6 +377,24 @@ def main():
 
     dfn = None if args.no_dfn else run_dfn(args, B, W, torch, dev)
 
+    def fp64_single(k):
+        """Time of one plain FP64 solve (first block column) at degree k on the same operator."""
+        rec = next((r for r in per_k if r["k"] == k), None)
+        if rec is not None:
+            return rec["s_per_solve"]
+        B.pp_setup(h, k, lmin, lmax, args.xi)
+        b0 = torch.from_numpy(W.rhs_uniform(n, 3000)).to(dev)
+        x.zero_()
+        B.pcg_solve(h, b0, x, args.tol, args.maxit)
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B.pcg_solve(h, b0, x, args.tol, args.maxit)
+        return time.perf_counter() - t0
+
+    block = None if args.no_block else run_block(args, B, W, torch, dev, a, lmin, lmax, fp64_single)
+    batch256 = run_batch256(args, B, W, torch, dev) if args.batch256 else None
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle as O
@@ -328,6 +435,8 @@ def main():
         "per_k": per_k,
         "mixed": mixed,
         "dfn": dfn,
+        "block": block,
+        "batch256": batch256,
         "setup": {"create_s": round(t_create, 3), "lanczos_s": round(t_bounds, 4),
                   "nnz_stored": st0["nnz_stored"]},
     }

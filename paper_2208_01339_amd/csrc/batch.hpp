@@ -13,9 +13,8 @@
 // lanes) and the gathers of X[col][c0 .. c0+CPL) are contiguous.
 //
 // Reductions.  Per-(segment, column) dot products: each workgroup writes NB
-// partials, and the last workgroup of the segment (a per-segment ticket) sums
-// them in workgroup order and runs the CG scalar logic for that segment's
-// columns.  A column that finished keeps its iterate frozen; a segment whose
+// partials, and a finalising kernel with one workgroup per segment sums them
+// in workgroup order and runs the CG scalar logic for that segment's columns.  A column that finished keeps its iterate frozen; a segment whose
 // columns all finished is skipped by every later kernel.
 #pragma once
 #include "kernels.hpp"
@@ -62,8 +61,8 @@ __device__ __forceinline__ void mark_done(const Batch &bt, BState &st, int s, in
     const int i = s * bt.NB + c;
     st.done[i] = 1;
     st.status[i] = status;
-    atomicAdd(st.ndone, 1);  // several segments may finalise at once
-    st.seg_ndone[s] += 1;    // only segment s's last workgroup writes its own entries
+    atomicAdd(st.ndone, 1);  // several segments finalise at once
+    st.seg_ndone[s] += 1;    // only segment s's finalising workgroup writes its own entries
     if (st.seg_ndone[s] >= bt.NB) st.seg_done[s] = 1;
 }
 
@@ -116,34 +115,27 @@ __device__ inline void bfinalize(const Batch &bt, BState &st, int fin, int s, in
     }
 }
 
-// Publish this workgroup's NB partials (part[c] valid in thread 0 after the
-// workgroup sum); the last workgroup of the segment reduces and finalises.
-// lds must hold NB * WPB doubles; called by every thread.
+// Publish this workgroup's NB column partials (plain stores); kb_fin reduces them.
 template <int NB>
-__device__ inline void commit_seg(const Batch &bt, BState &st, double *partials, const double *mine, int fin,
-                                  int idx, double *lds)
+__device__ __forceinline__ void store_seg(double *partials, const double *mine)
 {
-    const int b = blockIdx.x;
-    const int s = bt.blk_seg[b];
-    __shared__ int last;
-    if (threadIdx.x < NB)
-        __hip_atomic_store(&partials[(size_t)b * NB + threadIdx.x], mine[threadIdx.x], __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const int nb = bt.seg_blk0[s + 1] - bt.seg_blk0[s];
-        const uint32_t t = __hip_atomic_fetch_add(&st.ticket[s], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        last = (t == (uint32_t)(nb - 1));
-    }
-    __syncthreads();
-    if (!last) return;
-    // threads t = c + NB m (m < M) sum workgroups b0 + m, b0 + m + M, ... of column c
+    if (threadIdx.x < NB) partials[(size_t)logical_block() * NB + threadIdx.x] = mine[threadIdx.x];
+}
+
+// One workgroup per segment: sum the segment's workgroup partials per column
+// in workgroup order and run the scalar logic for its columns.
+template <int NB>
+__global__ __launch_bounds__(BLOCK) void kb_fin(Batch bt, BState st, const double *__restrict__ partials, int fin,
+                                                int idx)
+{
+    const int s = blockIdx.x;
+    if (fin < BF_LZN && st.seg_done[s]) return;
+    __shared__ double lds[BLOCK + NB_MAX];
     constexpr int M = BLOCK / NB;
     const int c = threadIdx.x % NB, m = threadIdx.x / NB;
     const int b0 = bt.seg_blk0[s], b1 = bt.seg_blk0[s + 1];
     double acc = 0.0;
-    for (int q = b0 + m; q < b1; q += M)
-        acc += __hip_atomic_load(&partials[(size_t)q * NB + c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int q = b0 + m; q < b1; q += M) acc += partials[(size_t)q * NB + c];
     lds[threadIdx.x] = acc;
     __syncthreads();
     if (threadIdx.x < NB) {
@@ -153,10 +145,8 @@ __device__ inline void commit_seg(const Batch &bt, BState &st, double *partials,
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int cc = 0; cc < NB; ++cc) {
+        for (int cc = 0; cc < NB; ++cc)
             if (fin >= BF_LZN || cc < bt.nrhs) bfinalize(bt, st, fin, s, cc, lds[BLOCK + cc], idx);
-        }
-        __hip_atomic_store(&st.ticket[s], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -191,10 +181,14 @@ struct BlockRange {
     int64_t s0, s1, row_end;  // slice range and end of the segment's real rows
 };
 
+// logical workgroup: consecutive logical workgroups (one system's slices) run on
+// the same XCD, so stencil neighbours are gathered from that XCD's L2
+__device__ __forceinline__ int logical_block() { return ppk::xcd_remap((int)blockIdx.x, (int)gridDim.x); }
+
 __device__ __forceinline__ BlockRange my_range(const Batch &bt)
 {
     BlockRange r;
-    const int b = blockIdx.x;
+    const int b = logical_block();
     r.seg = bt.blk_seg[b];
     r.s0 = bt.blk_s0[b];
     r.s1 = bt.blk_s1[b];
@@ -304,7 +298,7 @@ __global__ __launch_bounds__(BLOCK) void kb_init_scale(Batch bt, BState st, ppk:
         }
     });
     block_colsum<W, CPL>(part, lds, lds + BLOCK + NB_MAX);
-    commit_seg<NB>(bt, st, partials, lds + BLOCK + NB_MAX, BF_BNORM, 0, lds);
+    store_seg<NB>(partials, lds + BLOCK + NB_MAX);
 }
 
 // R = Bh - A Xh -> BF_RR0 ; Q = A P -> BF_GAMMA (p.q) ; both FP64
@@ -336,7 +330,7 @@ __global__ __launch_bounds__(BLOCK) void kb_apply64(Batch bt, BState st, ppk::Se
         }
     });
     block_colsum<W, CPL>(part, lds, lds + BLOCK + NB_MAX);
-    commit_seg<NB>(bt, st, partials, lds + BLOCK + NB_MAX, WHICH == 0 ? BF_RR0 : BF_GAMMA, 0, lds);
+    store_seg<NB>(partials, lds + BLOCK + NB_MAX);
 }
 
 // One Chebyshev step on all columns (coefficients of the row's segment):
@@ -374,7 +368,7 @@ __global__ __launch_bounds__(BLOCK) void kb_cheb(Batch bt, BState st, ppk::SellV
     });
     if (LAST) {
         block_colsum<W, CPL>(part, lds, lds + BLOCK + NB_MAX);
-        commit_seg<NB>(bt, st, partials, lds + BLOCK + NB_MAX, fin, 0, lds);
+        store_seg<NB>(partials, lds + BLOCK + NB_MAX);
     }
 }
 
@@ -399,7 +393,7 @@ __global__ __launch_bounds__(BLOCK) void kb_deg0(Batch bt, BState st, ppk::SellV
         }
     });
     block_colsum<W, CPL>(part, lds, lds + BLOCK + NB_MAX);
-    commit_seg<NB>(bt, st, partials, lds + BLOCK + NB_MAX, fin, 0, lds);
+    store_seg<NB>(partials, lds + BLOCK + NB_MAX);
 }
 
 // Xh += alpha P ; R -= alpha Q (frozen columns keep their values) -> BF_RR
@@ -429,7 +423,7 @@ __global__ __launch_bounds__(BLOCK) void kb_xr(Batch bt, BState st, ppk::SellVie
         }
     });
     block_colsum<W, CPL>(part, lds, lds + BLOCK + NB_MAX);
-    commit_seg<NB>(bt, st, partials, lds + BLOCK + NB_MAX, BF_RR, 0, lds);
+    store_seg<NB>(partials, lds + BLOCK + NB_MAX);
 }
 
 // P = Z + beta P (first: P = Z); frozen columns keep P
@@ -542,7 +536,7 @@ static __global__ __launch_bounds__(BLOCK) void kb_lz_start(Batch bt, BState st,
         part[0] += x * x;
     });
     block_colsum<1, 1>(part, lds, lds + BLOCK + NB_MAX);
-    commit_seg<1>(bt, st, partials, lds + BLOCK + NB_MAX, BF_LZN, 0, lds);
+    store_seg<1>(partials, lds + BLOCK + NB_MAX);
 }
 
 // mode 0: v /= ||v|| and vprev = 0 ; mode 1: vprev = v, v = w / beta_j
@@ -593,7 +587,7 @@ __global__ __launch_bounds__(BLOCK) void kb_lz_step(Batch bt, BState st, ppk::Se
         });
     }
     block_colsum<1, 1>(part, lds, lds + BLOCK + NB_MAX);
-    commit_seg<1>(bt, st, partials, lds + BLOCK + NB_MAX, WHICH == 0 ? BF_LZA : BF_LZB, j, lds);
+    store_seg<1>(partials, lds + BLOCK + NB_MAX);
 }
 
 // ---------------------------------------------------------------------------

@@ -16,9 +16,9 @@
 // the same XCD's L2.
 //
 // Reductions are deterministic: a fixed-order wave shuffle tree, a fixed
-// order over the waves of a workgroup, one partial per workgroup, and the
-// last workgroup to finish (agent-scope ticket) sums the G partials in index
-// order and applies the CG scalar logic on the device.
+// order over the waves of a workgroup, one partial per workgroup, and a
+// one-workgroup kernel that sums the G partials in index order and applies
+// the CG scalar logic on the device.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -49,7 +49,7 @@ struct State {
     int32_t status;  // pp_status
     int32_t zero_b;  // b_hat == 0 -> x = 0
     int32_t pad;
-    uint32_t ticket; // last-workgroup ticket, always 0 between kernels
+    uint32_t ticket; // unused
     uint32_t pad2;
 };
 
@@ -168,29 +168,15 @@ __device__ inline void finalize(State *st, int fin, int idx, double s)
     }
 }
 
-// Publish this workgroup's partial; the last workgroup reduces all partials in
-// index order and runs finalize().  Every thread of the workgroup must call it.
-__device__ inline void commit_partial(double part, double *partials, State *st, int fin, int idx,
-                                      int L, int G)
+// Publish this workgroup's partial (one double per workgroup, plain store).
+// The reduction over workgroups is a separate one-workgroup kernel (k_fin):
+// the kernel boundary orders the stores before it, so no workgroup has to
+// flush its L2 with an agent-scope release before retiring.
+__device__ __forceinline__ void store_partial(double part, double *partials, int L)
 {
     __shared__ double lds[WPB];
-    __shared__ int last;
-    double s = block_sum(part, lds);
-    if (threadIdx.x == 0) {
-        __hip_atomic_store(&partials[L], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        uint32_t t = __hip_atomic_fetch_add(&st->ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        last = (t == (uint32_t)(G - 1));
-    }
-    __syncthreads();
-    if (!last) return;
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < G; i += BLOCK)
-        acc += __hip_atomic_load(&partials[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    double tot = block_sum(acc, lds);
-    if (threadIdx.x == 0) {
-        finalize(st, fin, idx, tot);
-        __hip_atomic_store(&st->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    const double s = block_sum(part, lds);
+    if (threadIdx.x == 0) partials[L] = s;
 }
 
 template <bool NT, typename T>
@@ -468,7 +454,7 @@ static __global__ __launch_bounds__(BLOCK) void k_cheb(SellView A, const XT *__r
     PPK_PROLOGUE(st)
     const double part = ph_cheb<T, XT, RT, OT, MODE, SCHUR, DOT, SCALE, NT>(
         A, xg, w, r, sold, out, (T)cx, (T)cold, (T)cr, (T)cA, dis, L, G);
-    if (DOT) commit_partial(part, partials, st, fin, 0, L, G);
+    if (DOT) store_partial(part, partials, L);
 }
 
 static __global__ __launch_bounds__(BLOCK) void k_state_init(State *st, double tol, int maxit)
@@ -493,7 +479,7 @@ static __global__ __launch_bounds__(BLOCK) void k_init_scale(int64_t n, const do
 {
     PPK_PROLOGUE(st)
     const double part = ph_init_scale(n, b, x, dis, bh, xh, L, G);
-    commit_partial(part, partials, st, FIN_BNORM, 0, L, G);
+    store_partial(part, partials, L);
 }
 
 template <bool SCHUR>
@@ -505,7 +491,7 @@ __global__ __launch_bounds__(BLOCK) void k_init_resid(SellView A, const double *
 {
     PPK_PROLOGUE(st)
     const double part = ph_init_resid<SCHUR>(A, xh, w, bh, r, L, G);
-    commit_partial(part, partials, st, FIN_RR0, 0, L, G);
+    store_partial(part, partials, L);
 }
 
 template <bool SCHUR>
@@ -515,7 +501,7 @@ __global__ __launch_bounds__(BLOCK) void k_pq(SellView A, const double *__restri
 {
     PPK_PROLOGUE(st)
     const double part = nt ? ph_pq<SCHUR, true>(A, p, w, q, L, G) : ph_pq<SCHUR, false>(A, p, w, q, L, G);
-    commit_partial(part, partials, st, FIN_GAMMA, 0, L, G);
+    store_partial(part, partials, L);
 }
 
 static __global__ __launch_bounds__(BLOCK) void k_xr(int64_t n, const double *__restrict__ p,
@@ -524,7 +510,7 @@ static __global__ __launch_bounds__(BLOCK) void k_xr(int64_t n, const double *__
 {
     PPK_PROLOGUE(st)
     const double part = ph_xr(n, p, q, x, r, st->alpha, L, G);
-    commit_partial(part, partials, st, FIN_RR, 0, L, G);
+    store_partial(part, partials, L);
 }
 
 static __global__ __launch_bounds__(BLOCK) void k_p(int64_t n, const double *__restrict__ z,
@@ -576,6 +562,19 @@ static __global__ __launch_bounds__(BLOCK) void k_scale2(int64_t n, const double
     });
 }
 
+// Sum the G workgroup partials in index order and run the scalar logic.  Skips
+// when the solve is already done (the producer kernel then wrote nothing).
+static __global__ __launch_bounds__(BLOCK) void k_fin(const double *__restrict__ partials, int G, State *st,
+                                                      int fin, int idx)
+{
+    if (st->done) return;
+    __shared__ double lds[WPB];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < G; i += BLOCK) acc += partials[i];
+    const double tot = block_sum(acc, lds);
+    if (threadIdx.x == 0) finalize(st, fin, idx, tot);
+}
+
 // r.z into the CG state (degree-0 preconditioner: no operator step to fuse into)
 static __global__ __launch_bounds__(BLOCK) void k_dot_fin(int64_t n, const double *__restrict__ x,
                                                    const double *__restrict__ y, double *partials,
@@ -584,7 +583,7 @@ static __global__ __launch_bounds__(BLOCK) void k_dot_fin(int64_t n, const doubl
     PPK_PROLOGUE(st)
     double part = 0.0;
     for_my_elems(n, L, G, [&](int64_t i) { part += x[i] * y[i]; });
-    commit_partial(part, partials, st, fin, 0, L, G);
+    store_partial(part, partials, L);
 }
 
 // y = x ./ d
@@ -621,7 +620,7 @@ static __global__ __launch_bounds__(BLOCK) void k_lz_start(int64_t n, double *__
         v[i] = x;
         part += x * x;
     });
-    commit_partial(part, partials, st, FIN_LZ_NORM0, 0, L, G);
+    store_partial(part, partials, L);
 }
 
 // v /= scratch[0]
@@ -654,7 +653,7 @@ __global__ __launch_bounds__(BLOCK) void k_lz_apply(SellView A, const double *__
             part += v[row] * wi;
         }
     });
-    commit_partial(part, partials, st, FIN_LZ_ALPHA, j, L, G);
+    store_partial(part, partials, L);
 }
 
 // w -= alpha_j v ; reduce w.w -> lz_beta[j]
@@ -671,7 +670,7 @@ static __global__ __launch_bounds__(BLOCK) void k_lz_orth(int64_t n, const doubl
         w[i] = wi;
         part += wi * wi;
     });
-    commit_partial(part, partials, st, FIN_LZ_BETA, j, L, G);
+    store_partial(part, partials, L);
 }
 
 // vprev = v ; v = w / beta_j

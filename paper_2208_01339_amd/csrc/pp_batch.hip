@@ -140,8 +140,8 @@ using IC = std::integral_constant<int, V>;
 bool layout_ok(int NB, int W)
 {
     if (NB == 1) return W == 1;
-    if (NB == 8) return W == 8 || W == 4 || W == 2;
-    if (NB == 32) return W == 32 || W == 16 || W == 8;
+    if (NB == 8) return W == 8 || W == 4 || W == 2 || W == 1;
+    if (NB == 32) return W == 32 || W == 16 || W == 8 || W == 4;
     return false;
 }
 
@@ -155,6 +155,8 @@ void with_layout(int W, int CPL, F &&f)
     else if (W == 32 && CPL == 1) f(IC<32>{}, IC<1>{});
     else if (W == 16 && CPL == 2) f(IC<16>{}, IC<2>{});
     else if (W == 8 && CPL == 4) f(IC<8>{}, IC<4>{});
+    else if (W == 1 && CPL == 8) f(IC<1>{}, IC<8>{});
+    else if (W == 4 && CPL == 8) f(IC<4>{}, IC<8>{});
 }
 
 // caller stream -> internal stream ordering
@@ -212,7 +214,9 @@ pp_status build(pp_batch_s *op, const int64_t *rowptr, const int32_t *colind, co
         // workgroups: proportional to slices, at least one per system, never two systems in one
         int cus = 256;
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, op->device);
-        const int64_t target = (int64_t)cus * 8;
+        // many systems: 4x more workgroups, so that the systems still running
+        // after the small ones finish keep the device busy
+        const int64_t target = (int64_t)cus * (S > 1 ? 32 : 8);
         std::vector<int32_t> blk_seg, seg_blk0(S + 1, 0);
         std::vector<int64_t> blk_s0, blk_s1;
         for (int s = 0; s < S; ++s) {
@@ -319,6 +323,15 @@ pp_status build(pp_batch_s *op, const int64_t *rowptr, const int32_t *colind, co
 // launches
 // ---------------------------------------------------------------------------
 
+// per-segment reduction of the previous kernel's partials
+template <int NB>
+void launch_fin(pp_batch_s *op, const ppb::BState &st, int fin, int idx = 0)
+{
+    if (fin == ppb::BF_NONE) return;
+    hipLaunchKernelGGL((ppb::kb_fin<NB>), dim3(op->S), dim3(BLOCK), 0, op->stream, op->bt(), st,
+                       (const double *)op->partials, fin, idx);
+}
+
 void launch_state_init(pp_batch_s *op, double tol, int maxit)
 {
     const int m = std::max(op->S * op->NB, op->S);
@@ -338,6 +351,7 @@ void poly(pp_batch_s *op, const ppb::BState &st, int fin)
     if (k == 0) {
         hipLaunchKernelGGL((ppb::kb_deg0<W, CPL>), g, b, 0, op->stream, bt, st, op->view(false), (const double *)op->R,
                            op->Z, (const double *)op->thinv_d, op->partials, fin);
+        launch_fin<W * CPL>(op, st, fin);
         return;
     }
     const bool nt = op->ntload != 0;
@@ -356,6 +370,7 @@ void poly(pp_batch_s *op, const ppb::BState &st, int fin)
                 if (mode == 1) { if (nt) KB64(1, true, true); else KB64(1, true, false); }
                 else if (mode == 2) { if (nt) KB64(2, true, true); else KB64(2, true, false); }
                 else { if (nt) KB64(3, true, true); else KB64(3, true, false); }
+                launch_fin<W * CPL>(op, st, fin);
             } else {
                 if (mode == 1) { if (nt) KB64(1, false, true); else KB64(1, false, false); }
                 else if (mode == 2) { if (nt) KB64(2, false, true); else KB64(2, false, false); }
@@ -383,6 +398,7 @@ void poly(pp_batch_s *op, const ppb::BState &st, int fin)
             if (mode == 1) { if (nt) KB32L(1, true); else KB32L(1, false); }
             else if (mode == 2) { if (nt) KB32L(2, true); else KB32L(2, false); }
             else { if (nt) KB32L(3, true); else KB32L(3, false); }
+            launch_fin<W * CPL>(op, st, fin);
         } else {
             if (mode == 1) { if (nt) KB32(1, true); else KB32(1, false); }
             else if (mode == 2) { if (nt) KB32(2, true); else KB32(2, false); }
@@ -405,8 +421,10 @@ void iteration(pp_batch_s *op, const ppb::BState &st)
     else
         hipLaunchKernelGGL((ppb::kb_apply64<W, CPL, 1, false>), g, b, 0, op->stream, bt, st, A, (const double *)op->P,
                            (const double *)nullptr, op->Q, op->partials);
+    launch_fin<W * CPL>(op, st, ppb::BF_GAMMA);
     hipLaunchKernelGGL((ppb::kb_xr<W, CPL>), g, b, 0, op->stream, bt, st, A, (const double *)op->P,
                        (const double *)op->Q, op->Xh, op->R, op->partials);
+    launch_fin<W * CPL>(op, st, ppb::BF_RR);
     poly<W, CPL>(op, st, ppb::BF_RHO);
     hipLaunchKernelGGL((ppb::kb_p<W, CPL>), g, b, 0, op->stream, bt, st, A, (const double *)op->Z, op->P, 0);
 }
@@ -569,12 +587,15 @@ pp_status pp_batch_estimate_bounds(pp_batch op, int steps, double *lambda_min, d
         launch_state_init(op, 0.0, 0);
         double *v = op->P, *vprev = op->Q, *w = op->Z;
         hipLaunchKernelGGL(ppb::kb_lz_start, g, b, 0, op->stream, bt, st, A, v, op->partials);
+        launch_fin<1>(op, st, ppb::BF_LZN);
         hipLaunchKernelGGL(ppb::kb_lz_vec, g, b, 0, op->stream, bt, st, A, v, vprev, (const double *)w, 0, 0);
         for (int j = 0; j < steps; ++j) {
             hipLaunchKernelGGL(ppb::kb_lz_step<0>, g, b, 0, op->stream, bt, st, A, (const double *)v,
                                (const double *)vprev, w, op->partials, j);
+            launch_fin<1>(op, st, ppb::BF_LZA, j);
             hipLaunchKernelGGL(ppb::kb_lz_step<1>, g, b, 0, op->stream, bt, st, A, (const double *)v,
                                (const double *)vprev, w, op->partials, j);
+            launch_fin<1>(op, st, ppb::BF_LZB, j);
             if (j + 1 < steps)
                 hipLaunchKernelGGL(ppb::kb_lz_vec, g, b, 0, op->stream, bt, st, A, v, vprev, (const double *)w, 1, j);
         }
@@ -641,8 +662,10 @@ pp_status pcg_solve_batch(pp_batch op, const double *B, double *X, double tol, i
             const ppk::SellView A = op->view(false);
             hipLaunchKernelGGL((ppb::kb_init_scale<W, CPL>), g, b, 0, op->stream, bt, st, A, B, (const double *)X,
                                (const double *)op->dis, op->Bh, op->Xh, op->partials);
+            launch_fin<W * CPL>(op, st, ppb::BF_BNORM);
             hipLaunchKernelGGL((ppb::kb_apply64<W, CPL, 0, false>), g, b, 0, op->stream, bt, st, A,
                                (const double *)op->Xh, (const double *)op->Bh, op->R, op->partials);
+            launch_fin<W * CPL>(op, st, ppb::BF_RR0);
             poly<W, CPL>(op, st, ppb::BF_RHO0);
             hipLaunchKernelGGL((ppb::kb_p<W, CPL>), g, b, 0, op->stream, bt, st, A, (const double *)op->Z, op->P, 1);
             HIPCHK(hipGetLastError());
@@ -734,6 +757,7 @@ pp_status pp_batch_apply(pp_batch op, const double *Rin, double *Zout)
             // R = D^{-1/2} Rin in the internal layout (Bh holds it), polynomial, Z = D^{-1/2} z
             hipLaunchKernelGGL((ppb::kb_init_scale<W, CPL>), g, b, 0, op->stream, bt, st, A, Rin, Rin,
                                (const double *)op->dis, op->R, op->Xh, op->partials);
+            launch_fin<W * CPL>(op, st, ppb::BF_BNORM);
             poly<W, CPL>(op, st, ppb::BF_NONE);
             hipLaunchKernelGGL((ppb::kb_final<W, CPL>), g, b, 0, op->stream, bt, st, A, (const double *)op->Z,
                                (const double *)op->dis, Zout);
@@ -750,7 +774,7 @@ pp_status pp_batch_autotune(pp_batch op, int *best_w, double *best_us)
 {
     if (!op || !best_w) return fail(PP_ERR_ARG, "NULL argument");
     if (!op->setup_done || op->k < 3) return fail(PP_ERR_STATE, "autotune needs pp_batch_setup with k >= 3");
-    const int cands[3] = {op->NB, op->NB / 2, op->NB / 4};
+    const int cands[5] = {op->NB, op->NB / 2, op->NB / 4, op->NB / 8, op->NB == 8 ? 1 : 0};
     double best = 1e300;
     int bw = op->W;
     try {
@@ -760,8 +784,11 @@ pp_status pp_batch_autotune(pp_batch op, int *best_w, double *best_us)
         HIPCHK(hipEventCreate(&e1));
         const ppb::BState st = op->bst(0.0, 1);
         launch_state_init(op, 0.0, 1);
-        for (int w : cands) {
-            if (w < 1 || !layout_ok(op->NB, w)) continue;
+        for (int ci = 0; ci < 5; ++ci) {
+            const int w = cands[ci];
+            bool seen = false;
+            for (int cj = 0; cj < ci; ++cj) seen = seen || cands[cj] == w;
+            if (w < 1 || seen || !layout_ok(op->NB, w)) continue;
             const int cpl = op->NB / w;
             double us = 0;
             with_layout(w, cpl, [&](auto wc, auto cc) {

@@ -367,6 +367,13 @@ pp_status create_common(pp_op *out, int kind, int64_t n, int64_t nnz, const int6
 // polynomial application (Algorithm 2), queued on the handle's stream
 // ---------------------------------------------------------------------------
 
+// reduce the G partials of the previous kernel into the CG state
+void enqueue_fin(pp_op_s *op, int G, int fin, int idx = 0)
+{
+    hipLaunchKernelGGL(ppk::k_fin, dim3(1), dim3(BLOCK), 0, op->stream, (const double *)op->partials, G, op->st, fin,
+                       idx);
+}
+
 struct StepCoef {
     double cx, cold, cr, cA;
 };
@@ -398,6 +405,14 @@ void launch_cheb(pp_op_s *op, const XT *xg, const T *w, const RT *r, const T *so
                  const StepCoef &c, int fin)
 {
     const bool f32 = sizeof(T) == 4;
+    struct FinAfter {
+        pp_op_s *op;
+        int fin;
+        ~FinAfter()
+        {
+            if (DOT && fin != ppk::FIN_NONE) enqueue_fin(op, op->grid_slices(), fin);
+        }
+    } after{op, fin};
     if (op->ntload)
         hipLaunchKernelGGL((ppk::k_cheb<T, XT, RT, OT, MODE, SCHUR, DOT, SCALE, true>), dim3(op->grid_slices()),
                            dim3(BLOCK), 0, op->stream, op->view(f32), xg, w, r, sold, out, c.cx, c.cold, c.cr,
@@ -445,9 +460,11 @@ void enqueue_poly(pp_op_s *op, const double *rr, double *zout, int fin, bool sca
         hipLaunchKernelGGL((ppk::k_scale<double, double>), dim3(op->grid_elems(op->n)), dim3(BLOCK), 0,
                            op->stream, op->n, rr, (const double *)(scale ? op->dis : nullptr), 1.0 / op->theta,
                            zout);
-        if (fin != ppk::FIN_NONE)
+        if (fin != ppk::FIN_NONE) {
             hipLaunchKernelGGL(ppk::k_dot_fin, dim3(op->grid_elems(op->n)), dim3(BLOCK), 0, op->stream, op->n,
                                rr, (const double *)zout, op->partials, op->st, fin);
+            enqueue_fin(op, op->grid_elems(op->n), fin);
+        }
         return;
     }
     if (!op->mixed()) {
@@ -526,8 +543,10 @@ void enqueue_iteration(pp_op_s *op, hipEvent_t e0, hipEvent_t e1)
     else
         hipLaunchKernelGGL(ppk::k_pq<false>, dim3(gs), dim3(BLOCK), 0, op->stream, op->view(false), op->p,
                            (const double *)nullptr, op->q, op->partials, op->st, op->ntload);
+    enqueue_fin(op, gs, ppk::FIN_GAMMA);
     hipLaunchKernelGGL(ppk::k_xr, dim3(ge), dim3(BLOCK), 0, op->stream, op->n, op->p, op->q, op->xh, op->r,
                        op->partials, op->st);
+    enqueue_fin(op, ge, ppk::FIN_RR);
     if (e0) (void)hipEventRecord(e0, op->stream);
     enqueue_poly(op, op->r, op->z, ppk::FIN_RHO, false);
     if (e1) (void)hipEventRecord(e1, op->stream);
@@ -805,6 +824,7 @@ pp_status pcg_solve(pp_op op, const double *b, double *x, double tol, int maxit,
         if (!persisted) {
             hipLaunchKernelGGL(ppk::k_init_scale, dim3(ge), dim3(BLOCK), 0, op->stream, n, b, (const double *)x,
                                (const double *)op->dis, op->bh, op->xh, op->partials, op->st);
+            enqueue_fin(op, ge, ppk::FIN_BNORM);
             enqueue_trace_f64(op, op->xh);
             if (op->schur())
                 hipLaunchKernelGGL(ppk::k_init_resid<true>, dim3(gs), dim3(BLOCK), 0, op->stream, op->view(false),
@@ -814,6 +834,7 @@ pp_status pcg_solve(pp_op op, const double *b, double *x, double tol, int maxit,
                 hipLaunchKernelGGL(ppk::k_init_resid<false>, dim3(gs), dim3(BLOCK), 0, op->stream, op->view(false),
                                    (const double *)op->xh, (const double *)nullptr, (const double *)op->bh, op->r,
                                    op->partials, op->st, op->ntload);
+            enqueue_fin(op, gs, ppk::FIN_RR0);
             hipEvent_t e0 = op->timing ? timing_event(op, ev_i++) : nullptr;
             hipEvent_t e1 = op->timing ? timing_event(op, ev_i++) : nullptr;
             if (e0) HIPCHK(hipEventRecord(e0, op->stream));
@@ -900,6 +921,7 @@ pp_status pp_estimate_bounds(pp_op op, int steps, double *lambda_min, double *la
         double *v = op->sA, *vprev = op->sB, *w = op->q;
         hipLaunchKernelGGL(ppk::k_state_init, dim3(1), dim3(64), 0, op->stream, op->st, 0.0, 0);
         hipLaunchKernelGGL(ppk::k_lz_start, dim3(ge), dim3(BLOCK), 0, op->stream, n, v, op->partials, op->st);
+        enqueue_fin(op, ge, ppk::FIN_LZ_NORM0);
         hipLaunchKernelGGL(ppk::k_lz_norm, dim3(ge), dim3(BLOCK), 0, op->stream, n, v, (const ppk::State *)op->st);
         hipLaunchKernelGGL((ppk::k_scale<double, double>), dim3(ge), dim3(BLOCK), 0, op->stream, n,
                            (const double *)v, (const double *)nullptr, 0.0, vprev);
@@ -913,8 +935,10 @@ pp_status pp_estimate_bounds(pp_op op, int steps, double *lambda_min, double *la
                 hipLaunchKernelGGL(ppk::k_lz_apply<false>, dim3(gs), dim3(BLOCK), 0, op->stream, op->view(false),
                                    (const double *)v, (const double *)nullptr, (const double *)vprev, w,
                                    op->partials, op->st, j, op->ntload);
+            enqueue_fin(op, gs, ppk::FIN_LZ_ALPHA, j);
             hipLaunchKernelGGL(ppk::k_lz_orth, dim3(ge), dim3(BLOCK), 0, op->stream, n, (const double *)v, w,
                                op->partials, op->st, j);
+            enqueue_fin(op, ge, ppk::FIN_LZ_BETA, j);
             if (j + 1 < steps)
                 hipLaunchKernelGGL(ppk::k_lz_next, dim3(ge), dim3(BLOCK), 0, op->stream, n, vprev, v,
                                    (const double *)w, (const ppk::State *)op->st, j);
