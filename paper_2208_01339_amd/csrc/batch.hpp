@@ -115,6 +115,10 @@ __device__ inline void bfinalize(const Batch &bt, BState &st, int fin, int s, in
     }
 }
 
+// logical workgroup: consecutive logical workgroups (one system's slices) run on
+// the same XCD, so stencil neighbours are gathered from that XCD's L2
+__device__ __forceinline__ int logical_block() { return ppk::xcd_remap((int)blockIdx.x, (int)gridDim.x); }
+
 // Publish this workgroup's NB column partials (plain stores); kb_fin reduces them.
 template <int NB>
 __device__ __forceinline__ void store_seg(double *partials, const double *mine)
@@ -180,10 +184,6 @@ struct BlockRange {
     int seg;
     int64_t s0, s1, row_end;  // slice range and end of the segment's real rows
 };
-
-// logical workgroup: consecutive logical workgroups (one system's slices) run on
-// the same XCD, so stencil neighbours are gathered from that XCD's L2
-__device__ __forceinline__ int logical_block() { return ppk::xcd_remap((int)blockIdx.x, (int)gridDim.x); }
 
 __device__ __forceinline__ BlockRange my_range(const Batch &bt)
 {
