@@ -254,6 +254,60 @@ typedef struct {
 PP_API pp_status pp_batch_get_stats(pp_batch op, pp_batch_stats *st);
 
 PP_API void pp_destroy_batch(pp_batch op);
+
+/* ------------------------------------------------------------------------
+ * Learned bounds: a small multilayer perceptron (ReLU hidden layers, linear
+ * output, FP32) that maps 16 cheap operator features to
+ * (log lambda_min, log lambda_max, log10(xi + 1e-5)), trained on bounds and
+ * iteration counts produced by this library.  Hand-written kernels for the
+ * forward pass, the gradients of the mean squared error and Adam.  The
+ * paper leaves the choice of xi problem dependent (section 2.4); the
+ * Lanczos bounds stay the fallback and the reference.
+ * ------------------------------------------------------------------------ */
+typedef struct pp_mlp_s *pp_mlp;
+
+/* n_in <= 32 inputs, depth hidden layers of `hidden` units, n_out <= 8
+ * outputs; weights He-uniform from `seed` (splitmix64), biases 0. */
+PP_API pp_status pp_mlp_create(pp_mlp *out, int n_in, int hidden, int depth, int n_out, uint64_t seed,
+                               void *stream);
+PP_API void pp_mlp_destroy(pp_mlp mlp);
+/* number of parameters; the flat layout is, per layer, W [fan_in][fan_out] row-major then b [fan_out] */
+PP_API pp_status pp_mlp_num_params(pp_mlp mlp, int64_t *count);
+PP_API pp_status pp_mlp_get_params(pp_mlp mlp, float *dst);       /* device [count] */
+PP_API pp_status pp_mlp_set_params(pp_mlp mlp, const float *src); /* device [count]; resets Adam */
+/* feature / target normalisation used by pp_predict_bounds (host arrays) */
+PP_API pp_status pp_mlp_set_normalization(pp_mlp mlp, const double *in_mean, const double *in_std,
+                                          const double *out_mean, const double *out_std);
+/* Y [batch][n_out] = MLP(X [batch][n_in]); device arrays, batch <= 1024 */
+PP_API pp_status pp_mlp_forward(pp_mlp mlp, int batch, const float *X, float *Y);
+/* loss = mean (Y - T)^2 over the batch; grad (device [count], may be NULL) its gradient; host loss */
+PP_API pp_status pp_mlp_loss_grad(pp_mlp mlp, int batch, const float *X, const float *T, float *grad,
+                                  double *loss);
+/* one Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the batch; host loss before the step */
+PP_API pp_status pp_mlp_train_step(pp_mlp mlp, int batch, const float *X, const float *T, float lr,
+                                   double *loss);
+
+/*
+ * 16 features of the (scaled) operator, HOST output f[16]:
+ *  0 log10 n, 1 nnz/n, 2..5 mean/std/min/max of log10 of the unscaled diagonal,
+ *  6 Gershgorin upper bound of lambda_max, 7 mean off-diagonal absolute row sum,
+ *  8 Gershgorin lower bound (A / A_ff part), 9..12 Rayleigh quotients after
+ *  power_steps/4, /2, 3/4 and power_steps power steps (lower bounds of
+ *  lambda_max), 13 lambda_min estimate from power_steps steps on (c I - A),
+ *  c = feature 6, 14 longest row, 15 log10(feature 12 / |feature 13|).
+ *  power_steps: even, 2..64.
+ */
+PP_API pp_status pp_features(pp_op op, int power_steps, double *f);
+
+/*
+ * Predict (lambda_min, lambda_max, xi) for pp_setup.  The prediction is
+ * rejected (fallback = 1: 20-step Lanczos bounds, xi = 0) when it is not
+ * finite, lambda_min <= 0, lambda_min >= lambda_max, lambda_max lies below
+ * the last Rayleigh quotient (a certified lower bound of lambda_max) or
+ * above the Gershgorin upper bound, or xi > 0.1.  Host outputs.
+ */
+PP_API pp_status pp_predict_bounds(pp_op op, pp_mlp mlp, int power_steps, double *lambda_min,
+                                   double *lambda_max, double *scaling, int *fallback);
 PP_API const char *pp_status_str(pp_status s);
 PP_API const char *pp_last_error(void);
 

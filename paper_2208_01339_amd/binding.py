@@ -25,7 +25,9 @@ ABI_FUNCTIONS = (
     "pp_operator_apply", "pp_get_stats", "pp_set_option", "pp_destroy", "pp_status_str",
     "pp_last_error", "pp_create_batch", "pp_batch_estimate_bounds", "pp_batch_setup",
     "pcg_solve_batch", "pp_batch_apply", "pp_batch_set_layout", "pp_batch_autotune",
-    "pp_batch_set_option", "pp_batch_get_stats", "pp_destroy_batch",
+    "pp_batch_set_option", "pp_batch_get_stats", "pp_destroy_batch", "pp_mlp_create", "pp_mlp_destroy",
+    "pp_mlp_num_params", "pp_mlp_get_params", "pp_mlp_set_params", "pp_mlp_set_normalization",
+    "pp_mlp_forward", "pp_mlp_loss_grad", "pp_mlp_train_step", "pp_features", "pp_predict_bounds",
 )
 
 
@@ -91,8 +93,21 @@ def lib():
         L.pp_batch_get_stats.argtypes = [P, C.POINTER(pp_batch_stats)]
         L.pp_destroy_batch.argtypes = [P]
         L.pp_destroy_batch.restype = None
+        F32 = C.c_float
+        L.pp_mlp_create.argtypes = [C.POINTER(P), I32, I32, I32, I32, C.c_uint64, P]
+        L.pp_mlp_destroy.argtypes = [P]
+        L.pp_mlp_destroy.restype = None
+        L.pp_mlp_num_params.argtypes = [P, C.POINTER(I64)]
+        L.pp_mlp_get_params.argtypes = [P, P]
+        L.pp_mlp_set_params.argtypes = [P, P]
+        L.pp_mlp_set_normalization.argtypes = [P, P, P, P, P]
+        L.pp_mlp_forward.argtypes = [P, I32, P, P]
+        L.pp_mlp_loss_grad.argtypes = [P, I32, P, P, P, C.POINTER(D)]
+        L.pp_mlp_train_step.argtypes = [P, I32, P, P, F32, C.POINTER(D)]
+        L.pp_features.argtypes = [P, I32, P]
+        L.pp_predict_bounds.argtypes = [P, P, I32, C.POINTER(D), C.POINTER(D), C.POINTER(D), C.POINTER(I32)]
         for f in ABI_FUNCTIONS:
-            if f not in ("pp_destroy", "pp_status_str", "pp_last_error", "pp_destroy_batch"):
+            if f not in ("pp_destroy", "pp_status_str", "pp_last_error", "pp_destroy_batch", "pp_mlp_destroy"):
                 getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -328,6 +343,79 @@ class BatchOperator:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# learned bounds
+# ---------------------------------------------------------------------------
+
+NFEAT = 16
+
+
+def pp_mlp_create(n_in=16, hidden=128, depth=3, n_out=3, seed=0, stream=None):
+    h = C.c_void_p()
+    _check(lib().pp_mlp_create(C.byref(h), int(n_in), int(hidden), int(depth), int(n_out), int(seed),
+                               _stream(stream)))
+    return h
+
+
+def pp_mlp_destroy(h):
+    if h:
+        lib().pp_mlp_destroy(h)
+
+
+def pp_mlp_num_params(h):
+    c = C.c_int64()
+    _check(lib().pp_mlp_num_params(h, C.byref(c)))
+    return c.value
+
+
+def pp_mlp_get_params(h, dst):
+    return _check(lib().pp_mlp_get_params(h, _ptr(dst)))
+
+
+def pp_mlp_set_params(h, src):
+    return _check(lib().pp_mlp_set_params(h, _ptr(src)))
+
+
+def pp_mlp_set_normalization(h, in_mean, in_std, out_mean, out_std):
+    import numpy as np
+
+    a = [np.ascontiguousarray(v, dtype=np.float64) for v in (in_mean, in_std, out_mean, out_std)]
+    return _check(lib().pp_mlp_set_normalization(h, *[_hptr(v) for v in a]))
+
+
+def pp_mlp_forward(h, X, Y):
+    return _check(lib().pp_mlp_forward(h, int(X.shape[0]), _ptr(X), _ptr(Y)))
+
+
+def pp_mlp_loss_grad(h, X, T, grad=None):
+    loss = C.c_double()
+    _check(lib().pp_mlp_loss_grad(h, int(X.shape[0]), _ptr(X), _ptr(T), _ptr(grad), C.byref(loss)))
+    return loss.value
+
+
+def pp_mlp_train_step(h, X, T, lr):
+    loss = C.c_double()
+    _check(lib().pp_mlp_train_step(h, int(X.shape[0]), _ptr(X), _ptr(T), float(lr), C.byref(loss)))
+    return loss.value
+
+
+def pp_features(op, power_steps=8):
+    import numpy as np
+
+    f = np.zeros(NFEAT)
+    _check(lib().pp_features(op, int(power_steps), _hptr(f)))
+    return f
+
+
+def pp_predict_bounds(op, mlp, power_steps=8):
+    """Returns (lambda_min, lambda_max, xi, fallback)."""
+    lo, hi, xi = C.c_double(), C.c_double(), C.c_double()
+    fb = C.c_int()
+    _check(lib().pp_predict_bounds(op, mlp, int(power_steps), C.byref(lo), C.byref(hi), C.byref(xi),
+                                   C.byref(fb)))
+    return lo.value, hi.value, xi.value, bool(fb.value)
 
 
 # ---------------------------------------------------------------------------

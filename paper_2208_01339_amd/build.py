@@ -10,9 +10,9 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = [os.path.join(HERE, "csrc", f) for f in ("pp_lib.hip", "pp_batch.hip")]
+SRC = [os.path.join(HERE, "csrc", f) for f in ("pp_lib.hip", "pp_batch.hip", "pp_mlp.hip")]
 DEPS = SRC + [os.path.join(HERE, "csrc", f) for f in (
-    "kernels.hpp", "sym_eig.hpp", "persistent.hpp", "batch.hpp", "common.hpp")] + [
+    "kernels.hpp", "sym_eig.hpp", "persistent.hpp", "batch.hpp", "common.hpp", "op.hpp", "mlp.hpp")] + [
     os.path.join(ROOT, "include", "pp.h")]
 OUT = os.path.join(HERE, "libppcg.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -1,0 +1,114 @@
+// The single-operator handle, shared by the translation units of the library.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+constexpr int PP_GRID_DEFAULT = 2048;
+
+struct pp_op_s {
+    int kind = 0;  // 0 CSR, 1 Schur
+    int64_t n = 0, nt = 0, nnz_c = 0, nnz_given = 0;
+    unsigned flags = 0;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    // slice layout of A-hat (and appended trace columns)
+    int64_t nslices = 0, nstored = 0;
+    int64_t *sp = nullptr;
+    int32_t *scol = nullptr;
+    double *sval = nullptr;
+    float *sval32 = nullptr;
+    // trace operator M^{-1} C-hat (Schur)
+    int64_t *crp = nullptr;
+    int32_t *ccol = nullptr;
+    double *cm = nullptr;
+    float *cm32 = nullptr;
+    double *tw = nullptr;
+    float *tw32 = nullptr;
+    // Jacobi
+    double *dis = nullptr;
+    // work vectors
+    double *xh = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr, *bh = nullptr;
+    double *sA = nullptr, *sB = nullptr;
+    float *r32 = nullptr, *sA32 = nullptr, *sB32 = nullptr;
+    double *partials = nullptr;
+    double *coef_d = nullptr;  // [k][4] step coefficients for the persistent driver
+    int coef_k = -1;           // degree the device coefficients were uploaded for
+    std::vector<double> coef_h;
+    int persist_occ[4] = {0, 0, 0, 0};
+    ppk::State *st = nullptr;
+    ppk::State *hst = nullptr;  // pinned
+    int32_t *hflag = nullptr;   // pinned, 2 slots
+    hipEvent_t flag_ev[2] = {nullptr, nullptr};
+    std::vector<hipEvent_t> tev;  // timing events (pairs)
+    hipEvent_t solve_ev[2] = {nullptr, nullptr};
+    // polynomial
+    bool setup_done = false;
+    int k = 0;
+    double lmin = 0, lmax = 0, xi = 0, theta = 0, delta = 0, sigma = 0;
+    std::vector<double> rho;
+    // options
+    int grid_max = PP_GRID_DEFAULT;
+    int grid_auto = PP_GRID_DEFAULT;  // resident workgroups of the fused step (CUs x occupancy)
+    int chunk = 0;  // 0 = auto
+    int timing = 0;
+    int driver = -1;  // -1 auto, 0 stream-driven, 1 persistent
+    int ntload = 1;
+    pp_stats stats{};
+
+    bool schur() const { return kind == 1; }
+    bool mixed() const { return (flags & PP_MIXED) != 0; }
+
+    int grid_slices() const
+    {
+        int64_t g = (nslices + ppk::WPB - 1) / ppk::WPB;
+        return (int)std::max<int64_t>(1, std::min<int64_t>(g, grid_max));
+    }
+    int grid_elems(int64_t cnt) const
+    {
+        int64_t g = (cnt + ppk::BLOCK - 1) / ppk::BLOCK;
+        return (int)std::max<int64_t>(1, std::min<int64_t>(g, grid_max));
+    }
+    ppk::SellView view(bool f32) const
+    {
+        ppk::SellView v;
+        v.sp = sp;
+        v.col = scol;
+        v.val = f32 ? (const void *)sval32 : (const void *)sval;
+        v.n = n;
+        v.nslices = nslices;
+        v.nx = n;
+        return v;
+    }
+    ppk::CsrView cview(bool f32) const
+    {
+        ppk::CsrView v;
+        v.rp = crp;
+        v.col = ccol;
+        v.val = f32 ? (const void *)cm32 : (const void *)cm;
+        v.rows = nt;
+        return v;
+    }
+
+    void release()
+    {
+        ppc::dfree(sp); ppc::dfree(scol); ppc::dfree(sval); ppc::dfree(sval32);
+        ppc::dfree(crp); ppc::dfree(ccol); ppc::dfree(cm); ppc::dfree(cm32); ppc::dfree(tw); ppc::dfree(tw32);
+        ppc::dfree(dis);
+        ppc::dfree(xh); ppc::dfree(r); ppc::dfree(p); ppc::dfree(q); ppc::dfree(z); ppc::dfree(bh); ppc::dfree(sA); ppc::dfree(sB);
+        ppc::dfree(r32); ppc::dfree(sA32); ppc::dfree(sB32);
+        ppc::dfree(partials); ppc::dfree(coef_d); ppc::dfree(st);
+        if (hst) (void)hipHostFree(hst);
+        if (hflag) (void)hipHostFree(hflag);
+        hst = nullptr;
+        hflag = nullptr;
+        for (auto &e : flag_ev) if (e) { (void)hipEventDestroy(e); e = nullptr; }
+        for (auto &e : solve_ev) if (e) { (void)hipEventDestroy(e); e = nullptr; }
+        for (auto &e : tev) (void)hipEventDestroy(e);
+        tev.clear();
+    }
+};
