@@ -36,6 +36,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "PCG time-to-1e-8 residual (s) + p_k(A)v HBM GB/s; mixed/batched vs plain FP64"
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_SUMMARY = "k_cheb_fp64_hetero256_k20_hbm_counters.txt"
 
 
 def log(*a):
@@ -195,6 +196,23 @@ def run_batch256(args, B, W, torch, dev):
     return out
 
 
+def committed_traffic(args, n, k):
+    """HBM bytes per fused-step launch from the committed rocprofv3 counter summary.
+
+    Null unless the summary was taken on this workload and degree from the
+    kernel sources that are built now (same source digest).
+    """
+    from paper_2208_01339_amd import profsum
+
+    summ = profsum.read_summary(os.path.join(ROOT, "profiles", TRAFFIC_SUMMARY))
+    try:
+        ok = (summ.get("source_digest") == profsum.source_digest() and int(summ.get("n", -1)) == n
+              and int(summ.get("k", -1)) == k and args.grid == 0 and args.nt_loads < 0 and args.xi == 0.0)
+        return float(summ["traffic_bytes_per_launch"]) if ok else None
+    except (KeyError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -335,8 +353,9 @@ def main():
     step_us = best["cheb_step_us"]
     bps = cheb_bytes_per_step(n, nnz, kh)
     achieved = bps / (step_us * 1e-6) / 1e9
+    traffic = committed_traffic(args, n, kh)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_cheb (fused SpMV + Chebyshev three-term step, FP64)",
                 "bytes_per_launch": int(bps), "mean_launch_us": round(step_us, 2)}
 
