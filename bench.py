@@ -16,9 +16,13 @@ The JSON line also carries:
   roofline      the fused Chebyshev step kernel: algorithmic bytes per launch
                 (k B_A + 8n(4k-3)) / k with B_A = 12 nnz + 4(n+1) (FP64 CSR)
                 divided by its mean duration, measured with HIP events around
-                every polynomial application inside the timed solves;
-  cpu_baseline  the CPU oracle (single thread) on a bounded sample: one PCG
-                iteration at k = 20 (21 operator applications with their
+                every polynomial application inside the timed solves; also the
+                bytes of the storage actually read (symmetric stored diagonals
+                hold about half of the CSR bytes) and their rate, and the
+                measured HBM traffic when a counter summary of the same kernel
+                sources is committed under profiles/;
+  cpu_baseline  the CPU oracle (single thread) on a bounded sample: four PCG
+                iterations at k = 20 (105 operator applications with their
                 vector work), scaled per operator application to the
                 applications of the headline GPU solve;
   mixed         the same solve with the polynomial in FP32 (PP_MIXED).
@@ -37,6 +41,7 @@ sys.path.insert(0, ROOT)
 METRIC = "PCG time-to-1e-8 residual (s) + p_k(A)v HBM GB/s; mixed/batched vs plain FP64"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_SUMMARY = "k_cheb_fp64_hetero256_k20_hbm_counters.txt"
+CPU_SAMPLE_ITERS = 4  # about 10 s of single-thread oracle work at 256^3, k = 20
 
 
 def log(*a):
@@ -55,6 +60,22 @@ def cheb_bytes_per_step(n, nnz, k, fp32=False):
         return 0.0
     # step 1 reads r and writes s_1; step 2 reads s_1, r; steps >= 3 read s_{j-1}, r, s_{j-2}
     total = k * ba + vec * n * (4 * k - 3) if k >= 2 else ba + 2 * vec * n
+    return total / k
+
+
+def stored_bytes_per_step(n, stats, k, fp32=False):
+    """Bytes one fused step reads and writes in the storage the library chose.
+
+    Symmetric stored diagonals (d arrays of n padded to whole 64-row slices),
+    the sliced remainder (value + int32 column per stored entry, one int64
+    offset per slice), and the vector traffic of the step.
+    """
+    vb = 4 if fp32 else 8
+    npad = -(-n // 64) * 64
+    mat = vb * stats["diagonals"] * npad
+    if stats["nnz_stored"] > 0:
+        mat += (vb + 4) * stats["nnz_stored"] + 8 * (npad // 64 + 1)
+    total = k * mat + vb * n * (4 * k - 3) if k >= 2 else mat + 2 * vb * n
     return total / k
 
 
@@ -102,11 +123,14 @@ def run_dfn(args, B, W, torch, dev):
     tsolve = (time.perf_counter() - tt0) / max(1, args.steps)
     step_us = 1000.0 * cms / max(1, csteps)
     bps = schur_bytes_per_step(n, s.a.nnz, nt, s.c.nnz, k)
+    # stored: diagonals + sliced trace columns, plus the trace phase (C read, w written and read)
+    sbps = stored_bytes_per_step(n, st, k) + 12 * s.c.nnz + 8 * (nt + 1) + 16 * nt
     out = dict(workload="dfn_schur_2000x64x64_5000traces_jacobi", n=n, nt=nt, nnz_a=s.a.nnz, nnz_c=s.c.nnz,
                k=k, s_per_solve=tsolve, iters=it, relres=rel, status=B.pp_status_str(status),
                bounds=[lmin, lmax], step_us=step_us, step_gbs=bps / (step_us * 1e-6) / 1e9,
                step_frac_hbm=bps / (step_us * 1e-6) / 1e9 / HBM_PEAK_GBS, create_s=t_create,
-               nnz_stored=st["nnz_stored"])
+               nnz_stored=st["nnz_stored"], diagonals=st["diagonals"],
+               stored_bytes_per_step=int(sbps), stored_gbs=sbps / (step_us * 1e-6) / 1e9)
     B.pp_destroy(h)
     log("dfn k=%d: %.3f s/solve, iters %d, step %.1f us (%.0f GB/s)" % (k, tsolve, it, step_us, out["step_gbs"]))
     return out
@@ -353,11 +377,17 @@ def main():
     step_us = best["cheb_step_us"]
     bps = cheb_bytes_per_step(n, nnz, kh)
     achieved = bps / (step_us * 1e-6) / 1e9
+    sbps = stored_bytes_per_step(n, st0, kh)
     traffic = committed_traffic(args, n, kh)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_cheb (fused SpMV + Chebyshev three-term step, FP64)",
-                "bytes_per_launch": int(bps), "mean_launch_us": round(step_us, 2)}
+                "bytes_per_launch": int(bps), "mean_launch_us": round(step_us, 2),
+                "stored_bytes_per_launch": int(sbps),
+                "stored_gbs": round(sbps / (step_us * 1e-6) / 1e9, 1),
+                "stored_frac": round(sbps / (step_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                "storage": "%d symmetric stored diagonals + %d sliced entries" % (st0["diagonals"],
+                                                                                  st0["nnz_stored"])}
 
     mixed = None
     if not args.no_mixed:
@@ -421,14 +451,14 @@ def main():
         kc = args.cpu_sample_k or 20
         orc = O.Operator(a, jacobi=True)
         c0 = time.perf_counter()
-        _, sto = O.pcg(orc, kc, lmin, lmax, args.xi, b, tol=args.tol, maxit=1)
+        _, sto = O.pcg(orc, kc, lmin, lmax, args.xi, b, tol=args.tol, maxit=CPU_SAMPLE_ITERS)
         t_it = time.perf_counter() - c0
         per_apply = t_it / sto["n_apply"]
         cpu = {"value": round(per_apply * best["op_applies"], 2), "unit": "s", "cores": 1, "kind": "oracle",
-               "sample": "one PCG iteration at k=%d (%d operator applications with the vector work, %.1f s) "
+               "sample": "%d PCG iterations at k=%d (%d operator applications with the vector work, %.1f s) "
                          "of the same 256^3 FP64 system on 1 host thread; scaled per operator application "
                          "to the %d applications of the GPU's k=%d solve"
-                         % (kc, sto["n_apply"], t_it, best["op_applies"], kh)}
+                         % (CPU_SAMPLE_ITERS, kc, sto["n_apply"], t_it, best["op_applies"], kh)}
         log("cpu oracle: %.3fs per application -> %.0fs per solve" % (per_apply, cpu["value"]))
 
     out = {

@@ -62,8 +62,21 @@ typedef enum {
 /* create flags */
 enum {
     PP_JACOBI = 1u, /* iterate on D^{-1/2} A D^{-1/2}, D = diag(A) (section 3, 4.2)        */
-    PP_MIXED = 2u   /* p_k(A)v in FP32 (values, vectors, accumulation); CG stays FP64     */
+    PP_MIXED = 2u,  /* p_k(A)v in FP32 (values, vectors, accumulation); CG stays FP64     */
+    PP_SLICED = 4u  /* keep every entry in the sliced layout (no symmetric diagonal part)  */
 };
+
+/*
+ * Storage.  By default an operator whose column offsets j - i take few
+ * distinct values (stencils, the fracture blocks of the Schur shape) keeps
+ * the densely populated offsets as symmetric stored diagonals: for offset
+ * o >= 0 one array of n values a_{i,i+o}, the mirrored entry a_{i+o,i} read
+ * from the same array, so a symmetric operator is read at about half the
+ * bytes of CSR.  This is used only when the covered entries are exactly
+ * symmetric and free of duplicates; all other entries (and the trace columns
+ * of the Schur shape) go to a sliced ELLPACK layout.  PP_SLICED forces the
+ * sliced layout for everything.
+ */
 
 /*
  * Create an operator from a CSR matrix A (n x n, symmetric positive definite).
@@ -156,10 +169,13 @@ typedef struct {
     int64_t cheb_steps;     /* polynomial steps covered by cheb_ms                  */
     double solve_ms;        /* device time of the whole solve (events)             */
     int64_t n;              /* operator order                                       */
-    int64_t nnz_stored;     /* matrix entries held in the slice layout (padded)     */
+    int64_t nnz_stored;     /* entries held in the slice layout (padded)            */
     int64_t nnz_matrix;     /* entries of the CSR / A_ff + C^T parts given          */
     int32_t driver;         /* 0 = stream-driven kernels, 1 = persistent kernel     */
     int32_t grid;           /* workgroups per launch used                           */
+    int32_t diagonals;      /* stored diagonals of the symmetric diagonal part      */
+                            /* (0 = every entry in the slice layout)                */
+    int32_t pad;
 } pp_stats;
 
 PP_API pp_status pp_get_stats(pp_op op, pp_stats *st);

@@ -1,12 +1,19 @@
 // Device code for polynomial-preconditioned CG on gfx950 (CDNA4).
 //
-// Layout.  The operator lives in a wavefront-row-group ("sliced ELLPACK")
-// layout: rows are grouped in slices of 64 (one wavefront, one lane per row);
-// inside a slice the j-th stored entry of all 64 rows is contiguous, so every
-// load of values and column indices is a fully coalesced 512 B (FP64) or
-// 256 B (int32 / FP32) wave access.  A slice is padded to its longest row
-// with (col = own row, val = 0).  For the Schur shape the trace term C^T w is
-// appended to the rows as extra columns n + t that index the trace vector w.
+// Layout.  Rows are grouped in slices of 64 (one wavefront, one lane per
+// row).  The operator has up to two parts:
+//  * symmetric stored diagonals: for each densely populated column offset
+//    o >= 0 one array of a_{i,i+o}; the mirrored entry a_{i,i-o} = a_{i-o,i}
+//    is the same array read o places back (a cache hit: rows i - o were
+//    streamed moments before by a workgroup of the same XCD), so a symmetric
+//    stencil is read at half its CSR value bytes and with no column indices;
+//  * a wavefront-row-group ("sliced ELLPACK") part for everything else: inside
+//    a slice the j-th stored entry of all 64 rows is contiguous, so every
+//    load of values and column indices is a fully coalesced 512 B (FP64) or
+//    256 B (int32 / FP32) wave access; a slice is padded to its longest row
+//    with (col = own row, val = 0).  For the Schur shape the trace term C^T w
+//    is appended to the rows as extra columns n + t that index the trace
+//    vector w.
 //
 // Scheduling.  Every streaming kernel runs a fixed grid of G workgroups of
 // 256 threads.  Workgroup b runs on XCD b % 8; it is remapped so that the G/8
@@ -22,6 +29,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 namespace ppk {
 
@@ -66,13 +75,26 @@ enum Fin : int {
     FIN_LZ_BETA      // lz_beta[idx] = sqrt(sum)
 };
 
+constexpr int DMAX = 16;  // stored diagonals of the symmetric diagonal storage
+
+// The operator: an optional symmetric diagonal part plus an optional slice
+// part.  Diagonal part: stored diagonal d (0 <= d < nd) holds a_{i, i + doff[d]}
+// at dv[d * dstride + i] (doff[0] = 0 < doff[1] < ...); the mirrored entry
+// a_{i, i - doff[d]} of a symmetric matrix is the same value, read from index
+// i - doff[d].  Entries outside the covered offsets (and the trace columns of
+// the Schur shape) live in the slice part.
 struct SellView {
-    const int64_t *sp;   // [nslices + 1] element offset of each slice (multiple of 64)
-    const int32_t *col;  // [sp[nslices]]
-    const void *val;     // [sp[nslices]] double or float
-    int64_t n;           // rows
-    int64_t nslices;
-    int64_t nx;          // columns < nx index x; columns >= nx index w[col - nx]
+    const int64_t *sp = nullptr;   // [nslices + 1] element offset of each slice (multiple of 64)
+    const int32_t *col = nullptr;  // [sp[nslices]]
+    const void *val = nullptr;     // [sp[nslices]] double or float
+    int64_t n = 0;                 // rows
+    int64_t nslices = 0;
+    int64_t nx = 0;                // columns < nx index x; columns >= nx index w[col - nx]
+    int sell = 1;                  // 0: the slice part is empty and is skipped
+    int nd = 0;                    // stored diagonals, 0 = no diagonal part
+    const void *dv = nullptr;      // [nd][dstride] double or float
+    int64_t dstride = 0;
+    int64_t doff[DMAX] = {};
 };
 
 struct CsrView {         // plain CSR (trace operator M^{-1} C)
@@ -192,11 +214,10 @@ __device__ __forceinline__ T ldm(const T *p)
 // dependent memory round trips whatever its length; indices past the row's
 // width are clamped to the last entry (an L1 hit) and their product dropped.
 // Columns >= nx read the trace vector w.
-template <typename T, typename XT, bool SCHUR, bool NT = false>
-__device__ __forceinline__ T sell_row(const SellView &A, const XT *__restrict__ x,
-                                      const T *__restrict__ w, int64_t base, int width, int lane)
+template <int U, typename T, typename XT, bool SCHUR, bool NT>
+__device__ __forceinline__ T sell_row_u(const SellView &A, const XT *__restrict__ x,
+                                        const T *__restrict__ w, int64_t base, int width, int lane)
 {
-    constexpr int U = 8;
     const int32_t *c = A.col + base + lane;
     const T *v = (const T *)A.val + base + lane;
     T acc = (T)0;
@@ -222,10 +243,128 @@ __device__ __forceinline__ T sell_row(const SellView &A, const XT *__restrict__ 
     return acc;
 }
 
+// Slices of at most two entries per row (the trace columns left beside a
+// diagonal part) take chunks of two, so they issue no clamped loads.
+template <typename T, typename XT, bool SCHUR, bool NT = false>
+__device__ __forceinline__ T sell_row(const SellView &A, const XT *__restrict__ x,
+                                      const T *__restrict__ w, int64_t base, int width, int lane)
+{
+    if (width <= 2) return sell_row_u<2, T, XT, SCHUR, NT>(A, x, w, base, width, lane);
+    return sell_row_u<8, T, XT, SCHUR, NT>(A, x, w, base, width, lane);
+}
+
 __device__ __forceinline__ void slice_span(const SellView &A, int64_t s, int64_t &base, int &width)
 {
     base = A.sp[s];
     width = (int)((A.sp[s + 1] - base) >> 6);
+}
+
+// (A x)_i over the diagonal part.  The diagonal first, then the off-diagonal
+// offsets in chunks of U: the upper value a_{i,i+o} streams from HBM, the
+// mirrored value a_{i,i-o} = a_{i-o,i} is the same array U o entries back and
+// is read from cache (rows i - o were streamed by this or a neighbouring
+// workgroup of the same XCD moments before).  All loads of a chunk are issued
+// before any product; offsets past nd are clamped to the last one and their
+// products dropped.  Column indices past either end of the matrix are
+// redirected to row i (their value is zero).
+template <typename T, typename XT, int U>
+__device__ __forceinline__ T dia_chunk(const SellView &A, const XT *__restrict__ x, int64_t i, int d0)
+{
+    const T *dv = (const T *)A.dv;
+    const int64_t n = A.n, ds = A.dstride;
+    const int nd = A.nd;
+    T vl[U], vu[U], xl[U], xu[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int d = d0 + u < nd ? d0 + u : nd - 1;
+        const int64_t o = A.doff[d];
+        const int64_t il = i >= o ? i - o : i;
+        const int64_t iu = i + o < n ? i + o : i;
+        vu[u] = dv[(int64_t)d * ds + i];
+        vl[u] = dv[(int64_t)d * ds + il];
+        xu[u] = (T)x[iu];
+        xl[u] = (T)x[il];
+    }
+    T acc = (T)0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        if (d0 + u < nd) {
+            if (i >= A.doff[d0 + u]) acc += vl[u] * xl[u];
+            acc += vu[u] * xu[u];
+        }
+    }
+    return acc;
+}
+
+template <typename T, typename XT>
+__device__ __forceinline__ T dia_row(const SellView &A, const XT *__restrict__ x, int64_t i)
+{
+    const T *dv = (const T *)A.dv;
+    T acc = dv[i] * (T)x[i];
+    if (A.nd <= 3) {  // 5-point (and narrower) stencils: one chunk, nothing wasted
+        if (A.nd > 1) acc += dia_chunk<T, XT, 2>(A, x, i, 1);
+    } else if (A.nd == 4) {  // 7-point stencils
+        acc += dia_chunk<T, XT, 3>(A, x, i, 1);
+    } else {
+        for (int d0 = 1; d0 < A.nd; d0 += 4) acc += dia_chunk<T, XT, 4>(A, x, i, d0);
+    }
+    return acc;
+}
+
+// (A x)_row for lane `lane` of slice s: diagonal part plus slice part.  The
+// slice span is read first so that its load overlaps the diagonal part.
+template <typename T, typename XT, bool SCHUR, bool NT = false>
+__device__ __forceinline__ T op_row(const SellView &A, const XT *__restrict__ x, const T *__restrict__ w,
+                                    int64_t row, int64_t s, int lane)
+{
+    int64_t base = 0;
+    int width = 0;
+    if (A.sell) slice_span(A, s, base, width);
+    T acc = (T)0;
+    if (A.nd > 0) acc = dia_row<T, XT>(A, x, row < A.n ? row : A.n - 1);
+    if (A.sell) acc += sell_row<T, XT, SCHUR, NT>(A, x, w, base, width, lane);
+    return acc;
+}
+
+// The same with the storage fixed at compile time, for the hot loops: DK
+// off-diagonal offsets in one straight-line chunk (DK = 0: no diagonal part,
+// DK < 0: the runtime form above), SP: slice part present.  With no branch
+// between them, every load of the row is issued before the first product.
+template <int DK, bool SP, typename T, typename XT, bool SCHUR, bool NT>
+__device__ __forceinline__ T op_row_fixed(const SellView &A, const XT *__restrict__ x, const T *__restrict__ w,
+                                          int64_t row, int64_t s, int lane)
+{
+    if constexpr (DK < 0) {
+        return op_row<T, XT, SCHUR, NT>(A, x, w, row, s, lane);
+    } else {
+        int64_t base = 0;
+        int width = 0;
+        if constexpr (SP) slice_span(A, s, base, width);
+        T acc = (T)0;
+        if constexpr (DK > 0) {
+            const int64_t i = row < A.n ? row : A.n - 1;
+            acc = dia_chunk<T, XT, DK>(A, x, i, 1) + ((const T *)A.dv)[i] * (T)x[i];
+        } else if constexpr (!SP) {
+            // diagonal only (nd == 1)
+            const int64_t i = row < A.n ? row : A.n - 1;
+            acc = ((const T *)A.dv)[i] * (T)x[i];
+        }
+        if constexpr (SP) acc += sell_row<T, XT, SCHUR, NT>(A, x, w, base, width, lane);
+        return acc;
+    }
+}
+
+// Call f(integral_constant<int, DK>, bool_constant<SP>) with the storage of A.
+template <typename F>
+__device__ __forceinline__ void with_storage(const SellView &A, F f)
+{
+    using std::integral_constant;
+    if (A.nd == 0) f(integral_constant<int, 0>{}, std::true_type{});
+    else if (A.nd == 4 && !A.sell) f(integral_constant<int, 3>{}, std::false_type{});
+    else if (A.nd == 4) f(integral_constant<int, 3>{}, std::true_type{});
+    else if (A.nd == 3 && A.sell) f(integral_constant<int, 2>{}, std::true_type{});
+    else if (A.nd == 3) f(integral_constant<int, 2>{}, std::false_type{});
+    else f(integral_constant<int, -1>{}, std::true_type{});
 }
 
 // Iterate the rows owned by logical workgroup L: fn(row, slice, lane).
@@ -293,26 +432,27 @@ __device__ __forceinline__ double ph_cheb(const SellView &A, const XT *__restric
                                           const double *__restrict__ dis, int L, int G)
 {
     double part = 0.0;
-    for_my_slices(A.nslices, L, G, [&](int64_t row, int64_t s, int lane) {
-        int64_t base;
-        int width;
-        slice_span(A, s, base, width);
-        // row-level operands first, so they are in flight with the matrix stream
-        const int64_t rc = row < A.n ? row : A.n - 1;
-        const RT ri = r[rc];
-        const T xs = (MODE >= 2) ? (T)xg[rc] : (T)0;
-        const T so = (MODE == 3) ? sold[rc] : (T)0;
-        const double ds = SCALE ? dis[rc] : 1.0;
-        T a = sell_row<T, XT, SCHUR, NT>(A, xg, w, base, width, lane);
-        if (row < A.n) {
-            T o = aA * a + ar * (T)ri;
-            if (MODE >= 2) o += ax * xs;
-            if (MODE == 3) o += aold * so;
-            OT ov = (OT)o;
-            if (SCALE) ov = (OT)((double)ov * ds);
-            out[row] = ov;
-            if (DOT) part += (double)ri * (double)ov;
-        }
+    with_storage(A, [&](auto dk, auto sp) {
+        constexpr int DK = decltype(dk)::value;
+        constexpr bool SP = decltype(sp)::value;
+        for_my_slices(A.nslices, L, G, [&](int64_t row, int64_t s, int lane) {
+            // row-level operands first, so they are in flight with the matrix stream
+            const int64_t rc = row < A.n ? row : A.n - 1;
+            const RT ri = r[rc];
+            const T xs = (MODE >= 2) ? (T)xg[rc] : (T)0;
+            const T so = (MODE == 3) ? sold[rc] : (T)0;
+            const double ds = SCALE ? dis[rc] : 1.0;
+            T a = op_row_fixed<DK, SP, T, XT, SCHUR, NT>(A, xg, w, row, s, lane);
+            if (row < A.n) {
+                T o = aA * a + ar * (T)ri;
+                if (MODE >= 2) o += ax * xs;
+                if (MODE == 3) o += aold * so;
+                OT ov = (OT)o;
+                if (SCALE) ov = (OT)((double)ov * ds);
+                out[row] = ov;
+                if (DOT) part += (double)ri * (double)ov;
+            }
+        });
     });
     return part;
 }
@@ -342,8 +482,7 @@ __device__ __forceinline__ double ph_init_resid(const SellView &A, const double 
 {
     double part = 0.0;
     for_my_slices(A.nslices, L, G, [&](int64_t row, int64_t s, int lane) {
-        int64_t base; int width; slice_span(A, s, base, width);
-        double a = sell_row<double, double, SCHUR>(A, xh, w, base, width, lane);
+        double a = op_row<double, double, SCHUR>(A, xh, w, row, s, lane);
         if (row < A.n) {
             const double ri = bh[row] - a;
             r[row] = ri;
@@ -359,15 +498,18 @@ __device__ __forceinline__ double ph_pq(const SellView &A, const double *__restr
                                         const double *__restrict__ w, double *__restrict__ q, int L, int G)
 {
     double part = 0.0;
-    for_my_slices(A.nslices, L, G, [&](int64_t row, int64_t s, int lane) {
-        int64_t base; int width; slice_span(A, s, base, width);
-        const int64_t rc = row < A.n ? row : A.n - 1;
-        const double pi = p[rc];
-        double a = sell_row<double, double, SCHUR, NT>(A, p, w, base, width, lane);
-        if (row < A.n) {
-            q[row] = a;
-            part += pi * a;
-        }
+    with_storage(A, [&](auto dk, auto sp) {
+        constexpr int DK = decltype(dk)::value;
+        constexpr bool SP = decltype(sp)::value;
+        for_my_slices(A.nslices, L, G, [&](int64_t row, int64_t s, int lane) {
+            const int64_t rc = row < A.n ? row : A.n - 1;
+            const double pi = p[rc];
+            double a = op_row_fixed<DK, SP, double, double, SCHUR, NT>(A, p, w, row, s, lane);
+            if (row < A.n) {
+                q[row] = a;
+                part += pi * a;
+            }
+        });
     });
     return part;
 }
@@ -437,8 +579,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmv(SellView A, const T *__restrict_
     const int G = (int)gridDim.x;
     const int L = xcd_remap((int)blockIdx.x, G);
     for_my_slices(A.nslices, L, G, [&](int64_t row, int64_t s, int lane) {
-        int64_t base; int width; slice_span(A, s, base, width);
-        T a = sell_row<T, T, SCHUR>(A, x, w, base, width, lane);
+        T a = op_row<T, T, SCHUR>(A, x, w, row, s, lane);
         if (row < A.n) y[row] = a;
     });
 }
@@ -645,8 +786,7 @@ __global__ __launch_bounds__(BLOCK) void k_lz_apply(SellView A, const double *__
     const double bp = (j > 0) ? st->lz_beta[j - 1] : 0.0;
     double part = 0.0;
     for_my_slices(A.nslices, L, G, [&](int64_t row, int64_t s, int lane) {
-        int64_t base; int width; slice_span(A, s, base, width);
-        double a = sell_row<double, double, SCHUR>(A, v, tw, base, width, lane);
+        double a = op_row<double, double, SCHUR>(A, v, tw, row, s, lane);
         if (row < A.n) {
             const double wi = a - bp * vprev[row];
             wout[row] = wi;
@@ -692,6 +832,20 @@ static __global__ __launch_bounds__(BLOCK) void k_lz_next(int64_t n, double *__r
 // setup kernels: diagonal, Jacobi scaling, slice layout
 // ---------------------------------------------------------------------------
 
+// Offsets covered by the diagonal part: an entry (i, j) is covered when
+// |j - i| is one of off[0..nd).
+struct DiaSet {
+    int nd = 0;
+    int64_t off[DMAX] = {};
+};
+
+__device__ __forceinline__ int dia_index(const DiaSet &D, int64_t a)
+{
+    for (int d = 0; d < D.nd; ++d)
+        if (D.off[d] == a) return d;
+    return -1;
+}
+
 // d_i = a_ii + sum over appended trace entries (c_ti^2 / m_t); flag non-positive.
 static __global__ __launch_bounds__(BLOCK) void k_diag(int64_t n, const int64_t *__restrict__ rp,
                                                 const int32_t *__restrict__ col,
@@ -721,8 +875,10 @@ static __global__ __launch_bounds__(BLOCK) void k_diag(int64_t n, const int64_t 
 }
 
 // width of each slice = max over its rows of (row length + appended trace entries)
+// (entries covered by the diagonal part D are not counted)
 static __global__ __launch_bounds__(BLOCK) void k_slice_width(int64_t n, int64_t nslices,
                                                        const int64_t *__restrict__ rp,
+                                                       const int32_t *__restrict__ col, DiaSet D,
                                                        const int64_t *__restrict__ ctp,
                                                        int64_t *__restrict__ width)
 {
@@ -732,7 +888,14 @@ static __global__ __launch_bounds__(BLOCK) void k_slice_width(int64_t n, int64_t
     const int64_t row = s * WAVE + lane;
     int64_t len = 0;
     if (row < n) {
-        len = rp[row + 1] - rp[row];
+        if (D.nd == 0) {
+            len = rp[row + 1] - rp[row];
+        } else {
+            for (int64_t p = rp[row]; p < rp[row + 1]; ++p) {
+                const int64_t o = (int64_t)col[p] - row;
+                if (dia_index(D, o < 0 ? -o : o) < 0) ++len;
+            }
+        }
         if (ctp) len += ctp[row + 1] - ctp[row];
     }
 #pragma unroll
@@ -779,7 +942,7 @@ static __global__ __launch_bounds__(1024) void k_scan_slices(int64_t nslices, co
 static __global__ __launch_bounds__(BLOCK) void k_slice_fill(int64_t n, int64_t nslices, int64_t nx,
                                                       const int64_t *__restrict__ rp,
                                                       const int32_t *__restrict__ col,
-                                                      const double *__restrict__ val,
+                                                      const double *__restrict__ val, DiaSet D,
                                                       const int64_t *__restrict__ ctp,
                                                       const int32_t *__restrict__ ctt,
                                                       const double *__restrict__ ctv,
@@ -799,13 +962,18 @@ static __global__ __launch_bounds__(BLOCK) void k_slice_fill(int64_t n, int64_t 
     const int32_t self = (int32_t)(row < n ? row : 0);
     if (row < n) {
         const double di = dis ? dis[row] : 1.0;
-        for (int64_t p = rp[row]; p < rp[row + 1]; ++p, ++j) {
+        for (int64_t p = rp[row]; p < rp[row + 1]; ++p) {
             const int32_t c = col[p];
+            if (D.nd > 0) {
+                const int64_t o = (int64_t)c - row;
+                if (dia_index(D, o < 0 ? -o : o) >= 0) continue;
+            }
             const double v = dis ? val[p] * di * dis[c] : val[p];
             const int64_t o = base + (int64_t)j * WAVE + lane;
             scol[o] = c;
             sval[o] = v;
             if (sval32) sval32[o] = (float)v;
+            ++j;
         }
         if (ctp) {
             for (int64_t p = ctp[row]; p < ctp[row + 1]; ++p, ++j) {
@@ -822,6 +990,145 @@ static __global__ __launch_bounds__(BLOCK) void k_slice_fill(int64_t n, int64_t 
         scol[o] = self;
         sval[o] = 0.0;
         if (sval32) sval32[o] = 0.0f;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// symmetric diagonal storage: setup
+// ---------------------------------------------------------------------------
+
+constexpr int OFF_SLOTS = 128;  // distinct column offsets tracked (power of two)
+constexpr unsigned long long OFF_EMPTY = 0x8000000000000000ull;
+
+// Count one occurrence of offset o in an open-addressing table; false when full.
+__device__ __forceinline__ bool off_insert(unsigned long long *key, unsigned long long *cnt, int64_t o,
+                                           unsigned long long add)
+{
+    const unsigned long long k = (unsigned long long)o;
+    unsigned h = (unsigned)((k * 0x9E3779B97F4A7C15ull) >> 57) & (OFF_SLOTS - 1);
+    for (int probe = 0; probe < OFF_SLOTS; ++probe, h = (h + 1) & (OFF_SLOTS - 1)) {
+        const unsigned long long cur = atomicCAS(&key[h], OFF_EMPTY, k);
+        if (cur == OFF_EMPTY || cur == k) {
+            atomicAdd(&cnt[h], add);
+            return true;
+        }
+    }
+    return false;
+}
+
+// Histogram of the column offsets col - row over the nonzero entries (at
+// most OFF_SLOTS distinct ones; *overflow is set when there are more).  A
+// table per workgroup in LDS, merged into the global table at the end.
+static __global__ __launch_bounds__(BLOCK) void k_offsets(int64_t n, const int64_t *__restrict__ rp,
+                                                          const int32_t *__restrict__ col,
+                                                          const double *__restrict__ val,
+                                                          unsigned long long *gkey, unsigned long long *gcnt,
+                                                          int *overflow)
+{
+    __shared__ unsigned long long key[OFF_SLOTS], cnt[OFF_SLOTS];
+    __shared__ int full;
+    for (int t = threadIdx.x; t < OFF_SLOTS; t += BLOCK) {
+        key[t] = OFF_EMPTY;
+        cnt[t] = 0;
+    }
+    if (threadIdx.x == 0) full = 0;
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) {
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p)
+            if (val[p] != 0.0 && !off_insert(key, cnt, (int64_t)col[p] - i, 1)) {
+                full = 1;
+                break;
+            }
+        if (full) break;
+    }
+    __syncthreads();
+    if (full) {
+        if (threadIdx.x == 0) atomicOr(overflow, 1);
+        return;
+    }
+    for (int t = threadIdx.x; t < OFF_SLOTS; t += BLOCK)
+        if (key[t] != OFF_EMPTY && !off_insert(gkey, gcnt, (int64_t)key[t], cnt[t])) atomicOr(overflow, 1);
+}
+
+// Raw values of the covered entries with offset >= 0 into dv[d][i] (dv zeroed
+// beforehand).  cnt[0] / cnt[1] count the nonzero covered entries above / below
+// the diagonal; a covered offset seen twice in one row (a duplicate entry)
+// sets bad |= 16.
+static __global__ __launch_bounds__(BLOCK) void k_dia_fill(int64_t n, const int64_t *__restrict__ rp,
+                                                           const int32_t *__restrict__ col,
+                                                           const double *__restrict__ val, DiaSet D,
+                                                           double *__restrict__ dv, int64_t ds,
+                                                           unsigned long long *cnt, int *bad)
+{
+    __shared__ unsigned long long c[2];
+    if (threadIdx.x < 2) c[threadIdx.x] = 0;
+    __syncthreads();
+    unsigned long long cu = 0, cl = 0;
+    int b = 0;
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i < n) {
+        uint32_t seen_u = 0, seen_l = 0;
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+            const int64_t o = (int64_t)col[p] - i;
+            const int d = dia_index(D, o < 0 ? -o : o);
+            if (d < 0) continue;
+            const double v = val[p];
+            if (o >= 0) {
+                if ((seen_u >> d) & 1u) b |= 16;
+                seen_u |= 1u << d;
+                dv[(int64_t)d * ds + i] = v;
+                if (o > 0 && v != 0.0) ++cu;
+            } else {
+                if ((seen_l >> d) & 1u) b |= 16;
+                seen_l |= 1u << d;
+                if (v != 0.0) ++cl;
+            }
+        }
+    }
+    if (b) atomicOr(bad, b);
+    if (cu) atomicAdd(&c[0], cu);
+    if (cl) atomicAdd(&c[1], cl);
+    __syncthreads();
+    if (threadIdx.x < 2 && c[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], c[threadIdx.x]);
+}
+
+// Every covered entry below the diagonal must equal the stored value of its
+// mirror: a_{i, i-o} == a_{i-o, i} (else bad |= 32).  With no duplicates and
+// equal counts of nonzero entries above and below, the covered part is then
+// exactly symmetric and the mirrored reads reproduce it.
+static __global__ __launch_bounds__(BLOCK) void k_dia_check(int64_t n, const int64_t *__restrict__ rp,
+                                                            const int32_t *__restrict__ col,
+                                                            const double *__restrict__ val, DiaSet D,
+                                                            const double *__restrict__ dv, int64_t ds,
+                                                            int *bad)
+{
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= n) return;
+    for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+        const int64_t j = col[p];
+        if (j >= i) continue;
+        const int d = dia_index(D, i - j);
+        if (d >= 0 && !(dv[(int64_t)d * ds + j] == val[p])) {
+            atomicOr(bad, 32);
+            return;
+        }
+    }
+}
+
+// Scale the stored diagonals to the Jacobi-scaled operator:
+// dv[d][i] = (a_{i,i+o} dis_i) dis_{i+o}, and write the FP32 copy.
+static __global__ __launch_bounds__(BLOCK) void k_dia_scale(int64_t n, DiaSet D, const double *__restrict__ dis,
+                                                            double *__restrict__ dv, float *__restrict__ dv32,
+                                                            int64_t ds)
+{
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= n) return;
+    for (int d = 0; d < D.nd; ++d) {
+        const int64_t j = i + D.off[d];
+        double v = dv[(int64_t)d * ds + i];
+        if (dis) v = j < n ? v * dis[i] * dis[j] : 0.0;
+        dv[(int64_t)d * ds + i] = v;
+        if (dv32) dv32[(int64_t)d * ds + i] = (float)v;
     }
 }
 

@@ -108,11 +108,23 @@ static __global__ __launch_bounds__(BLOCK) void k_feat_rows(ppk::SellView A, con
            mx_len = 0, mn_len = INFINITY;
     ppk::for_my_slices(A.nslices, L, G, [&](int64_t row, int64_t s, int lane) {
         if (row >= A.n) return;
-        int64_t base;
-        int width;
-        ppk::slice_span(A, s, base, width);
-        const double *v = (const double *)A.val;
         double aii = 0, offa = 0, tr = 0, len = 0;
+        if (A.nd > 0) {  // symmetric diagonal part: a_{i,i+o} at [d][i], a_{i,i-o} at [d][i-o]
+            const double *dv = (const double *)A.dv;
+            aii = dv[row];
+            if (aii != 0.0) len += 1;
+            for (int d = 1; d < A.nd; ++d) {
+                const int64_t o = A.doff[d];
+                const double u = dv[(int64_t)d * A.dstride + row];
+                const double l = row >= o ? dv[(int64_t)d * A.dstride + row - o] : 0.0;
+                offa += fabs(u) + fabs(l);
+                len += (u != 0.0) + (l != 0.0);
+            }
+        }
+        int64_t base = 0;
+        int width = 0;
+        if (A.sell) ppk::slice_span(A, s, base, width);
+        const double *v = (const double *)A.val;
         for (int j = 0; j < width; ++j) {
             const int64_t o = base + (int64_t)j * WAVE + lane;
             const int c = A.col[o];

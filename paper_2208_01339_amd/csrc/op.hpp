@@ -22,6 +22,13 @@ struct pp_op_s {
     int32_t *scol = nullptr;
     double *sval = nullptr;
     float *sval32 = nullptr;
+    int sell = 1;  // slice part non-empty
+    // symmetric diagonal part: nd diagonals of dstride values each
+    int nd = 0;
+    int64_t doff[ppk::DMAX] = {};
+    int64_t dstride = 0;
+    double *dval = nullptr;
+    float *dval32 = nullptr;
     // trace operator M^{-1} C-hat (Schur)
     int64_t *crp = nullptr;
     int32_t *ccol = nullptr;
@@ -82,6 +89,11 @@ struct pp_op_s {
         v.n = n;
         v.nslices = nslices;
         v.nx = n;
+        v.sell = sell;
+        v.nd = nd;
+        v.dv = f32 ? (const void *)dval32 : (const void *)dval;
+        v.dstride = dstride;
+        for (int d = 0; d < ppk::DMAX; ++d) v.doff[d] = doff[d];
         return v;
     }
     ppk::CsrView cview(bool f32) const
@@ -97,6 +109,7 @@ struct pp_op_s {
     void release()
     {
         ppc::dfree(sp); ppc::dfree(scol); ppc::dfree(sval); ppc::dfree(sval32);
+        ppc::dfree(dval); ppc::dfree(dval32);
         ppc::dfree(crp); ppc::dfree(ccol); ppc::dfree(cm); ppc::dfree(cm32); ppc::dfree(tw); ppc::dfree(tw32);
         ppc::dfree(dis);
         ppc::dfree(xh); ppc::dfree(r); ppc::dfree(p); ppc::dfree(q); ppc::dfree(z); ppc::dfree(bh); ppc::dfree(sA); ppc::dfree(sB);

@@ -99,6 +99,100 @@ int check_csr_dev(pp_op_s *op, int64_t rows, int64_t ncols, int64_t nnz, const i
     return h;
 }
 
+// Symmetric diagonal part of the operator (see SellView): pick the column
+// offsets worth a stored diagonal, fill them, verify that the covered
+// entries are exactly symmetric, then scale.  A stored diagonal costs 8 n
+// bytes and is read once per application; the slice layout costs 12 bytes per
+// entry, so an offset pair is kept when it covers more than 2n/3 nonzero
+// entries (explicit zeros are counted nowhere; the fill stores them as the
+// zeros they are).
+// Returns the covered set; nd = 0 when the matrix does not qualify (more than
+// OFF_SLOTS distinct offsets, no dense diagonal, duplicate entries or
+// asymmetric values): every entry then stays in the slice part.
+ppk::DiaSet build_diagonals(pp_op_s *op, const int64_t *rp, const int32_t *col, const double *val)
+{
+    using ppk::OFF_SLOTS;
+    typedef unsigned long long u64;
+    ppk::DiaSet D;
+    const int64_t n = op->n;
+    struct Tmp {
+        u64 *key = nullptr, *cnt = nullptr;
+        int *flag = nullptr;
+        ~Tmp() { dfree(key); dfree(cnt); dfree(flag); }
+    } t;
+    t.key = dalloc<u64>(OFF_SLOTS);
+    t.cnt = dalloc<u64>(OFF_SLOTS);
+    t.flag = dalloc<int>(1);
+    std::vector<u64> hk(OFF_SLOTS, ppk::OFF_EMPTY), hc(OFF_SLOTS, 0);
+    HIPCHK(hipMemcpyAsync(t.key, hk.data(), sizeof(u64) * OFF_SLOTS, hipMemcpyHostToDevice, op->stream));
+    HIPCHK(hipMemsetAsync(t.cnt, 0, sizeof(u64) * OFF_SLOTS, op->stream));
+    HIPCHK(hipMemsetAsync(t.flag, 0, sizeof(int), op->stream));
+    const unsigned g = (unsigned)std::min<int64_t>(2048, (n + BLOCK - 1) / BLOCK);
+    hipLaunchKernelGGL(ppk::k_offsets, dim3(g), dim3(BLOCK), 0, op->stream, n, rp, col, val, t.key, t.cnt,
+                       t.flag);
+    HIPCHK(hipGetLastError());
+    int flag = 0;
+    HIPCHK(hipMemcpyAsync(hk.data(), t.key, sizeof(u64) * OFF_SLOTS, hipMemcpyDeviceToHost, op->stream));
+    HIPCHK(hipMemcpyAsync(hc.data(), t.cnt, sizeof(u64) * OFF_SLOTS, hipMemcpyDeviceToHost, op->stream));
+    HIPCHK(hipMemcpyAsync(&flag, t.flag, sizeof(int), hipMemcpyDeviceToHost, op->stream));
+    HIPCHK(hipStreamSynchronize(op->stream));
+    if (flag) return D;
+    std::vector<std::pair<int64_t, u64>> count;  // (offset, entries)
+    for (int q = 0; q < OFF_SLOTS; ++q)
+        if (hk[q] != ppk::OFF_EMPTY) count.push_back({(int64_t)hk[q], hc[q]});
+    auto entries = [&](int64_t o) -> u64 {
+        for (auto &c : count)
+            if (c.first == o) return c.second;
+        return 0;
+    };
+    if (3 * entries(0) <= 2 * (u64)n) return D;
+    std::vector<std::pair<u64, int64_t>> cand;  // (entries covered, offset > 0)
+    for (auto &c : count) {
+        if (c.first <= 0 || entries(-c.first) != c.second) continue;  // unpaired: not symmetric
+        const u64 cov = 2 * c.second;
+        if (3 * cov > 2 * (u64)n) cand.push_back({cov, c.first});
+    }
+    std::sort(cand.begin(), cand.end(), [](const std::pair<u64, int64_t> &a, const std::pair<u64, int64_t> &b) {
+        return a.first != b.first ? a.first > b.first : a.second < b.second;
+    });
+    if ((int)cand.size() > ppk::DMAX - 1) cand.resize(ppk::DMAX - 1);
+    std::vector<int64_t> offs{0};
+    for (auto &c : cand) offs.push_back(c.second);
+    std::sort(offs.begin(), offs.end());
+    D.nd = (int)offs.size();
+    for (int d = 0; d < D.nd; ++d) D.off[d] = offs[d];
+
+    const int64_t ds = op->nslices * WAVE;
+    op->dval = dalloc<double>((size_t)D.nd * ds);
+    HIPCHK(hipMemsetAsync(op->dval, 0, sizeof(double) * D.nd * ds, op->stream));
+    HIPCHK(hipMemsetAsync(t.cnt, 0, 2 * sizeof(u64), op->stream));
+    HIPCHK(hipMemsetAsync(t.flag, 0, sizeof(int), op->stream));
+    const unsigned gr = (unsigned)((n + BLOCK - 1) / BLOCK);
+    hipLaunchKernelGGL(ppk::k_dia_fill, dim3(gr), dim3(BLOCK), 0, op->stream, n, rp, col, val, D, op->dval, ds,
+                       t.cnt, t.flag);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(ppk::k_dia_check, dim3(gr), dim3(BLOCK), 0, op->stream, n, rp, col, val, D,
+                       (const double *)op->dval, ds, t.flag);
+    HIPCHK(hipGetLastError());
+    u64 ul[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(ul, t.cnt, 2 * sizeof(u64), hipMemcpyDeviceToHost, op->stream));
+    HIPCHK(hipMemcpyAsync(&flag, t.flag, sizeof(int), hipMemcpyDeviceToHost, op->stream));
+    HIPCHK(hipStreamSynchronize(op->stream));
+    if (flag || ul[0] != ul[1]) {
+        dfree(op->dval);
+        return ppk::DiaSet{};
+    }
+    if (op->mixed()) op->dval32 = dalloc<float>((size_t)D.nd * ds);
+    if (op->dval32) HIPCHK(hipMemsetAsync(op->dval32, 0, sizeof(float) * D.nd * ds, op->stream));
+    hipLaunchKernelGGL(ppk::k_dia_scale, dim3(gr), dim3(BLOCK), 0, op->stream, n, D, (const double *)op->dis,
+                       op->dval, op->dval32, ds);
+    HIPCHK(hipGetLastError());
+    op->nd = D.nd;
+    op->dstride = ds;
+    for (int d = 0; d < ppk::DMAX; ++d) op->doff[d] = D.off[d];
+    return D;
+}
+
 pp_status build_operator(pp_op_s *op, const int64_t *rp, const int32_t *col, const double *val,
                          const int64_t *c_rowptr, const int32_t *c_col, const double *c_val,
                          const double *m_diag)
@@ -140,12 +234,15 @@ pp_status build_operator(pp_op_s *op, const int64_t *rp, const int32_t *col, con
             HIPCHK(hipStreamSynchronize(op->stream));
             if (h) { cleanup(); return fail(PP_ERR_ARG, "Jacobi scaling needs a positive finite diagonal"); }
         }
-        // slice widths and offsets
         op->nslices = (n + WAVE - 1) / WAVE;
+        // symmetric diagonal part (unless the caller asked for the slice layout only)
+        ppk::DiaSet D;
+        if (!(op->flags & PP_SLICED)) D = build_diagonals(op, rp, col, val);
+        // slice part: the entries the diagonal part does not cover, plus trace columns
         width = dalloc<int64_t>(op->nslices);
         op->sp = dalloc<int64_t>(op->nslices + 1);
         const unsigned gs = (unsigned)((op->nslices + WPB - 1) / WPB);
-        hipLaunchKernelGGL(ppk::k_slice_width, dim3(gs), dim3(BLOCK), 0, op->stream, n, op->nslices, rp,
+        hipLaunchKernelGGL(ppk::k_slice_width, dim3(gs), dim3(BLOCK), 0, op->stream, n, op->nslices, rp, col, D,
                            (const int64_t *)ctp, width);
         HIPCHK(hipGetLastError());
         hipLaunchKernelGGL(ppk::k_scan_slices, dim3(1), dim3(1024), 0, op->stream, op->nslices,
@@ -153,11 +250,12 @@ pp_status build_operator(pp_op_s *op, const int64_t *rp, const int32_t *col, con
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(&op->nstored, op->sp + op->nslices, sizeof(int64_t), hipMemcpyDeviceToHost, op->stream));
         HIPCHK(hipStreamSynchronize(op->stream));
+        op->sell = op->nstored > 0 ? 1 : 0;
         op->scol = dalloc<int32_t>(op->nstored);
         op->sval = dalloc<double>(op->nstored);
         if (op->mixed()) op->sval32 = dalloc<float>(op->nstored);
         hipLaunchKernelGGL(ppk::k_slice_fill, dim3(gs), dim3(BLOCK), 0, op->stream, n, op->nslices, n, rp,
-                           col, val, (const int64_t *)ctp, (const int32_t *)ctt, (const double *)ctv,
+                           col, val, D, (const int64_t *)ctp, (const int32_t *)ctt, (const double *)ctv,
                            (const double *)op->dis, (const int64_t *)op->sp, op->scol, op->sval,
                            op->sval32);
         HIPCHK(hipGetLastError());
@@ -210,6 +308,7 @@ pp_status build_operator(pp_op_s *op, const int64_t *rp, const int32_t *col, con
     cleanup();
     op->stats.n = n;
     op->stats.nnz_stored = op->nstored;
+    op->stats.diagonals = op->nd;
     op->stats.nnz_matrix = op->nnz_given + op->nnz_c;
     return PP_OK;
 }
@@ -223,7 +322,7 @@ pp_status create_common(pp_op *out, int kind, int64_t n, int64_t nnz, const int6
     *out = nullptr;
     if (n <= 0 || nnz <= 0 || !rp || !col || !val) return fail(PP_ERR_ARG, "n, nnz must be positive and arrays non-NULL");
     if (n > (int64_t)INT32_MAX - 1) return fail(PP_ERR_ARG, "n must be below 2^31 (int32 column indices)");
-    if (flags & ~(unsigned)(PP_JACOBI | PP_MIXED)) return fail(PP_ERR_ARG, "unknown flags");
+    if (flags & ~(unsigned)(PP_JACOBI | PP_MIXED | PP_SLICED)) return fail(PP_ERR_ARG, "unknown flags");
     if (kind == 1) {
         if (nt <= 0 || nnz_c <= 0 || !c_rowptr || !c_col || !c_val || !m_diag)
             return fail(PP_ERR_ARG, "Schur: nt, nnz_c must be positive and arrays non-NULL");

@@ -26,11 +26,27 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 DIGEST_FILES = ("csrc/kernels.hpp", "csrc/op.hpp", "csrc/common.hpp", "csrc/pp_lib.hip", "build.py")
 
 
-def source_digest() -> str:
+def _code_only(text: str) -> str:
+    """Source text without // comments and blank lines (comment edits keep the digest)."""
+    out = []
+    for line in text.splitlines():
+        if not line.lstrip().startswith("#"):  # keep preprocessor lines and Python comments whole
+            line = re.sub(r"//.*$", "", line)
+        line = line.rstrip()
+        if line:
+            out.append(line)
+    return "\n".join(out)
+
+
+def source_digest(root: str = HERE) -> str:
+    """Digest of the code (not the comments) of the fused-step kernel sources."""
     h = hashlib.sha256()
     for rel in DIGEST_FILES:
-        with open(os.path.join(HERE, rel), "rb") as f:
-            h.update(rel.encode() + b"\0" + f.read())
+        with open(os.path.join(root, rel), encoding="utf-8") as f:
+            text = f.read()
+        if not rel.endswith(".py"):
+            text = _code_only(text)
+        h.update(rel.encode() + b"\0" + text.encode())
     return h.hexdigest()[:16]
 
 

@@ -58,8 +58,13 @@ def _cases():
     }
 
 
-def make_op(B, a, s, flags):
-    return B.Operator(a=a, schur=s, flags=flags)
+LAYOUTS = ["diag", "sliced"]
+
+
+def make_op(B, a, s, flags, layout="diag"):
+    """layout "diag": the library's default (symmetric stored diagonals where they pay);
+    "sliced": every entry in the sliced ELLPACK layout (PP_SLICED)."""
+    return B.Operator(a=a, schur=s, flags=flags | (B.PP_SLICED if layout == "sliced" else 0))
 
 
 def make_oracle(a, s, jacobi):
@@ -72,11 +77,12 @@ def make_oracle(a, s, jacobi):
 # operator application
 # ---------------------------------------------------------------------------
 
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("case", list(_cases()))
 @pytest.mark.parametrize("flags", [0, 1])
-def test_operator_apply(B, case, flags):
+def test_operator_apply(B, case, flags, layout):
     a, s = _cases()[case]()
-    op = make_op(B, a, s, flags)
+    op = make_op(B, a, s, flags, layout)
     orc = make_oracle(a, s, False)
     x = W.rhs_uniform(orc.n, 42)
     y = torch.empty(orc.n, dtype=torch.float64, device="cuda")
@@ -92,6 +98,8 @@ def test_operator_apply(B, case, flags):
     assert np.all(np.abs(got - ref) <= tol), np.max(np.abs(got - ref) / tol)
     st = B.pp_get_stats(op.handle)
     assert st["n"] == orc.n
+    # 7-point stencils keep 4 stored diagonals (0, 1, N, N^2), the fracture blocks 3 (0, 1, G)
+    assert st["diagonals"] == (0 if layout == "sliced" else (3 if s is not None else 4))
     op.close()
 
 
@@ -99,14 +107,15 @@ def test_operator_apply(B, case, flags):
 # p_k(A) r (Algorithm 2)
 # ---------------------------------------------------------------------------
 
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("case", list(_cases()))
 @pytest.mark.parametrize("jacobi", [False, True])
 @pytest.mark.parametrize("k,xi", [(0, 0.0), (1, 0.0), (2, 1e-3), (3, 0.0), (10, 1e-3), (40, 0.0)])
-def test_pp_apply(B, case, jacobi, k, xi):
+def test_pp_apply(B, case, jacobi, k, xi, layout):
     a, s = _cases()[case]()
     orc = make_oracle(a, s, jacobi)
     lmin, lmax = O.lanczos_bounds(orc, 20)
-    op = make_op(B, a, s, B.PP_JACOBI if jacobi else 0)
+    op = make_op(B, a, s, B.PP_JACOBI if jacobi else 0, layout)
     B.pp_setup(op.handle, k, lmin, lmax, xi)
     r = W.rhs_uniform(orc.n, 7)
     z = torch.empty(orc.n, dtype=torch.float64, device="cuda")
@@ -150,9 +159,10 @@ PCG_CASES = [
 ]
 
 
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("driver", [0, 1], ids=["stream", "persistent"])
 @pytest.mark.parametrize("name,builder,jacobi,k,xi", PCG_CASES, ids=[c[0] for c in PCG_CASES])
-def test_pcg_parity(B, name, builder, jacobi, k, xi, driver):
+def test_pcg_parity(B, name, builder, jacobi, k, xi, driver, layout):
     a, s = builder()
     orc = make_oracle(a, s, jacobi)
     n = orc.n
@@ -160,7 +170,7 @@ def test_pcg_parity(B, name, builder, jacobi, k, xi, driver):
     lmin, lmax = O.lanczos_bounds(orc, 20)
     xo, sto = O.pcg(orc, k, lmin, lmax, xi, b, tol=1e-8, maxit=5000)
     assert sto["status"] == O.OK
-    op = make_op(B, a, s, B.PP_JACOBI if jacobi else 0)
+    op = make_op(B, a, s, B.PP_JACOBI if jacobi else 0, layout)
     B.pp_set_option(op.handle, B.PP_OPT_DRIVER, driver)
     B.pp_setup(op.handle, k, lmin, lmax, xi)
     bd = dev(b)
@@ -265,13 +275,14 @@ def test_create_rejects_bad_input(B):
 # Lanczos bounds
 # ---------------------------------------------------------------------------
 
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("case", list(_cases()))
 @pytest.mark.parametrize("jacobi", [False, True])
-def test_lanczos_bounds(B, case, jacobi):
+def test_lanczos_bounds(B, case, jacobi, layout):
     a, s = _cases()[case]()
     orc = make_oracle(a, s, jacobi)
     lo_r, hi_r = O.lanczos_bounds(orc, 20)
-    op = make_op(B, a, s, B.PP_JACOBI if jacobi else 0)
+    op = make_op(B, a, s, B.PP_JACOBI if jacobi else 0, layout)
     lo, hi = B.pp_estimate_bounds(op.handle, 20)
     # Ritz values are eigenvalues of T_20; two T_20 built with different
     # rounding orders differ by O(eps ||A||) amplified by the loss of
@@ -307,16 +318,17 @@ def test_config0_end_to_end(B):
 # mixed precision (FP32 polynomial, FP64 CG)
 # ---------------------------------------------------------------------------
 
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("driver", [0, 1], ids=["stream", "persistent"])
 @pytest.mark.parametrize("name,builder,jacobi,k,xi", PCG_CASES[:4] + PCG_CASES[5:], ids=[c[0] for c in PCG_CASES[:4] + PCG_CASES[5:]])
-def test_mixed_pcg_residual(B, name, builder, jacobi, k, xi, driver):
+def test_mixed_pcg_residual(B, name, builder, jacobi, k, xi, driver, layout):
     a, s = builder()
     orc = make_oracle(a, s, jacobi)
     n = orc.n
     b = W.rhs_uniform(n, 1)
     lmin, lmax = O.lanczos_bounds(orc, 20)
     xo, sto = O.pcg(orc, k, lmin, lmax, xi, b, tol=1e-8, maxit=5000)
-    op = make_op(B, a, s, (B.PP_JACOBI if jacobi else 0) | B.PP_MIXED)
+    op = make_op(B, a, s, (B.PP_JACOBI if jacobi else 0) | B.PP_MIXED, layout)
     B.pp_set_option(op.handle, B.PP_OPT_DRIVER, driver)
     B.pp_setup(op.handle, k, lmin, lmax, xi)
     x = torch.zeros(n, dtype=torch.float64, device="cuda")
