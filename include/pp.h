@@ -210,7 +210,9 @@ typedef struct pp_batch_s *pp_batch;
  * rejected (PP_ERR_ARG).  rowptr [n+1] int64, colind [nnz] int32 (global
  * column numbers), val [nnz] double, n = sys_ptr[nsys] (device arrays).
  * nrhs in [1, 32]: width of the right-hand-side blocks (row-major [n][nrhs]).
- * flags: PP_JACOBI, PP_MIXED (FP32 polynomial / SpMM, FP64 CG).
+ * flags: PP_JACOBI, PP_MIXED (FP32 polynomial / SpMM, FP64 CG), PP_SLICED.
+ * Each system chooses its storage as pp_create_csr does (symmetric stored
+ * diagonals for 5- and 7-point-like systems, the sliced layout otherwise).
  */
 PP_API pp_status pp_create_batch(pp_batch *out, int nsys, const int64_t *sys_ptr, int64_t nnz,
                                  const int64_t *rowptr, const int32_t *colind, const double *val,
@@ -252,8 +254,9 @@ PP_API pp_status pp_batch_autotune(pp_batch op, int *best_w, double *best_us);
 enum { PP_BOPT_GRAPH = 100 };
 PP_API pp_status pp_batch_set_option(pp_batch op, int key, int64_t value);
 
-/* Sizes and last-solve timing: n rows, internal block width, stored matrix
- * entries, workgroups per launch, solve device time (ms), polynomial steps. */
+/* Sizes and last-solve timing: n rows, internal block width, entries in the
+ * slice layout, workgroups per launch, solve device time (ms), the most
+ * iterations of any (system, column), systems held as stored diagonals. */
 typedef struct {
     int64_t n;
     int32_t nsys;
@@ -265,7 +268,7 @@ typedef struct {
     int32_t graph;
     double solve_ms;
     int32_t max_iters;
-    int32_t pad;
+    int32_t diag_systems;
 } pp_batch_stats;
 PP_API pp_status pp_batch_get_stats(pp_batch op, pp_batch_stats *st);
 

@@ -51,7 +51,7 @@ class pp_batch_stats(C.Structure):
     _fields_ = [
         ("n", C.c_int64), ("nsys", C.c_int32), ("nb", C.c_int32), ("nrhs", C.c_int32), ("w", C.c_int32),
         ("nnz_stored", C.c_int64), ("grid", C.c_int32), ("graph", C.c_int32), ("solve_ms", C.c_double),
-        ("max_iters", C.c_int32), ("pad", C.c_int32),
+        ("max_iters", C.c_int32), ("diag_systems", C.c_int32),
     ]
 
 

@@ -12,7 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = [os.path.join(HERE, "csrc", f) for f in ("pp_lib.hip", "pp_batch.hip", "pp_mlp.hip")]
 DEPS = SRC + [os.path.join(HERE, "csrc", f) for f in (
-    "kernels.hpp", "sym_eig.hpp", "persistent.hpp", "batch.hpp", "common.hpp", "op.hpp", "mlp.hpp")] + [
+    "kernels.hpp", "sym_eig.hpp", "persistent.hpp", "batch.hpp", "common.hpp", "op.hpp", "mlp.hpp",
+    "dia_plan.hpp")] + [
     os.path.join(ROOT, "include", "pp.h")]
 OUT = os.path.join(HERE, "libppcg.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -31,8 +32,23 @@ FLAGS = [
 
 
 def build(verbose: bool = True) -> str:
+    """Compile the translation units in parallel (one hipcc each), then link."""
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    compile_flags = [f for f in FLAGS if f != "-shared"]
+    procs, objs = [], []
+    for src in SRC:
+        obj = os.path.join(objdir, os.path.basename(src) + ".o")
+        objs.append(obj)
+        cmd = [HIPCC, *compile_flags, "-c", "-o", obj, src]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((subprocess.Popen(cmd), cmd))
+    failed = [cmd for p, cmd in procs if p.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, failed[0])
     tmp = OUT + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-o", tmp, *SRC]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

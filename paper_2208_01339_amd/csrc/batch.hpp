@@ -40,6 +40,15 @@ struct Batch {
     int32_t NB;               // internal block width
     int32_t nrhs;             // caller's block width
     int32_t k;                // polynomial degree
+    // symmetric stored diagonals per system (see ppk::SellView): system s has
+    // seg_nd[s] of them (0: all its entries in the slice layout) with offsets
+    // seg_off[s * DMAX + d], values dv[d * dstride + internal row]
+    const int32_t *seg_nd;    // [S]
+    const int32_t *seg_sell;  // [S] 1 when system s also has entries in the slice layout
+    const int64_t *seg_off;   // [S * DMAX]
+    const double *dv64;
+    const float *dv32;
+    int64_t dstride;
 };
 
 // Per-(segment, column) CG state, arrays of S * NB (index s * NB + c).
@@ -240,8 +249,10 @@ __device__ __forceinline__ void spmm_row(const ppk::SellView &A, const T *__rest
     }
 }
 
-// Iterate the rows of this workgroup: fn(row, rin (row within slice), base, width).
-template <int W, typename F>
+// Iterate the rows of this workgroup: fn(row, rin (row within slice), base,
+// width); base and width (the slice's entries in the slice layout) are read
+// only when SP.
+template <int W, bool SP = true, typename F>
 __device__ __forceinline__ void for_rows(const ppk::SellView &A, const BlockRange &br, F fn)
 {
     constexpr int R = WAVE / W;  // rows per pass of a wave
@@ -249,12 +260,109 @@ __device__ __forceinline__ void for_rows(const ppk::SellView &A, const BlockRang
     const int lane = threadIdx.x & (WAVE - 1);
     const int g = lane / W;
     for (int64_t s = br.s0 + w; s < br.s1; s += WPB) {
-        const int64_t base = A.sp[s];
-        const int width = (int)((A.sp[s + 1] - base) >> 6);
+        int64_t base = 0;
+        int width = 0;
+        if constexpr (SP) {
+            base = A.sp[s];
+            width = (int)((A.sp[s + 1] - base) >> 6);
+        }
         for (int r0 = 0; r0 < WAVE; r0 += R) {
             const int rin = r0 + g;
             fn(s * WAVE + rin, rin, base, width);
         }
+    }
+}
+
+// The stored diagonals of one system, read once per workgroup.
+template <int DK>
+struct SegDia {
+    int64_t row0, row_end;  // internal rows of the system: [row0, row_end) are real
+    int64_t off[DK + 1];
+};
+
+template <int DK>
+__device__ __forceinline__ SegDia<DK> seg_dia(const Batch &bt, int seg)
+{
+    SegDia<DK> g;
+    g.row0 = bt.seg_row0[seg];
+    g.row_end = g.row0 + bt.seg_n[seg];
+#pragma unroll
+    for (int d = 0; d <= DK; ++d) g.off[d] = bt.seg_off[(int64_t)seg * ppk::DMAX + d];
+    return g;
+}
+
+template <typename T>
+__device__ __forceinline__ const T *dv_of(const Batch &bt)
+{
+    if constexpr (sizeof(T) == 8) return (const T *)bt.dv64;
+    else return (const T *)bt.dv32;
+}
+
+// Y = A X for one row over the system's stored diagonals (W lanes per row, CPL
+// columns per lane): the diagonal, then DK offset pairs, every load issued
+// before the first product.  Neighbours outside the system's real rows have a
+// zero value; their indices are redirected to the row itself.
+template <typename T, int CPL, int DK>
+__device__ __forceinline__ void spmm_dia(const T *__restrict__ dv, int64_t ds, const SegDia<DK> &g,
+                                         const T *__restrict__ X, int NB, int64_t row, int c0, T (&acc)[CPL])
+{
+    const Vec<T, CPL> x0 = ldv<T, CPL>(X + row * NB + c0);
+    const T v0 = dv[row];
+    T vu[DK], vl[DK];
+    Vec<T, CPL> xu[DK], xl[DK];
+#pragma unroll
+    for (int u = 0; u < DK; ++u) {
+        const int64_t o = g.off[u + 1];
+        const int64_t iu = row + o < g.row_end ? row + o : row;
+        const bool lok = row - o >= g.row0;
+        const int64_t il = lok ? row - o : row;
+        vu[u] = dv[(int64_t)(u + 1) * ds + row];
+        const T l = dv[(int64_t)(u + 1) * ds + il];
+        vl[u] = lok ? l : (T)0;
+        xu[u] = ldv<T, CPL>(X + iu * NB + c0);
+        xl[u] = ldv<T, CPL>(X + il * NB + c0);
+    }
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+        T a = v0 * x0.v[q];
+#pragma unroll
+        for (int u = 0; u < DK; ++u) a += vl[u] * xl[u].v[q] + vu[u] * xu[u].v[q];
+        acc[q] = a;
+    }
+}
+
+// Call f(integral_constant<int, DK>, bool_constant<SP>) with the storage of
+// system seg: DK stored off-diagonal offsets (0: slice layout only), SP: the
+// system has entries in the slice layout.
+template <typename F>
+__device__ __forceinline__ void with_seg_storage(const Batch &bt, int seg, F f)
+{
+    using std::integral_constant;
+    const int nd = bt.seg_nd[seg];
+    const bool sp = bt.seg_sell[seg] != 0;
+    if (nd == 4 && !sp) f(integral_constant<int, 3>{}, std::false_type{});
+    else if (nd == 4) f(integral_constant<int, 3>{}, std::true_type{});
+    else if (nd == 3 && !sp) f(integral_constant<int, 2>{}, std::false_type{});
+    else if (nd == 3) f(integral_constant<int, 2>{}, std::true_type{});
+    else f(integral_constant<int, 0>{}, std::true_type{});
+}
+
+// Y = A X for one row in the system's storage.
+template <typename T, int W, int CPL, int DK, bool SP, bool NT>
+__device__ __forceinline__ void spmm_any(const ppk::SellView &A, const Batch &bt, const SegDia<DK> &g,
+                                         const T *__restrict__ X, int NB, int64_t row, int64_t base, int width,
+                                         int rin, int c0, T (&acc)[CPL])
+{
+    if constexpr (DK > 0) {
+        spmm_dia<T, CPL, DK>(dv_of<T>(bt), bt.dstride, g, X, NB, row, c0, acc);
+        if constexpr (SP) {
+            T more[CPL];
+            spmm_row<T, W, CPL, NT>(A, X, NB, base, width, rin, c0, more);
+#pragma unroll
+            for (int q = 0; q < CPL; ++q) acc[q] += more[q];
+        }
+    } else {
+        spmm_row<T, W, CPL, NT>(A, X, NB, base, width, rin, c0, acc);
     }
 }
 
@@ -282,7 +390,7 @@ __global__ __launch_bounds__(BLOCK) void kb_init_scale(Batch bt, BState st, ppk:
     PPB_PROLOGUE()
     double part[CPL] = {};
     const int64_t ext0 = bt.ext_row0[br.seg], row0 = bt.seg_row0[br.seg];
-    for_rows<W>(A, br, [&](int64_t row, int rin, int64_t base, int width) {
+    for_rows<W, false>(A, br, [&](int64_t row, int rin, int64_t base, int width) {
         const bool real = row < br.row_end;
         const int64_t er = ext0 + (row - row0);
         const double d = real && dis ? dis[row] : 1.0;
@@ -311,23 +419,28 @@ __global__ __launch_bounds__(BLOCK) void kb_apply64(Batch bt, BState st, ppk::Se
     __shared__ double lds[BLOCK + NB_MAX * 2 + NB * WPB];
     PPB_PROLOGUE()
     double part[CPL] = {};
-    for_rows<W>(A, br, [&](int64_t row, int rin, int64_t base, int width) {
-        double acc[CPL];
-        spmm_row<double, W, CPL, NT>(A, X, NB, base, width, rin, c0, acc);
-        if (row < br.row_end) {
+    with_seg_storage(bt, br.seg, [&](auto dk, auto spc) {
+        constexpr int DK = decltype(dk)::value;
+        constexpr bool SP = decltype(spc)::value;
+        const SegDia<DK> g = seg_dia<DK>(bt, br.seg);
+        for_rows<W, SP>(A, br, [&](int64_t row, int rin, int64_t base, int width) {
+            double acc[CPL];
+            spmm_any<double, W, CPL, DK, SP, NT>(A, bt, g, X, NB, row, base, width, rin, c0, acc);
+            if (row < br.row_end) {
 #pragma unroll
-            for (int q = 0; q < CPL; ++q) {
-                const int64_t o = row * NB + c0 + q;
-                if (WHICH == 0) {
-                    const double ri = Bh[o] - acc[q];
-                    Y[o] = ri;
-                    part[q] += ri * ri;
-                } else {
-                    Y[o] = acc[q];
-                    part[q] += X[o] * acc[q];
+                for (int q = 0; q < CPL; ++q) {
+                    const int64_t o = row * NB + c0 + q;
+                    if (WHICH == 0) {
+                        const double ri = Bh[o] - acc[q];
+                        Y[o] = ri;
+                        part[q] += ri * ri;
+                    } else {
+                        Y[o] = acc[q];
+                        part[q] += X[o] * acc[q];
+                    }
                 }
             }
-        }
+        });
     });
     block_colsum<W, CPL>(part, lds, lds + BLOCK + NB_MAX);
     store_seg<NB>(partials, lds + BLOCK + NB_MAX);
@@ -347,24 +460,29 @@ __global__ __launch_bounds__(BLOCK) void kb_cheb(Batch bt, BState st, ppk::SellV
     const double *cf = coef + ((size_t)br.seg * bt.k + (j - 1)) * 4;
     const T ax = (T)cf[0], aold = (T)cf[1], ar = (T)cf[2], aA = (T)cf[3];
     double part[CPL] = {};
-    for_rows<W>(A, br, [&](int64_t row, int rin, int64_t base, int width) {
-        const int64_t o = row * NB + c0;
-        Vec<RT, CPL> rv = ldv<RT, CPL>(Rv + o);
-        Vec<T, CPL> xs, so;
-        if (MODE >= 2) xs = ldv<T, CPL>(X + o);
-        if (MODE == 3) so = ldv<T, CPL>(SOLD + o);
-        T acc[CPL];
-        spmm_row<T, W, CPL, NT>(A, X, NB, base, width, rin, c0, acc);
-        if (row < br.row_end) {
+    with_seg_storage(bt, br.seg, [&](auto dk, auto spc) {
+        constexpr int DK = decltype(dk)::value;
+        constexpr bool SP = decltype(spc)::value;
+        const SegDia<DK> g = seg_dia<DK>(bt, br.seg);
+        for_rows<W, SP>(A, br, [&](int64_t row, int rin, int64_t base, int width) {
+            const int64_t o = row * NB + c0;
+            Vec<RT, CPL> rv = ldv<RT, CPL>(Rv + o);
+            Vec<T, CPL> xs, so;
+            if (MODE >= 2) xs = ldv<T, CPL>(X + o);
+            if (MODE == 3) so = ldv<T, CPL>(SOLD + o);
+            T acc[CPL];
+            spmm_any<T, W, CPL, DK, SP, NT>(A, bt, g, X, NB, row, base, width, rin, c0, acc);
+            if (row < br.row_end) {
 #pragma unroll
-            for (int q = 0; q < CPL; ++q) {
-                T v = aA * acc[q] + ar * (T)rv.v[q];
-                if (MODE >= 2) v += ax * xs.v[q];
-                if (MODE == 3) v += aold * so.v[q];
-                OUT[o + q] = (OT)v;
-                if (LAST) part[q] += (double)rv.v[q] * (double)(OT)v;
+                for (int q = 0; q < CPL; ++q) {
+                    T v = aA * acc[q] + ar * (T)rv.v[q];
+                    if (MODE >= 2) v += ax * xs.v[q];
+                    if (MODE == 3) v += aold * so.v[q];
+                    OUT[o + q] = (OT)v;
+                    if (LAST) part[q] += (double)rv.v[q] * (double)(OT)v;
+                }
             }
-        }
+        });
     });
     if (LAST) {
         block_colsum<W, CPL>(part, lds, lds + BLOCK + NB_MAX);
@@ -383,7 +501,7 @@ __global__ __launch_bounds__(BLOCK) void kb_deg0(Batch bt, BState st, ppk::SellV
     PPB_PROLOGUE()
     const double ti = thinv[br.seg];
     double part[CPL] = {};
-    for_rows<W>(A, br, [&](int64_t row, int rin, int64_t base, int width) {
+    for_rows<W, false>(A, br, [&](int64_t row, int rin, int64_t base, int width) {
 #pragma unroll
         for (int q = 0; q < CPL; ++q) {
             const int64_t o = row * NB + c0 + q;
@@ -412,7 +530,7 @@ __global__ __launch_bounds__(BLOCK) void kb_xr(Batch bt, BState st, ppk::SellVie
         al[q] = st.done[i] ? 0.0 : st.alpha[i];
     }
     double part[CPL] = {};
-    for_rows<W>(A, br, [&](int64_t row, int rin, int64_t base, int width) {
+    for_rows<W, false>(A, br, [&](int64_t row, int rin, int64_t base, int width) {
 #pragma unroll
         for (int q = 0; q < CPL; ++q) {
             const int64_t o = row * NB + c0 + q;
@@ -441,7 +559,7 @@ __global__ __launch_bounds__(BLOCK) void kb_p(Batch bt, BState st, ppk::SellView
         fr[q] = st.done[i] != 0;
         be[q] = first ? 0.0 : st.beta[i];
     }
-    for_rows<W>(A, br, [&](int64_t row, int rin, int64_t base, int width) {
+    for_rows<W, false>(A, br, [&](int64_t row, int rin, int64_t base, int width) {
 #pragma unroll
         for (int q = 0; q < CPL; ++q) {
             const int64_t o = row * NB + c0 + q;
@@ -457,7 +575,7 @@ __global__ __launch_bounds__(BLOCK) void kb_conv(Batch bt, BState st, ppk::SellV
 {
     PPB_PROLOGUE()
     constexpr int NB = W * CPL;
-    for_rows<W>(A, br, [&](int64_t row, int rin, int64_t base, int width) {
+    for_rows<W, false>(A, br, [&](int64_t row, int rin, int64_t base, int width) {
 #pragma unroll
         for (int q = 0; q < CPL; ++q) R32[row * NB + c0 + q] = (float)Rv[row * NB + c0 + q];
     });
@@ -473,7 +591,7 @@ __global__ __launch_bounds__(BLOCK) void kb_final(Batch bt, BState st, ppk::Sell
     const int lane = threadIdx.x & (WAVE - 1);
     const int c0 = (lane % W) * CPL;
     const int64_t ext0 = bt.ext_row0[br.seg], row0 = bt.seg_row0[br.seg];
-    for_rows<W>(A, br, [&](int64_t row, int rin, int64_t base, int width) {
+    for_rows<W, false>(A, br, [&](int64_t row, int rin, int64_t base, int width) {
         if (row >= br.row_end) return;
         const int64_t er = ext0 + (row - row0);
         const double d = dis ? dis[row] : 1.0;
@@ -529,7 +647,7 @@ static __global__ __launch_bounds__(BLOCK) void kb_lz_start(Batch bt, BState st,
     const BlockRange br = my_range(bt);
     const int64_t row0 = bt.seg_row0[br.seg];
     double part[1] = {0.0};
-    for_rows<1>(A, br, [&](int64_t row, int rin, int64_t base, int width) {
+    for_rows<1, false>(A, br, [&](int64_t row, int rin, int64_t base, int width) {
         double x = 0.0;
         if (row < br.row_end) x = (double)ppk::fmix32((uint32_t)(row - row0)) / 4294967296.0 - 0.5;
         v[row] = x;
@@ -547,7 +665,7 @@ static __global__ __launch_bounds__(BLOCK) void kb_lz_vec(Batch bt, BState st, p
     const BlockRange br = my_range(bt);
     const double *lz = st.lz + (size_t)br.seg * (2 * ppk::LZ_MAX + 2);
     const double d = mode == 0 ? lz[2 * ppk::LZ_MAX] : lz[ppk::LZ_MAX + j];
-    for_rows<1>(A, br, [&](int64_t row, int rin, int64_t base, int width) {
+    for_rows<1, false>(A, br, [&](int64_t row, int rin, int64_t base, int width) {
         if (mode == 0) {
             v[row] = v[row] / d;
             vprev[row] = 0.0;
@@ -571,16 +689,21 @@ __global__ __launch_bounds__(BLOCK) void kb_lz_step(Batch bt, BState st, ppk::Se
     double part[1] = {0.0};
     if (WHICH == 0) {
         const double bp = j > 0 ? lz[ppk::LZ_MAX + j - 1] : 0.0;
-        for_rows<1>(A, br, [&](int64_t row, int rin, int64_t base, int width) {
-            double acc[1];
-            spmm_row<double, 1, 1, false>(A, v, 1, base, width, rin, 0, acc);
-            const double wi = row < br.row_end ? acc[0] - bp * vprev[row] : 0.0;
-            w[row] = wi;
-            part[0] += v[row] * wi;
+        with_seg_storage(bt, br.seg, [&](auto dk, auto spc) {
+            constexpr int DK = decltype(dk)::value;
+            constexpr bool SP = decltype(spc)::value;
+            const SegDia<DK> g = seg_dia<DK>(bt, br.seg);
+            for_rows<1, SP>(A, br, [&](int64_t row, int rin, int64_t base, int width) {
+                double acc[1];
+                spmm_any<double, 1, 1, DK, SP, false>(A, bt, g, v, 1, row, base, width, rin, 0, acc);
+                const double wi = row < br.row_end ? acc[0] - bp * vprev[row] : 0.0;
+                w[row] = wi;
+                part[0] += v[row] * wi;
+            });
         });
     } else {
         const double a = lz[j];
-        for_rows<1>(A, br, [&](int64_t row, int rin, int64_t base, int width) {
+        for_rows<1, false>(A, br, [&](int64_t row, int rin, int64_t base, int width) {
             const double wi = w[row] - a * v[row];
             w[row] = wi;
             part[0] += wi * wi;
@@ -603,16 +726,38 @@ __device__ __forceinline__ int64_t ext_of(const int32_t *slice_seg, const int64_
     return off < seg_n[s] ? ext_row0[s] + off : -1;
 }
 
+// Is entry (e, c) (caller rows) covered by system g's stored diagonals?
+__device__ __forceinline__ bool seg_covered(const int32_t *seg_nd, const int64_t *seg_off, int g, int64_t e,
+                                            int64_t c)
+{
+    const int nd = seg_nd[g];
+    const int64_t a = c >= e ? c - e : e - c;
+    for (int d = 0; d < nd; ++d)
+        if (seg_off[(int64_t)g * ppk::DMAX + d] == a) return true;
+    return false;
+}
+
+// entries per slice that are not covered by their system's stored diagonals
 static __global__ __launch_bounds__(BLOCK) void kb_slice_width(int64_t nslices, const int32_t *slice_seg,
                                                         const int64_t *seg_row0, const int64_t *seg_n,
                                                         const int64_t *ext_row0, const int64_t *__restrict__ rp,
-                                                        int64_t *__restrict__ width)
+                                                        const int32_t *__restrict__ col, const int32_t *seg_nd,
+                                                        const int64_t *seg_off, int64_t *__restrict__ width)
 {
     const int64_t s = (int64_t)blockIdx.x * WPB + threadIdx.x / WAVE;
     const int lane = threadIdx.x & (WAVE - 1);
     if (s >= nslices) return;
+    const int g = slice_seg[s];
     const int64_t e = ext_of(slice_seg, seg_row0, seg_n, ext_row0, s * WAVE + lane);
-    int64_t len = e >= 0 ? rp[e + 1] - rp[e] : 0;
+    int64_t len = 0;
+    if (e >= 0) {
+        if (seg_nd[g] == 0) {
+            len = rp[e + 1] - rp[e];
+        } else {
+            for (int64_t p = rp[e]; p < rp[e + 1]; ++p)
+                if (!seg_covered(seg_nd, seg_off, g, e, col[p])) ++len;
+        }
+    }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         const int64_t o = __shfl_down(len, off, WAVE);
@@ -658,6 +803,7 @@ static __global__ __launch_bounds__(BLOCK) void kb_slice_fill(int64_t nslices, c
                                                        const int64_t *seg_row0, const int64_t *seg_n,
                                                        const int64_t *ext_row0, const int64_t *__restrict__ rp,
                                                        const int32_t *__restrict__ col, const double *__restrict__ val,
+                                                       const int32_t *seg_nd, const int64_t *seg_off,
                                                        const double *__restrict__ dis, const int64_t *__restrict__ sp,
                                                        int32_t *__restrict__ scol, double *__restrict__ sval,
                                                        float *__restrict__ sval32, int jacobi)
@@ -673,13 +819,15 @@ static __global__ __launch_bounds__(BLOCK) void kb_slice_fill(int64_t nslices, c
     int j = 0;
     if (e >= 0) {
         const double di = dis[row];
-        for (int64_t p = rp[e]; p < rp[e + 1]; ++p, ++j) {
+        for (int64_t p = rp[e]; p < rp[e + 1]; ++p) {
+            if (seg_nd[g] > 0 && seg_covered(seg_nd, seg_off, g, e, col[p])) continue;
             const int64_t ci = (int64_t)col[p] - ext_row0[g] + seg_row0[g];  // internal column
             const double v = jacobi ? val[p] * di * dis[ci] : val[p];
             const int64_t o = base + (int64_t)j * WAVE + lane;
             scol[o] = (int32_t)ci;
             sval[o] = v;
             if (sval32) sval32[o] = (float)v;
+            ++j;
         }
     }
     for (; j < width; ++j) {

@@ -1019,7 +1019,9 @@ __device__ __forceinline__ bool off_insert(unsigned long long *key, unsigned lon
 // Histogram of the column offsets col - row over the nonzero entries (at
 // most OFF_SLOTS distinct ones; *overflow is set when there are more).  A
 // table per workgroup in LDS, merged into the global table at the end.
-static __global__ __launch_bounds__(BLOCK) void k_offsets(int64_t n, const int64_t *__restrict__ rp,
+// Rows are i = 0..n-1 of rp; their global index (that col refers to) is i + row_base.
+static __global__ __launch_bounds__(BLOCK) void k_offsets(int64_t n, int64_t row_base,
+                                                          const int64_t *__restrict__ rp,
                                                           const int32_t *__restrict__ col,
                                                           const double *__restrict__ val,
                                                           unsigned long long *gkey, unsigned long long *gcnt,
@@ -1035,7 +1037,7 @@ static __global__ __launch_bounds__(BLOCK) void k_offsets(int64_t n, const int64
     __syncthreads();
     for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) {
         for (int64_t p = rp[i]; p < rp[i + 1]; ++p)
-            if (val[p] != 0.0 && !off_insert(key, cnt, (int64_t)col[p] - i, 1)) {
+            if (val[p] != 0.0 && !off_insert(key, cnt, (int64_t)col[p] - (i + row_base), 1)) {
                 full = 1;
                 break;
             }
@@ -1053,8 +1055,8 @@ static __global__ __launch_bounds__(BLOCK) void k_offsets(int64_t n, const int64
 // Raw values of the covered entries with offset >= 0 into dv[d][i] (dv zeroed
 // beforehand).  cnt[0] / cnt[1] count the nonzero covered entries above / below
 // the diagonal; a covered offset seen twice in one row (a duplicate entry)
-// sets bad |= 16.
-static __global__ __launch_bounds__(BLOCK) void k_dia_fill(int64_t n, const int64_t *__restrict__ rp,
+// sets bad |= 16.  Row i of rp has global index i + row_base.
+static __global__ __launch_bounds__(BLOCK) void k_dia_fill(int64_t n, int64_t row_base, const int64_t *__restrict__ rp,
                                                            const int32_t *__restrict__ col,
                                                            const double *__restrict__ val, DiaSet D,
                                                            double *__restrict__ dv, int64_t ds,
@@ -1069,7 +1071,7 @@ static __global__ __launch_bounds__(BLOCK) void k_dia_fill(int64_t n, const int6
     if (i < n) {
         uint32_t seen_u = 0, seen_l = 0;
         for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
-            const int64_t o = (int64_t)col[p] - i;
+            const int64_t o = (int64_t)col[p] - (i + row_base);
             const int d = dia_index(D, o < 0 ? -o : o);
             if (d < 0) continue;
             const double v = val[p];
@@ -1096,7 +1098,8 @@ static __global__ __launch_bounds__(BLOCK) void k_dia_fill(int64_t n, const int6
 // mirror: a_{i, i-o} == a_{i-o, i} (else bad |= 32).  With no duplicates and
 // equal counts of nonzero entries above and below, the covered part is then
 // exactly symmetric and the mirrored reads reproduce it.
-static __global__ __launch_bounds__(BLOCK) void k_dia_check(int64_t n, const int64_t *__restrict__ rp,
+static __global__ __launch_bounds__(BLOCK) void k_dia_check(int64_t n, int64_t row_base,
+                                                            const int64_t *__restrict__ rp,
                                                             const int32_t *__restrict__ col,
                                                             const double *__restrict__ val, DiaSet D,
                                                             const double *__restrict__ dv, int64_t ds,
@@ -1105,7 +1108,7 @@ static __global__ __launch_bounds__(BLOCK) void k_dia_check(int64_t n, const int
     const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (i >= n) return;
     for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
-        const int64_t j = col[p];
+        const int64_t j = (int64_t)col[p] - row_base;
         if (j >= i) continue;
         const int d = dia_index(D, i - j);
         if (d >= 0 && !(dv[(int64_t)d * ds + j] == val[p])) {

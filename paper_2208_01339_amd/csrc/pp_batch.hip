@@ -10,6 +10,7 @@
 
 #include "batch.hpp"
 #include "common.hpp"
+#include "dia_plan.hpp"
 #include "sym_eig.hpp"
 
 using ppc::dalloc;
@@ -39,6 +40,12 @@ struct pp_batch_s {
     double *sval = nullptr;
     float *sval32 = nullptr;
     double *dis = nullptr;
+    // symmetric stored diagonals per system
+    int32_t *seg_nd = nullptr, *seg_sell = nullptr;
+    int64_t *seg_off = nullptr;
+    double *dv64 = nullptr;
+    float *dv32 = nullptr;
+    int diag_systems = 0;
     // vectors [n_int][NB]
     double *Xh = nullptr, *R = nullptr, *P = nullptr, *Q = nullptr, *Z = nullptr, *Bh = nullptr;
     double *SA64 = nullptr, *SB64 = nullptr;
@@ -83,6 +90,12 @@ struct pp_batch_s {
         b.NB = NB;
         b.nrhs = nrhs;
         b.k = k;
+        b.seg_nd = seg_nd;
+        b.seg_sell = seg_sell;
+        b.seg_off = seg_off;
+        b.dv64 = dv64;
+        b.dv32 = dv32;
+        b.dstride = n_int;
         return b;
     }
     ppb::BState bst(double tol, int maxit) const
@@ -115,6 +128,7 @@ struct pp_batch_s {
         dfree(blk_seg); dfree(seg_blk0); dfree(slice_seg); dfree(blk_s0); dfree(blk_s1); dfree(seg_row0);
         dfree(seg_n); dfree(ext_row0);
         dfree(sp); dfree(scol); dfree(sval); dfree(sval32); dfree(dis);
+        dfree(seg_nd); dfree(seg_sell); dfree(seg_off); dfree(dv64); dfree(dv32);
         dfree(Xh); dfree(R); dfree(P); dfree(Q); dfree(Z); dfree(Bh); dfree(SA64); dfree(SB64);
         dfree(R32); dfree(SA); dfree(SB); dfree(partials); dfree(coef_d); dfree(thinv_d);
         dfree(d_rho); dfree(d_alpha); dfree(d_beta); dfree(d_rr); dfree(d_bn2); dfree(d_tol2); dfree(d_lz);
@@ -170,6 +184,101 @@ void end_call(pp_batch_s *op)
 {
     HIPCHK(hipEventRecord(op->sync_ev, op->stream));
     HIPCHK(hipStreamWaitEvent(op->ustream, op->sync_ev, 0));
+}
+
+// Symmetric stored diagonals per system, chosen as for a single operator
+// (choose_diagonals) on the system's own offset histogram.  The batch kernels
+// take 5-point (3 diagonals) and 7-point (4) shapes; any other choice, a
+// duplicate entry or an asymmetric value leaves the system in the slice
+// layout.  Values live at dv[d * n_int + internal row], Jacobi-scaled.
+void build_diagonals(pp_batch_s *op, const int64_t *rowptr, const int32_t *colind, const double *val)
+{
+    using ppk::OFF_SLOTS;
+    typedef unsigned long long u64;
+    const int S = op->S;
+    std::vector<int32_t> nd(S, 0);
+    std::vector<int64_t> off((size_t)S * ppk::DMAX, 0);
+    struct Tmp {
+        u64 *key = nullptr, *cnt = nullptr;
+        int *flag = nullptr;
+        ~Tmp() { dfree(key); dfree(cnt); dfree(flag); }
+    } t;
+    if (!(op->flags & PP_SLICED)) {
+        t.key = dalloc<u64>((size_t)S * OFF_SLOTS);
+        t.cnt = dalloc<u64>((size_t)S * OFF_SLOTS);
+        t.flag = dalloc<int>(S);
+        std::vector<u64> hk((size_t)S * OFF_SLOTS, ppk::OFF_EMPTY), hc((size_t)S * OFF_SLOTS, 0);
+        std::vector<int> hf(S, 0);
+        HIPCHK(hipMemcpyAsync(t.key, hk.data(), sizeof(u64) * hk.size(), hipMemcpyHostToDevice, op->stream));
+        HIPCHK(hipMemsetAsync(t.cnt, 0, sizeof(u64) * hc.size(), op->stream));
+        HIPCHK(hipMemsetAsync(t.flag, 0, sizeof(int) * S, op->stream));
+        for (int s = 0; s < S; ++s) {
+            const int64_t n = op->seg_n_h[s], e0 = op->sys_ptr[s];
+            const unsigned g = (unsigned)std::min<int64_t>(2048, (n + BLOCK - 1) / BLOCK);
+            hipLaunchKernelGGL(ppk::k_offsets, dim3(g), dim3(BLOCK), 0, op->stream, n, e0, rowptr + e0, colind, val,
+                               t.key + (size_t)s * OFF_SLOTS, t.cnt + (size_t)s * OFF_SLOTS, t.flag + s);
+        }
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(hk.data(), t.key, sizeof(u64) * hk.size(), hipMemcpyDeviceToHost, op->stream));
+        HIPCHK(hipMemcpyAsync(hc.data(), t.cnt, sizeof(u64) * hc.size(), hipMemcpyDeviceToHost, op->stream));
+        HIPCHK(hipMemcpyAsync(hf.data(), t.flag, sizeof(int) * S, hipMemcpyDeviceToHost, op->stream));
+        HIPCHK(hipStreamSynchronize(op->stream));
+        int ndmax = 0;
+        std::vector<ppk::DiaSet> D(S);
+        for (int s = 0; s < S; ++s) {
+            if (hf[s]) continue;
+            D[s] = choose_diagonals(hk.data() + (size_t)s * OFF_SLOTS, hc.data() + (size_t)s * OFF_SLOTS,
+                                    op->seg_n_h[s]);
+            if (D[s].nd != 3 && D[s].nd != 4) D[s] = ppk::DiaSet{};
+            ndmax = std::max(ndmax, D[s].nd);
+        }
+        if (ndmax > 0) {
+            const int64_t ds = op->n_int;
+            op->dv64 = dalloc<double>((size_t)ndmax * ds);
+            HIPCHK(hipMemsetAsync(op->dv64, 0, sizeof(double) * ndmax * ds, op->stream));
+            HIPCHK(hipMemsetAsync(t.cnt, 0, sizeof(u64) * 2 * S, op->stream));
+            HIPCHK(hipMemsetAsync(t.flag, 0, sizeof(int) * S, op->stream));
+            for (int s = 0; s < S; ++s) {
+                if (D[s].nd == 0) continue;
+                const int64_t n = op->seg_n_h[s], e0 = op->sys_ptr[s], r0 = op->seg_row0_h[s];
+                const unsigned gr = (unsigned)((n + BLOCK - 1) / BLOCK);
+                hipLaunchKernelGGL(ppk::k_dia_fill, dim3(gr), dim3(BLOCK), 0, op->stream, n, e0, rowptr + e0, colind,
+                                   val, D[s], op->dv64 + r0, ds, t.cnt + 2 * s, t.flag + s);
+                hipLaunchKernelGGL(ppk::k_dia_check, dim3(gr), dim3(BLOCK), 0, op->stream, n, e0, rowptr + e0,
+                                   colind, val, D[s], (const double *)op->dv64 + r0, ds, t.flag + s);
+            }
+            HIPCHK(hipGetLastError());
+            std::vector<u64> ul(2 * S);
+            HIPCHK(hipMemcpyAsync(ul.data(), t.cnt, sizeof(u64) * 2 * S, hipMemcpyDeviceToHost, op->stream));
+            HIPCHK(hipMemcpyAsync(hf.data(), t.flag, sizeof(int) * S, hipMemcpyDeviceToHost, op->stream));
+            HIPCHK(hipStreamSynchronize(op->stream));
+            if (op->mixed()) {
+                op->dv32 = dalloc<float>((size_t)ndmax * ds);
+                HIPCHK(hipMemsetAsync(op->dv32, 0, sizeof(float) * ndmax * ds, op->stream));
+            }
+            const bool jac = (op->flags & PP_JACOBI) != 0;
+            for (int s = 0; s < S; ++s) {
+                if (D[s].nd == 0) continue;
+                if (hf[s] || ul[2 * s] != ul[2 * s + 1]) {
+                    D[s] = ppk::DiaSet{};
+                    continue;
+                }
+                const int64_t n = op->seg_n_h[s], r0 = op->seg_row0_h[s];
+                hipLaunchKernelGGL(ppk::k_dia_scale, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0,
+                                   op->stream, n, D[s], jac ? (const double *)op->dis + r0 : (const double *)nullptr,
+                                   op->dv64 + r0, op->dv32 ? op->dv32 + r0 : (float *)nullptr, ds);
+                nd[s] = D[s].nd;
+                for (int d = 0; d < ppk::DMAX; ++d) off[(size_t)s * ppk::DMAX + d] = D[s].off[d];
+            }
+            HIPCHK(hipGetLastError());
+        }
+    }
+    op->diag_systems = (int)std::count_if(nd.begin(), nd.end(), [](int v) { return v > 0; });
+    op->seg_nd = dalloc<int32_t>(S);
+    op->seg_off = dalloc<int64_t>((size_t)S * ppk::DMAX);
+    HIPCHK(hipMemcpyAsync(op->seg_nd, nd.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice, op->stream));
+    HIPCHK(hipMemcpyAsync(op->seg_off, off.data(), sizeof(int64_t) * off.size(), hipMemcpyHostToDevice, op->stream));
+    HIPCHK(hipStreamSynchronize(op->stream));  // host vectors go out of scope
 }
 
 pp_status build(pp_batch_s *op, const int64_t *rowptr, const int32_t *colind, const double *val)
@@ -259,13 +368,17 @@ pp_status build(pp_batch_s *op, const int64_t *rowptr, const int32_t *colind, co
         if (h & 8) { cleanup(); return fail(PP_ERR_ARG, "an entry couples two systems (matrix not block diagonal)"); }
         if (h & 1) { cleanup(); return fail(PP_ERR_ARG, "Jacobi scaling needs a positive finite diagonal"); }
 
-        // slice layout
+        // symmetric stored diagonals, chosen per system
+        build_diagonals(op, rowptr, colind, val);
+
+        // slice layout: the entries the stored diagonals do not cover
         width = dalloc<int64_t>(op->nslices);
         op->sp = dalloc<int64_t>(op->nslices + 1);
         const unsigned gs = (unsigned)((op->nslices + WPB - 1) / WPB);
         hipLaunchKernelGGL(ppb::kb_slice_width, dim3(gs), dim3(BLOCK), 0, op->stream, op->nslices,
                            (const int32_t *)op->slice_seg, (const int64_t *)op->seg_row0, (const int64_t *)op->seg_n,
-                           (const int64_t *)op->ext_row0, rowptr, width);
+                           (const int64_t *)op->ext_row0, rowptr, colind, (const int32_t *)op->seg_nd,
+                           (const int64_t *)op->seg_off, width);
         hipLaunchKernelGGL(ppk::k_scan_slices, dim3(1), dim3(1024), 0, op->stream, op->nslices, (const int64_t *)width,
                            op->sp);
         HIPCHK(hipGetLastError());
@@ -276,10 +389,23 @@ pp_status build(pp_batch_s *op, const int64_t *rowptr, const int32_t *colind, co
         if (op->mixed()) op->sval32 = dalloc<float>(op->nstored);
         hipLaunchKernelGGL(ppb::kb_slice_fill, dim3(gs), dim3(BLOCK), 0, op->stream, op->nslices,
                            (const int32_t *)op->slice_seg, (const int64_t *)op->seg_row0, (const int64_t *)op->seg_n,
-                           (const int64_t *)op->ext_row0, rowptr, colind, val, (const double *)op->dis,
-                           (const int64_t *)op->sp, op->scol, op->sval, op->sval32,
-                           (int)((op->flags & PP_JACOBI) != 0));
+                           (const int64_t *)op->ext_row0, rowptr, colind, val, (const int32_t *)op->seg_nd,
+                           (const int64_t *)op->seg_off, (const double *)op->dis, (const int64_t *)op->sp, op->scol,
+                           op->sval, op->sval32, (int)((op->flags & PP_JACOBI) != 0));
         HIPCHK(hipGetLastError());
+        // systems with entries in the slice layout
+        {
+            std::vector<int64_t> spb(S + 1);
+            for (int s = 0; s <= S; ++s)
+                HIPCHK(hipMemcpyAsync(&spb[s], op->sp + op->seg_row0_h[s] / WAVE, sizeof(int64_t),
+                                      hipMemcpyDeviceToHost, op->stream));
+            HIPCHK(hipStreamSynchronize(op->stream));
+            std::vector<int32_t> sell(S);
+            for (int s = 0; s < S; ++s) sell[s] = spb[s + 1] > spb[s] ? 1 : 0;
+            op->seg_sell = dalloc<int32_t>(S);
+            HIPCHK(hipMemcpyAsync(op->seg_sell, sell.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice, op->stream));
+            HIPCHK(hipStreamSynchronize(op->stream));
+        }
 
         // vectors (zeroed: padding rows and columns stay zero for good)
         const size_t nv = (size_t)op->n_int * op->NB;
@@ -474,7 +600,7 @@ pp_status pp_create_batch(pp_batch *out, int nsys, const int64_t *sys_ptr, int64
     if (nsys < 1 || !sys_ptr || nnz <= 0 || !rowptr || !colind || !val)
         return fail(PP_ERR_ARG, "nsys >= 1, nnz > 0 and non-NULL arrays required");
     if (nrhs < 1 || nrhs > ppb::NB_MAX) return fail(PP_ERR_ARG, "nrhs must be in [1, 32]");
-    if (flags & ~(unsigned)(PP_JACOBI | PP_MIXED)) return fail(PP_ERR_ARG, "unknown flags");
+    if (flags & ~(unsigned)(PP_JACOBI | PP_MIXED | PP_SLICED)) return fail(PP_ERR_ARG, "unknown flags");
     if (sys_ptr[0] != 0) return fail(PP_ERR_ARG, "sys_ptr[0] must be 0");
     for (int s = 0; s < nsys; ++s)
         if (sys_ptr[s + 1] <= sys_ptr[s]) return fail(PP_ERR_ARG, "sys_ptr must be strictly increasing");
@@ -505,6 +631,7 @@ pp_status pp_create_batch(pp_batch *out, int nsys, const int64_t *sys_ptr, int64
     op->stats.w = op->W;
     op->stats.nnz_stored = op->nstored;
     op->stats.grid = op->G;
+    op->stats.diag_systems = op->diag_systems;
     *out = op;
     return PP_OK;
 }

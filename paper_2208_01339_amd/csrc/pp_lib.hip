@@ -15,6 +15,7 @@
 #include "../../include/pp.h"
 #include "kernels.hpp"
 #include "op.hpp"
+#include "dia_plan.hpp"
 #include "persistent.hpp"
 #include "sym_eig.hpp"
 
@@ -99,16 +100,14 @@ int check_csr_dev(pp_op_s *op, int64_t rows, int64_t ncols, int64_t nnz, const i
     return h;
 }
 
-// Symmetric diagonal part of the operator (see SellView): pick the column
-// offsets worth a stored diagonal, fill them, verify that the covered
-// entries are exactly symmetric, then scale.  A stored diagonal costs 8 n
-// bytes and is read once per application; the slice layout costs 12 bytes per
-// entry, so an offset pair is kept when it covers more than 2n/3 nonzero
-// entries (explicit zeros are counted nowhere; the fill stores them as the
-// zeros they are).
-// Returns the covered set; nd = 0 when the matrix does not qualify (more than
-// OFF_SLOTS distinct offsets, no dense diagonal, duplicate entries or
-// asymmetric values): every entry then stays in the slice part.
+// Symmetric diagonal part of the operator (see SellView): histogram the
+// column offsets of the nonzero entries, pick the offsets worth a stored
+// diagonal (choose_diagonals), fill them, verify that the covered entries are
+// exactly symmetric, then scale.  Explicit zeros are counted nowhere; the
+// fill stores them as the zeros they are.  Returns the covered set; nd = 0
+// when the matrix does not qualify (more than OFF_SLOTS distinct offsets, no
+// dense diagonal, duplicate entries or asymmetric values): every entry then
+// stays in the slice part.
 ppk::DiaSet build_diagonals(pp_op_s *op, const int64_t *rp, const int32_t *col, const double *val)
 {
     using ppk::OFF_SLOTS;
@@ -128,8 +127,8 @@ ppk::DiaSet build_diagonals(pp_op_s *op, const int64_t *rp, const int32_t *col, 
     HIPCHK(hipMemsetAsync(t.cnt, 0, sizeof(u64) * OFF_SLOTS, op->stream));
     HIPCHK(hipMemsetAsync(t.flag, 0, sizeof(int), op->stream));
     const unsigned g = (unsigned)std::min<int64_t>(2048, (n + BLOCK - 1) / BLOCK);
-    hipLaunchKernelGGL(ppk::k_offsets, dim3(g), dim3(BLOCK), 0, op->stream, n, rp, col, val, t.key, t.cnt,
-                       t.flag);
+    hipLaunchKernelGGL(ppk::k_offsets, dim3(g), dim3(BLOCK), 0, op->stream, n, (int64_t)0, rp, col, val, t.key,
+                       t.cnt, t.flag);
     HIPCHK(hipGetLastError());
     int flag = 0;
     HIPCHK(hipMemcpyAsync(hk.data(), t.key, sizeof(u64) * OFF_SLOTS, hipMemcpyDeviceToHost, op->stream));
@@ -137,30 +136,8 @@ ppk::DiaSet build_diagonals(pp_op_s *op, const int64_t *rp, const int32_t *col, 
     HIPCHK(hipMemcpyAsync(&flag, t.flag, sizeof(int), hipMemcpyDeviceToHost, op->stream));
     HIPCHK(hipStreamSynchronize(op->stream));
     if (flag) return D;
-    std::vector<std::pair<int64_t, u64>> count;  // (offset, entries)
-    for (int q = 0; q < OFF_SLOTS; ++q)
-        if (hk[q] != ppk::OFF_EMPTY) count.push_back({(int64_t)hk[q], hc[q]});
-    auto entries = [&](int64_t o) -> u64 {
-        for (auto &c : count)
-            if (c.first == o) return c.second;
-        return 0;
-    };
-    if (3 * entries(0) <= 2 * (u64)n) return D;
-    std::vector<std::pair<u64, int64_t>> cand;  // (entries covered, offset > 0)
-    for (auto &c : count) {
-        if (c.first <= 0 || entries(-c.first) != c.second) continue;  // unpaired: not symmetric
-        const u64 cov = 2 * c.second;
-        if (3 * cov > 2 * (u64)n) cand.push_back({cov, c.first});
-    }
-    std::sort(cand.begin(), cand.end(), [](const std::pair<u64, int64_t> &a, const std::pair<u64, int64_t> &b) {
-        return a.first != b.first ? a.first > b.first : a.second < b.second;
-    });
-    if ((int)cand.size() > ppk::DMAX - 1) cand.resize(ppk::DMAX - 1);
-    std::vector<int64_t> offs{0};
-    for (auto &c : cand) offs.push_back(c.second);
-    std::sort(offs.begin(), offs.end());
-    D.nd = (int)offs.size();
-    for (int d = 0; d < D.nd; ++d) D.off[d] = offs[d];
+    D = choose_diagonals(hk.data(), hc.data(), n);
+    if (D.nd == 0) return D;
 
     const int64_t ds = op->nslices * WAVE;
     op->dval = dalloc<double>((size_t)D.nd * ds);
@@ -168,10 +145,10 @@ ppk::DiaSet build_diagonals(pp_op_s *op, const int64_t *rp, const int32_t *col, 
     HIPCHK(hipMemsetAsync(t.cnt, 0, 2 * sizeof(u64), op->stream));
     HIPCHK(hipMemsetAsync(t.flag, 0, sizeof(int), op->stream));
     const unsigned gr = (unsigned)((n + BLOCK - 1) / BLOCK);
-    hipLaunchKernelGGL(ppk::k_dia_fill, dim3(gr), dim3(BLOCK), 0, op->stream, n, rp, col, val, D, op->dval, ds,
-                       t.cnt, t.flag);
+    hipLaunchKernelGGL(ppk::k_dia_fill, dim3(gr), dim3(BLOCK), 0, op->stream, n, (int64_t)0, rp, col, val, D,
+                       op->dval, ds, t.cnt, t.flag);
     HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL(ppk::k_dia_check, dim3(gr), dim3(BLOCK), 0, op->stream, n, rp, col, val, D,
+    hipLaunchKernelGGL(ppk::k_dia_check, dim3(gr), dim3(BLOCK), 0, op->stream, n, (int64_t)0, rp, col, val, D,
                        (const double *)op->dval, ds, t.flag);
     HIPCHK(hipGetLastError());
     u64 ul[2] = {0, 0};

@@ -23,7 +23,8 @@ import re
 import statistics
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-DIGEST_FILES = ("csrc/kernels.hpp", "csrc/op.hpp", "csrc/common.hpp", "csrc/pp_lib.hip", "build.py")
+DIGEST_FILES = ("csrc/kernels.hpp", "csrc/op.hpp", "csrc/common.hpp", "csrc/dia_plan.hpp", "csrc/pp_lib.hip",
+                "build.py")
 
 
 def _code_only(text: str) -> str:

@@ -60,24 +60,35 @@ def block_rhs(sys_ptr, nrhs, seed0):
     return W.block_rhs(n, nrhs, seed0)
 
 
+LAYOUTS = ["diag", "sliced"]
+
+
+def lay(B, layout):
+    """Storage flag: "diag" = the default per-system choice, "sliced" = PP_SLICED."""
+    return B.PP_SLICED if layout == "sliced" else 0
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("nrhs", [1, 3, 8])
-def test_batch_bounds_match_oracle(B, nrhs):
+def test_batch_bounds_match_oracle(B, nrhs, layout):
     systems = members()
     ops, lo, hi = oracle_bounds(systems)
-    bo = B.BatchOperator(systems, nrhs=nrhs, flags=B.PP_JACOBI)
+    bo = B.BatchOperator(systems, nrhs=nrhs, flags=B.PP_JACOBI | lay(B, layout))
+    assert B.pp_batch_get_stats(bo.handle)["diag_systems"] == (len(systems) if layout == "diag" else 0)
     glo, ghi = B.pp_batch_estimate_bounds(bo.handle, len(systems), 20)
     assert np.all(np.abs(glo - lo) <= 1e-7 * hi)
     assert np.all(np.abs(ghi - hi) <= 1e-7 * hi)
     bo.close()
 
 
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("nrhs,w", [(1, 1), (3, 8), (3, 4), (3, 2), (3, 1), (8, 8), (8, 2), (8, 1), (20, 32),
                                     (20, 16), (20, 8), (20, 4)])
-def test_batch_fp64_equal_iterations(B, nrhs, w):
+def test_batch_fp64_equal_iterations(B, nrhs, w, layout):
     systems = members()
     ops, lo, hi = oracle_bounds(systems)
     k, xi, m = 7, 1e-3, 9
-    bo = B.BatchOperator(systems, nrhs=nrhs, flags=B.PP_JACOBI)
+    bo = B.BatchOperator(systems, nrhs=nrhs, flags=B.PP_JACOBI | lay(B, layout))
     B.pp_batch_set_layout(bo.handle, w)
     B.pp_batch_setup(bo.handle, k, lo, hi, xi)
     Bm = block_rhs(bo.sys_ptr, nrhs, 40)
@@ -116,12 +127,56 @@ def test_batch_fp64_tol_driven(B, nrhs):
     bo.close()
 
 
+def random_spd(n, seed):
+    """Random symmetric sparsity (too many distinct offsets for stored diagonals), diagonally dominant."""
+    rng = np.random.default_rng(seed)
+    i = rng.integers(0, n, 3 * n)
+    j = rng.integers(0, n, 3 * n)
+    keep = i != j
+    i, j = i[keep], j[keep]
+    w = -rng.uniform(0.1, 1.0, len(i))
+    import scipy.sparse as sp
+
+    A = sp.coo_matrix((np.concatenate([w, w]), (np.concatenate([i, j]), np.concatenate([j, i]))), shape=(n, n)).tocsr()
+    A = A + sp.diags(np.asarray(abs(A).sum(axis=1)).ravel() + 1.0)
+    A = A.tocsr()
+    A.sum_duplicates()
+    A.sort_indices()
+    return W.CSR(n, n, A.indptr.astype(np.int64), A.indices.astype(np.int32), A.data.astype(np.float64))
+
+
+def test_batch_mixed_storage(B):
+    """Systems with different storages in one batch: 7-point (4 stored diagonals),
+    fracture blocks (3), and a random pattern (slice layout only)."""
+    systems = [W.hetero_diffusion(8, 2.0, 5), W.dfn_schur(n_frac=3, G=12, n_traces=4, L_lo=2, L_hi=6, seed=1).a,
+               random_spd(700, 3), W.hetero_diffusion(5, 1.0, 6)]
+    ops, lo, hi = oracle_bounds(systems)
+    k, xi, m = 6, 0.0, 8
+    for nrhs in (1, 4):
+        bo = B.BatchOperator(systems, nrhs=nrhs, flags=B.PP_JACOBI)
+        assert B.pp_batch_get_stats(bo.handle)["diag_systems"] == 3
+        B.pp_batch_setup(bo.handle, k, lo, hi, xi)
+        Bm = block_rhs(bo.sys_ptr, nrhs, 90)
+        X = torch.zeros(bo.n, nrhs, dtype=torch.float64, device="cuda")
+        s, it, rel, stt = B.pcg_solve_batch(bo.handle, len(systems), nrhs, dev(Bm), X, 0.0, m)
+        assert np.all(it == m)
+        Xg = host(X)
+        for i, o in enumerate(ops):
+            r0, r1 = bo.sys_ptr[i], bo.sys_ptr[i + 1]
+            for c in range(nrhs):
+                xo, sto = O.pcg(o, k, lo[i], hi[i], xi, Bm[r0:r1, c], tol=0.0, maxit=m)
+                err = np.linalg.norm(Xg[r0:r1, c] - xo) / np.linalg.norm(xo)
+                assert err <= 1e-10, (i, c, err)
+        bo.close()
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("nrhs", [1, 8])
-def test_batch_mixed_residual(B, nrhs):
+def test_batch_mixed_residual(B, nrhs, layout):
     systems = members()
     ops, lo, hi = oracle_bounds(systems)
     k = 12
-    bo = B.BatchOperator(systems, nrhs=nrhs, flags=B.PP_JACOBI | B.PP_MIXED)
+    bo = B.BatchOperator(systems, nrhs=nrhs, flags=B.PP_JACOBI | B.PP_MIXED | lay(B, layout))
     B.pp_batch_setup(bo.handle, k, lo, hi, 0.0)
     Bm = block_rhs(bo.sys_ptr, nrhs, 3)
     X = torch.zeros(bo.n, nrhs, dtype=torch.float64, device="cuda")
