@@ -57,6 +57,13 @@ def lib():
         L.orc_pcg.restype = C.c_int
         L.orc_pcg.argtypes = [P, C.c_int, C.c_double, C.c_double, C.c_double, P, P, C.c_double,
                               C.c_int, P]
+        L.orc_lowrank_setup.restype = C.c_int
+        L.orc_lowrank_setup.argtypes = [P, C.c_int, P, P]
+        L.orc_lowrank_apply.restype = C.c_int
+        L.orc_lowrank_apply.argtypes = [P, C.c_int, C.c_double, C.c_double, C.c_double, C.c_int, P, P, P, P, P]
+        L.orc_pcg_lowrank.restype = C.c_int
+        L.orc_pcg_lowrank.argtypes = [P, C.c_int, C.c_double, C.c_double, C.c_double, C.c_int, P, P, P, P,
+                                      C.c_double, C.c_int, P]
         L.orc_lanczos.restype = C.c_int
         L.orc_lanczos.argtypes = [P, C.c_int, P, P]
         L.orc_fmix32_start.argtypes = [C.c_int64, P]
@@ -223,6 +230,87 @@ def pcg(op: Operator, k: int, lmin: float, lmax: float, xi: float, b, x0=None, t
         raise ValueError("invalid PCG arguments")
     return x, dict(iters=int(st.iters), status=int(st.status), relres=float(st.relres),
                    n_apply=int(st.n_apply), n_dot=int(st.n_dot), seconds=dt)
+
+
+def _cols(V) -> np.ndarray:
+    """n x p array -> contiguous column-major storage (column j at j*n)."""
+    V = np.asarray(V, dtype=np.float64)
+    if V.ndim == 1:
+        V = V[:, None]
+    return np.ascontiguousarray(V.T)
+
+
+def lowrank_setup(op: Operator, V) -> np.ndarray:
+    """(V^T op-hat V)^{-1} for the spectral low-rank correction of section 3.1 (p x p)."""
+    Vc = _cols(V)
+    p = Vc.shape[0]
+    hinv = np.empty((p, p))
+    if lib().orc_lowrank_setup(C.byref(op._s), p, _p(Vc), _p(hinv)) != OK:
+        raise ValueError("V^T A V is singular")
+    return hinv
+
+
+def lowrank_apply_hat(op: Operator, k: int, lmin: float, lmax: float, xi: float, V, hinv, r) -> np.ndarray:
+    """(p_k(op-hat) + V (V^T op-hat V)^{-1} V^T) r in the scaled space."""
+    Vc = _cols(V)
+    r = _f64(r)
+    z = np.empty(op.n)
+    work = np.empty(3 * op.n)
+    h = np.ascontiguousarray(hinv, dtype=np.float64)
+    st = lib().orc_lowrank_apply(C.byref(op._s), k, lmin, lmax, xi, Vc.shape[0], _p(Vc), _p(h), _p(r), _p(z),
+                                 _p(work))
+    if st != OK:
+        raise ValueError("invalid polynomial parameters")
+    return z
+
+
+def pcg_lowrank(op: Operator, k: int, lmin: float, lmax: float, xi: float, V, b, x0=None, tol: float = 1e-8,
+                maxit: int = 1000, hinv=None):
+    """CG preconditioned by p_k + V (V^T A V)^{-1} V^T (V in the scaled space); returns (x, stats)."""
+    Vc = _cols(V)
+    h = lowrank_setup(op, V) if hinv is None else np.ascontiguousarray(hinv, dtype=np.float64)
+    b = _f64(b)
+    x = np.zeros(op.n) if x0 is None else _f64(x0).copy()
+    st = _PcgStats()
+    ret = lib().orc_pcg_lowrank(C.byref(op._s), k, lmin, lmax, xi, Vc.shape[0], _p(Vc), _p(h), _p(b), _p(x),
+                                tol, maxit, C.byref(st))
+    if ret == ERR_ARG:
+        raise ValueError("invalid PCG arguments")
+    return x, dict(iters=int(st.iters), status=int(st.status), relres=float(st.relres),
+                   n_apply=int(st.n_apply), n_dot=int(st.n_dot))
+
+
+def lanczos_basis(op: Operator, m: int):
+    """The Lanczos recurrence of orc_lanczos, keeping the basis: (alpha, beta, Q) with Q n x j."""
+    n = op.n
+    v = fmix32_start(n)
+    v = v / np.sqrt(v @ v)
+    vprev = np.zeros(n)
+    bprev = 0.0
+    a, b, Q = [], [], []
+    for _ in range(m):
+        Q.append(v.copy())
+        w = op.apply(v) - bprev * vprev
+        al = float(v @ w)
+        w = w - al * v
+        be = float(np.sqrt(w @ w))
+        a.append(al)
+        b.append(be)
+        if be == 0.0:
+            break
+        vprev, v = v, w / be
+        bprev = be
+    return np.array(a), np.array(b), np.array(Q).T
+
+
+def ritz_vectors(op: Operator, m: int, p: int):
+    """Ritz values and vectors of the p smallest Ritz values after m Lanczos steps (scaled space)."""
+    from scipy.linalg import eigh_tridiagonal
+
+    a, b, Q = lanczos_basis(op, m)
+    j = len(a)
+    w, S = eigh_tridiagonal(a, b[: j - 1]) if j > 1 else (a.copy(), np.ones((1, 1)))
+    return w[:p], Q @ S[:, :p]
 
 
 def fmix32_start(n: int) -> np.ndarray:

@@ -29,6 +29,11 @@
  *   orc_pcg          CG preconditioned by p_k(A), standard Hestenes-Stiefel
  *                    loop; counts operator applications and dot products as
  *                    reported in Table tab11.
+ *   orc_lowrank_setup, orc_lowrank_apply, orc_pcg_lowrank
+ *                    the spectral low-rank correction of section 3.1:
+ *                    P = P_0 + V (V^T A V)^{-1} V^T with P_0 = p_k(A), and CG
+ *                    preconditioned by it (one extra dot product per column
+ *                    of V per iteration, as in the rank-one rows of tab11).
  *   orc_lanczos      plain Lanczos tridiagonalisation (no
  *                    reorthogonalisation) used to estimate the extremal
  *                    eigenvalues alpha, beta that section 2 assumes known.
@@ -268,8 +273,103 @@ typedef struct {
  *     if ||r|| <= tol ||b|| : converged after it iterations
  *     z = P r;  rho' = r.z;  beta = rho' / rho;  p = z + beta p;  rho = rho'
  */
+/*
+ * Spectral low-rank correction (section 3.1).  V: n x p, column j at
+ * V[j*n .. j*n+n-1] (vectors of the scaled operator when op->dis is set).
+ * orc_lowrank_setup forms H = V^T A V with p operator applications and its
+ * inverse by Gauss-Jordan elimination with partial pivoting (p is small);
+ * Hinv: p x p row-major.  Returns ORC_ERR_ARG if H is singular.
+ */
+int orc_lowrank_setup(orc_op *op, int p, const double *V, double *Hinv)
+{
+    int64_t n = op->n;
+    if (p < 1 || p > 64) return ORC_ERR_ARG;
+    double *av = (double *)malloc(sizeof(double) * (size_t)n);
+    double *h = (double *)malloc(sizeof(double) * (size_t)p * 2 * p);
+    if (!av || !h) { free(av); free(h); return ORC_ERR_ARG; }
+    /* augmented [H | I] */
+    for (int j = 0; j < p; ++j) {
+        orc_op_apply(op, V + (size_t)j * n, av);
+        for (int i = 0; i < p; ++i) h[(size_t)i * 2 * p + j] = orc_dot(n, V + (size_t)i * n, av);
+    }
+    for (int i = 0; i < p; ++i)
+        for (int j = 0; j < p; ++j) h[(size_t)i * 2 * p + p + j] = (i == j) ? 1.0 : 0.0;
+    int ret = ORC_OK;
+    for (int c = 0; c < p && ret == ORC_OK; ++c) {
+        int piv = c;
+        for (int i = c + 1; i < p; ++i)
+            if (fabs(h[(size_t)i * 2 * p + c]) > fabs(h[(size_t)piv * 2 * p + c])) piv = i;
+        if (!(fabs(h[(size_t)piv * 2 * p + c]) > 0.0)) { ret = ORC_ERR_ARG; break; }
+        if (piv != c)
+            for (int j = 0; j < 2 * p; ++j) {
+                double t = h[(size_t)c * 2 * p + j];
+                h[(size_t)c * 2 * p + j] = h[(size_t)piv * 2 * p + j];
+                h[(size_t)piv * 2 * p + j] = t;
+            }
+        double d = h[(size_t)c * 2 * p + c];
+        for (int j = 0; j < 2 * p; ++j) h[(size_t)c * 2 * p + j] /= d;
+        for (int i = 0; i < p; ++i) {
+            if (i == c) continue;
+            double f = h[(size_t)i * 2 * p + c];
+            for (int j = 0; j < 2 * p; ++j) h[(size_t)i * 2 * p + j] -= f * h[(size_t)c * 2 * p + j];
+        }
+    }
+    if (ret == ORC_OK)
+        for (int i = 0; i < p; ++i)
+            for (int j = 0; j < p; ++j) Hinv[(size_t)i * p + j] = h[(size_t)i * 2 * p + p + j];
+    free(av);
+    free(h);
+    return ret;
+}
+
+/* z += V Hinv V^T r  (p dot products; counted in *ndot when given) */
+static void lowrank_add(int64_t n, int p, const double *V, const double *Hinv, const double *r, double *z,
+                        int64_t *ndot)
+{
+    double c[64], y[64];
+    for (int j = 0; j < p; ++j) c[j] = orc_dot(n, V + (size_t)j * n, r);
+    if (ndot) *ndot += p;
+    for (int i = 0; i < p; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < p; ++j) s += Hinv[(size_t)i * p + j] * c[j];
+        y[i] = s;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < p; ++j) s += V[(size_t)j * n + i] * y[j];
+        z[i] += s;
+    }
+}
+
+/* z = (p_k(A) + V (V^T A V)^{-1} V^T) r ; work: 3 n doubles */
+int orc_lowrank_apply(orc_op *op, int k, double lmin, double lmax, double xi, int p, const double *V,
+                      const double *Hinv, const double *r, double *z, double *work)
+{
+    int ret = orc_cheb_apply(op, k, lmin, lmax, xi, r, z, work);
+    if (ret != ORC_OK) return ret;
+    if (p > 0) lowrank_add(op->n, p, V, Hinv, r, z, NULL);
+    return ORC_OK;
+}
+
+static int pcg_core(orc_op *op, int k, double lmin, double lmax, double xi, int lr_p, const double *V,
+                    const double *Hinv, const double *b, double *x, double tol, int maxit, orc_pcg_stats *st);
+
 int orc_pcg(orc_op *op, int k, double lmin, double lmax, double xi, const double *b, double *x,
             double tol, int maxit, orc_pcg_stats *st)
+{
+    return pcg_core(op, k, lmin, lmax, xi, 0, NULL, NULL, b, x, tol, maxit, st);
+}
+
+/* CG preconditioned by P = p_k(A) + V Hinv V^T (Hinv from orc_lowrank_setup). */
+int orc_pcg_lowrank(orc_op *op, int k, double lmin, double lmax, double xi, int p, const double *V,
+                    const double *Hinv, const double *b, double *x, double tol, int maxit, orc_pcg_stats *st)
+{
+    if (p < 0 || p > 64) return ORC_ERR_ARG;
+    return pcg_core(op, k, lmin, lmax, xi, p, V, Hinv, b, x, tol, maxit, st);
+}
+
+static int pcg_core(orc_op *op, int k, double lmin, double lmax, double xi, int lr_p, const double *V,
+                    const double *Hinv, const double *b, double *x, double tol, int maxit, orc_pcg_stats *st)
 {
     int64_t n = op->n;
     memset(st, 0, sizeof(*st));
@@ -307,6 +407,7 @@ int orc_pcg(orc_op *op, int k, double lmin, double lmax, double xi, const double
     }
     ret = orc_cheb_apply(op, k, lmin, lmax, xi, r, z, cw);
     if (ret != ORC_OK) goto done;
+    if (lr_p > 0) lowrank_add(n, lr_p, V, Hinv, r, z, &st->n_dot);
     double rho = orc_dot(n, r, z);
     st->n_dot += 1;
     if (!(rho > 0.0) || !isfinite(rho)) { ret = ORC_BREAKDOWN; goto done; }
@@ -331,6 +432,7 @@ int orc_pcg(orc_op *op, int k, double lmin, double lmax, double xi, const double
         if (sqrt(rr) <= tol * bnorm) { ret = ORC_OK; break; }
         if (it == maxit) { ret = ORC_NOT_CONVERGED; break; }
         orc_cheb_apply(op, k, lmin, lmax, xi, r, z, cw);
+        if (lr_p > 0) lowrank_add(n, lr_p, V, Hinv, r, z, &st->n_dot);
         double rho_new = orc_dot(n, r, z);
         st->n_dot += 1;
         if (!(rho_new > 0.0) || !isfinite(rho_new)) { ret = ORC_BREAKDOWN; break; }
