@@ -142,6 +142,34 @@ PP_API pp_status pcg_solve(pp_op op, const double *b, double *x, double tol, int
                     double *relres);
 
 /*
+ * Spectral low-rank correction (section 3.1): the preconditioner becomes
+ *   P = p_k(A) + V (V^T A V)^{-1} V^T
+ * (A and V in the Jacobi-scaled space under PP_JACOBI; pp_apply then returns
+ * D^{-1/2} P D^{-1/2} r).  With V spanning approximate eigenvectors of the
+ * smallest eigenvalues, their eigenvalues of P A move from lambda_j p_k(lambda_j)
+ * to about 1 + lambda_j p_k(lambda_j) (eq. plusone), away from the origin.
+ * Each CG iteration then reads V twice and reduces p more values (the
+ * rank-one rows of Table tab11 use four dot products per iteration).
+ *
+ * pp_lowrank_set: V device n x p, column-major (column j at V + j n), copied;
+ *   p in [0, 8], p = 0 removes the correction.  V^T A V is formed with p
+ *   operator applications and inverted on the host; PP_ERR_ARG if it is
+ *   singular.  Synchronises.
+ * pp_lowrank_ritz: run `steps` (1..64) Lanczos steps from the start vector of
+ *   pp_estimate_bounds keeping the basis, and install as V the Ritz vectors of
+ *   the p smallest Ritz values (p in [1, min(8, steps)]); theta: HOST [p]
+ *   receives those Ritz values (may be NULL).  Uses steps x n doubles of
+ *   scratch during the call.  Synchronises.
+ * pp_lowrank_get: the rank in use (*p) and, when V is not NULL, a copy of the
+ *   vectors (device n x p).
+ * The persistent driver does not apply the correction: pcg_solve uses the
+ * stream-driven kernels while a correction is installed.
+ */
+PP_API pp_status pp_lowrank_set(pp_op op, int p, const double *V);
+PP_API pp_status pp_lowrank_ritz(pp_op op, int steps, int p, double *theta);
+PP_API pp_status pp_lowrank_get(pp_op op, int *p, double *V);
+
+/*
  * Estimate lambda_min, lambda_max of the (scaled) operator with `steps`
  * Lanczos steps (1..64) from the start vector v_i = fmix32(i)/2^32 - 0.5
  * (MurmurHash3 finaliser of the row index), no reorthogonalisation:
@@ -163,7 +191,7 @@ typedef struct {
     int32_t status;         /* pp_status of the last solve                          */
     double relres;          /* recursive ||r_hat|| / ||b_hat||                       */
     int64_t op_applies;     /* operator applications in the last solve              */
-    int64_t dots;           /* dot products (global reductions), excluding ||b||    */
+    int64_t dots;           /* values reduced over the grid (dot products), not ||b|| */
     double cheb_ms;         /* summed device time of the polynomial steps (events), */
                             /* valid only with PP_OPT_TIMING = 1                    */
     int64_t cheb_steps;     /* polynomial steps covered by cheb_ms                  */

@@ -28,6 +28,7 @@ ABI_FUNCTIONS = (
     "pp_batch_set_option", "pp_batch_get_stats", "pp_destroy_batch", "pp_mlp_create", "pp_mlp_destroy",
     "pp_mlp_num_params", "pp_mlp_get_params", "pp_mlp_set_params", "pp_mlp_set_normalization",
     "pp_mlp_forward", "pp_mlp_loss_grad", "pp_mlp_train_step", "pp_features", "pp_predict_bounds",
+    "pp_lowrank_set", "pp_lowrank_ritz", "pp_lowrank_get",
 )
 
 
@@ -105,6 +106,9 @@ def lib():
         L.pp_mlp_loss_grad.argtypes = [P, I32, P, P, P, C.POINTER(D)]
         L.pp_mlp_train_step.argtypes = [P, I32, P, P, F32, C.POINTER(D)]
         L.pp_features.argtypes = [P, I32, P]
+        L.pp_lowrank_set.argtypes = [P, I32, P]
+        L.pp_lowrank_ritz.argtypes = [P, I32, I32, P]
+        L.pp_lowrank_get.argtypes = [P, C.POINTER(I32), P]
         L.pp_predict_bounds.argtypes = [P, P, I32, C.POINTER(D), C.POINTER(D), C.POINTER(D), C.POINTER(I32)]
         for f in ABI_FUNCTIONS:
             if f not in ("pp_destroy", "pp_status_str", "pp_last_error", "pp_destroy_batch", "pp_mlp_destroy"):
@@ -202,6 +206,27 @@ def pp_estimate_bounds(op, steps=20):
     lo, hi = C.c_double(), C.c_double()
     _check(lib().pp_estimate_bounds(op, int(steps), C.byref(lo), C.byref(hi)))
     return lo.value, hi.value
+
+
+def pp_lowrank_set(op, p, V=None):
+    """V: device tensor [p][n] (row j = vector j, i.e. column-major n x p), or None with p = 0."""
+    return _check(lib().pp_lowrank_set(op, int(p), _ptr(V)))
+
+
+def pp_lowrank_ritz(op, steps, p):
+    """Installs the Ritz vectors of the p smallest Ritz values; returns those Ritz values."""
+    import numpy as np
+
+    th = np.zeros(int(p))
+    _check(lib().pp_lowrank_ritz(op, int(steps), int(p), _hptr(th)))
+    return th
+
+
+def pp_lowrank_get(op, V=None):
+    """Rank in use; copies the vectors into V (device [p][n]) when given."""
+    p = C.c_int()
+    _check(lib().pp_lowrank_get(op, C.byref(p), _ptr(V)))
+    return p.value
 
 
 def pp_operator_apply(op, x, y):

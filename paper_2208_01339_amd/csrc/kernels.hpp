@@ -38,6 +38,7 @@ constexpr int WAVE = 64;
 constexpr int BLOCK = 256;
 constexpr int WPB = BLOCK / WAVE;  // waves per workgroup
 constexpr int LZ_MAX = 64;         // max Lanczos steps
+constexpr int LR_MAX = 8;          // max rank of the low-rank correction
 
 // Device-resident solver state: CG scalars live here, never on the host.
 struct State {
@@ -52,6 +53,10 @@ struct State {
     double lz_alpha[LZ_MAX];
     double lz_beta[LZ_MAX];
     double scratch[4];
+    double lr_c[LR_MAX];  // low-rank correction: V^T r of the current residual
+    double lr_y[LR_MAX];  // (V^T A V)^{-1} lr_c; r.z gains lr_c . lr_y
+    int32_t lr_p;         // rank in use for this solve (0 = no correction)
+    int32_t lr_pad;
     int32_t it;      // iterations done
     int32_t maxit;
     int32_t done;    // 1 once converged / failed / maxit: later kernels return at entry
@@ -162,6 +167,7 @@ __device__ inline void finalize(State *st, int fin, int idx, double s)
         else if (st->maxit <= 0) { st->done = 1; st->status = 1; }
         break;
     case FIN_RHO0:
+        for (int j = 0; j < st->lr_p; ++j) s += st->lr_c[j] * st->lr_y[j];
         st->rho = s;
         if (!finite_pos(s)) { st->done = 1; st->status = 2; }
         break;
@@ -178,6 +184,7 @@ __device__ inline void finalize(State *st, int fin, int idx, double s)
         else if (st->it >= st->maxit) { st->done = 1; st->status = 1; }
         break;
     case FIN_RHO: {
+        for (int j = 0; j < st->lr_p; ++j) s += st->lr_c[j] * st->lr_y[j];
         if (!finite_pos(s)) { st->done = 1; st->status = 2; break; }
         st->beta = s / st->rho;
         st->rho = s;
@@ -609,6 +616,7 @@ static __global__ __launch_bounds__(BLOCK) void k_state_init(State *st, double t
         st->status = 1;
         st->zero_b = 0;
         st->ticket = 0u;
+        st->lr_p = 0;
     }
 }
 

@@ -42,7 +42,11 @@ struct pp_op_s {
     double *xh = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr, *bh = nullptr;
     double *sA = nullptr, *sB = nullptr;
     float *r32 = nullptr, *sA32 = nullptr, *sB32 = nullptr;
-    double *partials = nullptr;
+    double *partials = nullptr;  // (1 + LR_MAX) * 8192 doubles
+    // spectral low-rank correction: V (n x lr_p, column-major), (V^T A V)^{-1}
+    int lr_p = 0;
+    double *lr_v = nullptr;
+    double *lr_hinv = nullptr;
     double *coef_d = nullptr;  // [k][4] step coefficients for the persistent driver
     int coef_k = -1;           // degree the device coefficients were uploaded for
     std::vector<double> coef_h;
@@ -115,6 +119,7 @@ struct pp_op_s {
         ppc::dfree(xh); ppc::dfree(r); ppc::dfree(p); ppc::dfree(q); ppc::dfree(z); ppc::dfree(bh); ppc::dfree(sA); ppc::dfree(sB);
         ppc::dfree(r32); ppc::dfree(sA32); ppc::dfree(sB32);
         ppc::dfree(partials); ppc::dfree(coef_d); ppc::dfree(st);
+        ppc::dfree(lr_v); ppc::dfree(lr_hinv);
         if (hst) (void)hipHostFree(hst);
         if (hflag) (void)hipHostFree(hflag);
         hst = nullptr;

@@ -16,6 +16,7 @@
 #include "kernels.hpp"
 #include "op.hpp"
 #include "dia_plan.hpp"
+#include "lowrank.hpp"
 #include "persistent.hpp"
 #include "sym_eig.hpp"
 
@@ -265,7 +266,7 @@ pp_status build_operator(pp_op_s *op, const int64_t *rp, const int32_t *col, con
             op->sA32 = dalloc<float>(n);
             op->sB32 = dalloc<float>(n);
         }
-        op->partials = dalloc<double>(2 * 8192);
+        op->partials = dalloc<double>((size_t)(1 + ppk::LR_MAX) * 8192);
         op->st = dalloc<ppk::State>(1);
         HIPCHK(hipMemsetAsync(op->st, 0, sizeof(ppk::State), op->stream));
         HIPCHK(hipHostMalloc((void **)&op->hst, sizeof(ppk::State), hipHostMallocDefault));
@@ -508,6 +509,29 @@ void enqueue_trace_f64(pp_op_s *op, const double *x, bool live_state = true)
                        op->cview(false), x, op->tw, (const ppk::State *)(live_state ? op->st : nullptr));
 }
 
+// p = z (+ V y) + beta p
+void enqueue_p(pp_op_s *op, bool first)
+{
+    const int ge = op->grid_elems(op->n);
+    if (op->lr_p > 0)
+        hipLaunchKernelGGL(ppk::k_p_lr, dim3(ge), dim3(BLOCK), 0, op->stream, op->n, op->lr_p,
+                           (const double *)op->lr_v, op->n, (const double *)op->z, op->p, (const ppk::State *)op->st,
+                           first ? 1 : 0);
+    else
+        hipLaunchKernelGGL(ppk::k_p, dim3(ge), dim3(BLOCK), 0, op->stream, op->n, (const double *)op->z, op->p,
+                           (const ppk::State *)op->st, first ? 1 : 0);
+}
+
+// c = V^T (s .* r) and y = Hinv c into the state (s = scale or 1)
+void enqueue_lr_c(pp_op_s *op, const double *r, const double *scale)
+{
+    const int ge = op->grid_elems(op->n), lp = op->lr_p;
+    hipLaunchKernelGGL(ppk::k_lr_dots, dim3(ge), dim3(BLOCK), 0, op->stream, op->n, lp, (const double *)op->lr_v,
+                       op->n, r, scale, op->partials, (const ppk::State *)op->st);
+    hipLaunchKernelGGL(ppk::k_fin_lr, dim3(1), dim3(BLOCK), 0, op->stream, (const double *)op->partials, ge, lp,
+                       op->st, (int)ppk::LR_FIN_C, lp, (const double *)op->lr_hinv);
+}
+
 void enqueue_iteration(pp_op_s *op, hipEvent_t e0, hipEvent_t e1)
 {
     const int gs = op->grid_slices(), ge = op->grid_elems(op->n);
@@ -519,14 +543,22 @@ void enqueue_iteration(pp_op_s *op, hipEvent_t e0, hipEvent_t e1)
         hipLaunchKernelGGL(ppk::k_pq<false>, dim3(gs), dim3(BLOCK), 0, op->stream, op->view(false), op->p,
                            (const double *)nullptr, op->q, op->partials, op->st, op->ntload);
     enqueue_fin(op, gs, ppk::FIN_GAMMA);
-    hipLaunchKernelGGL(ppk::k_xr, dim3(ge), dim3(BLOCK), 0, op->stream, op->n, op->p, op->q, op->xh, op->r,
-                       op->partials, op->st);
-    enqueue_fin(op, ge, ppk::FIN_RR);
+    const int lp = op->lr_p;
+    if (lp > 0) {
+        // r update with c = V^T r in the same pass; y = Hinv c in the finaliser
+        hipLaunchKernelGGL(ppk::k_xr_lr, dim3(ge), dim3(BLOCK), 0, op->stream, op->n, lp, (const double *)op->lr_v,
+                           op->n, (const double *)op->p, (const double *)op->q, op->xh, op->r, op->partials, op->st);
+        hipLaunchKernelGGL(ppk::k_fin_lr, dim3(1), dim3(BLOCK), 0, op->stream, (const double *)op->partials, ge,
+                           1 + lp, op->st, (int)ppk::LR_FIN_RR, lp, (const double *)op->lr_hinv);
+    } else {
+        hipLaunchKernelGGL(ppk::k_xr, dim3(ge), dim3(BLOCK), 0, op->stream, op->n, op->p, op->q, op->xh, op->r,
+                           op->partials, op->st);
+        enqueue_fin(op, ge, ppk::FIN_RR);
+    }
     if (e0) (void)hipEventRecord(e0, op->stream);
     enqueue_poly(op, op->r, op->z, ppk::FIN_RHO, false);
     if (e1) (void)hipEventRecord(e1, op->stream);
-    hipLaunchKernelGGL(ppk::k_p, dim3(ge), dim3(BLOCK), 0, op->stream, op->n, op->z, op->p,
-                       (const ppk::State *)op->st, 0);
+    enqueue_p(op, false);
 }
 
 hipEvent_t timing_event(pp_op_s *op, size_t i)
@@ -771,6 +803,12 @@ pp_status pp_apply(pp_op op, const double *r, double *z)
             rr = op->bh;
         }
         enqueue_poly(op, rr, z, ppk::FIN_NONE, op->dis != nullptr);
+        if (op->lr_p > 0) {
+            // z += D^{-1/2} V Hinv V^T D^{-1/2} r
+            enqueue_lr_c(op, rr, nullptr);
+            hipLaunchKernelGGL(ppk::k_lr_axpy, dim3(op->grid_elems(n)), dim3(BLOCK), 0, op->stream, n, op->lr_p,
+                               (const double *)op->lr_v, n, (const double *)op->dis, z, (const ppk::State *)op->st);
+        }
         HIPCHK(hipGetLastError());
     } catch (HipError &e) {
         return hip_fail(e);
@@ -793,7 +831,7 @@ pp_status pcg_solve(pp_op op, const double *b, double *x, double tol, int maxit,
         // persistent driver on request only: its grid-wide barriers cost more
         // than kernel boundaries on this chip at every size measured (each
         // barrier serialises one same-address atomic per workgroup)
-        const bool want_persist = op->driver == 1;
+        const bool want_persist = op->driver == 1 && op->lr_p == 0;
         bool persisted = want_persist && persistent_solve(op, b, x, tol, maxit);
         size_t ev_i = 0;
         if (!persisted) {
@@ -810,13 +848,13 @@ pp_status pcg_solve(pp_op op, const double *b, double *x, double tol, int maxit,
                                    (const double *)op->xh, (const double *)nullptr, (const double *)op->bh, op->r,
                                    op->partials, op->st, op->ntload);
             enqueue_fin(op, gs, ppk::FIN_RR0);
+            if (op->lr_p > 0) enqueue_lr_c(op, op->r, nullptr);
             hipEvent_t e0 = op->timing ? timing_event(op, ev_i++) : nullptr;
             hipEvent_t e1 = op->timing ? timing_event(op, ev_i++) : nullptr;
             if (e0) HIPCHK(hipEventRecord(e0, op->stream));
             enqueue_poly(op, op->r, op->z, ppk::FIN_RHO0, false);
             if (e1) HIPCHK(hipEventRecord(e1, op->stream));
-            hipLaunchKernelGGL(ppk::k_p, dim3(ge), dim3(BLOCK), 0, op->stream, n, (const double *)op->z, op->p,
-                               (const ppk::State *)op->st, 1);
+            enqueue_p(op, true);
             HIPCHK(hipGetLastError());
 
             int chunk = op->chunk;
@@ -861,7 +899,8 @@ pp_status pcg_solve(pp_op op, const double *b, double *x, double tol, int maxit,
         // except after the last iteration, the preconditioner (k)
         const int64_t polys = it > 0 ? it : 1;
         op->stats.op_applies = s.zero_b ? 0 : 1 + (int64_t)op->k * polys + it;
-        op->stats.dots = s.zero_b ? 0 : 1 + 3LL * it;
+        // and, with a rank-p correction, p more values reduced at the start and in every iteration
+        op->stats.dots = s.zero_b ? 0 : 1 + 3LL * it + (int64_t)op->lr_p * (1 + it);
         float ms = 0;
         HIPCHK(hipEventElapsedTime(&ms, op->solve_ev[0], op->solve_ev[1]));
         op->stats.solve_ms = ms;
@@ -884,6 +923,197 @@ pp_status pcg_solve(pp_op op, const double *b, double *x, double tol, int maxit,
     } catch (HipError &e) {
         return hip_fail(e);
     }
+}
+
+namespace {
+
+// H = V^T A-hat V (p operator applications), inverted on the host by
+// Gauss-Jordan elimination with partial pivoting; false if H is singular or
+// not finite.
+bool lowrank_hinv(pp_op_s *op, int p, const double *V, std::vector<double> &hinv)
+{
+    const int64_t n = op->n;
+    const int gs = op->grid_slices(), ge = op->grid_elems(n);
+    double *out = dalloc<double>(ppk::LR_MAX);
+    struct Free {
+        double *&p;
+        ~Free() { dfree(p); }
+    } f{out};
+    std::vector<double> h((size_t)p * 2 * p, 0.0), col(p);
+    for (int j = 0; j < p; ++j) {
+        const double *vj = V + (int64_t)j * n;
+        enqueue_trace_f64(op, vj, false);
+        if (op->schur())
+            hipLaunchKernelGGL((ppk::k_spmv<double, true>), dim3(gs), dim3(BLOCK), 0, op->stream, op->view(false), vj,
+                               (const double *)op->tw, op->q, op->ntload);
+        else
+            hipLaunchKernelGGL((ppk::k_spmv<double, false>), dim3(gs), dim3(BLOCK), 0, op->stream, op->view(false),
+                               vj, (const double *)nullptr, op->q, op->ntload);
+        hipLaunchKernelGGL(ppk::k_lr_dots, dim3(ge), dim3(BLOCK), 0, op->stream, n, p, V, n, (const double *)op->q,
+                           (const double *)nullptr, op->partials, (const ppk::State *)nullptr);
+        hipLaunchKernelGGL(ppk::k_colsum, dim3(1), dim3(BLOCK), 0, op->stream, (const double *)op->partials, ge, p,
+                           out);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(col.data(), out, sizeof(double) * p, hipMemcpyDeviceToHost, op->stream));
+        HIPCHK(hipStreamSynchronize(op->stream));
+        for (int i = 0; i < p; ++i) h[(size_t)i * 2 * p + j] = col[i];  // H_ij = V_i^T A V_j
+    }
+    for (int i = 0; i < p; ++i) h[(size_t)i * 2 * p + p + i] = 1.0;
+    for (int c = 0; c < p; ++c) {
+        int piv = c;
+        for (int i = c + 1; i < p; ++i)
+            if (std::fabs(h[(size_t)i * 2 * p + c]) > std::fabs(h[(size_t)piv * 2 * p + c])) piv = i;
+        const double d = h[(size_t)piv * 2 * p + c];
+        if (!(std::fabs(d) > 0.0) || !std::isfinite(d)) return false;
+        if (piv != c)
+            for (int j = 0; j < 2 * p; ++j) std::swap(h[(size_t)c * 2 * p + j], h[(size_t)piv * 2 * p + j]);
+        for (int j = 0; j < 2 * p; ++j) h[(size_t)c * 2 * p + j] /= d;
+        for (int i = 0; i < p; ++i) {
+            if (i == c) continue;
+            const double fct = h[(size_t)i * 2 * p + c];
+            for (int j = 0; j < 2 * p; ++j) h[(size_t)i * 2 * p + j] -= fct * h[(size_t)c * 2 * p + j];
+        }
+    }
+    hinv.assign((size_t)p * p, 0.0);
+    for (int i = 0; i < p; ++i)
+        for (int j = 0; j < p; ++j) {
+            hinv[(size_t)i * p + j] = h[(size_t)i * 2 * p + p + j];
+            if (!std::isfinite(hinv[(size_t)i * p + j])) return false;
+        }
+    return true;
+}
+
+}  // namespace
+
+pp_status pp_lowrank_set(pp_op op, int p, const double *V)
+{
+    if (!op) return fail(PP_ERR_ARG, "NULL operator");
+    if (p < 0 || p > ppk::LR_MAX) return fail(PP_ERR_ARG, "rank must be in [0, 8]");
+    if (p > 0 && !V) return fail(PP_ERR_ARG, "V is NULL");
+    try {
+        if (p == 0) {
+            op->lr_p = 0;
+            return PP_OK;
+        }
+        const int64_t n = op->n;
+        if (!op->lr_v) op->lr_v = dalloc<double>((size_t)ppk::LR_MAX * n);
+        if (!op->lr_hinv) op->lr_hinv = dalloc<double>((size_t)ppk::LR_MAX * ppk::LR_MAX);
+        if (V != op->lr_v)
+            HIPCHK(hipMemcpyAsync(op->lr_v, V, sizeof(double) * (size_t)p * n, hipMemcpyDeviceToDevice, op->stream));
+        std::vector<double> hinv;
+        if (!lowrank_hinv(op, p, op->lr_v, hinv)) {
+            op->lr_p = 0;
+            return fail(PP_ERR_ARG, "V^T A V is singular or not finite");
+        }
+        HIPCHK(hipMemcpyAsync(op->lr_hinv, hinv.data(), sizeof(double) * hinv.size(), hipMemcpyHostToDevice,
+                              op->stream));
+        HIPCHK(hipStreamSynchronize(op->stream));
+        op->lr_p = p;
+    } catch (std::bad_alloc &) {
+        return fail(PP_ERR_OOM, "device allocation failed");
+    } catch (HipError &e) {
+        return hip_fail(e);
+    }
+    return PP_OK;
+}
+
+pp_status pp_lowrank_ritz(pp_op op, int steps, int p, double *theta)
+{
+    if (!op) return fail(PP_ERR_ARG, "NULL operator");
+    if (steps < 1 || steps > ppk::LZ_MAX) return fail(PP_ERR_ARG, "steps must be in [1, 64]");
+    if (p < 1 || p > ppk::LR_MAX || p > steps) return fail(PP_ERR_ARG, "rank must be in [1, min(8, steps)]");
+    double *Q = nullptr, *S = nullptr;
+    struct Free {
+        double *&a, *&b;
+        ~Free() { dfree(a); dfree(b); }
+    } f{Q, S};
+    try {
+        const int64_t n = op->n;
+        const int gs = op->grid_slices(), ge = op->grid_elems(n);
+        Q = dalloc<double>((size_t)steps * n);
+        double *v = op->sA, *vprev = op->sB, *w = op->q;
+        // the Lanczos recurrence of pp_estimate_bounds, keeping every basis vector
+        hipLaunchKernelGGL(ppk::k_state_init, dim3(1), dim3(64), 0, op->stream, op->st, 0.0, 0);
+        hipLaunchKernelGGL(ppk::k_lz_start, dim3(ge), dim3(BLOCK), 0, op->stream, n, v, op->partials, op->st);
+        enqueue_fin(op, ge, ppk::FIN_LZ_NORM0);
+        hipLaunchKernelGGL(ppk::k_lz_norm, dim3(ge), dim3(BLOCK), 0, op->stream, n, v, (const ppk::State *)op->st);
+        hipLaunchKernelGGL((ppk::k_scale<double, double>), dim3(ge), dim3(BLOCK), 0, op->stream, n,
+                           (const double *)v, (const double *)nullptr, 0.0, vprev);
+        for (int j = 0; j < steps; ++j) {
+            HIPCHK(hipMemcpyAsync(Q + (size_t)j * n, v, sizeof(double) * n, hipMemcpyDeviceToDevice, op->stream));
+            enqueue_trace_f64(op, v);
+            if (op->schur())
+                hipLaunchKernelGGL(ppk::k_lz_apply<true>, dim3(gs), dim3(BLOCK), 0, op->stream, op->view(false),
+                                   (const double *)v, (const double *)op->tw, (const double *)vprev, w,
+                                   op->partials, op->st, j, op->ntload);
+            else
+                hipLaunchKernelGGL(ppk::k_lz_apply<false>, dim3(gs), dim3(BLOCK), 0, op->stream, op->view(false),
+                                   (const double *)v, (const double *)nullptr, (const double *)vprev, w,
+                                   op->partials, op->st, j, op->ntload);
+            enqueue_fin(op, gs, ppk::FIN_LZ_ALPHA, j);
+            hipLaunchKernelGGL(ppk::k_lz_orth, dim3(ge), dim3(BLOCK), 0, op->stream, n, (const double *)v, w,
+                               op->partials, op->st, j);
+            enqueue_fin(op, ge, ppk::FIN_LZ_BETA, j);
+            if (j + 1 < steps)
+                hipLaunchKernelGGL(ppk::k_lz_next, dim3(ge), dim3(BLOCK), 0, op->stream, n, vprev, v,
+                                   (const double *)w, (const ppk::State *)op->st, j);
+        }
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(op->hst, op->st, sizeof(ppk::State), hipMemcpyDeviceToHost, op->stream));
+        HIPCHK(hipStreamSynchronize(op->stream));
+        int m = steps;
+        for (int j = 0; j < steps; ++j) {
+            if (!std::isfinite(op->hst->lz_alpha[j]) || !std::isfinite(op->hst->lz_beta[j]))
+                return fail(PP_ERR_ARG, "non-finite value in Lanczos (operator not finite?)");
+            if (op->hst->lz_beta[j] == 0.0) { m = j + 1; break; }
+        }
+        if (p > m) return fail(PP_ERR_ARG, "the Krylov space is smaller than the rank asked for");
+        std::vector<double> T((size_t)m * m, 0.0), wv, E;
+        for (int j = 0; j < m; ++j) {
+            T[(size_t)j * m + j] = op->hst->lz_alpha[j];
+            if (j + 1 < m) {
+                T[(size_t)j * m + j + 1] = op->hst->lz_beta[j];
+                T[(size_t)(j + 1) * m + j] = op->hst->lz_beta[j];
+            }
+        }
+        ppeig::jacobi_eig(m, T, wv, E);
+        std::vector<int> idx(m);
+        for (int i = 0; i < m; ++i) idx[i] = i;
+        std::sort(idx.begin(), idx.end(), [&](int a, int b) { return wv[a] < wv[b]; });
+        std::vector<double> Sh((size_t)m * p);
+        for (int j = 0; j < m; ++j)
+            for (int c = 0; c < p; ++c) Sh[(size_t)j * p + c] = E[(size_t)j * m + idx[c]];
+        if (theta)
+            for (int c = 0; c < p; ++c) theta[c] = wv[idx[c]];
+        S = dalloc<double>(Sh.size());
+        HIPCHK(hipMemcpyAsync(S, Sh.data(), sizeof(double) * Sh.size(), hipMemcpyHostToDevice, op->stream));
+        if (!op->lr_v) op->lr_v = dalloc<double>((size_t)ppk::LR_MAX * n);
+        if (!op->lr_hinv) op->lr_hinv = dalloc<double>((size_t)ppk::LR_MAX * ppk::LR_MAX);
+        hipLaunchKernelGGL(ppk::k_lr_combine, dim3(ge), dim3(BLOCK), 0, op->stream, n, m, p, (const double *)Q,
+                           (const double *)S, op->lr_v);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(op->stream));  // Sh leaves scope
+    } catch (std::bad_alloc &) {
+        return fail(PP_ERR_OOM, "device allocation failed");
+    } catch (HipError &e) {
+        return hip_fail(e);
+    }
+    return pp_lowrank_set(op, p, op->lr_v);
+}
+
+pp_status pp_lowrank_get(pp_op op, int *p, double *V)
+{
+    if (!op || !p) return fail(PP_ERR_ARG, "NULL argument");
+    *p = op->lr_p;
+    if (V && op->lr_p > 0) {
+        try {
+            HIPCHK(hipMemcpyAsync(V, op->lr_v, sizeof(double) * (size_t)op->lr_p * op->n, hipMemcpyDeviceToDevice,
+                                  op->stream));
+        } catch (HipError &e) {
+            return hip_fail(e);
+        }
+    }
+    return PP_OK;
 }
 
 pp_status pp_estimate_bounds(pp_op op, int steps, double *lambda_min, double *lambda_max)

@@ -1,0 +1,167 @@
+"""GPU parity of the spectral low-rank correction (section 3.1).
+
+The same V (Ritz vectors computed by the oracle, in the scaled space) goes to
+both sides.  pp_apply with the correction: relative error <= 1e-12 against
+the oracle's D^{-1/2} (p_k(A-hat) + V (V^T A-hat V)^{-1} V^T) D^{-1/2} r.
+PCG: equal iteration count -> relative solution error <= 1e-10; tol-driven
+iteration counts within +-2.  The library's own Ritz vectors: Ritz values
+within 1e-7 lambda_max of the oracle's (Weyl), residuals of the same size.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2208_01339_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2208_01339_amd import binding
+
+    binding.lib()
+    return binding
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+CASES = {
+    "poisson20": (lambda: (W.poisson3d(20), None), False),
+    "hetero21_jac": (lambda: (W.hetero_diffusion(21, 2.0, 5), None), True),
+    "dfn_small_jac": (lambda: (None, W.dfn_schur(n_frac=13, G=16, n_traces=30, L_lo=3, L_hi=12, seed=2)), True),
+}
+
+
+def setup_case(B, name, p, sliced=False):
+    build, jac = CASES[name]
+    a, s = build()
+    flags = (B.PP_JACOBI if jac else 0) | (B.PP_SLICED if sliced else 0)
+    if s is not None:
+        op = B.Operator(schur=s, flags=flags)
+        orc = O.Operator(s.a, s.c, s.m, jacobi=jac)
+    else:
+        op = B.Operator(a=a, flags=flags)
+        orc = O.Operator(a, jacobi=jac)
+    lmin, lmax = O.lanczos_bounds(orc, 20)
+    _, V = O.ritz_vectors(orc, 40, p)
+    B.pp_lowrank_set(op.handle, p, dev(V.T))
+    return op, orc, V, lmin, lmax
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("p,k,xi", [(1, 0, 0.0), (1, 10, 1e-3), (3, 4, 0.0), (8, 20, 1e-2)])
+def test_lowrank_apply(B, name, p, k, xi):
+    op, orc, V, lmin, lmax = setup_case(B, name, p)
+    B.pp_setup(op.handle, k, lmin, lmax, xi)
+    assert B.pp_lowrank_get(op.handle) == p
+    r = W.rhs_uniform(orc.n, 7)
+    z = torch.empty(orc.n, dtype=torch.float64, device="cuda")
+    B.pp_apply(op.handle, dev(r), z)
+    hinv = O.lowrank_setup(orc, V)
+    if orc.dis is None:
+        ref = O.lowrank_apply_hat(orc, k, lmin, lmax, xi, V, hinv, r)
+    else:
+        ref = orc.dis * O.lowrank_apply_hat(orc, k, lmin, lmax, xi, V, hinv, orc.dis * r)
+    got = host(z)
+    assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
+    op.close()
+
+
+@pytest.mark.parametrize("sliced", [False, True], ids=["diag", "sliced"])
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("p,k,xi", [(1, 10, 1e-3), (4, 6, 1e-2)])
+def test_lowrank_pcg(B, name, p, k, xi, sliced):
+    op, orc, V, lmin, lmax = setup_case(B, name, p, sliced)
+    B.pp_setup(op.handle, k, lmin, lmax, xi)
+    n = orc.n
+    b = W.rhs_uniform(n, 1)
+    xo, sto = O.pcg_lowrank(orc, k, lmin, lmax, xi, V, b, tol=1e-8, maxit=3000)
+    assert sto["status"] == O.OK
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    s, it, rel = B.pcg_solve(op.handle, dev(b), x, 1e-8, 3000)
+    assert s == B.PP_OK and abs(it - sto["iters"]) <= 2
+    st = B.pp_get_stats(op.handle)
+    assert st["dots"] == 1 + 3 * it + p * (1 + it)
+    assert st["op_applies"] == 1 + k * it + it
+    # equal iteration count
+    x.zero_()
+    s, it2, rel2 = B.pcg_solve(op.handle, dev(b), x, 0.0, sto["iters"])
+    assert it2 == sto["iters"]
+    got = host(x)
+    assert np.linalg.norm(got - xo) <= 1e-10 * np.linalg.norm(xo)
+    assert abs(rel2 - sto["relres"]) <= 1e-6 * sto["relres"] + 1e-14
+    op.close()
+
+
+def test_lowrank_ritz_on_gpu(B):
+    a = W.hetero_diffusion(18, 2.0, 7)
+    orc = O.Operator(a, jacobi=True)
+    op = B.Operator(a=a, flags=B.PP_JACOBI)
+    p, m = 4, 40
+    th = B.pp_lowrank_ritz(op.handle, m, p)
+    th_o, V_o = O.ritz_vectors(orc, m, p)
+    lmax = O.lanczos_bounds(orc, 20)[1]
+    assert np.all(np.abs(th - th_o) <= 1e-7 * lmax), (th, th_o)
+    assert B.pp_lowrank_get(op.handle) == p
+    Vd = torch.empty(p, a.n_rows, dtype=torch.float64, device="cuda")
+    B.pp_lowrank_get(op.handle, Vd)
+    V = host(Vd).T
+    for j in range(p):
+        res_g = np.linalg.norm(orc.apply(V[:, j]) - th[j] * V[:, j]) / np.linalg.norm(V[:, j])
+        res_o = np.linalg.norm(orc.apply(V_o[:, j]) - th_o[j] * V_o[:, j]) / np.linalg.norm(V_o[:, j])
+        assert res_g <= 10 * res_o + 1e-8, (j, res_g, res_o)
+    # and the solve with these vectors converges
+    lmin, lmax = O.lanczos_bounds(orc, 20)
+    B.pp_setup(op.handle, 10, lmin, lmax, 1e-3)
+    b = W.rhs_uniform(a.n_rows, 3)
+    x = torch.zeros(a.n_rows, dtype=torch.float64, device="cuda")
+    s, it, rel = B.pcg_solve(op.handle, dev(b), x, 1e-8, 2000)
+    assert s == B.PP_OK and rel <= 1e-8
+    op.close()
+
+
+def test_lowrank_clear_errors_and_driver(B):
+    a = W.hetero_diffusion(10, 1.0, 2)
+    orc = O.Operator(a, jacobi=True)
+    op = B.Operator(a=a, flags=B.PP_JACOBI)
+    lmin, lmax = O.lanczos_bounds(orc, 20)
+    B.pp_setup(op.handle, 8, lmin, lmax, 0.0)
+    b = dev(W.rhs_uniform(a.n_rows, 4))
+    x = torch.zeros(a.n_rows, dtype=torch.float64, device="cuda")
+    s0, it0, _ = B.pcg_solve(op.handle, b, x, 1e-9, 500)
+    x0 = host(x).copy()
+    _, V = O.ritz_vectors(orc, 30, 2)
+    B.pp_lowrank_set(op.handle, 2, dev(V.T))
+    # the persistent driver does not apply the correction: the stream driver runs
+    B.pp_set_option(op.handle, B.PP_OPT_DRIVER, 1)
+    x.zero_()
+    s, it, _ = B.pcg_solve(op.handle, b, x, 1e-9, 500)
+    assert s == B.PP_OK and B.pp_get_stats(op.handle)["driver"] == 0
+    # rank 0 removes it: bitwise the plain solve again
+    B.pp_lowrank_set(op.handle, 0)
+    B.pp_set_option(op.handle, B.PP_OPT_DRIVER, 0)
+    x.zero_()
+    s, it1, _ = B.pcg_solve(op.handle, b, x, 1e-9, 500)
+    assert it1 == it0 and np.array_equal(host(x), x0)
+    assert B.pp_lowrank_get(op.handle) == 0
+    # invalid: rank > 8, singular V^T A V (repeated column)
+    with pytest.raises(B.PPError):
+        B.pp_lowrank_set(op.handle, 9, dev(np.zeros((9, a.n_rows))))
+    with pytest.raises(B.PPError) as e:
+        B.pp_lowrank_set(op.handle, 2, dev(np.stack([V[:, 0], V[:, 0]])))
+    assert e.value.status == B.PP_ERR_ARG
+    assert B.pp_lowrank_get(op.handle) == 0
+    with pytest.raises(B.PPError):
+        B.pp_lowrank_ritz(op.handle, 3, 5)
+    op.close()
