@@ -25,7 +25,11 @@ The JSON line also carries:
                 iterations at k = 20 (105 operator applications with their
                 vector work), scaled per operator application to the
                 applications of the headline GPU solve;
-  mixed         the same solve with the polynomial in FP32 (PP_MIXED).
+  mixed         the same solve with the polynomial in FP32 (PP_MIXED);
+  lowrank       the same solve, the DFN one and the Poisson 32^3 one (k = 10)
+                with the spectral low-rank correction of section 3.1 from
+                Ritz vectors of 64 Lanczos steps, ranks 1 and 4 (3 for
+                Poisson), xi in {0, 1e-2}, against no correction.
 """
 import argparse
 import json
@@ -131,8 +135,10 @@ def run_dfn(args, B, W, torch, dev):
                step_frac_hbm=bps / (step_us * 1e-6) / 1e9 / HBM_PEAK_GBS, create_s=t_create,
                nnz_stored=st["nnz_stored"], diagonals=st["diagonals"],
                stored_bytes_per_step=int(sbps), stored_gbs=sbps / (step_us * 1e-6) / 1e9)
-    B.pp_destroy(h)
     log("dfn k=%d: %.3f s/solve, iters %d, step %.1f us (%.0f GB/s)" % (k, tsolve, it, step_us, out["step_gbs"]))
+    if not args.no_lowrank:
+        out["lowrank"] = lowrank_leg(B, torch, h, bd, x, k, lmin, lmax, args.tol, args.maxit)
+    B.pp_destroy(h)
     return out
 
 
@@ -220,6 +226,38 @@ def run_batch256(args, B, W, torch, dev):
     return out
 
 
+def lowrank_leg(B, torch, h, bd, x, k, lmin, lmax, tol, maxit, ranks=(1, 4), xis=(0.0, 1e-2), steps=64):
+    """PCG with the spectral low-rank correction (section 3.1) from Ritz vectors of `steps`
+    Lanczos steps, against the same solve without it; one timed solve each."""
+    def solve():
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, it, rel = B.pcg_solve(h, bd, x, tol, maxit)
+        return time.perf_counter() - t0, it, B.pp_status_str(st)
+
+    rows = []
+    for xi in xis:
+        B.pp_lowrank_set(h, 0)
+        B.pp_setup(h, k, lmin, lmax, xi)
+        solve()
+        t0, it0, s0 = solve()
+        for p in ranks:
+            torch.cuda.synchronize()
+            tr = time.perf_counter()
+            th = B.pp_lowrank_ritz(h, steps, p)
+            tr = time.perf_counter() - tr
+            solve()
+            t1, it1, s1 = solve()
+            rows.append(dict(xi=xi, rank=p, ritz_steps=steps, ritz_s=round(tr, 4), ritz_values=[float(v) for v in th],
+                             iters=it1, s_per_solve=round(t1, 4), status=s1, iters_without=it0,
+                             s_without=round(t0, 4)))
+            log("lowrank k=%d xi=%g rank %d: %d iters %.3f s (without: %d iters %.3f s), Ritz %.3f s"
+                % (k, xi, p, it1, t1, it0, t0, tr))
+    B.pp_lowrank_set(h, 0)
+    return rows
+
+
 def committed_traffic(args, n, k):
     """HBM bytes per fused-step launch from the committed rocprofv3 counter summary.
 
@@ -252,6 +290,7 @@ def main():
     ap.add_argument("--no-dfn", action="store_true", help="skip the DFN-shaped Schur leg")
     ap.add_argument("--dfn-k", type=int, default=40)
     ap.add_argument("--no-block", action="store_true", help="skip the 32-RHS block leg")
+    ap.add_argument("--no-lowrank", action="store_true", help="skip the low-rank correction legs")
     ap.add_argument("--block-rhs", type=int, default=32)
     ap.add_argument("--block-k", type=int, default=60)
     ap.add_argument("--batch256", action="store_true",
@@ -424,6 +463,20 @@ def main():
             % (kh, tm, it_m, tr, mixed["speedup_vs_fp64"]))
         B.pp_destroy(hm)
 
+    lowrank = None
+    if not args.no_lowrank:
+        lowrank = {"hetero256": lowrank_leg(B, torch, h, bd, x, kh, lmin, lmax, args.tol, args.maxit)}
+        B.pp_setup(h, kh, lmin, lmax, args.xi)
+        # Poisson 32^3 (degree 10): 20 Lanczos steps overestimate its well separated lambda_1
+        ap, bp = W.config_poisson32()
+        hp = B.pp_create_csr(ap.n_rows, ap.nnz, torch.from_numpy(ap.rowptr).to(dev),
+                             torch.from_numpy(ap.col).to(dev), torch.from_numpy(ap.val).to(dev), 0)
+        lp, up = B.pp_estimate_bounds(hp, 20)
+        xp = torch.zeros(ap.n_rows, dtype=torch.float64, device=dev)
+        lowrank["poisson32"] = lowrank_leg(B, torch, hp, torch.from_numpy(bp).to(dev), xp, 10, lp, up, args.tol,
+                                           args.maxit, ranks=(1, 3))
+        B.pp_destroy(hp)
+
     dfn = None if args.no_dfn else run_dfn(args, B, W, torch, dev)
 
     def fp64_single(k):
@@ -483,6 +536,7 @@ def main():
                      "frac_hbm": round(apply_gbs / HBM_PEAK_GBS, 4)},
         "per_k": per_k,
         "mixed": mixed,
+        "lowrank": lowrank,
         "dfn": dfn,
         "block": block,
         "batch256": batch256,
