@@ -116,6 +116,20 @@ PP_API pp_status pp_create_schur(pp_op *out, int64_t n, int64_t nnz_a, const int
 PP_API pp_status pp_setup(pp_op op, int k, double lambda_min, double lambda_max, double scaling);
 
 /*
+ * The same preconditioner family in the Newton form of Algorithm 1 (section
+ * 2.1): degree k = 2^nlev - 1 (nlev in [0, 12]), applied by the recursion
+ * P_0 r = zeta_0 r, P_j r = zeta_j (2 P_{j-1} r - P_{j-1} A P_{j-1} r) with
+ * zeta_0 = 1/theta-bar, zeta_1 = 2/(1 + 2 a zeta_0 - (a zeta_0)^2) (a =
+ * theta-bar - delta, the left end of the shifted interval) and eq. zetaNewt
+ * for zeta_i, i >= 2.  In exact arithmetic it equals the Chebyshev
+ * polynomial of the same degree (pp_setup).  Every operator application is
+ * one fused kernel; the recursion keeps 2 (nlev - 1) work vectors (allocated
+ * here).  Runs in FP64 even under PP_MIXED, with the stream-driven kernels.
+ * pp_setup switches back to the three-term Chebyshev form.
+ */
+PP_API pp_status pp_setup_newton(pp_op op, int nlev, double lambda_min, double lambda_max, double scaling);
+
+/*
  * z = P r by Algorithm 2 (k operator applications, no dot product).
  * With PP_JACOBI: z = D^{-1/2} p_k(D^{-1/2} A D^{-1/2}) D^{-1/2} r, the
  * effective preconditioner of A.  With PP_MIXED the recurrence runs in FP32.

@@ -28,7 +28,7 @@ ABI_FUNCTIONS = (
     "pp_batch_set_option", "pp_batch_get_stats", "pp_destroy_batch", "pp_mlp_create", "pp_mlp_destroy",
     "pp_mlp_num_params", "pp_mlp_get_params", "pp_mlp_set_params", "pp_mlp_set_normalization",
     "pp_mlp_forward", "pp_mlp_loss_grad", "pp_mlp_train_step", "pp_features", "pp_predict_bounds",
-    "pp_lowrank_set", "pp_lowrank_ritz", "pp_lowrank_get",
+    "pp_lowrank_set", "pp_lowrank_ritz", "pp_lowrank_get", "pp_setup_newton",
 )
 
 
@@ -107,6 +107,7 @@ def lib():
         L.pp_mlp_train_step.argtypes = [P, I32, P, P, F32, C.POINTER(D)]
         L.pp_features.argtypes = [P, I32, P]
         L.pp_lowrank_set.argtypes = [P, I32, P]
+        L.pp_setup_newton.argtypes = [P, I32, D, D, D]
         L.pp_lowrank_ritz.argtypes = [P, I32, I32, P]
         L.pp_lowrank_get.argtypes = [P, C.POINTER(I32), P]
         L.pp_predict_bounds.argtypes = [P, P, I32, C.POINTER(D), C.POINTER(D), C.POINTER(D), C.POINTER(I32)]
@@ -206,6 +207,10 @@ def pp_estimate_bounds(op, steps=20):
     lo, hi = C.c_double(), C.c_double()
     _check(lib().pp_estimate_bounds(op, int(steps), C.byref(lo), C.byref(hi)))
     return lo.value, hi.value
+
+
+def pp_setup_newton(op, nlev, lambda_min, lambda_max, scaling=0.0):
+    return _check(lib().pp_setup_newton(op, int(nlev), float(lambda_min), float(lambda_max), float(scaling)))
 
 
 def pp_lowrank_set(op, p, V=None):

@@ -698,6 +698,15 @@ __global__ __launch_bounds__(BLOCK) void k_scale(int64_t n, const XT *__restrict
     });
 }
 
+// out = a x + b y   (y may be null when b == 0; out may alias x or y)
+static __global__ __launch_bounds__(BLOCK) void k_lin2(int64_t n, double a, const double *x, double b,
+                                                       const double *y, double *out)
+{
+    const int G = (int)gridDim.x;
+    const int L = xcd_remap((int)blockIdx.x, G);
+    for_my_elems(n, L, G, [&](int64_t i) { out[i] = a * x[i] + (y ? b * y[i] : 0.0); });
+}
+
 // y = s .* s .* x * c   (k = 0 preconditioner with Jacobi)
 static __global__ __launch_bounds__(BLOCK) void k_scale2(int64_t n, const double *__restrict__ x,
                                                   const double *__restrict__ s, double c,

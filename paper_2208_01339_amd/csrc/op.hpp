@@ -62,6 +62,13 @@ struct pp_op_s {
     int k = 0;
     double lmin = 0, lmax = 0, xi = 0, theta = 0, delta = 0, sigma = 0;
     std::vector<double> rho;
+    // Newton form (Algorithm 1): form = 1, degree 2^nlev - 1, scalings zeta_0..nlev,
+    // two work vectors per level
+    int form = 0;
+    int nlev = 0;
+    std::vector<double> zeta;
+    double *nbuf = nullptr;
+    int nbuf_levels = 0;
     // options
     int grid_max = PP_GRID_DEFAULT;
     int grid_auto = PP_GRID_DEFAULT;  // resident workgroups of the fused step (CUs x occupancy)
@@ -119,7 +126,7 @@ struct pp_op_s {
         ppc::dfree(xh); ppc::dfree(r); ppc::dfree(p); ppc::dfree(q); ppc::dfree(z); ppc::dfree(bh); ppc::dfree(sA); ppc::dfree(sB);
         ppc::dfree(r32); ppc::dfree(sA32); ppc::dfree(sB32);
         ppc::dfree(partials); ppc::dfree(coef_d); ppc::dfree(st);
-        ppc::dfree(lr_v); ppc::dfree(lr_hinv);
+        ppc::dfree(lr_v); ppc::dfree(lr_hinv); ppc::dfree(nbuf);
         if (hst) (void)hipHostFree(hst);
         if (hflag) (void)hipHostFree(hflag);
         hst = nullptr;

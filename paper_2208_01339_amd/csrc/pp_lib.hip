@@ -425,11 +425,76 @@ void launch_step(pp_op_s *op, const XT *xg, const RT *r, const T *sold, OT *out,
     }
 }
 
+// Algorithm 1 (Newton form), FP64:  out = alpha P_j(in) + beta extra, with
+// P_0 v = zeta_0 v and P_j v = zeta_j (2 P_{j-1} v - P_{j-1} A P_{j-1} v).
+// Every operator application is one fused step; level j >= 2 keeps
+// u = P_{j-1}(in) and A u in its own two work vectors, so the recursion holds
+// 2 nlev vectors at most.  P_1 v = zeta_1 zeta_0 (2 v - zeta_0 A v) is a
+// single fused step, and the outer combination of every level is folded into
+// the last step of its second sub-call (extra term).
+void newton_level(pp_op_s *op, int j, const double *in, double *out, double alpha, const double *extra,
+                  double beta)
+{
+    const double *zt = op->zeta.data();
+    if (j == 1) {
+        StepCoef c{0, 0, 0, 0};
+        c.cA = -zt[1] * zt[0] * zt[0] * alpha;
+        if (extra) {
+            c.cx = 2.0 * zt[1] * zt[0] * alpha;
+            c.cr = beta;
+            launch_step<double, double, double, double, 2>(op, in, extra, (const double *)nullptr, out, c,
+                                                           ppk::FIN_NONE, false);
+        } else {
+            c.cr = 2.0 * zt[1] * zt[0] * alpha;
+            launch_step<double, double, double, double, 1>(op, in, in, (const double *)nullptr, out, c,
+                                                           ppk::FIN_NONE, false);
+        }
+        return;
+    }
+    const int64_t n = op->n;
+    double *U = op->nbuf + (size_t)(2 * (j - 2)) * n, *AU = U + n;  // this level's vectors (j >= 2)
+    newton_level(op, j - 1, in, U, 1.0, nullptr, 0.0);
+    StepCoef c{0, 0, 0, 1.0};  // AU = A U
+    launch_step<double, double, double, double, 1>(op, U, U, (const double *)nullptr, AU, c, ppk::FIN_NONE, false);
+    // out = alpha zeta_j (2 U - P_{j-1}(AU)) + beta extra
+    const double a2 = 2.0 * alpha * zt[j];
+    if (extra) {
+        hipLaunchKernelGGL(ppk::k_lin2, dim3(op->grid_elems(n)), dim3(BLOCK), 0, op->stream, n, a2, (const double *)U,
+                           beta, extra, U);
+        newton_level(op, j - 1, AU, out, -alpha * zt[j], U, 1.0);
+    } else {
+        newton_level(op, j - 1, AU, out, -alpha * zt[j], U, a2);
+    }
+}
+
+void enqueue_newton(pp_op_s *op, const double *rr, double *zout, int fin, bool scale)
+{
+    const int64_t n = op->n;
+    const int ge = op->grid_elems(n);
+    if (op->nlev == 0)
+        hipLaunchKernelGGL(ppk::k_lin2, dim3(ge), dim3(BLOCK), 0, op->stream, n, op->zeta[0], rr, 0.0,
+                           (const double *)nullptr, zout);
+    else
+        newton_level(op, op->nlev, rr, zout, 1.0, nullptr, 0.0);
+    if (scale)
+        hipLaunchKernelGGL((ppk::k_scale<double, double>), dim3(ge), dim3(BLOCK), 0, op->stream, n,
+                           (const double *)zout, (const double *)op->dis, 1.0, zout);
+    if (fin != ppk::FIN_NONE) {
+        hipLaunchKernelGGL(ppk::k_dot_fin, dim3(ge), dim3(BLOCK), 0, op->stream, n, rr, (const double *)zout,
+                           op->partials, op->st, fin);
+        enqueue_fin(op, ge, fin);
+    }
+}
+
 // z = p_k(A-hat) rr, rr in the scaled space (double).  fin: FIN_NONE,
 // FIN_RHO0 or FIN_RHO (reduce rr.z).  scale: multiply the output by dis
 // (pp_apply under Jacobi).  r32src: FP32 copy of rr already made (mixed).
 void enqueue_poly(pp_op_s *op, const double *rr, double *zout, int fin, bool scale)
 {
+    if (op->form == 1) {
+        enqueue_newton(op, rr, zout, fin, scale);
+        return;
+    }
     const int k = op->k;
     if (k == 0) {
         // z = rr / theta (and the dot when requested)
@@ -723,7 +788,39 @@ pp_status pp_setup(pp_op op, int k, double lambda_min, double lambda_max, double
     op->rho.assign((size_t)k + 1, 0.0);
     op->rho[0] = 1.0 / op->sigma;
     for (int j = 1; j <= k; ++j) op->rho[j] = 1.0 / (2.0 * op->sigma - op->rho[j - 1]);
+    op->form = 0;
     op->setup_done = true;
+    return PP_OK;
+}
+
+pp_status pp_setup_newton(pp_op op, int nlev, double lambda_min, double lambda_max, double scaling)
+{
+    if (!op) return fail(PP_ERR_ARG, "op is NULL");
+    if (nlev < 0 || nlev > 12) return fail(PP_ERR_ARG, "nlev must be in [0, 12]");
+    const pp_status s = pp_setup(op, (1 << nlev) - 1, lambda_min, lambda_max, scaling);
+    if (s != PP_OK) return s;
+    try {
+        if (nlev >= 2 && op->nbuf_levels < nlev - 1) {
+            dfree(op->nbuf);
+            op->nbuf = dalloc<double>((size_t)2 * (nlev - 1) * op->n);
+            op->nbuf_levels = nlev - 1;
+        }
+    } catch (std::bad_alloc &) {
+        op->setup_done = false;
+        return fail(PP_ERR_OOM, "device allocation failed");
+    }
+    // zeta_0 = 1 / theta-bar; zeta_1 from the left end a = theta-bar - delta of
+    // the (shifted) interval; zeta_i = 2 / (1 + 2 zeta_{i-1} - zeta_{i-1}^2)
+    op->zeta.assign((size_t)nlev + 1, 0.0);
+    op->zeta[0] = 1.0 / op->theta;
+    if (nlev >= 1) {
+        const double az = (op->theta - op->delta) * op->zeta[0];
+        op->zeta[1] = 2.0 / (1.0 + 2.0 * az - az * az);
+    }
+    for (int i = 2; i <= nlev; ++i)
+        op->zeta[i] = 2.0 / (1.0 + 2.0 * op->zeta[i - 1] - op->zeta[i - 1] * op->zeta[i - 1]);
+    op->nlev = nlev;
+    op->form = 1;
     return PP_OK;
 }
 
@@ -831,7 +928,7 @@ pp_status pcg_solve(pp_op op, const double *b, double *x, double tol, int maxit,
         // persistent driver on request only: its grid-wide barriers cost more
         // than kernel boundaries on this chip at every size measured (each
         // barrier serialises one same-address atomic per workgroup)
-        const bool want_persist = op->driver == 1 && op->lr_p == 0;
+        const bool want_persist = op->driver == 1 && op->lr_p == 0 && op->form == 0;
         bool persisted = want_persist && persistent_solve(op, b, x, tol, maxit);
         size_t ev_i = 0;
         if (!persisted) {
