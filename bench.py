@@ -26,6 +26,8 @@ The JSON line also carries:
                 vector work), scaled per operator application to the
                 applications of the headline GPU solve;
   mixed         the same solve with the polynomial in FP32 (PP_MIXED);
+  newton        the same solve with the Newton form of Algorithm 1 at degrees
+                15 and 63 against the three-term form at the same degrees;
   lowrank       the same solve, the DFN one and the Poisson 32^3 one (k = 10)
                 with the spectral low-rank correction of section 3.1 from
                 Ritz vectors of 64 Lanczos steps, ranks 1 and 4 (3 for
@@ -291,6 +293,7 @@ def main():
     ap.add_argument("--dfn-k", type=int, default=40)
     ap.add_argument("--no-block", action="store_true", help="skip the 32-RHS block leg")
     ap.add_argument("--no-lowrank", action="store_true", help="skip the low-rank correction legs")
+    ap.add_argument("--no-newton", action="store_true", help="skip the Newton-form leg")
     ap.add_argument("--block-rhs", type=int, default=32)
     ap.add_argument("--block-k", type=int, default=60)
     ap.add_argument("--batch256", action="store_true",
@@ -463,6 +466,32 @@ def main():
             % (kh, tm, it_m, tr, mixed["speedup_vs_fp64"]))
         B.pp_destroy(hm)
 
+    newton = None
+    if not args.no_newton:
+        # Algorithm 1 (Newton form) against the three-term form at the same degree 2^nlev - 1
+        newton = []
+        for nlev in (4, 6):
+            kk = 2 ** nlev - 1
+            row = dict(nlev=nlev, k=kk)
+            for form in ("chebyshev", "newton"):
+                if form == "newton":
+                    B.pp_setup_newton(h, nlev, lmin, lmax, args.xi)
+                else:
+                    B.pp_setup(h, kk, lmin, lmax, args.xi)
+                x.zero_()
+                B.pcg_solve(h, bd, x, args.tol, args.maxit)
+                x.zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                stn, itn, reln = B.pcg_solve(h, bd, x, args.tol, args.maxit)
+                row[form] = dict(s_per_solve=round(time.perf_counter() - t0, 4), iters=itn,
+                                 status=B.pp_status_str(stn))
+            newton.append(row)
+            log("degree %d: chebyshev %.3f s (%d iters), newton %.3f s (%d iters)"
+                % (kk, row["chebyshev"]["s_per_solve"], row["chebyshev"]["iters"], row["newton"]["s_per_solve"],
+                   row["newton"]["iters"]))
+        B.pp_setup(h, kh, lmin, lmax, args.xi)
+
     lowrank = None
     if not args.no_lowrank:
         lowrank = {"hetero256": lowrank_leg(B, torch, h, bd, x, kh, lmin, lmax, args.tol, args.maxit)}
@@ -536,6 +565,7 @@ def main():
                      "frac_hbm": round(apply_gbs / HBM_PEAK_GBS, 4)},
         "per_k": per_k,
         "mixed": mixed,
+        "newton": newton,
         "lowrank": lowrank,
         "dfn": dfn,
         "block": block,
