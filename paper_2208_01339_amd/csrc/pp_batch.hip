@@ -31,6 +31,11 @@ struct pp_batch_s {
     int64_t n_ext = 0, nnz = 0, nslices = 0, n_int = 0, nstored = 0;
     int G = 0;
     std::vector<int64_t> sys_ptr, seg_row0_h, seg_n_h;
+    // workgroup map at create (restored after every solve) and the map in use
+    std::vector<int32_t> blk_seg_h, seg_blk0_h, map_seg, map_blk0;
+    std::vector<int64_t> blk_s0_h, blk_s1_h, map_s0, map_s1;
+    std::vector<int32_t> seg_done_h;
+    bool remapped = false;
     // maps
     int32_t *blk_seg = nullptr, *seg_blk0 = nullptr, *slice_seg = nullptr;
     int64_t *blk_s0 = nullptr, *blk_s1 = nullptr, *seg_row0 = nullptr, *seg_n = nullptr, *ext_row0 = nullptr;
@@ -59,6 +64,7 @@ struct pp_batch_s {
             *d_seg_done = nullptr, *d_ndone = nullptr;
     uint32_t *d_ticket = nullptr;
     int32_t *h_ndone = nullptr;  // pinned [2]
+    int32_t *h_segdone = nullptr;  // pinned [2][S]
     hipEvent_t flag_ev[2] = {nullptr, nullptr};
     hipEvent_t sync_ev = nullptr, solve_ev[2] = {nullptr, nullptr};
     // polynomial
@@ -136,6 +142,8 @@ struct pp_batch_s {
         dfree(d_ndone); dfree(d_ticket);
         if (h_ndone) (void)hipHostFree(h_ndone);
         h_ndone = nullptr;
+        if (h_segdone) (void)hipHostFree(h_segdone);
+        h_segdone = nullptr;
         for (auto &e : flag_ev) if (e) { (void)hipEventDestroy(e); e = nullptr; }
         for (auto &e : solve_ev) if (e) { (void)hipEventDestroy(e); e = nullptr; }
         if (sync_ev) (void)hipEventDestroy(sync_ev);
@@ -340,6 +348,10 @@ pp_status build(pp_batch_s *op, const int64_t *rowptr, const int32_t *colind, co
             seg_blk0[s + 1] = (int32_t)blk_seg.size();
         }
         op->G = (int)blk_seg.size();
+        op->blk_seg_h = blk_seg;
+        op->blk_s0_h = blk_s0;
+        op->blk_s1_h = blk_s1;
+        op->seg_blk0_h = seg_blk0;
         auto upload = [&](auto *&dst, const auto &src) {
             using T = typename std::remove_reference<decltype(src[0])>::type;
             dst = dalloc<typename std::remove_const<T>::type>(src.size());
@@ -432,6 +444,7 @@ pp_status build(pp_batch_s *op, const int64_t *rowptr, const int32_t *colind, co
         op->d_ndone = dalloc<int32_t>(1);
         HIPCHK(hipMemsetAsync(op->d_ticket, 0, sizeof(uint32_t) * S, op->stream));
         HIPCHK(hipHostMalloc((void **)&op->h_ndone, 2 * sizeof(int32_t), hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void **)&op->h_segdone, 2 * sizeof(int32_t) * S, hipHostMallocDefault));
         HIPCHK(hipStreamSynchronize(op->stream));
         end_call(op);
     } catch (std::bad_alloc &) {
@@ -443,6 +456,79 @@ pp_status build(pp_batch_s *op, const int64_t *rowptr, const int32_t *colind, co
     }
     cleanup();
     return PP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// load balance: once systems finish, their workgroups would idle for the rest
+// of the solve; the same G workgroups are redistributed over the systems
+// still running, in proportion to their slices (blocks past the work get an
+// empty range).  Only the map's contents change, so captured graphs stay valid.
+// ---------------------------------------------------------------------------
+
+void upload_map(pp_batch_s *op, const std::vector<int32_t> &seg, const std::vector<int64_t> &s0,
+                const std::vector<int64_t> &s1, const std::vector<int32_t> &blk0)
+{
+    const int G = op->G, S = op->S;
+    HIPCHK(hipMemcpyAsync(op->blk_seg, seg.data(), sizeof(int32_t) * G, hipMemcpyHostToDevice, op->stream));
+    HIPCHK(hipMemcpyAsync(op->blk_s0, s0.data(), sizeof(int64_t) * G, hipMemcpyHostToDevice, op->stream));
+    HIPCHK(hipMemcpyAsync(op->blk_s1, s1.data(), sizeof(int64_t) * G, hipMemcpyHostToDevice, op->stream));
+    HIPCHK(hipMemcpyAsync(op->seg_blk0, blk0.data(), sizeof(int32_t) * (S + 1), hipMemcpyHostToDevice, op->stream));
+}
+
+// New map over the systems with seg_done == 0; false when none is left.
+bool rebalance(pp_batch_s *op, const std::vector<int32_t> &seg_done)
+{
+    const int G = op->G, S = op->S;
+    std::vector<int64_t> sl(S, 0);
+    int64_t total = 0;
+    for (int s = 0; s < S; ++s)
+        if (!seg_done[s]) {
+            sl[s] = (op->seg_row0_h[s + 1] - op->seg_row0_h[s]) / WAVE;
+            total += sl[s];
+        }
+    if (total == 0) return false;
+    std::vector<int64_t> nb(S, 0);
+    int64_t used = 0;
+    for (int s = 0; s < S; ++s)
+        if (sl[s] > 0) {
+            nb[s] = std::max<int64_t>(1, std::min<int64_t>((int64_t)((double)G * sl[s] / total),
+                                                           (sl[s] + WPB - 1) / WPB));
+            used += nb[s];
+        }
+    while (used > G) {  // more systems than workgroups cannot happen (G >= S), trim the largest
+        int big = 0;
+        for (int s = 1; s < S; ++s)
+            if (nb[s] > nb[big]) big = s;
+        --nb[big];
+        --used;
+    }
+    op->map_seg.assign(G, 0);
+    op->map_s0.assign(G, 0);
+    op->map_s1.assign(G, 0);
+    op->map_blk0.assign(S + 1, 0);
+    int last = -1;
+    for (int s = 0; s < S; ++s)
+        if (sl[s] > 0) last = s;
+    int b = 0;
+    for (int s = 0; s < S; ++s) {
+        op->map_blk0[s] = b;
+        const int64_t first = op->seg_row0_h[s] / WAVE;
+        for (int64_t i = 0; i < nb[s]; ++i, ++b) {
+            op->map_seg[b] = s;
+            op->map_s0[b] = first + sl[s] * i / nb[s];
+            op->map_s1[b] = first + sl[s] * (i + 1) / nb[s];
+        }
+        if (s == last)  // the spare blocks join the last running system with an empty range
+            for (; b < G; ++b) {
+                op->map_seg[b] = s;
+                op->map_s0[b] = first + sl[s];
+                op->map_s1[b] = first + sl[s];
+            }
+    }
+    op->map_blk0[S] = G;
+    upload_map(op, op->map_seg, op->map_s0, op->map_s1, op->map_blk0);
+    op->remapped = true;
+    return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -810,7 +896,8 @@ pp_status pcg_solve_batch(pp_batch op, const double *B, double *X, double tol, i
                 HIPCHK(hipGraphDestroy(gr));
                 op->g_k = op->k; op->g_chunk = chunk; op->g_tol = tol; op->g_maxit = maxit; op->g_W = op->W;
             }
-            int enq = 0, c = 0;
+            int enq = 0, c = 0, ndone_mapped = 0;
+            const bool balance = op->S > 1;
             while (enq < maxit) {
                 if (graph) HIPCHK(hipGraphLaunch(op->gexec, op->stream));
                 else
@@ -819,13 +906,33 @@ pp_status pcg_solve_batch(pp_batch op, const double *B, double *X, double tol, i
                 enq += chunk;
                 HIPCHK(hipMemcpyAsync(&op->h_ndone[c & 1], op->d_ndone, sizeof(int32_t), hipMemcpyDeviceToHost,
                                       op->stream));
+                if (balance)
+                    HIPCHK(hipMemcpyAsync(op->h_segdone + (size_t)(c & 1) * op->S, op->d_seg_done,
+                                          sizeof(int32_t) * op->S, hipMemcpyDeviceToHost, op->stream));
                 HIPCHK(hipEventRecord(op->flag_ev[c & 1], op->stream));
                 if (c >= 1) {
                     HIPCHK(hipEventSynchronize(op->flag_ev[(c - 1) & 1]));
-                    if (op->h_ndone[(c - 1) & 1] >= total) break;
+                    const int nd = op->h_ndone[(c - 1) & 1];
+                    if (nd >= total) break;
+                    if (balance && nd > ndone_mapped) {
+                        // a system finished (as of chunk c-1): spread the idle workgroups
+                        const int32_t *sd = op->h_segdone + (size_t)((c - 1) & 1) * op->S;
+                        std::vector<int32_t> done(sd, sd + op->S);
+                        if (done != op->seg_done_h) {
+                            op->seg_done_h = done;
+                            if (rebalance(op, done)) HIPCHK(hipStreamSynchronize(op->stream));
+                        }
+                        ndone_mapped = nd;
+                    }
                 }
                 ++c;
             }
+            if (op->remapped) {  // every system's rows again, for the final scaling and later calls
+                upload_map(op, op->blk_seg_h, op->blk_s0_h, op->blk_s1_h, op->seg_blk0_h);
+                HIPCHK(hipStreamSynchronize(op->stream));
+                op->remapped = false;
+            }
+            op->seg_done_h.clear();
             hipLaunchKernelGGL((ppb::kb_final<W, CPL>), g, b, 0, op->stream, bt, st, A, (const double *)op->Xh,
                                (const double *)op->dis, X);
             HIPCHK(hipGetLastError());

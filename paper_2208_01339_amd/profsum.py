@@ -76,6 +76,17 @@ def kernels(trace_csv, match, top=15):
                        mean_full_us=sum(keep) / max(1, len(keep)))
 
 
+def stats_table(stats_csv, top=16):
+    """Per-kernel table from a rocprofv3 --stats kernel_stats CSV (when the trace is too large to keep)."""
+    rows = list(csv.DictReader(open(stats_csv)))
+    lines = ["%-10s %8s %12s %10s  %s" % ("share", "calls", "total_ms", "avg_us", "kernel")]
+    for r in rows[:top]:
+        lines.append("%9.2f%% %8d %12.3f %10.2f  %s" % (float(r["Percentage"]), int(r["Calls"]),
+                                                        float(r["TotalDurationNs"]) / 1e6,
+                                                        float(r["AverageNs"]) / 1e3, r["Name"][:150]))
+    return lines
+
+
 def _counter(path, name):
     out = []
     for r in csv.DictReader(open(path)):
@@ -128,6 +139,12 @@ def main():
     k.add_argument("--command", required=True)
     k.add_argument("--out", required=True)
     k.add_argument("--field", action="append", default=[], help="extra KEY=VALUE line")
+    t = sub.add_parser("stats")
+    t.add_argument("--stats", required=True)
+    t.add_argument("--title", required=True)
+    t.add_argument("--command", required=True)
+    t.add_argument("--out", required=True)
+    t.add_argument("--field", action="append", default=[], help="extra KEY=VALUE line")
     c = sub.add_parser("counters")
     c.add_argument("--fetch", required=True)
     c.add_argument("--write", required=True)
@@ -141,7 +158,12 @@ def main():
     c.add_argument("--field", action="append", default=[], help="extra KEY=VALUE line")
     a = ap.parse_args()
     extra = "".join("%s: %s\n" % tuple(f.split("=", 1)) for f in a.field)
-    if a.cmd == "kernels":
+    if a.cmd == "stats":
+        with open(a.out, "w") as fo:
+            fo.write("# %s\n\ncommand: %s\nsource_digest: %s\n" % (a.title, a.command, source_digest()))
+            fo.write(extra + "\n")
+            fo.write("\n".join(stats_table(a.stats)) + "\n")
+    elif a.cmd == "kernels":
         lines, fam = kernels(a.trace, a.match)
         with open(a.out, "w") as fo:
             fo.write("# %s\n\ncommand: %s\nsource_digest: %s\nmatch: %s\n" % (a.title, a.command,
