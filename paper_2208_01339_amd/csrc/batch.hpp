@@ -210,12 +210,12 @@ struct Vec {
     T v[CPL];
 };
 
-template <typename T, int CPL>
+template <typename T, int CPL, bool NT = false>
 __device__ __forceinline__ Vec<T, CPL> ldv(const T *p)
 {
     Vec<T, CPL> r;
 #pragma unroll
-    for (int q = 0; q < CPL; ++q) r.v[q] = p[q];
+    for (int q = 0; q < CPL; ++q) r.v[q] = ppk::ldm<NT>(p + q);
     return r;
 }
 
@@ -464,12 +464,14 @@ __global__ __launch_bounds__(BLOCK) void kb_cheb(Batch bt, BState st, ppk::SellV
         constexpr int DK = decltype(dk)::value;
         constexpr bool SP = decltype(spc)::value;
         const SegDia<DK> g = seg_dia<DK>(bt, br.seg);
+        // stored diagonals: R, SOLD and OUT are pure streams (see ph_cheb)
+        constexpr bool NTV = DK > 0;
         for_rows<W, SP>(A, br, [&](int64_t row, int rin, int64_t base, int width) {
             const int64_t o = row * NB + c0;
-            Vec<RT, CPL> rv = ldv<RT, CPL>(Rv + o);
+            Vec<RT, CPL> rv = ldv<RT, CPL, NTV>(Rv + o);
             Vec<T, CPL> xs, so;
             if (MODE >= 2) xs = ldv<T, CPL>(X + o);
-            if (MODE == 3) so = ldv<T, CPL>(SOLD + o);
+            if (MODE == 3) so = ldv<T, CPL, NTV>(SOLD + o);
             T acc[CPL];
             spmm_any<T, W, CPL, DK, SP, NT>(A, bt, g, X, NB, row, base, width, rin, c0, acc);
             if (row < br.row_end) {
@@ -478,7 +480,8 @@ __global__ __launch_bounds__(BLOCK) void kb_cheb(Batch bt, BState st, ppk::SellV
                     T v = aA * acc[q] + ar * (T)rv.v[q];
                     if (MODE >= 2) v += ax * xs.v[q];
                     if (MODE == 3) v += aold * so.v[q];
-                    OUT[o + q] = (OT)v;
+                    if constexpr (NTV) __builtin_nontemporal_store((OT)v, OUT + o + q);
+                    else OUT[o + q] = (OT)v;
                     if (LAST) part[q] += (double)rv.v[q] * (double)(OT)v;
                 }
             }

@@ -442,12 +442,19 @@ __device__ __forceinline__ double ph_cheb(const SellView &A, const XT *__restric
     with_storage(A, [&](auto dk, auto sp) {
         constexpr int DK = decltype(dk)::value;
         constexpr bool SP = decltype(sp)::value;
+        // With a diagonal part, r, s_{j-2} and the output are pure streams:
+        // non-temporal accesses (NT: operators much larger than the caches)
+        // keep them from evicting the gathered x and the mirrored diagonal
+        // values that the neighbouring rows re-read.  (With the slice layout
+        // only, the matrix stream is the non-temporal one and the vectors do
+        // better cached.)
+        constexpr bool NTV = DK != 0 && NT;
         for_my_slices(A.nslices, L, G, [&](int64_t row, int64_t s, int lane) {
             // row-level operands first, so they are in flight with the matrix stream
             const int64_t rc = row < A.n ? row : A.n - 1;
-            const RT ri = r[rc];
+            const RT ri = ldm<NTV>(r + rc);
             const T xs = (MODE >= 2) ? (T)xg[rc] : (T)0;
-            const T so = (MODE == 3) ? sold[rc] : (T)0;
+            const T so = (MODE == 3) ? ldm<NTV>(sold + rc) : (T)0;
             const double ds = SCALE ? dis[rc] : 1.0;
             T a = op_row_fixed<DK, SP, T, XT, SCHUR, NT>(A, xg, w, row, s, lane);
             if (row < A.n) {
@@ -456,7 +463,8 @@ __device__ __forceinline__ double ph_cheb(const SellView &A, const XT *__restric
                 if (MODE == 3) o += aold * so;
                 OT ov = (OT)o;
                 if (SCALE) ov = (OT)((double)ov * ds);
-                out[row] = ov;
+                if constexpr (NTV) __builtin_nontemporal_store(ov, out + row);
+                else out[row] = ov;
                 if (DOT) part += (double)ri * (double)ov;
             }
         });

@@ -75,7 +75,7 @@ struct pp_op_s {
     int chunk = 0;  // 0 = auto
     int timing = 0;
     int driver = -1;  // -1 auto, 0 stream-driven, 1 persistent
-    int ntload = 1;
+    int ntload = 1;   // set at create from the operator's size
     pp_stats stats{};
 
     bool schur() const { return kind == 1; }

@@ -335,6 +335,10 @@ pp_status create_common(pp_op *out, int kind, int64_t n, int64_t nnz, const int6
         op->grid_max = op->grid_auto;
     }
     (void)hipGetLastError();
+    // non-temporal streams pay only when a step's working set (about 64 bytes
+    // per row in FP64) does not fit in the 256 MB Infinity Cache: below 2^22
+    // rows the steps re-read matrix and vectors from it
+    op->ntload = n >= (int64_t)1 << 22 ? 1 : 0;
     *out = op;
     return PP_OK;
 }
