@@ -217,7 +217,7 @@ typedef struct {
     int32_t grid;           /* workgroups per launch used                           */
     int32_t diagonals;      /* stored diagonals of the symmetric diagonal part      */
                             /* (0 = every entry in the slice layout)                */
-    int32_t pad;
+    int32_t two_step;       /* 1 when pairs of Chebyshev steps share one pass        */
 } pp_stats;
 
 PP_API pp_status pp_get_stats(pp_op op, pp_stats *st);
@@ -228,9 +228,14 @@ enum {
     PP_OPT_CHUNK = 2,       /* CG iterations queued between host convergence checks       */
     PP_OPT_TIMING = 3,      /* 1 = record events around the polynomial steps              */
     PP_OPT_DRIVER = 4,      /* 0 = stream-driven, 1 = persistent cooperative kernel, -1 = auto */
-    PP_OPT_NT_LOADS = 5     /* 1 = non-temporal accesses for the streams read once per step */
+    PP_OPT_NT_LOADS = 5,    /* 1 = non-temporal accesses for the streams read once per step */
                             /* (the sliced matrix; r, s_{j-2} and the output with stored */
                             /* diagonals), 0 = plain; default 1 from 2^22 rows on       */
+    PP_OPT_TWO_STEP = 6     /* 1 (default) = on 3-D 7-point operators (stored diagonals at  */
+                            /* offsets 0, 1, N, N^2, no coupling across the box's x- and   */
+                            /* y-faces) fuse pairs of Chebyshev steps into one pass        */
+                            /* (x-y tiles with a recomputed one-cell ring, z-march through */
+                            /* LDS), 0 = one pass per step                                */
 };
 PP_API pp_status pp_set_option(pp_op op, int key, int64_t value);
 

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libppcg.so")
 PP_OK, PP_NOT_CONVERGED, PP_BREAKDOWN = 0, 1, 2
 PP_ERR_ARG, PP_ERR_OOM, PP_ERR_HIP, PP_ERR_STATE = -1, -2, -3, -4
 PP_JACOBI, PP_MIXED, PP_SLICED = 1, 2, 4
-PP_OPT_GRID, PP_OPT_CHUNK, PP_OPT_TIMING, PP_OPT_DRIVER, PP_OPT_NT_LOADS = 1, 2, 3, 4, 5
+PP_OPT_GRID, PP_OPT_CHUNK, PP_OPT_TIMING, PP_OPT_DRIVER, PP_OPT_NT_LOADS, PP_OPT_TWO_STEP = 1, 2, 3, 4, 5, 6
 
 PP_BOPT_GRAPH = 100
 
@@ -44,7 +44,7 @@ class pp_stats(C.Structure):
         ("op_applies", C.c_int64), ("dots", C.c_int64), ("cheb_ms", C.c_double),
         ("cheb_steps", C.c_int64), ("solve_ms", C.c_double), ("n", C.c_int64),
         ("nnz_stored", C.c_int64), ("nnz_matrix", C.c_int64), ("driver", C.c_int32),
-        ("grid", C.c_int32), ("diagonals", C.c_int32), ("pad", C.c_int32),
+        ("grid", C.c_int32), ("diagonals", C.c_int32), ("two_step", C.c_int32),
     ]
 
 

@@ -42,6 +42,12 @@ struct pp_op_s {
     double *xh = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr, *bh = nullptr;
     double *sA = nullptr, *sB = nullptr;
     float *r32 = nullptr, *sA32 = nullptr, *sB32 = nullptr;
+    // two Chebyshev steps per pass (3-D 7-point operators): box N x N x s2NZ,
+    // two more step buffers
+    bool s2 = false;
+    int two_step = 1;
+    int64_t s2N = 0, s2NZ = 0;
+    double *sC = nullptr, *sD = nullptr;
     double *partials = nullptr;  // (1 + LR_MAX) * 8192 doubles
     // spectral low-rank correction: V (n x lr_p, column-major), (V^T A V)^{-1}
     int lr_p = 0;
@@ -125,6 +131,7 @@ struct pp_op_s {
         ppc::dfree(dis);
         ppc::dfree(xh); ppc::dfree(r); ppc::dfree(p); ppc::dfree(q); ppc::dfree(z); ppc::dfree(bh); ppc::dfree(sA); ppc::dfree(sB);
         ppc::dfree(r32); ppc::dfree(sA32); ppc::dfree(sB32);
+        ppc::dfree(sC); ppc::dfree(sD);
         ppc::dfree(partials); ppc::dfree(coef_d); ppc::dfree(st);
         ppc::dfree(lr_v); ppc::dfree(lr_hinv); ppc::dfree(nbuf);
         if (hst) (void)hipHostFree(hst);

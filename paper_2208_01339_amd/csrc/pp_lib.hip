@@ -18,6 +18,7 @@
 #include "dia_plan.hpp"
 #include "lowrank.hpp"
 #include "persistent.hpp"
+#include "stencil2.hpp"
 #include "sym_eig.hpp"
 
 using ppk::BLOCK;
@@ -339,6 +340,32 @@ pp_status create_common(pp_op *out, int kind, int64_t n, int64_t nnz, const int6
     // per row in FP64) does not fit in the 256 MB Infinity Cache: below 2^22
     // rows the steps re-read matrix and vectors from it
     op->ntload = n >= (int64_t)1 << 22 ? 1 : 0;
+    // 3-D 7-point shape (offsets 0, 1, N, N^2, n = N^2 NZ, no coupling across
+    // the x- and y-faces): pairs of Chebyshev steps can share one pass
+    if (op->nd == 4 && !op->sell && !op->schur() && op->doff[1] == 1 && op->doff[2] > 1 &&
+        op->doff[2] <= ppk::S2_NMAX && op->doff[3] == op->doff[2] * op->doff[2] && n % op->doff[3] == 0) {
+        try {
+            int *bad = dalloc<int>(1);
+            int h = 0;
+            HIPCHK(hipMemsetAsync(bad, 0, sizeof(int), op->stream));
+            hipLaunchKernelGGL(ppk::k_s2_check, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, op->stream,
+                               n, op->doff[2], (const double *)op->dval, op->dstride, bad);
+            HIPCHK(hipMemcpyAsync(&h, bad, sizeof(int), hipMemcpyDeviceToHost, op->stream));
+            HIPCHK(hipStreamSynchronize(op->stream));
+            dfree(bad);
+            if (!h && !op->mixed()) {
+                op->sC = dalloc<double>(n);
+                op->sD = dalloc<double>(n);
+                op->s2 = true;
+                op->s2N = op->doff[2];
+                op->s2NZ = n / op->doff[3];
+            }
+        } catch (...) {
+            // the one-step kernels serve every operator: keep them
+            op->s2 = false;
+            (void)hipGetLastError();
+        }
+    }
     *out = op;
     return PP_OK;
 }
@@ -490,6 +517,60 @@ void enqueue_newton(pp_op_s *op, const double *rr, double *zout, int fin, bool s
     }
 }
 
+// Steps j and j+1 (both three-term steps) in one pass of k_cheb2_stencil.
+template <typename T>
+void launch_pair(pp_op_s *op, const T *sm1, const T *sm2, const T *r, T *o1, T *o2, const StepCoef &c1,
+                 const StepCoef &c2)
+{
+    ppk::Stencil2 g;
+    g.N = op->s2N;
+    g.NZ = op->s2NZ;
+    g.n = op->n;
+    g.nty = (int)((g.N + ppk::S2_TY - 1) / ppk::S2_TY);
+    g.nzc = (int)((g.NZ + ppk::S2_ZC - 1) / ppk::S2_ZC);
+    const dim3 grid((unsigned)(g.nty * g.nzc));
+    const size_t lds = sizeof(T) * 3 * ppk::S2_RY * (size_t)g.N;
+    const T *dv = sizeof(T) == 4 ? (const T *)op->dval32 : (const T *)op->dval;
+    if (op->ntload)
+        hipLaunchKernelGGL((ppk::k_cheb2_stencil<T, true>), grid, dim3(BLOCK), lds, op->stream, g, dv, op->dstride,
+                           sm1, sm2, r, o1, o2, c1.cx, c1.cold, c1.cr, c1.cA, c2.cx, c2.cold, c2.cr, c2.cA,
+                           (const ppk::State *)op->st);
+    else
+        hipLaunchKernelGGL((ppk::k_cheb2_stencil<T, false>), grid, dim3(BLOCK), lds, op->stream, g, dv,
+                           op->dstride, sm1, sm2, r, o1, o2, c1.cx, c1.cold, c1.cr, c1.cA, c2.cx, c2.cold, c2.cr,
+                           c2.cA, (const ppk::State *)op->st);
+}
+
+// p_k(A-hat) rr with pairs of three-term steps fused (3-D 7-point operators,
+// k >= 5).  T: the step precision (double, or float in mixed mode with r32 =
+// (float) rr already made); the last step writes the FP64 output with the
+// dot product / scaling.  Four step buffers rotate: a pair writes s_j and
+// s_{j+1} to the two that hold neither input.
+template <typename T>
+void enqueue_poly_pairs(pp_op_s *op, const double *rr, const T *rT, T *const (&buf)[4], double *zout, int fin,
+                        bool scale)
+{
+    const int k = op->k;
+    launch_step<T, T, T, T, 1>(op, rT, rT, (const T *)nullptr, buf[0], step_coef(op, 1), ppk::FIN_NONE, false);
+    launch_step<T, T, T, T, 2>(op, buf[0], rT, (const T *)nullptr, buf[1], step_coef(op, 2), ppk::FIN_NONE, false);
+    int ic = 1, io = 0;  // buffers of s_{j-1} and s_{j-2}
+    int j = 3;
+    for (; j + 1 <= k - 1; j += 2) {
+        int a = -1, b = -1;
+        for (int q = 0; q < 4; ++q)
+            if (q != ic && q != io) (a < 0 ? a : b) = q;
+        launch_pair<T>(op, buf[ic], buf[io], rT, buf[a], buf[b], step_coef(op, j), step_coef(op, j + 1));
+        io = a;
+        ic = b;
+    }
+    if (j <= k - 1) {  // one three-term step left before the last: in place over s_{j-2}
+        launch_step<T, T, T, T, 3>(op, buf[ic], rT, buf[io], buf[io], step_coef(op, j), ppk::FIN_NONE, false);
+        std::swap(ic, io);
+        ++j;
+    }
+    launch_step<T, T, double, double, 3>(op, buf[ic], rr, buf[io], zout, step_coef(op, k), fin, scale);
+}
+
 // z = p_k(A-hat) rr, rr in the scaled space (double).  fin: FIN_NONE,
 // FIN_RHO0 or FIN_RHO (reduce rr.z).  scale: multiply the output by dis
 // (pp_apply under Jacobi).  r32src: FP32 copy of rr already made (mixed).
@@ -500,6 +581,13 @@ void enqueue_poly(pp_op_s *op, const double *rr, double *zout, int fin, bool sca
         return;
     }
     const int k = op->k;
+    // fused pairs in FP64 only: in FP32 the bytes saved do not pay for the halo
+    // rows and the lower occupancy (measured)
+    if (op->s2 && op->two_step && k >= 5 && !op->mixed()) {
+        double *const buf[4] = {op->sA, op->sB, op->sC, op->sD};
+        enqueue_poly_pairs<double>(op, rr, rr, buf, zout, fin, scale);
+        return;
+    }
     if (k == 0) {
         // z = rr / theta (and the dot when requested)
         hipLaunchKernelGGL((ppk::k_scale<double, double>), dim3(op->grid_elems(op->n)), dim3(BLOCK), 0,
@@ -846,6 +934,7 @@ pp_status pp_set_option(pp_op op, int key, int64_t value)
         op->driver = (int)value;
         return PP_OK;
     case PP_OPT_NT_LOADS: op->ntload = value != 0; return PP_OK;
+    case PP_OPT_TWO_STEP: op->two_step = value != 0; return PP_OK;
     default: return fail(PP_ERR_ARG, "unknown option");
     }
 }
@@ -854,6 +943,7 @@ pp_status pp_get_stats(pp_op op, pp_stats *st)
 {
     if (!op || !st) return fail(PP_ERR_ARG, "NULL argument");
     *st = op->stats;
+    st->two_step = (op->s2 && op->two_step && op->form == 0) ? 1 : 0;
     return PP_OK;
 }
 

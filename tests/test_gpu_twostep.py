@@ -1,0 +1,129 @@
+"""GPU checks of the fused pairs of Chebyshev steps on 3-D 7-point operators.
+
+The pair kernel computes the same terms per row as the one-step kernels, so
+p_k(A) r with pairs and without them agree to a few ulps (relative 1e-14,
+FP64; the FP32 mixed mode keeps one pass per step), and both match the oracle's Algorithm 2
+to 1e-12.  Box shapes cover ragged x-y tiles (30 cells + remainder, a
+remainder of one), z-ranges that are not whole chunks of 16 planes, and a
+box that is not a cube (a principal block of the first z-planes).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2208_01339_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2208_01339_amd import binding
+
+    binding.lib()
+    return binding
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def first_planes(a, N, nz):
+    """Principal block of the first nz z-planes of an N^3 operator: an N x N x nz box."""
+    m = N * N * nz
+    S = a.to_scipy()[:m, :m].tocsr()
+    S.sort_indices()
+    return W.CSR(m, m, S.indptr.astype(np.int64), S.indices.astype(np.int32), S.data)
+
+
+CASES = {
+    "poisson32": (lambda: W.poisson3d(32), False),
+    "hetero37": (lambda: W.hetero_diffusion(37, 2.0, 3), True),
+    "hetero31": (lambda: W.hetero_diffusion(31, 1.0, 4), True),  # x-y tiles of 30 and 1
+    "box23x23x9": (lambda: first_planes(W.hetero_diffusion(23, 2.0, 6), 23, 9), True),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("k,xi", [(5, 0.0), (6, 1e-3), (20, 0.0), (21, 1e-2)])
+def test_pairs_match_single_steps_and_oracle(B, name, k, xi):
+    build, jac = CASES[name]
+    a = build()
+    op = B.Operator(a=a, flags=B.PP_JACOBI if jac else 0)
+    assert B.pp_get_stats(op.handle)["two_step"] == 1
+    orc = O.Operator(a, jacobi=jac)
+    lmin, lmax = O.lanczos_bounds(orc, 20)
+    B.pp_setup(op.handle, k, lmin, lmax, xi)
+    r = W.rhs_uniform(a.n_rows, 7)
+    z2 = torch.empty(a.n_rows, dtype=torch.float64, device="cuda")
+    z1 = torch.empty_like(z2)
+    B.pp_apply(op.handle, dev(r), z2)
+    B.pp_set_option(op.handle, B.PP_OPT_TWO_STEP, 0)
+    assert B.pp_get_stats(op.handle)["two_step"] == 0
+    B.pp_apply(op.handle, dev(r), z1)
+    g2, g1 = host(z2), host(z1)
+    assert np.linalg.norm(g2 - g1) <= 1e-14 * np.linalg.norm(g1)
+    ref = O.cheb_apply(orc, k, lmin, lmax, xi, r)
+    assert np.linalg.norm(g2 - ref) <= 1e-12 * np.linalg.norm(ref)
+    op.close()
+
+
+def test_mixed_mode_keeps_single_steps(B):
+    """The FP32 polynomial runs one pass per step (fused pairs are FP64 only)."""
+    a = W.hetero_diffusion(21, 2.0, 5)
+    op = B.Operator(a=a, flags=B.PP_JACOBI | B.PP_MIXED)
+    assert B.pp_get_stats(op.handle)["two_step"] == 0
+    op.close()
+
+
+@pytest.mark.parametrize("name", ["hetero37", "box23x23x9"])
+def test_pairs_pcg_parity(B, name):
+    build, jac = CASES[name]
+    a = build()
+    op = B.Operator(a=a, flags=B.PP_JACOBI)
+    orc = O.Operator(a, jacobi=True)
+    lmin, lmax = O.lanczos_bounds(orc, 20)
+    k, xi = 12, 1e-3
+    b = W.rhs_uniform(a.n_rows, 1)
+    xo, sto = O.pcg(orc, k, lmin, lmax, xi, b, tol=1e-8, maxit=2000)
+    B.pp_setup(op.handle, k, lmin, lmax, xi)
+    x = torch.zeros(a.n_rows, dtype=torch.float64, device="cuda")
+    s, it, rel = B.pcg_solve(op.handle, dev(b), x, 1e-8, 2000)
+    assert s == B.PP_OK and abs(it - sto["iters"]) <= 2
+    x.zero_()
+    s, it2, rel2 = B.pcg_solve(op.handle, dev(b), x, 0.0, sto["iters"])
+    assert np.linalg.norm(host(x) - xo) <= 1e-10 * np.linalg.norm(xo)
+    op.close()
+
+
+def test_face_coupling_disables_pairs(B):
+    """A coupling across an x-face of the box (row x = N-1 to the next line's x = 0,
+    both ways) keeps offset 1 a stored diagonal but rules the pair kernel out."""
+    N = 12
+    A = W.poisson3d(N).to_scipy().tolil()
+    i = N - 1  # (x = N-1, y = 0, z = 0) -> (0, 1, 0)
+    A[i, i + 1] = -0.5
+    A[i + 1, i] = -0.5
+    A = A.tocsr()
+    A.sort_indices()
+    a = W.CSR(N ** 3, N ** 3, A.indptr.astype(np.int64), A.indices.astype(np.int32), A.data)
+    op = B.Operator(a=a)
+    st = B.pp_get_stats(op.handle)
+    assert st["diagonals"] == 4 and st["two_step"] == 0
+    orc = O.Operator(a)
+    lmin, lmax = O.lanczos_bounds(orc, 20)
+    B.pp_setup(op.handle, 9, lmin, lmax, 0.0)
+    r = W.rhs_uniform(a.n_rows, 3)
+    z = torch.empty(a.n_rows, dtype=torch.float64, device="cuda")
+    B.pp_apply(op.handle, dev(r), z)
+    ref = O.cheb_apply(orc, 9, lmin, lmax, 0.0, r)
+    assert np.linalg.norm(host(z) - ref) <= 1e-12 * np.linalg.norm(ref)
+    op.close()
