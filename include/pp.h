@@ -218,6 +218,9 @@ typedef struct {
     int32_t diagonals;      /* stored diagonals of the symmetric diagonal part      */
                             /* (0 = every entry in the slice layout)                */
     int32_t two_step;       /* 1 when pairs of Chebyshev steps share one pass        */
+    double pair_ms;         /* summed device time of the fused-pair launches (events */
+                            /* around each run of pairs; PP_OPT_TIMING = 1)           */
+    int64_t pair_launches;  /* fused-pair launches covered by pair_ms                */
 } pp_stats;
 
 PP_API pp_status pp_get_stats(pp_op op, pp_stats *st);
@@ -233,9 +236,9 @@ enum {
                             /* diagonals), 0 = plain; default 1 from 2^22 rows on       */
     PP_OPT_TWO_STEP = 6     /* 1 (default) = on 3-D 7-point operators (stored diagonals at  */
                             /* offsets 0, 1, N, N^2, no coupling across the box's x- and   */
-                            /* y-faces) fuse pairs of Chebyshev steps into one pass        */
-                            /* (x-y tiles with a recomputed one-cell ring, z-march through */
-                            /* LDS), 0 = one pass per step                                */
+                            /* y-faces, N <= 256) fuse pairs of FP64 Chebyshev steps into  */
+                            /* one pass (tiles of whole x-lines with one recomputed halo   */
+                            /* line each side, marching up z), 0 = one pass per step      */
 };
 PP_API pp_status pp_set_option(pp_op op, int key, int64_t value);
 

@@ -45,6 +45,7 @@ class pp_stats(C.Structure):
         ("cheb_steps", C.c_int64), ("solve_ms", C.c_double), ("n", C.c_int64),
         ("nnz_stored", C.c_int64), ("nnz_matrix", C.c_int64), ("driver", C.c_int32),
         ("grid", C.c_int32), ("diagonals", C.c_int32), ("two_step", C.c_int32),
+        ("pair_ms", C.c_double), ("pair_launches", C.c_int64),
     ]
 
 

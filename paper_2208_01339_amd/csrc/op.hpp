@@ -62,6 +62,10 @@ struct pp_op_s {
     int32_t *hflag = nullptr;   // pinned, 2 slots
     hipEvent_t flag_ev[2] = {nullptr, nullptr};
     std::vector<hipEvent_t> tev;  // timing events (pairs)
+    std::vector<hipEvent_t> pev;  // timing events around the fused-pair launches
+    size_t pev_i = 0;             // pev used in the current solve
+    int pairs_per_poly = 0;       // fused-pair launches in one polynomial application
+    bool time_pairs = false;      // record pev (a timed solve is being enqueued)
     hipEvent_t solve_ev[2] = {nullptr, nullptr};
     // polynomial
     bool setup_done = false;
@@ -142,5 +146,7 @@ struct pp_op_s {
         for (auto &e : solve_ev) if (e) { (void)hipEventDestroy(e); e = nullptr; }
         for (auto &e : tev) (void)hipEventDestroy(e);
         tev.clear();
+        for (auto &e : pev) (void)hipEventDestroy(e);
+        pev.clear();
     }
 };

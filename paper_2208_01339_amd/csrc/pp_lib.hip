@@ -529,16 +529,26 @@ void launch_pair(pp_op_s *op, const T *sm1, const T *sm2, const T *r, T *o1, T *
     g.nty = (int)((g.N + ppk::S2_TY - 1) / ppk::S2_TY);
     g.nzc = (int)((g.NZ + ppk::S2_ZC - 1) / ppk::S2_ZC);
     const dim3 grid((unsigned)(g.nty * g.nzc));
-    const size_t lds = sizeof(T) * 3 * ppk::S2_RY * (size_t)g.N;
     const T *dv = sizeof(T) == 4 ? (const T *)op->dval32 : (const T *)op->dval;
+    const size_t lds = sizeof(T) * (2 * ppk::S2_RY + (ppk::S2_SL ? 2 * (ppk::S2_RY + 2) : 0)) * (size_t)g.N;
     if (op->ntload)
-        hipLaunchKernelGGL((ppk::k_cheb2_stencil<T, true>), grid, dim3(BLOCK), lds, op->stream, g, dv, op->dstride,
-                           sm1, sm2, r, o1, o2, c1.cx, c1.cold, c1.cr, c1.cA, c2.cx, c2.cold, c2.cr, c2.cA,
-                           (const ppk::State *)op->st);
-    else
-        hipLaunchKernelGGL((ppk::k_cheb2_stencil<T, false>), grid, dim3(BLOCK), lds, op->stream, g, dv,
-                           op->dstride, sm1, sm2, r, o1, o2, c1.cx, c1.cold, c1.cr, c1.cA, c2.cx, c2.cold, c2.cr,
+        hipLaunchKernelGGL((ppk::k_cheb2_stencil<T, true, ppk::S2_BS, ppk::S2_SL>), grid, dim3(ppk::S2_BS), lds, op->stream, g,
+                           dv, op->dstride, sm1, sm2, r, o1, o2, c1.cx, c1.cold, c1.cr, c1.cA, c2.cx, c2.cold, c2.cr,
                            c2.cA, (const ppk::State *)op->st);
+    else
+        hipLaunchKernelGGL((ppk::k_cheb2_stencil<T, false, ppk::S2_BS, ppk::S2_SL>), grid, dim3(ppk::S2_BS), lds, op->stream, g,
+                           dv, op->dstride, sm1, sm2, r, o1, o2, c1.cx, c1.cold, c1.cr, c1.cA, c2.cx, c2.cold, c2.cr,
+                           c2.cA, (const ppk::State *)op->st);
+}
+
+hipEvent_t pair_event(pp_op_s *op)
+{
+    if (op->pev_i == op->pev.size()) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        op->pev.push_back(e);
+    }
+    return op->pev[op->pev_i++];
 }
 
 // p_k(A-hat) rr with pairs of three-term steps fused (3-D 7-point operators,
@@ -555,14 +565,20 @@ void enqueue_poly_pairs(pp_op_s *op, const double *rr, const T *rT, T *const (&b
     launch_step<T, T, T, T, 2>(op, buf[0], rT, (const T *)nullptr, buf[1], step_coef(op, 2), ppk::FIN_NONE, false);
     int ic = 1, io = 0;  // buffers of s_{j-1} and s_{j-2}
     int j = 3;
+    const bool timed = op->time_pairs && 4 <= k - 1;
+    if (timed) HIPCHK(hipEventRecord(pair_event(op), op->stream));
+    int pairs = 0;
     for (; j + 1 <= k - 1; j += 2) {
         int a = -1, b = -1;
         for (int q = 0; q < 4; ++q)
             if (q != ic && q != io) (a < 0 ? a : b) = q;
         launch_pair<T>(op, buf[ic], buf[io], rT, buf[a], buf[b], step_coef(op, j), step_coef(op, j + 1));
+        ++pairs;
         io = a;
         ic = b;
     }
+    if (timed) op->pairs_per_poly = pairs;
+    if (timed) HIPCHK(hipEventRecord(pair_event(op), op->stream));
     if (j <= k - 1) {  // one three-term step left before the last: in place over s_{j-2}
         launch_step<T, T, T, T, 3>(op, buf[ic], rT, buf[io], buf[io], step_coef(op, j), ppk::FIN_NONE, false);
         std::swap(ic, io);
@@ -1025,6 +1041,9 @@ pp_status pcg_solve(pp_op op, const double *b, double *x, double tol, int maxit,
         const bool want_persist = op->driver == 1 && op->lr_p == 0 && op->form == 0;
         bool persisted = want_persist && persistent_solve(op, b, x, tol, maxit);
         size_t ev_i = 0;
+        op->pev_i = 0;
+        op->pairs_per_poly = 0;
+        op->time_pairs = op->timing;
         if (!persisted) {
             hipLaunchKernelGGL(ppk::k_init_scale, dim3(ge), dim3(BLOCK), 0, op->stream, n, b, (const double *)x,
                                (const double *)op->dis, op->bh, op->xh, op->partials, op->st);
@@ -1095,8 +1114,11 @@ pp_status pcg_solve(pp_op op, const double *b, double *x, double tol, int maxit,
         float ms = 0;
         HIPCHK(hipEventElapsedTime(&ms, op->solve_ev[0], op->solve_ev[1]));
         op->stats.solve_ms = ms;
+        op->time_pairs = false;
         op->stats.cheb_ms = 0;
         op->stats.cheb_steps = 0;
+        op->stats.pair_ms = 0;
+        op->stats.pair_launches = 0;
         op->stats.driver = persisted ? 1 : 0;
         if (!persisted) op->stats.grid = gs;
         if (op->timing && !s.zero_b) {
@@ -1109,6 +1131,17 @@ pp_status pcg_solve(pp_op op, const double *b, double *x, double tol, int maxit,
             }
             op->stats.cheb_ms = tot;
             op->stats.cheb_steps = (int64_t)op->k * polys;
+            // one run of pairs per polynomial application, in the same order
+            double pt = 0;
+            int64_t runs = 0;
+            for (int64_t i = 0; i < polys && (size_t)(2 * i + 1) < op->pev_i; ++i) {
+                float t = 0;
+                HIPCHK(hipEventElapsedTime(&t, op->pev[2 * i], op->pev[2 * i + 1]));
+                pt += t;
+                ++runs;
+            }
+            op->stats.pair_ms = pt;
+            op->stats.pair_launches = runs * op->pairs_per_poly;
         }
         return ret;
     } catch (HipError &e) {

@@ -6,14 +6,13 @@
 //   s_{j+1} = c2x s_j     + c2o s_{j-1} + c2r r + c2A (A s_j)
 //
 // Each workgroup owns S2_TY whole x-lines (contiguous rows of N cells, so the
-// HBM streams stay long) over a range of z-planes and marches up z.  For
-// every plane it computes s_j on its lines plus one halo line each side (from
-// s_{j-1} in HBM / cache) into an LDS ring of three planes, and from that
-// ring s_{j+1} one plane behind.  The operator, r and s_{j-1} are
-// thus read once for both steps; the ring cells and the planes just outside
-// the z-range are computed twice (by the neighbouring tiles too), with the
-// same arithmetic, so both copies are identical.  s_j and s_{j+1} go to two
-// fresh buffers: no input may be overwritten while neighbours still read it.
+// HBM streams stay long) over S2_ZC z-planes and marches up z.  For every
+// plane it computes s_j on its lines plus one halo line each side, and s_{j+1}
+// one plane behind.  The operator, r and s_{j-1} are read once for both steps;
+// the halo lines and the planes just outside the z-range are computed twice
+// (by the neighbouring tiles too), with the same arithmetic, so both copies
+// are identical.  s_j and s_{j+1} go to two fresh buffers: no input may be
+// overwritten while neighbours still read it.
 #pragma once
 #include "kernels.hpp"
 
@@ -21,121 +20,178 @@ namespace ppk {
 
 constexpr int S2_TY = 8;              // y-rows per tile (full x-lines, one halo row each side)
 constexpr int S2_RY = S2_TY + 2;
-constexpr int S2_ZC = 16;             // z-planes per workgroup
-constexpr int64_t S2_NMAX = 256;      // widest x-line: the ring (3 x 10 x N doubles) stays within 64 KB
+constexpr int S2_ZC = 32;             // z-planes per workgroup
+constexpr int64_t S2_NMAX = 256;      // widest x-line (sizes the per-thread register arrays)
+constexpr int S2_BS = 512;            // threads per workgroup
+constexpr bool S2_SL = true;          // in-plane neighbours of s_{j-1} from LDS
 
 struct Stencil2 {
     int64_t N, NZ, n;
     int nty, nzc;   // y-tiles and z-chunks
 };
 
-// (A v)_i over the stored diagonals with the neighbour coordinates checked:
-// the same terms, in the same order, as the one-step kernels (the couplings
-// a face-crossing index would reach are zero).
-template <typename T>
-__device__ __forceinline__ T s2_apply(const T *__restrict__ dv, int64_t ds, const Stencil2 &g,
-                                      const T *__restrict__ v, int64_t i, int64_t x, int64_t y, int64_t z)
-{
-    const int64_t N = g.N, N2 = g.N * g.N;
-    const bool xl = x > 0, xu = x + 1 < N, yl = y > 0, yu = y + 1 < N, zl = z > 0, zu = z + 1 < g.NZ;
-    // loads first (indices of absent neighbours redirected to i, values zeroed)
-    const T v0 = dv[i];
-    const T u1 = dv[ds + i], u2 = dv[2 * ds + i], u3 = dv[3 * ds + i];
-    const T l1 = dv[ds + (xl ? i - 1 : i)], l2 = dv[2 * ds + (yl ? i - N : i)], l3 = dv[3 * ds + (zl ? i - N2 : i)];
-    const T xc = v[i];
-    const T x1m = v[xl ? i - 1 : i], x1p = v[xu ? i + 1 : i];
-    const T x2m = v[yl ? i - N : i], x2p = v[yu ? i + N : i];
-    const T x3m = v[zl ? i - N2 : i], x3p = v[zu ? i + N2 : i];
-    T acc = (T)0;
-    if (xl) acc += l1 * x1m;
-    acc += (xu ? u1 : (T)0) * x1p;
-    if (yl) acc += l2 * x2m;
-    acc += (yu ? u2 : (T)0) * x2p;
-    if (zl) acc += l3 * x3m;
-    acc += (zu ? u3 : (T)0) * x3p;
-    return acc + v0 * xc;
-}
+template <int BS>
+constexpr int s2_cells_per_thread() { return (S2_RY * (int)S2_NMAX + BS - 1) / BS; }
 
-// Dynamic LDS: 3 planes of S2_RY x N values (the ring of s_j).
-template <typename T, bool NT>
-static __global__ __launch_bounds__(BLOCK) void k_cheb2_stencil(Stencil2 g, const T *__restrict__ dv, int64_t ds,
-                                                                const T *__restrict__ sm1, const T *__restrict__ sm2,
-                                                                const T *__restrict__ r, T *__restrict__ out1,
-                                                                T *__restrict__ out2, double c1x, double c1o,
-                                                                double c1r, double c1A, double c2x, double c2o,
-                                                                double c2r, double c2A, const State *st)
+// Thread t owns the cells c = t + BS m of the tile's plane (S2_RY x N) on
+// every plane.  While it computes s_j on plane z it holds row z of the
+// operator in registers, so once s_j(z) is in LDS it forms the part of
+// (A s_j) on plane z that needs only planes z-1 and z (the x-, y- and -z
+// terms, in the order of the one-step kernels) and adds the +z term and the
+// diagonal term one plane later, when s_j(z+1) exists.  s_{j-1} on planes z-1
+// and z and the coupling to plane z-1 travel in registers from plane to
+// plane, so nothing is read twice apart from the in-plane neighbours of
+// s_{j-1} (cache hits).  LDS: two planes of s_j (double buffer, one barrier
+// per plane).  Absent neighbours enter as zero couplings times a clamped
+// (in-range) value.
+template <typename T, bool NT, int BS, bool SL>
+static __global__ __launch_bounds__(BS) void k_cheb2_stencil(Stencil2 g, const T *__restrict__ dv, int64_t ds,
+                                                         const T *__restrict__ sm1, const T *__restrict__ sm2,
+                                                         const T *__restrict__ r, T *__restrict__ out1,
+                                                         T *__restrict__ out2, double c1x, double c1o, double c1r,
+                                                         double c1A, double c2x, double c2o, double c2r,
+                                                         double c2A, const State *st)
 {
     if (st != nullptr && st->done) return;
+    constexpr int MM = s2_cells_per_thread<BS>();
     extern __shared__ __align__(16) unsigned char s2_lds[];
-    T *ring = (T *)s2_lds;
     const int G = (int)gridDim.x;
     const int L = xcd_remap((int)blockIdx.x, G);
     const int ty = L % g.nty, tz = L / g.nty;
-    const int64_t N = g.N, N2 = N * N;
-    const int64_t y0 = (int64_t)ty * S2_TY - 1;  // region row 0
-    const int64_t z0 = (int64_t)tz * S2_ZC, z1 = z0 + S2_ZC < g.NZ ? z0 + S2_ZC : g.NZ;
-    const int64_t plane_cells = (int64_t)S2_RY * N;
+    const int64_t N = g.N, N2 = N * N, NZ = g.NZ;
+    const int64_t y0 = (int64_t)ty * S2_TY - 1;
+    const int64_t z0 = (int64_t)tz * S2_ZC, z1 = z0 + S2_ZC < NZ ? z0 + S2_ZC : NZ;
+    const int64_t cells = (int64_t)S2_RY * N;
     const T a1x = (T)c1x, a1o = (T)c1o, a1r = (T)c1r, a1A = (T)c1A;
     const T a2x = (T)c2x, a2o = (T)c2o, a2r = (T)c2r, a2A = (T)c2A;
+    // carried per owned cell
+    T s_c[MM], s_m[MM];  // s_{j-1} on planes z and z-1
+    T u3p[MM];           // coupling of plane z-1 to plane z (= the -z coupling of plane z)
+    T v0p[MM], rp[MM], sjp[MM], part[MM];  // plane z-1: diagonal, r, s_j, partial (A s_j)
+#pragma unroll
+    for (int m = 0; m < MM; ++m) {
+        const int64_t c = threadIdx.x + (int64_t)BS * m;
+        const int64_t ly = c / N, x = c - ly * N, y = y0 + ly;
+        const bool rowok = c < cells && y >= 0 && y < N;
+        const int64_t za = z0 - 1, zb = z0 - 2;
+        s_c[m] = rowok && za >= 0 ? sm1[x + N * (y + N * za)] : (T)0;
+        s_m[m] = rowok && zb >= 0 ? sm1[x + N * (y + N * zb)] : (T)0;
+        u3p[m] = rowok && zb >= 0 ? dv[3 * ds + x + N * (y + N * zb)] : (T)0;
+        v0p[m] = rp[m] = sjp[m] = part[m] = (T)0;
+        if constexpr (SL)
+            if (c < cells) ((T *)s2_lds + 2 * cells)[c + N] = s_c[m];
+    }
+    // s_{j-1} planes in LDS (SL): rows -1 .. S2_RY of the tile, two buffers
+    T *const sl0 = (T *)s2_lds + 2 * cells;
+    const int64_t scells = cells + 2 * N;
+    if constexpr (SL) {
+        for (int64_t e = threadIdx.x; e < 2 * N; e += BS) {
+            const int64_t row = e < N ? -1 : S2_RY, x = e < N ? e : e - N, y = y0 + row, za = z0 - 1;
+            sl0[(row + 1) * N + x] = y >= 0 && y < N && za >= 0 ? sm1[x + N * (y + N * za)] : (T)0;
+        }
+        __syncthreads();
+    }
+    int buf = 0;
     for (int64_t zz = z0 - 1; zz <= z1; ++zz) {
-        // s_j on plane zz over the tile's rows plus one halo row each side
-        T *plane = ring + ((zz + 3) % 3) * plane_cells;
-        for (int64_t c = threadIdx.x; c < plane_cells; c += BLOCK) {
+        const bool zin = zz >= 0 && zz < NZ;
+        const bool fin2 = zz - 1 >= z0 && zz - 1 < z1;  // finish s_{j+1} on plane zz-1
+        const bool part_now = zz >= z0 && zz < z1;      // partial sums for plane zz
+        T *pl = (T *)s2_lds + buf * cells;
+        T cur[MM], xp[MM], nl1[MM], nu1[MM], nl2[MM], nu2[MM], nv0[MM], nu3[MM], nr[MM];
+#pragma unroll
+        for (int m = 0; m < MM; ++m) {
+            const int64_t c = threadIdx.x + (int64_t)BS * m;
             const int64_t ly = c / N, x = c - ly * N, y = y0 + ly;
-            const bool valid = y >= 0 && y < N && zz >= 0 && zz < g.NZ;
+            const bool rowok = c < cells && y >= 0 && y < N;
+            const bool interior = ly >= 1 && ly <= S2_TY && rowok;
             T sj = (T)0;
-            if (valid) {
+            xp[m] = rowok && zz + 1 < NZ ? sm1[x + N * (y + N * (zz + 1))] : (T)0;
+            nl1[m] = nu1[m] = nl2[m] = nu2[m] = nv0[m] = nu3[m] = nr[m] = (T)0;
+            if (rowok && zin) {
                 const int64_t i = x + N * (y + N * zz);
-                const T ri = r[i];  // cached: the s_{j+1} pass re-reads it one plane later
-                const T xs = sm1[i];
+                const bool xl = x > 0, xu = x + 1 < N, yl = y > 0, yu = y + 1 < N, zl = zz > 0, zu = zz + 1 < NZ;
+                const T v0 = dv[i];
+                const T u1 = dv[ds + i], u2 = dv[2 * ds + i], u3 = dv[3 * ds + i];
+                const T l1 = dv[ds + (xl ? i - 1 : i)], l2 = dv[2 * ds + (yl ? i - N : i)];
+                const T ri = r[i];
                 const T so = ldm<NT>(sm2 + i);
-                const T a = s2_apply<T>(dv, ds, g, sm1, i, x, y, zz);
+                T x1m, x1p, x2m, x2p;
+                if constexpr (SL) {
+                    const T *sp = sl0 + buf * scells + c + N;
+                    x1m = sp[xl ? -1 : 0];
+                    x1p = sp[xu ? 1 : 0];
+                    x2m = sp[-N];
+                    x2p = sp[N];
+                } else {
+                    x1m = sm1[xl ? i - 1 : i];
+                    x1p = sm1[xu ? i + 1 : i];
+                    x2m = sm1[yl ? i - N : i];
+                    x2p = sm1[yu ? i + N : i];
+                }
+                const T xs = s_c[m];
+                T acc = (T)0;
+                acc += (xl ? l1 : (T)0) * x1m;
+                acc += (xu ? u1 : (T)0) * x1p;
+                acc += (yl ? l2 : (T)0) * x2m;
+                acc += (yu ? u2 : (T)0) * x2p;
+                acc += (zl ? u3p[m] : (T)0) * s_m[m];
+                acc += (zu ? u3 : (T)0) * xp[m];
+                const T a = acc + v0 * xs;
                 T o = a1A * a + a1r * ri;
                 o += a1x * xs;
                 o += a1o * so;
                 sj = o;
-                if (ly >= 1 && ly <= S2_TY && zz >= z0 && zz < z1) {
+                if (interior && zz >= z0 && zz < z1) {
                     if constexpr (NT) __builtin_nontemporal_store(sj, out1 + i);
                     else out1[i] = sj;
                 }
+                nl1[m] = l1; nu1[m] = u1; nl2[m] = l2; nu2[m] = u2; nv0[m] = v0; nu3[m] = u3; nr[m] = ri;
             }
-            plane[c] = sj;
+            if (fin2 && interior) {
+                const int64_t i2 = x + N * (y + N * (zz - 1));
+                const T acc2 = part[m] + (zz < NZ ? u3p[m] : (T)0) * sj;
+                const T a2 = acc2 + v0p[m] * sjp[m];
+                T o2 = a2A * a2 + a2r * rp[m];
+                o2 += a2x * sjp[m];
+                o2 += a2o * s_m[m];
+                if constexpr (NT) __builtin_nontemporal_store(o2, out2 + i2);
+                else out2[i2] = o2;
+            }
+            cur[m] = sj;
+            if (c < cells) pl[c] = sj;
+            if constexpr (SL)
+                if (c < cells) sl0[(buf ^ 1) * scells + c + N] = xp[m];
         }
-        __syncthreads();
-        // s_{j+1} on plane zz - 1 (tile rows only), from the ring
-        const int64_t zm = zz - 1;
-        if (zm >= z0 && zm < z1) {
-            const T *pc = ring + ((zm + 3) % 3) * plane_cells;
-            const T *pl = ring + ((zm + 2) % 3) * plane_cells;
-            const T *pu = ring + ((zm + 4) % 3) * plane_cells;
-            for (int64_t c = N + threadIdx.x; c < (int64_t)(S2_TY + 1) * N; c += BLOCK) {
-                const int64_t ly = c / N, x = c - ly * N, y = y0 + ly;
-                if (y >= N) continue;
-                const int64_t i = x + N * (y + N * zm);
-                const bool xl = x > 0, xu = x + 1 < N, yl = y > 0, yu = y + 1 < N, zl = zm > 0, zu = zm + 1 < g.NZ;
-                const T v0 = dv[i];
-                const T u1 = dv[ds + i], u2 = dv[2 * ds + i], u3 = dv[3 * ds + i];
-                const T l1 = dv[ds + (xl ? i - 1 : i)], l2 = dv[2 * ds + (yl ? i - N : i)],
-                        l3 = dv[3 * ds + (zl ? i - N2 : i)];
-                const T ri = r[i];
-                const T so = sm1[i];
-                const T xc = pc[c];
-                T acc = (T)0;
-                if (xl) acc += l1 * pc[c - 1];
-                acc += (xu ? u1 : (T)0) * pc[xu ? c + 1 : c];
-                if (yl) acc += l2 * pc[c - N];
-                acc += (yu ? u2 : (T)0) * pc[c + N];
-                if (zl) acc += l3 * pl[c];
-                acc += (zu ? u3 : (T)0) * pu[c];
-                const T a = acc + v0 * xc;
-                T o = a2A * a + a2r * ri;
-                o += a2x * xc;
-                o += a2o * so;
-                if constexpr (NT) __builtin_nontemporal_store(o, out2 + i);
-                else out2[i] = o;
+        if constexpr (SL) {
+            for (int64_t e = threadIdx.x; e < 2 * N; e += BS) {
+                const int64_t row = e < N ? -1 : S2_RY, x = e < N ? e : e - N, y = y0 + row;
+                sl0[(buf ^ 1) * scells + (row + 1) * N + x] =
+                    y >= 0 && y < N && zz + 1 < NZ ? sm1[x + N * (y + N * (zz + 1))] : (T)0;
             }
         }
         __syncthreads();
+#pragma unroll
+        for (int m = 0; m < MM; ++m) {
+            const int64_t c = threadIdx.x + (int64_t)BS * m;
+            const int64_t ly = c / N, x = c - ly * N, y = y0 + ly;
+            T pn = (T)0;
+            if (part_now && ly >= 1 && ly <= S2_TY && c < cells && y < N) {
+                const bool xl = x > 0, xu = x + 1 < N, yl = y > 0, yu = y + 1 < N, zl = zz > 0;
+                pn += (xl ? nl1[m] : (T)0) * pl[xl ? c - 1 : c];
+                pn += (xu ? nu1[m] : (T)0) * pl[xu ? c + 1 : c];
+                pn += (yl ? nl2[m] : (T)0) * pl[c - N];
+                pn += (yu ? nu2[m] : (T)0) * pl[c + N];
+                pn += (zl ? u3p[m] : (T)0) * sjp[m];
+            }
+            part[m] = pn;
+            v0p[m] = nv0[m];
+            rp[m] = nr[m];
+            sjp[m] = cur[m];
+            u3p[m] = nu3[m];
+            s_m[m] = s_c[m];
+            s_c[m] = xp[m];
+        }
+        buf ^= 1;
     }
 }
 

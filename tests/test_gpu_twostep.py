@@ -3,9 +3,10 @@
 The pair kernel computes the same terms per row as the one-step kernels, so
 p_k(A) r with pairs and without them agree to a few ulps (relative 1e-14,
 FP64; the FP32 mixed mode keeps one pass per step), and both match the oracle's Algorithm 2
-to 1e-12.  Box shapes cover ragged x-y tiles (30 cells + remainder, a
-remainder of one), z-ranges that are not whole chunks of 16 planes, and a
-box that is not a cube (a principal block of the first z-planes).
+to 1e-12.  Box shapes cover ragged y-tiles (tiles of 8 lines: remainders of
+5 and 7), z-ranges that are not whole chunks of 32 planes (37 planes; 33,
+so that the last chunk holds one plane), and boxes that are not cubes
+(principal blocks of the first z-planes).
 """
 import numpy as np
 import pytest
@@ -49,6 +50,7 @@ CASES = {
     "hetero37": (lambda: W.hetero_diffusion(37, 2.0, 3), True),
     "hetero31": (lambda: W.hetero_diffusion(31, 1.0, 4), True),  # x-y tiles of 30 and 1
     "box23x23x9": (lambda: first_planes(W.hetero_diffusion(23, 2.0, 6), 23, 9), True),
+    "box40x40x33": (lambda: first_planes(W.hetero_diffusion(40, 2.0, 9), 40, 33), True),
 }
 
 
@@ -126,4 +128,30 @@ def test_face_coupling_disables_pairs(B):
     B.pp_apply(op.handle, dev(r), z)
     ref = O.cheb_apply(orc, 9, lmin, lmax, 0.0, r)
     assert np.linalg.norm(host(z) - ref) <= 1e-12 * np.linalg.norm(ref)
+    op.close()
+
+
+def test_pair_timing_stats(B):
+    """With PP_OPT_TIMING the solve reports the fused-pair launches it timed:
+    floor((k - 3) / 2) per polynomial application, one application per iteration."""
+    a = W.hetero_diffusion(24, 2.0, 2)
+    op = B.Operator(a=a, flags=B.PP_JACOBI)
+    orc = O.Operator(a, jacobi=True)
+    lmin, lmax = O.lanczos_bounds(orc, 20)
+    b = dev(W.rhs_uniform(a.n_rows, 3))
+    x = torch.zeros(a.n_rows, dtype=torch.float64, device="cuda")
+    for k in (12, 13):
+        B.pp_setup(op.handle, k, lmin, lmax, 0.0)
+        B.pp_set_option(op.handle, B.PP_OPT_TIMING, 1)
+        x.zero_()
+        s, it, _ = B.pcg_solve(op.handle, b, x, 1e-8, 500)
+        st = B.pp_get_stats(op.handle)
+        assert s == B.PP_OK and it > 0
+        assert st["pair_launches"] == it * ((k - 3) // 2)
+        assert 0 < st["pair_ms"] < st["cheb_ms"]
+        B.pp_set_option(op.handle, B.PP_OPT_TIMING, 0)
+        x.zero_()
+        B.pcg_solve(op.handle, b, x, 1e-8, 500)
+        st = B.pp_get_stats(op.handle)
+        assert st["pair_launches"] == 0 and st["pair_ms"] == 0
     op.close()
