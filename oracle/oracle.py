@@ -67,6 +67,13 @@ def lib():
         L.orc_lanczos.restype = C.c_int
         L.orc_lanczos.argtypes = [P, C.c_int, P, P]
         L.orc_fmix32_start.argtypes = [C.c_int64, P]
+        L.orc_dfn_factor.restype = C.c_int
+        L.orc_dfn_factor.argtypes = [P]
+        L.orc_dfn_ainv.argtypes = [P, P, P]
+        L.orc_dfn_su.argtypes = [P, P, P]
+        L.orc_dfn_diag.argtypes = [P, P]
+        L.orc_dfn_rhs.argtypes = [P, P, P]
+        L.orc_dfn_recover.argtypes = [P, P, P, P, P]
         _lib = L
     return _lib
 
@@ -77,8 +84,16 @@ class _OpStruct(C.Structure):
         ("arp", C.c_void_p), ("aci", C.c_void_p), ("av", C.c_void_p),
         ("nt", C.c_int64), ("crp", C.c_void_p), ("cci", C.c_void_p), ("cv", C.c_void_p),
         ("m", C.c_void_p), ("dis", C.c_void_p), ("work_n", C.c_void_p), ("work_nt", C.c_void_p),
-        ("n_apply", C.c_int64),
+        ("n_apply", C.c_int64), ("dfn", C.c_void_p),
     ]
+
+
+class _DfnStruct(C.Structure):
+    _fields_ = [("n_frac", C.c_int64), ("G", C.c_int64), ("nf", C.c_int64), ("nh", C.c_int64),
+                ("nu", C.c_int64)] + [
+        (nm + sfx, C.c_void_p) for nm in ("a", "gh", "c", "b", "gu") for sfx in ("rp", "ci", "v")] + [
+        ("alpha", C.c_double), ("L", C.c_void_p), ("w1", C.c_void_p), ("w2", C.c_void_p),
+        ("w3", C.c_void_p), ("w4", C.c_void_p), ("wu", C.c_void_p)]
 
 
 class _PcgStats(C.Structure):
@@ -165,6 +180,84 @@ class Operator:
             return self.apply(x)
         finally:
             self._s.dis = saved
+
+
+class DfnOperator(Operator):
+    """The DFN Schur complement S_u(alpha) of section 4.1, applied by
+    Algorithm 3 with the exact (banded) Cholesky factor of A; with ``jacobi``
+    the operator is D_S^{-1/2} S_u D_S^{-1/2}, D_S = diag(S_u) by Algorithm 4.
+
+    ``parts`` carries the CSR blocks ``a, gh, c, b, gu``, ``alpha``, ``n_frac``
+    and ``grid`` (each fracture a block of grid^2 rows of A and G^h).  Every
+    routine of this module that takes an ``Operator`` takes this one.
+    """
+
+    def __init__(self, parts, jacobi: bool = True):
+        G = int(parts.grid)
+        nf = G * G
+        nh = int(len(parts.a.rowptr) - 1)
+        nu = int(len(parts.gu.rowptr) - 1)
+        self.n = nu
+        self.kind = 2
+        self._keep = []
+        d = _DfnStruct()
+        d.n_frac, d.G, d.nf, d.nh, d.nu = int(parts.n_frac), G, nf, nh, nu
+        for nm in ("a", "gh", "c", "b", "gu"):
+            m = getattr(parts, nm)
+            rp = np.ascontiguousarray(m.rowptr, dtype=np.int64)
+            ci = np.ascontiguousarray(m.col, dtype=np.int32)
+            v = _f64(m.val)
+            self._keep += [rp, ci, v]
+            setattr(d, nm + "rp", _p(rp).value)
+            setattr(d, nm + "ci", _p(ci).value)
+            setattr(d, nm + "v", _p(v).value)
+        d.alpha = float(parts.alpha)
+        self.L = np.zeros(nh * (G + 1))
+        self._w = [np.zeros(nh) for _ in range(4)] + [np.zeros(nu)]
+        d.L = _p(self.L).value
+        d.w1, d.w2, d.w3, d.w4, d.wu = (_p(w).value for w in self._w)
+        self._d = d
+        self.nh = nh
+        if lib().orc_dfn_factor(C.byref(d)) != OK:
+            raise ValueError("A is not block diagonal within the band, or not SPD")
+        self._work_n = np.zeros(nu)
+        s = _OpStruct()
+        s.kind = 2
+        s.n = nu
+        s.work_n = _p(self._work_n)
+        s.dfn = C.cast(C.pointer(d), C.c_void_p)
+        self._s = s
+        self.nt = 0
+        self.jacobi = bool(jacobi)
+        self.dis = None
+        if jacobi:
+            dd = self.diag_raw()
+            if not np.all(dd > 0):
+                raise ValueError("diag(S_u) must be positive")
+            self.dis = 1.0 / np.sqrt(dd)
+            s.dis = _p(self.dis)
+
+    def ainv(self, b) -> np.ndarray:
+        """A^{-1} b with the Cholesky factor."""
+        b = _f64(b)
+        x = np.empty(self.nh)
+        lib().orc_dfn_ainv(C.byref(self._d), _p(b), _p(x))
+        return x
+
+    def rhs(self, q) -> np.ndarray:
+        """r = W^T M^{-1} (q, 0) = a B^T A^{-1} q - C^T A^{-1} G^h A^{-1} q (unscaled)."""
+        q = _f64(q)
+        r = np.empty(self.n)
+        lib().orc_dfn_rhs(C.byref(self._d), _p(q), _p(r))
+        return r
+
+    def recover(self, q, u):
+        """(h, p) = (A^{-1} (q + C u), A^{-1} (a B u - G^h h))."""
+        q, u = _f64(q), _f64(u)
+        h = np.empty(self.nh)
+        p = np.empty(self.nh)
+        lib().orc_dfn_recover(C.byref(self._d), _p(q), _p(u), _p(h), _p(p))
+        return h, p
 
 
 def csr_matvec(a, x) -> np.ndarray:

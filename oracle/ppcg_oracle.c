@@ -39,14 +39,37 @@
  *                    eigenvalues alpha, beta that section 2 assumes known.
  *   orc_fmix32_start Lanczos start vector from the MurmurHash3 32-bit
  *                    finaliser of the row index.
+ *   orc_dfn_*        the DFN Schur complement of section 4.1 (operator kind
+ *                    2): the exact Cholesky factor of the block-diagonal A
+ *                    (orc_dfn_factor), y = S_u r by Algorithm 3 (used by
+ *                    orc_op_apply), diag(S_u) by Algorithm 4 (orc_op_diag),
+ *                    the reduced right-hand side r = W^T M^{-1} f_1 and the
+ *                    recovery of h and p after the solve for u.
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
+/* Blocks of the DFN system (section 4.1, eq. (sys)) in the unknowns (h, u, p):
+ * A (n_h x n_h, block diagonal SPD, one block of nf = G*G rows per fracture,
+ * entries within distance G of the diagonal), G^h (n_h x n_h, same blocks),
+ * C, B (n_h x n_u), G^u (n_u x n_u), the scalar alpha.  All CSR. */
 typedef struct {
-    int32_t kind;          /* 0 = CSR matrix, 1 = Schur-shaped operator          */
+    int64_t n_frac, G, nf, nh, nu;
+    const int64_t *arp; const int32_t *aci; const double *av;
+    const int64_t *ghrp; const int32_t *ghci; const double *ghv;
+    const int64_t *crp; const int32_t *cci; const double *cv;
+    const int64_t *brp; const int32_t *bci; const double *bv;
+    const int64_t *gurp; const int32_t *guci; const double *guv;
+    double alpha;
+    double *L;                 /* band factor, row-major: L[i (G+1) + k] = L(i, i-k) */
+    double *w1, *w2, *w3, *w4; /* scratch, n_h doubles each                         */
+    double *wu;                /* scratch, n_u doubles                               */
+} orc_dfn;
+
+typedef struct {
+    int32_t kind;          /* 0 = CSR matrix, 1 = Schur-shaped, 2 = DFN S_u      */
     int32_t pad0;
     int64_t n;             /* order of the operator                              */
     const int64_t *arp;    /* A (or A_ff): CSR row pointers, n + 1               */
@@ -61,6 +84,7 @@ typedef struct {
     double *work_n;        /* scratch, n doubles                                 */
     double *work_nt;       /* scratch, nt doubles (Schur only)                   */
     int64_t n_apply;       /* operator applications performed (counter)          */
+    orc_dfn *dfn;          /* kind 2: the DFN blocks and factor                  */
 } orc_op;
 
 enum { ORC_OK = 0, ORC_NOT_CONVERGED = 1, ORC_BREAKDOWN = 2, ORC_ERR_ARG = -1 };
@@ -91,9 +115,181 @@ void orc_csr_matvec(int64_t n, const int64_t *rp, const int32_t *ci, const doubl
     }
 }
 
-/* y = op x (unscaled).  Schur: y = A_ff x + C^T (M^{-1} (C x)). */
+/* ------------------------------------------------------------------------ */
+/* DFN Schur complement (section 4.1)                                        */
+/* ------------------------------------------------------------------------ */
+
+/* y = M^T x for a CSR matrix M with n rows (y has M's column count, zeroed here). */
+static void csr_tmatvec(int64_t n, int64_t ncol, const int64_t *rp, const int32_t *ci, const double *v,
+                        const double *x, double *y)
+{
+    for (int64_t j = 0; j < ncol; ++j) y[j] = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p) y[ci[p]] += v[p] * x[i];
+}
+
+/* Exact Cholesky factor of A, block by block (Cholesky-Banachiewicz, by rows):
+ *   L(i,j) = (a_ij - sum_{m<j} L(i,m) L(j,m)) / L(j,j),   j < i
+ *   L(i,i) = sqrt(a_ii - sum_{m<i} L(i,m)^2)
+ * with m, j restricted to the band of the block.  Returns ORC_ERR_ARG when an
+ * entry of A lies outside its fracture's block or band, or a pivot is not
+ * positive (A not SPD). */
+int orc_dfn_factor(orc_dfn *d)
+{
+    const int64_t G = d->G, nf = d->nf, W = G + 1;
+    for (int64_t i = 0; i < d->nh * W; ++i) d->L[i] = 0.0;
+    for (int64_t i = 0; i < d->nh; ++i) {
+        const int64_t f0 = (i / nf) * nf;
+        for (int64_t p = d->arp[i]; p < d->arp[i + 1]; ++p) {
+            const int64_t j = d->aci[p];
+            if (j < f0 || j >= f0 + nf || j > i + G || j < i - G) return ORC_ERR_ARG;
+            if (j <= i) d->L[i * W + (i - j)] += d->av[p];
+        }
+    }
+    for (int64_t i = 0; i < d->nh; ++i) {
+        const int64_t f0 = (i / nf) * nf;
+        const int64_t j0 = i - G > f0 ? i - G : f0;
+        for (int64_t j = j0; j < i; ++j) {
+            double s = d->L[i * W + (i - j)];
+            const int64_t m0 = j - G > j0 ? j - G : j0;
+            for (int64_t m = m0; m < j; ++m) s -= d->L[i * W + (i - m)] * d->L[j * W + (j - m)];
+            d->L[i * W + (i - j)] = s / d->L[j * W];
+        }
+        double s = d->L[i * W];
+        for (int64_t m = j0; m < i; ++m) s -= d->L[i * W + (i - m)] * d->L[i * W + (i - m)];
+        if (!(s > 0.0)) return ORC_ERR_ARG;
+        d->L[i * W] = sqrt(s);
+    }
+    return ORC_OK;
+}
+
+/* x = A^{-1} b = L^{-T} (L^{-1} b), fracture by fracture (the two triangular
+ * solves of Algorithm 3).  x may alias b. */
+void orc_dfn_ainv(const orc_dfn *d, const double *b, double *x)
+{
+    const int64_t G = d->G, nf = d->nf, W = G + 1;
+    for (int64_t i = 0; i < d->nh; ++i) x[i] = b[i];
+    for (int64_t f0 = 0; f0 < d->nh; f0 += nf) {
+        /* L y = b */
+        for (int64_t i = f0; i < f0 + nf; ++i) {
+            double s = x[i];
+            const int64_t j0 = i - G > f0 ? i - G : f0;
+            for (int64_t j = j0; j < i; ++j) s -= d->L[i * W + (i - j)] * x[j];
+            x[i] = s / d->L[i * W];
+        }
+        /* L^T x = y */
+        for (int64_t i = f0 + nf - 1; i >= f0; --i) {
+            double s = x[i];
+            const int64_t j1 = i + G < f0 + nf - 1 ? i + G : f0 + nf - 1;
+            for (int64_t j = i + 1; j <= j1; ++j) s -= d->L[j * W + (j - i)] * x[j];
+            x[i] = s / d->L[i * W];
+        }
+    }
+}
+
+/* y = S_u r by Algorithm 3, with the alpha of S_u(alpha) on every product by B
+ * (the listing takes alpha = 1):
+ *   v = C r;  z = a B r;  t = A^{-1} v;  w = A^{-1} z;
+ *   z = G^u r - a B^T t - C^T w;  v = G^h t;  w = A^{-1} v;  y = z + C^T w. */
+void orc_dfn_su(orc_dfn *d, const double *r, double *y)
+{
+    const int64_t nh = d->nh, nu = d->nu;
+    double *v = d->w1, *z = d->w2, *t = d->w3, *w = d->w4, *zu = d->wu;
+    orc_csr_matvec(nh, d->crp, d->cci, d->cv, r, v);
+    orc_csr_matvec(nh, d->brp, d->bci, d->bv, r, z);
+    for (int64_t i = 0; i < nh; ++i) z[i] = d->alpha * z[i];
+    orc_dfn_ainv(d, v, t);
+    orc_dfn_ainv(d, z, w);
+    orc_csr_matvec(nu, d->gurp, d->guci, d->guv, r, zu);
+    csr_tmatvec(nh, nu, d->brp, d->bci, d->bv, t, y);   /* y = B^T t */
+    for (int64_t j = 0; j < nu; ++j) zu[j] -= d->alpha * y[j];
+    csr_tmatvec(nh, nu, d->crp, d->cci, d->cv, w, y);   /* y = C^T w */
+    for (int64_t j = 0; j < nu; ++j) zu[j] -= y[j];
+    orc_csr_matvec(nh, d->ghrp, d->ghci, d->ghv, t, v);
+    orc_dfn_ainv(d, v, w);
+    csr_tmatvec(nh, nu, d->crp, d->cci, d->cv, w, y);   /* y = C^T w */
+    for (int64_t j = 0; j < nu; ++j) y[j] = zu[j] + y[j];
+}
+
+/* diag(S_u) by Algorithm 4:  Z = A^{-1} C;  T = G^h Z - 2 a B;
+ * (D_S)_i = (G^u)_ii + z_i^T t_i, one column i at a time.  A block whose part
+ * of c_i is zero has a zero part of z_i and is not solved. */
+void orc_dfn_diag(orc_dfn *d, double *ds)
+{
+    const int64_t nh = d->nh, nu = d->nu, G = d->G, nf = d->nf, W = G + 1;
+    double *c = d->w1, *z = d->w2, *t = d->w3, *b = d->w4;
+    for (int64_t i = 0; i < nu; ++i) {
+        for (int64_t r = 0; r < nh; ++r) c[r] = 0.0, b[r] = 0.0;
+        for (int64_t r = 0; r < nh; ++r) {
+            for (int64_t p = d->crp[r]; p < d->crp[r + 1]; ++p)
+                if (d->cci[p] == i) c[r] += d->cv[p];
+            for (int64_t p = d->brp[r]; p < d->brp[r + 1]; ++p)
+                if (d->bci[p] == i) b[r] += d->bv[p];
+        }
+        /* z_i = A^{-1} c_i, block by block */
+        for (int64_t f0 = 0; f0 < nh; f0 += nf) {
+            int nonzero = 0;
+            for (int64_t r = f0; r < f0 + nf; ++r) nonzero |= c[r] != 0.0;
+            if (!nonzero) {
+                for (int64_t r = f0; r < f0 + nf; ++r) z[r] = 0.0;
+                continue;
+            }
+            for (int64_t r = f0; r < f0 + nf; ++r) {
+                double s = c[r];
+                const int64_t j0 = r - G > f0 ? r - G : f0;
+                for (int64_t j = j0; j < r; ++j) s -= d->L[r * W + (r - j)] * z[j];
+                z[r] = s / d->L[r * W];
+            }
+            for (int64_t r = f0 + nf - 1; r >= f0; --r) {
+                double s = z[r];
+                const int64_t j1 = r + G < f0 + nf - 1 ? r + G : f0 + nf - 1;
+                for (int64_t j = r + 1; j <= j1; ++j) s -= d->L[j * W + (j - r)] * z[j];
+                z[r] = s / d->L[r * W];
+            }
+        }
+        orc_csr_matvec(nh, d->ghrp, d->ghci, d->ghv, z, t);
+        for (int64_t r = 0; r < nh; ++r) t[r] = t[r] - 2.0 * d->alpha * b[r];
+        double gii = 0.0;
+        for (int64_t p = d->gurp[i]; p < d->gurp[i + 1]; ++p)
+            if (d->guci[p] == i) gii += d->guv[p];
+        ds[i] = gii + orc_dot(nh, z, t);
+    }
+}
+
+/* r = W^T M^{-1} f_1 with f_1 = (q, 0):  r = a B^T A^{-1} q - C^T A^{-1} G^h A^{-1} q. */
+void orc_dfn_rhs(orc_dfn *d, const double *q, double *r)
+{
+    const int64_t nh = d->nh, nu = d->nu;
+    double *a1 = d->w1, *g = d->w2, *a2 = d->w3;
+    orc_dfn_ainv(d, q, a1);
+    orc_csr_matvec(nh, d->ghrp, d->ghci, d->ghv, a1, g);
+    orc_dfn_ainv(d, g, a2);
+    csr_tmatvec(nh, nu, d->brp, d->bci, d->bv, a1, r);
+    csr_tmatvec(nh, nu, d->crp, d->cci, d->cv, a2, d->wu);
+    for (int64_t j = 0; j < nu; ++j) r[j] = d->alpha * r[j] - d->wu[j];
+}
+
+/* h = A^{-1} (q + C u),  p = A^{-1} (a B u - G^h h). */
+void orc_dfn_recover(orc_dfn *d, const double *q, const double *u, double *h, double *p)
+{
+    const int64_t nh = d->nh;
+    double *v = d->w1, *g = d->w2;
+    orc_csr_matvec(nh, d->crp, d->cci, d->cv, u, v);
+    for (int64_t i = 0; i < nh; ++i) v[i] = q[i] + v[i];
+    orc_dfn_ainv(d, v, h);
+    orc_csr_matvec(nh, d->brp, d->bci, d->bv, u, v);
+    orc_csr_matvec(nh, d->ghrp, d->ghci, d->ghv, h, g);
+    for (int64_t i = 0; i < nh; ++i) v[i] = d->alpha * v[i] - g[i];
+    orc_dfn_ainv(d, v, p);
+}
+
+/* y = op x (unscaled).  Schur: y = A_ff x + C^T (M^{-1} (C x)).  DFN: S_u x. */
 static void op_apply_raw(const orc_op *op, const double *x, double *y)
 {
+    if (op->kind == 2) {
+        orc_dfn_su(op->dfn, x, y);
+        return;
+    }
     orc_csr_matvec(op->n, op->arp, op->aci, op->av, x, y);
     if (op->kind == 1) {
         double *w = op->work_nt;
@@ -122,9 +318,14 @@ void orc_op_apply(orc_op *op, const double *x, double *y)
     for (int64_t i = 0; i < op->n; ++i) y[i] = op->dis[i] * y[i];
 }
 
-/* d = diag(op), unscaled.  CSR: a_ii.  Schur: (A_ff)_ii + sum_t C_ti^2 / M_t. */
+/* d = diag(op), unscaled.  CSR: a_ii.  Schur: (A_ff)_ii + sum_t C_ti^2 / M_t.
+ * DFN: Algorithm 4. */
 void orc_op_diag(const orc_op *op, double *d)
 {
+    if (op->kind == 2) {
+        orc_dfn_diag(op->dfn, d);
+        return;
+    }
     for (int64_t i = 0; i < op->n; ++i) {
         double s = 0.0;
         for (int64_t p = op->arp[i]; p < op->arp[i + 1]; ++p)

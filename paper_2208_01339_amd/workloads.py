@@ -25,6 +25,16 @@ Workloads (stand-ins for the paper's matrices, which are not public here):
   a lognormal transmissivity; ``C`` has one row per trace cell pair with +1 on
   the cell of one fracture and -1 on the matching cell of the other; ``M`` is a
   positive diagonal.  ``S`` itself is never formed.
+* ``dfn_su(...)`` -- the blocks of the paper's DFN system (section 4.1,
+  eq. (sys)): A block diagonal, one G x G 5-point finite-volume block per
+  fracture with lognormal cell permeability (harmonic faces, Dirichlet
+  boundary faces); G^h = gamma times the Neumann graph Laplacian of each
+  fracture grid (SPSD, fracture-local); traces between pairs of fractures
+  carry L flux unknowns on each side, ordered by the fracture that owns them;
+  C (fracture-local) has 1 at the owner's trace cell, B = C + E with E = -1 at
+  the matching cell of the other fracture; G^u = g_u [[1, 1], [1, 1]] on the
+  two unknowns of every trace cell pair (SPSD, global).  The Schur complement
+  S_u = G^u - a B^T A^-1 C - a C^T A^-1 B + C^T A^-1 G^h A^-1 C is never formed.
 """
 from __future__ import annotations
 
@@ -163,6 +173,127 @@ def rhs_uniform(n: int, seed: int) -> np.ndarray:
 # ---------------------------------------------------------------------------
 # DFN-shaped Schur operator
 # ---------------------------------------------------------------------------
+
+@dataclass
+class DfnSuParts:
+    """Blocks of the DFN saddle-point system in the unknowns (h, u, p)."""
+
+    a: CSR  # n_h x n_h, block diagonal SPD (one G x G grid per fracture)
+    gh: CSR  # n_h x n_h, block diagonal SPSD
+    c: CSR  # n_h x n_u, fracture-local
+    b: CSR  # n_h x n_u, C + E
+    gu: CSR  # n_u x n_u, SPSD
+    alpha: float
+    n_frac: int
+    grid: int
+    u_off: np.ndarray  # int64, n_frac + 1: unknowns owned by fracture f are u_off[f] .. u_off[f+1]-1
+
+    @property
+    def n_h(self) -> int:
+        return self.a.n_rows
+
+    @property
+    def n_u(self) -> int:
+        return self.gu.n_rows
+
+
+def _csr_from_coo(n_rows: int, n_cols: int, r, c, v) -> CSR:
+    import scipy.sparse as sp
+
+    m = sp.coo_matrix((v, (r, c)), shape=(n_rows, n_cols)).tocsr()
+    m.sum_duplicates()
+    m.sort_indices()
+    return CSR(n_rows, n_cols, m.indptr.astype(np.int64), m.indices.astype(np.int32), m.data.astype(np.float64))
+
+
+def _grid_faces(n_frac: int, G: int):
+    """Interior faces of every fracture grid: (cell_a, cell_b) global indices, x- then y-faces."""
+    m = G * G
+    f = np.arange(n_frac, dtype=np.int64)[:, None, None]
+    ii, jj = np.meshgrid(np.arange(G, dtype=np.int64), np.arange(G, dtype=np.int64), indexing="ij")
+    base = f * m
+    xa = (base + ii[:, :-1] * G + jj[:, :-1]).reshape(-1)
+    ya = (base + ii[:-1, :] * G + jj[:-1, :]).reshape(-1)
+    return np.concatenate([xa, ya]), np.concatenate([xa + 1, ya + G])
+
+
+def dfn_su(n_frac: int = 400, G: int = 48, n_traces: int = 1100, L_lo: int = 10, L_hi: int = 40,
+           sigma: float = 1.0, gamma: float = 100.0, g_u: float = 10.0, alpha: float = 1.0,
+           seed: int = 0) -> DfnSuParts:
+    """Blocks A, G^h, C, B, G^u of the DFN system of section 4.1 (see module docstring).
+
+    Traces: ``n_frac - 1`` spanning-tree traces then random pairs of distinct
+    fractures, lengths uniform in [L_lo, L_hi], an independent straight
+    segment of L cells on each side (as in ``dfn_schur``).  Unknown l of a
+    trace side is owned by that side's fracture; unknowns are ordered by owner
+    (stable), so C is block diagonal by fracture in its columns.
+    """
+    if n_traces < n_frac - 1:
+        raise ValueError("need at least n_frac - 1 traces for a connected network")
+    if L_hi > G or L_lo < 1:
+        raise ValueError("trace lengths must lie in [1, G]")
+    rng = np.random.default_rng(seed)
+    m = G * G
+    n_h = n_frac * m
+    kc = np.exp(sigma * rng.standard_normal(n_h))
+    fa, fb = _grid_faces(n_frac, G)
+    coef = 2.0 * kc[fa] * kc[fb] / (kc[fa] + kc[fb])
+    nbr = np.zeros(n_h)
+    np.add.at(nbr, fa, 1.0)
+    np.add.at(nbr, fb, 1.0)
+    diag_a = np.zeros(n_h)
+    np.add.at(diag_a, fa, coef)
+    np.add.at(diag_a, fb, coef)
+    diag_a += (4.0 - nbr) * kc  # Dirichlet boundary faces
+    cells = np.arange(n_h, dtype=np.int64)
+    a = _csr_from_coo(n_h, n_h, np.concatenate([fa, fb, cells]), np.concatenate([fb, fa, cells]),
+                      np.concatenate([-coef, -coef, diag_a]))
+    gh = _csr_from_coo(n_h, n_h, np.concatenate([fa, fb, cells]), np.concatenate([fb, fa, cells]),
+                       gamma * np.concatenate([-np.ones(fa.size), -np.ones(fb.size), nbr]))
+
+    pa = np.empty(n_traces, dtype=np.int64)
+    pb = np.empty(n_traces, dtype=np.int64)
+    for f in range(1, n_frac):
+        pa[f - 1] = f
+        pb[f - 1] = int(rng.integers(0, f))
+    for t in range(n_frac - 1, n_traces):
+        x = int(rng.integers(0, n_frac))
+        y = int(rng.integers(0, n_frac - 1))
+        if y >= x:
+            y += 1
+        pa[t], pb[t] = x, y
+    own, cell_own, cell_other, pair = [], [], [], []
+    npair = 0
+    for t in range(n_traces):
+        L = int(rng.integers(L_lo, L_hi + 1))
+        sa = _segment(rng, G, L) + pa[t] * m
+        sb = _segment(rng, G, L) + pb[t] * m
+        k = np.arange(npair, npair + L, dtype=np.int64)
+        own += [np.full(L, pa[t]), np.full(L, pb[t])]
+        cell_own += [sa, sb]
+        cell_other += [sb, sa]
+        pair += [k, k]
+        npair += L
+    own = np.concatenate(own)
+    cell_own = np.concatenate(cell_own)
+    cell_other = np.concatenate(cell_other)
+    pair = np.concatenate(pair)
+    order = np.argsort(own, kind="stable")
+    own, cell_own, cell_other, pair = own[order], cell_own[order], cell_other[order], pair[order]
+    n_u = own.size
+    u = np.arange(n_u, dtype=np.int64)
+    c = _csr_from_coo(n_h, n_u, cell_own, u, np.ones(n_u))
+    b = _csr_from_coo(n_h, n_u, np.concatenate([cell_own, cell_other]), np.concatenate([u, u]),
+                      np.concatenate([np.ones(n_u), -np.ones(n_u)]))
+    # the two unknowns of every trace cell pair
+    pos_sorted = np.argsort(pair, kind="stable")
+    first = u[pos_sorted[0::2]]
+    second = u[pos_sorted[1::2]]
+    gu = _csr_from_coo(n_u, n_u, np.concatenate([first, second, first, second]),
+                       np.concatenate([first, second, second, first]), np.full(4 * npair, g_u))
+    u_off = np.zeros(n_frac + 1, dtype=np.int64)
+    np.cumsum(np.bincount(own, minlength=n_frac), out=u_off[1:])
+    return DfnSuParts(a, gh, c, b, gu, float(alpha), n_frac, G, u_off)
 
 def _lap2d_block_pattern(G: int):
     """5-point Dirichlet Laplacian pattern of one G x G fracture grid.

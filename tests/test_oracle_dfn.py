@@ -1,0 +1,133 @@
+"""Pins of the oracle's DFN Schur complement (section 4.1).
+
+Each test checks the oracle against something other than itself:
+- the exact Cholesky factor reproduces every diagonal block of A;
+- Algorithm 3 against S_u assembled densely from its formula
+  G^u - a B^T A^-1 C - a C^T A^-1 B + C^T A^-1 G^h A^-1 C (numpy inverse);
+- Algorithm 4 against the diagonal of that dense S_u;
+- the reduced right-hand side, the solve for u and the recovery of h, p
+  against a dense solve of the whole saddle-point system of eq. (sys);
+- the PCG of Algorithm 2 on the scaled S_u reaches the tolerance and the
+  recovered unknowns satisfy the three block equations.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2208_01339_amd import workloads as W
+
+CASES = {
+    "f6g8": dict(n_frac=6, G=8, n_traces=10, L_lo=3, L_hi=8, seed=0),
+    "f9g5_alpha0.5": dict(n_frac=9, G=5, n_traces=14, L_lo=1, L_hi=5, seed=3, alpha=0.5),
+    "f4g11_odd": dict(n_frac=4, G=11, n_traces=7, L_lo=4, L_hi=11, seed=5),
+    "f5g1": dict(n_frac=5, G=1, n_traces=6, L_lo=1, L_hi=1, seed=7),
+}
+# one-cell fractures: G^h is zero there, so S_u is only SPSD (degenerate shape)
+NOT_SPD = {"f5g1"}
+
+
+def dense(P):
+    A = P.a.to_scipy().toarray()
+    C = P.c.to_scipy().toarray()
+    B = P.b.to_scipy().toarray()
+    Gh = P.gh.to_scipy().toarray()
+    Gu = P.gu.to_scipy().toarray()
+    return A, C, B, Gh, Gu
+
+
+def dense_su(P):
+    A, C, B, Gh, Gu = dense(P)
+    Ai = np.linalg.inv(A)
+    a = P.alpha
+    return Gu - a * B.T @ Ai @ C - a * C.T @ Ai @ B + C.T @ Ai @ Gh @ Ai @ C
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def case(request):
+    P = W.dfn_su(**CASES[request.param])
+    P.name = request.param
+    return P, O.DfnOperator(P, jacobi=False), dense_su(P)
+
+
+def test_factor_reproduces_blocks(case):
+    P, op, _ = case
+    G = P.grid
+    nf = G * G
+    A = P.a.to_scipy().toarray()
+    for f in range(P.n_frac):
+        Lf = np.zeros((nf, nf))
+        for il in range(nf):
+            i = f * nf + il
+            for k in range(min(G, il) + 1):
+                Lf[il, il - k] = op.L[i * (G + 1) + k]
+        blk = A[f * nf:(f + 1) * nf, f * nf:(f + 1) * nf]
+        assert np.allclose(Lf @ Lf.T, blk, rtol=0, atol=1e-12 * np.abs(blk).max())
+
+
+def test_alg3_matches_dense_formula(case):
+    P, op, S = case
+    rng = np.random.default_rng(11)
+    for _ in range(3):
+        r = rng.standard_normal(P.n_u)
+        y = op.apply(r)
+        assert np.linalg.norm(y - S @ r) <= 1e-12 * np.linalg.norm(S @ r)
+
+
+def test_su_is_symmetric_positive_definite(case):
+    P, _, S = case
+    assert np.abs(S - S.T).max() <= 1e-12 * np.abs(S).max()
+    if P.name not in NOT_SPD:
+        assert np.linalg.eigvalsh((S + S.T) / 2).min() > 0
+
+
+def test_alg4_matches_dense_diagonal(case):
+    P, op, S = case
+    d = op.diag_raw()
+    assert np.allclose(d, np.diag(S), rtol=1e-12, atol=0)
+
+
+def test_reduced_system_solves_the_saddle_point_system(case):
+    """eq. (sys): [[G^h, -aB, A], [-aB^T, G^u, -C^T], [A, -C, 0]] (h, u, p) = (0, 0, q)."""
+    P, op, S = case
+    if P.name in NOT_SPD:
+        pytest.skip("S_u singular for one-cell fractures")
+    A, C, B, Gh, Gu = dense(P)
+    a = P.alpha
+    nh, nu = P.n_h, P.n_u
+    K = np.block([[Gh, -a * B, A], [-a * B.T, Gu, -C.T], [A, -C, np.zeros((nh, nh))]])
+    q = W.rhs_uniform(nh, 2)
+    sol = np.linalg.solve(K, np.concatenate([np.zeros(nh + nu), q]))
+    h0, u0, p0 = sol[:nh], sol[nh:nh + nu], sol[nh + nu:]
+    r = op.rhs(q)
+    u = np.linalg.solve(S, r)
+    h, p = op.recover(q, u)
+    for got, want in ((u, u0), (h, h0), (p, p0)):
+        assert np.linalg.norm(got - want) <= 1e-9 * np.linalg.norm(want)
+
+
+def test_pcg_on_scaled_su_and_recovery():
+    P = W.dfn_su(n_frac=12, G=10, n_traces=20, L_lo=3, L_hi=10, seed=4)
+    op = O.DfnOperator(P, jacobi=True)
+    q = W.rhs_uniform(P.n_h, 1)
+    r = op.rhs(q)
+    lmin, lmax = O.lanczos_bounds(op, 20)
+    u, st = O.pcg(op, 8, lmin, lmax, 1e-3, r, tol=1e-10, maxit=2000)
+    assert st["status"] == O.OK
+    h, p = op.recover(q, u)
+    A, C, B, Gh, Gu = dense(P)
+    a = P.alpha
+    sc = np.linalg.norm(q)
+    assert np.linalg.norm(Gh @ h - a * B @ u + A @ p) <= 1e-7 * sc
+    assert np.linalg.norm(-a * B.T @ h + Gu @ u - C.T @ p) <= 1e-7 * sc
+    assert np.linalg.norm(A @ h - C @ u - q) <= 1e-7 * sc
+
+
+def test_factor_rejects_entries_outside_the_band():
+    P = W.dfn_su(n_frac=3, G=6, n_traces=3, L_lo=2, L_hi=6, seed=1)
+    a = P.a.to_scipy().tolil()
+    a[0, 6 * 6 - 1] = a[6 * 6 - 1, 0] = -1e-3  # distance 35 > G within fracture 0
+    a = a.tocsr()
+    a.sort_indices()
+    P.a = W.CSR(P.n_h, P.n_h, a.indptr.astype(np.int64), a.indices.astype(np.int32), a.data)
+    with pytest.raises(ValueError):
+        O.DfnOperator(P, jacobi=False)

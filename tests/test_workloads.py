@@ -69,3 +69,27 @@ def test_dfn_full_size_counts():
 def test_batch_sizes():
     sides = W.batch_sizes()
     assert sides.size == 256 and sides.min() >= 21 and sides.max() <= 126
+
+
+def test_dfn_su_structure():
+    """Blocks of the DFN system: A and G^h fracture-local within distance G of
+    the diagonal, C columns inside their owner fracture, B = C + E with E on the
+    other side of the trace, G^u pairing the two sides; deterministic per seed."""
+    P = W.dfn_su(n_frac=7, G=9, n_traces=12, L_lo=2, L_hi=9, seed=2)
+    nf = P.grid ** 2
+    for M in (P.a, P.gh):
+        S = M.to_scipy().tocoo()
+        assert np.all(S.row // nf == S.col // nf)
+        assert np.all(np.abs(S.row - S.col) <= P.grid)
+        D = M.to_scipy().toarray()
+        assert np.array_equal(D, D.T)
+    own = np.searchsorted(P.u_off, np.arange(P.n_u), side="right") - 1
+    Cc = P.c.to_scipy().tocoo()
+    assert np.all(Cc.row // nf == own[Cc.col]) and Cc.nnz == P.n_u
+    E = (P.b.to_scipy() - P.c.to_scipy()).tocoo()
+    E.eliminate_zeros()
+    assert E.nnz == P.n_u and np.all(E.row // nf != own[E.col]) and np.all(E.data == -1.0)
+    Gu = P.gu.to_scipy().toarray()
+    assert np.array_equal(Gu, Gu.T) and np.all(Gu.sum(axis=1) == 2 * 10.0)
+    Q = W.dfn_su(n_frac=7, G=9, n_traces=12, L_lo=2, L_hi=9, seed=2)
+    assert np.array_equal(P.b.val, Q.b.val) and np.array_equal(P.a.val, Q.a.val)
