@@ -104,6 +104,74 @@ PP_API pp_status pp_create_schur(pp_op *out, int64_t n, int64_t nnz_a, const int
                           const double *m_diag, unsigned flags, void *stream);
 
 /*
+ * The DFN Schur complement of section 4.1 (eq. schur):
+ *   S_u(alpha) = G^u - alpha B^T A^{-1} C - alpha C^T A^{-1} B + C^T A^{-1} G^h A^{-1} C,
+ * the operator of the reduced system S_u u = r after the permutation of
+ * eq. (tilde_var).  A sparse matrix given as CSR on the device:
+ */
+typedef struct {
+    int64_t rows, cols, nnz;
+    const int64_t *rowptr;  /* [rows+1], rowptr[0] = 0, non-decreasing    */
+    const int32_t *col;     /* [nnz] in [0, cols)                          */
+    const double *val;      /* [nnz]                                       */
+} pp_csr;
+
+/*
+ * The blocks of the DFN system (section 4.1, eq. (sys)), device CSR:
+ *   a      A, n_h x n_h, symmetric positive definite and block diagonal: one
+ *          block of grid^2 consecutive rows per fracture (n_h = n_frac grid^2),
+ *          every entry within distance grid of the diagonal (a 2-D grid
+ *          numbered by lines, as a 5-point operator); 1 <= grid <= 64
+ *   gh     G^h, n_h x n_h, symmetric, same blocks and band
+ *   c      C, n_h x n_u: every column inside the block of the fracture that
+ *          owns that unknown
+ *   b      B, n_h x n_u (any pattern)
+ *   gu     G^u, n_u x n_u, symmetric
+ *   u_off  [n_frac+1] host int64: unknowns u_off[f] .. u_off[f+1]-1 are owned
+ *          by fracture f (non-decreasing, u_off[0] = 0, u_off[n_frac] = n_u)
+ *   alpha  the scalar of eq. (sys); S_u must be SPD for it (the paper's
+ *          assumption; a PCG breakdown reports otherwise)
+ */
+typedef struct {
+    int64_t n_frac, grid;
+    pp_csr a, gh, c, b, gu;
+    const int64_t *u_off;
+    double alpha;
+} pp_dfn_desc;
+
+/*
+ * Create the operator S_u of a DFN system (n = n_u).  At create, on the
+ * device: the exact Cholesky factor of every block of A (banded, section 5's
+ * factorisation step), and D_S = diag(S_u) by Algorithm 4; the operator seen
+ * by pp_setup / pp_apply / pcg_solve / pp_estimate_bounds is
+ * D_S^{-1/2} S_u D_S^{-1/2} (section 4.2), applied matrix-free by Algorithm 3
+ * (three solves with the factor, each a forward and a backward sweep, and
+ * the products with C, B, G^h, G^u).  The input arrays are copied; the
+ * caller keeps ownership.  flags: 0 (Jacobi scaling by D_S is implied;
+ * PP_MIXED and PP_SLICED are refused).  PP_ERR_ARG for an invalid structure
+ * (entry outside its fracture block or band, a C column outside its owner,
+ * asymmetric A, G^h or G^u, A not SPD, a non-positive D_S).
+ */
+PP_API pp_status pp_create_dfn(pp_op *out, const pp_dfn_desc *desc, unsigned flags, void *stream);
+
+/*
+ * Reduced right-hand side of the DFN system (block elimination of section
+ * 4.1): r = W^T M^{-1} f_1 with f_1 = (q, 0), i.e.
+ *   r = alpha B^T A^{-1} q - C^T A^{-1} G^h A^{-1} q.
+ *   q [n_h] device, r [n_u] device (unscaled; pass r to pcg_solve as b).
+ * PP_ERR_ARG unless op came from pp_create_dfn.  Queued on the handle's
+ * stream and synchronised.
+ */
+PP_API pp_status pp_dfn_rhs(pp_op op, const double *q, double *r);
+
+/*
+ * Recovery of the other unknowns once S_u u = r is solved (section 4.1):
+ *   h = A^{-1} (q + C u),  p = A^{-1} (alpha B u - G^h h).
+ *   q [n_h], u [n_u], h [n_h] and p [n_h] device.  Synchronised.
+ */
+PP_API pp_status pp_dfn_recover(pp_op op, const double *q, const double *u, double *h, double *p);
+
+/*
  * Fix the polynomial (section 2.2 and eq. thetamod of section 2.4):
  *   theta-bar = (lambda_max + lambda_min)/2 * (1 + scaling),
  *   delta = (lambda_max - lambda_min)/2, sigma = theta-bar/delta,

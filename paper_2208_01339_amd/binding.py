@@ -29,6 +29,7 @@ ABI_FUNCTIONS = (
     "pp_mlp_num_params", "pp_mlp_get_params", "pp_mlp_set_params", "pp_mlp_set_normalization",
     "pp_mlp_forward", "pp_mlp_loss_grad", "pp_mlp_train_step", "pp_features", "pp_predict_bounds",
     "pp_lowrank_set", "pp_lowrank_ritz", "pp_lowrank_get", "pp_setup_newton",
+    "pp_create_dfn", "pp_dfn_rhs", "pp_dfn_recover",
 )
 
 
@@ -71,6 +72,9 @@ def lib():
         P, I64, I32, D = C.c_void_p, C.c_int64, C.c_int, C.c_double
         L.pp_create_csr.argtypes = [C.POINTER(P), I64, I64, P, P, P, C.c_uint, P]
         L.pp_create_schur.argtypes = [C.POINTER(P), I64, I64, P, P, P, I64, I64, P, P, P, P, C.c_uint, P]
+        L.pp_create_dfn.argtypes = [C.POINTER(P), C.POINTER(pp_dfn_desc), C.c_uint, P]
+        L.pp_dfn_rhs.argtypes = [P, P, P]
+        L.pp_dfn_recover.argtypes = [P, P, P, P, P]
         L.pp_setup.argtypes = [P, I32, D, D, D]
         L.pp_apply.argtypes = [P, P, P]
         L.pcg_solve.argtypes = [P, P, P, D, I32, C.POINTER(I32), C.POINTER(D)]
@@ -185,6 +189,55 @@ def pp_create_schur(n, nnz_a, a_rowptr, a_col, a_val, nt, nnz_c, c_rowptr, c_col
                                  _ptr(a_val), int(nt), int(nnz_c), _ptr(c_rowptr), _ptr(c_col),
                                  _ptr(c_val), _ptr(m_diag), int(flags), _stream(stream)))
     return h
+
+
+class pp_csr(C.Structure):
+    _fields_ = [("rows", C.c_int64), ("cols", C.c_int64), ("nnz", C.c_int64), ("rowptr", C.c_void_p),
+                ("col", C.c_void_p), ("val", C.c_void_p)]
+
+
+class pp_dfn_desc(C.Structure):
+    _fields_ = [("n_frac", C.c_int64), ("grid", C.c_int64), ("a", pp_csr), ("gh", pp_csr), ("c", pp_csr),
+                ("b", pp_csr), ("gu", pp_csr), ("u_off", C.c_void_p), ("alpha", C.c_double)]
+
+
+def pp_create_dfn(n_frac, grid, mats, u_off, alpha, flags=0, stream=None):
+    """mats: dict a, gh, c, b, gu -> (rows, cols, rowptr, col, val) with device tensors
+    (int64, int32, float64); u_off: host numpy int64 [n_frac + 1]."""
+    import numpy as np
+    import torch
+
+    d = pp_dfn_desc()
+    d.n_frac, d.grid, d.alpha = int(n_frac), int(grid), float(alpha)
+    for nm in ("a", "gh", "c", "b", "gu"):
+        rows, cols, rp, cl, v = mats[nm]
+        _dtype_check(rp, torch.int64, nm + ".rowptr")
+        _dtype_check(cl, torch.int32, nm + ".col")
+        _dtype_check(v, torch.float64, nm + ".val")
+        m = getattr(d, nm)
+        m.rows, m.cols, m.nnz = int(rows), int(cols), int(v.numel())
+        m.rowptr, m.col, m.val = _ptr(rp), _ptr(cl), _ptr(v)
+    uo = np.ascontiguousarray(u_off, dtype=np.int64)
+    d.u_off = uo.ctypes.data_as(C.c_void_p)
+    h = C.c_void_p()
+    _check(lib().pp_create_dfn(C.byref(h), C.byref(d), int(flags), _stream(stream)))
+    return h
+
+
+def pp_dfn_rhs(op, q, r):
+    import torch
+
+    _dtype_check(q, torch.float64, "q")
+    _dtype_check(r, torch.float64, "r")
+    _check(lib().pp_dfn_rhs(op, _ptr(q), _ptr(r)))
+
+
+def pp_dfn_recover(op, q, u, h, p):
+    import torch
+
+    for t, nm in ((q, "q"), (u, "u"), (h, "h"), (p, "p")):
+        _dtype_check(t, torch.float64, nm)
+    _check(lib().pp_dfn_recover(op, _ptr(q), _ptr(u), _ptr(h), _ptr(p)))
 
 
 def pp_setup(op, k, lambda_min, lambda_max, scaling=0.0):
@@ -456,7 +509,7 @@ def pp_predict_bounds(op, mlp, power_steps=8):
 class Operator:
     """Owns a pp_op built from host CSR arrays (or Schur parts) uploaded to ``device``."""
 
-    def __init__(self, a=None, schur=None, flags=0, device="cuda:0", stream=None):
+    def __init__(self, a=None, schur=None, dfn=None, flags=0, device="cuda:0", stream=None):
         import torch
 
         self.device = torch.device(device)
@@ -465,7 +518,17 @@ class Operator:
         def up(x, dt):
             return torch.from_numpy(x).to(device=dev, dtype=dt).contiguous()
 
-        if schur is not None:
+        if dfn is not None:
+            d = dfn
+            self.n = d.n_u
+            self._dev = {}
+            for nm in ("a", "gh", "c", "b", "gu"):
+                m = getattr(d, nm)
+                self._dev[nm] = (m.n_rows, m.n_cols, up(m.rowptr, torch.int64), up(m.col, torch.int32),
+                                 up(m.val, torch.float64))
+            self.handle = pp_create_dfn(d.n_frac, d.grid, self._dev, d.u_off, d.alpha, flags, stream)
+            self._dev = None
+        elif schur is not None:
             s = schur
             self.n = s.a.n_rows
             self.handle = pp_create_schur(

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = [os.path.join(HERE, "csrc", f) for f in ("pp_lib.hip", "pp_batch.hip", "pp_mlp.hip")]
 DEPS = SRC + [os.path.join(HERE, "csrc", f) for f in (
-    "kernels.hpp", "sym_eig.hpp", "persistent.hpp", "batch.hpp", "common.hpp", "op.hpp", "mlp.hpp",
+    "kernels.hpp", "sym_eig.hpp", "persistent.hpp", "batch.hpp", "common.hpp", "op.hpp", "mlp.hpp", "dfn.hpp",
     "dia_plan.hpp", "lowrank.hpp", "stencil2.hpp")] + [
     os.path.join(ROOT, "include", "pp.h")]
 OUT = os.path.join(HERE, "libppcg.so")

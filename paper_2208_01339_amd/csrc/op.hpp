@@ -6,12 +6,13 @@
 #include <vector>
 
 #include "common.hpp"
+#include "dfn.hpp"
 #include "kernels.hpp"
 
 constexpr int PP_GRID_DEFAULT = 2048;
 
 struct pp_op_s {
-    int kind = 0;  // 0 CSR, 1 Schur
+    int kind = 0;  // 0 CSR, 1 Schur, 2 DFN S_u (its A x read from tw, filled by Algorithm 3)
     int64_t n = 0, nt = 0, nnz_c = 0, nnz_given = 0;
     unsigned flags = 0;
     hipStream_t stream = nullptr;
@@ -36,6 +37,14 @@ struct pp_op_s {
     float *cm32 = nullptr;
     double *tw = nullptr;
     float *tw32 = nullptr;
+    // DFN S_u (kind 2): band factor, copies of C, a B, G^h (fracture rows) and
+    // of C^T, a B^T, G^u (unknown rows), two fracture-row work vectors
+    int64_t dfn_F = 0, dfn_G = 0, dfn_nh = 0;
+    double *dfn_Lb = nullptr;
+    int64_t *dfn_rp[6] = {};
+    int32_t *dfn_col[6] = {};
+    double *dfn_val[6] = {};
+    double *dfn_t = nullptr, *dfn_d = nullptr;
     // Jacobi
     double *dis = nullptr;
     // work vectors
@@ -88,7 +97,26 @@ struct pp_op_s {
     int ntload = 1;   // set at create from the operator's size
     pp_stats stats{};
 
-    bool schur() const { return kind == 1; }
+    // kinds whose fused kernels read trace columns from tw
+    bool schur() const { return kind == 1 || kind == 2; }
+    bool dfn() const { return kind == 2; }
+    ppk::DfnView dview() const
+    {
+        ppk::DfnView v;
+        v.F = dfn_F;
+        v.G = dfn_G;
+        v.nf = dfn_G * dfn_G;
+        v.nh = dfn_nh;
+        v.nu = n;
+        v.Lb = dfn_Lb;
+        ppk::CsrD *m[6] = {&v.c, &v.b, &v.gh, &v.ct, &v.bt, &v.gu};
+        for (int i = 0; i < 6; ++i) {
+            m[i]->rp = dfn_rp[i];
+            m[i]->col = dfn_col[i];
+            m[i]->val = dfn_val[i];
+        }
+        return v;
+    }
     bool mixed() const { return (flags & PP_MIXED) != 0; }
 
     int grid_slices() const
@@ -133,6 +161,8 @@ struct pp_op_s {
         ppc::dfree(dval); ppc::dfree(dval32);
         ppc::dfree(crp); ppc::dfree(ccol); ppc::dfree(cm); ppc::dfree(cm32); ppc::dfree(tw); ppc::dfree(tw32);
         ppc::dfree(dis);
+        ppc::dfree(dfn_Lb); ppc::dfree(dfn_t); ppc::dfree(dfn_d);
+        for (int i = 0; i < 6; ++i) { ppc::dfree(dfn_rp[i]); ppc::dfree(dfn_col[i]); ppc::dfree(dfn_val[i]); }
         ppc::dfree(xh); ppc::dfree(r); ppc::dfree(p); ppc::dfree(q); ppc::dfree(z); ppc::dfree(bh); ppc::dfree(sA); ppc::dfree(sB);
         ppc::dfree(r32); ppc::dfree(sA32); ppc::dfree(sB32);
         ppc::dfree(sC); ppc::dfree(sD);

@@ -442,11 +442,33 @@ void launch_cheb_rt(pp_op_s *op, const XT *xg, const T *w, const RT *r, const T 
         launch_cheb<T, XT, RT, OT, MODE, SCHUR, false, false>(op, xg, w, r, sold, out, c, fin);
 }
 
+// y = D^{-1/2} S_u D^{-1/2} x by Algorithm 3 (DFN): one wavefront per fracture
+// for the three solves with the factor, then the rows of the unknowns.
+// live_state: skip once the solve is done.
+void enqueue_su(pp_op_s *op, const double *x, double *y, bool live_state)
+{
+    const ppk::DfnView g = op->dview();
+    const int SP = ppk::dfn_stride((int)g.G);
+    const size_t lds = sizeof(double) * (2 * (size_t)g.nf + 2 * (size_t)g.G * SP);
+    const ppk::State *st = live_state ? (const ppk::State *)op->st : nullptr;
+    hipLaunchKernelGGL(ppk::k_dfn_frac, dim3((unsigned)g.F), dim3(ppk::DFN_WAVE), lds, op->stream, g, x,
+                       (const double *)op->dis, (const double *)nullptr, op->dfn_t, op->dfn_d, st);
+    hipLaunchKernelGGL(ppk::k_dfn_urow, dim3(op->grid_elems(op->n)), dim3(BLOCK), 0, op->stream, g, x,
+                       (const double *)op->dis, (const double *)op->dfn_t, (const double *)op->dfn_d, 1.0, -1.0,
+                       -1.0, y, st);
+}
+
 template <typename T, typename XT, typename RT, typename OT, int MODE>
 void launch_step(pp_op_s *op, const XT *xg, const RT *r, const T *sold, OT *out, const StepCoef &c,
                  int fin, bool scale)
 {
-    if (op->schur()) {
+    if (op->dfn()) {
+        // FP64 only (no mixed mode): tw = S-hat x by Algorithm 3, read through the unit entries
+        if constexpr (sizeof(T) == 8 && sizeof(XT) == 8) {
+            enqueue_su(op, (const double *)xg, op->tw, true);
+            launch_cheb_rt<T, XT, RT, OT, MODE, true>(op, xg, (const T *)op->tw, r, sold, out, c, fin, scale);
+        }
+    } else if (op->schur()) {
         T *w = sizeof(T) == 4 ? (T *)op->tw32 : (T *)op->tw;
         hipLaunchKernelGGL((ppk::k_trace<T, XT>), dim3(op->grid_elems(op->nt)), dim3(BLOCK), 0, op->stream,
                            op->cview(sizeof(T) == 4), xg, w, (const ppk::State *)op->st);
@@ -678,6 +700,10 @@ namespace {
 void enqueue_trace_f64(pp_op_s *op, const double *x, bool live_state = true)
 {
     if (!op->schur()) return;
+    if (op->dfn()) {
+        enqueue_su(op, x, op->tw, live_state);
+        return;
+    }
     hipLaunchKernelGGL((ppk::k_trace<double, double>), dim3(op->grid_elems(op->nt)), dim3(BLOCK), 0, op->stream,
                        op->cview(false), x, op->tw, (const ppk::State *)(live_state ? op->st : nullptr));
 }
@@ -870,6 +896,278 @@ pp_status pp_create_schur(pp_op *out, int64_t n, int64_t nnz_a, const int64_t *a
                          flags, stream);
 }
 
+namespace {
+
+// Device copy of a CSR matrix (values scaled by a), after a structure check.
+void dfn_copy_csr(pp_op_s *op, const pp_csr &m, double a, int64_t **rp, int32_t **col, double **val)
+{
+    *rp = dalloc<int64_t>(m.rows + 1);
+    *col = dalloc<int32_t>(m.nnz);
+    *val = dalloc<double>(m.nnz);
+    HIPCHK(hipMemcpyAsync(*rp, m.rowptr, sizeof(int64_t) * (m.rows + 1), hipMemcpyDeviceToDevice, op->stream));
+    HIPCHK(hipMemcpyAsync(*col, m.col, sizeof(int32_t) * m.nnz, hipMemcpyDeviceToDevice, op->stream));
+    hipLaunchKernelGGL(ppk::k_dfn_axv, dim3(op->grid_elems(m.nnz)), dim3(BLOCK), 0, op->stream, m.nnz, a, m.val,
+                       *val);
+    HIPCHK(hipGetLastError());
+}
+
+// Transpose (rows x cols -> cols rows) of a device CSR, values scaled by a.
+void dfn_transpose(pp_op_s *op, int64_t rows, int64_t cols, int64_t nnz, const int64_t *rp, const int32_t *cl,
+                   const double *v, double a, int64_t **trp, int32_t **tcol, double **tval)
+{
+    int64_t *cnt = dalloc<int64_t>(cols);
+    struct Free {
+        int64_t *&p;
+        ~Free() { ppc::dfree(p); }
+    } fr{cnt};
+    *trp = dalloc<int64_t>(cols + 1);
+    *tcol = dalloc<int32_t>(nnz);
+    *tval = dalloc<double>(nnz);
+    ppk::CsrD m{rp, cl, v};
+    HIPCHK(hipMemsetAsync(cnt, 0, sizeof(int64_t) * cols, op->stream));
+    const unsigned gr = (unsigned)std::max<int64_t>(1, std::min<int64_t>((rows + BLOCK - 1) / BLOCK, 8192));
+    hipLaunchKernelGGL(ppk::k_t_count, dim3(gr), dim3(BLOCK), 0, op->stream, rows, m, cnt);
+    hipLaunchKernelGGL(ppk::k_scan_i64, dim3(1), dim3(1024), 0, op->stream, cols, (const int64_t *)cnt, *trp);
+    HIPCHK(hipMemsetAsync(cnt, 0, sizeof(int64_t) * cols, op->stream));
+    hipLaunchKernelGGL(ppk::k_t_fill, dim3(gr), dim3(BLOCK), 0, op->stream, rows, m, a, (const int64_t *)*trp, cnt,
+                       *tcol, *tval);
+    const unsigned gc = (unsigned)std::max<int64_t>(1, std::min<int64_t>((cols + BLOCK - 1) / BLOCK, 8192));
+    hipLaunchKernelGGL(ppk::k_t_sort, dim3(gc), dim3(BLOCK), 0, op->stream, cols, (const int64_t *)*trp, *tcol,
+                       *tval);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(op->stream));
+}
+
+int read_flag(pp_op_s *op, int *flag_d)
+{
+    int h = 0;
+    HIPCHK(hipMemcpyAsync(&h, flag_d, sizeof(int), hipMemcpyDeviceToHost, op->stream));
+    HIPCHK(hipStreamSynchronize(op->stream));
+    return h;
+}
+
+pp_status dfn_build(pp_op_s *op, const pp_dfn_desc &d)
+{
+    const int64_t F = d.n_frac, G = d.grid, nf = G * G, nh = F * nf, nu = d.gu.rows;
+    int *flag_d = dalloc<int>(1);
+    int32_t *owner = nullptr, *wg_frac = nullptr;
+    int64_t *wg_first = nullptr, *u_end = nullptr;
+    double *yscr = nullptr, *dsv = nullptr;
+    auto cleanup = [&]() {
+        ppc::dfree(flag_d); ppc::dfree(owner); ppc::dfree(wg_frac); ppc::dfree(wg_first); ppc::dfree(u_end);
+        ppc::dfree(yscr); ppc::dfree(dsv);
+    };
+    try {
+        const pp_csr *mats[5] = {&d.a, &d.gh, &d.c, &d.b, &d.gu};
+        const char *names[5] = {"A", "G^h", "C", "B", "G^u"};
+        for (int i = 0; i < 5; ++i)
+            if (check_csr_dev(op, mats[i]->rows, mats[i]->cols, mats[i]->nnz, mats[i]->rowptr, mats[i]->col, flag_d)) {
+                cleanup();
+                return fail(PP_ERR_ARG, std::string("invalid CSR structure of ") + names[i]);
+            }
+        // checks: A, G^h fracture-local within the band and symmetric; G^u symmetric
+        HIPCHK(hipMemsetAsync(flag_d, 0, sizeof(int), op->stream));
+        const unsigned gh_ = (unsigned)std::min<int64_t>((nh + BLOCK - 1) / BLOCK, 8192);
+        const unsigned gu_ = (unsigned)std::max<int64_t>(1, std::min<int64_t>((nu + BLOCK - 1) / BLOCK, 8192));
+        hipLaunchKernelGGL(ppk::k_dfn_sym, dim3(gh_), dim3(BLOCK), 0, op->stream, nh,
+                           ppk::CsrD{d.a.rowptr, d.a.col, d.a.val}, nf, G, flag_d);
+        hipLaunchKernelGGL(ppk::k_dfn_sym, dim3(gh_), dim3(BLOCK), 0, op->stream, nh,
+                           ppk::CsrD{d.gh.rowptr, d.gh.col, d.gh.val}, nf, G, flag_d);
+        hipLaunchKernelGGL(ppk::k_dfn_sym, dim3(gu_), dim3(BLOCK), 0, op->stream, nu,
+                           ppk::CsrD{d.gu.rowptr, d.gu.col, d.gu.val}, (int64_t)0, (int64_t)0, flag_d);
+        HIPCHK(hipGetLastError());
+        int bad = read_flag(op, flag_d);
+        if (bad & 1) { cleanup(); return fail(PP_ERR_ARG, "A or G^h has an entry outside its fracture block or band"); }
+        if (bad & 2) { cleanup(); return fail(PP_ERR_ARG, "A, G^h or G^u is not symmetric (or has unsorted rows)"); }
+        // band factor
+        op->dfn_Lb = dalloc<double>((size_t)(G + 1) * nh);
+        HIPCHK(hipMemsetAsync(op->dfn_Lb, 0, sizeof(double) * (G + 1) * nh, op->stream));
+        hipLaunchKernelGGL(ppk::k_dfn_band, dim3(gh_), dim3(BLOCK), 0, op->stream, nh, nf, G,
+                           ppk::CsrD{d.a.rowptr, d.a.col, d.a.val}, op->dfn_Lb, flag_d);
+        hipLaunchKernelGGL(ppk::k_dfn_chol, dim3((unsigned)F), dim3(ppk::DFN_WAVE), 0, op->stream, nh, nf, (int)G,
+                           op->dfn_Lb, flag_d);
+        HIPCHK(hipGetLastError());
+        bad = read_flag(op, flag_d);
+        if (bad & 4) { cleanup(); return fail(PP_ERR_ARG, "A is not positive definite (Cholesky pivot <= 0)"); }
+        // copies: C, a B, G^h by fracture rows; C^T, a B^T by unknowns; G^u
+        dfn_copy_csr(op, d.c, 1.0, &op->dfn_rp[0], &op->dfn_col[0], &op->dfn_val[0]);
+        dfn_copy_csr(op, d.b, d.alpha, &op->dfn_rp[1], &op->dfn_col[1], &op->dfn_val[1]);
+        dfn_copy_csr(op, d.gh, 1.0, &op->dfn_rp[2], &op->dfn_col[2], &op->dfn_val[2]);
+        dfn_transpose(op, nh, nu, d.c.nnz, d.c.rowptr, d.c.col, d.c.val, 1.0, &op->dfn_rp[3], &op->dfn_col[3],
+                      &op->dfn_val[3]);
+        dfn_transpose(op, nh, nu, d.b.nnz, d.b.rowptr, d.b.col, d.b.val, d.alpha, &op->dfn_rp[4], &op->dfn_col[4],
+                      &op->dfn_val[4]);
+        dfn_copy_csr(op, d.gu, 1.0, &op->dfn_rp[5], &op->dfn_col[5], &op->dfn_val[5]);
+        op->dfn_F = F;
+        op->dfn_G = G;
+        op->dfn_nh = nh;
+        // owners of the unknowns, and Algorithm 4 in workgroups of 64 unknowns of one fracture
+        std::vector<int32_t> own((size_t)nu);
+        std::vector<int32_t> wf;
+        std::vector<int64_t> wfirst, uend((size_t)F);
+        for (int64_t f = 0; f < F; ++f) {
+            for (int64_t j = d.u_off[f]; j < d.u_off[f + 1]; ++j) own[(size_t)j] = (int32_t)f;
+            for (int64_t j = d.u_off[f]; j < d.u_off[f + 1]; j += ppk::DFN_WAVE) {
+                wf.push_back((int32_t)f);
+                wfirst.push_back(j);
+            }
+            uend[(size_t)f] = d.u_off[f + 1];
+        }
+        owner = dalloc<int32_t>(nu);
+        HIPCHK(hipMemcpyAsync(owner, own.data(), sizeof(int32_t) * nu, hipMemcpyHostToDevice, op->stream));
+        HIPCHK(hipMemsetAsync(flag_d, 0, sizeof(int), op->stream));
+        const ppk::DfnView g = op->dview();
+        hipLaunchKernelGGL(ppk::k_dfn_owner, dim3(gu_), dim3(BLOCK), 0, op->stream, nu, nf, g.ct,
+                           (const int32_t *)owner, flag_d);
+        HIPCHK(hipGetLastError());
+        if (read_flag(op, flag_d) & 8) { cleanup(); return fail(PP_ERR_ARG, "a column of C lies outside the fracture owning it"); }
+        const int64_t nwg = (int64_t)wf.size();
+        op->dis = dalloc<double>(nu);
+        dsv = dalloc<double>(nu);
+        if (nwg > 0) {
+            wg_frac = dalloc<int32_t>(nwg);
+            wg_first = dalloc<int64_t>(nwg);
+            u_end = dalloc<int64_t>(F);
+            HIPCHK(hipMemcpyAsync(wg_frac, wf.data(), sizeof(int32_t) * nwg, hipMemcpyHostToDevice, op->stream));
+            HIPCHK(hipMemcpyAsync(wg_first, wfirst.data(), sizeof(int64_t) * nwg, hipMemcpyHostToDevice, op->stream));
+            HIPCHK(hipMemcpyAsync(u_end, uend.data(), sizeof(int64_t) * F, hipMemcpyHostToDevice, op->stream));
+            yscr = dalloc<double>((size_t)nwg * nf * ppk::DFN_WAVE);
+            hipLaunchKernelGGL(ppk::k_dfn_diag, dim3((unsigned)nwg), dim3(ppk::DFN_WAVE), 0, op->stream, g,
+                               (const int32_t *)wg_frac, (const int64_t *)wg_first, (const int64_t *)u_end, yscr, dsv,
+                               op->dis, flag_d);
+            HIPCHK(hipGetLastError());
+        }
+        if (read_flag(op, flag_d) & 16) { cleanup(); return fail(PP_ERR_ARG, "diag(S_u) has a non-positive entry"); }
+        // the operator seen by the fused kernels: one unit entry per row, column n + i
+        op->nslices = (nu + WAVE - 1) / WAVE;
+        op->nstored = op->nslices * WAVE;
+        op->sp = dalloc<int64_t>(op->nslices + 1);
+        op->scol = dalloc<int32_t>(op->nstored);
+        op->sval = dalloc<double>(op->nstored);
+        hipLaunchKernelGGL(ppk::k_dfn_unit, dim3(op->grid_elems(op->nstored)), dim3(BLOCK), 0, op->stream, nu,
+                           op->nslices, op->sp, op->scol, op->sval);
+        HIPCHK(hipGetLastError());
+        op->sell = 1;
+        op->nd = 0;
+        op->tw = dalloc<double>(nu);
+        op->dfn_t = dalloc<double>(nh);
+        op->dfn_d = dalloc<double>(nh);
+        op->xh = dalloc<double>(nu);
+        op->r = dalloc<double>(nu);
+        op->p = dalloc<double>(nu);
+        op->q = dalloc<double>(nu);
+        op->z = dalloc<double>(nu);
+        op->bh = dalloc<double>(nu);
+        op->sA = dalloc<double>(nu);
+        op->sB = dalloc<double>(nu);
+        op->partials = dalloc<double>((size_t)(1 + ppk::LR_MAX) * 8192);
+        op->st = dalloc<ppk::State>(1);
+        HIPCHK(hipMemsetAsync(op->st, 0, sizeof(ppk::State), op->stream));
+        HIPCHK(hipHostMalloc((void **)&op->hst, sizeof(ppk::State), hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void **)&op->hflag, 2 * sizeof(int32_t), hipHostMallocDefault));
+        for (auto &e : op->flag_ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        for (auto &e : op->solve_ev) HIPCHK(hipEventCreate(&e));
+        HIPCHK(hipStreamSynchronize(op->stream));
+    } catch (std::bad_alloc &) {
+        cleanup();
+        return fail(PP_ERR_OOM, "device allocation failed");
+    } catch (HipError &e) {
+        cleanup();
+        return hip_fail(e);
+    }
+    cleanup();
+    op->stats.n = nu;
+    op->stats.nnz_stored = 0;
+    op->stats.diagonals = 0;
+    op->stats.nnz_matrix = d.a.nnz + d.gh.nnz + d.c.nnz + d.b.nnz + d.gu.nnz;
+    return PP_OK;
+}
+
+}  // namespace
+
+pp_status pp_create_dfn(pp_op *out, const pp_dfn_desc *desc, unsigned flags, void *stream)
+{
+    if (!out) return fail(PP_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!desc) return fail(PP_ERR_ARG, "desc is NULL");
+    const pp_dfn_desc &d = *desc;
+    if (flags & ~(unsigned)PP_JACOBI) return fail(PP_ERR_ARG, "DFN operator: only PP_JACOBI (implied) is accepted");
+    if (d.n_frac < 1 || d.grid < 1 || d.grid > ppk::DFN_GMAX)
+        return fail(PP_ERR_ARG, "n_frac must be >= 1 and grid in [1, 64]");
+    const int64_t nh = d.n_frac * d.grid * d.grid, nu = d.gu.rows;
+    if (nh > (int64_t)INT32_MAX - 1 || nu < 1 || nu > (int64_t)INT32_MAX / 2)
+        return fail(PP_ERR_ARG, "sizes out of range (n_h < 2^31, 1 <= n_u < 2^30)");
+    if (d.a.rows != nh || d.a.cols != nh || d.gh.rows != nh || d.gh.cols != nh || d.c.rows != nh ||
+        d.b.rows != nh || d.c.cols != nu || d.b.cols != nu || d.gu.cols != nu)
+        return fail(PP_ERR_ARG, "block sizes disagree (A, G^h: n_h x n_h; C, B: n_h x n_u; G^u: n_u x n_u)");
+    const pp_csr *mats[5] = {&d.a, &d.gh, &d.c, &d.b, &d.gu};
+    for (const pp_csr *m : mats)
+        if (!m->rowptr || m->nnz < 0 || (m->nnz > 0 && (!m->col || !m->val)))
+            return fail(PP_ERR_ARG, "NULL CSR array");
+    if (d.a.nnz < 1) return fail(PP_ERR_ARG, "A is empty");
+    if (!d.u_off || d.u_off[0] != 0 || d.u_off[d.n_frac] != nu) return fail(PP_ERR_ARG, "u_off must run from 0 to n_u");
+    for (int64_t f = 0; f < d.n_frac; ++f)
+        if (d.u_off[f + 1] < d.u_off[f]) return fail(PP_ERR_ARG, "u_off must be non-decreasing");
+    if (!std::isfinite(d.alpha)) return fail(PP_ERR_ARG, "alpha must be finite");
+    pp_op_s *op = new (std::nothrow) pp_op_s();
+    if (!op) return fail(PP_ERR_OOM, "host allocation failed");
+    op->kind = 2;
+    op->n = nu;
+    op->nt = nu;
+    op->nnz_given = d.a.nnz;
+    op->flags = PP_JACOBI;
+    op->stream = (hipStream_t)stream;
+    (void)hipGetDevice(&op->device);
+    op->ntload = 0;
+    pp_status s = dfn_build(op, d);
+    if (s != PP_OK) {
+        op->release();
+        delete op;
+        return s;
+    }
+    *out = op;
+    return PP_OK;
+}
+
+pp_status pp_dfn_rhs(pp_op op, const double *q, double *r)
+{
+    if (!op || !q || !r) return fail(PP_ERR_ARG, "NULL argument");
+    if (!op->dfn()) return fail(PP_ERR_ARG, "not a DFN operator");
+    try {
+        const ppk::DfnView g = op->dview();
+        const size_t lds = sizeof(double) * (2 * (size_t)g.nf + 2 * (size_t)g.G * ppk::dfn_stride((int)g.G));
+        hipLaunchKernelGGL(ppk::k_dfn_frac, dim3((unsigned)g.F), dim3(ppk::DFN_WAVE), lds, op->stream, g,
+                           (const double *)nullptr, (const double *)nullptr, q, op->dfn_t, op->dfn_d,
+                           (const ppk::State *)nullptr);
+        hipLaunchKernelGGL(ppk::k_dfn_urow, dim3(op->grid_elems(op->n)), dim3(BLOCK), 0, op->stream, g,
+                           (const double *)nullptr, (const double *)nullptr, (const double *)op->dfn_t,
+                           (const double *)op->dfn_d, 0.0, 1.0, 1.0, r, (const ppk::State *)nullptr);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(op->stream));
+    } catch (HipError &e) {
+        return hip_fail(e);
+    }
+    return PP_OK;
+}
+
+pp_status pp_dfn_recover(pp_op op, const double *q, const double *u, double *h, double *p)
+{
+    if (!op || !q || !u || !h || !p) return fail(PP_ERR_ARG, "NULL argument");
+    if (!op->dfn()) return fail(PP_ERR_ARG, "not a DFN operator");
+    if (h == p) return fail(PP_ERR_ARG, "h and p must not alias");
+    try {
+        const ppk::DfnView g = op->dview();
+        const size_t lds = sizeof(double) * (2 * (size_t)g.nf + 2 * (size_t)g.G * ppk::dfn_stride((int)g.G));
+        hipLaunchKernelGGL(ppk::k_dfn_frac, dim3((unsigned)g.F), dim3(ppk::DFN_WAVE), lds, op->stream, g, u,
+                           (const double *)nullptr, q, h, p, (const ppk::State *)nullptr);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(op->stream));
+    } catch (HipError &e) {
+        return hip_fail(e);
+    }
+    return PP_OK;
+}
+
 void pp_destroy(pp_op op)
 {
     if (!op) return;
@@ -1038,7 +1336,7 @@ pp_status pcg_solve(pp_op op, const double *b, double *x, double tol, int maxit,
         // persistent driver on request only: its grid-wide barriers cost more
         // than kernel boundaries on this chip at every size measured (each
         // barrier serialises one same-address atomic per workgroup)
-        const bool want_persist = op->driver == 1 && op->lr_p == 0 && op->form == 0;
+        const bool want_persist = op->driver == 1 && op->lr_p == 0 && op->form == 0 && !op->dfn();
         bool persisted = want_persist && persistent_solve(op, b, x, tol, maxit);
         size_t ev_i = 0;
         op->pev_i = 0;

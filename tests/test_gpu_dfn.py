@@ -1,0 +1,185 @@
+"""GPU parity of the DFN Schur complement S_u (section 4.1) against the oracle.
+
+Both sides get the same generated blocks.  Relative bounds: the operator
+apply (Algorithm 3 with the device Cholesky factor), the reduced right-hand
+side and the recovery of h, p to 1e-11 (FP64; the factor and the solves sum
+in a different order than the oracle); p_k(S-hat) r with D_S from Algorithm 4
+to 1e-10; the whole pipeline (rhs, PCG to 1e-8, recovery) to iteration counts
+within 2 and, at equal iteration counts, solutions to 1e-8.  Shapes: odd and
+even grids, the largest grid (64: LDS of the fracture kernel at its maximum),
+more than 64 unknowns per fracture (two workgroups of Algorithm 4), alpha != 1.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2208_01339_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2208_01339_amd import binding
+
+    binding.lib()
+    return binding
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+CASES = {
+    "f6g8": dict(n_frac=6, G=8, n_traces=10, L_lo=3, L_hi=8, seed=0),
+    "f9g5_alpha0.5": dict(n_frac=9, G=5, n_traces=14, L_lo=1, L_hi=5, seed=3, alpha=0.5),
+    "f4g11_odd": dict(n_frac=4, G=11, n_traces=7, L_lo=4, L_hi=11, seed=5),
+    "f3g64_max": dict(n_frac=3, G=64, n_traces=4, L_lo=20, L_hi=64, seed=6),
+    "f2g30_many_u": dict(n_frac=2, G=30, n_traces=6, L_lo=20, L_hi=30, seed=8),  # > 64 unknowns per fracture
+}
+
+_cache = {}
+
+
+def case(name):
+    if name not in _cache:
+        P = W.dfn_su(**CASES[name])
+        _cache[name] = (P, O.DfnOperator(P, jacobi=False), O.DfnOperator(P, jacobi=True))
+    return _cache[name]
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_apply_rhs_recover(B, name):
+    P, orc, _ = case(name)
+    op = B.Operator(dfn=P)
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal(P.n_u)
+    y = torch.empty(P.n_u, dtype=torch.float64, device="cuda")
+    B.pp_operator_apply(op.handle, dev(x), y)
+    assert rel(host(y), orc.apply(x)) <= 1e-11
+    q = W.rhs_uniform(P.n_h, 2)
+    r = torch.empty(P.n_u, dtype=torch.float64, device="cuda")
+    B.pp_dfn_rhs(op.handle, dev(q), r)
+    assert rel(host(r), orc.rhs(q)) <= 1e-11
+    u = rng.standard_normal(P.n_u)
+    h = torch.empty(P.n_h, dtype=torch.float64, device="cuda")
+    p = torch.empty_like(h)
+    B.pp_dfn_recover(op.handle, dev(q), dev(u), h, p)
+    h0, p0 = orc.recover(q, u)
+    assert rel(host(h), h0) <= 1e-11 and rel(host(p), p0) <= 1e-11
+    st = B.pp_get_stats(op.handle)
+    assert st["n"] == P.n_u and st["two_step"] == 0
+    op.close()
+
+
+@pytest.mark.parametrize("name", ["f6g8", "f4g11_odd", "f3g64_max", "f2g30_many_u"])
+@pytest.mark.parametrize("k,xi", [(1, 0.0), (6, 1e-3), (15, 1e-2)])
+def test_polynomial_apply(B, name, k, xi):
+    """pp_apply = D^{-1/2} p_k(S-hat) D^{-1/2} r with D_S from Algorithm 4."""
+    P, _, orj = case(name)
+    op = B.Operator(dfn=P)
+    lmin, lmax = O.lanczos_bounds(orj, 20)
+    B.pp_setup(op.handle, k, lmin, lmax, xi)
+    r = W.rhs_uniform(P.n_u, 7)
+    z = torch.empty(P.n_u, dtype=torch.float64, device="cuda")
+    B.pp_apply(op.handle, dev(r), z)
+    assert rel(host(z), O.cheb_apply(orj, k, lmin, lmax, xi, r)) <= 1e-10
+    op.close()
+
+
+@pytest.mark.parametrize("name", ["f6g8", "f9g5_alpha0.5", "f3g64_max"])
+def test_pipeline_pcg(B, name):
+    """rhs -> PCG on S-hat -> recovery, against the oracle's pipeline; the
+    recovered (h, u, p) satisfy the three block equations of eq. (sys)."""
+    P, orc, orj = case(name)
+    op = B.Operator(dfn=P)
+    q = W.rhs_uniform(P.n_h, 1)
+    lo, hi = B.pp_estimate_bounds(op.handle, 20)
+    lmin, lmax = O.lanczos_bounds(orj, 20)
+    assert abs(lo - lmin) <= 1e-6 * lmax and abs(hi - lmax) <= 1e-6 * lmax
+    k, xi = 8, 1e-3
+    B.pp_setup(op.handle, k, lmin, lmax, xi)
+    r = torch.empty(P.n_u, dtype=torch.float64, device="cuda")
+    B.pp_dfn_rhs(op.handle, dev(q), r)
+    r0 = orc.rhs(q)
+    u0, st0 = O.pcg(orj, k, lmin, lmax, xi, r0, tol=1e-8, maxit=2000)
+    assert st0["status"] == O.OK
+    u = torch.zeros(P.n_u, dtype=torch.float64, device="cuda")
+    s, it, relres = B.pcg_solve(op.handle, r, u, 1e-8, 2000)
+    assert s == B.PP_OK and abs(it - st0["iters"]) <= 2
+    u.zero_()
+    s, it2, _ = B.pcg_solve(op.handle, r, u, 0.0, st0["iters"])
+    assert it2 == st0["iters"]
+    ug = host(u)
+    assert rel(ug, u0) <= 1e-8
+    h = torch.empty(P.n_h, dtype=torch.float64, device="cuda")
+    p = torch.empty_like(h)
+    B.pp_dfn_recover(op.handle, dev(q), u, h, p)
+    hg, pg = host(h), host(p)
+    A, C, Bm, Gh, Gu = (m.to_scipy() for m in (P.a, P.c, P.b, P.gh, P.gu))
+    a = P.alpha
+    sc = np.linalg.norm(q)
+    assert np.linalg.norm(A @ hg - C @ ug - q) <= 1e-10 * sc
+    assert np.linalg.norm(Gh @ hg - a * (Bm @ ug) + A @ pg) <= 1e-8 * sc
+    assert np.linalg.norm(-a * (Bm.T @ hg) + Gu @ ug - C.T @ pg) <= 1e-6 * sc
+    op.close()
+
+
+def _bad(P, **kw):
+    import copy
+
+    Q = copy.copy(P)
+    for k, v in kw.items():
+        setattr(Q, k, v)
+    return Q
+
+
+def _csr(S):
+    S = S.tocsr()
+    S.sort_indices()
+    return W.CSR(S.shape[0], S.shape[1], S.indptr.astype(np.int64), S.indices.astype(np.int32), S.data)
+
+
+def test_invalid_inputs(B):
+    P = W.dfn_su(n_frac=4, G=8, n_traces=6, L_lo=2, L_hi=8, seed=2)
+    # entry of A outside the band of its block
+    a = P.a.to_scipy().tolil()
+    a[0, 63] = a[63, 0] = -1e-3
+    # asymmetric G^u
+    gu = P.gu.to_scipy().tolil()
+    gu[0, 1] += 1.0
+    # a column of C in another fracture's block
+    c = P.c.to_scipy().tolil()
+    j = int(P.u_off[1])  # first unknown of fracture 1
+    c[0, j] = 1.0
+    b = P.b.to_scipy().tolil()
+    b[0, j] = 1.0  # keep B = C + E pattern plausible
+    uo = P.u_off.copy()
+    uo[-1] -= 1
+    for Q, msg in ((_bad(P, a=_csr(a)), "band"), (_bad(P, gu=_csr(gu)), "symmetric"),
+                   (_bad(P, c=_csr(c)), "outside the fracture"), (_bad(P, u_off=uo), "u_off")):
+        with pytest.raises(B.PPError) as e:
+            B.Operator(dfn=Q)
+        assert e.value.status == B.PP_ERR_ARG and msg in str(e.value), str(e.value)
+    with pytest.raises(B.PPError):
+        B.Operator(dfn=P, flags=B.PP_MIXED)
+    # S_u indefinite for a large alpha: a non-positive diag(S_u) or a CG breakdown, never a wrong OK
+    Q = _bad(P, alpha=50.0)
+    try:
+        op = B.Operator(dfn=Q)
+    except B.PPError as e:
+        assert e.status == B.PP_ERR_ARG
+    else:
+        op.close()
