@@ -4,8 +4,9 @@
 //
 // A's blocks are 2-D grids of G x G cells numbered by lines, so every entry lies
 // within distance G of the diagonal and the factor L of a block is banded with
-// the same half-width.  The factor is held by diagonals, Lb[k * n_h + i] =
-// L(i, i-k), k = 0..G (zero where i-k leaves the block).
+// the same half-width.  The factor is held by rows, Lb[i * SP + k] = L(i, i-k),
+// k = 0..G (zero where i-k leaves the block), SP = dfn_stride(G) >= G + 1 even,
+// so a row loads as 16-byte vectors from one address.
 //
 // One wavefront owns one fracture.  A triangular sweep runs over the G grid
 // lines of the block: lane l owns row l of the current line; the coupling to
@@ -29,13 +30,16 @@ struct CsrD {
 
 struct DfnView {
     int64_t F, G, nf, nh, nu;
-    const double *Lb;       // band factor by diagonals, (G + 1) x nh
+    const double *Lb;       // band factor by rows, nh x dfn_stride(G) (+ DFN_GMAX + 2 padding)
     CsrD c, b, gh;          // rows of the fracture cells (b holds a B)
     CsrD ct, bt, gu;        // rows of the unknowns (bt holds a B^T)
 };
 
-// LDS row stride of a staged line of the factor (even, >= G + 1)
+// row stride of the factor in HBM (even, >= G + 1: rows load as 16-byte vectors)
 __host__ __device__ constexpr int dfn_stride(int G) { return (G + 2) & ~1; }
+// row stride of a staged line in LDS (odd, >= G + 1: lanes reading their own
+// rows hit distinct banks)
+__host__ __device__ constexpr int dfn_lstride(int G) { return (G + 1) | 1; }
 
 __device__ __forceinline__ double dfn_rdlane(double v, int l)
 {
@@ -49,7 +53,7 @@ __device__ __forceinline__ double dfn_rdlane(double v, int l)
 // set-up
 // ---------------------------------------------------------------------------
 
-// Lower band of A into Lb (zeroed before): Lb[(i - j) nh + i] = a_ij, j <= i.
+// Lower band of A into Lb (zeroed before): Lb[i SP + (i - j)] = a_ij, j <= i.
 // bad = 1 for an entry outside its fracture block or farther than G from the
 // diagonal.
 static __global__ __launch_bounds__(BLOCK) void k_dfn_band(int64_t nh, int64_t nf, int64_t G, CsrD a,
@@ -63,7 +67,7 @@ static __global__ __launch_bounds__(BLOCK) void k_dfn_band(int64_t nh, int64_t n
                 atomicOr(bad, 1);
                 continue;
             }
-            if (j <= i) Lb[(i - j) * nh + i] += a.val[e];
+            if (j <= i) Lb[i * dfn_stride((int)G) + (i - j)] += a.val[e];
         }
     }
 }
@@ -110,7 +114,7 @@ static __global__ __launch_bounds__(DFN_WAVE) void k_dfn_chol(int64_t nh, int64_
         const int64_t i = f0 + il;
         const int64_t jl = il - G + lane;  // local column of this lane
         const bool act = lane < G && jl >= 0;
-        double s = act ? Lb[(int64_t)(G - lane) * nh + i] : 0.0;
+        double s = act ? Lb[i * SP + (G - lane)] : 0.0;
         for (int q = 0; q < G; ++q) {
             const int64_t jq = il - G + q;
             if (jq < 0) continue;  // uniform
@@ -120,7 +124,7 @@ static __global__ __launch_bounds__(DFN_WAVE) void k_dfn_chol(int64_t nh, int64_
         }
         double sq = act ? s * s : 0.0;
         for (int o = DFN_WAVE / 2; o > 0; o >>= 1) sq += __shfl_xor(sq, o);
-        const double d = Lb[i] - sq;
+        const double d = Lb[i * SP] - sq;
         const bool ok = d > 0.0;
         const double lii = ok ? sqrt(d) : 1.0;
         if (!ok && lane == 0) atomicOr(bad, 4);
@@ -129,12 +133,12 @@ static __global__ __launch_bounds__(DFN_WAVE) void k_dfn_chol(int64_t nh, int64_
         if (lane < G) {
             const double v = act ? s : 0.0;
             ring[slot * SP + (G - lane)] = v;
-            Lb[(int64_t)(G - lane) * nh + i] = v;
+            Lb[i * SP + (G - lane)] = v;
         }
         if (lane == 0) {
             ring[slot * SP] = lii;
             rinv[slot] = 1.0 / lii;
-            Lb[i] = lii;
+            Lb[i * SP] = lii;
         }
         __syncthreads();
     }
@@ -240,8 +244,8 @@ static __global__ __launch_bounds__(DFN_WAVE) void k_dfn_diag(DfnView g, const i
     const int f = wg_frac[blockIdx.x];
     const int64_t j = wg_first[blockIdx.x] + lane;
     const bool act = j < u_end[f];
-    const int64_t nf = g.nf, nh = g.nh, f0 = (int64_t)f * nf;
-    const int G = (int)g.G;
+    const int64_t nf = g.nf, f0 = (int64_t)f * nf;
+    const int G = (int)g.G, SP = dfn_stride(G);
     double *y = yscr + (int64_t)blockIdx.x * nf * DFN_WAVE;
     int64_t pc = act ? g.ct.rp[j] : 0, pce = act ? g.ct.rp[j + 1] : 0;
     for (int64_t r = 0; r < nf; ++r) {
@@ -249,8 +253,8 @@ static __global__ __launch_bounds__(DFN_WAVE) void k_dfn_diag(DfnView g, const i
         double acc = 0.0;
         if (pc < pce && g.ct.col[pc] == gr) acc = g.ct.val[pc++];
         const int kmax = r < G ? (int)r : G;
-        for (int k = kmax; k >= 1; --k) acc -= g.Lb[(int64_t)k * nh + gr] * ring[((r - k) & (DFN_GMAX - 1)) * DFN_WAVE + lane];
-        const double v = acc / g.Lb[gr];
+        for (int k = kmax; k >= 1; --k) acc -= g.Lb[gr * SP + k] * ring[((r - k) & (DFN_GMAX - 1)) * DFN_WAVE + lane];
+        const double v = acc / g.Lb[gr * SP];
         ring[(r & (DFN_GMAX - 1)) * DFN_WAVE + lane] = v;
         y[r * DFN_WAVE + lane] = v;
     }
@@ -263,8 +267,8 @@ static __global__ __launch_bounds__(DFN_WAVE) void k_dfn_diag(DfnView g, const i
         double acc = y[r * DFN_WAVE + lane];
         const int kmax = nf - 1 - r < G ? (int)(nf - 1 - r) : G;
         for (int k = kmax; k >= 1; --k)
-            acc -= g.Lb[(int64_t)k * nh + gr + k] * ring[((r + k) & (DFN_GMAX - 1)) * DFN_WAVE + lane];
-        const double z = acc / g.Lb[gr];
+            acc -= g.Lb[(gr + k) * SP + k] * ring[((r + k) & (DFN_GMAX - 1)) * DFN_WAVE + lane];
+        const double z = acc / g.Lb[gr * SP];
         double gz = 0.0;
         for (int64_t e = g.gh.rp[gr]; e < g.gh.rp[gr + 1]; ++e) {
             const int64_t c = g.gh.col[e];
@@ -290,103 +294,205 @@ static __global__ __launch_bounds__(DFN_WAVE) void k_dfn_diag(DfnView g, const i
 // application (Algorithm 3), right-hand side and recovery
 // ---------------------------------------------------------------------------
 
-// L x = b for NR right-hand sides held in LDS (in place), one wavefront.
-template <int NR>
-__device__ __forceinline__ void dfn_fwd(const DfnView &g, int64_t f0, double *const (&X)[NR], double *LS)
+// The factor entries L(row, row-k), k = 0..GM, of one row as 16-byte loads
+// from one address (entries past G are the row's padding or the next row:
+// masked by the callers).  Lb carries DFN_GMAX + 2 doubles of padding at its end.
+template <int GM>
+__device__ __forceinline__ void dfn_load_row(const DfnView &g, int64_t row, double (&Lr)[GM + 2])
 {
-    const int lane = threadIdx.x, G = (int)g.G, SP = dfn_stride(G);
-    const int64_t nh = g.nh;
-    const bool act = lane < G;
-    for (int K = 0; K < G; ++K) {
-        const int il = K * G + lane;
-        double Lr[DFN_GMAX + 1];
+    const double2 *p = (const double2 *)(g.Lb + row * dfn_stride((int)g.G));
 #pragma unroll
-        for (int k = 0; k <= DFN_GMAX; ++k) Lr[k] = (act && k <= G) ? g.Lb[(int64_t)k * nh + f0 + il] : 0.0;
-        if (act) {
-#pragma unroll
-            for (int k = 0; k <= DFN_GMAX; ++k)
-                if (k <= G) LS[lane * SP + k] = Lr[k];
-        }
-        double s[NR];
-#pragma unroll
-        for (int r = 0; r < NR; ++r) s[r] = act ? X[r][il] : 0.0;
-        if (K > 0) {
-#pragma unroll
-            for (int k = 1; k <= DFN_GMAX; ++k)
-                if (act && k <= G && k > lane) {
-#pragma unroll
-                    for (int r = 0; r < NR; ++r) s[r] -= Lr[k] * X[r][il - k];
-                }
-        }
-        __syncthreads();
-        const double inv = act ? 1.0 / Lr[0] : 0.0;
-        for (int q = 0; q < G; ++q) {
-            double xq[NR];
-#pragma unroll
-            for (int r = 0; r < NR; ++r) xq[r] = dfn_rdlane(s[r] * inv, q);
-            if (lane == q) {
-#pragma unroll
-                for (int r = 0; r < NR; ++r) s[r] = xq[r];
-            } else if (act && lane > q) {
-                const double l = LS[lane * SP + (lane - q)];
-#pragma unroll
-                for (int r = 0; r < NR; ++r) s[r] -= l * xq[r];
-            }
-        }
-        if (act) {
-#pragma unroll
-            for (int r = 0; r < NR; ++r) X[r][il] = s[r];
-        }
-        __syncthreads();
+    for (int k = 0; k < GM + 2; k += 2) {
+        const double2 v = p[k / 2];
+        Lr[k] = v.x;
+        Lr[k + 1] = v.y;
     }
 }
 
-// L^T x = b for NR right-hand sides in LDS (in place); LSa, LSb: two staged lines.
-template <int NR>
-__device__ __forceinline__ void dfn_bwd(const DfnView &g, int64_t f0, double *const (&X)[NR], double *LSa, double *LSb)
+// The fracture kernels run one wavefront per workgroup, so LDS traffic between
+// lanes needs only wavefront-scope ordering; a workgroup barrier would also
+// wait for the next line's factor rows, which are meant to stay in flight.
+__device__ __forceinline__ void dfn_wave_sync()
 {
-    const int lane = threadIdx.x, G = (int)g.G, SP = dfn_stride(G);
-    const int64_t nh = g.nh;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The steps of a sweep go in blocks of DFN_U, and the LDS reads of the next
+// block are issued before the current block's dependent chain runs (one
+// wavefront per SIMD has nothing else to hide LDS latency behind).  Masks
+// enter as factors (1 or 0) so no read hides behind a branch, and every index
+// is clamped into the staged data, so the steps past G change nothing.
+constexpr int DFN_U = 4;
+
+// One step of a line's triangle: lane q's residual sq, times the broadcast
+// reciprocal of its diagonal, is x_q; every lane with a coupling l to row q
+// (l = 0 elsewhere, lane q included) takes l x_q off its residual.  Each lane
+// scales its own residual once at the end of the line.
+template <int NR>
+__device__ __forceinline__ void dfn_step(double (&s)[NR], double l, double invq, int q)
+{
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const double xq = dfn_rdlane(s[r], q) * invq;
+        s[r] -= l * xq;
+    }
+}
+
+// L x = b for NR right-hand sides held in LDS (in place), one wavefront,
+// G <= GM.  Lane l owns row l of the current grid line; the factor rows of the
+// next line load into registers while the current line is solved.
+template <int GM, int NR>
+__device__ __forceinline__ void dfn_fwd(const DfnView &g, int64_t f0, double *const (&X)[NR], double *LS)
+{
+    const int lane = threadIdx.x, G = (int)g.G, SL = dfn_lstride(G);
     const bool act = lane < G;
-    double *cur = LSa, *nxt = LSb;
-    for (int K = G - 1; K >= 0; --K) {
-        const int il = K * G + lane;
-        if (act)
-            for (int k = 0; k <= G; ++k) cur[lane * SP + k] = g.Lb[(int64_t)k * nh + f0 + il];
-        __syncthreads();
+    const int ml = act ? lane : 0;  // row loaded by an idle lane (its values are masked)
+    double *own = LS + ml * SL;
+    double Lr[GM + 2];
+    dfn_load_row<GM>(g, f0 + ml, Lr);
+    for (int K = 0; K < G; ++K) {
+        const int il = K * G + ml;
+        // own row to LDS: the in-line steps read it at lane-dependent offsets
+#pragma unroll
+        for (int k = 0; k <= GM; ++k)
+            if (k <= G) own[k] = Lr[k];
+        const double inv = act ? 1.0 / Lr[0] : 0.0;
         double s[NR];
 #pragma unroll
-        for (int r = 0; r < NR; ++r) s[r] = act ? X[r][il] : 0.0;
-        if (K < G - 1 && act) {
-            // rows (K+1) G + m of the next line couple at distance G + m - lane <= G
-            for (int m = 0; m <= lane; ++m) {
-                const double l = nxt[m * SP + (G + m - lane)];
+        for (int r = 0; r < NR; ++r) s[r] = X[r][il];
+        if (K > 0) {
+            // previous line: rows il - k for lane < k <= G, coefficients from the row in registers
 #pragma unroll
-                for (int r = 0; r < NR; ++r) s[r] -= l * X[r][(K + 1) * G + m];
+            for (int k0 = 1; k0 <= GM; k0 += 8) {
+                double xv[8][NR];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int k = k0 + u, kc = k <= G ? k : G;
+#pragma unroll
+                    for (int r = 0; r < NR; ++r) xv[u][r] = X[r][il - kc];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int k = k0 + u;
+                    if (k <= GM) {
+                        const double c = Lr[k] * ((act && k <= G && k > lane) ? 1.0 : 0.0);
+#pragma unroll
+                        for (int r = 0; r < NR; ++r) s[r] -= c * xv[u][r];
+                    }
+                }
             }
         }
-        const double inv = act ? 1.0 / cur[lane * SP] : 0.0;
-        for (int q = G - 1; q >= 0; --q) {
-            double xq[NR];
+        dfn_load_row<GM>(g, f0 + (K + 1 < G ? il + G : il), Lr);
+        // the line's lower triangle: row q finishes at step q
+        double l[2][DFN_U], iv[2][DFN_U];
+        auto lfetch = [&](int b, int q0) {
 #pragma unroll
-            for (int r = 0; r < NR; ++r) xq[r] = dfn_rdlane(s[r] * inv, q);
-            if (lane == q) {
-#pragma unroll
-                for (int r = 0; r < NR; ++r) s[r] = xq[r];
-            } else if (act && lane < q) {
-                const double l = cur[q * SP + (q - lane)];
-#pragma unroll
-                for (int r = 0; r < NR; ++r) s[r] -= l * xq[r];
+            for (int u = 0; u < DFN_U; ++u) {
+                const int q = q0 + u, d = lane - q;
+                l[b][u] = own[d > 0 ? (d < G ? d : G) : 0] * ((act && d > 0) ? 1.0 : 0.0);
+                iv[b][u] = dfn_rdlane(inv, q & (DFN_WAVE - 1));
             }
+        };
+        lfetch(0, 0);
+        for (int q0 = 0; q0 < G; q0 += 2 * DFN_U) {
+            lfetch(1, q0 + DFN_U);
+#pragma unroll
+            for (int u = 0; u < DFN_U; ++u) dfn_step<NR>(s, l[0][u], iv[0][u], (q0 + u) & (DFN_WAVE - 1));
+            lfetch(0, q0 + 2 * DFN_U);
+#pragma unroll
+            for (int u = 0; u < DFN_U; ++u)
+                dfn_step<NR>(s, l[1][u], iv[1][u], (q0 + DFN_U + u) & (DFN_WAVE - 1));
         }
         if (act) {
 #pragma unroll
-            for (int r = 0; r < NR; ++r) X[r][il] = s[r];
+            for (int r = 0; r < NR; ++r) X[r][il] = s[r] * inv;
         }
-        __syncthreads();
-        double *t = cur;
+        dfn_wave_sync();
+    }
+}
+
+// L^T x = b for NR right-hand sides in LDS (in place); LSa, LSb: two staged
+// lines of factor rows (the current one and the next, already solved, one).
+template <int GM, int NR>
+__device__ __forceinline__ void dfn_bwd(const DfnView &g, int64_t f0, double *const (&X)[NR], double *LSa, double *LSb)
+{
+    const int lane = threadIdx.x, G = (int)g.G, SL = dfn_lstride(G);
+    const bool act = lane < G;
+    const int ml = act ? lane : 0;
+    double *cur = LSa, *nxt = LSb;
+    double Lr[GM + 2];
+    dfn_load_row<GM>(g, f0 + (int64_t)(G - 1) * G + ml, Lr);
+    for (int K = G - 1; K >= 0; --K) {
+        const int il = K * G + ml;
+        if (act) {
+#pragma unroll
+            for (int k = 0; k <= GM; ++k)
+                if (k <= G) cur[lane * SL + k] = Lr[k];
+        }
+        const double inv = act ? 1.0 / Lr[0] : 0.0;
+        dfn_load_row<GM>(g, f0 + (K > 0 ? il - G : il), Lr);
+        dfn_wave_sync();
+        double s[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) s[r] = X[r][il];
+        if (K < G - 1) {
+            // rows (K+1) G + m of the next line couple at distance G + m - lane <= G (m <= lane)
+            double c[2][DFN_U], xv[2][DFN_U][NR];
+            auto fetch = [&](int b, int m0) {
+#pragma unroll
+                for (int u = 0; u < DFN_U; ++u) {
+                    const int m = m0 + u, mc = m < G ? m : G - 1;
+                    const bool on = act && m < G && m <= lane;
+                    c[b][u] = nxt[mc * SL + (on ? G + m - lane : G)] * (on ? 1.0 : 0.0);
+#pragma unroll
+                    for (int r = 0; r < NR; ++r) xv[b][u][r] = X[r][(K + 1) * G + mc];
+                }
+            };
+            fetch(0, 0);
+            for (int m0 = 0; m0 < G; m0 += 2 * DFN_U) {
+                fetch(1, m0 + DFN_U);
+#pragma unroll
+                for (int u = 0; u < DFN_U; ++u)
+#pragma unroll
+                    for (int r = 0; r < NR; ++r) s[r] -= c[0][u] * xv[0][u][r];
+                fetch(0, m0 + 2 * DFN_U);
+#pragma unroll
+                for (int u = 0; u < DFN_U; ++u)
+#pragma unroll
+                    for (int r = 0; r < NR; ++r) s[r] -= c[1][u] * xv[1][u][r];
+            }
+        }
+        // the line's upper triangle (of L^T): row q finishes at step G-1-q
+        double l[2][DFN_U], iv[2][DFN_U];
+        auto lfetch = [&](int b, int t0) {
+#pragma unroll
+            for (int u = 0; u < DFN_U; ++u) {
+                const int q = G - 1 - (t0 + u), qc = q > 0 ? q : 0, d = q - lane;
+                l[b][u] = cur[qc * SL + (d > 0 ? d : 0)] * ((act && d > 0) ? 1.0 : 0.0);
+                iv[b][u] = dfn_rdlane(inv, q & (DFN_WAVE - 1));
+            }
+        };
+        lfetch(0, 0);
+        for (int t0 = 0; t0 < G; t0 += 2 * DFN_U) {
+            lfetch(1, t0 + DFN_U);
+#pragma unroll
+            for (int u = 0; u < DFN_U; ++u)
+                dfn_step<NR>(s, l[0][u], iv[0][u], (G - 1 - (t0 + u)) & (DFN_WAVE - 1));
+            lfetch(0, t0 + 2 * DFN_U);
+#pragma unroll
+            for (int u = 0; u < DFN_U; ++u)
+                dfn_step<NR>(s, l[1][u], iv[1][u], (G - 1 - (t0 + DFN_U + u)) & (DFN_WAVE - 1));
+        }
+        if (act) {
+#pragma unroll
+            for (int r = 0; r < NR; ++r) X[r][il] = s[r] * inv;
+        }
+        dfn_wave_sync();
+        double *tt = cur;
         cur = nxt;
-        nxt = t;
+        nxt = tt;
     }
 }
 
@@ -396,7 +502,8 @@ __device__ __forceinline__ void dfn_bwd(const DfnView &g, int64_t f0, double *co
 // and t, d to HBM.  For Algorithm 3 (q = 0) these are the t of its step 4 and
 // the w of step 6 minus the w of step 10; with x = 0 they give the reduced
 // right-hand side (t = A^{-1} q, d = -A^{-1} G^h A^{-1} q); with x = u they are
-// the recovered h and p.  Dynamic LDS: 2 nf + 2 G SP doubles.
+// the recovered h and p.  Dynamic LDS: 2 nf + 2 G dfn_lstride(G) doubles.
+template <int GM>
 static __global__ __launch_bounds__(DFN_WAVE) void k_dfn_frac(DfnView g, const double *__restrict__ x,
                                                               const double *__restrict__ s,
                                                               const double *__restrict__ q, double *__restrict__ out_t,
@@ -405,9 +512,9 @@ static __global__ __launch_bounds__(DFN_WAVE) void k_dfn_frac(DfnView g, const d
     if (st != nullptr && st->done) return;
     extern __shared__ __align__(16) unsigned char dfn_lds[];
     const int lane = threadIdx.x;
-    const int G = (int)g.G, SP = dfn_stride(G);
+    const int G = (int)g.G, SL = dfn_lstride(G);
     const int64_t nf = g.nf, f0 = (int64_t)blockIdx.x * nf;
-    double *X1 = (double *)dfn_lds, *X2 = X1 + nf, *LSa = X2 + nf, *LSb = LSa + (int64_t)G * SP;
+    double *X1 = (double *)dfn_lds, *X2 = X1 + nf, *LSa = X2 + nf, *LSb = LSa + (int64_t)G * SL;
     for (int64_t il = lane; il < nf; il += DFN_WAVE) {
         const int64_t gi = f0 + il;
         double v = q ? q[gi] : 0.0, z = 0.0;
@@ -427,8 +534,8 @@ static __global__ __launch_bounds__(DFN_WAVE) void k_dfn_frac(DfnView g, const d
     __syncthreads();
     {
         double *const XX[2] = {X1, X2};
-        dfn_fwd<2>(g, f0, XX, LSa);
-        dfn_bwd<2>(g, f0, XX, LSa, LSb);
+        dfn_fwd<GM, 2>(g, f0, XX, LSa);
+        dfn_bwd<GM, 2>(g, f0, XX, LSa, LSb);
     }
     for (int64_t il = lane; il < nf; il += DFN_WAVE) {
         out_t[f0 + il] = X1[il];
@@ -444,8 +551,8 @@ static __global__ __launch_bounds__(DFN_WAVE) void k_dfn_frac(DfnView g, const d
     __syncthreads();
     {
         double *const XX[1] = {X2};
-        dfn_fwd<1>(g, f0, XX, LSa);
-        dfn_bwd<1>(g, f0, XX, LSa, LSb);
+        dfn_fwd<GM, 1>(g, f0, XX, LSa);
+        dfn_bwd<GM, 1>(g, f0, XX, LSa, LSb);
     }
     for (int64_t il = lane; il < nf; il += DFN_WAVE) out_d[f0 + il] = out_d[f0 + il] - X2[il];
 }

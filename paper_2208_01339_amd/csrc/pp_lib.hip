@@ -442,17 +442,31 @@ void launch_cheb_rt(pp_op_s *op, const XT *xg, const T *w, const RT *r, const T 
         launch_cheb<T, XT, RT, OT, MODE, SCHUR, false, false>(op, xg, w, r, sold, out, c, fin);
 }
 
+// The fracture kernel for the smallest compiled band bound >= G.
+void launch_frac(pp_op_s *op, const double *x, const double *s, const double *q, double *t, double *d,
+                 const ppk::State *st)
+{
+    const ppk::DfnView g = op->dview();
+    const size_t lds = sizeof(double) * (2 * (size_t)g.nf + 2 * (size_t)g.G * ppk::dfn_lstride((int)g.G));
+    const dim3 grid((unsigned)g.F), blk(ppk::DFN_WAVE);
+    if (g.G <= 16)
+        hipLaunchKernelGGL(ppk::k_dfn_frac<16>, grid, blk, lds, op->stream, g, x, s, q, t, d, st);
+    else if (g.G <= 32)
+        hipLaunchKernelGGL(ppk::k_dfn_frac<32>, grid, blk, lds, op->stream, g, x, s, q, t, d, st);
+    else if (g.G <= 48)
+        hipLaunchKernelGGL(ppk::k_dfn_frac<48>, grid, blk, lds, op->stream, g, x, s, q, t, d, st);
+    else
+        hipLaunchKernelGGL(ppk::k_dfn_frac<64>, grid, blk, lds, op->stream, g, x, s, q, t, d, st);
+}
+
 // y = D^{-1/2} S_u D^{-1/2} x by Algorithm 3 (DFN): one wavefront per fracture
 // for the three solves with the factor, then the rows of the unknowns.
 // live_state: skip once the solve is done.
 void enqueue_su(pp_op_s *op, const double *x, double *y, bool live_state)
 {
     const ppk::DfnView g = op->dview();
-    const int SP = ppk::dfn_stride((int)g.G);
-    const size_t lds = sizeof(double) * (2 * (size_t)g.nf + 2 * (size_t)g.G * SP);
     const ppk::State *st = live_state ? (const ppk::State *)op->st : nullptr;
-    hipLaunchKernelGGL(ppk::k_dfn_frac, dim3((unsigned)g.F), dim3(ppk::DFN_WAVE), lds, op->stream, g, x,
-                       (const double *)op->dis, (const double *)nullptr, op->dfn_t, op->dfn_d, st);
+    launch_frac(op, x, (const double *)op->dis, (const double *)nullptr, op->dfn_t, op->dfn_d, st);
     hipLaunchKernelGGL(ppk::k_dfn_urow, dim3(op->grid_elems(op->n)), dim3(BLOCK), 0, op->stream, g, x,
                        (const double *)op->dis, (const double *)op->dfn_t, (const double *)op->dfn_d, 1.0, -1.0,
                        -1.0, y, st);
@@ -980,8 +994,9 @@ pp_status dfn_build(pp_op_s *op, const pp_dfn_desc &d)
         if (bad & 1) { cleanup(); return fail(PP_ERR_ARG, "A or G^h has an entry outside its fracture block or band"); }
         if (bad & 2) { cleanup(); return fail(PP_ERR_ARG, "A, G^h or G^u is not symmetric (or has unsorted rows)"); }
         // band factor
-        op->dfn_Lb = dalloc<double>((size_t)(G + 1) * nh);
-        HIPCHK(hipMemsetAsync(op->dfn_Lb, 0, sizeof(double) * (G + 1) * nh, op->stream));
+        const size_t lbn = (size_t)nh * ppk::dfn_stride((int)G) + ppk::DFN_GMAX + 2;
+        op->dfn_Lb = dalloc<double>(lbn);
+        HIPCHK(hipMemsetAsync(op->dfn_Lb, 0, sizeof(double) * lbn, op->stream));
         hipLaunchKernelGGL(ppk::k_dfn_band, dim3(gh_), dim3(BLOCK), 0, op->stream, nh, nf, G,
                            ppk::CsrD{d.a.rowptr, d.a.col, d.a.val}, op->dfn_Lb, flag_d);
         hipLaunchKernelGGL(ppk::k_dfn_chol, dim3((unsigned)F), dim3(ppk::DFN_WAVE), 0, op->stream, nh, nf, (int)G,
@@ -1135,10 +1150,8 @@ pp_status pp_dfn_rhs(pp_op op, const double *q, double *r)
     if (!op->dfn()) return fail(PP_ERR_ARG, "not a DFN operator");
     try {
         const ppk::DfnView g = op->dview();
-        const size_t lds = sizeof(double) * (2 * (size_t)g.nf + 2 * (size_t)g.G * ppk::dfn_stride((int)g.G));
-        hipLaunchKernelGGL(ppk::k_dfn_frac, dim3((unsigned)g.F), dim3(ppk::DFN_WAVE), lds, op->stream, g,
-                           (const double *)nullptr, (const double *)nullptr, q, op->dfn_t, op->dfn_d,
-                           (const ppk::State *)nullptr);
+        launch_frac(op, (const double *)nullptr, (const double *)nullptr, q, op->dfn_t, op->dfn_d,
+                    (const ppk::State *)nullptr);
         hipLaunchKernelGGL(ppk::k_dfn_urow, dim3(op->grid_elems(op->n)), dim3(BLOCK), 0, op->stream, g,
                            (const double *)nullptr, (const double *)nullptr, (const double *)op->dfn_t,
                            (const double *)op->dfn_d, 0.0, 1.0, 1.0, r, (const ppk::State *)nullptr);
@@ -1156,10 +1169,7 @@ pp_status pp_dfn_recover(pp_op op, const double *q, const double *u, double *h, 
     if (!op->dfn()) return fail(PP_ERR_ARG, "not a DFN operator");
     if (h == p) return fail(PP_ERR_ARG, "h and p must not alias");
     try {
-        const ppk::DfnView g = op->dview();
-        const size_t lds = sizeof(double) * (2 * (size_t)g.nf + 2 * (size_t)g.G * ppk::dfn_stride((int)g.G));
-        hipLaunchKernelGGL(ppk::k_dfn_frac, dim3((unsigned)g.F), dim3(ppk::DFN_WAVE), lds, op->stream, g, u,
-                           (const double *)nullptr, q, h, p, (const ppk::State *)nullptr);
+        launch_frac(op, u, (const double *)nullptr, q, h, p, (const ppk::State *)nullptr);
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(op->stream));
     } catch (HipError &e) {
