@@ -32,6 +32,10 @@ The JSON line also carries:
   mixed         the same solve with the polynomial in FP32 (PP_MIXED);
   newton        the same solve with the Newton form of Algorithm 1 at degrees
                 15 and 63 against the three-term form at the same degrees;
+  dfn_su        the DFN Schur complement S_u of section 4.1 (Algorithms 3 and 4;
+                400 fractures of 48 x 48, n_u = 55,132): iterations, time and
+                S_u applications at the degrees of Table tab11 (xi = 1e-3),
+                the rank-one correction at degree 31, and the recovery of h, p;
   lowrank       the same solve, the DFN one and the Poisson 32^3 one (k = 10)
                 with the spectral low-rank correction of section 3.1 from
                 Ritz vectors of 64 Lanczos steps, ranks 1 and 4 (3 for
@@ -145,6 +149,90 @@ def run_dfn(args, B, W, torch, dev):
     if not args.no_lowrank:
         out["lowrank"] = lowrank_leg(B, torch, h, bd, x, k, lmin, lmax, args.tol, args.maxit)
     B.pp_destroy(h)
+    return out
+
+
+def run_dfn_su(args, B, W, torch, dev):
+    """The DFN Schur complement S_u of section 4.1 (400 fractures of 48 x 48 cells,
+    1100 traces: n_h = 921,600, n_u = 55,132, the sizes of the paper's DFN test
+    case #1): reduced right-hand side, PCG on D_S^{-1/2} S_u D_S^{-1/2} at the
+    degrees of Table tab11 (xi = 1e-3), recovery of h and p.  The time of one
+    S_u application (Algorithm 3) is the solve time over the operator
+    applications."""
+    t0 = time.perf_counter()
+    P = W.dfn_su()
+    t_gen = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    op = B.Operator(dfn=P)
+    torch.cuda.synchronize()
+    t_create = time.perf_counter() - t0
+    h = op.handle
+    t0 = time.perf_counter()
+    lmin, lmax = B.pp_estimate_bounds(h, 20)
+    t_bounds = time.perf_counter() - t0
+    q = torch.from_numpy(W.rhs_uniform(P.n_h, 1)).to(dev)
+    r = torch.empty(P.n_u, dtype=torch.float64, device=dev)
+    B.pp_dfn_rhs(h, q, r)
+    u = torch.zeros(P.n_u, dtype=torch.float64, device=dev)
+    xi = 1e-3
+    rows = []
+    for k in args.dfn_su_ks:
+        B.pp_setup(h, k, lmin, lmax, xi)
+        u.zero_()
+        B.pcg_solve(h, r, u, args.tol, args.maxit)
+        u.zero_()
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        status, it, rel = B.pcg_solve(h, r, u, args.tol, args.maxit)
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - s0
+        st = B.pp_get_stats(h)
+        rows.append(dict(k=k, iters=it, s_per_solve=ts, op_applies=st["op_applies"], dots=st["dots"],
+                         us_per_su_apply=1e6 * ts / max(1, st["op_applies"]), relres=rel,
+                         status=B.pp_status_str(status)))
+        log("dfn S_u k=%d: %d iters, %.3f s, %d S_u applications (%.0f us each), %d dots"
+            % (k, it, ts, st["op_applies"], rows[-1]["us_per_su_apply"], st["dots"]))
+    best = min(rows, key=lambda x: x["s_per_solve"])
+    B.pp_setup(h, best["k"], lmin, lmax, xi)
+    u.zero_()
+    B.pcg_solve(h, r, u, args.tol, args.maxit)
+    hh = torch.empty(P.n_h, dtype=torch.float64, device=dev)
+    pp = torch.empty_like(hh)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.pp_dfn_recover(h, q, u, hh, pp)
+    t_rec = time.perf_counter() - t0
+    # residual of the mass balance A h - C u = q (sparse product on the device)
+    a = P.a.to_scipy().tocsr()
+    c = P.c.to_scipy().tocsr()
+    mb = a @ hh.cpu().numpy() - c @ u.cpu().numpy() - q.cpu().numpy()
+    mb_rel = float(np.linalg.norm(mb) / np.linalg.norm(q.cpu().numpy()))
+    lowrank = None
+    if not args.no_lowrank:
+        th = B.pp_lowrank_ritz(h, 64, 1)
+        B.pp_setup(h, 31, lmin, lmax, xi)
+        u.zero_()
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        status, it, rel = B.pcg_solve(h, r, u, args.tol, args.maxit)
+        torch.cuda.synchronize()
+        st = B.pp_get_stats(h)
+        lowrank = dict(k=31, rank=1, iters=it, s_per_solve=time.perf_counter() - s0, op_applies=st["op_applies"],
+                       dots=st["dots"], ritz_value=float(th[0]), status=B.pp_status_str(status))
+        log("dfn S_u k=31 rank-one correction: %d iters, %d S_u applications, %d dots"
+            % (it, st["op_applies"], st["dots"]))
+        B.pp_lowrank_set(h, 0)
+    # stored factor bytes per application: three solves in two paired sweeps (fwd + bwd each)
+    sp = (P.grid + 2) & ~1
+    fbytes = 4 * P.n_h * sp * 8
+    out = dict(workload="dfn_su_400x48x48_1100traces_alpha1", n_h=P.n_h, n_u=P.n_u, n_frac=P.n_frac, grid=P.grid,
+               nnz=dict(a=P.a.nnz, gh=P.gh.nnz, c=P.c.nnz, b=P.b.nnz, gu=P.gu.nnz), xi=xi,
+               bounds=[lmin, lmax], gen_s=t_gen, create_s=t_create, bounds_s=t_bounds, per_k=rows,
+               best_k=best["k"], s_per_solve=best["s_per_solve"], recover_s=t_rec, mass_balance_relres=mb_rel,
+               lowrank=lowrank, factor_bytes_per_apply=fbytes,
+               factor_gbs=fbytes / (best["us_per_su_apply"] * 1e-6) / 1e9)
+    op.close()
     return out
 
 
@@ -298,6 +386,8 @@ def main():
     ap.add_argument("--no-block", action="store_true", help="skip the 32-RHS block leg")
     ap.add_argument("--no-lowrank", action="store_true", help="skip the low-rank correction legs")
     ap.add_argument("--no-newton", action="store_true", help="skip the Newton-form leg")
+    ap.add_argument("--no-dfn-su", action="store_true", help="skip the DFN S_u leg (section 4.1)")
+    ap.add_argument("--dfn-su-ks", default="0,7,15,31,63")
     ap.add_argument("--no-two-step", action="store_true",
                     help="one pass per Chebyshev step (no fused pairs) in the main leg")
     ap.add_argument("--block-rhs", type=int, default=32)
@@ -539,6 +629,8 @@ def main():
         B.pp_destroy(hp)
 
     dfn = None if args.no_dfn else run_dfn(args, B, W, torch, dev)
+    args.dfn_su_ks = [int(v) for v in args.dfn_su_ks.split(",")]
+    dfn_su = None if args.no_dfn_su else run_dfn_su(args, B, W, torch, dev)
 
     def fp64_single(k):
         """Time of one plain FP64 solve (first block column) at degree k on the same operator."""
@@ -600,6 +692,7 @@ def main():
         "newton": newton,
         "lowrank": lowrank,
         "dfn": dfn,
+        "dfn_su": dfn_su,
         "block": block,
         "batch256": batch256,
         "setup": {"create_s": round(t_create, 3), "lanczos_s": round(t_bounds, 4),
