@@ -556,7 +556,7 @@ void enqueue_newton(pp_op_s *op, const double *rr, double *zout, int fin, bool s
 // Steps j and j+1 (both three-term steps) in one pass of k_cheb2_stencil.
 template <typename T>
 void launch_pair(pp_op_s *op, const T *sm1, const T *sm2, const T *r, T *o1, T *o2, const StepCoef &c1,
-                 const StepCoef &c2)
+                 const StepCoef &c2, bool dot)
 {
     ppk::Stencil2 g;
     g.N = op->s2N;
@@ -567,14 +567,25 @@ void launch_pair(pp_op_s *op, const T *sm1, const T *sm2, const T *r, T *o1, T *
     const dim3 grid((unsigned)(g.nty * g.nzc));
     const T *dv = sizeof(T) == 4 ? (const T *)op->dval32 : (const T *)op->dval;
     const size_t lds = sizeof(T) * (2 * ppk::S2_RY + (ppk::S2_SL ? 2 * (ppk::S2_RY + 2) : 0)) * (size_t)g.N;
-    if (op->ntload)
-        hipLaunchKernelGGL((ppk::k_cheb2_stencil<T, true, ppk::S2_BS, ppk::S2_SL>), grid, dim3(ppk::S2_BS), lds, op->stream, g,
-                           dv, op->dstride, sm1, sm2, r, o1, o2, c1.cx, c1.cold, c1.cr, c1.cA, c2.cx, c2.cold, c2.cr,
-                           c2.cA, (const ppk::State *)op->st);
-    else
-        hipLaunchKernelGGL((ppk::k_cheb2_stencil<T, false, ppk::S2_BS, ppk::S2_SL>), grid, dim3(ppk::S2_BS), lds, op->stream, g,
-                           dv, op->dstride, sm1, sm2, r, o1, o2, c1.cx, c1.cold, c1.cr, c1.cA, c2.cx, c2.cold, c2.cr,
-                           c2.cA, (const ppk::State *)op->st);
+    const ppk::State *st = (const ppk::State *)op->st;
+#define PP_PAIR(NTV, DOTV)                                                                                          \
+    hipLaunchKernelGGL((ppk::k_cheb2_stencil<T, NTV, ppk::S2_BS, ppk::S2_SL, DOTV>), grid, dim3(ppk::S2_BS), lds,   \
+                       op->stream, g, dv, op->dstride, sm1, sm2, r, o1, o2, c1.cx, c1.cold, c1.cr, c1.cA, c2.cx,      \
+                       c2.cold, c2.cr, c2.cA, st, op->partials)
+    if (op->ntload) {
+        if (dot) PP_PAIR(true, true);
+        else PP_PAIR(true, false);
+    } else {
+        if (dot) PP_PAIR(false, true);
+        else PP_PAIR(false, false);
+    }
+#undef PP_PAIR
+}
+
+// workgroups of a pair launch (the partials it writes when it ends the polynomial)
+int pair_grid(const pp_op_s *op)
+{
+    return (int)(((op->s2N + ppk::S2_TY - 1) / ppk::S2_TY) * ((op->s2NZ + ppk::S2_ZC - 1) / ppk::S2_ZC));
 }
 
 hipEvent_t pair_event(pp_op_s *op)
@@ -587,34 +598,45 @@ hipEvent_t pair_event(pp_op_s *op)
     return op->pev[op->pev_i++];
 }
 
-// p_k(A-hat) rr with pairs of three-term steps fused (3-D 7-point operators,
-// k >= 5).  T: the step precision (double, or float in mixed mode with r32 =
-// (float) rr already made); the last step writes the FP64 output with the
-// dot product / scaling.  Four step buffers rotate: a pair writes s_j and
-// s_{j+1} to the two that hold neither input.
+// p_k(A-hat) rr with pairs of Chebyshev steps fused (3-D 7-point operators,
+// k >= 4): steps (1, 2), (3, 4), ...; step 1 reads r in place of s_{j-1}
+// (its coefficients of s_{j-1} and s_{j-2} are zero, as is step 2's of
+// s_{j-2}).  When k is even and the output is not scaled, the last pair
+// writes zout and reduces rr . zout; otherwise the remaining step(s) run
+// alone, the last one with the reduction / scaling.  T: double.  Four step
+// buffers rotate: a pair writes s_j and s_{j+1} to two that hold neither input.
 template <typename T>
 void enqueue_poly_pairs(pp_op_s *op, const double *rr, const T *rT, T *const (&buf)[4], double *zout, int fin,
                         bool scale)
 {
     const int k = op->k;
-    launch_step<T, T, T, T, 1>(op, rT, rT, (const T *)nullptr, buf[0], step_coef(op, 1), ppk::FIN_NONE, false);
-    launch_step<T, T, T, T, 2>(op, buf[0], rT, (const T *)nullptr, buf[1], step_coef(op, 2), ppk::FIN_NONE, false);
-    int ic = 1, io = 0;  // buffers of s_{j-1} and s_{j-2}
-    int j = 3;
-    const bool timed = op->time_pairs && 4 <= k - 1;
+    const bool last_pair = !scale && k % 2 == 0 && pair_grid(op) <= 8192;  // partials hold 8192 per column
+    int ic = -1, io = -1;  // buffers of s_{j-1} and s_{j-2} (-1: r)
+    int j = 1;
+    const bool timed = op->time_pairs;
     if (timed) HIPCHK(hipEventRecord(pair_event(op), op->stream));
     int pairs = 0;
-    for (; j + 1 <= k - 1; j += 2) {
+    while (j + 1 <= k - 1 || (j + 1 == k && last_pair)) {
+        const bool ends = j + 1 == k;
         int a = -1, b = -1;
         for (int q = 0; q < 4; ++q)
             if (q != ic && q != io) (a < 0 ? a : b) = q;
-        launch_pair<T>(op, buf[ic], buf[io], rT, buf[a], buf[b], step_coef(op, j), step_coef(op, j + 1));
+        const T *sm1 = ic < 0 ? rT : buf[ic], *sm2 = io < 0 ? rT : buf[io];
+        launch_pair<T>(op, sm1, sm2, rT, buf[a], ends ? (T *)zout : buf[b], step_coef(op, j), step_coef(op, j + 1),
+                       ends && fin != ppk::FIN_NONE);
         ++pairs;
         io = a;
         ic = b;
+        j += 2;
     }
-    if (timed) op->pairs_per_poly = pairs;
-    if (timed) HIPCHK(hipEventRecord(pair_event(op), op->stream));
+    if (timed) {
+        op->pairs_per_poly = pairs;
+        HIPCHK(hipEventRecord(pair_event(op), op->stream));
+    }
+    if (j > k) {  // the last pair ended the polynomial
+        if (fin != ppk::FIN_NONE) enqueue_fin(op, pair_grid(op), fin);
+        return;
+    }
     if (j <= k - 1) {  // one three-term step left before the last: in place over s_{j-2}
         launch_step<T, T, T, T, 3>(op, buf[ic], rT, buf[io], buf[io], step_coef(op, j), ppk::FIN_NONE, false);
         std::swap(ic, io);
@@ -635,7 +657,7 @@ void enqueue_poly(pp_op_s *op, const double *rr, double *zout, int fin, bool sca
     const int k = op->k;
     // fused pairs in FP64 only: in FP32 the bytes saved do not pay for the halo
     // rows and the lower occupancy (measured)
-    if (op->s2 && op->two_step && k >= 5 && !op->mixed()) {
+    if (op->s2 && op->two_step && k >= 4 && !op->mixed()) {
         double *const buf[4] = {op->sA, op->sB, op->sC, op->sD};
         enqueue_poly_pairs<double>(op, rr, rr, buf, zout, fin, scale);
         return;

@@ -42,17 +42,19 @@ constexpr int s2_cells_per_thread() { return (S2_RY * (int)S2_NMAX + BS - 1) / B
 // and z and the coupling to plane z-1 travel in registers from plane to
 // plane, so nothing is read twice apart from the in-plane neighbours of
 // s_{j-1} (cache hits).  LDS: two planes of s_j (double buffer, one barrier
-// per plane).  Absent neighbours enter as zero couplings times a clamped
+// per plane).  DOT: the pair ends the polynomial; partials[L] receives this
+// workgroup's part of r . s_{j+1} (the dot product of the CG step).  Absent neighbours enter as zero couplings times a clamped
 // (in-range) value.
-template <typename T, bool NT, int BS, bool SL>
+template <typename T, bool NT, int BS, bool SL, bool DOT>
 static __global__ __launch_bounds__(BS) void k_cheb2_stencil(Stencil2 g, const T *__restrict__ dv, int64_t ds,
                                                          const T *__restrict__ sm1, const T *__restrict__ sm2,
                                                          const T *__restrict__ r, T *__restrict__ out1,
                                                          T *__restrict__ out2, double c1x, double c1o, double c1r,
                                                          double c1A, double c2x, double c2o, double c2r,
-                                                         double c2A, const State *st)
+                                                         double c2A, const State *st, double *partials)
 {
     if (st != nullptr && st->done) return;
+    double dotp = 0.0;  // r . s_{j+1} over this workgroup (DOT)
     constexpr int MM = s2_cells_per_thread<BS>();
     extern __shared__ __align__(16) unsigned char s2_lds[];
     const int G = (int)gridDim.x;
@@ -156,6 +158,7 @@ static __global__ __launch_bounds__(BS) void k_cheb2_stencil(Stencil2 g, const T
                 o2 += a2o * s_m[m];
                 if constexpr (NT) __builtin_nontemporal_store(o2, out2 + i2);
                 else out2[i2] = o2;
+                if constexpr (DOT) dotp += (double)rp[m] * (double)o2;
             }
             cur[m] = sj;
             if (c < cells) pl[c] = sj;
@@ -192,6 +195,19 @@ static __global__ __launch_bounds__(BS) void k_cheb2_stencil(Stencil2 g, const T
             s_c[m] = xp[m];
         }
         buf ^= 1;
+    }
+    if constexpr (DOT) {
+        // this workgroup's part of r . s_{j+1}, summed in a fixed order
+        __shared__ double red[BS / WAVE];
+        dotp = wave_sum(dotp);
+        if ((threadIdx.x & (WAVE - 1)) == 0) red[threadIdx.x / WAVE] = dotp;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double tot = 0.0;
+#pragma unroll
+            for (int w = 0; w < BS / WAVE; ++w) tot += red[w];
+            partials[L] = tot;
+        }
     }
 }
 
