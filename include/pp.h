@@ -302,11 +302,14 @@ enum {
     PP_OPT_NT_LOADS = 5,    /* 1 = non-temporal accesses for the streams read once per step */
                             /* (the sliced matrix; r, s_{j-2} and the output with stored */
                             /* diagonals), 0 = plain; default 1 from 2^22 rows on       */
-    PP_OPT_TWO_STEP = 6     /* 1 (default) = on 3-D 7-point operators (stored diagonals at  */
-                            /* offsets 0, 1, N, N^2, no coupling across the box's x- and   */
-                            /* y-faces, N <= 256) fuse pairs of FP64 Chebyshev steps into  */
-                            /* one pass (tiles of whole x-lines with one recomputed halo   */
-                            /* line each side, marching up z), 0 = one pass per step      */
+    PP_OPT_TWO_STEP = 6     /* on 3-D 7-point operators (stored diagonals at offsets 0, 1,  */
+                            /* N, N^2, no coupling across the box's x- and y-faces,        */
+                            /* N <= 256) fuse pairs of FP64 Chebyshev steps into one pass  */
+                            /* (tiles of whole x-lines with one recomputed halo line each  */
+                            /* side, marching up z): 1 (default) = when the box's tiles    */
+                            /* fill whole rounds of compute units (one tile per CU) at     */
+                            /* least 90 %, 2 = for any box, 0 = one pass per step.  Other  */
+                            /* values: PP_ERR_ARG                                          */
 };
 PP_API pp_status pp_set_option(pp_op op, int key, int64_t value);
 

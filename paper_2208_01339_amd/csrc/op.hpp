@@ -54,7 +54,8 @@ struct pp_op_s {
     // two Chebyshev steps per pass (3-D 7-point operators): box N x N x s2NZ,
     // two more step buffers
     bool s2 = false;
-    int two_step = 1;
+    int two_step = 1;  // 0 off, 1 when the box fills the device, 2 for any box
+    int cus = 256;     // compute units of the device (pair launches want one workgroup per CU)
     int64_t s2N = 0, s2NZ = 0;
     double *sC = nullptr, *sD = nullptr;
     double *partials = nullptr;  // (1 + LR_MAX) * 8192 doubles

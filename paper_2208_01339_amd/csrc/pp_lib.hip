@@ -332,6 +332,7 @@ pp_status create_common(pp_op *out, int kind, int64_t n, int64_t nnz, const int6
             &occ, (const void *)ppk::k_cheb<double, double, double, double, 3, false, false, false, true>, BLOCK,
             0) == hipSuccess &&
         cus > 0 && occ > 0) {
+        op->cus = cus;
         op->grid_auto = std::min(8192, cus * occ);
         op->grid_max = op->grid_auto;
     }
@@ -554,16 +555,45 @@ void enqueue_newton(pp_op_s *op, const double *rr, double *zout, int fin, bool s
 }
 
 // Steps j and j+1 (both three-term steps) in one pass of k_cheb2_stencil.
-template <typename T>
-void launch_pair(pp_op_s *op, const T *sm1, const T *sm2, const T *r, T *o1, T *o2, const StepCoef &c1,
-                 const StepCoef &c2, bool dot)
+// Tiles of a pair launch: y-tiles of S2_TY lines; z-chunks of 32 planes, or
+// 16 or 8.  A pair workgroup holds a whole CU, so the chunk is taken only if
+// the tiles fill whole rounds of CUs at least 90 % (256^3: 256 tiles of 32
+// planes); zc = 0 when none does (the one-step kernels are then faster:
+// 160^3 and 192^3 measured 25-30 % slower with a part-filled last round).
+ppk::Stencil2 pair_shape(const pp_op_s *op)
 {
     ppk::Stencil2 g;
     g.N = op->s2N;
     g.NZ = op->s2NZ;
     g.n = op->n;
     g.nty = (int)((g.N + ppk::S2_TY - 1) / ppk::S2_TY);
-    g.nzc = (int)((g.NZ + ppk::S2_ZC - 1) / ppk::S2_ZC);
+    g.zc = 0;
+    const int64_t cus = op->cus;
+    for (int zc = ppk::S2_ZC_MAX; zc >= 8; zc /= 2) {
+        const int64_t nwg = (int64_t)g.nty * ((g.NZ + zc - 1) / zc);
+        const int64_t rounds = (nwg + cus - 1) / cus;
+        if (nwg >= cus && 10 * nwg >= 9 * rounds * cus) {
+            g.zc = zc;
+            break;
+        }
+    }
+    if (g.zc == 0 && op->two_step == 2) g.zc = ppk::S2_ZC_MAX;
+    g.nzc = g.zc > 0 ? (int)((g.NZ + g.zc - 1) / g.zc) : 0;
+    return g;
+}
+
+// Fused pairs of Chebyshev steps for this polynomial (three-term form, FP64,
+// a 3-D 7-point box large enough, or forced)
+bool use_pairs(const pp_op_s *op)
+{
+    return op->s2 && op->two_step != 0 && op->form == 0 && !op->mixed() && pair_shape(op).zc > 0;
+}
+
+template <typename T>
+void launch_pair(pp_op_s *op, const T *sm1, const T *sm2, const T *r, T *o1, T *o2, const StepCoef &c1,
+                 const StepCoef &c2, bool dot)
+{
+    const ppk::Stencil2 g = pair_shape(op);
     const dim3 grid((unsigned)(g.nty * g.nzc));
     const T *dv = sizeof(T) == 4 ? (const T *)op->dval32 : (const T *)op->dval;
     const size_t lds = sizeof(T) * (2 * ppk::S2_RY + (ppk::S2_SL ? 2 * (ppk::S2_RY + 2) : 0)) * (size_t)g.N;
@@ -585,7 +615,8 @@ void launch_pair(pp_op_s *op, const T *sm1, const T *sm2, const T *r, T *o1, T *
 // workgroups of a pair launch (the partials it writes when it ends the polynomial)
 int pair_grid(const pp_op_s *op)
 {
-    return (int)(((op->s2N + ppk::S2_TY - 1) / ppk::S2_TY) * ((op->s2NZ + ppk::S2_ZC - 1) / ppk::S2_ZC));
+    const ppk::Stencil2 g = pair_shape(op);
+    return g.nty * g.nzc;
 }
 
 hipEvent_t pair_event(pp_op_s *op)
@@ -657,7 +688,7 @@ void enqueue_poly(pp_op_s *op, const double *rr, double *zout, int fin, bool sca
     const int k = op->k;
     // fused pairs in FP64 only: in FP32 the bytes saved do not pay for the halo
     // rows and the lower occupancy (measured)
-    if (op->s2 && op->two_step && k >= 4 && !op->mixed()) {
+    if (k >= 4 && use_pairs(op)) {
         double *const buf[4] = {op->sA, op->sB, op->sC, op->sD};
         enqueue_poly_pairs<double>(op, rr, rr, buf, zout, fin, scale);
         return;
@@ -1280,7 +1311,10 @@ pp_status pp_set_option(pp_op op, int key, int64_t value)
         op->driver = (int)value;
         return PP_OK;
     case PP_OPT_NT_LOADS: op->ntload = value != 0; return PP_OK;
-    case PP_OPT_TWO_STEP: op->two_step = value != 0; return PP_OK;
+    case PP_OPT_TWO_STEP:
+        if (value < 0 || value > 2) return fail(PP_ERR_ARG, "PP_OPT_TWO_STEP must be 0, 1 or 2");
+        op->two_step = (int)value;
+        return PP_OK;
     default: return fail(PP_ERR_ARG, "unknown option");
     }
 }
@@ -1289,7 +1323,7 @@ pp_status pp_get_stats(pp_op op, pp_stats *st)
 {
     if (!op || !st) return fail(PP_ERR_ARG, "NULL argument");
     *st = op->stats;
-    st->two_step = (op->s2 && op->two_step && op->form == 0) ? 1 : 0;
+    st->two_step = use_pairs(op) ? 1 : 0;
     return PP_OK;
 }
 

@@ -6,7 +6,7 @@
 //   s_{j+1} = c2x s_j     + c2o s_{j-1} + c2r r + c2A (A s_j)
 //
 // Each workgroup owns S2_TY whole x-lines (contiguous rows of N cells, so the
-// HBM streams stay long) over S2_ZC z-planes and marches up z.  For every
+// HBM streams stay long) over zc z-planes and marches up z.  For every
 // plane it computes s_j on its lines plus one halo line each side, and s_{j+1}
 // one plane behind.  The operator, r and s_{j-1} are read once for both steps;
 // the halo lines and the planes just outside the z-range are computed twice
@@ -20,7 +20,7 @@ namespace ppk {
 
 constexpr int S2_TY = 8;              // y-rows per tile (full x-lines, one halo row each side)
 constexpr int S2_RY = S2_TY + 2;
-constexpr int S2_ZC = 32;             // z-planes per workgroup
+constexpr int S2_ZC_MAX = 32;         // z-planes per workgroup: 32, else 16 or 8 (enough workgroups)
 constexpr int64_t S2_NMAX = 256;      // widest x-line (sizes the per-thread register arrays)
 constexpr int S2_BS = 512;            // threads per workgroup
 constexpr bool S2_SL = true;          // in-plane neighbours of s_{j-1} from LDS
@@ -28,6 +28,7 @@ constexpr bool S2_SL = true;          // in-plane neighbours of s_{j-1} from LDS
 struct Stencil2 {
     int64_t N, NZ, n;
     int nty, nzc;   // y-tiles and z-chunks
+    int zc;         // z-planes per chunk
 };
 
 template <int BS>
@@ -62,7 +63,7 @@ static __global__ __launch_bounds__(BS) void k_cheb2_stencil(Stencil2 g, const T
     const int ty = L % g.nty, tz = L / g.nty;
     const int64_t N = g.N, N2 = N * N, NZ = g.NZ;
     const int64_t y0 = (int64_t)ty * S2_TY - 1;
-    const int64_t z0 = (int64_t)tz * S2_ZC, z1 = z0 + S2_ZC < NZ ? z0 + S2_ZC : NZ;
+    const int64_t z0 = (int64_t)tz * g.zc, z1 = z0 + g.zc < NZ ? z0 + g.zc : NZ;
     const int64_t cells = (int64_t)S2_RY * N;
     const T a1x = (T)c1x, a1o = (T)c1o, a1r = (T)c1r, a1A = (T)c1A;
     const T a2x = (T)c2x, a2o = (T)c2o, a2r = (T)c2r, a2A = (T)c2A;

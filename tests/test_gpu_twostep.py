@@ -55,11 +55,12 @@ CASES = {
 
 
 @pytest.mark.parametrize("name", list(CASES))
-@pytest.mark.parametrize("k,xi", [(5, 0.0), (6, 1e-3), (20, 0.0), (21, 1e-2)])
+@pytest.mark.parametrize("k,xi", [(4, 0.0), (5, 0.0), (6, 1e-3), (20, 0.0), (21, 1e-2)])
 def test_pairs_match_single_steps_and_oracle(B, name, k, xi):
     build, jac = CASES[name]
     a = build()
     op = B.Operator(a=a, flags=B.PP_JACOBI if jac else 0)
+    B.pp_set_option(op.handle, B.PP_OPT_TWO_STEP, 2)  # these boxes are smaller than the automatic rule's
     assert B.pp_get_stats(op.handle)["two_step"] == 1
     orc = O.Operator(a, jacobi=jac)
     lmin, lmax = O.lanczos_bounds(orc, 20)
@@ -86,14 +87,19 @@ def test_mixed_mode_keeps_single_steps(B):
     op.close()
 
 
-@pytest.mark.parametrize("name", ["hetero37", "box23x23x9"])
-def test_pairs_pcg_parity(B, name):
+@pytest.mark.parametrize("k", [4, 7, 12])
+@pytest.mark.parametrize("name", ["hetero37", "box23x23x9", "box40x40x33"])
+def test_pairs_pcg_parity(B, name, k):
+    """Even k: the last pair carries the dot product of the CG step; odd k: the
+    last step runs alone; k = 4: the smallest degree that uses pairs."""
     build, jac = CASES[name]
     a = build()
     op = B.Operator(a=a, flags=B.PP_JACOBI)
+    B.pp_set_option(op.handle, B.PP_OPT_TWO_STEP, 2)
+    assert B.pp_get_stats(op.handle)["two_step"] == 1
     orc = O.Operator(a, jacobi=True)
     lmin, lmax = O.lanczos_bounds(orc, 20)
-    k, xi = 12, 1e-3
+    xi = 1e-3
     b = W.rhs_uniform(a.n_rows, 1)
     xo, sto = O.pcg(orc, k, lmin, lmax, xi, b, tol=1e-8, maxit=2000)
     B.pp_setup(op.handle, k, lmin, lmax, xi)
@@ -137,6 +143,7 @@ def test_pair_timing_stats(B):
     for even k the last pair carries the dot product), one application per iteration."""
     a = W.hetero_diffusion(24, 2.0, 2)
     op = B.Operator(a=a, flags=B.PP_JACOBI)
+    B.pp_set_option(op.handle, B.PP_OPT_TWO_STEP, 2)
     orc = O.Operator(a, jacobi=True)
     lmin, lmax = O.lanczos_bounds(orc, 20)
     b = dev(W.rhs_uniform(a.n_rows, 3))
@@ -155,4 +162,20 @@ def test_pair_timing_stats(B):
         B.pcg_solve(op.handle, b, x, 1e-8, 500)
         st = B.pp_get_stats(op.handle)
         assert st["pair_launches"] == 0 and st["pair_ms"] == 0
+    op.close()
+
+
+def test_automatic_rule(B):
+    """By default pairs run only when the box gives at least one tile per compute
+    unit (a 24^3 box gives three); 2 forces them, 0 turns them off, other values
+    are refused."""
+    a = W.hetero_diffusion(24, 1.0, 3)
+    op = B.Operator(a=a, flags=B.PP_JACOBI)
+    assert B.pp_get_stats(op.handle)["two_step"] == 0
+    B.pp_set_option(op.handle, B.PP_OPT_TWO_STEP, 2)
+    assert B.pp_get_stats(op.handle)["two_step"] == 1
+    B.pp_set_option(op.handle, B.PP_OPT_TWO_STEP, 0)
+    assert B.pp_get_stats(op.handle)["two_step"] == 0
+    with pytest.raises(B.PPError):
+        B.pp_set_option(op.handle, B.PP_OPT_TWO_STEP, 3)
     op.close()
