@@ -4,9 +4,14 @@
 //
 // A's blocks are 2-D grids of G x G cells numbered by lines, so every entry lies
 // within distance G of the diagonal and the factor L of a block is banded with
-// the same half-width.  The factor is held by rows, Lb[i * SP + k] = L(i, i-k),
-// k = 0..G (zero where i-k leaves the block), SP = dfn_stride(G) >= G + 1 even,
-// so a row loads as 16-byte vectors from one address.
+// the same half-width.  The factor is held by rows with its columns scaled by
+// their diagonal, L~ = L D^{-1} (D = diag L): Lb[i * SP] = 1 / L(i, i) and
+// Lb[i * SP + k] = L(i, i-k) / L(i-k, i-k), k = 1..G (zero where i-k leaves the
+// block), SP = dfn_stride(G) >= G + 1 even, so a row loads as 16-byte vectors
+// from one address.  With L~ the forward sweep gives y = D x for L x = b and
+// the backward sweep takes x / L(i, i) = y / L(i, i)^2: every step of a sweep
+// subtracts a coupling times an unscaled, broadcast value, with no division
+// or product by a diagonal on the dependent chain.
 //
 // One wavefront owns one fracture.  A triangular sweep runs over the G grid
 // lines of the block: lane l owns row l of the current line; the coupling to
@@ -97,7 +102,7 @@ static __global__ __launch_bounds__(BLOCK) void k_dfn_sym(int64_t n, CsrD a, int
 }
 
 // Exact Cholesky factor of every block, in place in Lb (which holds A's lower
-// band on entry).  One wavefront per fracture, row by row:
+// band on entry; L~ and 1 / L(i, i) on exit).  One wavefront per fracture, row by row:
 //   L(i, j) = (a_ij - sum_{m<j} L(i, m) L(j, m)) / L(j, j)   for the G columns j < i,
 //   L(i, i) = sqrt(a_ii - sum_{m<i} L(i, m)^2).
 // Lane l holds column j = i - G + l; the G columns are finished in order, the
@@ -130,15 +135,18 @@ static __global__ __launch_bounds__(DFN_WAVE) void k_dfn_chol(int64_t nh, int64_
         if (!ok && lane == 0) atomicOr(bad, 4);
         __syncthreads();
         const int slot = (int)(il % G);
+        // the ring keeps L itself (the recurrence needs it), Lb gets L~
+        const double v = act ? s : 0.0;
+        const double vs = act ? s * rinv[jl % G] : 0.0;
+        __syncthreads();
         if (lane < G) {
-            const double v = act ? s : 0.0;
             ring[slot * SP + (G - lane)] = v;
-            Lb[i * SP + (G - lane)] = v;
+            Lb[i * SP + (G - lane)] = vs;
         }
         if (lane == 0) {
             ring[slot * SP] = lii;
             rinv[slot] = 1.0 / lii;
-            Lb[i * SP] = lii;
+            Lb[i * SP] = 1.0 / lii;
         }
         __syncthreads();
     }
@@ -254,9 +262,8 @@ static __global__ __launch_bounds__(DFN_WAVE) void k_dfn_diag(DfnView g, const i
         if (pc < pce && g.ct.col[pc] == gr) acc = g.ct.val[pc++];
         const int kmax = r < G ? (int)r : G;
         for (int k = kmax; k >= 1; --k) acc -= g.Lb[gr * SP + k] * ring[((r - k) & (DFN_GMAX - 1)) * DFN_WAVE + lane];
-        const double v = acc / g.Lb[gr * SP];
-        ring[(r & (DFN_GMAX - 1)) * DFN_WAVE + lane] = v;
-        y[r * DFN_WAVE + lane] = v;
+        ring[(r & (DFN_GMAX - 1)) * DFN_WAVE + lane] = acc;  // y = D (L^{-1} c)
+        y[r * DFN_WAVE + lane] = acc;
     }
     double zgz = 0.0, zb = 0.0;
     int64_t pb = act ? g.bt.rp[j + 1] - 1 : -1;
@@ -264,11 +271,12 @@ static __global__ __launch_bounds__(DFN_WAVE) void k_dfn_diag(DfnView g, const i
     while (pb >= pbe && g.bt.col[pb] >= f0 + nf) --pb;
     for (int64_t r = nf - 1; r >= 0; --r) {
         const int64_t gr = f0 + r;
-        double acc = y[r * DFN_WAVE + lane];
+        const double iv = g.Lb[gr * SP];
+        double acc = y[r * DFN_WAVE + lane] * iv * iv;
         const int kmax = nf - 1 - r < G ? (int)(nf - 1 - r) : G;
         for (int k = kmax; k >= 1; --k)
             acc -= g.Lb[(gr + k) * SP + k] * ring[((r + k) & (DFN_GMAX - 1)) * DFN_WAVE + lane];
-        const double z = acc / g.Lb[gr * SP];
+        const double z = acc;
         double gz = 0.0;
         for (int64_t e = g.gh.rp[gr]; e < g.gh.rp[gr + 1]; ++e) {
             const int64_t c = g.gh.col[e];
@@ -326,23 +334,20 @@ __device__ __forceinline__ void dfn_wave_sync()
 // is clamped into the staged data, so the steps past G change nothing.
 constexpr int DFN_U = 4;
 
-// One step of a line's triangle: lane q's residual sq, times the broadcast
-// reciprocal of its diagonal, is x_q; every lane with a coupling l to row q
-// (l = 0 elsewhere, lane q included) takes l x_q off its residual.  Each lane
-// scales its own residual once at the end of the line.
+// One step of a line's triangle: lane q's value is final; every lane with a
+// coupling l (an entry of L~) to row q takes l times it off its own
+// (l = 0 elsewhere, lane q included).
 template <int NR>
-__device__ __forceinline__ void dfn_step(double (&s)[NR], double l, double invq, int q)
+__device__ __forceinline__ void dfn_step(double (&s)[NR], double l, int q)
 {
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        const double xq = dfn_rdlane(s[r], q) * invq;
-        s[r] -= l * xq;
-    }
+    for (int r = 0; r < NR; ++r) s[r] -= l * dfn_rdlane(s[r], q);
 }
 
-// L x = b for NR right-hand sides held in LDS (in place), one wavefront,
-// G <= GM.  Lane l owns row l of the current grid line; the factor rows of the
-// next line load into registers while the current line is solved.
+// y = D L^{-1} b for NR right-hand sides held in LDS (in place), one
+// wavefront, G <= GM:  y_i = b_i - sum_{j<i} L~(i, j) y_j.  Lane l owns row l
+// of the current grid line; the factor rows of the next line load into
+// registers while the current line is solved.
 template <int GM, int NR>
 __device__ __forceinline__ void dfn_fwd(const DfnView &g, int64_t f0, double *const (&X)[NR], double *LS)
 {
@@ -358,7 +363,6 @@ __device__ __forceinline__ void dfn_fwd(const DfnView &g, int64_t f0, double *co
 #pragma unroll
         for (int k = 0; k <= GM; ++k)
             if (k <= G) own[k] = Lr[k];
-        const double inv = act ? 1.0 / Lr[0] : 0.0;
         double s[NR];
 #pragma unroll
         for (int r = 0; r < NR; ++r) s[r] = X[r][il];
@@ -386,35 +390,35 @@ __device__ __forceinline__ void dfn_fwd(const DfnView &g, int64_t f0, double *co
         }
         dfn_load_row<GM>(g, f0 + (K + 1 < G ? il + G : il), Lr);
         // the line's lower triangle: row q finishes at step q
-        double l[2][DFN_U], iv[2][DFN_U];
+        double l[2][DFN_U];
         auto lfetch = [&](int b, int q0) {
 #pragma unroll
             for (int u = 0; u < DFN_U; ++u) {
                 const int q = q0 + u, d = lane - q;
                 l[b][u] = own[d > 0 ? (d < G ? d : G) : 0] * ((act && d > 0) ? 1.0 : 0.0);
-                iv[b][u] = dfn_rdlane(inv, q & (DFN_WAVE - 1));
             }
         };
         lfetch(0, 0);
         for (int q0 = 0; q0 < G; q0 += 2 * DFN_U) {
             lfetch(1, q0 + DFN_U);
 #pragma unroll
-            for (int u = 0; u < DFN_U; ++u) dfn_step<NR>(s, l[0][u], iv[0][u], (q0 + u) & (DFN_WAVE - 1));
+            for (int u = 0; u < DFN_U; ++u) dfn_step<NR>(s, l[0][u], (q0 + u) & (DFN_WAVE - 1));
             lfetch(0, q0 + 2 * DFN_U);
 #pragma unroll
-            for (int u = 0; u < DFN_U; ++u)
-                dfn_step<NR>(s, l[1][u], iv[1][u], (q0 + DFN_U + u) & (DFN_WAVE - 1));
+            for (int u = 0; u < DFN_U; ++u) dfn_step<NR>(s, l[1][u], (q0 + DFN_U + u) & (DFN_WAVE - 1));
         }
         if (act) {
 #pragma unroll
-            for (int r = 0; r < NR; ++r) X[r][il] = s[r] * inv;
+            for (int r = 0; r < NR; ++r) X[r][il] = s[r];
         }
         dfn_wave_sync();
     }
 }
 
-// L^T x = b for NR right-hand sides in LDS (in place); LSa, LSb: two staged
-// lines of factor rows (the current one and the next, already solved, one).
+// x = L^{-T} D^{-1} y for NR right-hand sides in LDS (in place):
+// x_i = y_i / L(i, i)^2 - sum_{j>i} L~(j, i) x_j, so after the forward sweep
+// X holds A^{-1} b.  LSa, LSb: two staged lines of factor rows (the current
+// one and the next, already solved, one).
 template <int GM, int NR>
 __device__ __forceinline__ void dfn_bwd(const DfnView &g, int64_t f0, double *const (&X)[NR], double *LSa, double *LSb)
 {
@@ -431,12 +435,12 @@ __device__ __forceinline__ void dfn_bwd(const DfnView &g, int64_t f0, double *co
             for (int k = 0; k <= GM; ++k)
                 if (k <= G) cur[lane * SL + k] = Lr[k];
         }
-        const double inv = act ? 1.0 / Lr[0] : 0.0;
+        const double inv = act ? Lr[0] : 0.0;
         dfn_load_row<GM>(g, f0 + (K > 0 ? il - G : il), Lr);
         dfn_wave_sync();
         double s[NR];
 #pragma unroll
-        for (int r = 0; r < NR; ++r) s[r] = X[r][il];
+        for (int r = 0; r < NR; ++r) s[r] = X[r][il] * inv * inv;
         if (K < G - 1) {
             // rows (K+1) G + m of the next line couple at distance G + m - lane <= G (m <= lane)
             double c[2][DFN_U], xv[2][DFN_U][NR];
@@ -465,29 +469,27 @@ __device__ __forceinline__ void dfn_bwd(const DfnView &g, int64_t f0, double *co
             }
         }
         // the line's upper triangle (of L^T): row q finishes at step G-1-q
-        double l[2][DFN_U], iv[2][DFN_U];
+        double l[2][DFN_U];
         auto lfetch = [&](int b, int t0) {
 #pragma unroll
             for (int u = 0; u < DFN_U; ++u) {
                 const int q = G - 1 - (t0 + u), qc = q > 0 ? q : 0, d = q - lane;
                 l[b][u] = cur[qc * SL + (d > 0 ? d : 0)] * ((act && d > 0) ? 1.0 : 0.0);
-                iv[b][u] = dfn_rdlane(inv, q & (DFN_WAVE - 1));
             }
         };
         lfetch(0, 0);
         for (int t0 = 0; t0 < G; t0 += 2 * DFN_U) {
             lfetch(1, t0 + DFN_U);
 #pragma unroll
-            for (int u = 0; u < DFN_U; ++u)
-                dfn_step<NR>(s, l[0][u], iv[0][u], (G - 1 - (t0 + u)) & (DFN_WAVE - 1));
+            for (int u = 0; u < DFN_U; ++u) dfn_step<NR>(s, l[0][u], (G - 1 - (t0 + u)) & (DFN_WAVE - 1));
             lfetch(0, t0 + 2 * DFN_U);
 #pragma unroll
             for (int u = 0; u < DFN_U; ++u)
-                dfn_step<NR>(s, l[1][u], iv[1][u], (G - 1 - (t0 + DFN_U + u)) & (DFN_WAVE - 1));
+                dfn_step<NR>(s, l[1][u], (G - 1 - (t0 + DFN_U + u)) & (DFN_WAVE - 1));
         }
         if (act) {
 #pragma unroll
-            for (int r = 0; r < NR; ++r) X[r][il] = s[r] * inv;
+            for (int r = 0; r < NR; ++r) X[r][il] = s[r];
         }
         dfn_wave_sync();
         double *tt = cur;
