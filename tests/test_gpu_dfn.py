@@ -183,3 +183,57 @@ def test_invalid_inputs(B):
         assert e.status == B.PP_ERR_ARG
     else:
         op.close()
+
+
+def _with_empty_fracture(P):
+    """P plus one more fracture (a copy of block 0 of A and G^h) that owns no
+    unknowns and meets no trace."""
+    import scipy.sparse as sp
+
+    nf = P.grid ** 2
+    Q = _bad(P)
+    for nm in ("a", "gh"):
+        M = getattr(P, nm).to_scipy()
+        blk = M[:nf, :nf]
+        setattr(Q, nm, _csr(sp.block_diag([M, blk]).tocsr()))
+    for nm in ("c", "b"):
+        M = getattr(P, nm).to_scipy()
+        setattr(Q, nm, _csr(sp.vstack([M, sp.csr_matrix((nf, P.n_u))]).tocsr()))
+    Q.n_frac = P.n_frac + 1
+    Q.u_off = np.concatenate([P.u_off, P.u_off[-1:]])
+    return Q
+
+
+@pytest.mark.parametrize("shape", ["empty_fracture", "one_cell"])
+def test_degenerate_shapes(B, shape):
+    """A fracture with no unknowns (skipped by Algorithm 4's workgroups, a zero
+    block in every solve); one-cell fractures (G = 1: G^h = 0, alpha small
+    enough for a positive diag(S_u); S_u itself is only semidefinite there)."""
+    if shape == "empty_fracture":
+        P = _with_empty_fracture(W.dfn_su(n_frac=5, G=7, n_traces=8, L_lo=2, L_hi=7, seed=9))
+    else:
+        P = W.dfn_su(n_frac=6, G=1, n_traces=9, L_lo=1, L_hi=1, seed=7, alpha=0.01)
+    orc = O.DfnOperator(P, jacobi=False)
+    assert np.all(orc.diag_raw() > 0)
+    op = B.Operator(dfn=P)
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(P.n_u)
+    y = torch.empty(P.n_u, dtype=torch.float64, device="cuda")
+    B.pp_operator_apply(op.handle, dev(x), y)
+    assert rel(host(y), orc.apply(x)) <= 1e-11
+    q = W.rhs_uniform(P.n_h, 4)
+    r = torch.empty(P.n_u, dtype=torch.float64, device="cuda")
+    B.pp_dfn_rhs(op.handle, dev(q), r)
+    assert rel(host(r), orc.rhs(q)) <= 1e-11
+    h = torch.empty(P.n_h, dtype=torch.float64, device="cuda")
+    p = torch.empty_like(h)
+    B.pp_dfn_recover(op.handle, dev(q), dev(x), h, p)
+    h0, p0 = orc.recover(q, x)
+    assert rel(host(h), h0) <= 1e-11 and rel(host(p), p0) <= 1e-11
+    # D_S from Algorithm 4 on the device: pp_apply at k = 0 is D_S^{-1} r / theta
+    B.pp_setup(op.handle, 0, 0.5, 2.0, 0.0)
+    z = torch.empty(P.n_u, dtype=torch.float64, device="cuda")
+    B.pp_apply(op.handle, dev(x), z)
+    theta = (0.5 + 2.0) / 2
+    assert rel(host(z), x / orc.diag_raw() / theta) <= 1e-12
+    op.close()
