@@ -13,12 +13,11 @@
 // subtracts a coupling times an unscaled, broadcast value, with no division
 // or product by a diagonal on the dependent chain.
 //
-// One wavefront owns one fracture.  A triangular sweep runs over the G grid
-// lines of the block: lane l owns row l of the current line; the coupling to
-// the previous (forward) or next (backward) line is a dense product, and the
-// line's own lower (upper) triangle is solved in G steps, each finishing one
-// row and broadcasting its value from that lane.  All vectors of the block
-// live in LDS during the three solves of Algorithm 3.
+// One wavefront owns one fracture.  The sweeps of the application read the
+// factor rearranged by sweep step (k_dfn_qcoef): a sweep is a chain of nf
+// steps, each finishing one row and broadcasting its value from the lane that
+// holds it, while every lane takes that value's coupling off its own row.  All
+// vectors of the block live in LDS during the solves of Algorithm 3.
 #pragma once
 #include "kernels.hpp"
 
@@ -36,6 +35,8 @@ struct CsrD {
 struct DfnView {
     int64_t F, G, nf, nh, nu;
     const double *Lb;       // band factor by rows, nh x dfn_stride(G) (+ DFN_GMAX + 2 padding)
+    const double *Qf, *Qb;  // the factor by sweep steps, nh x G each (+ DFN_WAVE padding)
+    const double *di2;      // 1 / L(i, i)^2, nh
     CsrD c, b, gh;          // rows of the fracture cells (b holds a B)
     CsrD ct, bt, gu;        // rows of the unknowns (bt holds a B^T)
 };
@@ -302,24 +303,60 @@ static __global__ __launch_bounds__(DFN_WAVE) void k_dfn_diag(DfnView g, const i
 // application (Algorithm 3), right-hand side and recovery
 // ---------------------------------------------------------------------------
 
-// The factor entries L(row, row-k), k = 0..GM, of one row as 16-byte loads
-// from one address (entries past G are the row's padding or the next row:
-// masked by the callers).  Lb carries DFN_GMAX + 2 doubles of padding at its end.
-template <int GM>
-__device__ __forceinline__ void dfn_load_row(const DfnView &g, int64_t row, double (&Lr)[GM + 2])
+// Sweep layout of the factor.  Either triangular sweep of a block is one
+// recurrence over its rows in sweep order (rows 0, 1, ... for L~; rows nf-1,
+// nf-2, ... for L~^T), and sweep position p sits in lane p mod G: one grid line
+// of G rows across the lanes.  At step p the value of position p is final.  Its
+// lane broadcasts it, and every lane subtracts its row's coupling to that
+// value; a lane's row is the next position of its residue class after p, at
+// distance k = ((l - p - 1) mod G) + 1 in 1..G.  The broadcasting lane moves on
+// to position p + G, and its coefficient carries an extra 1: the FMA clears
+// the finished value and leaves only the new row's coupling to it.  Step p's
+// coefficients for lanes 0..G-1 are stored together:
+//   forward   Qf[p][l] = L~(p + k, p)
+//   backward  Qb[p][l] = L~(nf-1-p, nf-1-p-k)
+// plus 1 where l = p mod G, and 0 where the coupled row leaves the block (the
+// forward sweep reads a column of L~ per step, the backward one a row).  Both
+// arrays carry DFN_WAVE doubles of padding.  di2[i] = 1 / L(i, i)^2.
+static __global__ __launch_bounds__(BLOCK) void k_dfn_qcoef(int64_t nh, int64_t nf, int G,
+                                                            const double *__restrict__ Lb, double *__restrict__ Qf,
+                                                            double *__restrict__ Qb, double *__restrict__ di2)
 {
-    const double2 *p = (const double2 *)(g.Lb + row * dfn_stride((int)g.G));
-#pragma unroll
-    for (int k = 0; k < GM + 2; k += 2) {
-        const double2 v = p[k / 2];
-        Lr[k] = v.x;
-        Lr[k + 1] = v.y;
+    const int SP = dfn_stride(G);
+    const int64_t tot = nh * G;
+    for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < tot; e += (int64_t)gridDim.x * BLOCK) {
+        const int64_t gp = e / G;
+        const int l = (int)(e - gp * G);
+        const int64_t f0 = gp / nf * nf, p = gp - f0;
+        const int s = (int)(p % G);
+        const int k = (l - s - 1 + 2 * G) % G + 1;
+        const double one = l == s ? 1.0 : 0.0;
+        const int64_t rf = p + k;  // forward: row p + k couples to row p
+        Qf[e] = (rf < nf ? Lb[(f0 + rf) * SP + k] : 0.0) + one;
+        const int64_t t = nf - 1 - p;  // backward: row t couples to row t - k
+        Qb[e] = (t - k >= 0 ? Lb[(f0 + t) * SP + k] : 0.0) + one;
+        if (l == 0) {
+            const double v = Lb[gp * SP];
+            di2[gp] = v * v;
+        }
     }
 }
 
+// v_writelane through its LLVM intrinsic (clang exposes no builtin for it)
+__device__ int dfn_writelane_i32(int v, int lane, int old) __asm("llvm.amdgcn.writelane");
+
+// old with lane l replaced by the (uniform) value v
+__device__ __forceinline__ double dfn_wrlane(double v, double old, int l)
+{
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const unsigned long long o = (unsigned long long)__double_as_longlong(old);
+    const int lo = dfn_writelane_i32((int)(unsigned)(u & 0xffffffffull), l, (int)(unsigned)(o & 0xffffffffull));
+    const int hi = dfn_writelane_i32((int)(unsigned)(u >> 32), l, (int)(unsigned)(o >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
 // The fracture kernels run one wavefront per workgroup, so LDS traffic between
-// lanes needs only wavefront-scope ordering; a workgroup barrier would also
-// wait for the next line's factor rows, which are meant to stay in flight.
+// lanes needs only wavefront-scope ordering.
 __device__ __forceinline__ void dfn_wave_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -327,185 +364,68 @@ __device__ __forceinline__ void dfn_wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// The steps of a sweep go in blocks of DFN_U, and the LDS reads of the next
-// block are issued before the current block's dependent chain runs (one
-// wavefront per SIMD has nothing else to hide LDS latency behind).  Masks
-// enter as factors (1 or 0) so no read hides behind a branch, and every index
-// is clamped into the staged data, so the steps past G change nothing.
-constexpr int DFN_U = 4;
-
-// One step of a line's triangle: lane q's value is final; every lane with a
-// coupling l (an entry of L~) to row q takes l times it off its own
-// (l = 0 elsewhere, lane q included).
-template <int NR>
-__device__ __forceinline__ void dfn_step(double (&s)[NR], double l, int q)
+// One triangular sweep of a block, in place on its nf values X (LDS):
+//   forward  (REV = false): X = D^{-2} L~^{-1} X   (di2: the block's 1/L(i,i)^2)
+//   backward (REV = true):  X = L~^{-T} X
+// so forward then backward gives A^{-1} X (A = L~ D^2 L~^T).  Q: the block's
+// Qf or Qb.  A line of G steps is unrolled (GM >= G; EX: GM == G) with the
+// lane's coefficients in registers, two buffers used by alternate lines: the
+// next line's G loads are in flight while this line runs.  Lanes G..63 hold
+// no row: they load lane 0's coefficients and their values are never
+// broadcast or stored.
+template <int GM, bool EX, bool REV>
+__device__ __forceinline__ void dfn_sweep(const double *__restrict__ Q, const double *__restrict__ di2, int G,
+                                          double *X)
 {
-#pragma unroll
-    for (int r = 0; r < NR; ++r) s[r] -= l * dfn_rdlane(s[r], q);
-}
-
-// y = D L^{-1} b for NR right-hand sides held in LDS (in place), one
-// wavefront, G <= GM:  y_i = b_i - sum_{j<i} L~(i, j) y_j.  Lane l owns row l
-// of the current grid line; the factor rows of the next line load into
-// registers while the current line is solved.
-template <int GM, int NR>
-__device__ __forceinline__ void dfn_fwd(const DfnView &g, int64_t f0, double *const (&X)[NR], double *LS)
-{
-    const int lane = threadIdx.x, G = (int)g.G, SL = dfn_lstride(G);
+    const int lane = threadIdx.x;
     const bool act = lane < G;
-    const int ml = act ? lane : 0;  // row loaded by an idle lane (its values are masked)
-    double *own = LS + ml * SL;
-    double Lr[GM + 2];
-    dfn_load_row<GM>(g, f0 + ml, Lr);
-    for (int K = 0; K < G; ++K) {
-        const int il = K * G + ml;
-        // own row to LDS: the in-line steps read it at lane-dependent offsets
+    const int64_t nf = (int64_t)G * G;
+    const double *qp = Q + (act ? lane : 0);  // the lane's coefficient of step p: qp[p * G]
+    auto row = [&](int K) -> int64_t {       // the row of line K in this lane
+        const int64_t p = (int64_t)K * G + lane;
+        return REV ? nf - 1 - p : p;
+    };
+    double ca[GM], cb[GM];
+    double acc = act ? X[row(0)] : 0.0, fin = 0.0;
+    // line K with coefficients cur; the next line's (the last line: its own again) into nxt
+    auto line = [&](int K, double (&cur)[GM], double (&nxt)[GM]) {
+        const int64_t nl = (int64_t)(K + 1 < G ? K + 1 : K) * G;
+        const double sc = (!REV && act) ? di2[row(K)] : 1.0;
 #pragma unroll
-        for (int k = 0; k <= GM; ++k)
-            if (k <= G) own[k] = Lr[k];
-        double s[NR];
-#pragma unroll
-        for (int r = 0; r < NR; ++r) s[r] = X[r][il];
-        if (K > 0) {
-            // previous line: rows il - k for lane < k <= G, coefficients from the row in registers
-#pragma unroll
-            for (int k0 = 1; k0 <= GM; k0 += 8) {
-                double xv[8][NR];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int k = k0 + u, kc = k <= G ? k : G;
-#pragma unroll
-                    for (int r = 0; r < NR; ++r) xv[u][r] = X[r][il - kc];
-                }
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int k = k0 + u;
-                    if (k <= GM) {
-                        const double c = Lr[k] * ((act && k <= G && k > lane) ? 1.0 : 0.0);
-#pragma unroll
-                        for (int r = 0; r < NR; ++r) s[r] -= c * xv[u][r];
-                    }
-                }
-            }
+        for (int q = 0; q < GM; ++q) {
+            if (!EX && q >= G) break;
+            nxt[q] = qp[(nl + q) * G];
         }
-        dfn_load_row<GM>(g, f0 + (K + 1 < G ? il + G : il), Lr);
-        // the line's lower triangle: row q finishes at step q
-        double l[2][DFN_U];
-        auto lfetch = [&](int b, int q0) {
 #pragma unroll
-            for (int u = 0; u < DFN_U; ++u) {
-                const int q = q0 + u, d = lane - q;
-                l[b][u] = own[d > 0 ? (d < G ? d : G) : 0] * ((act && d > 0) ? 1.0 : 0.0);
-            }
-        };
-        lfetch(0, 0);
-        for (int q0 = 0; q0 < G; q0 += 2 * DFN_U) {
-            lfetch(1, q0 + DFN_U);
-#pragma unroll
-            for (int u = 0; u < DFN_U; ++u) dfn_step<NR>(s, l[0][u], (q0 + u) & (DFN_WAVE - 1));
-            lfetch(0, q0 + 2 * DFN_U);
-#pragma unroll
-            for (int u = 0; u < DFN_U; ++u) dfn_step<NR>(s, l[1][u], (q0 + DFN_U + u) & (DFN_WAVE - 1));
+        for (int q = 0; q < GM; ++q) {
+            if (!EX && q >= G) break;
+            const double v = dfn_rdlane(acc, q);
+            fin = dfn_wrlane(v, fin, q);
+            acc -= cur[q] * v;
         }
-        if (act) {
+        if (act) X[row(K)] = REV ? fin : fin * sc;
+        if (K + 1 < G && act) acc += X[row(K + 1)];
+    };
 #pragma unroll
-            for (int r = 0; r < NR; ++r) X[r][il] = s[r];
-        }
-        dfn_wave_sync();
+    for (int q = 0; q < GM; ++q) {
+        if (!EX && q >= G) break;
+        ca[q] = qp[(int64_t)q * G];
     }
-}
-
-// x = L^{-T} D^{-1} y for NR right-hand sides in LDS (in place):
-// x_i = y_i / L(i, i)^2 - sum_{j>i} L~(j, i) x_j, so after the forward sweep
-// X holds A^{-1} b.  LSa, LSb: two staged lines of factor rows (the current
-// one and the next, already solved, one).
-template <int GM, int NR>
-__device__ __forceinline__ void dfn_bwd(const DfnView &g, int64_t f0, double *const (&X)[NR], double *LSa, double *LSb)
-{
-    const int lane = threadIdx.x, G = (int)g.G, SL = dfn_lstride(G);
-    const bool act = lane < G;
-    const int ml = act ? lane : 0;
-    double *cur = LSa, *nxt = LSb;
-    double Lr[GM + 2];
-    dfn_load_row<GM>(g, f0 + (int64_t)(G - 1) * G + ml, Lr);
-    for (int K = G - 1; K >= 0; --K) {
-        const int il = K * G + ml;
-        if (act) {
-#pragma unroll
-            for (int k = 0; k <= GM; ++k)
-                if (k <= G) cur[lane * SL + k] = Lr[k];
-        }
-        const double inv = act ? Lr[0] : 0.0;
-        dfn_load_row<GM>(g, f0 + (K > 0 ? il - G : il), Lr);
-        dfn_wave_sync();
-        double s[NR];
-#pragma unroll
-        for (int r = 0; r < NR; ++r) s[r] = X[r][il] * inv * inv;
-        if (K < G - 1) {
-            // rows (K+1) G + m of the next line couple at distance G + m - lane <= G (m <= lane)
-            double c[2][DFN_U], xv[2][DFN_U][NR];
-            auto fetch = [&](int b, int m0) {
-#pragma unroll
-                for (int u = 0; u < DFN_U; ++u) {
-                    const int m = m0 + u, mc = m < G ? m : G - 1;
-                    const bool on = act && m < G && m <= lane;
-                    c[b][u] = nxt[mc * SL + (on ? G + m - lane : G)] * (on ? 1.0 : 0.0);
-#pragma unroll
-                    for (int r = 0; r < NR; ++r) xv[b][u][r] = X[r][(K + 1) * G + mc];
-                }
-            };
-            fetch(0, 0);
-            for (int m0 = 0; m0 < G; m0 += 2 * DFN_U) {
-                fetch(1, m0 + DFN_U);
-#pragma unroll
-                for (int u = 0; u < DFN_U; ++u)
-#pragma unroll
-                    for (int r = 0; r < NR; ++r) s[r] -= c[0][u] * xv[0][u][r];
-                fetch(0, m0 + 2 * DFN_U);
-#pragma unroll
-                for (int u = 0; u < DFN_U; ++u)
-#pragma unroll
-                    for (int r = 0; r < NR; ++r) s[r] -= c[1][u] * xv[1][u][r];
-            }
-        }
-        // the line's upper triangle (of L^T): row q finishes at step G-1-q
-        double l[2][DFN_U];
-        auto lfetch = [&](int b, int t0) {
-#pragma unroll
-            for (int u = 0; u < DFN_U; ++u) {
-                const int q = G - 1 - (t0 + u), qc = q > 0 ? q : 0, d = q - lane;
-                l[b][u] = cur[qc * SL + (d > 0 ? d : 0)] * ((act && d > 0) ? 1.0 : 0.0);
-            }
-        };
-        lfetch(0, 0);
-        for (int t0 = 0; t0 < G; t0 += 2 * DFN_U) {
-            lfetch(1, t0 + DFN_U);
-#pragma unroll
-            for (int u = 0; u < DFN_U; ++u) dfn_step<NR>(s, l[0][u], (G - 1 - (t0 + u)) & (DFN_WAVE - 1));
-            lfetch(0, t0 + 2 * DFN_U);
-#pragma unroll
-            for (int u = 0; u < DFN_U; ++u)
-                dfn_step<NR>(s, l[1][u], (G - 1 - (t0 + DFN_U + u)) & (DFN_WAVE - 1));
-        }
-        if (act) {
-#pragma unroll
-            for (int r = 0; r < NR; ++r) X[r][il] = s[r];
-        }
-        dfn_wave_sync();
-        double *tt = cur;
-        cur = nxt;
-        nxt = tt;
+    for (int K = 0; K < G; K += 2) {
+        line(K, ca, cb);
+        if (K + 1 < G) line(K + 1, cb, ca);
     }
 }
 
 // One fracture per wavefront (fracture = blockIdx.x):
 //   v = q + C (s.x),  z = a B (s.x)      (q, x, s may be NULL: zero / 1)
-//   t = A^{-1} v,  w = A^{-1} z,  w2 = A^{-1} (G^h t),  d = w - w2
-// and t, d to HBM.  For Algorithm 3 (q = 0) these are the t of its step 4 and
-// the w of step 6 minus the w of step 10; with x = 0 they give the reduced
+//   t = A^{-1} v,  d = A^{-1} (z - G^h t)
+// and t, d to HBM.  Algorithm 3 (q = 0) solves with A three times, for its t,
+// its w and the w of its step 10; d is that w minus the latter, obtained with
+// one solve since A^{-1} is linear.  With x = 0 they give the reduced
 // right-hand side (t = A^{-1} q, d = -A^{-1} G^h A^{-1} q); with x = u they are
-// the recovered h and p.  Dynamic LDS: 2 nf + 2 G dfn_lstride(G) doubles.
-template <int GM>
+// the recovered h and p.  Dynamic LDS: 2 nf doubles.
+template <int GM, bool EX>
 static __global__ __launch_bounds__(DFN_WAVE) void k_dfn_frac(DfnView g, const double *__restrict__ x,
                                                               const double *__restrict__ s,
                                                               const double *__restrict__ q, double *__restrict__ out_t,
@@ -514,9 +434,9 @@ static __global__ __launch_bounds__(DFN_WAVE) void k_dfn_frac(DfnView g, const d
     if (st != nullptr && st->done) return;
     extern __shared__ __align__(16) unsigned char dfn_lds[];
     const int lane = threadIdx.x;
-    const int G = (int)g.G, SL = dfn_lstride(G);
-    const int64_t nf = g.nf, f0 = (int64_t)blockIdx.x * nf;
-    double *X1 = (double *)dfn_lds, *X2 = X1 + nf, *LSa = X2 + nf, *LSb = LSa + (int64_t)G * SL;
+    const int G = EX ? GM : (int)g.G;
+    const int64_t nf = (int64_t)G * G, f0 = (int64_t)blockIdx.x * nf;
+    double *X1 = (double *)dfn_lds, *X2 = X1 + nf;
     for (int64_t il = lane; il < nf; il += DFN_WAVE) {
         const int64_t gi = f0 + il;
         double v = q ? q[gi] : 0.0, z = 0.0;
@@ -533,30 +453,25 @@ static __global__ __launch_bounds__(DFN_WAVE) void k_dfn_frac(DfnView g, const d
         X1[il] = v;
         X2[il] = z;
     }
-    __syncthreads();
-    {
-        double *const XX[2] = {X1, X2};
-        dfn_fwd<GM, 2>(g, f0, XX, LSa);
-        dfn_bwd<GM, 2>(g, f0, XX, LSa, LSb);
-    }
-    for (int64_t il = lane; il < nf; il += DFN_WAVE) {
-        out_t[f0 + il] = X1[il];
-        out_d[f0 + il] = X2[il];
-    }
-    __syncthreads();
+    const double *Qf = g.Qf + f0 * G, *Qb = g.Qb + f0 * G, *di2 = g.di2 + f0;
+    dfn_wave_sync();
+    dfn_sweep<GM, EX, false>(Qf, di2, G, X1);
+    dfn_wave_sync();
+    dfn_sweep<GM, EX, true>(Qb, di2, G, X1);
+    dfn_wave_sync();
     for (int64_t il = lane; il < nf; il += DFN_WAVE) {
         const int64_t gi = f0 + il;
         double v = 0.0;
         for (int64_t e = g.gh.rp[gi]; e < g.gh.rp[gi + 1]; ++e) v += g.gh.val[e] * X1[g.gh.col[e] - f0];
-        X2[il] = v;
+        out_t[gi] = X1[il];
+        X2[il] -= v;
     }
-    __syncthreads();
-    {
-        double *const XX[1] = {X2};
-        dfn_fwd<GM, 1>(g, f0, XX, LSa);
-        dfn_bwd<GM, 1>(g, f0, XX, LSa, LSb);
-    }
-    for (int64_t il = lane; il < nf; il += DFN_WAVE) out_d[f0 + il] = out_d[f0 + il] - X2[il];
+    dfn_wave_sync();
+    dfn_sweep<GM, EX, false>(Qf, di2, G, X2);
+    dfn_wave_sync();
+    dfn_sweep<GM, EX, true>(Qb, di2, G, X2);
+    dfn_wave_sync();
+    for (int64_t il = lane; il < nf; il += DFN_WAVE) out_d[f0 + il] = X2[il];
 }
 
 // Rows of the unknowns:  y = s .* (cg G^u (s.x) + cb (a B^T) t + cc C^T d)

@@ -448,16 +448,25 @@ void launch_frac(pp_op_s *op, const double *x, const double *s, const double *q,
                  const ppk::State *st)
 {
     const ppk::DfnView g = op->dview();
-    const size_t lds = sizeof(double) * (2 * (size_t)g.nf + 2 * (size_t)g.G * ppk::dfn_lstride((int)g.G));
+    const size_t lds = sizeof(double) * 2 * (size_t)g.nf;
     const dim3 grid((unsigned)g.F), blk(ppk::DFN_WAVE);
-    if (g.G <= 16)
-        hipLaunchKernelGGL(ppk::k_dfn_frac<16>, grid, blk, lds, op->stream, g, x, s, q, t, d, st);
-    else if (g.G <= 32)
-        hipLaunchKernelGGL(ppk::k_dfn_frac<32>, grid, blk, lds, op->stream, g, x, s, q, t, d, st);
-    else if (g.G <= 48)
-        hipLaunchKernelGGL(ppk::k_dfn_frac<48>, grid, blk, lds, op->stream, g, x, s, q, t, d, st);
+#define PP_FRAC(GM, EX) hipLaunchKernelGGL((ppk::k_dfn_frac<GM, EX>), grid, blk, lds, op->stream, g, x, s, q, t, d, st)
+    switch (g.G) {
+    case 16: PP_FRAC(16, true); return;
+    case 32: PP_FRAC(32, true); return;
+    case 48: PP_FRAC(48, true); return;
+    case 64: PP_FRAC(64, true); return;
+    default: break;
+    }
+    if (g.G < 16)
+        PP_FRAC(16, false);
+    else if (g.G < 32)
+        PP_FRAC(32, false);
+    else if (g.G < 48)
+        PP_FRAC(48, false);
     else
-        hipLaunchKernelGGL(ppk::k_dfn_frac<64>, grid, blk, lds, op->stream, g, x, s, q, t, d, st);
+        PP_FRAC(64, false);
+#undef PP_FRAC
 }
 
 // y = D^{-1/2} S_u D^{-1/2} x by Algorithm 3 (DFN): one wavefront per fracture
@@ -1069,6 +1078,17 @@ pp_status dfn_build(pp_op_s *op, const pp_dfn_desc &d)
         op->dfn_F = F;
         op->dfn_G = G;
         op->dfn_nh = nh;
+        // the factor by sweep steps for the application
+        {
+            const size_t qn = (size_t)nh * G + ppk::DFN_WAVE;
+            op->dfn_Q = dalloc<double>(2 * qn + nh);
+            HIPCHK(hipMemsetAsync(op->dfn_Q, 0, sizeof(double) * (2 * qn + nh), op->stream));
+            const ppk::DfnView gq = op->dview();
+            hipLaunchKernelGGL(ppk::k_dfn_qcoef, dim3(op->grid_elems(nh * G)), dim3(BLOCK), 0, op->stream, nh, nf,
+                               (int)G, (const double *)op->dfn_Lb, const_cast<double *>(gq.Qf),
+                               const_cast<double *>(gq.Qb), const_cast<double *>(gq.di2));
+            HIPCHK(hipGetLastError());
+        }
         // owners of the unknowns, and Algorithm 4 in workgroups of 64 unknowns of one fracture
         std::vector<int32_t> own((size_t)nu);
         std::vector<int32_t> wf;

@@ -6,8 +6,9 @@ side and the recovery of h, p to 1e-11 (FP64; the factor and the solves sum
 in a different order than the oracle); p_k(S-hat) r with D_S from Algorithm 4
 to 1e-10; the whole pipeline (rhs, PCG to 1e-8, recovery) to iteration counts
 within 2 and, at equal iteration counts, solutions to 1e-8.  Shapes: odd and
-even grids, the largest grid (64: LDS of the fracture kernel at its maximum),
-more than 64 unknowns per fracture (two workgroups of Algorithm 4), alpha != 1.
+even grids, the grids whose sweeps are compiled for their exact width (16,
+32, 48, 64) and others, the largest grid (64), more than 64 unknowns per
+fracture (two workgroups of Algorithm 4), alpha != 1.
 """
 import numpy as np
 import pytest
@@ -44,7 +45,14 @@ CASES = {
     "f4g11_odd": dict(n_frac=4, G=11, n_traces=7, L_lo=4, L_hi=11, seed=5),
     "f3g64_max": dict(n_frac=3, G=64, n_traces=4, L_lo=20, L_hi=64, seed=6),
     "f2g30_many_u": dict(n_frac=2, G=30, n_traces=6, L_lo=20, L_hi=30, seed=8),  # > 64 unknowns per fracture
+    # grids with a sweep compiled for exactly their width, and one just below
+    "f3g16": dict(n_frac=3, G=16, n_traces=5, L_lo=4, L_hi=16, seed=11),
+    "f2g32": dict(n_frac=2, G=32, n_traces=4, L_lo=8, L_hi=32, seed=12),
+    "f2g48": dict(n_frac=2, G=48, n_traces=4, L_lo=10, L_hi=40, seed=10),
+    "f2g47_odd": dict(n_frac=2, G=47, n_traces=4, L_lo=10, L_hi=40, seed=13),
 }
+
+CLUSTERED_MIN = {"f2g48"}
 
 _cache = {}
 
@@ -84,7 +92,7 @@ def test_apply_rhs_recover(B, name):
     op.close()
 
 
-@pytest.mark.parametrize("name", ["f6g8", "f4g11_odd", "f3g64_max", "f2g30_many_u"])
+@pytest.mark.parametrize("name", ["f6g8", "f4g11_odd", "f3g64_max", "f2g30_many_u", "f2g48"])
 @pytest.mark.parametrize("k,xi", [(1, 0.0), (6, 1e-3), (15, 1e-2)])
 def test_polynomial_apply(B, name, k, xi):
     """pp_apply = D^{-1/2} p_k(S-hat) D^{-1/2} r with D_S from Algorithm 4."""
@@ -99,7 +107,7 @@ def test_polynomial_apply(B, name, k, xi):
     op.close()
 
 
-@pytest.mark.parametrize("name", ["f6g8", "f9g5_alpha0.5", "f3g64_max"])
+@pytest.mark.parametrize("name", ["f6g8", "f9g5_alpha0.5", "f3g64_max", "f2g48"])
 def test_pipeline_pcg(B, name):
     """rhs -> PCG on S-hat -> recovery, against the oracle's pipeline; the
     recovered (h, u, p) satisfy the three block equations of eq. (sys)."""
@@ -108,7 +116,17 @@ def test_pipeline_pcg(B, name):
     q = W.rhs_uniform(P.n_h, 1)
     lo, hi = B.pp_estimate_bounds(op.handle, 20)
     lmin, lmax = O.lanczos_bounds(orj, 20)
-    assert abs(lo - lmin) <= 1e-6 * lmax and abs(hi - lmax) <= 1e-6 * lmax
+    if name in CLUSTERED_MIN:
+        # The smallest eigenvalues of S-hat are clustered (0.0555, 0.0563,
+        # 0.0633 for f2g48): the 20-step Ritz value moves in its third digit
+        # when the operator is perturbed by 1e-15, so the two Lanczos runs
+        # agree only roughly; both must stay above lambda_min (interlacing).
+        S = np.column_stack([orj.apply(e) for e in np.eye(P.n_u)])
+        ev = np.linalg.eigvalsh((S + S.T) / 2)
+        assert ev[0] - 1e-9 * ev[-1] <= lo and abs(lo - lmin) <= 0.05 * lmin
+        assert abs(hi - lmax) <= 1e-6 * lmax
+    else:
+        assert abs(lo - lmin) <= 1e-6 * lmax and abs(hi - lmax) <= 1e-6 * lmax
     k, xi = 8, 1e-3
     B.pp_setup(op.handle, k, lmin, lmax, xi)
     r = torch.empty(P.n_u, dtype=torch.float64, device="cuda")
