@@ -37,6 +37,9 @@ struct DfnView {
     const double *Lb;       // band factor by rows, nh x dfn_stride(G) (+ DFN_GMAX + 2 padding)
     const double *Qf, *Qb;  // the factor by sweep steps, nh x G each (+ DFN_WAVE padding)
     const double *di2;      // 1 / L(i, i)^2, nh
+    const int32_t *ghc;     // G^h by entry slots: entry j of row i at j nh + i (W = ghw slots,
+    const double *ghv;      // padded with column i and value 0); ghw = 0: use the CSR gh
+    int ghw;
     CsrD c, b, gh;          // rows of the fracture cells (b holds a B)
     CsrD ct, bt, gu;        // rows of the unknowns (bt holds a B^T)
 };
@@ -417,28 +420,15 @@ __device__ __forceinline__ void dfn_sweep(const double *__restrict__ Q, const do
     }
 }
 
-// One fracture per wavefront (fracture = blockIdx.x):
+// The fracture kernel's right-hand sides, one thread per cell (all fractures):
 //   v = q + C (s.x),  z = a B (s.x)      (q, x, s may be NULL: zero / 1)
-//   t = A^{-1} v,  d = A^{-1} (z - G^h t)
-// and t, d to HBM.  Algorithm 3 (q = 0) solves with A three times, for its t,
-// its w and the w of its step 10; d is that w minus the latter, obtained with
-// one solve since A^{-1} is linear.  With x = 0 they give the reduced
-// right-hand side (t = A^{-1} q, d = -A^{-1} G^h A^{-1} q); with x = u they are
-// the recovered h and p.  Dynamic LDS: 2 nf doubles.
-template <int GM, bool EX>
-static __global__ __launch_bounds__(DFN_WAVE) void k_dfn_frac(DfnView g, const double *__restrict__ x,
-                                                              const double *__restrict__ s,
-                                                              const double *__restrict__ q, double *__restrict__ out_t,
-                                                              double *__restrict__ out_d, const State *st)
+static __global__ __launch_bounds__(BLOCK) void k_dfn_cb(DfnView g, const double *__restrict__ x,
+                                                         const double *__restrict__ s, const double *__restrict__ q,
+                                                         double *__restrict__ vo, double *__restrict__ zo,
+                                                         const State *st)
 {
     if (st != nullptr && st->done) return;
-    extern __shared__ __align__(16) unsigned char dfn_lds[];
-    const int lane = threadIdx.x;
-    const int G = EX ? GM : (int)g.G;
-    const int64_t nf = (int64_t)G * G, f0 = (int64_t)blockIdx.x * nf;
-    double *X1 = (double *)dfn_lds, *X2 = X1 + nf;
-    for (int64_t il = lane; il < nf; il += DFN_WAVE) {
-        const int64_t gi = f0 + il;
+    for (int64_t gi = (int64_t)blockIdx.x * BLOCK + threadIdx.x; gi < g.nh; gi += (int64_t)gridDim.x * BLOCK) {
         double v = q ? q[gi] : 0.0, z = 0.0;
         if (x) {
             for (int64_t e = g.c.rp[gi]; e < g.c.rp[gi + 1]; ++e) {
@@ -450,8 +440,58 @@ static __global__ __launch_bounds__(DFN_WAVE) void k_dfn_frac(DfnView g, const d
                 z += g.b.val[e] * (s ? s[c] * x[c] : x[c]);
             }
         }
-        X1[il] = v;
-        X2[il] = z;
+        vo[gi] = v;
+        zo[gi] = z;
+    }
+}
+
+// G^h entry-slot layout from its CSR rows (one thread per row).
+static __global__ __launch_bounds__(BLOCK) void k_dfn_ghell(int64_t nh, CsrD gh, int W, int32_t *__restrict__ ghc,
+                                                            double *__restrict__ ghv)
+{
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < nh; i += (int64_t)gridDim.x * BLOCK) {
+        const int64_t b = gh.rp[i], n = gh.rp[i + 1] - b;
+        for (int j = 0; j < W; ++j) {
+            ghc[j * nh + i] = j < n ? gh.col[b + j] : (int32_t)i;
+            ghv[j * nh + i] = j < n ? gh.val[b + j] : 0.0;
+        }
+    }
+}
+
+// The longest row of a CSR matrix (atomicMax into *w).
+static __global__ __launch_bounds__(BLOCK) void k_dfn_maxrow(int64_t n, const int64_t *__restrict__ rp, int *w)
+{
+    int m = 0;
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK)
+        m = max(m, (int)min<int64_t>(rp[i + 1] - rp[i], 1 << 30));
+    if (m > 0) atomicMax(w, m);
+}
+
+constexpr int DFN_ELL_MAX = 16;  // widest G^h row kept in the entry-slot layout
+constexpr int DFN_GH_ROWS = 24;  // rows per lane whose G^h loads are in flight together
+
+// One fracture per wavefront (fracture = blockIdx.x), after k_dfn_cb wrote v
+// to t and z to d:
+//   t = A^{-1} v,  d = A^{-1} (z - G^h t)
+// in place.  Algorithm 3 (q = 0) solves with A three times, for its t, its w
+// and the w of its step 10; d is that w minus the latter, obtained with one
+// solve since A^{-1} is linear.  With x = 0 they give the reduced right-hand
+// side (t = A^{-1} q, d = -A^{-1} G^h A^{-1} q); with x = u they are the
+// recovered h and p.  Dynamic LDS: 2 nf doubles.
+template <int GM, bool EX>
+static __global__ __launch_bounds__(DFN_WAVE) void k_dfn_frac(DfnView g, double *__restrict__ io_t,
+                                                              double *__restrict__ io_d, const State *st)
+{
+    if (st != nullptr && st->done) return;
+    extern __shared__ __align__(16) unsigned char dfn_lds[];
+    const int lane = threadIdx.x;
+    const int G = EX ? GM : (int)g.G;
+    const int64_t nf = (int64_t)G * G, f0 = (int64_t)blockIdx.x * nf;
+    double *X1 = (double *)dfn_lds, *X2 = X1 + nf;
+#pragma unroll 6
+    for (int64_t il = lane; il < nf; il += DFN_WAVE) {
+        X1[il] = io_t[f0 + il];
+        X2[il] = io_d[f0 + il];
     }
     const double *Qf = g.Qf + f0 * G, *Qb = g.Qb + f0 * G, *di2 = g.di2 + f0;
     dfn_wave_sync();
@@ -459,19 +499,46 @@ static __global__ __launch_bounds__(DFN_WAVE) void k_dfn_frac(DfnView g, const d
     dfn_wave_sync();
     dfn_sweep<GM, EX, true>(Qb, di2, G, X1);
     dfn_wave_sync();
-    for (int64_t il = lane; il < nf; il += DFN_WAVE) {
-        const int64_t gi = f0 + il;
-        double v = 0.0;
-        for (int64_t e = g.gh.rp[gi]; e < g.gh.rp[gi + 1]; ++e) v += g.gh.val[e] * X1[g.gh.col[e] - f0];
-        out_t[gi] = X1[il];
-        X2[il] -= v;
+    if (g.ghw > 0) {
+        // z - G^h t: the loads of DFN_GH_ROWS rows per lane go out together, slot by slot
+        const int64_t nh = g.nh;
+        for (int64_t b0 = lane; b0 < nf; b0 += (int64_t)DFN_GH_ROWS * DFN_WAVE) {
+            double v[DFN_GH_ROWS];
+#pragma unroll
+            for (int m = 0; m < DFN_GH_ROWS; ++m) v[m] = 0.0;
+            for (int j = 0; j < g.ghw; ++j) {
+                const int32_t *cj = g.ghc + j * nh + f0;
+                const double *vj = g.ghv + j * nh + f0;
+#pragma unroll
+                for (int m = 0; m < DFN_GH_ROWS; ++m) {
+                    const int64_t il = b0 + (int64_t)m * DFN_WAVE;
+                    if (il < nf) v[m] += vj[il] * X1[cj[il] - f0];
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < DFN_GH_ROWS; ++m) {
+                const int64_t il = b0 + (int64_t)m * DFN_WAVE;
+                if (il < nf) {
+                    io_t[f0 + il] = X1[il];
+                    X2[il] -= v[m];
+                }
+            }
+        }
+    } else {
+        for (int64_t il = lane; il < nf; il += DFN_WAVE) {
+            const int64_t gi = f0 + il;
+            double v = 0.0;
+            for (int64_t e = g.gh.rp[gi]; e < g.gh.rp[gi + 1]; ++e) v += g.gh.val[e] * X1[g.gh.col[e] - f0];
+            io_t[gi] = X1[il];
+            X2[il] -= v;
+        }
     }
     dfn_wave_sync();
     dfn_sweep<GM, EX, false>(Qf, di2, G, X2);
     dfn_wave_sync();
     dfn_sweep<GM, EX, true>(Qb, di2, G, X2);
     dfn_wave_sync();
-    for (int64_t il = lane; il < nf; il += DFN_WAVE) out_d[f0 + il] = X2[il];
+    for (int64_t il = lane; il < nf; il += DFN_WAVE) io_d[f0 + il] = X2[il];
 }
 
 // Rows of the unknowns:  y = s .* (cg G^u (s.x) + cb (a B^T) t + cc C^T d)

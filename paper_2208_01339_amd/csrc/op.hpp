@@ -42,6 +42,9 @@ struct pp_op_s {
     int64_t dfn_F = 0, dfn_G = 0, dfn_nh = 0;
     double *dfn_Lb = nullptr;
     double *dfn_Q = nullptr;  // Qf, Qb (nh G + DFN_WAVE each), di2 (nh)
+    int32_t *dfn_ghc = nullptr;  // G^h by entry slots (dfn_ghw > 0)
+    double *dfn_ghv = nullptr;
+    int dfn_ghw = 0;
     int64_t *dfn_rp[6] = {};
     int32_t *dfn_col[6] = {};
     double *dfn_val[6] = {};
@@ -115,6 +118,9 @@ struct pp_op_s {
         v.Qf = dfn_Q;
         v.Qb = dfn_Q ? dfn_Q + qn : nullptr;
         v.di2 = dfn_Q ? dfn_Q + 2 * qn : nullptr;
+        v.ghc = dfn_ghc;
+        v.ghv = dfn_ghv;
+        v.ghw = dfn_ghw;
         ppk::CsrD *m[6] = {&v.c, &v.b, &v.gh, &v.ct, &v.bt, &v.gu};
         for (int i = 0; i < 6; ++i) {
             m[i]->rp = dfn_rp[i];
@@ -167,7 +173,7 @@ struct pp_op_s {
         ppc::dfree(dval); ppc::dfree(dval32);
         ppc::dfree(crp); ppc::dfree(ccol); ppc::dfree(cm); ppc::dfree(cm32); ppc::dfree(tw); ppc::dfree(tw32);
         ppc::dfree(dis);
-        ppc::dfree(dfn_Lb); ppc::dfree(dfn_Q); ppc::dfree(dfn_t); ppc::dfree(dfn_d);
+        ppc::dfree(dfn_Lb); ppc::dfree(dfn_Q); ppc::dfree(dfn_ghc); ppc::dfree(dfn_ghv); ppc::dfree(dfn_t); ppc::dfree(dfn_d);
         for (int i = 0; i < 6; ++i) { ppc::dfree(dfn_rp[i]); ppc::dfree(dfn_col[i]); ppc::dfree(dfn_val[i]); }
         ppc::dfree(xh); ppc::dfree(r); ppc::dfree(p); ppc::dfree(q); ppc::dfree(z); ppc::dfree(bh); ppc::dfree(sA); ppc::dfree(sB);
         ppc::dfree(r32); ppc::dfree(sA32); ppc::dfree(sB32);

@@ -448,9 +448,10 @@ void launch_frac(pp_op_s *op, const double *x, const double *s, const double *q,
                  const ppk::State *st)
 {
     const ppk::DfnView g = op->dview();
+    hipLaunchKernelGGL(ppk::k_dfn_cb, dim3(op->grid_elems(g.nh)), dim3(BLOCK), 0, op->stream, g, x, s, q, t, d, st);
     const size_t lds = sizeof(double) * 2 * (size_t)g.nf;
     const dim3 grid((unsigned)g.F), blk(ppk::DFN_WAVE);
-#define PP_FRAC(GM, EX) hipLaunchKernelGGL((ppk::k_dfn_frac<GM, EX>), grid, blk, lds, op->stream, g, x, s, q, t, d, st)
+#define PP_FRAC(GM, EX) hipLaunchKernelGGL((ppk::k_dfn_frac<GM, EX>), grid, blk, lds, op->stream, g, t, d, st)
     switch (g.G) {
     case 16: PP_FRAC(16, true); return;
     case 32: PP_FRAC(32, true); return;
@@ -1078,6 +1079,23 @@ pp_status dfn_build(pp_op_s *op, const pp_dfn_desc &d)
         op->dfn_F = F;
         op->dfn_G = G;
         op->dfn_nh = nh;
+        // G^h by entry slots when its rows are short
+        {
+            HIPCHK(hipMemsetAsync(flag_d, 0, sizeof(int), op->stream));
+            hipLaunchKernelGGL(ppk::k_dfn_maxrow, dim3(gh_), dim3(BLOCK), 0, op->stream, nh,
+                               (const int64_t *)op->dfn_rp[2], flag_d);
+            HIPCHK(hipGetLastError());
+            const int W = read_flag(op, flag_d);
+            if (W > 0 && W <= ppk::DFN_ELL_MAX) {
+                op->dfn_ghc = dalloc<int32_t>((size_t)W * nh);
+                op->dfn_ghv = dalloc<double>((size_t)W * nh);
+                hipLaunchKernelGGL(ppk::k_dfn_ghell, dim3(gh_), dim3(BLOCK), 0, op->stream, nh,
+                                   ppk::CsrD{op->dfn_rp[2], op->dfn_col[2], op->dfn_val[2]}, W, op->dfn_ghc,
+                                   op->dfn_ghv);
+                HIPCHK(hipGetLastError());
+                op->dfn_ghw = W;
+            }
+        }
         // the factor by sweep steps for the application
         {
             const size_t qn = (size_t)nh * G + ppk::DFN_WAVE;
