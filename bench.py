@@ -223,9 +223,9 @@ def run_dfn_su(args, B, W, torch, dev):
         log("dfn S_u k=31 rank-one correction: %d iters, %d S_u applications, %d dots"
             % (it, st["op_applies"], st["dots"]))
         B.pp_lowrank_set(h, 0)
-    # stored factor bytes per application: three solves in two paired sweeps (fwd + bwd each)
-    sp = (P.grid + 2) & ~1
-    fbytes = 4 * P.n_h * sp * 8
+    # factor bytes per application: two solves, each a forward and a backward sweep over the
+    # step-ordered coefficients (G doubles per row) plus 1/L(i,i)^2 in the forward sweep
+    fbytes = 4 * P.n_h * P.grid * 8 + 2 * P.n_h * 8
     out = dict(workload="dfn_su_400x48x48_1100traces_alpha1", n_h=P.n_h, n_u=P.n_u, n_frac=P.n_frac, grid=P.grid,
                nnz=dict(a=P.a.nnz, gh=P.gh.nnz, c=P.c.nnz, b=P.b.nnz, gu=P.gu.nnz), xi=xi,
                bounds=[lmin, lmax], gen_s=t_gen, create_s=t_create, bounds_s=t_bounds, per_k=rows,

@@ -145,8 +145,9 @@ typedef struct {
  * factorisation step), and D_S = diag(S_u) by Algorithm 4; the operator seen
  * by pp_setup / pp_apply / pcg_solve / pp_estimate_bounds is
  * D_S^{-1/2} S_u D_S^{-1/2} (section 4.2), applied matrix-free by Algorithm 3
- * (three solves with the factor, each a forward and a backward sweep, and
- * the products with C, B, G^h, G^u).  The input arrays are copied; the
+ * (its three solves with A done as two, since A^{-1} is linear, each a
+ * forward and a backward sweep with the factor, and the products with C, B,
+ * G^h, G^u).  The input arrays are copied; the
  * caller keeps ownership.  flags: 0 (Jacobi scaling by D_S is implied;
  * PP_MIXED and PP_SLICED are refused).  PP_ERR_ARG for an invalid structure
  * (entry outside its fracture block or band, a C column outside its owner,

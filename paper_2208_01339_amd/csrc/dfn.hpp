@@ -46,9 +46,6 @@ struct DfnView {
 
 // row stride of the factor in HBM (even, >= G + 1: rows load as 16-byte vectors)
 __host__ __device__ constexpr int dfn_stride(int G) { return (G + 2) & ~1; }
-// row stride of a staged line in LDS (odd, >= G + 1: lanes reading their own
-// rows hit distinct banks)
-__host__ __device__ constexpr int dfn_lstride(int G) { return (G + 1) | 1; }
 
 __device__ __forceinline__ double dfn_rdlane(double v, int l)
 {

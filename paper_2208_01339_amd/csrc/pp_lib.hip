@@ -470,8 +470,8 @@ void launch_frac(pp_op_s *op, const double *x, const double *s, const double *q,
 #undef PP_FRAC
 }
 
-// y = D^{-1/2} S_u D^{-1/2} x by Algorithm 3 (DFN): one wavefront per fracture
-// for the three solves with the factor, then the rows of the unknowns.
+// y = D^{-1/2} S_u D^{-1/2} x by Algorithm 3 (DFN): the fracture kernels
+// (its three solves with A as two), then the rows of the unknowns.
 // live_state: skip once the solve is done.
 void enqueue_su(pp_op_s *op, const double *x, double *y, bool live_state)
 {
