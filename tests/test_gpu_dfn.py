@@ -255,3 +255,37 @@ def test_degenerate_shapes(B, shape):
     theta = (0.5 + 2.0) / 2
     assert rel(host(z), x / orc.diag_raw() / theta) <= 1e-12
     op.close()
+
+
+def test_gh_wide_rows(B):
+    """G^h with rows longer than the entry-slot layout holds (17 entries: the
+    whole band of a G = 8 grid), so the fracture kernel reads G^h by CSR rows."""
+    import scipy.sparse as sp
+
+    P = W.dfn_su(n_frac=4, G=8, n_traces=6, L_lo=2, L_hi=8, seed=4)
+    gh = P.gh.to_scipy().tolil()
+    lo, m = 20, 17  # a principal block of fracture 0 inside its band: SPD, so G^h stays SPSD
+    for i in range(m):
+        for j in range(m):
+            d = abs(i - j)
+            if d <= P.grid:
+                gh[lo + i, lo + j] += 1e-2 * (3.0 if d == 0 else 0.5 ** d)
+    Q = _bad(P, gh=_csr(gh))
+    assert np.diff(Q.gh.rowptr).max() > 16
+    orc = O.DfnOperator(Q, jacobi=False)
+    op = B.Operator(dfn=Q)
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal(Q.n_u)
+    y = torch.empty(Q.n_u, dtype=torch.float64, device="cuda")
+    B.pp_operator_apply(op.handle, dev(x), y)
+    assert rel(host(y), orc.apply(x)) <= 1e-11
+    q = W.rhs_uniform(Q.n_h, 2)
+    r = torch.empty(Q.n_u, dtype=torch.float64, device="cuda")
+    B.pp_dfn_rhs(op.handle, dev(q), r)
+    assert rel(host(r), orc.rhs(q)) <= 1e-11
+    h = torch.empty(Q.n_h, dtype=torch.float64, device="cuda")
+    p = torch.empty_like(h)
+    B.pp_dfn_recover(op.handle, dev(q), dev(x), h, p)
+    h0, p0 = orc.recover(q, x)
+    assert rel(host(h), h0) <= 1e-11 and rel(host(p), p0) <= 1e-11
+    op.close()
