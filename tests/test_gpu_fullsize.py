@@ -2,6 +2,7 @@
 
 * 7-point heterogeneous diffusion, 256^3 (n = 16.8M), Jacobi on.
 * DFN-shaped Schur operator, 2000 fractures of 64 x 64 cells (n = 8.19M), Jacobi on.
+* The DFN Schur complement S_u, 400 fractures of 48 x 48 cells (n_u = 55,132).
 
 Where the oracle finishes in seconds the whole output vector is compared;
 for degree 120 the oracle is run on the principal submatrix of the graph
@@ -224,3 +225,47 @@ def test_dfn_pcg_properties(B, dfn, dfn_ops):
     assert st == B.PP_OK and rel <= 1e-8
     res = (orc.apply_raw(host(x)) - b) * orc.dis
     assert np.linalg.norm(res) / np.linalg.norm(b * orc.dis) <= 2e-8
+
+
+def test_dfn_su_bench_size(B):
+    """The DFN Schur complement S_u at the size bench.py times (400 fractures
+    of 48 x 48 cells, n_h = 921,600, n_u = 55,132), whole vectors: apply,
+    reduced right-hand side and recovery (oracle: a few seconds); D_S from
+    Algorithm 4 on sampled unknowns, read back through pp_apply at k = 0
+    (z = r / (theta D_S)) and compared with (S_u e_j)_j.  The polynomial is
+    checked on the small shapes of test_gpu_dfn.py: the oracle's Algorithm 4
+    for every unknown at this size takes about 11 minutes on one core."""
+    P = W.dfn_su()
+    orc = O.DfnOperator(P, jacobi=False)
+    op = B.Operator(dfn=P)
+    try:
+        rng = np.random.default_rng(1)
+        x = rng.standard_normal(P.n_u)
+        y = torch.empty(P.n_u, dtype=torch.float64, device="cuda")
+        B.pp_operator_apply(op.handle, dev(x), y)
+        ref = orc.apply(x)
+        assert np.linalg.norm(host(y) - ref) <= 1e-11 * np.linalg.norm(ref)
+        q = W.rhs_uniform(P.n_h, 2)
+        r = torch.empty(P.n_u, dtype=torch.float64, device="cuda")
+        B.pp_dfn_rhs(op.handle, dev(q), r)
+        ref = orc.rhs(q)
+        assert np.linalg.norm(host(r) - ref) <= 1e-11 * np.linalg.norm(ref)
+        h = torch.empty(P.n_h, dtype=torch.float64, device="cuda")
+        p = torch.empty_like(h)
+        B.pp_dfn_recover(op.handle, dev(q), dev(x), h, p)
+        h0, p0 = orc.recover(q, x)
+        assert np.linalg.norm(host(h) - h0) <= 1e-11 * np.linalg.norm(h0)
+        assert np.linalg.norm(host(p) - p0) <= 1e-11 * np.linalg.norm(p0)
+        # k = 0 with lambda in [1, 3], xi = 0: theta = 2 and z = r / (2 D_S)
+        B.pp_setup(op.handle, 0, 1.0, 3.0, 0.0)
+        ones = torch.ones(P.n_u, dtype=torch.float64, device="cuda")
+        z = torch.empty_like(ones)
+        B.pp_apply(op.handle, ones, z)
+        ds = 1.0 / (2.0 * host(z))
+        for j in [0, 1, 17, P.n_u // 3, P.n_u // 2, P.n_u - 2, P.n_u - 1]:
+            e = np.zeros(P.n_u)
+            e[j] = 1.0
+            dj = orc.apply(e)[j]
+            assert abs(ds[j] - dj) <= 1e-11 * abs(dj), (j, ds[j], dj)
+    finally:
+        op.close()
