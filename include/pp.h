@@ -170,7 +170,9 @@ PP_API pp_status pp_dfn_rhs(pp_op op, const double *q, double *r);
 /*
  * Recovery of the other unknowns once S_u u = r is solved (section 4.1):
  *   h = A^{-1} (q + C u),  p = A^{-1} (alpha B u - G^h h).
- *   q [n_h], u [n_u], h [n_h] and p [n_h] device.  Synchronised.
+ *   q [n_h], u [n_u], h [n_h] and p [n_h] device.  h and p must be distinct
+ *   arrays; either may be q itself (q is read before it is overwritten).
+ *   Synchronised.
  */
 PP_API pp_status pp_dfn_recover(pp_op op, const double *q, const double *u, double *h, double *p);
 

@@ -289,3 +289,20 @@ def test_gh_wide_rows(B):
     h0, p0 = orc.recover(q, x)
     assert rel(host(h), h0) <= 1e-11 and rel(host(p), p0) <= 1e-11
     op.close()
+
+
+def test_recover_into_q(B):
+    """pp_dfn_recover with h (or p) written over q itself."""
+    P, orc, _ = case("f6g8")
+    op = B.Operator(dfn=P)
+    rng = np.random.default_rng(6)
+    q = W.rhs_uniform(P.n_h, 4)
+    u = rng.standard_normal(P.n_u)
+    h0, p0 = orc.recover(q, u)
+    for into in ("h", "p"):
+        qd = dev(q)
+        other = torch.empty_like(qd)
+        h, p = (qd, other) if into == "h" else (other, qd)
+        B.pp_dfn_recover(op.handle, qd, dev(u), h, p)
+        assert rel(host(h), h0) <= 1e-11 and rel(host(p), p0) <= 1e-11, into
+    op.close()
