@@ -148,9 +148,9 @@ typedef struct {
  * (its three solves with A done as two, since A^{-1} is linear, each a
  * forward and a backward sweep with the factor, and the products with C, B,
  * G^h, G^u).  The input arrays are copied; the
- * caller keeps ownership.  Device memory held: the banded factor (n_h (G+2)
- * doubles), two step-ordered copies of it for the sweeps (2 n_h G doubles)
- * and copies of the blocks.  flags: 0 (Jacobi scaling by D_S is implied;
+ * caller keeps ownership.  Device memory held: two step-ordered copies of
+ * the banded factor for the sweeps (2 n_h G doubles) and copies of the
+ * blocks; the factor by rows (n_h (G+2) doubles) is freed within the call.  flags: 0 (Jacobi scaling by D_S is implied;
  * PP_MIXED and PP_SLICED are refused).  PP_ERR_ARG for an invalid structure
  * (entry outside its fracture block or band, a C column outside its owner,
  * asymmetric A, G^h or G^u, A not SPD, a non-positive D_S).

@@ -34,7 +34,7 @@ struct CsrD {
 
 struct DfnView {
     int64_t F, G, nf, nh, nu;
-    const double *Lb;       // band factor by rows, nh x dfn_stride(G) (+ DFN_GMAX + 2 padding)
+    const double *Lb;       // band factor by rows, nh x dfn_stride(G) (+ DFN_GMAX + 2 padding); create only
     const double *Qf, *Qb;  // the factor by sweep steps, nh x G each (+ DFN_WAVE padding)
     const double *di2;      // 1 / L(i, i)^2, nh
     const int32_t *ghc;     // G^h by entry slots: entry j of row i at j nh + i (W = ghw slots,

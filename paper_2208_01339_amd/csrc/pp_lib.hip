@@ -1144,6 +1144,9 @@ pp_status dfn_build(pp_op_s *op, const pp_dfn_desc &d)
             HIPCHK(hipGetLastError());
         }
         if (read_flag(op, flag_d) & 16) { cleanup(); return fail(PP_ERR_ARG, "diag(S_u) has a non-positive entry"); }
+        // the factor by rows served the step-ordered copies and Algorithm 4 (both done: read_flag synchronised)
+        ppc::dfree(op->dfn_Lb);
+        op->dfn_Lb = nullptr;
         // the operator seen by the fused kernels: one unit entry per row, column n + i
         op->nslices = (nu + WAVE - 1) / WAVE;
         op->nstored = op->nslices * WAVE;
