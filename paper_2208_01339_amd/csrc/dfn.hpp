@@ -368,11 +368,10 @@ __device__ __forceinline__ void dfn_wave_sync()
 //   forward  (REV = false): X = D^{-2} L~^{-1} X   (di2: the block's 1/L(i,i)^2)
 //   backward (REV = true):  X = L~^{-T} X
 // so forward then backward gives A^{-1} X (A = L~ D^2 L~^T).  Q: the block's
-// Qf or Qb.  A line of G steps is unrolled (GM >= G; EX: GM == G) with the
+// Qf or Qb.  A line of GM steps is unrolled (GM >= G; EX: GM == G) with the
 // lane's coefficients in registers, two buffers used by alternate lines: the
-// next line's G loads are in flight while this line runs.  Lanes G..63 hold
-// no row: they load lane 0's coefficients and their values are never
-// broadcast or stored.
+// next line's loads are in flight while this line runs.  Lanes G..63 hold no
+// row and their values are never stored.
 template <int GM, bool EX, bool REV>
 __device__ __forceinline__ void dfn_sweep(const double *__restrict__ Q, const double *__restrict__ di2, int G,
                                           double *X)
@@ -385,6 +384,15 @@ __device__ __forceinline__ void dfn_sweep(const double *__restrict__ Q, const do
         const int64_t p = (int64_t)K * G + lane;
         return REV ? nf - 1 - p : p;
     };
+    // coefficient q of the line starting at step nl.  Narrower blocks (not EX)
+    // run all GM steps of a line: steps q >= G get coefficient 0 on every lane
+    // and lanes >= G get 0 on every step, so those lanes stay 0 and those steps
+    // change nothing (the loops stay fully unrolled, the buffers in registers).
+    auto coef = [&](int64_t nl, int q) -> double {
+        if (EX) return qp[(nl + q) * G];
+        const double c = qp[(nl + (q < G ? q : 0)) * G];
+        return (q < G && act) ? c : 0.0;
+    };
     double ca[GM], cb[GM];
     double acc = act ? X[row(0)] : 0.0, fin = 0.0;
     // line K with coefficients cur; the next line's (the last line: its own again) into nxt
@@ -392,13 +400,9 @@ __device__ __forceinline__ void dfn_sweep(const double *__restrict__ Q, const do
         const int64_t nl = (int64_t)(K + 1 < G ? K + 1 : K) * G;
         const double sc = (!REV && act) ? di2[row(K)] : 1.0;
 #pragma unroll
-        for (int q = 0; q < GM; ++q) {
-            if (!EX && q >= G) break;
-            nxt[q] = qp[(nl + q) * G];
-        }
+        for (int q = 0; q < GM; ++q) nxt[q] = coef(nl, q);
 #pragma unroll
         for (int q = 0; q < GM; ++q) {
-            if (!EX && q >= G) break;
             const double v = dfn_rdlane(acc, q);
             fin = dfn_wrlane(v, fin, q);
             acc -= cur[q] * v;
@@ -407,10 +411,7 @@ __device__ __forceinline__ void dfn_sweep(const double *__restrict__ Q, const do
         if (K + 1 < G && act) acc += X[row(K + 1)];
     };
 #pragma unroll
-    for (int q = 0; q < GM; ++q) {
-        if (!EX && q >= G) break;
-        ca[q] = qp[(int64_t)q * G];
-    }
+    for (int q = 0; q < GM; ++q) ca[q] = coef(0, q);
     for (int K = 0; K < G; K += 2) {
         line(K, ca, cb);
         if (K + 1 < G) line(K + 1, cb, ca);
