@@ -466,7 +466,7 @@ static __global__ __launch_bounds__(BLOCK) void k_dfn_maxrow(int64_t n, const in
 }
 
 constexpr int DFN_ELL_MAX = 16;  // widest G^h row kept in the entry-slot layout
-constexpr int DFN_GH_ROWS = 24;  // rows per lane whose G^h loads are in flight together
+constexpr int DFN_GH_ROWS = 36;  // rows per lane whose G^h loads are in flight together
 
 // One fracture per wavefront (fracture = blockIdx.x), after k_dfn_cb wrote v
 // to t and z to d:
@@ -486,7 +486,7 @@ static __global__ __launch_bounds__(DFN_WAVE) void k_dfn_frac(DfnView g, double 
     const int G = EX ? GM : (int)g.G;
     const int64_t nf = (int64_t)G * G, f0 = (int64_t)blockIdx.x * nf;
     double *X1 = (double *)dfn_lds, *X2 = X1 + nf;
-#pragma unroll 6
+#pragma unroll 18
     for (int64_t il = lane; il < nf; il += DFN_WAVE) {
         X1[il] = io_t[f0 + il];
         X2[il] = io_d[f0 + il];
