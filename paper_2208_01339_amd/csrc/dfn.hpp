@@ -369,9 +369,9 @@ __device__ __forceinline__ void dfn_wave_sync()
 //   backward (REV = true):  X = L~^{-T} X
 // so forward then backward gives A^{-1} X (A = L~ D^2 L~^T).  Q: the block's
 // Qf or Qb.  A line of GM steps is unrolled (GM >= G; EX: GM == G) with the
-// lane's coefficients in registers, two buffers used by alternate lines: the
-// next line's loads are in flight while this line runs.  Lanes G..63 hold no
-// row and their values are never stored.
+// lane's coefficients in registers, two buffers used by alternate lines, so
+// the loads of the lines ahead are in flight while this line runs.  Lanes
+// G..63 hold no row and their values are never stored.
 template <int GM, bool EX, bool REV>
 __device__ __forceinline__ void dfn_sweep(const double *__restrict__ Q, const double *__restrict__ di2, int G,
                                           double *X)
@@ -396,22 +396,44 @@ __device__ __forceinline__ void dfn_sweep(const double *__restrict__ Q, const do
     double ca[GM], cb[GM];
     double acc = act ? X[row(0)] : 0.0, fin = 0.0;
     // line K with coefficients cur; the next line's (the last line: its own again) into nxt
-    auto line = [&](int K, double (&cur)[GM], double (&nxt)[GM]) {
-        const int64_t nl = (int64_t)(K + 1 < G ? K + 1 : K) * G;
-        const double sc = (!REV && act) ? di2[row(K)] : 1.0;
-#pragma unroll
-        for (int q = 0; q < GM; ++q) nxt[q] = coef(nl, q);
+    // steps q0..q1-1 of the current line
+    auto steps = [&](const double (&cur)[GM], int q0, int q1) {
 #pragma unroll
         for (int q = 0; q < GM; ++q) {
+            if (q < q0 || q >= q1) continue;
             const double v = dfn_rdlane(acc, q);
             fin = dfn_wrlane(v, fin, q);
             acc -= cur[q] * v;
+        }
+    };
+    // HALF (lines of at most 48 steps): the first half of line K+2 is loaded
+    // into the half of cur just used, the second half of line K+1 into nxt at
+    // the start of line K, so every coefficient is requested 1.5 lines ahead.
+    // Otherwise all of line K+1 into nxt at the start of line K (one line
+    // ahead: the wider buffers would not fit the registers).
+    constexpr bool HALF = GM <= 48;
+    constexpr int H = HALF ? GM / 2 : 0;
+    auto line = [&](int K, double (&cur)[GM], double (&nxt)[GM]) {
+        const int64_t n1 = (int64_t)(K + 1 < G ? K + 1 : K) * G;
+        const int64_t n2 = (int64_t)(K + 2 < G ? K + 2 : K) * G;
+        const double sc = (!REV && act) ? di2[row(K)] : 1.0;
+#pragma unroll
+        for (int q = H; q < GM; ++q) nxt[q] = coef(n1, q);
+        if constexpr (HALF) {
+            steps(cur, 0, H);
+#pragma unroll
+            for (int q = 0; q < H; ++q) cur[q] = coef(n2, q);
+            steps(cur, H, GM);
+        } else {
+            steps(cur, 0, GM);
         }
         if (act) X[row(K)] = REV ? fin : fin * sc;
         if (K + 1 < G && act) acc += X[row(K + 1)];
     };
 #pragma unroll
     for (int q = 0; q < GM; ++q) ca[q] = coef(0, q);
+#pragma unroll
+    for (int q = 0; q < H; ++q) cb[q] = coef(1 < G ? G : 0, q);
     for (int K = 0; K < G; K += 2) {
         line(K, ca, cb);
         if (K + 1 < G) line(K + 1, cb, ca);
