@@ -19,29 +19,36 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ppcg_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# The same source built with OpenMP: used only to time the oracle on all host
+# cores (its dot products sum in another order; it is never a parity reference).
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
 
 OK, NOT_CONVERGED, BREAKDOWN, ERR_ARG = 0, 1, 2, -1
 
+_CFLAGS = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (no FMA contraction, no fast-math)."""
-    if force or not os.path.exists(_LIB):
-        cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-               "-shared", "-o", _LIB + ".tmp", _SRC, "-lm"]
-        subprocess.check_call(cmd)
-        os.replace(_LIB + ".tmp", _LIB)
+    """Compile the oracle with gcc (no FMA contraction, no fast-math), and its
+    OpenMP timing build."""
+    for out, extra in ((_LIB, []), (_LIB_OMP, ["-fopenmp"])):
+        if force or not os.path.exists(out):
+            subprocess.check_call(_CFLAGS + extra + ["-o", out + ".tmp", _SRC, "-lm"])
+            os.replace(out + ".tmp", out)
     return _LIB
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+def lib(omp: bool = False):
+    """The checker build, or with ``omp`` the OpenMP timing build."""
+    key = bool(omp)
+    if key not in _libs:
+        path = _LIB_OMP if omp else _LIB
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
             build(force=True)
-        L = C.CDLL(_LIB)
+        L = C.CDLL(path)
         P = C.c_void_p
         L.orc_dot.restype = C.c_double
         L.orc_dot.argtypes = [C.c_int64, P, P]
@@ -57,6 +64,9 @@ def lib():
         L.orc_pcg.restype = C.c_int
         L.orc_pcg.argtypes = [P, C.c_int, C.c_double, C.c_double, C.c_double, P, P, C.c_double,
                               C.c_int, P]
+        L.orc_pcg_newton.restype = C.c_int
+        L.orc_pcg_newton.argtypes = [P, C.c_int, C.c_double, C.c_double, C.c_double, P, P, C.c_double,
+                                     C.c_int, P]
         L.orc_lowrank_setup.restype = C.c_int
         L.orc_lowrank_setup.argtypes = [P, C.c_int, P, P]
         L.orc_lowrank_apply.restype = C.c_int
@@ -74,8 +84,8 @@ def lib():
         L.orc_dfn_diag.argtypes = [P, P]
         L.orc_dfn_rhs.argtypes = [P, P, P]
         L.orc_dfn_recover.argtypes = [P, P, P, P, P]
-        _lib = L
-    return _lib
+        _libs[key] = L
+    return _libs[key]
 
 
 class _OpStruct(C.Structure):
@@ -115,7 +125,7 @@ class Operator:
     ``a`` is any object with ``rowptr``, ``col``, ``val`` (CSR, n x n); for the
     Schur shape pass ``c`` (nt x n CSR) and ``m`` (nt).  With ``jacobi`` the
     operator seen by every routine is D^{-1/2} op D^{-1/2}, D = diag(op)
-    (section 3 with W = D^{-1/2}; section 4.2 for the Schur case).
+    (section 3 with W = D^{-1/2}; section 4.3 for the Schur case).
     """
 
     def __init__(self, a, c=None, m=None, jacobi: bool = False):
@@ -183,9 +193,10 @@ class Operator:
 
 
 class DfnOperator(Operator):
-    """The DFN Schur complement S_u(alpha) of section 4.1, applied by
-    Algorithm 3 with the exact (banded) Cholesky factor of A; with ``jacobi``
-    the operator is D_S^{-1/2} S_u D_S^{-1/2}, D_S = diag(S_u) by Algorithm 4.
+    """The DFN Schur complement S_u(alpha) of section 4.2, applied from the
+    expansion of eq. (schur) with the exact (banded) Cholesky factor of A; with
+    ``jacobi`` the operator is D_S^{-1/2} S_u D_S^{-1/2}, D_S = diag(S_u)
+    (section 4.3, the quantity of Algorithm 4).
 
     ``parts`` carries the CSR blocks ``a, gh, c, b, gu``, ``alpha``, ``n_frac``
     and ``grid`` (each fracture a block of grid^2 rows of A and G^h).  Every
@@ -311,18 +322,33 @@ def newton_apply_hat(op: Operator, nlev: int, lmin: float, lmax: float, xi: floa
 
 
 def pcg(op: Operator, k: int, lmin: float, lmax: float, xi: float, b, x0=None, tol: float = 1e-8,
-        maxit: int = 1000):
-    """CG on op x = b preconditioned by p_k; returns (x, stats)."""
+        maxit: int = 1000, omp: bool = False):
+    """CG on op x = b preconditioned by p_k; returns (x, stats).
+
+    ``omp`` runs the OpenMP timing build (CSR and Schur operators only)."""
     b = _f64(b)
     x = np.zeros(op.n) if x0 is None else _f64(x0).copy()
     st = _PcgStats()
     t0 = time.perf_counter()
-    ret = lib().orc_pcg(C.byref(op._s), k, lmin, lmax, xi, _p(b), _p(x), tol, maxit, C.byref(st))
+    ret = lib(omp).orc_pcg(C.byref(op._s), k, lmin, lmax, xi, _p(b), _p(x), tol, maxit, C.byref(st))
     dt = time.perf_counter() - t0
     if ret == ERR_ARG:
         raise ValueError("invalid PCG arguments")
     return x, dict(iters=int(st.iters), status=int(st.status), relres=float(st.relres),
                    n_apply=int(st.n_apply), n_dot=int(st.n_dot), seconds=dt)
+
+
+def pcg_newton(op: Operator, nlev: int, lmin: float, lmax: float, xi: float, b, x0=None, tol: float = 1e-8,
+               maxit: int = 1000):
+    """CG on op x = b preconditioned by P_nlev of Algorithm 1; returns (x, stats)."""
+    b = _f64(b)
+    x = np.zeros(op.n) if x0 is None else _f64(x0).copy()
+    st = _PcgStats()
+    ret = lib().orc_pcg_newton(C.byref(op._s), nlev, lmin, lmax, xi, _p(b), _p(x), tol, maxit, C.byref(st))
+    if ret == ERR_ARG:
+        raise ValueError("invalid PCG arguments")
+    return x, dict(iters=int(st.iters), status=int(st.status), relres=float(st.relres),
+                   n_apply=int(st.n_apply), n_dot=int(st.n_dot))
 
 
 def _cols(V) -> np.ndarray:

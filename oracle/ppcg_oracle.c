@@ -6,8 +6,11 @@
  * CPU-baseline leg of the benchmark load it; the GPU library never does, and
  * the two share no code.  Everything here is written for a reader to compare
  * by eye with the paper: plain loops, left-to-right sums, no blocking, no
- * fusion, no threads.  Build with -ffp-contract=off so that no FMA changes the
- * rounding of the printed formulas.
+ * fusion.  Build with -ffp-contract=off so that no FMA changes the rounding of
+ * the printed formulas.  The checker build has no threads.  The few OpenMP
+ * pragmas on row loops and dot products are read only by a second build
+ * (-fopenmp), used solely to time the oracle on all host cores; that build
+ * sums dot products in another order and is never a parity reference.
  *
  * Paper: Bergamaschi, Ferronato, Isotton, Janna, Martinez, "Parallel
  * matrix-free polynomial preconditioners with application to flow simulations
@@ -16,19 +19,21 @@
  * Contents and the passage each follows:
  *   orc_op_apply     y = A x for a CSR matrix, or for the Schur-shaped
  *                    operator y = A_ff x + C^T (M^{-1} (C x)) (the
- *                    G - W^T M^{-1} Z pattern of section 4.1, eq. (schur),
+ *                    G - W^T M^{-1} Z pattern of section 4.2, eq. (schur),
  *                    with a diagonal middle block), optionally symmetrically
- *                    scaled by D^{-1/2} (section 3, W = D^{-1/2}; section 4.2).
+ *                    scaled by D^{-1/2} (section 3, W = D^{-1/2}; section 4.3).
  *   orc_op_diag      diag of that operator without forming it (the analogue
  *                    of Algorithm 4 for the Schur shape).
  *   orc_cheb_coeffs  theta-bar, delta, sigma and rho_j: section 2.2 eqs.
  *                    (polycheb)/(rhocheb) with theta replaced by
  *                    theta-bar = (beta+alpha)/2 (1+xi), eq. (thetamod).
- *   orc_cheb_apply   z = p_k(A) r, Algorithm 2.
+ *   orc_cheb_apply   z = p_k(A) r from the recurrence of the polynomials,
+ *                    section 2.2 eq. (polycheb) (what Algorithm 2 computes).
  *   orc_newton_apply z = P_nlev r, Algorithm 1 (degree 2^nlev - 1).
  *   orc_pcg          CG preconditioned by p_k(A), standard Hestenes-Stiefel
  *                    loop; counts operator applications and dot products as
  *                    reported in Table tab11.
+ *   orc_pcg_newton   the same loop preconditioned by P_nlev of Algorithm 1.
  *   orc_lowrank_setup, orc_lowrank_apply, orc_pcg_lowrank
  *                    the spectral low-rank correction of section 3.1:
  *                    P = P_0 + V (V^T A V)^{-1} V^T with P_0 = p_k(A), and CG
@@ -39,12 +44,14 @@
  *                    eigenvalues alpha, beta that section 2 assumes known.
  *   orc_fmix32_start Lanczos start vector from the MurmurHash3 32-bit
  *                    finaliser of the row index.
- *   orc_dfn_*        the DFN Schur complement of section 4.1 (operator kind
- *                    2): the exact Cholesky factor of the block-diagonal A
- *                    (orc_dfn_factor), y = S_u r by Algorithm 3 (used by
- *                    orc_op_apply), diag(S_u) by Algorithm 4 (orc_op_diag),
- *                    the reduced right-hand side r = W^T M^{-1} f_1 and the
- *                    recovery of h and p after the solve for u.
+ *   orc_dfn_*        the DFN Schur complement of sections 4.2-4.3 (operator
+ *                    kind 2): the exact Cholesky factor of the block-diagonal
+ *                    A (orc_dfn_factor), y = S_u r from the expansion of
+ *                    eq. (schur) (used by orc_op_apply), diag(S_u) from the
+ *                    same expansion (orc_op_diag; the quantity Algorithm 4
+ *                    computes), the reduced right-hand side
+ *                    r = W^T M^{-1} f_1 and the recovery of h and p after the
+ *                    solve for u (section 4.2).
  */
 #include <math.h>
 #include <stdint.h>
@@ -96,6 +103,7 @@ enum { ORC_OK = 0, ORC_NOT_CONVERGED = 1, ORC_BREAKDOWN = 2, ORC_ERR_ARG = -1 };
 double orc_dot(int64_t n, const double *x, const double *y)
 {
     double s = 0.0;
+    #pragma omp parallel for schedule(static) reduction(+ : s)
     for (int64_t i = 0; i < n; ++i) s += x[i] * y[i];
     return s;
 }
@@ -108,6 +116,7 @@ double orc_dot(int64_t n, const double *x, const double *y)
 void orc_csr_matvec(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
                     const double *x, double *y)
 {
+    #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         double s = 0.0;
         for (int64_t p = rp[i]; p < rp[i + 1]; ++p) s += v[p] * x[ci[p]];
@@ -116,7 +125,7 @@ void orc_csr_matvec(int64_t n, const int64_t *rp, const int32_t *ci, const doubl
 }
 
 /* ------------------------------------------------------------------------ */
-/* DFN Schur complement (section 4.1)                                        */
+/* DFN Schur complement (sections 4.2 and 4.3)                              */
 /* ------------------------------------------------------------------------ */
 
 /* y = M^T x for a CSR matrix M with n rows (y has M's column count, zeroed here). */
@@ -163,8 +172,8 @@ int orc_dfn_factor(orc_dfn *d)
     return ORC_OK;
 }
 
-/* x = A^{-1} b = L^{-T} (L^{-1} b), fracture by fracture (the two triangular
- * solves of Algorithm 3).  x may alias b. */
+/* x = A^{-1} b = L^{-T} (L^{-1} b) with A = L L^T, fracture by fracture
+ * (section 4.2).  x may alias b. */
 void orc_dfn_ainv(const orc_dfn *d, const double *b, double *x)
 {
     const int64_t G = d->G, nf = d->nf, W = G + 1;
@@ -187,37 +196,45 @@ void orc_dfn_ainv(const orc_dfn *d, const double *b, double *x)
     }
 }
 
-/* y = S_u r by Algorithm 3, with the alpha of S_u(alpha) on every product by B
- * (the listing takes alpha = 1):
- *   v = C r;  z = a B r;  t = A^{-1} v;  w = A^{-1} z;
- *   z = G^u r - a B^T t - C^T w;  v = G^h t;  w = A^{-1} v;  y = z + C^T w. */
+/* y = S_u r from the expansion of the Schur complement (section 4.2, eq. (schur)):
+ *   S_u(a) = G^u - a B^T A^{-1} C - a C^T A^{-1} B + C^T A^{-1} G^h A^{-1} C,
+ * one term after the other, each A^{-1} by the two triangular solves with
+ * the exact factor.  A^{-1} C r is formed once and used by the second and the
+ * last term.  (Algorithm 3 evaluates the same products in another grouping.) */
 void orc_dfn_su(orc_dfn *d, const double *r, double *y)
 {
     const int64_t nh = d->nh, nu = d->nu;
-    double *v = d->w1, *z = d->w2, *t = d->w3, *w = d->w4, *zu = d->wu;
-    orc_csr_matvec(nh, d->crp, d->cci, d->cv, r, v);
-    orc_csr_matvec(nh, d->brp, d->bci, d->bv, r, z);
-    for (int64_t i = 0; i < nh; ++i) z[i] = d->alpha * z[i];
-    orc_dfn_ainv(d, v, t);
-    orc_dfn_ainv(d, z, w);
-    orc_csr_matvec(nu, d->gurp, d->guci, d->guv, r, zu);
-    csr_tmatvec(nh, nu, d->brp, d->bci, d->bv, t, y);   /* y = B^T t */
-    for (int64_t j = 0; j < nu; ++j) zu[j] -= d->alpha * y[j];
-    csr_tmatvec(nh, nu, d->crp, d->cci, d->cv, w, y);   /* y = C^T w */
-    for (int64_t j = 0; j < nu; ++j) zu[j] -= y[j];
-    orc_csr_matvec(nh, d->ghrp, d->ghci, d->ghv, t, v);
-    orc_dfn_ainv(d, v, w);
-    csr_tmatvec(nh, nu, d->crp, d->cci, d->cv, w, y);   /* y = C^T w */
-    for (int64_t j = 0; j < nu; ++j) y[j] = zu[j] + y[j];
+    double *cr = d->w1, *ainv_cr = d->w2, *tmp = d->w3, *tmp2 = d->w4, *term = d->wu;
+    /* term 1: G^u r */
+    orc_csr_matvec(nu, d->gurp, d->guci, d->guv, r, y);
+    /* term 2: - a B^T (A^{-1} C r) */
+    orc_csr_matvec(nh, d->crp, d->cci, d->cv, r, cr);
+    orc_dfn_ainv(d, cr, ainv_cr);
+    csr_tmatvec(nh, nu, d->brp, d->bci, d->bv, ainv_cr, term);
+    for (int64_t j = 0; j < nu; ++j) y[j] -= d->alpha * term[j];
+    /* term 3: - a C^T (A^{-1} B r) */
+    orc_csr_matvec(nh, d->brp, d->bci, d->bv, r, tmp);
+    orc_dfn_ainv(d, tmp, tmp2);
+    csr_tmatvec(nh, nu, d->crp, d->cci, d->cv, tmp2, term);
+    for (int64_t j = 0; j < nu; ++j) y[j] -= d->alpha * term[j];
+    /* term 4: + C^T A^{-1} G^h (A^{-1} C r) */
+    orc_csr_matvec(nh, d->ghrp, d->ghci, d->ghv, ainv_cr, tmp);
+    orc_dfn_ainv(d, tmp, tmp2);
+    csr_tmatvec(nh, nu, d->crp, d->cci, d->cv, tmp2, term);
+    for (int64_t j = 0; j < nu; ++j) y[j] += term[j];
 }
 
-/* diag(S_u) by Algorithm 4:  Z = A^{-1} C;  T = G^h Z - 2 a B;
- * (D_S)_i = (G^u)_ii + z_i^T t_i, one column i at a time.  A block whose part
- * of c_i is zero has a zero part of z_i and is not solved. */
+/* diag(S_u) without forming S_u (section 4.3): entry i of the expansion above
+ * is, with c_i, b_i the i-th columns of C and B and z_i = A^{-1} c_i (A and
+ * so A^{-1} symmetric, hence c_i^T A^{-1} b_i = b_i^T z_i):
+ *   (S_u)_ii = (G^u)_ii - 2 a b_i^T z_i + z_i^T G^h z_i,
+ * which Algorithm 4 groups as (G^u)_ii + z_i^T (G^h z_i - 2 a b_i).  One
+ * column at a time; a block whose part of c_i is zero has a zero part of z_i
+ * and is not solved. */
 void orc_dfn_diag(orc_dfn *d, double *ds)
 {
     const int64_t nh = d->nh, nu = d->nu, G = d->G, nf = d->nf, W = G + 1;
-    double *c = d->w1, *z = d->w2, *t = d->w3, *b = d->w4;
+    double *c = d->w1, *z = d->w2, *ghz = d->w3, *b = d->w4;
     for (int64_t i = 0; i < nu; ++i) {
         for (int64_t r = 0; r < nh; ++r) c[r] = 0.0, b[r] = 0.0;
         for (int64_t r = 0; r < nh; ++r) {
@@ -247,12 +264,11 @@ void orc_dfn_diag(orc_dfn *d, double *ds)
                 z[r] = s / d->L[r * W];
             }
         }
-        orc_csr_matvec(nh, d->ghrp, d->ghci, d->ghv, z, t);
-        for (int64_t r = 0; r < nh; ++r) t[r] = t[r] - 2.0 * d->alpha * b[r];
         double gii = 0.0;
         for (int64_t p = d->gurp[i]; p < d->gurp[i + 1]; ++p)
             if (d->guci[p] == i) gii += d->guv[p];
-        ds[i] = gii + orc_dot(nh, z, t);
+        orc_csr_matvec(nh, d->ghrp, d->ghci, d->ghv, z, ghz);
+        ds[i] = gii - 2.0 * d->alpha * orc_dot(nh, b, z) + orc_dot(nh, z, ghz);
     }
 }
 
@@ -313,8 +329,10 @@ void orc_op_apply(orc_op *op, const double *x, double *y)
         return;
     }
     double *t = op->work_n;
+    #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < op->n; ++i) t[i] = op->dis[i] * x[i];
     op_apply_raw(op, t, y);
+    #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < op->n; ++i) y[i] = op->dis[i] * y[i];
 }
 
@@ -366,11 +384,15 @@ int orc_cheb_coeffs(int k, double lmin, double lmax, double xi,
 }
 
 /*
- * z = p_k(op-hat) r by Algorithm 2: k operator applications.
- *   x_old = r / theta
- *   x     = (2 rho_1 / delta) (2 r - A r / theta)
- *   for j = 2..k:  t = (2/delta)(r - A x);  r_hat = rho_j (2 sigma x - rho_{j-1} x_old + t)
- *                  x_old = x;  x = r_hat
+ * z = p_k(op-hat) r, from the recurrence that defines the polynomials
+ * (section 2.2, eq. (polycheb), theta replaced by theta-bar of eq. (thetamod)):
+ *   p_{-1} = 0,   p_0 = 1/theta,
+ *   p_j(x) = rho_j (2 sigma (1 - x/theta) p_{j-1}(x) - rho_{j-1} p_{j-2}(x) + 2/delta),
+ * taken at the operator and applied to r.  With s_j = p_j(A) r:
+ *   s_{-1} = 0,  s_0 = r / theta,
+ *   s_j = rho_j (2 sigma (s_{j-1} - A s_{j-1} / theta) - rho_{j-1} s_{j-2} + (2/delta) r).
+ * One operator application per degree, k in all.  Algorithm 2 forms the same
+ * vectors (its first step is s_1 with s_{-1} = 0 written out).
  * work must hold 3 n doubles.
  */
 int orc_cheb_apply(orc_op *op, int k, double lmin, double lmax, double xi,
@@ -382,25 +404,23 @@ int orc_cheb_apply(orc_op *op, int k, double lmin, double lmax, double xi,
     if (!rho) return ORC_ERR_ARG;
     int st = orc_cheb_coeffs(k, lmin, lmax, xi, &th, &de, &si, rho);
     if (st != ORC_OK) { free(rho); return st; }
-    if (k == 0) {
-        for (int64_t i = 0; i < n; ++i) z[i] = r[i] / th;
-        free(rho);
-        return ORC_OK;
+    double *s_prev = work, *s = work + n, *as = work + 2 * n;
+    #pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        s_prev[i] = 0.0;          /* s_{-1} */
+        s[i] = r[i] / th;         /* s_0    */
     }
-    double *xold = work, *x = work + n, *ax = work + 2 * n;
-    for (int64_t i = 0; i < n; ++i) xold[i] = r[i] / th;
-    orc_op_apply(op, r, ax);
-    for (int64_t i = 0; i < n; ++i) x[i] = (2.0 * rho[1] / de) * (2.0 * r[i] - ax[i] / th);
-    for (int j = 2; j <= k; ++j) {
-        orc_op_apply(op, x, ax);
+    for (int j = 1; j <= k; ++j) {
+        orc_op_apply(op, s, as);
+        const double rj = rho[j], rjm1 = rho[j - 1];
+        #pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < n; ++i) {
-            double t = (2.0 / de) * (r[i] - ax[i]);
-            double rh = rho[j] * (2.0 * si * x[i] - rho[j - 1] * xold[i] + t);
-            xold[i] = x[i];
-            x[i] = rh;
+            double next = rj * (2.0 * si * (s[i] - as[i] / th) - rjm1 * s_prev[i] + (2.0 / de) * r[i]);
+            s_prev[i] = s[i];
+            s[i] = next;
         }
     }
-    memcpy(z, x, sizeof(double) * (size_t)n);
+    memcpy(z, s, sizeof(double) * (size_t)n);
     free(rho);
     return ORC_OK;
 }
@@ -552,13 +572,31 @@ int orc_lowrank_apply(orc_op *op, int k, double lmin, double lmax, double xi, in
     return ORC_OK;
 }
 
-static int pcg_core(orc_op *op, int k, double lmin, double lmax, double xi, int lr_p, const double *V,
-                    const double *Hinv, const double *b, double *x, double tol, int maxit, orc_pcg_stats *st);
+/* The polynomial part of the preconditioner: p_k(A) r (Chebyshev, nlev < 0)
+ * or P_nlev r (Newton form of Algorithm 1, degree 2^nlev - 1). */
+static int poly_apply(orc_op *op, int k, int nlev, double lmin, double lmax, double xi, const double *r,
+                      double *z, double *work)
+{
+    if (nlev >= 0) return orc_newton_apply(op, nlev, lmin, lmax, xi, r, z);
+    return orc_cheb_apply(op, k, lmin, lmax, xi, r, z, work);
+}
+
+static int pcg_core(orc_op *op, int k, int nlev, double lmin, double lmax, double xi, int lr_p,
+                    const double *V, const double *Hinv, const double *b, double *x, double tol, int maxit,
+                    orc_pcg_stats *st);
 
 int orc_pcg(orc_op *op, int k, double lmin, double lmax, double xi, const double *b, double *x,
             double tol, int maxit, orc_pcg_stats *st)
 {
-    return pcg_core(op, k, lmin, lmax, xi, 0, NULL, NULL, b, x, tol, maxit, st);
+    return pcg_core(op, k, -1, lmin, lmax, xi, 0, NULL, NULL, b, x, tol, maxit, st);
+}
+
+/* CG preconditioned by the Newton form P_nlev of Algorithm 1 (section 2.1). */
+int orc_pcg_newton(orc_op *op, int nlev, double lmin, double lmax, double xi, const double *b, double *x,
+                   double tol, int maxit, orc_pcg_stats *st)
+{
+    if (nlev < 0 || nlev > 20) return ORC_ERR_ARG;
+    return pcg_core(op, 0, nlev, lmin, lmax, xi, 0, NULL, NULL, b, x, tol, maxit, st);
 }
 
 /* CG preconditioned by P = p_k(A) + V Hinv V^T (Hinv from orc_lowrank_setup). */
@@ -566,11 +604,12 @@ int orc_pcg_lowrank(orc_op *op, int k, double lmin, double lmax, double xi, int 
                     const double *Hinv, const double *b, double *x, double tol, int maxit, orc_pcg_stats *st)
 {
     if (p < 0 || p > 64) return ORC_ERR_ARG;
-    return pcg_core(op, k, lmin, lmax, xi, p, V, Hinv, b, x, tol, maxit, st);
+    return pcg_core(op, k, -1, lmin, lmax, xi, p, V, Hinv, b, x, tol, maxit, st);
 }
 
-static int pcg_core(orc_op *op, int k, double lmin, double lmax, double xi, int lr_p, const double *V,
-                    const double *Hinv, const double *b, double *x, double tol, int maxit, orc_pcg_stats *st)
+static int pcg_core(orc_op *op, int k, int nlev, double lmin, double lmax, double xi, int lr_p,
+                    const double *V, const double *Hinv, const double *b, double *x, double tol, int maxit,
+                    orc_pcg_stats *st)
 {
     int64_t n = op->n;
     memset(st, 0, sizeof(*st));
@@ -606,7 +645,7 @@ static int pcg_core(orc_op *op, int k, double lmin, double lmax, double xi, int 
             goto done;
         }
     }
-    ret = orc_cheb_apply(op, k, lmin, lmax, xi, r, z, cw);
+    ret = poly_apply(op, k, nlev, lmin, lmax, xi, r, z, cw);
     if (ret != ORC_OK) goto done;
     if (lr_p > 0) lowrank_add(n, lr_p, V, Hinv, r, z, &st->n_dot);
     double rho = orc_dot(n, r, z);
@@ -621,6 +660,7 @@ static int pcg_core(orc_op *op, int k, double lmin, double lmax, double xi, int 
         st->n_dot += 1;
         if (!(gamma > 0.0) || !isfinite(gamma)) { ret = ORC_BREAKDOWN; break; }
         double alpha = rho / gamma;
+        #pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < n; ++i) {
             xh[i] = xh[i] + alpha * p[i];
             r[i] = r[i] - alpha * q[i];
@@ -632,12 +672,13 @@ static int pcg_core(orc_op *op, int k, double lmin, double lmax, double xi, int 
         if (!isfinite(rr)) { ret = ORC_BREAKDOWN; break; }
         if (sqrt(rr) <= tol * bnorm) { ret = ORC_OK; break; }
         if (it == maxit) { ret = ORC_NOT_CONVERGED; break; }
-        orc_cheb_apply(op, k, lmin, lmax, xi, r, z, cw);
+        poly_apply(op, k, nlev, lmin, lmax, xi, r, z, cw);
         if (lr_p > 0) lowrank_add(n, lr_p, V, Hinv, r, z, &st->n_dot);
         double rho_new = orc_dot(n, r, z);
         st->n_dot += 1;
         if (!(rho_new > 0.0) || !isfinite(rho_new)) { ret = ORC_BREAKDOWN; break; }
         double beta = rho_new / rho;
+        #pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
         rho = rho_new;
     }

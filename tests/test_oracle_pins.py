@@ -429,3 +429,57 @@ def test_effective_preconditioner_jacobi():
     Ph = V @ np.diag(poly_closed_form(k, lmin, lmax, xi, lam)) @ V.T
     r = np.array([1.0, -2.0, 0.5])
     assert np.allclose(O.cheb_apply(op, k, lmin, lmax, xi, r), dis * (Ph @ (dis * r)), rtol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Newton-form PCG (Algorithm 1 inside the CG loop)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("nlev", [0, 2, 4])
+def test_pcg_newton_matches_dense_cholesky(nlev):
+    """CG preconditioned by P_nlev solves the system: against a dense Cholesky
+    solve within kappa * tol, and its loop counts obey the tab11 identities
+    (operator applications = iters (degree + 1), dots = 3 iters)."""
+    a = W.hetero_diffusion(6, 2.0, 13)
+    b = W.rhs_uniform(a.n_rows, 14)
+    op = O.Operator(a, jacobi=True)
+    lmin, lmax = O.lanczos_bounds(op, 20)
+    tol = 1e-12
+    x, st = O.pcg_newton(op, nlev, lmin, lmax, 1e-3, b, tol=tol, maxit=5000)
+    assert st["status"] == O.OK
+    Ad = a.to_scipy().toarray()
+    xs = sla.cho_solve(sla.cho_factor(Ad), b)
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= np.linalg.cond(Ad) * tol * 10
+    deg = 2 ** nlev - 1
+    assert st["n_apply"] == st["iters"] * (deg + 1)
+    assert st["n_dot"] == 3 * st["iters"]
+
+
+def test_pcg_newton_degree0_equals_plain_cg():
+    """nlev = 0 gives P_0 = zeta_0 I: CG must take exactly the iterations of textbook
+    CG, as for the Chebyshev form at k = 0."""
+    a, b = W.config_poisson32()
+    op = O.Operator(a)
+    xo, st = O.pcg(op, 0, 0.0598, 12.01, 0.0, b, tol=1e-8, maxit=2000)
+    xn, sn = O.pcg_newton(op, 0, 0.0598, 12.01, 0.0, b, tol=1e-8, maxit=2000)
+    assert sn["iters"] == st["iters"]
+    assert np.linalg.norm(xn - xo) / np.linalg.norm(xo) < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# The OpenMP timing build runs the same arithmetic
+# ---------------------------------------------------------------------------
+
+def test_omp_timing_build_same_solution():
+    """The oracle built with -fopenmp (used only to time the CPU baseline) takes
+    the iterations of the checker build and reaches its solution to rounding."""
+    a = W.hetero_diffusion(24, 2.0, 0)
+    b = W.rhs_uniform(a.n_rows, 1)
+    op = O.Operator(a, jacobi=True)
+    lmin, lmax = O.lanczos_bounds(op, 20)
+    x1, s1 = O.pcg(op, 20, lmin, lmax, 0.0, b, tol=1e-8, maxit=500)
+    x2, s2 = O.pcg(op, 20, lmin, lmax, 0.0, b, tol=1e-8, maxit=500, omp=True)
+    assert s1["status"] == s2["status"] == O.OK
+    assert abs(s1["iters"] - s2["iters"]) <= 1
+    x3, _ = O.pcg(op, 20, lmin, lmax, 0.0, b, tol=0.0, maxit=s1["iters"], omp=True)
+    assert np.linalg.norm(x3 - x1) / np.linalg.norm(x1) < 1e-12
