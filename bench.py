@@ -32,7 +32,7 @@ The JSON line also carries:
   mixed         the same solve with the polynomial in FP32 (PP_MIXED);
   newton        the same solve with the Newton form of Algorithm 1 at degrees
                 15 and 63 against the three-term form at the same degrees;
-  dfn_su        the DFN Schur complement S_u of section 4.1 (Algorithms 3 and 4;
+  dfn_su        the DFN Schur complement S_u of section 4.2 (Algorithms 3 and 4;
                 400 fractures of 48 x 48, n_u = 55,132): iterations, time and
                 S_u applications at the degrees of Table tab11 (xi = 1e-3),
                 the rank-one correction at degree 31, and the recovery of h, p;
@@ -153,7 +153,7 @@ def run_dfn(args, B, W, torch, dev):
 
 
 def run_dfn_su(args, B, W, torch, dev):
-    """The DFN Schur complement S_u of section 4.1 (400 fractures of 48 x 48 cells,
+    """The DFN Schur complement S_u of section 4.2 (400 fractures of 48 x 48 cells,
     1100 traces: n_h = 921,600, n_u = 55,132, the sizes of the paper's DFN test
     case #1): reduced right-hand side, PCG on D_S^{-1/2} S_u D_S^{-1/2} at the
     degrees of Table tab11 (xi = 1e-3), recovery of h and p.  The time of one
@@ -386,7 +386,7 @@ def main():
     ap.add_argument("--no-block", action="store_true", help="skip the 32-RHS block leg")
     ap.add_argument("--no-lowrank", action="store_true", help="skip the low-rank correction legs")
     ap.add_argument("--no-newton", action="store_true", help="skip the Newton-form leg")
-    ap.add_argument("--no-dfn-su", action="store_true", help="skip the DFN S_u leg (section 4.1)")
+    ap.add_argument("--no-dfn-su", action="store_true", help="skip the DFN S_u leg (section 4.2)")
     ap.add_argument("--dfn-su-ks", default="0,7,15,31,63")
     ap.add_argument("--no-two-step", action="store_true",
                     help="one pass per Chebyshev step (no fused pairs) in the main leg")

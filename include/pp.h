@@ -11,10 +11,10 @@
  * rhocheb; section 2.4, eq. thetamod).  P is applied matrix-free by the
  * three-term recurrence of Algorithm 2: k operator applications and a few
  * vector updates, no dot product.  The operator is either a CSR matrix or the
- * never-assembled Schur-shaped operator S = A_ff + C^T M^{-1} C of section 4.1
+ * never-assembled Schur-shaped operator S = A_ff + C^T M^{-1} C of section 4.2
  * (eq. schur, with a diagonal middle block).  Optional symmetric Jacobi
  * scaling D^{-1/2} A D^{-1/2} is the diagonal seed preconditioner of
- * section 3 (W = D^{-1/2}) and section 4.2.
+ * section 3 (W = D^{-1/2}) and section 4.3.
  *
  * Conventions for every entry point:
  *  - Array arguments are DEVICE pointers (hipMalloc'ed or torch CUDA tensors)
@@ -61,7 +61,7 @@ typedef enum {
 
 /* create flags */
 enum {
-    PP_JACOBI = 1u, /* iterate on D^{-1/2} A D^{-1/2}, D = diag(A) (section 3, 4.2)        */
+    PP_JACOBI = 1u, /* iterate on D^{-1/2} A D^{-1/2}, D = diag(A) (section 3, 4.3)        */
     PP_MIXED = 2u,  /* p_k(A)v in FP32 (values, vectors, accumulation); CG stays FP64     */
     PP_SLICED = 4u  /* keep every entry in the sliced layout (no symmetric diagonal part)  */
 };
@@ -90,7 +90,7 @@ PP_API pp_status pp_create_csr(pp_op *out, int64_t n, int64_t nnz, const int64_t
                         const int32_t *colind, const double *val, unsigned flags, void *stream);
 
 /*
- * Create the Schur-shaped operator S = A_ff + C^T diag(m)^{-1} C (section 4.1,
+ * Create the Schur-shaped operator S = A_ff + C^T diag(m)^{-1} C (section 4.2,
  * eq. schur; Algorithm 3 applies the paper's S_u the same way, matrix-free).
  *   A_ff    n x n CSR (a_rowptr [n+1] int64, a_col [nnz_a] int32, a_val [nnz_a])
  *   C       nt x n CSR (c_rowptr [nt+1] int64, c_col [nnz_c] int32, c_val [nnz_c])
@@ -104,7 +104,7 @@ PP_API pp_status pp_create_schur(pp_op *out, int64_t n, int64_t nnz_a, const int
                           const double *m_diag, unsigned flags, void *stream);
 
 /*
- * The DFN Schur complement of section 4.1 (eq. schur):
+ * The DFN Schur complement of section 4.2 (eq. schur):
  *   S_u(alpha) = G^u - alpha B^T A^{-1} C - alpha C^T A^{-1} B + C^T A^{-1} G^h A^{-1} C,
  * the operator of the reduced system S_u u = r after the permutation of
  * eq. (tilde_var).  A sparse matrix given as CSR on the device:
@@ -141,10 +141,11 @@ typedef struct {
 
 /*
  * Create the operator S_u of a DFN system (n = n_u).  At create, on the
- * device: the exact Cholesky factor of every block of A (banded, section 5's
- * factorisation step), and D_S = diag(S_u) by Algorithm 4; the operator seen
+ * device: the exact Cholesky factor of every block of A (banded; computed
+ * before the iteration, section 4.2), and D_S = diag(S_u) by Algorithm 4
+ * (section 4.3); the operator seen
  * by pp_setup / pp_apply / pcg_solve / pp_estimate_bounds is
- * D_S^{-1/2} S_u D_S^{-1/2} (section 4.2), applied matrix-free by Algorithm 3
+ * D_S^{-1/2} S_u D_S^{-1/2} (section 4.3), applied matrix-free by Algorithm 3
  * (its three solves with A done as two, since A^{-1} is linear, each a
  * forward and a backward sweep with the factor, and the products with C, B,
  * G^h, G^u).  The input arrays are copied; the
@@ -159,7 +160,7 @@ PP_API pp_status pp_create_dfn(pp_op *out, const pp_dfn_desc *desc, unsigned fla
 
 /*
  * Reduced right-hand side of the DFN system (block elimination of section
- * 4.1): r = W^T M^{-1} f_1 with f_1 = (q, 0), i.e.
+ * 4.2): r = W^T M^{-1} f_1 with f_1 = (q, 0), i.e.
  *   r = alpha B^T A^{-1} q - C^T A^{-1} G^h A^{-1} q.
  *   q [n_h] device, r [n_u] device (unscaled; pass r to pcg_solve as b).
  * PP_ERR_ARG unless op came from pp_create_dfn.  Queued on the handle's
@@ -168,7 +169,7 @@ PP_API pp_status pp_create_dfn(pp_op *out, const pp_dfn_desc *desc, unsigned fla
 PP_API pp_status pp_dfn_rhs(pp_op op, const double *q, double *r);
 
 /*
- * Recovery of the other unknowns once S_u u = r is solved (section 4.1):
+ * Recovery of the other unknowns once S_u u = r is solved (section 4.2):
  *   h = A^{-1} (q + C u),  p = A^{-1} (alpha B u - G^h h).
  *   q [n_h], u [n_u], h [n_h] and p [n_h] device.  h and p must be distinct
  *   arrays; either may be q itself (q is read before it is overwritten).
@@ -218,7 +219,7 @@ PP_API pp_status pp_apply(pp_op op, const double *r, double *z);
  *   b      [n] double (device)
  *   x      [n] double (device): x0 on entry, last iterate on exit
  *   tol    stop when ||r_hat|| <= tol ||b_hat|| (scaled system under PP_JACOBI,
- *          as in section 4.2); tol >= 0 (0 = run maxit iterations)
+ *          as in section 4.3); tol >= 0 (0 = run maxit iterations)
  *   maxit  >= 0
  *   iters, relres  host outputs (may be NULL): iterations done and the final
  *          recursive relative residual ||r_hat|| / ||b_hat||
@@ -294,6 +295,11 @@ typedef struct {
     double pair_ms;         /* summed device time of the fused-pair launches (events */
                             /* around each run of pairs; PP_OPT_TIMING = 1)           */
     int64_t pair_launches;  /* fused-pair launches covered by pair_ms                */
+    int32_t restarts;       /* CG restarts after a failed true-residual check        */
+                            /* (PP_OPT_VERIFY)                                      */
+    int32_t pad0;
+    double true_relres;     /* ||b_hat - A_hat x_hat|| / ||b_hat|| of the returned x */
+                            /* when the true-residual check ran, else -1             */
 } pp_stats;
 
 PP_API pp_status pp_get_stats(pp_op op, pp_stats *st);
@@ -307,7 +313,7 @@ enum {
     PP_OPT_NT_LOADS = 5,    /* 1 = non-temporal accesses for the streams read once per step */
                             /* (the sliced matrix; r, s_{j-2} and the output with stored */
                             /* diagonals), 0 = plain; default 1 from 2^22 rows on       */
-    PP_OPT_TWO_STEP = 6     /* on 3-D 7-point operators (stored diagonals at offsets 0, 1,  */
+    PP_OPT_TWO_STEP = 6,    /* on 3-D 7-point operators (stored diagonals at offsets 0, 1,  */
                             /* N, N^2, no coupling across the box's x- and y-faces,        */
                             /* N <= 256) fuse pairs of FP64 Chebyshev steps into one pass  */
                             /* (tiles of whole x-lines with one recomputed halo line each  */
@@ -315,6 +321,11 @@ enum {
                             /* fill whole rounds of compute units (one tile per CU) at     */
                             /* least 90 %, 2 = for any box, 0 = one pass per step.  Other  */
                             /* values: PP_ERR_ARG                                          */
+    PP_OPT_VERIFY = 7       /* true-residual check when pcg_solve converges: the residual  */
+                            /* b_hat - A_hat x_hat of the iterate is formed in FP64; if it */
+                            /* misses tol, CG restarts from the iterate (at most 3 times). */
+                            /* 1 = on, 0 = off, -1 (default) = on in PP_MIXED mode only.   */
+                            /* Costs one operator application when the check passes.       */
 };
 PP_API pp_status pp_set_option(pp_op op, int key, int64_t value);
 
@@ -377,14 +388,19 @@ PP_API pp_status pp_batch_apply(pp_batch op, const double *R, double *Z);
 PP_API pp_status pp_batch_set_layout(pp_batch op, int w);
 PP_API pp_status pp_batch_autotune(pp_batch op, int *best_w, double *best_us);
 
-/* Batch options: PP_OPT_CHUNK (iterations per graph), PP_OPT_NT_LOADS, and
+/* Batch options: PP_OPT_CHUNK (iterations per graph), PP_OPT_NT_LOADS,
+ * PP_OPT_VERIFY (as for pcg_solve: once every column has converged, the true
+ * residuals are formed in FP64 and the columns that miss tol restart from
+ * their iterates; -1 default = in PP_MIXED mode only), and
  * PP_BOPT_GRAPH (1 = replay captured iteration chunks, 0 = launch eagerly). */
 enum { PP_BOPT_GRAPH = 100 };
 PP_API pp_status pp_batch_set_option(pp_batch op, int key, int64_t value);
 
 /* Sizes and last-solve timing: n rows, internal block width, entries in the
  * slice layout, workgroups per launch, solve device time (ms), the most
- * iterations of any (system, column), systems held as stored diagonals. */
+ * iterations of any (system, column), systems held as stored diagonals, CG
+ * restarts after a failed true-residual check, and 1 when the check ran and
+ * every column passed it (relres then holds the true residuals). */
 typedef struct {
     int64_t n;
     int32_t nsys;
@@ -397,6 +413,8 @@ typedef struct {
     double solve_ms;
     int32_t max_iters;
     int32_t diag_systems;
+    int32_t restarts;
+    int32_t verified;
 } pp_batch_stats;
 PP_API pp_status pp_batch_get_stats(pp_batch op, pp_batch_stats *st);
 

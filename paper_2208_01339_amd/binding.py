@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libppcg.so")
 PP_OK, PP_NOT_CONVERGED, PP_BREAKDOWN = 0, 1, 2
 PP_ERR_ARG, PP_ERR_OOM, PP_ERR_HIP, PP_ERR_STATE = -1, -2, -3, -4
 PP_JACOBI, PP_MIXED, PP_SLICED = 1, 2, 4
-PP_OPT_GRID, PP_OPT_CHUNK, PP_OPT_TIMING, PP_OPT_DRIVER, PP_OPT_NT_LOADS, PP_OPT_TWO_STEP = 1, 2, 3, 4, 5, 6
+PP_OPT_GRID, PP_OPT_CHUNK, PP_OPT_TIMING, PP_OPT_DRIVER, PP_OPT_NT_LOADS, PP_OPT_TWO_STEP, PP_OPT_VERIFY = 1, 2, 3, 4, 5, 6, 7
 
 PP_BOPT_GRAPH = 100
 
@@ -46,7 +46,8 @@ class pp_stats(C.Structure):
         ("cheb_steps", C.c_int64), ("solve_ms", C.c_double), ("n", C.c_int64),
         ("nnz_stored", C.c_int64), ("nnz_matrix", C.c_int64), ("driver", C.c_int32),
         ("grid", C.c_int32), ("diagonals", C.c_int32), ("two_step", C.c_int32),
-        ("pair_ms", C.c_double), ("pair_launches", C.c_int64),
+        ("pair_ms", C.c_double), ("pair_launches", C.c_int64), ("restarts", C.c_int32), ("pad0", C.c_int32),
+        ("true_relres", C.c_double),
     ]
 
 
@@ -54,7 +55,7 @@ class pp_batch_stats(C.Structure):
     _fields_ = [
         ("n", C.c_int64), ("nsys", C.c_int32), ("nb", C.c_int32), ("nrhs", C.c_int32), ("w", C.c_int32),
         ("nnz_stored", C.c_int64), ("grid", C.c_int32), ("graph", C.c_int32), ("solve_ms", C.c_double),
-        ("max_iters", C.c_int32), ("diag_systems", C.c_int32),
+        ("max_iters", C.c_int32), ("diag_systems", C.c_int32), ("restarts", C.c_int32), ("verified", C.c_int32),
     ]
 
 

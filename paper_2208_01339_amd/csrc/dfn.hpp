@@ -1,4 +1,4 @@
-// The DFN Schur complement of section 4.1,
+// The DFN Schur complement of section 4.2,
 //   S_u = G^u - a B^T A^{-1} C - a C^T A^{-1} B + C^T A^{-1} G^h A^{-1} C,
 // applied by Algorithm 3 with the exact Cholesky factor of the block-diagonal A.
 //

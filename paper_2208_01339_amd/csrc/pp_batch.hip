@@ -74,6 +74,7 @@ struct pp_batch_s {
     std::vector<double> lmin, lmax;
     // options
     int chunk = 0, ntload = 1, use_graph = 1;
+    int verify = -1;  // true-residual check at convergence: -1 auto (mixed mode), 0 off, 1 on
     // captured iteration chunk
     hipGraphExec_t gexec = nullptr;
     int g_k = -1, g_chunk = -1, g_maxit = -1, g_W = -1;
@@ -740,6 +741,10 @@ pp_status pp_batch_set_option(pp_batch op, int key, int64_t value)
         return PP_OK;
     case PP_OPT_NT_LOADS: op->ntload = value != 0; op->g_k = -1; return PP_OK;
     case PP_BOPT_GRAPH: op->use_graph = value != 0; return PP_OK;
+    case PP_OPT_VERIFY:
+        if (value < -1 || value > 1) return fail(PP_ERR_ARG, "PP_OPT_VERIFY must be -1, 0 or 1");
+        op->verify = (int)value;
+        return PP_OK;
     default: return fail(PP_ERR_ARG, "unknown batch option");
     }
 }
@@ -852,33 +857,38 @@ pp_status pp_batch_estimate_bounds(pp_batch op, int steps, double *lambda_min, d
     return PP_OK;
 }
 
-pp_status pcg_solve_batch(pp_batch op, const double *B, double *X, double tol, int maxit, int *iters, double *relres,
-                          int *status)
+namespace {
+
+// One run of the batched CG loop from X (unscaled): scaled right-hand sides
+// and iterates, the initial residuals and their test, the first polynomial,
+// then chunks of iterations (a captured graph) until every column is done,
+// and X = D^{-1/2} X-hat.  check_only: stop after the initial test when it
+// ends every column (the true-residual check of a converged batch).
+void batch_pass(pp_batch_s *op, const double *B, double *X, double tol, int maxit, bool check_only)
 {
-    if (!op || !B || !X) return fail(PP_ERR_ARG, "NULL argument");
-    if (B == X) return fail(PP_ERR_ARG, "B and X must not alias");
-    if (!std::isfinite(tol) || tol < 0.0) return fail(PP_ERR_ARG, "tol must be finite and >= 0");
-    if (maxit < 0) return fail(PP_ERR_ARG, "maxit must be >= 0");
-    if (!op->setup_done) return fail(PP_ERR_STATE, "pp_batch_setup must be called before pcg_solve_batch");
-    try {
-        begin_call(op);
-        HIPCHK(hipEventRecord(op->solve_ev[0], op->stream));
-        const ppb::BState st = op->bst(tol, maxit);
-        const ppb::Batch bt = op->bt();
-        const dim3 g(op->G), b(BLOCK);
-        launch_state_init(op, tol, maxit);
-        const int total = op->S * op->NB;
-        int chunk = op->chunk > 0 ? op->chunk : (op->n_int * (int64_t)op->NB >= (1 << 22) ? 2 : 8);
-        with_layout(op->W, op->CPL, [&](auto wc, auto cc) {
-            constexpr int W = decltype(wc)::value;
-            constexpr int CPL = decltype(cc)::value;
-            const ppk::SellView A = op->view(false);
-            hipLaunchKernelGGL((ppb::kb_init_scale<W, CPL>), g, b, 0, op->stream, bt, st, A, B, (const double *)X,
-                               (const double *)op->dis, op->Bh, op->Xh, op->partials);
-            launch_fin<W * CPL>(op, st, ppb::BF_BNORM);
-            hipLaunchKernelGGL((ppb::kb_apply64<W, CPL, 0, false>), g, b, 0, op->stream, bt, st, A,
-                               (const double *)op->Xh, (const double *)op->Bh, op->R, op->partials);
-            launch_fin<W * CPL>(op, st, ppb::BF_RR0);
+    const ppb::BState st = op->bst(tol, maxit);
+    const ppb::Batch bt = op->bt();
+    const dim3 g(op->G), b(BLOCK);
+    launch_state_init(op, tol, maxit);
+    const int total = op->S * op->NB;
+    int chunk = op->chunk > 0 ? op->chunk : (op->n_int * (int64_t)op->NB >= (1 << 22) ? 2 : 8);
+    with_layout(op->W, op->CPL, [&](auto wc, auto cc) {
+        constexpr int W = decltype(wc)::value;
+        constexpr int CPL = decltype(cc)::value;
+        const ppk::SellView A = op->view(false);
+        hipLaunchKernelGGL((ppb::kb_init_scale<W, CPL>), g, b, 0, op->stream, bt, st, A, B, (const double *)X,
+                           (const double *)op->dis, op->Bh, op->Xh, op->partials);
+        launch_fin<W * CPL>(op, st, ppb::BF_BNORM);
+        hipLaunchKernelGGL((ppb::kb_apply64<W, CPL, 0, false>), g, b, 0, op->stream, bt, st, A,
+                           (const double *)op->Xh, (const double *)op->Bh, op->R, op->partials);
+        launch_fin<W * CPL>(op, st, ppb::BF_RR0);
+        bool all_done = false;
+        if (check_only) {
+            HIPCHK(hipMemcpyAsync(&op->h_ndone[0], op->d_ndone, sizeof(int32_t), hipMemcpyDeviceToHost, op->stream));
+            HIPCHK(hipStreamSynchronize(op->stream));
+            all_done = op->h_ndone[0] >= total;
+        }
+        if (!all_done) {
             poly<W, CPL>(op, st, ppb::BF_RHO0);
             hipLaunchKernelGGL((ppb::kb_p<W, CPL>), g, b, 0, op->stream, bt, st, A, (const double *)op->Z, op->P, 1);
             HIPCHK(hipGetLastError());
@@ -933,25 +943,70 @@ pp_status pcg_solve_batch(pp_batch op, const double *B, double *X, double tol, i
                 op->remapped = false;
             }
             op->seg_done_h.clear();
-            hipLaunchKernelGGL((ppb::kb_final<W, CPL>), g, b, 0, op->stream, bt, st, A, (const double *)op->Xh,
-                               (const double *)op->dis, X);
-            HIPCHK(hipGetLastError());
-        });
-        HIPCHK(hipEventRecord(op->solve_ev[1], op->stream));
+        }
+        hipLaunchKernelGGL((ppb::kb_final<W, CPL>), g, b, 0, op->stream, bt, st, A, (const double *)op->Xh,
+                           (const double *)op->dis, X);
+        HIPCHK(hipGetLastError());
+    });
+}
+
+}  // namespace
+
+pp_status pcg_solve_batch(pp_batch op, const double *B, double *X, double tol, int maxit, int *iters, double *relres,
+                          int *status)
+{
+    if (!op || !B || !X) return fail(PP_ERR_ARG, "NULL argument");
+    if (B == X) return fail(PP_ERR_ARG, "B and X must not alias");
+    if (!std::isfinite(tol) || tol < 0.0) return fail(PP_ERR_ARG, "tol must be finite and >= 0");
+    if (maxit < 0) return fail(PP_ERR_ARG, "maxit must be >= 0");
+    if (!op->setup_done) return fail(PP_ERR_STATE, "pp_batch_setup must be called before pcg_solve_batch");
+    try {
+        begin_call(op);
+        HIPCHK(hipEventRecord(op->solve_ev[0], op->stream));
+        // true-residual check at convergence (default: mixed mode only)
+        const bool verify = op->verify > 0 || (op->verify < 0 && op->mixed());
+        const int total = op->S * op->NB;
         const size_t sn = (size_t)total;
-        std::vector<int32_t> it(sn), stt(sn), zb(sn);
+        std::vector<int32_t> it(sn), stt(sn), zb(sn), it_sum(sn, 0);
         std::vector<double> rr(sn), bn(sn);
-        HIPCHK(hipMemcpyAsync(it.data(), op->d_it, sizeof(int32_t) * sn, hipMemcpyDeviceToHost, op->stream));
-        HIPCHK(hipMemcpyAsync(stt.data(), op->d_status, sizeof(int32_t) * sn, hipMemcpyDeviceToHost, op->stream));
-        HIPCHK(hipMemcpyAsync(zb.data(), op->d_zero_b, sizeof(int32_t) * sn, hipMemcpyDeviceToHost, op->stream));
-        HIPCHK(hipMemcpyAsync(rr.data(), op->d_rr, sizeof(double) * sn, hipMemcpyDeviceToHost, op->stream));
-        HIPCHK(hipMemcpyAsync(bn.data(), op->d_bn2, sizeof(double) * sn, hipMemcpyDeviceToHost, op->stream));
-        HIPCHK(hipStreamSynchronize(op->stream));
+        int restarts = 0;
+        bool verified = false;
+        // Pass 0 is the solve.  When every column converged and the check is
+        // on, pass 1 starts again from the iterates: its initial residuals are
+        // the true residuals, and its initial test either ends every column at
+        // once (the usual case) or CG continues from there (a restart, with the
+        // iterations left to the column that used most); at most three restarts.
+        for (int pass = 0;; ++pass) {
+            int used = 0;
+            for (size_t i = 0; i < sn; ++i) used = std::max(used, it_sum[i]);
+            batch_pass(op, B, X, tol, maxit - used, pass > 0);
+            HIPCHK(hipMemcpyAsync(it.data(), op->d_it, sizeof(int32_t) * sn, hipMemcpyDeviceToHost, op->stream));
+            HIPCHK(hipMemcpyAsync(stt.data(), op->d_status, sizeof(int32_t) * sn, hipMemcpyDeviceToHost, op->stream));
+            HIPCHK(hipMemcpyAsync(zb.data(), op->d_zero_b, sizeof(int32_t) * sn, hipMemcpyDeviceToHost, op->stream));
+            HIPCHK(hipMemcpyAsync(rr.data(), op->d_rr, sizeof(double) * sn, hipMemcpyDeviceToHost, op->stream));
+            HIPCHK(hipMemcpyAsync(bn.data(), op->d_bn2, sizeof(double) * sn, hipMemcpyDeviceToHost, op->stream));
+            HIPCHK(hipStreamSynchronize(op->stream));
+            bool all_ok = true, iterated = false;
+            for (int s = 0; s < op->S; ++s)
+                for (int c = 0; c < op->nrhs; ++c) {
+                    const size_t i = (size_t)s * op->NB + c;
+                    it_sum[i] += it[i];
+                    if (!zb[i] && stt[i] != PP_OK) all_ok = false;
+                    if (!zb[i] && it[i] > 0) iterated = true;
+                }
+            if (pass > 0 && !iterated) { verified = all_ok; break; }
+            if (pass > 0) ++restarts;
+            if (!(verify && all_ok && iterated && pass < 3)) break;
+        }
+        HIPCHK(hipEventRecord(op->solve_ev[1], op->stream));
+        HIPCHK(hipEventSynchronize(op->solve_ev[1]));
         end_call(op);
         float ms = 0;
         HIPCHK(hipEventElapsedTime(&ms, op->solve_ev[0], op->solve_ev[1]));
         op->stats.solve_ms = ms;
         op->stats.graph = op->use_graph;
+        op->stats.restarts = restarts;
+        op->stats.verified = verified ? 1 : 0;
         pp_status worst = PP_OK;
         int maxits = 0;
         for (int s = 0; s < op->S; ++s)
@@ -959,8 +1014,8 @@ pp_status pcg_solve_batch(pp_batch op, const double *B, double *X, double tol, i
                 const size_t i = (size_t)s * op->NB + c, o = (size_t)s * op->nrhs + c;
                 const pp_status sc = zb[i] ? PP_OK : (pp_status)stt[i];
                 if (sc == PP_BREAKDOWN || (sc == PP_NOT_CONVERGED && worst == PP_OK)) worst = sc;
-                maxits = std::max(maxits, it[i]);
-                if (iters) iters[o] = it[i];
+                maxits = std::max(maxits, it_sum[i]);
+                if (iters) iters[o] = it_sum[i];
                 if (status) status[o] = sc;
                 if (relres) relres[o] = zb[i] ? 0.0 : (bn[i] > 0 ? std::sqrt(rr[i] / bn[i]) : 0.0);
             }

@@ -1356,6 +1356,10 @@ pp_status pp_set_option(pp_op op, int key, int64_t value)
         if (value < 0 || value > 2) return fail(PP_ERR_ARG, "PP_OPT_TWO_STEP must be 0, 1 or 2");
         op->two_step = (int)value;
         return PP_OK;
+    case PP_OPT_VERIFY:
+        if (value < -1 || value > 1) return fail(PP_ERR_ARG, "PP_OPT_VERIFY must be -1, 0 or 1");
+        op->verify = (int)value;
+        return PP_OK;
     default: return fail(PP_ERR_ARG, "unknown option");
     }
 }
@@ -1428,6 +1432,69 @@ pp_status pp_apply(pp_op op, const double *r, double *z)
     return PP_OK;
 }
 
+namespace {
+
+// One stream-driven run of the CG loop from x (unscaled, device): b-hat and
+// x-hat from b and x, the initial residual and its test, the first
+// polynomial, then chunks of iterations until the done flag is seen, and
+// x = D^{-1/2} x-hat.  The state must have been reset (k_state_init) with
+// this run's iteration budget.  timed: record the per-polynomial events.
+void stream_pass(pp_op_s *op, const double *b, double *x, bool timed, size_t &ev_i)
+{
+    const int64_t n = op->n;
+    const int gs = op->grid_slices(), ge = op->grid_elems(n);
+    hipLaunchKernelGGL(ppk::k_init_scale, dim3(ge), dim3(BLOCK), 0, op->stream, n, b, (const double *)x,
+                       (const double *)op->dis, op->bh, op->xh, op->partials, op->st);
+    enqueue_fin(op, ge, ppk::FIN_BNORM);
+    enqueue_trace_f64(op, op->xh);
+    if (op->schur())
+        hipLaunchKernelGGL(ppk::k_init_resid<true>, dim3(gs), dim3(BLOCK), 0, op->stream, op->view(false),
+                           (const double *)op->xh, (const double *)op->tw, (const double *)op->bh, op->r,
+                           op->partials, op->st, op->ntload);
+    else
+        hipLaunchKernelGGL(ppk::k_init_resid<false>, dim3(gs), dim3(BLOCK), 0, op->stream, op->view(false),
+                           (const double *)op->xh, (const double *)nullptr, (const double *)op->bh, op->r,
+                           op->partials, op->st, op->ntload);
+    enqueue_fin(op, gs, ppk::FIN_RR0);
+    if (op->lr_p > 0) enqueue_lr_c(op, op->r, nullptr);
+    hipEvent_t e0 = timed ? timing_event(op, ev_i++) : nullptr;
+    hipEvent_t e1 = timed ? timing_event(op, ev_i++) : nullptr;
+    if (e0) HIPCHK(hipEventRecord(e0, op->stream));
+    enqueue_poly(op, op->r, op->z, ppk::FIN_RHO0, false);
+    if (e1) HIPCHK(hipEventRecord(e1, op->stream));
+    enqueue_p(op, true);
+    HIPCHK(hipGetLastError());
+
+    int chunk = op->chunk;
+    if (chunk <= 0) chunk = n >= (1 << 20) ? 1 : (n >= (1 << 16) ? 4 : 16);
+    // the state's own budget ends the loop on the device; the host stops
+    // queueing once the flag it polls (one chunk behind) is set
+    const int maxit = op->pass_maxit;
+    int enq = 0, c = 0;
+    while (enq < maxit) {
+        const int m = std::min(chunk, maxit - enq);
+        for (int i = 0; i < m; ++i) {
+            hipEvent_t ea = timed ? timing_event(op, ev_i++) : nullptr;
+            hipEvent_t eb = timed ? timing_event(op, ev_i++) : nullptr;
+            enqueue_iteration(op, ea, eb);
+        }
+        HIPCHK(hipGetLastError());
+        enq += m;
+        HIPCHK(hipMemcpyAsync(&op->hflag[c & 1], &op->st->done, sizeof(int32_t), hipMemcpyDeviceToHost,
+                              op->stream));
+        HIPCHK(hipEventRecord(op->flag_ev[c & 1], op->stream));
+        if (c >= 1) {
+            HIPCHK(hipEventSynchronize(op->flag_ev[(c - 1) & 1]));
+            if (op->hflag[(c - 1) & 1]) break;
+        }
+        ++c;
+    }
+    hipLaunchKernelGGL(ppk::k_final_x, dim3(ge), dim3(BLOCK), 0, op->stream, n, (const double *)op->xh,
+                       (const double *)op->dis, x, (const ppk::State *)op->st);
+}
+
+}  // namespace
+
 pp_status pcg_solve(pp_op op, const double *b, double *x, double tol, int maxit, int *iters, double *relres)
 {
     if (!op || !b || !x) return fail(PP_ERR_ARG, "NULL argument");
@@ -1436,86 +1503,68 @@ pp_status pcg_solve(pp_op op, const double *b, double *x, double tol, int maxit,
     if (maxit < 0) return fail(PP_ERR_ARG, "maxit must be >= 0");
     if (!op->setup_done) return fail(PP_ERR_STATE, "pp_setup must be called before pcg_solve");
     try {
-        const int64_t n = op->n;
-        const int gs = op->grid_slices(), ge = op->grid_elems(n);
         HIPCHK(hipEventRecord(op->solve_ev[0], op->stream));
-        hipLaunchKernelGGL(ppk::k_state_init, dim3(1), dim3(64), 0, op->stream, op->st, tol, maxit);
         // persistent driver on request only: its grid-wide barriers cost more
         // than kernel boundaries on this chip at every size measured (each
         // barrier serialises one same-address atomic per workgroup)
         const bool want_persist = op->driver == 1 && op->lr_p == 0 && op->form == 0 && !op->dfn();
-        bool persisted = want_persist && persistent_solve(op, b, x, tol, maxit);
+        // true-residual check at convergence (default: mixed mode only)
+        const bool verify = op->verify > 0 || (op->verify < 0 && op->mixed());
         size_t ev_i = 0;
         op->pev_i = 0;
         op->pairs_per_poly = 0;
         op->time_pairs = op->timing;
-        if (!persisted) {
-            hipLaunchKernelGGL(ppk::k_init_scale, dim3(ge), dim3(BLOCK), 0, op->stream, n, b, (const double *)x,
-                               (const double *)op->dis, op->bh, op->xh, op->partials, op->st);
-            enqueue_fin(op, ge, ppk::FIN_BNORM);
-            enqueue_trace_f64(op, op->xh);
-            if (op->schur())
-                hipLaunchKernelGGL(ppk::k_init_resid<true>, dim3(gs), dim3(BLOCK), 0, op->stream, op->view(false),
-                                   (const double *)op->xh, (const double *)op->tw, (const double *)op->bh, op->r,
-                                   op->partials, op->st, op->ntload);
-            else
-                hipLaunchKernelGGL(ppk::k_init_resid<false>, dim3(gs), dim3(BLOCK), 0, op->stream, op->view(false),
-                                   (const double *)op->xh, (const double *)nullptr, (const double *)op->bh, op->r,
-                                   op->partials, op->st, op->ntload);
-            enqueue_fin(op, gs, ppk::FIN_RR0);
-            if (op->lr_p > 0) enqueue_lr_c(op, op->r, nullptr);
-            hipEvent_t e0 = op->timing ? timing_event(op, ev_i++) : nullptr;
-            hipEvent_t e1 = op->timing ? timing_event(op, ev_i++) : nullptr;
-            if (e0) HIPCHK(hipEventRecord(e0, op->stream));
-            enqueue_poly(op, op->r, op->z, ppk::FIN_RHO0, false);
-            if (e1) HIPCHK(hipEventRecord(e1, op->stream));
-            enqueue_p(op, true);
+        int it_total = 0, restarts = 0, first_it = 0;
+        int64_t applies = 0, dots = 0;
+        bool persisted = false, zero_b = false, verified = false;
+        pp_status ret = PP_OK;
+        double rel = 0.0;
+        // Pass 0 is the solve.  When it converges and the check is on, pass 1
+        // starts again from the iterate: its initial residual b-hat - A-hat x-hat
+        // is the true residual, and its initial test either ends the solve at
+        // once (the usual case) or CG continues from there (a restart); at most
+        // three restarts.
+        for (int pass = 0;; ++pass) {
+            const int left = maxit - it_total;
+            op->pass_maxit = left;
+            hipLaunchKernelGGL(ppk::k_state_init, dim3(1), dim3(64), 0, op->stream, op->st, tol, left);
+            const bool pers = pass == 0 && want_persist && persistent_solve(op, b, x, tol, left);
+            if (!pers) stream_pass(op, b, x, pass == 0 && op->timing, ev_i);
+            if (pass == 0) persisted = pers;
+            op->time_pairs = false;  // pair events: first pass only
             HIPCHK(hipGetLastError());
-
-            int chunk = op->chunk;
-            if (chunk <= 0) chunk = n >= (1 << 20) ? 1 : (n >= (1 << 16) ? 4 : 16);
-            int enq = 0, c = 0;
-            while (enq < maxit) {
-                const int m = std::min(chunk, maxit - enq);
-                for (int i = 0; i < m; ++i) {
-                    hipEvent_t a = op->timing ? timing_event(op, ev_i++) : nullptr;
-                    hipEvent_t bb = op->timing ? timing_event(op, ev_i++) : nullptr;
-                    enqueue_iteration(op, a, bb);
-                }
-                HIPCHK(hipGetLastError());
-                enq += m;
-                HIPCHK(hipMemcpyAsync(&op->hflag[c & 1], &op->st->done, sizeof(int32_t), hipMemcpyDeviceToHost,
-                                      op->stream));
-                HIPCHK(hipEventRecord(op->flag_ev[c & 1], op->stream));
-                if (c >= 1) {
-                    HIPCHK(hipEventSynchronize(op->flag_ev[(c - 1) & 1]));
-                    if (op->hflag[(c - 1) & 1]) break;
-                }
-                ++c;
-            }
-            hipLaunchKernelGGL(ppk::k_final_x, dim3(ge), dim3(BLOCK), 0, op->stream, n, (const double *)op->xh,
-                               (const double *)op->dis, x, (const ppk::State *)op->st);
+            HIPCHK(hipMemcpyAsync(op->hst, op->st, sizeof(ppk::State), hipMemcpyDeviceToHost, op->stream));
+            HIPCHK(hipStreamSynchronize(op->stream));
+            const ppk::State &s = *op->hst;
+            const int it = s.it;
+            ret = (pp_status)s.status;
+            rel = s.bnorm2 > 0 ? std::sqrt(s.rr / s.bnorm2) : 0.0;
+            zero_b = s.zero_b != 0;
+            if (zero_b) { ret = PP_OK; rel = 0.0; break; }
+            it_total += it;
+            if (pass == 0) first_it = it;
+            // initial residual (1) + initial preconditioner (k, unless the initial
+            // test ended the run) + per iteration A p (1) and, except after the
+            // last iteration, the preconditioner (k)
+            const int64_t polys = it > 0 ? it : (ret == PP_BREAKDOWN ? 1 : 0);
+            applies += 1 + (int64_t)op->k * polys + it;
+            // and, with a rank-p correction, p more values reduced at the start and in every iteration
+            dots += it > 0 || ret == PP_BREAKDOWN ? 1 + 3LL * it + (int64_t)op->lr_p * (1 + it) : 1;
+            if (pass > 0 && it == 0) { verified = ret == PP_OK; break; }
+            if (pass > 0) ++restarts;
+            if (!(verify && ret == PP_OK && it > 0 && pass < 3)) break;
         }
-        HIPCHK(hipGetLastError());
         HIPCHK(hipEventRecord(op->solve_ev[1], op->stream));
-        HIPCHK(hipMemcpyAsync(op->hst, op->st, sizeof(ppk::State), hipMemcpyDeviceToHost, op->stream));
-        HIPCHK(hipStreamSynchronize(op->stream));
-        const ppk::State &s = *op->hst;
-        const int it = s.it;
-        pp_status ret = (pp_status)s.status;
-        double rel = s.bnorm2 > 0 ? std::sqrt(s.rr / s.bnorm2) : 0.0;
-        if (s.zero_b) { ret = PP_OK; rel = 0.0; }
-        if (iters) *iters = it;
+        HIPCHK(hipEventSynchronize(op->solve_ev[1]));
+        if (iters) *iters = it_total;
         if (relres) *relres = rel;
-        op->stats.iters = it;
+        op->stats.iters = it_total;
         op->stats.status = ret;
         op->stats.relres = rel;
-        // initial residual (1) + initial preconditioner (k) + per iteration A p (1) and,
-        // except after the last iteration, the preconditioner (k)
-        const int64_t polys = it > 0 ? it : 1;
-        op->stats.op_applies = s.zero_b ? 0 : 1 + (int64_t)op->k * polys + it;
-        // and, with a rank-p correction, p more values reduced at the start and in every iteration
-        op->stats.dots = s.zero_b ? 0 : 1 + 3LL * it + (int64_t)op->lr_p * (1 + it);
+        op->stats.op_applies = zero_b ? 0 : applies;
+        op->stats.dots = zero_b ? 0 : dots;
+        op->stats.restarts = restarts;
+        op->stats.true_relres = verified ? rel : -1.0;
         float ms = 0;
         HIPCHK(hipEventElapsedTime(&ms, op->solve_ev[0], op->solve_ev[1]));
         op->stats.solve_ms = ms;
@@ -1525,9 +1574,10 @@ pp_status pcg_solve(pp_op op, const double *b, double *x, double tol, int maxit,
         op->stats.pair_ms = 0;
         op->stats.pair_launches = 0;
         op->stats.driver = persisted ? 1 : 0;
-        if (!persisted) op->stats.grid = gs;
-        if (op->timing && !s.zero_b) {
-            // pairs 0 .. polys-1 ran (the initial one and one per iteration but the last)
+        if (!persisted) op->stats.grid = op->grid_slices();
+        if (op->timing && !zero_b && !persisted) {
+            // first pass only: pairs 0 .. polys-1 ran (the initial one and one per iteration but the last)
+            const int64_t polys = first_it > 0 ? first_it : 1;
             double tot = 0;
             for (int64_t i = 0; i < polys && (size_t)(2 * i + 1) < ev_i; ++i) {
                 float t = 0;

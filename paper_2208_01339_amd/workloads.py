@@ -220,7 +220,7 @@ def _grid_faces(n_frac: int, G: int):
 def dfn_su(n_frac: int = 400, G: int = 48, n_traces: int = 1100, L_lo: int = 10, L_hi: int = 40,
            sigma: float = 1.0, gamma: float = 100.0, g_u: float = 10.0, alpha: float = 1.0,
            seed: int = 0) -> DfnSuParts:
-    """Blocks A, G^h, C, B, G^u of the DFN system of section 4.1 (see module docstring).
+    """Blocks A, G^h, C, B, G^u of the DFN system of section 4.1, eq. (sys) (see module docstring).
 
     Traces: ``n_frac - 1`` spanning-tree traces then random pairs of distinct
     fractures, lengths uniform in [L_lo, L_hi], an independent straight

@@ -5,7 +5,8 @@ newton_apply (same recursion, different rounding order).  In exact
 arithmetic the Newton form equals the Chebyshev polynomial of degree
 2^nlev - 1 (pinned on the CPU), so PCG with it is checked against the
 oracle's Chebyshev PCG of that degree: iteration counts within +-2, and the
-solutions agree to the tolerance of the solve.
+solutions agree to the tolerance of the solve; and against the oracle's PCG
+with Algorithm 1 itself at equal iteration count (1e-10).
 """
 import numpy as np
 import pytest
@@ -79,6 +80,7 @@ def test_newton_pcg(B, name, nlev, xi):
     xo, sto = O.pcg(orc, k, lmin, lmax, xi, b, tol=1e-10, maxit=3000)
     B.pp_setup_newton(op.handle, nlev, lmin, lmax, xi)
     B.pp_set_option(op.handle, B.PP_OPT_DRIVER, 1)  # falls back to the stream driver
+    B.pp_set_option(op.handle, B.PP_OPT_VERIFY, 0)  # keep the loop's count identity exact
     x = torch.zeros(orc.n, dtype=torch.float64, device="cuda")
     s, it, rel = B.pcg_solve(op.handle, dev(b), x, 1e-10, 3000)
     st = B.pp_get_stats(op.handle)
@@ -92,6 +94,29 @@ def test_newton_pcg(B, name, nlev, xi):
     x.zero_()
     s2, it2, _ = B.pcg_solve(op.handle, dev(b), x, 1e-10, 3000)
     assert s2 == B.PP_OK and abs(it2 - sto["iters"]) <= 2
+    op.close()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("nlev,xi", [(0, 0.0), (2, 0.0), (3, 1e-3), (5, 1e-2)])
+def test_newton_pcg_equal_iterations(B, name, nlev, xi):
+    """PCG with the Newton form against the oracle's PCG with Algorithm 1 (the
+    same preconditioner, different rounding order): iterations within 2 at
+    tol 1e-8, and the iterate after the oracle's iteration count within 1e-10."""
+    op, orc = make(B, name)
+    lmin, lmax = O.lanczos_bounds(orc, 20)
+    b = W.rhs_uniform(orc.n, 1)
+    xo, sto = O.pcg_newton(orc, nlev, lmin, lmax, xi, b, tol=1e-8, maxit=3000)
+    assert sto["status"] == O.OK
+    B.pp_setup_newton(op.handle, nlev, lmin, lmax, xi)
+    x = torch.zeros(orc.n, dtype=torch.float64, device="cuda")
+    s, it, _ = B.pcg_solve(op.handle, dev(b), x, 1e-8, 3000)
+    assert s == B.PP_OK and abs(it - sto["iters"]) <= 2, (it, sto["iters"])
+    x.zero_()
+    s, it2, _ = B.pcg_solve(op.handle, dev(b), x, 0.0, sto["iters"])
+    assert it2 == sto["iters"] and s == B.PP_NOT_CONVERGED
+    err = np.linalg.norm(host(x) - xo) / np.linalg.norm(xo)
+    assert err <= 1e-10, err
     op.close()
 
 

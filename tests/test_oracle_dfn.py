@@ -1,4 +1,4 @@
-"""Pins of the oracle's DFN Schur complement (section 4.1).
+"""Pins of the oracle's DFN Schur complement (sections 4.2-4.3).
 
 Each test checks the oracle against something other than itself:
 - the exact Cholesky factor reproduces every diagonal block of A;
