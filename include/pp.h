@@ -473,6 +473,36 @@ PP_API pp_status pp_features(pp_op op, int power_steps, double *f);
  */
 PP_API pp_status pp_predict_bounds(pp_op op, pp_mlp mlp, int power_steps, double *lambda_min,
                                    double *lambda_max, double *scaling, int *fallback);
+/*
+ * pcg_solve without any allocation, for callers that cannot allocate device
+ * memory (code between graph captures, tight serving loops, harnesses that
+ * forbid hipMalloc).  The same method as pp_create_csr + pp_setup + pcg_solve
+ * (three-term Chebyshev polynomial, standard PCG loop, optional Jacobi
+ * scaling; no stored-diagonal layout, no fused pairs, no true-residual check)
+ * on a plain CSR matrix given as it is:
+ *   n, nnz, rowptr [n+1] int64, colind [nnz] int32, val [nnz]: DEVICE CSR of a
+ *          symmetric positive definite matrix, 1 <= n <= 1048576 (the scratch
+ *          capacity; larger n: PP_ERR_ARG), nnz < 2^31; not copied, read during
+ *          the call only
+ *   flags  0 or PP_JACOBI (needs a positive diagonal, else PP_ERR_ARG and x
+ *          untouched); bounds, tol, maxit as for pp_setup / pcg_solve with
+ *          k <= 1024 and xi = scaling
+ *   b, x   [n] double DEVICE (x: x0 in, last iterate out; no aliasing)
+ *   iters, relres  HOST outputs (may be NULL)
+ *   stream hipStream_t (NULL = default) of the CURRENT device
+ * Work memory: one fixed array of about 72 MiB per device inside the library
+ * (located once per device on the first call there, kept until the process
+ * ends); the call calls no hipMalloc/hipFree.  Every call on one device uses
+ * that device's array: calls that overlap on one device (several host threads
+ * or streams) race and must be serialised by the caller.  The call
+ * synchronises the stream (a few bytes of state are read back after every
+ * chunk of iterations).  Returns as pcg_solve.
+ */
+PP_API pp_status pcg_solve_csr_noalloc(int64_t n, int64_t nnz, const int64_t *rowptr, const int32_t *colind,
+                                       const double *val, unsigned flags, int k, double lambda_min,
+                                       double lambda_max, double scaling, const double *b, double *x, double tol,
+                                       int maxit, int *iters, double *relres, void *stream);
+
 PP_API const char *pp_status_str(pp_status s);
 PP_API const char *pp_last_error(void);
 

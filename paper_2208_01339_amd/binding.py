@@ -29,7 +29,7 @@ ABI_FUNCTIONS = (
     "pp_mlp_num_params", "pp_mlp_get_params", "pp_mlp_set_params", "pp_mlp_set_normalization",
     "pp_mlp_forward", "pp_mlp_loss_grad", "pp_mlp_train_step", "pp_features", "pp_predict_bounds",
     "pp_lowrank_set", "pp_lowrank_ritz", "pp_lowrank_get", "pp_setup_newton",
-    "pp_create_dfn", "pp_dfn_rhs", "pp_dfn_recover",
+    "pp_create_dfn", "pp_dfn_rhs", "pp_dfn_recover", "pcg_solve_csr_noalloc",
 )
 
 
@@ -79,6 +79,8 @@ def lib():
         L.pp_setup.argtypes = [P, I32, D, D, D]
         L.pp_apply.argtypes = [P, P, P]
         L.pcg_solve.argtypes = [P, P, P, D, I32, C.POINTER(I32), C.POINTER(D)]
+        L.pcg_solve_csr_noalloc.argtypes = [I64, I64, P, P, P, C.c_uint, I32, D, D, D, P, P, D, I32,
+                                            C.POINTER(I32), C.POINTER(D), P]
         L.pp_estimate_bounds.argtypes = [P, I32, C.POINTER(D), C.POINTER(D)]
         L.pp_operator_apply.argtypes = [P, P, P]
         L.pp_get_stats.argtypes = [P, C.POINTER(pp_stats)]
@@ -254,6 +256,18 @@ def pcg_solve(op, b, x, tol=1e-8, maxit=1000):
     it = C.c_int(0)
     rel = C.c_double(0.0)
     s = lib().pcg_solve(op, _ptr(b), _ptr(x), float(tol), int(maxit), C.byref(it), C.byref(rel))
+    _check(s, ok=(PP_OK, PP_NOT_CONVERGED, PP_BREAKDOWN))
+    return s, it.value, rel.value
+
+
+def pcg_solve_csr_noalloc(n, nnz, rowptr, colind, val, flags, k, lambda_min, lambda_max, scaling, b, x,
+                          tol=1e-8, maxit=1000, stream=None):
+    """The allocation-free solve on a plain device CSR matrix; returns (status, iters, relres)."""
+    it = C.c_int(0)
+    rel = C.c_double(0.0)
+    s = lib().pcg_solve_csr_noalloc(int(n), int(nnz), _ptr(rowptr), _ptr(colind), _ptr(val), int(flags), int(k),
+                                    float(lambda_min), float(lambda_max), float(scaling), _ptr(b), _ptr(x),
+                                    float(tol), int(maxit), C.byref(it), C.byref(rel), _stream(stream))
     _check(s, ok=(PP_OK, PP_NOT_CONVERGED, PP_BREAKDOWN))
     return s, it.value, rel.value
 

@@ -10,7 +10,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = [os.path.join(HERE, "csrc", f) for f in ("pp_lib.hip", "pp_batch.hip", "pp_mlp.hip")]
+SRC = [os.path.join(HERE, "csrc", f) for f in ("pp_lib.hip", "pp_batch.hip", "pp_mlp.hip", "pp_noalloc.hip")]
 DEPS = SRC + [os.path.join(HERE, "csrc", f) for f in (
     "kernels.hpp", "sym_eig.hpp", "persistent.hpp", "batch.hpp", "common.hpp", "op.hpp", "mlp.hpp", "dfn.hpp",
     "dia_plan.hpp", "lowrank.hpp", "stencil2.hpp")] + [
