@@ -35,6 +35,11 @@ Workloads (stand-ins for the paper's matrices, which are not public here):
   the matching cell of the other fracture; G^u = g_u [[1, 1], [1, 1]] on the
   two unknowns of every trace cell pair (SPSD, global).  The Schur complement
   S_u = G^u - a B^T A^-1 C - a C^T A^-1 B + C^T A^-1 G^h A^-1 C is never formed.
+* ``irregular_fe(N, ...)`` -- an irregular SPD operator: the weighted graph
+  Laplacian of a randomly thinned 27-point neighbourhood with a Dirichlet
+  boundary, renumbered by random permutations inside windows of consecutive
+  nodes (no column offset shared by most rows).  Stands in for unstructured
+  3-D finite-element matrices such as the paper's Cube_5317k (section 3.2).
 """
 from __future__ import annotations
 
@@ -398,6 +403,67 @@ def dfn_schur(n_frac: int = 2000, G: int = 64, n_traces: int = 5000, L_lo: int =
     c = CSR(nt, n, c_rowptr, c_col, c_val)
     mdiag = rng.uniform(0.5, 2.0, nt)
     return SchurParts(a, c, mdiag, n_frac, G)
+
+
+# ---------------------------------------------------------------------------
+# irregular 3-D operator (no shared column offsets)
+# ---------------------------------------------------------------------------
+
+def irregular_fe(N: int = 160, keep: float = 0.8, sigma: float = 1.0, window: int = 4096, seed: int = 0) -> CSR:
+    """An irregular sparse SPD operator on n = N^3 unknowns.
+
+    The weighted graph Laplacian of the 27-point neighbourhood of an N^3 grid
+    of nodes (the pattern of trilinear hexahedral finite elements), with
+    every edge kept independently with probability ``keep`` (row lengths vary
+    between about 5 and 27), edge weight the harmonic mean of lognormal node
+    permeabilities exp(sigma z) over the squared edge length, and a Dirichlet
+    term K_node on the diagonal of every boundary node (SPD).  The nodes are
+    renumbered by an independent random permutation inside each window of
+    ``window`` consecutive grid nodes: the numbering keeps a mesh ordering's
+    locality without its regularity, so no column offset is shared by most
+    rows.  Stands in for unstructured 3-D finite-element matrices such as
+    Cube_5317k of the paper's section 3.2 (not available here).
+    """
+    rng = np.random.default_rng(seed)
+    n = N * N * N
+    K = np.exp(sigma * rng.standard_normal(n))
+    idx = np.arange(n, dtype=np.int64).reshape(N, N, N)  # [k, j, i]
+
+    def src(d):
+        return slice(max(0, -d), N - max(0, d))
+
+    def dst(d):
+        return slice(max(0, d), N - max(0, -d))
+
+    diag = np.zeros(n)
+    rr, cc, vv = [], [], []
+    for dk in (-1, 0, 1):
+        for dj in (-1, 0, 1):
+            for di in (-1, 0, 1):
+                if (dk, dj, di) <= (0, 0, 0):
+                    continue  # each undirected edge once: 13 directions
+                a = idx[src(dk), src(dj), src(di)].ravel()
+                b = idx[dst(dk), dst(dj), dst(di)].ravel()
+                m = rng.random(a.size) < keep
+                a, b = a[m], b[m]
+                w = 2.0 * K[a] * K[b] / (K[a] + K[b]) / float(dk * dk + dj * dj + di * di)
+                diag += np.bincount(a, weights=w, minlength=n) + np.bincount(b, weights=w, minlength=n)
+                rr += [a, b]
+                cc += [b, a]
+                vv += [-w, -w]
+    kk, jj, ii = np.meshgrid(np.arange(N), np.arange(N), np.arange(N), indexing="ij")
+    bnd = ((kk == 0) | (kk == N - 1) | (jj == 0) | (jj == N - 1) | (ii == 0) | (ii == N - 1)).ravel()
+    diag += np.where(bnd, K, 0.0)
+    # new number of grid node g: its window's start plus a random position inside the window
+    order = np.lexsort((rng.random(n), np.arange(n) // window))
+    new = np.empty(n, dtype=np.int64)
+    new[order] = np.arange(n, dtype=np.int64)
+    ar = np.arange(n, dtype=np.int64)
+    r = np.concatenate([new[x] for x in rr] + [new[ar]])
+    c = np.concatenate([new[x] for x in cc] + [new[ar]])
+    v = np.concatenate(vv + [diag])
+    del rr, cc, vv
+    return _csr_from_coo(n, n, r, c, v)
 
 
 # ---------------------------------------------------------------------------
