@@ -240,8 +240,11 @@ def run_dfn_su(args, B, W, torch, dev):
     mb_rel = float(np.linalg.norm(mb) / np.linalg.norm(q.cpu().numpy()))
     lowrank = None
     if not args.no_lowrank:
-        th = B.pp_lowrank_ritz(h, 64, 1)
+        # the leftmost eigenvector from 24 Lanczos steps on the degree-31 preconditioner
         B.pp_setup(h, 31, lmin, lmax, xi)
+        B.pp_set_option(h, B.PP_OPT_RITZ, 1)
+        th = B.pp_lowrank_ritz(h, 24, 1)
+        _, res = B.pp_lowrank_info(h)
         u.zero_()
         torch.cuda.synchronize()
         s0 = time.perf_counter()
@@ -249,10 +252,12 @@ def run_dfn_su(args, B, W, torch, dev):
         torch.cuda.synchronize()
         st = B.pp_get_stats(h)
         lowrank = dict(k=31, rank=1, iters=it, s_per_solve=time.perf_counter() - s0, op_applies=st["op_applies"],
-                       dots=st["dots"], ritz_value=float(th[0]), status=B.pp_status_str(status))
-        log("dfn S_u k=31 rank-one correction: %d iters, %d S_u applications, %d dots"
-            % (it, st["op_applies"], st["dots"]))
+                       dots=st["dots"], ritz_value=float(th[0]), ritz_residual=float(res[0]),
+                       ritz="24 Lanczos steps on p_31(S-hat)", status=B.pp_status_str(status))
+        log("dfn S_u k=31 rank-one correction: %d iters, %d S_u applications, %d dots (Ritz residual %.1e)"
+            % (it, st["op_applies"], st["dots"], res[0]))
         B.pp_lowrank_set(h, 0)
+        B.pp_set_option(h, B.PP_OPT_RITZ, 0)
     # factor bytes per application: two solves, each a forward and a backward sweep over the
     # step-ordered coefficients (G doubles per row) plus 1/L(i,i)^2 in the forward sweep
     fbytes = 4 * P.n_h * P.grid * 8 + 2 * P.n_h * 8
@@ -565,9 +570,15 @@ def run_cpu_baseline(args, a, b, lmin, lmax, kc, gpu_applies):
     return cpu
 
 
-def lowrank_leg(B, torch, h, bd, x, k, lmin, lmax, tol, maxit, ranks=(1, 4), xis=(0.0, 1e-2), steps=64):
-    """PCG with the spectral low-rank correction (section 3.1) from Ritz vectors of `steps`
-    Lanczos steps, against the same solve without it; one timed solve each."""
+def lowrank_leg(B, torch, h, bd, x, k, lmin, lmax, tol, maxit, ranks=(1, 4), xis=(0.0, 1e-2), steps=None,
+                ritz="poly"):
+    """PCG with the spectral low-rank correction (section 3.1) against the same solve without
+    it; one timed solve each.  Ritz vectors: ritz="poly" from 24 Lanczos steps on the
+    preconditioner p_k(A-hat) with full reorthogonalisation (PP_OPT_RITZ = 1), "lanczos"
+    from 64 plain Lanczos steps on A-hat; their relative residuals are reported."""
+    if steps is None:
+        steps = 24 if ritz == "poly" else 64
+    B.pp_set_option(h, B.PP_OPT_RITZ, 1 if ritz == "poly" else 0)
     def solve():
         x.zero_()
         torch.cuda.synchronize()
@@ -586,14 +597,17 @@ def lowrank_leg(B, torch, h, bd, x, k, lmin, lmax, tol, maxit, ranks=(1, 4), xis
             tr = time.perf_counter()
             th = B.pp_lowrank_ritz(h, steps, p)
             tr = time.perf_counter() - tr
+            _, res = B.pp_lowrank_info(h)
             solve()
             t1, it1, s1 = solve()
-            rows.append(dict(xi=xi, rank=p, ritz_steps=steps, ritz_s=round(tr, 4), ritz_values=[float(v) for v in th],
+            rows.append(dict(xi=xi, rank=p, ritz=ritz, ritz_steps=steps, ritz_s=round(tr, 4),
+                             ritz_values=[float(v) for v in th], ritz_residuals=[float(v) for v in res],
                              iters=it1, s_per_solve=round(t1, 4), status=s1, iters_without=it0,
                              s_without=round(t0, 4)))
-            log("lowrank k=%d xi=%g rank %d: %d iters %.3f s (without: %d iters %.3f s), Ritz %.3f s"
-                % (k, xi, p, it1, t1, it0, t0, tr))
+            log("lowrank (%s) k=%d xi=%g rank %d: %d iters %.3f s (without: %d iters %.3f s), Ritz %.3f s, "
+                "residuals %s" % (ritz, k, xi, p, it1, t1, it0, t0, tr, " ".join("%.1e" % v for v in res)))
     B.pp_lowrank_set(h, 0)
+    B.pp_set_option(h, B.PP_OPT_RITZ, 0)
     return rows
 
 
@@ -905,7 +919,9 @@ def main():
 
     lowrank = None
     if not args.no_lowrank:
-        lowrank = {"hetero256": lowrank_leg(B, torch, h, bd, x, kh, lmin, lmax, args.tol, args.maxit)}
+        lowrank = {"hetero256": lowrank_leg(B, torch, h, bd, x, kh, lmin, lmax, args.tol, args.maxit),
+                   "hetero256_lanczos64": lowrank_leg(B, torch, h, bd, x, kh, lmin, lmax, args.tol, args.maxit,
+                                                      ranks=(1,), xis=(0.0,), ritz="lanczos")}
         B.pp_setup(h, kh, lmin, lmax, args.xi)
         # Poisson 32^3 (degree 10): 20 Lanczos steps overestimate its well separated lambda_1
         ap, bp = W.config_poisson32()

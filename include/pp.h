@@ -247,15 +247,29 @@ PP_API pp_status pcg_solve(pp_op op, const double *b, double *x, double tol, int
  *   pp_estimate_bounds keeping the basis, and install as V the Ritz vectors of
  *   the p smallest Ritz values (p in [1, min(8, steps)]); theta: HOST [p]
  *   receives those Ritz values (may be NULL).  Uses steps x n doubles of
- *   scratch during the call.  Synchronises.
+ *   scratch during the call.  Synchronises.  With PP_OPT_RITZ = 1 the
+ *   Lanczos process runs on the preconditioner p_k(A-hat) of the last
+ *   pp_setup instead (k operator applications per step, every new vector
+ *   reorthogonalised against the whole basis): p_k(x) is close to 1/x on
+ *   [lambda_min, lambda_max] and larger below it, so the largest Ritz values
+ *   of p_k(A-hat) belong to the smallest eigenvalues of A-hat and converge in
+ *   few steps (the paper takes the leftmost eigenvectors from a preconditioned
+ *   eigensolver, DACG, section 6.1; here the polynomial is the
+ *   preconditioner); V gets the Ritz vectors of the p largest, and theta
+ *   their Rayleigh quotients v^T A-hat v.
+ *   PP_ERR_STATE without a Chebyshev polynomial set up.
  * pp_lowrank_get: the rank in use (*p) and, when V is not NULL, a copy of the
  *   vectors (device n x p).
+ * pp_lowrank_info: for the installed V, HOST [p] outputs (either may be NULL):
+ *   theta_j = v_j^T A-hat v_j / v_j^T v_j and the relative residual
+ *   ||A-hat v_j - theta_j v_j|| / (|theta_j| ||v_j||).
  * The persistent driver does not apply the correction: pcg_solve uses the
  * stream-driven kernels while a correction is installed.
  */
 PP_API pp_status pp_lowrank_set(pp_op op, int p, const double *V);
 PP_API pp_status pp_lowrank_ritz(pp_op op, int steps, int p, double *theta);
 PP_API pp_status pp_lowrank_get(pp_op op, int *p, double *V);
+PP_API pp_status pp_lowrank_info(pp_op op, double *theta, double *resid);
 
 /*
  * Estimate lambda_min, lambda_max of the (scaled) operator with `steps`
@@ -321,11 +335,13 @@ enum {
                             /* fill whole rounds of compute units (one tile per CU) at     */
                             /* least 90 %, 2 = for any box, 0 = one pass per step.  Other  */
                             /* values: PP_ERR_ARG                                          */
-    PP_OPT_VERIFY = 7       /* true-residual check when pcg_solve converges: the residual  */
+    PP_OPT_VERIFY = 7,      /* true-residual check when pcg_solve converges: the residual  */
                             /* b_hat - A_hat x_hat of the iterate is formed in FP64; if it */
                             /* misses tol, CG restarts from the iterate (at most 3 times). */
                             /* 1 = on, 0 = off, -1 (default) = on in PP_MIXED mode only.   */
                             /* Costs one operator application when the check passes.       */
+    PP_OPT_RITZ = 8         /* pp_lowrank_ritz: 0 (default) Lanczos on A-hat, 1 Lanczos on   */
+                            /* p_k(A-hat) with full reorthogonalisation                    */
 };
 PP_API pp_status pp_set_option(pp_op op, int key, int64_t value);
 

@@ -432,6 +432,42 @@ def ritz_vectors(op: Operator, m: int, p: int):
     return w[:p], Q @ S[:, :p]
 
 
+def poly_ritz_vectors(op: Operator, k: int, lmin: float, lmax: float, xi: float, m: int, p: int):
+    """Ritz pairs of the smallest eigenvalues of op-hat from m Lanczos steps on the
+    preconditioner p_k(op-hat) (Algorithm 2 for each product) with full
+    reorthogonalisation: the Ritz vectors of the p largest Ritz values of
+    p_k(op-hat), which p_k maps from the smallest eigenvalues of op-hat, and
+    their Rayleigh quotients v^T op-hat v / v^T v.  Returns (theta, V n x p)."""
+    from scipy.linalg import eigh_tridiagonal
+
+    n = op.n
+    v = fmix32_start(n)
+    v = v / np.sqrt(v @ v)
+    vprev = np.zeros(n)
+    bprev = 0.0
+    a, b, Q = [], [], []
+    for _ in range(m):
+        Q.append(v.copy())
+        w = cheb_apply_hat(op, k, lmin, lmax, xi, v) - bprev * vprev
+        al = float(v @ w)
+        w = w - al * v
+        Qm = np.array(Q).T
+        w = w - Qm @ (Qm.T @ w)
+        be = float(np.sqrt(w @ w))
+        a.append(al)
+        b.append(be)
+        if be == 0.0:
+            break
+        vprev, v = v, w / be
+        bprev = be
+    j = len(a)
+    wv, S = eigh_tridiagonal(np.array(a), np.array(b)[: j - 1]) if j > 1 else (np.array(a), np.ones((1, 1)))
+    top = np.argsort(-wv)[:p]
+    V = np.array(Q).T @ S[:, top]
+    theta = np.array([float(V[:, c] @ op.apply(V[:, c])) / float(V[:, c] @ V[:, c]) for c in range(V.shape[1])])
+    return theta, V
+
+
 def fmix32_start(n: int) -> np.ndarray:
     v = np.empty(n)
     lib().orc_fmix32_start(n, _p(v))

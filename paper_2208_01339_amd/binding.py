@@ -17,6 +17,7 @@ PP_OK, PP_NOT_CONVERGED, PP_BREAKDOWN = 0, 1, 2
 PP_ERR_ARG, PP_ERR_OOM, PP_ERR_HIP, PP_ERR_STATE = -1, -2, -3, -4
 PP_JACOBI, PP_MIXED, PP_SLICED = 1, 2, 4
 PP_OPT_GRID, PP_OPT_CHUNK, PP_OPT_TIMING, PP_OPT_DRIVER, PP_OPT_NT_LOADS, PP_OPT_TWO_STEP, PP_OPT_VERIFY = 1, 2, 3, 4, 5, 6, 7
+PP_OPT_RITZ = 8
 
 PP_BOPT_GRAPH = 100
 
@@ -28,7 +29,7 @@ ABI_FUNCTIONS = (
     "pp_batch_set_option", "pp_batch_get_stats", "pp_destroy_batch", "pp_mlp_create", "pp_mlp_destroy",
     "pp_mlp_num_params", "pp_mlp_get_params", "pp_mlp_set_params", "pp_mlp_set_normalization",
     "pp_mlp_forward", "pp_mlp_loss_grad", "pp_mlp_train_step", "pp_features", "pp_predict_bounds",
-    "pp_lowrank_set", "pp_lowrank_ritz", "pp_lowrank_get", "pp_setup_newton",
+    "pp_lowrank_set", "pp_lowrank_ritz", "pp_lowrank_get", "pp_lowrank_info", "pp_setup_newton",
     "pp_create_dfn", "pp_dfn_rhs", "pp_dfn_recover", "pcg_solve_csr_noalloc",
 )
 
@@ -118,6 +119,7 @@ def lib():
         L.pp_setup_newton.argtypes = [P, I32, D, D, D]
         L.pp_lowrank_ritz.argtypes = [P, I32, I32, P]
         L.pp_lowrank_get.argtypes = [P, C.POINTER(I32), P]
+        L.pp_lowrank_info.argtypes = [P, P, P]
         L.pp_predict_bounds.argtypes = [P, P, I32, C.POINTER(D), C.POINTER(D), C.POINTER(D), C.POINTER(I32)]
         for f in ABI_FUNCTIONS:
             if f not in ("pp_destroy", "pp_status_str", "pp_last_error", "pp_destroy_batch", "pp_mlp_destroy"):
@@ -301,6 +303,18 @@ def pp_lowrank_get(op, V=None):
     p = C.c_int()
     _check(lib().pp_lowrank_get(op, C.byref(p), _ptr(V)))
     return p.value
+
+
+def pp_lowrank_info(op):
+    """(theta, resid) host arrays of the installed correction: Rayleigh quotients and relative
+    Ritz residuals ||A-hat v - theta v|| / (|theta| ||v||)."""
+    import numpy as np
+
+    p = pp_lowrank_get(op)
+    th = np.zeros(max(1, p))
+    rs = np.zeros(max(1, p))
+    _check(lib().pp_lowrank_info(op, _hptr(th), _hptr(rs)))
+    return th[:p], rs[:p]
 
 
 def pp_operator_apply(op, x, y):

@@ -177,4 +177,54 @@ static __global__ __launch_bounds__(BLOCK) void k_lr_combine(int64_t n, int m, i
     });
 }
 
+// partials[L] = sum over my rows of (y_i - a x_i)^2
+static __global__ __launch_bounds__(BLOCK) void k_resid_norm2(int64_t n, double a, const double *__restrict__ x,
+                                                              const double *__restrict__ y, double *partials)
+{
+    const int G = (int)gridDim.x;
+    const int L = xcd_remap((int)blockIdx.x, G);
+    double part = 0.0;
+    for_my_elems(n, L, G, [&](int64_t i) {
+        const double d = y[i] - a * x[i];
+        part += d * d;
+    });
+    store_partial(part, partials, L);
+}
+
+// w -= sum_j Q_j coef[j]   (j < p <= LR_MAX; coef on the device)
+static __global__ __launch_bounds__(BLOCK) void k_lr_sub(int64_t n, int p, const double *__restrict__ Q, int64_t ldq,
+                                                         const double *__restrict__ coef, double *__restrict__ w)
+{
+    const int G = (int)gridDim.x;
+    const int L = xcd_remap((int)blockIdx.x, G);
+    double c[LR_MAX];
+#pragma unroll
+    for (int j = 0; j < LR_MAX; ++j) c[j] = j < p ? coef[j] : 0.0;
+    for_my_elems(n, L, G, [&](int64_t i) {
+        double a = 0.0;
+#pragma unroll
+        for (int j = 0; j < LR_MAX; ++j)
+            if (j < p) a += Q[(int64_t)j * ldq + i] * c[j];
+        w[i] = w[i] - a;
+    });
+}
+
+// Lanczos step on another operator whose product w = B v is already formed:
+// w -= beta_{j-1} vprev ; reduce v.w -> lz_alpha[j]
+static __global__ __launch_bounds__(BLOCK) void k_lz_wsub(int64_t n, const double *__restrict__ v,
+                                                          const double *__restrict__ vprev, double *__restrict__ w,
+                                                          double *partials, State *st, int j)
+{
+    const int G = (int)gridDim.x;
+    const int L = xcd_remap((int)blockIdx.x, G);
+    const double bp = (j > 0) ? st->lz_beta[j - 1] : 0.0;
+    double part = 0.0;
+    for_my_elems(n, L, G, [&](int64_t i) {
+        const double wi = w[i] - bp * vprev[i];
+        w[i] = wi;
+        part += v[i] * wi;
+    });
+    store_partial(part, partials, L);
+}
+
 }  // namespace ppk

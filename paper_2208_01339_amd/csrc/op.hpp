@@ -99,6 +99,8 @@ struct pp_op_s {
     int chunk = 0;  // 0 = auto
     int timing = 0;
     int driver = -1;  // -1 auto, 0 stream-driven, 1 persistent
+    int ritz_poly = 0;  // pp_lowrank_ritz: 0 Lanczos on A-hat, 1 on p_k(A-hat) with full reorthogonalisation
+    std::vector<double> lr_theta, lr_res;  // v^T A-hat v and ||A-hat v - theta v|| of the installed V
     int verify = -1;  // true-residual check at convergence: -1 auto (mixed mode), 0 off, 1 on
     int pass_maxit = 0;  // iteration budget of the current pass of pcg_solve
     int ntload = 1;   // set at create from the operator's size

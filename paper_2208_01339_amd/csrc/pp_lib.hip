@@ -1360,6 +1360,10 @@ pp_status pp_set_option(pp_op op, int key, int64_t value)
         if (value < -1 || value > 1) return fail(PP_ERR_ARG, "PP_OPT_VERIFY must be -1, 0 or 1");
         op->verify = (int)value;
         return PP_OK;
+    case PP_OPT_RITZ:
+        if (value < 0 || value > 1) return fail(PP_ERR_ARG, "PP_OPT_RITZ must be 0 or 1");
+        op->ritz_poly = (int)value;
+        return PP_OK;
     default: return fail(PP_ERR_ARG, "unknown option");
     }
 }
@@ -1613,12 +1617,14 @@ bool lowrank_hinv(pp_op_s *op, int p, const double *V, std::vector<double> &hinv
 {
     const int64_t n = op->n;
     const int gs = op->grid_slices(), ge = op->grid_elems(n);
-    double *out = dalloc<double>(ppk::LR_MAX);
+    double *out = dalloc<double>(ppk::LR_MAX + 2);
     struct Free {
         double *&p;
         ~Free() { dfree(p); }
     } f{out};
-    std::vector<double> h((size_t)p * 2 * p, 0.0), col(p);
+    std::vector<double> h((size_t)p * 2 * p, 0.0), col(p), nrm(2);
+    op->lr_theta.assign(p, 0.0);
+    op->lr_res.assign(p, 0.0);
     for (int j = 0; j < p; ++j) {
         const double *vj = V + (int64_t)j * n;
         enqueue_trace_f64(op, vj, false);
@@ -1632,10 +1638,26 @@ bool lowrank_hinv(pp_op_s *op, int p, const double *V, std::vector<double> &hinv
                            (const double *)nullptr, op->partials, (const ppk::State *)nullptr);
         hipLaunchKernelGGL(ppk::k_colsum, dim3(1), dim3(BLOCK), 0, op->stream, (const double *)op->partials, ge, p,
                            out);
+        // ||v_j||^2, then theta = v^T A v / v^T v and ||A v_j - theta v_j||^2
+        hipLaunchKernelGGL(ppk::k_lr_dots, dim3(ge), dim3(BLOCK), 0, op->stream, n, 1, vj, n, vj,
+                           (const double *)nullptr, op->partials, (const ppk::State *)nullptr);
+        hipLaunchKernelGGL(ppk::k_colsum, dim3(1), dim3(BLOCK), 0, op->stream, (const double *)op->partials, ge, 1,
+                           out + p);
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(col.data(), out, sizeof(double) * p, hipMemcpyDeviceToHost, op->stream));
+        HIPCHK(hipMemcpyAsync(nrm.data(), out + p, sizeof(double), hipMemcpyDeviceToHost, op->stream));
         HIPCHK(hipStreamSynchronize(op->stream));
         for (int i = 0; i < p; ++i) h[(size_t)i * 2 * p + j] = col[i];  // H_ij = V_i^T A V_j
+        const double vv = nrm[0] > 0.0 ? nrm[0] : 1.0, th = col[j] / vv;
+        hipLaunchKernelGGL(ppk::k_resid_norm2, dim3(ge), dim3(BLOCK), 0, op->stream, n, th, vj,
+                           (const double *)op->q, op->partials);
+        hipLaunchKernelGGL(ppk::k_colsum, dim3(1), dim3(BLOCK), 0, op->stream, (const double *)op->partials, ge, 1,
+                           out + p + 1);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(nrm.data() + 1, out + p + 1, sizeof(double), hipMemcpyDeviceToHost, op->stream));
+        HIPCHK(hipStreamSynchronize(op->stream));
+        op->lr_theta[j] = th;
+        op->lr_res[j] = std::sqrt(nrm[1]) / (std::fabs(th) * std::sqrt(vv) + 1e-300);
     }
     for (int i = 0; i < p; ++i) h[(size_t)i * 2 * p + p + i] = 1.0;
     for (int c = 0; c < p; ++c) {
@@ -1701,16 +1723,21 @@ pp_status pp_lowrank_ritz(pp_op op, int steps, int p, double *theta)
     if (!op) return fail(PP_ERR_ARG, "NULL operator");
     if (steps < 1 || steps > ppk::LZ_MAX) return fail(PP_ERR_ARG, "steps must be in [1, 64]");
     if (p < 1 || p > ppk::LR_MAX || p > steps) return fail(PP_ERR_ARG, "rank must be in [1, min(8, steps)]");
-    double *Q = nullptr, *S = nullptr;
+    const bool poly = op->ritz_poly != 0;
+    if (poly && (!op->setup_done || op->form != 0))
+        return fail(PP_ERR_STATE, "PP_OPT_RITZ = 1 needs a Chebyshev polynomial (pp_setup) first");
+    double *Q = nullptr, *S = nullptr, *coef = nullptr;
     struct Free {
-        double *&a, *&b;
-        ~Free() { dfree(a); dfree(b); }
-    } f{Q, S};
+        double *&a, *&b, *&c;
+        ~Free() { dfree(a); dfree(b); dfree(c); }
+    } f{Q, S, coef};
     try {
         const int64_t n = op->n;
         const int gs = op->grid_slices(), ge = op->grid_elems(n);
         Q = dalloc<double>((size_t)steps * n);
-        double *v = op->sA, *vprev = op->sB, *w = op->q;
+        // the polynomial uses sA..sD: its Lanczos vectors live in r, p, z
+        double *v = poly ? op->r : op->sA, *vprev = poly ? op->p : op->sB, *w = poly ? op->z : op->q;
+        if (poly) coef = dalloc<double>(ppk::LR_MAX);
         // the Lanczos recurrence of pp_estimate_bounds, keeping every basis vector
         hipLaunchKernelGGL(ppk::k_state_init, dim3(1), dim3(64), 0, op->stream, op->st, 0.0, 0);
         hipLaunchKernelGGL(ppk::k_lz_start, dim3(ge), dim3(BLOCK), 0, op->stream, n, v, op->partials, op->st);
@@ -1718,7 +1745,35 @@ pp_status pp_lowrank_ritz(pp_op op, int steps, int p, double *theta)
         hipLaunchKernelGGL(ppk::k_lz_norm, dim3(ge), dim3(BLOCK), 0, op->stream, n, v, (const ppk::State *)op->st);
         hipLaunchKernelGGL((ppk::k_scale<double, double>), dim3(ge), dim3(BLOCK), 0, op->stream, n,
                            (const double *)v, (const double *)nullptr, 0.0, vprev);
-        for (int j = 0; j < steps; ++j) {
+        for (int j = 0; j < steps && poly; ++j) {
+            // w = p_k(A-hat) v, then the three-term Lanczos step and a full
+            // reorthogonalisation of w against the basis so far (blocks of LR_MAX)
+            HIPCHK(hipMemcpyAsync(Q + (size_t)j * n, v, sizeof(double) * n, hipMemcpyDeviceToDevice, op->stream));
+            enqueue_poly(op, v, w, ppk::FIN_NONE, false);
+            hipLaunchKernelGGL(ppk::k_lz_wsub, dim3(ge), dim3(BLOCK), 0, op->stream, n, (const double *)v,
+                               (const double *)vprev, w, op->partials, op->st, j);
+            enqueue_fin(op, ge, ppk::FIN_LZ_ALPHA, j);
+            hipLaunchKernelGGL(ppk::k_lz_orth, dim3(ge), dim3(BLOCK), 0, op->stream, n, (const double *)v, w,
+                               op->partials, op->st, j);
+            for (int c0 = 0; c0 <= j; c0 += ppk::LR_MAX) {
+                const int pc = std::min(ppk::LR_MAX, j + 1 - c0);
+                const double *Qc = Q + (size_t)c0 * n;
+                hipLaunchKernelGGL(ppk::k_lr_dots, dim3(ge), dim3(BLOCK), 0, op->stream, n, pc, Qc, n,
+                                   (const double *)w, (const double *)nullptr, op->partials,
+                                   (const ppk::State *)nullptr);
+                hipLaunchKernelGGL(ppk::k_colsum, dim3(1), dim3(BLOCK), 0, op->stream, (const double *)op->partials,
+                                   ge, pc, coef);
+                hipLaunchKernelGGL(ppk::k_lr_sub, dim3(ge), dim3(BLOCK), 0, op->stream, n, pc, Qc, n,
+                                   (const double *)coef, w);
+            }
+            hipLaunchKernelGGL(ppk::k_dot_fin, dim3(ge), dim3(BLOCK), 0, op->stream, n, (const double *)w,
+                               (const double *)w, op->partials, op->st, (int)ppk::FIN_LZ_BETA);
+            enqueue_fin(op, ge, ppk::FIN_LZ_BETA, j);
+            if (j + 1 < steps)
+                hipLaunchKernelGGL(ppk::k_lz_next, dim3(ge), dim3(BLOCK), 0, op->stream, n, vprev, v,
+                                   (const double *)w, (const ppk::State *)op->st, j);
+        }
+        for (int j = 0; j < steps && !poly; ++j) {
             HIPCHK(hipMemcpyAsync(Q + (size_t)j * n, v, sizeof(double) * n, hipMemcpyDeviceToDevice, op->stream));
             enqueue_trace_f64(op, v);
             if (op->schur())
@@ -1758,7 +1813,8 @@ pp_status pp_lowrank_ritz(pp_op op, int steps, int p, double *theta)
         ppeig::jacobi_eig(m, T, wv, E);
         std::vector<int> idx(m);
         for (int i = 0; i < m; ++i) idx[i] = i;
-        std::sort(idx.begin(), idx.end(), [&](int a, int b) { return wv[a] < wv[b]; });
+        // smallest Ritz values of A-hat; of p_k(A-hat) the largest
+        std::sort(idx.begin(), idx.end(), [&](int a, int b) { return poly ? wv[a] > wv[b] : wv[a] < wv[b]; });
         std::vector<double> Sh((size_t)m * p);
         for (int j = 0; j < m; ++j)
             for (int c = 0; c < p; ++c) Sh[(size_t)j * p + c] = E[(size_t)j * m + idx[c]];
@@ -1777,7 +1833,21 @@ pp_status pp_lowrank_ritz(pp_op op, int steps, int p, double *theta)
     } catch (HipError &e) {
         return hip_fail(e);
     }
-    return pp_lowrank_set(op, p, op->lr_v);
+    const pp_status s = pp_lowrank_set(op, p, op->lr_v);
+    // of p_k(A-hat) the Ritz values are not eigenvalue estimates of A-hat: report v^T A-hat v
+    if (s == PP_OK && poly && theta)
+        for (int c = 0; c < p; ++c) theta[c] = op->lr_theta[c];
+    return s;
+}
+
+pp_status pp_lowrank_info(pp_op op, double *theta, double *resid)
+{
+    if (!op) return fail(PP_ERR_ARG, "NULL operator");
+    for (int c = 0; c < op->lr_p; ++c) {
+        if (theta) theta[c] = op->lr_theta[c];
+        if (resid) resid[c] = op->lr_res[c];
+    }
+    return PP_OK;
 }
 
 pp_status pp_lowrank_get(pp_op op, int *p, double *V)

@@ -131,6 +131,56 @@ def test_lowrank_ritz_on_gpu(B):
     op.close()
 
 
+@pytest.mark.parametrize("name", ["hetero21_jac", "dfn_small_jac"])
+def test_lowrank_poly_ritz_on_gpu(B, name):
+    """Ritz vectors from Lanczos on p_k(A-hat) (PP_OPT_RITZ = 1) against the oracle's
+    poly_ritz_vectors: Rayleigh quotients to 1e-9, the same vectors (|cos| to 1e-7),
+    residuals as reported by pp_lowrank_info; and the corrected solve converges."""
+    build, jac = CASES[name]
+    a, s = build()
+    if s is not None:
+        op = B.Operator(schur=s, flags=B.PP_JACOBI)
+        orc = O.Operator(s.a, s.c, s.m, jacobi=True)
+    else:
+        op = B.Operator(a=a, flags=B.PP_JACOBI)
+        orc = O.Operator(a, jacobi=True)
+    n = orc.n
+    lmin, lmax = O.lanczos_bounds(orc, 20)
+    k, m, p = 20, 24, 2
+    B.pp_setup(op.handle, k, lmin, lmax, 0.0)
+    B.pp_set_option(op.handle, B.PP_OPT_RITZ, 1)
+    th = B.pp_lowrank_ritz(op.handle, m, p)
+    th_o, V_o = O.poly_ritz_vectors(orc, k, lmin, lmax, 0.0, m, p)
+    assert np.all(np.abs(th - th_o) <= 1e-9 * np.abs(th_o)), (th, th_o)
+    Vd = torch.empty(p, n, dtype=torch.float64, device="cuda")
+    B.pp_lowrank_get(op.handle, Vd)
+    V = host(Vd).T
+    th_i, res_i = B.pp_lowrank_info(op.handle)
+    assert np.allclose(th_i, th, rtol=1e-14)
+    for j in range(p):
+        cos = abs(V[:, j] @ V_o[:, j]) / (np.linalg.norm(V[:, j]) * np.linalg.norm(V_o[:, j]))
+        assert cos >= 1 - 1e-7, (j, cos)
+        res = np.linalg.norm(orc.apply(V[:, j]) - th[j] * V[:, j]) / (abs(th[j]) * np.linalg.norm(V[:, j]))
+        assert abs(res_i[j] - res) <= 1e-6 * max(res, 1e-3), (j, res_i[j], res)
+        assert res <= 1e-3, (j, res)
+    b = W.rhs_uniform(n, 3)
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    s_, it, rel = B.pcg_solve(op.handle, dev(b), x, 1e-8, 2000)
+    assert s_ == B.PP_OK and rel <= 1e-8
+    B.pp_set_option(op.handle, B.PP_OPT_RITZ, 0)
+    op.close()
+
+
+def test_lowrank_poly_ritz_needs_setup(B):
+    op = B.Operator(a=W.poisson3d(8))
+    B.pp_set_option(op.handle, B.PP_OPT_RITZ, 1)
+    with pytest.raises(B.PPError):
+        B.pp_lowrank_ritz(op.handle, 10, 1)
+    with pytest.raises(B.PPError):
+        B.pp_set_option(op.handle, B.PP_OPT_RITZ, 2)
+    op.close()
+
+
 def test_lowrank_clear_errors_and_driver(B):
     a = W.hetero_diffusion(10, 1.0, 2)
     orc = O.Operator(a, jacobi=True)

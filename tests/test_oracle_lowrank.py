@@ -106,3 +106,34 @@ def test_lowrank_pcg_solves_and_zero_rank_is_plain():
     x1, st1 = O.pcg_lowrank(op, 6, lmin, lmax, 1e-3, np.zeros((a.n_rows, 0)), b, tol=1e-10, maxit=500,
                             hinv=np.zeros((0, 0)))
     assert st1["iters"] == st0["iters"] and np.array_equal(x0, x1)
+
+
+def test_poly_ritz_on_diagonal_matrix():
+    """Lanczos on p_k(D) for D with three isolated small eigenvalues below the
+    polynomial's interval: p_k maps them to its largest values, so the Ritz
+    vectors are the unit vectors of those rows, in order, and the Rayleigh
+    quotients are the eigenvalues themselves."""
+    d = np.concatenate([[0.01, 0.03, 0.2], np.linspace(1.0, 10.0, 197)])
+    op = O.Operator(DiagCSR(d))
+    theta, V = O.poly_ritz_vectors(op, 10, 1.0, 10.0, 0.0, 30, 3)
+    assert np.allclose(theta, d[:3], rtol=1e-10)
+    for c in range(3):
+        assert abs(abs(V[c, c]) / np.linalg.norm(V[:, c]) - 1.0) < 1e-10
+
+
+def test_poly_ritz_matches_dense_eigenvectors():
+    """On a small Jacobi-scaled heterogeneous operator the p Ritz vectors from 30
+    steps on p_k(A-hat) are the eigenvectors of the p smallest eigenvalues of
+    A-hat (dense eigh): Rayleigh quotients to 1e-8, residuals below 1e-4."""
+    a = W.hetero_diffusion(8, 2.0, 3)
+    op = O.Operator(a, jacobi=True)
+    lmin, lmax = O.lanczos_bounds(op, 20)
+    theta, V = O.poly_ritz_vectors(op, 20, lmin, lmax, 0.0, 30, 3)
+    A = a.to_scipy().toarray()
+    dis = 1.0 / np.sqrt(np.diag(A))
+    lam = np.linalg.eigvalsh(A * np.outer(dis, dis))
+    assert np.allclose(theta, lam[:3], rtol=1e-8)
+    for c in range(3):
+        v = V[:, c]
+        res = np.linalg.norm(op.apply(v) - theta[c] * v) / (abs(theta[c]) * np.linalg.norm(v))
+        assert res < 1e-4, (c, res)
