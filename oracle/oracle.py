@@ -46,7 +46,10 @@ def lib(omp: bool = False):
     key = bool(omp)
     if key not in _libs:
         path = _LIB_OMP if omp else _LIB
-        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+        override = os.environ.get("PPCG_ORACLE_LIB")  # a sanitizer build of the same source (tests)
+        if override and not omp:
+            path = override
+        elif not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
             build(force=True)
         L = C.CDLL(path)
         P = C.c_void_p

@@ -67,10 +67,11 @@ def lib():
     """Load libppcg.so (raises if it has not been built)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
+        path = os.environ.get("PPCG_LIB", LIB_PATH)  # another build of the same sources (sanitizer tests)
+        if not os.path.exists(path):
             raise RuntimeError("libppcg.so is not built; run __graft_entry__.build() "
                                "(python -m paper_2208_01339_amd.build)")
-        L = C.CDLL(LIB_PATH)
+        L = C.CDLL(path)
         P, I64, I32, D = C.c_void_p, C.c_int64, C.c_int, C.c_double
         L.pp_create_csr.argtypes = [C.POINTER(P), I64, I64, P, P, P, C.c_uint, P]
         L.pp_create_schur.argtypes = [C.POINTER(P), I64, I64, P, P, P, I64, I64, P, P, P, P, C.c_uint, P]
