@@ -63,8 +63,23 @@ typedef enum {
 enum {
     PP_JACOBI = 1u, /* iterate on D^{-1/2} A D^{-1/2}, D = diag(A) (section 3, 4.3)        */
     PP_MIXED = 2u,  /* p_k(A)v in FP32 (values, vectors, accumulation); CG stays FP64     */
-    PP_SLICED = 4u  /* keep every entry in the sliced layout (no symmetric diagonal part)  */
+    PP_SLICED = 4u, /* keep every entry in the sliced layout (no symmetric diagonal part)  */
+    PP_NO_REORDER = 8u /* CSR: keep the caller's row order (see Renumbering below)         */
 };
+
+/*
+ * Renumbering.  A CSR operator held in slices only (no stored diagonals) whose
+ * numbering scatters the columns that a slice of 64 consecutive rows gathers
+ * (more than 0.25 distinct 64-byte lines of x per stored entry, sampled) is
+ * renumbered at create by reverse Cuthill-McKee (breadth-first levels from a
+ * peripheral vertex), when that at least halves the spread.  Vectors stay in
+ * the caller's numbering at every entry point (b, x, r, z, V); internally the
+ * library holds P A P^T.  The Lanczos start vectors use the caller's row
+ * index, so bounds, Ritz vectors and features are those of the caller's
+ * numbering up to rounding.  Create copies the matrix structure to the host
+ * for this (n + 1 row pointers and nnz column indices).  The persistent
+ * driver is not used for renumbered operators.
+ */
 
 /*
  * Storage.  By default an operator whose column offsets j - i take few
@@ -311,9 +326,11 @@ typedef struct {
     int64_t pair_launches;  /* fused-pair launches covered by pair_ms                */
     int32_t restarts;       /* CG restarts after a failed true-residual check        */
                             /* (PP_OPT_VERIFY)                                      */
-    int32_t pad0;
+    int32_t reordered;      /* 1 when create renumbered the rows (PP_NO_REORDER)     */
     double true_relres;     /* ||b_hat - A_hat x_hat|| / ||b_hat|| of the returned x */
                             /* when the true-residual check ran, else -1             */
+    double gather_spread;   /* distinct 64-byte lines of x per stored entry that a   */
+                            /* slice of 64 rows gathers (sampled; after renumbering) */
 } pp_stats;
 
 PP_API pp_status pp_get_stats(pp_op op, pp_stats *st);

@@ -473,17 +473,21 @@ __device__ __forceinline__ double ph_cheb(const SellView &A, const XT *__restric
 }
 
 // bh = dis .* b, xh = x ./ dis; returns the share of bh.bh
+// perm (new -> old numbering, or null): the operator was renumbered at create
+// and b, x are in the caller's numbering.
 __device__ __forceinline__ double ph_init_scale(int64_t n, const double *__restrict__ b,
                                                 const double *__restrict__ x,
                                                 const double *__restrict__ dis, double *__restrict__ bh,
-                                                double *__restrict__ xh, int L, int G)
+                                                double *__restrict__ xh, int L, int G,
+                                                const int32_t *__restrict__ perm = nullptr)
 {
     double part = 0.0;
     for_my_elems(n, L, G, [&](int64_t i) {
+        const int64_t o = perm ? (int64_t)perm[i] : i;
         const double d = dis ? dis[i] : 1.0;
-        const double bi = d * b[i];
+        const double bi = d * b[o];
         bh[i] = bi;
-        xh[i] = x[i] / d;
+        xh[i] = x[o] / d;
         part += bi * bi;
     });
     return part;
@@ -551,12 +555,14 @@ __device__ __forceinline__ void ph_p(int64_t n, const double *__restrict__ z, do
     for_my_elems(n, L, G, [&](int64_t i) { p[i] = first ? z[i] : z[i] + beta * p[i]; });
 }
 
-// x = dis .* xh (or 0 when b_hat == 0)
+// x = dis .* xh (or 0 when b_hat == 0); with perm, x in the caller's numbering
 __device__ __forceinline__ void ph_final_x(int64_t n, const double *__restrict__ xh,
                                            const double *__restrict__ dis, double *__restrict__ x, bool zb,
-                                           int L, int G)
+                                           int L, int G, const int32_t *__restrict__ perm = nullptr)
 {
-    for_my_elems(n, L, G, [&](int64_t i) { x[i] = zb ? 0.0 : (dis ? dis[i] : 1.0) * xh[i]; });
+    for_my_elems(n, L, G, [&](int64_t i) {
+        x[perm ? (int64_t)perm[i] : i] = zb ? 0.0 : (dis ? dis[i] : 1.0) * xh[i];
+    });
 }
 
 // y = c x (converting type); returns the share of x.y when DOT
@@ -632,10 +638,11 @@ static __global__ __launch_bounds__(BLOCK) void k_init_scale(int64_t n, const do
                                                       const double *__restrict__ x,
                                                       const double *__restrict__ dis,
                                                       double *__restrict__ bh, double *__restrict__ xh,
-                                                      double *partials, State *st)
+                                                      double *partials, State *st,
+                                                      const int32_t *__restrict__ perm)
 {
     PPK_PROLOGUE(st)
-    const double part = ph_init_scale(n, b, x, dis, bh, xh, L, G);
+    const double part = ph_init_scale(n, b, x, dis, bh, xh, L, G, perm);
     store_partial(part, partials, L);
 }
 
@@ -680,11 +687,12 @@ static __global__ __launch_bounds__(BLOCK) void k_p(int64_t n, const double *__r
 // runs even when done is set
 static __global__ __launch_bounds__(BLOCK) void k_final_x(int64_t n, const double *__restrict__ xh,
                                                    const double *__restrict__ dis,
-                                                   double *__restrict__ x, const State *st)
+                                                   double *__restrict__ x, const State *st,
+                                                   const int32_t *__restrict__ perm)
 {
     const int G = (int)gridDim.x;
     const int L = xcd_remap((int)blockIdx.x, G);
-    ph_final_x(n, xh, dis, x, st->zero_b != 0, L, G);
+    ph_final_x(n, xh, dis, x, st->zero_b != 0, L, G, perm);
 }
 
 // ---------------------------------------------------------------------------
@@ -775,14 +783,17 @@ __device__ __forceinline__ uint32_t fmix32(uint32_t h)
     return h;
 }
 
-// v_i = fmix32(i) / 2^32 - 0.5 ; reduce v.v -> FIN_LZ_NORM0
+// v_i = fmix32(i) / 2^32 - 0.5 ; reduce v.v -> FIN_LZ_NORM0.  i is the row in the
+// caller's numbering (perm[i] when the operator was renumbered).
 static __global__ __launch_bounds__(BLOCK) void k_lz_start(int64_t n, double *__restrict__ v,
-                                                    double *partials, State *st)
+                                                    double *partials, State *st,
+                                                    const int32_t *__restrict__ perm)
 {
     PPK_PROLOGUE(st)
     double part = 0.0;
     for_my_elems(n, L, G, [&](int64_t i) {
-        const double x = (double)fmix32((uint32_t)i) / 4294967296.0 - 0.5;
+        const uint32_t g = perm ? (uint32_t)perm[i] : (uint32_t)i;
+        const double x = (double)fmix32(g) / 4294967296.0 - 0.5;
         v[i] = x;
         part += x * x;
     });
@@ -851,6 +862,55 @@ static __global__ __launch_bounds__(BLOCK) void k_lz_next(int64_t n, double *__r
         vprev[i] = v[i];
         v[i] = w[i] / b;
     });
+}
+
+// y[i] = c s[i] x[perm[i]]  (s may be null = 1): a vector of the caller's numbering
+// into the operator's
+static __global__ __launch_bounds__(BLOCK) void k_gather_scale(int64_t n, const double *__restrict__ x,
+                                                               const int32_t *__restrict__ perm,
+                                                               const double *__restrict__ s, double c,
+                                                               double *__restrict__ y)
+{
+    const int G = (int)gridDim.x;
+    const int L = xcd_remap((int)blockIdx.x, G);
+    for_my_elems(n, L, G, [&](int64_t i) { y[i] = c * (s ? s[i] : 1.0) * x[perm[i]]; });
+}
+
+// dst[perm[i]] = src[i]: back to the caller's numbering
+static __global__ __launch_bounds__(BLOCK) void k_scatter(int64_t n, const double *__restrict__ src,
+                                                          const int32_t *__restrict__ perm,
+                                                          double *__restrict__ dst)
+{
+    const int G = (int)gridDim.x;
+    const int L = xcd_remap((int)blockIdx.x, G);
+    for_my_elems(n, L, G, [&](int64_t i) { dst[perm[i]] = src[i]; });
+}
+
+// Renumbered CSR: new row i is old row perm[i], its columns mapped by iperm
+// and sorted (insertion sort: rows are short, the host refuses long ones).
+static __global__ __launch_bounds__(BLOCK) void k_perm_csr(int64_t n, const int64_t *__restrict__ rp,
+                                                           const int32_t *__restrict__ col,
+                                                           const double *__restrict__ val,
+                                                           const int32_t *__restrict__ perm,
+                                                           const int32_t *__restrict__ iperm,
+                                                           const int64_t *__restrict__ nrp, int32_t *__restrict__ ncol,
+                                                           double *__restrict__ nval)
+{
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= n) return;
+    const int64_t o = perm[i], p0 = rp[o], len = rp[o + 1] - p0, q0 = nrp[i];
+    for (int64_t t = 0; t < len; ++t) {
+        const int32_t c = iperm[col[p0 + t]];
+        const double v = val[p0 + t];
+        int64_t u = t;
+        while (u > 0 && ncol[q0 + u - 1] > c) {
+            ncol[q0 + u] = ncol[q0 + u - 1];
+            nval[q0 + u] = nval[q0 + u - 1];
+            --u;
+        }
+        ncol[q0 + u] = c;
+        nval[q0 + u] = v;
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -51,6 +51,9 @@ struct pp_op_s {
     double *dfn_t = nullptr, *dfn_d = nullptr;
     // Jacobi
     double *dis = nullptr;
+    // renumbering chosen at create (reverse Cuthill-McKee), new -> old row; null = none
+    int32_t *perm = nullptr;
+    double spread[2] = {0.0, 0.0};  // gather spread of the slices before / after renumbering
     // work vectors
     double *xh = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr, *bh = nullptr;
     double *sA = nullptr, *sB = nullptr;
@@ -176,7 +179,7 @@ struct pp_op_s {
         ppc::dfree(sp); ppc::dfree(scol); ppc::dfree(sval); ppc::dfree(sval32);
         ppc::dfree(dval); ppc::dfree(dval32);
         ppc::dfree(crp); ppc::dfree(ccol); ppc::dfree(cm); ppc::dfree(cm32); ppc::dfree(tw); ppc::dfree(tw32);
-        ppc::dfree(dis);
+        ppc::dfree(dis); ppc::dfree(perm);
         ppc::dfree(dfn_Lb); ppc::dfree(dfn_Q); ppc::dfree(dfn_ghc); ppc::dfree(dfn_ghv); ppc::dfree(dfn_t); ppc::dfree(dfn_d);
         for (int i = 0; i < 6; ++i) { ppc::dfree(dfn_rp[i]); ppc::dfree(dfn_col[i]); ppc::dfree(dfn_val[i]); }
         ppc::dfree(xh); ppc::dfree(r); ppc::dfree(p); ppc::dfree(q); ppc::dfree(z); ppc::dfree(bh); ppc::dfree(sA); ppc::dfree(sB);

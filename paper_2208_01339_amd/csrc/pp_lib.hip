@@ -18,6 +18,7 @@
 #include "dia_plan.hpp"
 #include "lowrank.hpp"
 #include "persistent.hpp"
+#include "reorder.hpp"
 #include "stencil2.hpp"
 #include "sym_eig.hpp"
 
@@ -172,6 +173,59 @@ ppk::DiaSet build_diagonals(pp_op_s *op, const int64_t *rp, const int32_t *col, 
     return D;
 }
 
+// A CSR matrix that neither fits the stored diagonals nor numbers neighbouring
+// rows close together (the gathers of a slice spread over many cache lines)
+// is renumbered by reverse Cuthill-McKee when that brings the spread down at
+// least twofold: op->perm (new -> old) is set and a renumbered device copy is
+// returned in *prp, *pcol, *pval (the caller frees it).  Rows longer than 512
+// entries (the device sort is quadratic in the row length) keep the order.
+bool maybe_reorder(pp_op_s *op, const int64_t *rp, const int32_t *col, const double *val, int64_t **prp,
+                   int32_t **pcol, double **pval)
+{
+    const int64_t n = op->n, nnz = op->nnz_given;
+    std::vector<int64_t> hrp(n + 1);
+    std::vector<int32_t> hcol(nnz);
+    HIPCHK(hipMemcpyAsync(hrp.data(), rp, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, op->stream));
+    HIPCHK(hipMemcpyAsync(hcol.data(), col, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost, op->stream));
+    HIPCHK(hipStreamSynchronize(op->stream));
+    for (int64_t i = 0; i < n; ++i)
+        if (hrp[i + 1] - hrp[i] > 512) return false;
+    const std::vector<int64_t> none;
+    const double s0 = pprc::gather_spread(n, hrp, hcol, none, none);
+    op->spread[0] = op->spread[1] = s0;
+    if (s0 <= 0.25) return false;
+    const std::vector<int64_t> perm = pprc::rcm(n, hrp, hcol);
+    std::vector<int64_t> iperm(n);
+    for (int64_t i = 0; i < n; ++i) iperm[perm[i]] = i;
+    const double s1 = pprc::gather_spread(n, hrp, hcol, perm, iperm);
+    if (!(s1 < 0.5 * s0)) return false;
+    op->spread[1] = s1;
+    std::vector<int64_t> nrp(n + 1, 0);
+    std::vector<int32_t> p32(n), ip32(n);
+    for (int64_t i = 0; i < n; ++i) {
+        nrp[i + 1] = nrp[i] + (hrp[perm[i] + 1] - hrp[perm[i]]);
+        p32[i] = (int32_t)perm[i];
+        ip32[i] = (int32_t)iperm[i];
+    }
+    int32_t *ip = dalloc<int32_t>(n);
+    struct Free {
+        int32_t *&p;
+        ~Free() { dfree(p); }
+    } f{ip};
+    op->perm = dalloc<int32_t>(n);
+    *prp = dalloc<int64_t>(n + 1);
+    *pcol = dalloc<int32_t>(nnz);
+    *pval = dalloc<double>(nnz);
+    HIPCHK(hipMemcpyAsync(op->perm, p32.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, op->stream));
+    HIPCHK(hipMemcpyAsync(ip, ip32.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, op->stream));
+    HIPCHK(hipMemcpyAsync(*prp, nrp.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, op->stream));
+    hipLaunchKernelGGL(ppk::k_perm_csr, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, op->stream, n, rp,
+                       col, val, (const int32_t *)op->perm, (const int32_t *)ip, (const int64_t *)*prp, *pcol, *pval);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(op->stream));  // host vectors leave scope
+    return true;
+}
+
 pp_status build_operator(pp_op_s *op, const int64_t *rp, const int32_t *col, const double *val,
                          const int64_t *c_rowptr, const int32_t *c_col, const double *c_val,
                          const double *m_diag)
@@ -183,8 +237,12 @@ pp_status build_operator(pp_op_s *op, const int64_t *rp, const int32_t *col, con
     double *ctv = nullptr;
     int64_t *width = nullptr;
     double *dtmp = nullptr;
+    int64_t *prp = nullptr;  // renumbered copy of A (maybe_reorder)
+    int32_t *pcol = nullptr;
+    double *pval = nullptr;
     auto cleanup = [&]() {
         dfree(flag_d); dfree(ctp); dfree(ctt); dfree(ctv); dfree(width); dfree(dtmp);
+        dfree(prp); dfree(pcol); dfree(pval);
     };
     try {
         int bad = check_csr_dev(op, n, n, op->nnz_given, rp, col, flag_d);
@@ -217,6 +275,20 @@ pp_status build_operator(pp_op_s *op, const int64_t *rp, const int32_t *col, con
         // symmetric diagonal part (unless the caller asked for the slice layout only)
         ppk::DiaSet D;
         if (!(op->flags & PP_SLICED)) D = build_diagonals(op, rp, col, val);
+        // slices only: renumber when the gathers of a slice are scattered
+        if (op->kind == 0 && D.nd == 0 && !(op->flags & PP_NO_REORDER) &&
+            maybe_reorder(op, rp, col, val, &prp, &pcol, &pval)) {
+            rp = prp;
+            col = pcol;
+            val = pval;
+            if (op->flags & PP_JACOBI) {
+                hipLaunchKernelGGL(ppk::k_diag, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0,
+                                   op->stream, n, rp, col, val, (const int64_t *)nullptr, (const int32_t *)nullptr,
+                                   (const double *)nullptr, m_diag, dtmp, op->dis, flag_d);
+                HIPCHK(hipGetLastError());
+            }
+            if (!(op->flags & PP_SLICED)) D = build_diagonals(op, rp, col, val);
+        }
         // slice part: the entries the diagonal part does not cover, plus trace columns
         width = dalloc<int64_t>(op->nslices);
         op->sp = dalloc<int64_t>(op->nslices + 1);
@@ -289,6 +361,8 @@ pp_status build_operator(pp_op_s *op, const int64_t *rp, const int32_t *col, con
     op->stats.nnz_stored = op->nstored;
     op->stats.diagonals = op->nd;
     op->stats.nnz_matrix = op->nnz_given + op->nnz_c;
+    op->stats.reordered = op->perm ? 1 : 0;
+    op->stats.gather_spread = op->spread[1];
     return PP_OK;
 }
 
@@ -301,7 +375,7 @@ pp_status create_common(pp_op *out, int kind, int64_t n, int64_t nnz, const int6
     *out = nullptr;
     if (n <= 0 || nnz <= 0 || !rp || !col || !val) return fail(PP_ERR_ARG, "n, nnz must be positive and arrays non-NULL");
     if (n > (int64_t)INT32_MAX - 1) return fail(PP_ERR_ARG, "n must be below 2^31 (int32 column indices)");
-    if (flags & ~(unsigned)(PP_JACOBI | PP_MIXED | PP_SLICED)) return fail(PP_ERR_ARG, "unknown flags");
+    if (flags & ~(unsigned)(PP_JACOBI | PP_MIXED | PP_SLICED | PP_NO_REORDER)) return fail(PP_ERR_ARG, "unknown flags");
     if (kind == 1) {
         if (nt <= 0 || nnz_c <= 0 || !c_rowptr || !c_col || !c_val || !m_diag)
             return fail(PP_ERR_ARG, "Schur: nt, nnz_c must be positive and arrays non-NULL");
@@ -1383,14 +1457,20 @@ pp_status pp_operator_apply(pp_op op, const double *x, double *y)
     try {
         const int64_t n = op->n;
         const double *src = x;
+        if (op->perm) {
+            // P x into the operator's numbering (y comes back through P^T below)
+            hipLaunchKernelGGL(ppk::k_gather_scale, dim3(op->grid_elems(n)), dim3(BLOCK), 0, op->stream, n, x,
+                               (const int32_t *)op->perm, (const double *)nullptr, 1.0, op->z);
+            src = op->z;
+        }
         if (op->dis) {
             // A = D^{1/2} A-hat D^{1/2}: xh = x / dis, y = (A-hat xh) / dis
-            hipLaunchKernelGGL(ppk::k_div, dim3(op->grid_elems(n)), dim3(BLOCK), 0, op->stream, n, x,
+            hipLaunchKernelGGL(ppk::k_div, dim3(op->grid_elems(n)), dim3(BLOCK), 0, op->stream, n, src,
                                (const double *)op->dis, op->bh);
             src = op->bh;
         }
         enqueue_trace_f64(op, src, false);
-        double *dst = op->dis ? op->sA : y;
+        double *dst = op->dis || op->perm ? op->sA : y;
         if (op->schur())
             hipLaunchKernelGGL((ppk::k_spmv<double, true>), dim3(op->grid_slices()), dim3(BLOCK), 0, op->stream,
                                op->view(false), src, (const double *)op->tw, dst, op->ntload);
@@ -1399,7 +1479,10 @@ pp_status pp_operator_apply(pp_op op, const double *x, double *y)
                                op->view(false), src, (const double *)nullptr, dst, op->ntload);
         if (op->dis)
             hipLaunchKernelGGL(ppk::k_div, dim3(op->grid_elems(n)), dim3(BLOCK), 0, op->stream, n,
-                               (const double *)op->sA, (const double *)op->dis, y);
+                               (const double *)op->sA, (const double *)op->dis, op->perm ? op->sB : y);
+        if (op->perm)
+            hipLaunchKernelGGL(ppk::k_scatter, dim3(op->grid_elems(n)), dim3(BLOCK), 0, op->stream, n,
+                               (const double *)(op->dis ? op->sB : op->sA), (const int32_t *)op->perm, y);
         HIPCHK(hipGetLastError());
     } catch (HipError &e) {
         return hip_fail(e);
@@ -1417,18 +1500,27 @@ pp_status pp_apply(pp_op op, const double *r, double *z)
         // the polynomial kernels check the device state: make sure it is live
         hipLaunchKernelGGL(ppk::k_state_init, dim3(1), dim3(64), 0, op->stream, op->st, 0.0, 0);
         const double *rr = r;
-        if (op->dis) {
+        if (op->perm) {
+            // the caller's numbering in and out: bh = D^{-1/2} P r, z = P^T z'
+            hipLaunchKernelGGL(ppk::k_gather_scale, dim3(op->grid_elems(n)), dim3(BLOCK), 0, op->stream, n, r,
+                               (const int32_t *)op->perm, (const double *)op->dis, 1.0, op->bh);
+            rr = op->bh;
+        } else if (op->dis) {
             hipLaunchKernelGGL((ppk::k_scale<double, double>), dim3(op->grid_elems(n)), dim3(BLOCK), 0, op->stream,
                                n, r, (const double *)op->dis, 1.0, op->bh);
             rr = op->bh;
         }
-        enqueue_poly(op, rr, z, ppk::FIN_NONE, op->dis != nullptr);
+        double *zz = op->perm ? op->z : z;
+        enqueue_poly(op, rr, zz, ppk::FIN_NONE, op->dis != nullptr);
         if (op->lr_p > 0) {
             // z += D^{-1/2} V Hinv V^T D^{-1/2} r
             enqueue_lr_c(op, rr, nullptr);
             hipLaunchKernelGGL(ppk::k_lr_axpy, dim3(op->grid_elems(n)), dim3(BLOCK), 0, op->stream, n, op->lr_p,
-                               (const double *)op->lr_v, n, (const double *)op->dis, z, (const ppk::State *)op->st);
+                               (const double *)op->lr_v, n, (const double *)op->dis, zz, (const ppk::State *)op->st);
         }
+        if (op->perm)
+            hipLaunchKernelGGL(ppk::k_scatter, dim3(op->grid_elems(n)), dim3(BLOCK), 0, op->stream, n,
+                               (const double *)zz, (const int32_t *)op->perm, z);
         HIPCHK(hipGetLastError());
     } catch (HipError &e) {
         return hip_fail(e);
@@ -1448,7 +1540,7 @@ void stream_pass(pp_op_s *op, const double *b, double *x, bool timed, size_t &ev
     const int64_t n = op->n;
     const int gs = op->grid_slices(), ge = op->grid_elems(n);
     hipLaunchKernelGGL(ppk::k_init_scale, dim3(ge), dim3(BLOCK), 0, op->stream, n, b, (const double *)x,
-                       (const double *)op->dis, op->bh, op->xh, op->partials, op->st);
+                       (const double *)op->dis, op->bh, op->xh, op->partials, op->st, (const int32_t *)op->perm);
     enqueue_fin(op, ge, ppk::FIN_BNORM);
     enqueue_trace_f64(op, op->xh);
     if (op->schur())
@@ -1494,7 +1586,7 @@ void stream_pass(pp_op_s *op, const double *b, double *x, bool timed, size_t &ev
         ++c;
     }
     hipLaunchKernelGGL(ppk::k_final_x, dim3(ge), dim3(BLOCK), 0, op->stream, n, (const double *)op->xh,
-                       (const double *)op->dis, x, (const ppk::State *)op->st);
+                       (const double *)op->dis, x, (const ppk::State *)op->st, (const int32_t *)op->perm);
 }
 
 }  // namespace
@@ -1511,7 +1603,7 @@ pp_status pcg_solve(pp_op op, const double *b, double *x, double tol, int maxit,
         // persistent driver on request only: its grid-wide barriers cost more
         // than kernel boundaries on this chip at every size measured (each
         // barrier serialises one same-address atomic per workgroup)
-        const bool want_persist = op->driver == 1 && op->lr_p == 0 && op->form == 0 && !op->dfn();
+        const bool want_persist = op->driver == 1 && op->lr_p == 0 && op->form == 0 && !op->dfn() && !op->perm;
         // true-residual check at convergence (default: mixed mode only)
         const bool verify = op->verify > 0 || (op->verify < 0 && op->mixed());
         size_t ev_i = 0;
@@ -1699,8 +1791,15 @@ pp_status pp_lowrank_set(pp_op op, int p, const double *V)
         const int64_t n = op->n;
         if (!op->lr_v) op->lr_v = dalloc<double>((size_t)ppk::LR_MAX * n);
         if (!op->lr_hinv) op->lr_hinv = dalloc<double>((size_t)ppk::LR_MAX * ppk::LR_MAX);
-        if (V != op->lr_v)
+        if (V != op->lr_v && op->perm) {
+            for (int j = 0; j < p; ++j)  // into the operator's numbering
+                hipLaunchKernelGGL(ppk::k_gather_scale, dim3(op->grid_elems(n)), dim3(BLOCK), 0, op->stream, n,
+                                   V + (size_t)j * n, (const int32_t *)op->perm, (const double *)nullptr, 1.0,
+                                   op->lr_v + (size_t)j * n);
+            HIPCHK(hipGetLastError());
+        } else if (V != op->lr_v) {
             HIPCHK(hipMemcpyAsync(op->lr_v, V, sizeof(double) * (size_t)p * n, hipMemcpyDeviceToDevice, op->stream));
+        }
         std::vector<double> hinv;
         if (!lowrank_hinv(op, p, op->lr_v, hinv)) {
             op->lr_p = 0;
@@ -1740,7 +1839,8 @@ pp_status pp_lowrank_ritz(pp_op op, int steps, int p, double *theta)
         if (poly) coef = dalloc<double>(ppk::LR_MAX);
         // the Lanczos recurrence of pp_estimate_bounds, keeping every basis vector
         hipLaunchKernelGGL(ppk::k_state_init, dim3(1), dim3(64), 0, op->stream, op->st, 0.0, 0);
-        hipLaunchKernelGGL(ppk::k_lz_start, dim3(ge), dim3(BLOCK), 0, op->stream, n, v, op->partials, op->st);
+        hipLaunchKernelGGL(ppk::k_lz_start, dim3(ge), dim3(BLOCK), 0, op->stream, n, v, op->partials, op->st,
+                           (const int32_t *)op->perm);
         enqueue_fin(op, ge, ppk::FIN_LZ_NORM0);
         hipLaunchKernelGGL(ppk::k_lz_norm, dim3(ge), dim3(BLOCK), 0, op->stream, n, v, (const ppk::State *)op->st);
         hipLaunchKernelGGL((ppk::k_scale<double, double>), dim3(ge), dim3(BLOCK), 0, op->stream, n,
@@ -1856,8 +1956,16 @@ pp_status pp_lowrank_get(pp_op op, int *p, double *V)
     *p = op->lr_p;
     if (V && op->lr_p > 0) {
         try {
-            HIPCHK(hipMemcpyAsync(V, op->lr_v, sizeof(double) * (size_t)op->lr_p * op->n, hipMemcpyDeviceToDevice,
-                                  op->stream));
+            if (op->perm) {
+                for (int j = 0; j < op->lr_p; ++j)  // back to the caller's numbering
+                    hipLaunchKernelGGL(ppk::k_scatter, dim3(op->grid_elems(op->n)), dim3(BLOCK), 0, op->stream,
+                                       op->n, (const double *)op->lr_v + (size_t)j * op->n,
+                                       (const int32_t *)op->perm, V + (size_t)j * op->n);
+                HIPCHK(hipGetLastError());
+            } else {
+                HIPCHK(hipMemcpyAsync(V, op->lr_v, sizeof(double) * (size_t)op->lr_p * op->n,
+                                      hipMemcpyDeviceToDevice, op->stream));
+            }
         } catch (HipError &e) {
             return hip_fail(e);
         }
@@ -1874,7 +1982,8 @@ pp_status pp_estimate_bounds(pp_op op, int steps, double *lambda_min, double *la
         const int gs = op->grid_slices(), ge = op->grid_elems(n);
         double *v = op->sA, *vprev = op->sB, *w = op->q;
         hipLaunchKernelGGL(ppk::k_state_init, dim3(1), dim3(64), 0, op->stream, op->st, 0.0, 0);
-        hipLaunchKernelGGL(ppk::k_lz_start, dim3(ge), dim3(BLOCK), 0, op->stream, n, v, op->partials, op->st);
+        hipLaunchKernelGGL(ppk::k_lz_start, dim3(ge), dim3(BLOCK), 0, op->stream, n, v, op->partials, op->st,
+                           (const int32_t *)op->perm);
         enqueue_fin(op, ge, ppk::FIN_LZ_NORM0);
         hipLaunchKernelGGL(ppk::k_lz_norm, dim3(ge), dim3(BLOCK), 0, op->stream, n, v, (const ppk::State *)op->st);
         hipLaunchKernelGGL((ppk::k_scale<double, double>), dim3(ge), dim3(BLOCK), 0, op->stream, n,

@@ -320,7 +320,7 @@ pp_status pp_features(pp_op op, int power_steps, double *f)
         double *v = op->sA, *w = op->sB, *y = op->q;
         for (int shifted = 0; shifted < 2; ++shifted) {
             hipLaunchKernelGGL(ppk::k_lz_start, dim3(ge), dim3(BLOCK), 0, op->stream, n, v, part,
-                               (ppk::State *)nullptr);
+                               (ppk::State *)nullptr, (const int32_t *)op->perm);
             for (int t = 0; t < power_steps; ++t) {
                 if (op->schur()) {
                     hipLaunchKernelGGL((ppk::k_trace<double, double>), dim3(op->grid_elems(op->nt)), dim3(BLOCK), 0,

@@ -347,7 +347,7 @@ pp_status pcg_solve_csr_noalloc(int64_t n, int64_t nnz, const int64_t *rowptr, c
             if (bad) return fail(PP_ERR_ARG, "pcg_solve_csr_noalloc: a diagonal entry is not positive");
         }
         hipLaunchKernelGGL(ppk::k_init_scale, dim3(ge), dim3(BLOCK), 0, c.s, n, b, (const double *)x,
-                           (const double *)c.dis, bh, xh, c.partials, c.st);
+                           (const double *)c.dis, bh, xh, c.partials, c.st, (const int32_t *)nullptr);
         na_fin(c, ppk::FIN_BNORM);
         na_csr<NA_RESID, true>(c, xh, bh, nullptr, r, none);
         na_fin(c, ppk::FIN_RR0);
@@ -376,7 +376,7 @@ pp_status pcg_solve_csr_noalloc(int64_t n, int64_t nnz, const int64_t *rowptr, c
             HIPCHK(hipStreamSynchronize(c.s));
         }
         hipLaunchKernelGGL(ppk::k_final_x, dim3(ge), dim3(BLOCK), 0, c.s, n, (const double *)xh,
-                           (const double *)c.dis, x, (const State *)c.st);
+                           (const double *)c.dis, x, (const State *)c.st, (const int32_t *)nullptr);
         HIPCHK(hipGetLastError());
         State hs;
         HIPCHK(hipMemcpyAsync(&hs, c.st, sizeof(State), hipMemcpyDeviceToHost, c.s));

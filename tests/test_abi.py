@@ -54,7 +54,7 @@ def test_argument_validation_without_device_work(B):
     assert L.pp_create_csr(None, 10, 10, None, None, None, 0, None) == B.PP_ERR_ARG
     assert L.pp_create_csr(C.byref(h), 0, 5, None, None, None, 0, None) == B.PP_ERR_ARG
     assert "positive" in B.pp_last_error()
-    assert L.pp_create_csr(C.byref(h), 10, 10, C.c_void_p(8), C.c_void_p(8), C.c_void_p(8), 8, None) == B.PP_ERR_ARG
+    assert L.pp_create_csr(C.byref(h), 10, 10, C.c_void_p(8), C.c_void_p(8), C.c_void_p(8), 64, None) == B.PP_ERR_ARG
     assert L.pp_create_schur(C.byref(h), 10, 10, C.c_void_p(8), C.c_void_p(8), C.c_void_p(8), 0, 0, None, None,
                              None, None, 0, None) == B.PP_ERR_ARG
     assert L.pp_setup(None, 3, 0.1, 1.0, 0.0) == B.PP_ERR_ARG
