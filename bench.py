@@ -383,12 +383,20 @@ def timed_solves(B, torch, h, bd, x, tol, maxit, warmup, runs):
     return float(np.median(times)), status, it, rel, st
 
 
-def sliced_roofline(n, nnz, st, k, what):
-    """Roofline record of the one-step kernel k_cheb on an operator held in the slice layout."""
-    sb = stored_bytes_per_step(n, st, k)
+def sliced_roofline(n, nnz, st, k, what, lds_tiles=0):
+    """Roofline record of the one-step kernel on an operator held in the slice layout: k_cheb_lt
+    (x staged in LDS per tile, 8-byte value + 2-byte staging index per slot, x read once per
+    tile) or k_cheb (8-byte value + 4-byte column per slot)."""
+    if lds_tiles:
+        npad = -(-n // 64) * 64
+        sb = 10 * st["nnz_stored"] + 8 * (npad // 64 + 1) + 8 * n * (4 * k - 3) / k
+        kern = "k_cheb_lt (fused SpMV + Chebyshev step, 64-row slices, x staged in LDS per tile, FP64): "
+    else:
+        sb = stored_bytes_per_step(n, st, k)
+        kern = "k_cheb (fused SpMV + Chebyshev step, 64-row slices, FP64): "
     us = st["step_us"]
     ach = sb / (us * 1e-6) / 1e9
-    return {"bound": "hbm", "kernel": "k_cheb (fused SpMV + Chebyshev step, 64-row slices, FP64): " + what,
+    return {"bound": "hbm", "kernel": kern + what,
             "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
             "bytes_per_launch": int(sb), "mean_launch_us": round(us, 2),
             "csr_equiv_gbs": round(cheb_bytes_per_step(n, nnz, k) / (us * 1e-6) / 1e9, 1),
@@ -408,7 +416,13 @@ def run_general(args, B, W, torch, dev, a, bd, lmin, lmax):
     x = torch.zeros(n, dtype=torch.float64, device=dev)
     ts, status, it, rel, st = timed_solves(B, torch, h, bd, x, args.tol, args.maxit, 1, runs)
     out["hetero256_sliced"] = dict(k=k, s_per_solve=ts, iters=it, relres=rel, status=B.pp_status_str(status),
-                                   roofline=sliced_roofline(n, nnz, st, k, "256^3 operator, every entry sliced"))
+                                   lds_tiles=st["lds_tiles"],
+                                   roofline=sliced_roofline(n, nnz, st, k, "256^3 operator, every entry sliced",
+                                                            st["lds_tiles"]))
+    if st["lds_tiles"]:
+        B.pp_set_option(h, B.PP_OPT_LDS_TILES, 0)
+        ts0, _, _, _, st0_ = timed_solves(B, torch, h, bd, x, args.tol, args.maxit, 1, runs)
+        out["hetero256_sliced"]["without_lds_tiles"] = dict(s_per_solve=ts0, step_us=st0_["step_us"])
     log("general: 256^3 sliced k=%d: %.3f s/solve, %d iters, step %.1f us (%.0f GB/s stored)"
         % (k, ts, it, st["step_us"], out["hetero256_sliced"]["roofline"]["achieved"]))
     B.pp_destroy(h)
@@ -428,13 +442,22 @@ def run_general(args, B, W, torch, dev, a, bd, lmin, lmax):
     bg = up(b)
     x = torch.zeros(g.n_rows, dtype=torch.float64, device=dev)
     ts, status, it, rel, st = timed_solves(B, torch, h, bg, x, args.tol, args.maxit, 1, runs)
+    no_lt = None
+    if st["lds_tiles"]:
+        B.pp_set_option(h, B.PP_OPT_LDS_TILES, 0)
+        ts0, _, _, _, st0_ = timed_solves(B, torch, h, bg, x, args.tol, args.maxit, 1, runs)
+        no_lt = dict(s_per_solve=ts0, step_us=st0_["step_us"])
+        B.pp_set_option(h, B.PP_OPT_LDS_TILES, 1)
     row_len = np.diff(g.rowptr)
     out["irregular"] = dict(workload="irregular_fe_%d^3_27pt_thinned0.8_window4096_jacobi" % args.general_N,
                             n=g.n_rows, nnz=g.nnz, row_len_min=int(row_len.min()), row_len_max=int(row_len.max()),
                             diagonals=st0["diagonals"], gen_s=round(t_gen, 1), create_s=round(t_create, 3),
                             bounds=[lo, hi], k=k, s_per_solve=ts, iters=it, relres=rel,
-                            status=B.pp_status_str(status),
-                            roofline=sliced_roofline(g.n_rows, g.nnz, st, k, "irregular operator, 4.1M rows"))
+                            status=B.pp_status_str(status), reordered=st0["reordered"],
+                            gather_spread=st0["gather_spread"], lds_tiles=st["lds_tiles"],
+                            without_lds_tiles=no_lt,
+                            roofline=sliced_roofline(g.n_rows, g.nnz, st, k, "irregular operator, 4.1M rows",
+                                                     st["lds_tiles"]))
     log("general: irregular n=%d nnz=%d (%d stored diagonals) k=%d: %.3f s/solve, %d iters, step %.1f us "
         "(%.0f GB/s stored)" % (g.n_rows, g.nnz, st0["diagonals"], k, ts, it, st["step_us"],
                                 out["irregular"]["roofline"]["achieved"]))

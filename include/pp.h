@@ -331,6 +331,8 @@ typedef struct {
                             /* when the true-residual check ran, else -1             */
     double gather_spread;   /* distinct 64-byte lines of x per stored entry that a   */
                             /* slice of 64 rows gathers (sampled; after renumbering) */
+    int32_t lds_tiles;      /* 1 when the FP64 steps stage x in LDS per tile         */
+    int32_t pad1;
 } pp_stats;
 
 PP_API pp_status pp_get_stats(pp_op op, pp_stats *st);
@@ -357,8 +359,13 @@ enum {
                             /* misses tol, CG restarts from the iterate (at most 3 times). */
                             /* 1 = on, 0 = off, -1 (default) = on in PP_MIXED mode only.   */
                             /* Costs one operator application when the check passes.       */
-    PP_OPT_RITZ = 8         /* pp_lowrank_ritz: 0 (default) Lanczos on A-hat, 1 Lanczos on   */
+    PP_OPT_RITZ = 8,        /* pp_lowrank_ritz: 0 (default) Lanczos on A-hat, 1 Lanczos on   */
                             /* p_k(A-hat) with full reorthogonalisation                    */
+    PP_OPT_LDS_TILES = 9    /* FP64 CSR operators held in slices only: 1 (default) = the    */
+                            /* Chebyshev steps stage the x segments of each tile of 1024  */
+                            /* rows in LDS and gather from there (tiles touching more     */
+                            /* than 6144 values of x gather from memory; create plans     */
+                            /* no tiles when over a tenth would), 0 = gather from memory  */
 };
 PP_API pp_status pp_set_option(pp_op op, int key, int64_t value);
 

@@ -17,7 +17,7 @@ PP_OK, PP_NOT_CONVERGED, PP_BREAKDOWN = 0, 1, 2
 PP_ERR_ARG, PP_ERR_OOM, PP_ERR_HIP, PP_ERR_STATE = -1, -2, -3, -4
 PP_JACOBI, PP_MIXED, PP_SLICED, PP_NO_REORDER = 1, 2, 4, 8
 PP_OPT_GRID, PP_OPT_CHUNK, PP_OPT_TIMING, PP_OPT_DRIVER, PP_OPT_NT_LOADS, PP_OPT_TWO_STEP, PP_OPT_VERIFY = 1, 2, 3, 4, 5, 6, 7
-PP_OPT_RITZ = 8
+PP_OPT_RITZ, PP_OPT_LDS_TILES = 8, 9
 
 PP_BOPT_GRAPH = 100
 
@@ -48,7 +48,7 @@ class pp_stats(C.Structure):
         ("nnz_stored", C.c_int64), ("nnz_matrix", C.c_int64), ("driver", C.c_int32),
         ("grid", C.c_int32), ("diagonals", C.c_int32), ("two_step", C.c_int32),
         ("pair_ms", C.c_double), ("pair_launches", C.c_int64), ("restarts", C.c_int32), ("reordered", C.c_int32),
-        ("true_relres", C.c_double), ("gather_spread", C.c_double),
+        ("true_relres", C.c_double), ("gather_spread", C.c_double), ("lds_tiles", C.c_int32), ("pad1", C.c_int32),
     ]
 
 

@@ -8,6 +8,7 @@
 #include "common.hpp"
 #include "dfn.hpp"
 #include "kernels.hpp"
+#include "ltile.hpp"
 
 constexpr int PP_GRID_DEFAULT = 2048;
 
@@ -54,6 +55,14 @@ struct pp_op_s {
     // renumbering chosen at create (reverse Cuthill-McKee), new -> old row; null = none
     int32_t *perm = nullptr;
     double spread[2] = {0.0, 0.0};  // gather spread of the slices before / after renumbering
+    // LDS-staged x tiles (ltile.hpp): slices-only FP64 operators whose tiles fit
+    int lt_on = 0;       // planned at create
+    int lt_use = 1;      // PP_OPT_LDS_TILES
+    int64_t lt_ntiles = 0;
+    int lt_cap = 0;
+    int32_t *lt_seg = nullptr;  // seg_ptr [ntiles+1], staged [ntiles], then seg_col, seg_lds, seg_len [nseg each]
+    uint16_t *lt_lcol = nullptr;
+    int64_t lt_nseg = 0;
     // work vectors
     double *xh = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr, *bh = nullptr;
     double *sA = nullptr, *sB = nullptr;
@@ -164,6 +173,19 @@ struct pp_op_s {
         for (int d = 0; d < ppk::DMAX; ++d) v.doff[d] = doff[d];
         return v;
     }
+    ppk::LtView ltview() const
+    {
+        ppk::LtView v;
+        v.ntiles = lt_ntiles;
+        v.cap = lt_cap;
+        v.seg_ptr = lt_seg;
+        v.staged = lt_seg + lt_ntiles + 1;
+        v.seg_col = v.staged + lt_ntiles;
+        v.seg_lds = v.seg_col + lt_nseg;
+        v.seg_len = v.seg_lds + lt_nseg;
+        v.lcol = lt_lcol;
+        return v;
+    }
     ppk::CsrView cview(bool f32) const
     {
         ppk::CsrView v;
@@ -179,7 +201,7 @@ struct pp_op_s {
         ppc::dfree(sp); ppc::dfree(scol); ppc::dfree(sval); ppc::dfree(sval32);
         ppc::dfree(dval); ppc::dfree(dval32);
         ppc::dfree(crp); ppc::dfree(ccol); ppc::dfree(cm); ppc::dfree(cm32); ppc::dfree(tw); ppc::dfree(tw32);
-        ppc::dfree(dis); ppc::dfree(perm);
+        ppc::dfree(dis); ppc::dfree(perm); ppc::dfree(lt_seg); ppc::dfree(lt_lcol);
         ppc::dfree(dfn_Lb); ppc::dfree(dfn_Q); ppc::dfree(dfn_ghc); ppc::dfree(dfn_ghv); ppc::dfree(dfn_t); ppc::dfree(dfn_d);
         for (int i = 0; i < 6; ++i) { ppc::dfree(dfn_rp[i]); ppc::dfree(dfn_col[i]); ppc::dfree(dfn_val[i]); }
         ppc::dfree(xh); ppc::dfree(r); ppc::dfree(p); ppc::dfree(q); ppc::dfree(z); ppc::dfree(bh); ppc::dfree(sA); ppc::dfree(sB);

@@ -12,6 +12,7 @@
 #include <string>
 #include <vector>
 
+#include <thread>
 #include "../../include/pp.h"
 #include "kernels.hpp"
 #include "op.hpp"
@@ -226,6 +227,109 @@ bool maybe_reorder(pp_op_s *op, const int64_t *rp, const int32_t *col, const dou
     return true;
 }
 
+// LDS-staged x tiles (ltile.hpp) for a CSR operator held in slices only, FP64:
+// per tile of LT_TS slices, the touched columns merged into segments (gaps
+// up to LT_GAP bridged) and a 16-bit staging index per stored slot.  A tile
+// that would stage more than LT_CAP values gathers from memory; lt_on stays 0
+// when more than a tenth of the tiles would, or when the lanes of a slot row
+// mostly read columns that are not consecutive: the staged reads then meet in
+// LDS banks (measured: a renumbered irregular operator ran 15 % slower staged,
+// the 7-point box in slices 6 % faster).  Tiles are planned on host threads.
+void plan_ltiles(pp_op_s *op)
+{
+    using ppk::LT_TS;
+    const int64_t ns = op->nslices, nst = op->nstored;
+    if (ns == 0 || nst == 0) return;
+    std::vector<int64_t> sp(ns + 1);
+    std::vector<int32_t> col(nst);
+    HIPCHK(hipMemcpyAsync(sp.data(), op->sp, sizeof(int64_t) * (ns + 1), hipMemcpyDeviceToHost, op->stream));
+    HIPCHK(hipMemcpyAsync(col.data(), op->scol, sizeof(int32_t) * nst, hipMemcpyDeviceToHost, op->stream));
+    HIPCHK(hipStreamSynchronize(op->stream));
+    const int64_t nt = (ns + LT_TS - 1) / LT_TS;
+    std::vector<std::vector<int32_t>> seg(nt);  // per tile: (first column, length) pairs
+    std::vector<uint16_t> lcol(nst);
+    std::vector<int> caps(nt, 0);
+    std::vector<int32_t> staged(nt, 1);
+    const int nth = (int)std::max<unsigned>(1, std::min<unsigned>(16, std::thread::hardware_concurrency()));
+    std::vector<int64_t> consec(nth, 0);  // lanes whose column follows the previous lane's
+    auto work = [&](int64_t ta, int64_t tb, int64_t *cons) {
+        std::vector<int32_t> c;
+        for (int64_t t = ta; t < tb; ++t) {
+            const int64_t e0 = sp[t * LT_TS], e1 = sp[std::min(ns, (t + 1) * LT_TS)];
+            for (int64_t e = e0 + 1; e < e1; ++e)
+                if ((e & 63) != 0 && col[e] == col[e - 1] + 1) ++*cons;
+            c.assign(col.begin() + e0, col.begin() + e1);
+            std::sort(c.begin(), c.end());
+            c.erase(std::unique(c.begin(), c.end()), c.end());
+            std::vector<int32_t> &s = seg[t];
+            int total = 0;
+            for (size_t i = 0; i < c.size();) {
+                size_t j = i;
+                while (j + 1 < c.size() && c[j + 1] - c[j] <= ppk::LT_GAP) ++j;
+                const int len = c[j] - c[i] + 1;
+                s.push_back(c[i]);
+                s.push_back(len);
+                total += len;
+                i = j + 1;
+            }
+            if (total > ppk::LT_CAP) {  // this tile gathers from memory
+                staged[t] = 0;
+                s.clear();
+                continue;
+            }
+            caps[t] = total;
+            // staging index of every slot: offset of its segment plus the column's place in it
+            for (int64_t e = e0; e < e1; ++e) {
+                const int32_t cv = col[e];
+                size_t lo = 0, hi = s.size() / 2;  // last segment starting at or before cv
+                while (hi - lo > 1) {
+                    const size_t mid = (lo + hi) / 2;
+                    if (s[2 * mid] <= cv) lo = mid; else hi = mid;
+                }
+                int off = 0;
+                for (size_t q = 0; q < lo; ++q) off += s[2 * q + 1];
+                lcol[e] = (uint16_t)(off + (cv - s[2 * lo]));
+            }
+        }
+    };
+    std::vector<std::thread> pool;
+    for (int k = 0; k < nth; ++k) pool.emplace_back(work, nt * k / nth, nt * (k + 1) / nth, &consec[k]);
+    for (auto &th : pool) th.join();
+    int64_t unstaged = 0, cons = 0;
+    for (int32_t f : staged) unstaged += f == 0;
+    for (int64_t v : consec) cons += v;
+    if (10 * unstaged > nt || 2 * cons < nst * 63 / 64) return;
+    std::vector<int32_t> seg_ptr(nt + 1, 0), seg_col, seg_lds, seg_len;
+    for (int64_t t = 0; t < nt; ++t) {
+        seg_ptr[t + 1] = seg_ptr[t] + (int32_t)(seg[t].size() / 2);
+        int off = 0;
+        for (size_t q = 0; q < seg[t].size(); q += 2) {
+            seg_col.push_back(seg[t][q]);
+            seg_lds.push_back(off);
+            seg_len.push_back(seg[t][q + 1]);
+            off += seg[t][q + 1];
+        }
+    }
+    const int64_t nseg = (int64_t)seg_col.size();
+    std::vector<int32_t> packed;
+    packed.reserve(2 * nt + 1 + 3 * nseg);
+    packed.insert(packed.end(), seg_ptr.begin(), seg_ptr.end());
+    packed.insert(packed.end(), staged.begin(), staged.end());
+    packed.insert(packed.end(), seg_col.begin(), seg_col.end());
+    packed.insert(packed.end(), seg_lds.begin(), seg_lds.end());
+    packed.insert(packed.end(), seg_len.begin(), seg_len.end());
+    op->lt_seg = dalloc<int32_t>(packed.size());
+    op->lt_lcol = dalloc<uint16_t>(nst);
+    HIPCHK(hipMemcpyAsync(op->lt_seg, packed.data(), sizeof(int32_t) * packed.size(), hipMemcpyHostToDevice,
+                          op->stream));
+    HIPCHK(hipMemcpyAsync(op->lt_lcol, lcol.data(), sizeof(uint16_t) * nst, hipMemcpyHostToDevice, op->stream));
+    HIPCHK(hipStreamSynchronize(op->stream));
+    op->lt_ntiles = nt;
+    op->lt_nseg = nseg;
+    op->lt_cap = *std::max_element(caps.begin(), caps.end());
+    op->lt_on = 1;
+}
+
 pp_status build_operator(pp_op_s *op, const int64_t *rp, const int32_t *col, const double *val,
                          const int64_t *c_rowptr, const int32_t *c_col, const double *c_val,
                          const double *m_diag)
@@ -310,6 +414,7 @@ pp_status build_operator(pp_op_s *op, const int64_t *rp, const int32_t *col, con
                            (const double *)op->dis, (const int64_t *)op->sp, op->scol, op->sval,
                            op->sval32);
         HIPCHK(hipGetLastError());
+        if (op->kind == 0 && op->nd == 0 && !op->mixed()) plan_ltiles(op);
         if (op->schur()) {
             const int64_t nt = op->nt;
             op->crp = dalloc<int64_t>(nt + 1);
@@ -362,6 +467,7 @@ pp_status build_operator(pp_op_s *op, const int64_t *rp, const int32_t *col, con
     op->stats.diagonals = op->nd;
     op->stats.nnz_matrix = op->nnz_given + op->nnz_c;
     op->stats.reordered = op->perm ? 1 : 0;
+    op->stats.lds_tiles = op->lt_on;
     op->stats.gather_spread = op->spread[1];
     return PP_OK;
 }
@@ -487,6 +593,18 @@ void launch_cheb(pp_op_s *op, const XT *xg, const T *w, const RT *r, const T *so
                  const StepCoef &c, int fin)
 {
     const bool f32 = sizeof(T) == 4;
+    if constexpr (sizeof(T) == 8 && sizeof(XT) == 8 && sizeof(RT) == 8 && sizeof(OT) == 8 && !SCHUR) {
+        if (op->lt_on && op->lt_use) {
+            // LDS-staged x tiles: one workgroup per tile range
+            const int g = (int)std::max<int64_t>(1, std::min<int64_t>(op->lt_ntiles, op->grid_max));
+            hipLaunchKernelGGL((ppk::k_cheb_lt<MODE, DOT, SCALE>), dim3(g), dim3(BLOCK),
+                               sizeof(double) * (size_t)op->lt_cap, op->stream, op->view(false), op->ltview(),
+                               (const double *)xg, (const double *)r, (const double *)sold, (double *)out, c.cx,
+                               c.cold, c.cr, c.cA, (const double *)op->dis, op->partials, op->st);
+            if (DOT && fin != ppk::FIN_NONE) enqueue_fin(op, g, fin);
+            return;
+        }
+    }
     struct FinAfter {
         pp_op_s *op;
         int fin;
@@ -1437,6 +1555,10 @@ pp_status pp_set_option(pp_op op, int key, int64_t value)
     case PP_OPT_RITZ:
         if (value < 0 || value > 1) return fail(PP_ERR_ARG, "PP_OPT_RITZ must be 0 or 1");
         op->ritz_poly = (int)value;
+        return PP_OK;
+    case PP_OPT_LDS_TILES:
+        if (value < 0 || value > 1) return fail(PP_ERR_ARG, "PP_OPT_LDS_TILES must be 0 or 1");
+        op->lt_use = (int)value;
         return PP_OK;
     default: return fail(PP_ERR_ARG, "unknown option");
     }
