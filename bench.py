@@ -475,14 +475,20 @@ def run_poisson32(args, B, W, torch, dev):
     B.pp_set_option(h, B.PP_OPT_TIMING, 1)
     B.pp_setup(h, 10, lo, hi, 0.0)
     x = torch.zeros(a.n_rows, dtype=torch.float64, device=dev)
+    # the default driver (persistent at this size) and the stream-driven kernels (with step events)
     ts, status, it, rel, st = timed_solves(B, torch, h, up(b), x, args.tol, args.maxit, 5, 20)
+    B.pp_set_option(h, B.PP_OPT_DRIVER, 0)
+    ts0, _, it0, _, st0 = timed_solves(B, torch, h, up(b), x, args.tol, args.maxit, 5, 20)
     B.pp_destroy(h)
-    eff = cheb_bytes_per_step(a.n_rows, a.nnz, 10) / (st["step_us"] * 1e-6) / 1e9
+    eff = cheb_bytes_per_step(a.n_rows, a.nnz, 10) / (st0["step_us"] * 1e-6) / 1e9
     out = dict(workload="poisson3d_32^3_k10", n=a.n_rows, nnz=a.nnz, bounds=[lo, hi], k=10, s_per_solve=ts,
-               iters=it, relres=rel, status=B.pp_status_str(status), step_us=st["step_us"],
-               effective_gbs_cache_resident=eff)
-    log("poisson32 k=10: %.2f ms/solve, %d iters, step %.1f us (%.0f GB/s effective, cache-resident)"
-        % (1000 * ts, it, st["step_us"], eff))
+               iters=it, relres=rel, status=B.pp_status_str(status),
+               driver="persistent" if st["driver"] == 1 else "stream", grid=st["grid"],
+               stream_driver=dict(s_per_solve=ts0, iters=it0, step_us=st0["step_us"],
+                                  effective_gbs_cache_resident=eff))
+    log("poisson32 k=10: %.2f ms/solve (%s driver, %d workgroups), %d iters; stream-driven %.2f ms, step %.1f us "
+        "(%.0f GB/s effective, cache-resident)" % (1000 * ts, out["driver"], st["grid"], it, 1000 * ts0,
+                                                   st0["step_us"], eff))
     return out
 
 

@@ -343,6 +343,9 @@ enum {
     PP_OPT_CHUNK = 2,       /* CG iterations queued between host convergence checks       */
     PP_OPT_TIMING = 3,      /* 1 = record events around the polynomial steps              */
     PP_OPT_DRIVER = 4,      /* 0 = stream-driven, 1 = persistent cooperative kernel, -1 = auto */
+                            /* (default: persistent for operators of at most 65536 rows   */
+                            /* whose polynomial runs single steps, on 8 to 32 workgroups, */
+                            /* stream-driven otherwise)                                   */
     PP_OPT_NT_LOADS = 5,    /* 1 = non-temporal accesses for the streams read once per step */
                             /* (the sliced matrix; r, s_{j-2} and the output with stored */
                             /* diagonals), 0 = plain; default 1 from 2^22 rows on       */

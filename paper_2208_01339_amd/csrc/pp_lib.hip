@@ -1042,6 +1042,9 @@ hipEvent_t timing_event(pp_op_s *op, size_t i)
 
 }  // namespace
 
+// operators of at most 1024 slices (65536 rows) take the persistent driver by default
+constexpr int64_t PERSIST_SMALL_SLICES = 1024;
+
 namespace {
 
 template <bool SCHUR, bool MIXED>
@@ -1079,6 +1082,12 @@ bool persistent_solve(pp_op_s *op, const double *b, double *x, double tol, int m
     }
     int G = (int)std::min<int64_t>({(int64_t)op->persist_occ[slot], (op->nslices + WPB - 1) / WPB, 8192,
                                     (int64_t)op->grid_max});
+    // A grid barrier costs about 0.1 us per workgroup (a same-address atomic
+    // each), so small operators run on few workgroups: 16 slices per
+    // workgroup, 8 to 32 of them (measured: Poisson 32^3 1.46 ms at 32
+    // workgroups, 2.85 ms at 128; 24^3 1.38 ms at 16).
+    if (op->nslices <= PERSIST_SMALL_SLICES && op->grid_max == op->grid_auto)
+        G = (int)std::min<int64_t>(G, std::max<int64_t>(8, std::min<int64_t>(32, op->nslices / 16)));
     if (G < 1) return false;
     const int k = op->k;
     if (op->coef_k != k) {
@@ -1722,10 +1731,12 @@ pp_status pcg_solve(pp_op op, const double *b, double *x, double tol, int maxit,
     if (!op->setup_done) return fail(PP_ERR_STATE, "pp_setup must be called before pcg_solve");
     try {
         HIPCHK(hipEventRecord(op->solve_ev[0], op->stream));
-        // persistent driver on request only: its grid-wide barriers cost more
-        // than kernel boundaries on this chip at every size measured (each
-        // barrier serialises one same-address atomic per workgroup)
-        const bool want_persist = op->driver == 1 && op->lr_p == 0 && op->form == 0 && !op->dfn() && !op->perm;
+        // persistent driver: on request, or by default for small operators whose
+        // polynomial runs single steps (few workgroups and cheap barriers beat
+        // a kernel boundary per step there; measured to 32^3)
+        const bool small = op->driver == -1 && op->nslices <= PERSIST_SMALL_SLICES && !use_pairs(op);
+        const bool want_persist = (op->driver == 1 || small) && op->lr_p == 0 && op->form == 0 && !op->dfn() &&
+                                  !op->perm;
         // true-residual check at convergence (default: mixed mode only)
         const bool verify = op->verify > 0 || (op->verify < 0 && op->mixed());
         size_t ev_i = 0;

@@ -187,6 +187,7 @@ def test_lowrank_clear_errors_and_driver(B):
     op = B.Operator(a=a, flags=B.PP_JACOBI)
     lmin, lmax = O.lanczos_bounds(orc, 20)
     B.pp_setup(op.handle, 8, lmin, lmax, 0.0)
+    B.pp_set_option(op.handle, B.PP_OPT_DRIVER, 0)  # the stream-driven solve is the reference below
     b = dev(W.rhs_uniform(a.n_rows, 4))
     x = torch.zeros(a.n_rows, dtype=torch.float64, device="cuda")
     s0, it0, _ = B.pcg_solve(op.handle, b, x, 1e-9, 500)
