@@ -78,6 +78,9 @@ sys.path.insert(0, ROOT)
 METRIC = "PCG time-to-1e-8 residual (s) + p_k(A)v HBM GB/s; mixed/batched vs plain FP64"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_SUMMARY = "k_cheb2_stencil_fp64_hetero256_k20_hbm_counters.txt"
+SLICED_TRAFFIC = {1: "k_cheb_lt_fp64_sliced256_k20_hbm_counters.txt",
+                  0: "k_cheb_fp64_sliced256_plain_k20_hbm_counters.txt"}
+IRREGULAR_TRAFFIC = "k_cheb_fp64_irregular160_k20_hbm_counters.txt"
 
 
 def log(*a):
@@ -417,8 +420,10 @@ def run_general(args, B, W, torch, dev, a, bd, lmin, lmax):
     ts, status, it, rel, st = timed_solves(B, torch, h, bd, x, args.tol, args.maxit, 1, runs)
     out["hetero256_sliced"] = dict(k=k, s_per_solve=ts, iters=it, relres=rel, status=B.pp_status_str(status),
                                    lds_tiles=st["lds_tiles"],
-                                   roofline=sliced_roofline(n, nnz, st, k, "256^3 operator, every entry sliced",
-                                                            st["lds_tiles"]))
+                                   roofline=with_traffic(
+                                       sliced_roofline(n, nnz, st, k, "256^3 operator, every entry sliced",
+                                                       st["lds_tiles"]),
+                                       committed_traffic(args, n, k, SLICED_TRAFFIC[st["lds_tiles"]])))
     if st["lds_tiles"]:
         B.pp_set_option(h, B.PP_OPT_LDS_TILES, 0)
         ts0, _, _, _, st0_ = timed_solves(B, torch, h, bd, x, args.tol, args.maxit, 1, runs)
@@ -456,8 +461,11 @@ def run_general(args, B, W, torch, dev, a, bd, lmin, lmax):
                             status=B.pp_status_str(status), reordered=st0["reordered"],
                             gather_spread=st0["gather_spread"], lds_tiles=st["lds_tiles"],
                             without_lds_tiles=no_lt,
-                            roofline=sliced_roofline(g.n_rows, g.nnz, st, k, "irregular operator, 4.1M rows",
-                                                     st["lds_tiles"]))
+                            roofline=with_traffic(
+                                sliced_roofline(g.n_rows, g.nnz, st, k, "irregular operator, %.1fM rows"
+                                                % (g.n_rows / 1e6), st["lds_tiles"]),
+                                None if st["lds_tiles"] else committed_traffic(args, g.n_rows, k,
+                                                                               IRREGULAR_TRAFFIC)))
     log("general: irregular n=%d nnz=%d (%d stored diagonals) k=%d: %.3f s/solve, %d iters, step %.1f us "
         "(%.0f GB/s stored)" % (g.n_rows, g.nnz, st0["diagonals"], k, ts, it, st["step_us"],
                                 out["irregular"]["roofline"]["achieved"]))
@@ -640,21 +648,31 @@ def lowrank_leg(B, torch, h, bd, x, k, lmin, lmax, tol, maxit, ranks=(1, 4), xis
     return rows
 
 
-def committed_traffic(args, n, k):
-    """HBM bytes per fused-step launch from the committed rocprofv3 counter summary.
+def committed_traffic(args, n, k, summary=TRAFFIC_SUMMARY):
+    """HBM bytes per launch (per step for one-step kernels) from a committed
+    rocprofv3 counter summary under profiles/.
 
     Null unless the summary was taken on this workload and degree from the
-    kernel sources that are built now (same source digest).
+    kernel sources that are built now (same source digest), with the default
+    launch options.
     """
     from paper_2208_01339_amd import profsum
 
-    summ = profsum.read_summary(os.path.join(ROOT, "profiles", TRAFFIC_SUMMARY))
+    summ = profsum.read_summary(os.path.join(ROOT, "profiles", summary))
     try:
         ok = (summ.get("source_digest") == profsum.source_digest() and int(summ.get("n", -1)) == n
               and int(summ.get("k", -1)) == k and args.grid == 0 and args.nt_loads < 0 and args.xi == 0.0)
         return float(summ["traffic_bytes_per_launch"]) if ok else None
     except (KeyError, ValueError):
         return None
+
+
+def with_traffic(roof, traffic):
+    """Adds the counter-measured HBM bytes per launch (or null) to a roofline record."""
+    us = roof["mean_launch_us"]
+    roof["traffic"] = round(traffic) if traffic else None
+    roof["traffic_gbs"] = round(traffic / (us * 1e-6) / 1e9, 1) if traffic else None
+    return roof
 
 
 def main():

@@ -24,8 +24,8 @@ import re
 import statistics
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-DIGEST_FILES = ("csrc/kernels.hpp", "csrc/op.hpp", "csrc/dfn.hpp", "csrc/common.hpp", "csrc/dia_plan.hpp", "csrc/stencil2.hpp",
-                "csrc/lowrank.hpp", "csrc/pp_lib.hip",
+DIGEST_FILES = ("csrc/kernels.hpp", "csrc/op.hpp", "csrc/dfn.hpp", "csrc/common.hpp", "csrc/dia_plan.hpp",
+                "csrc/stencil2.hpp", "csrc/lowrank.hpp", "csrc/ltile.hpp", "csrc/reorder.hpp", "csrc/pp_lib.hip",
                 "build.py")
 
 
