@@ -71,27 +71,47 @@ static __global__ __launch_bounds__(BS) void k_cheb2_stencil(Stencil2 g, const T
     T s_c[MM], s_m[MM];  // s_{j-1} on planes z and z-1
     T u3p[MM];           // coupling of plane z-1 to plane z (= the -z coupling of plane z)
     T v0p[MM], rp[MM], sjp[MM], part[MM];  // plane z-1: diagonal, r, s_j, partial (A s_j)
+    // Every global load of a plane is issued before the first use of any of
+    // them: indices are clamped to a valid row (0) where a cell is absent and
+    // the values are masked where they are used, so the loads form one
+    // branch-free block and are in flight together.
 #pragma unroll
     for (int m = 0; m < MM; ++m) {
         const int64_t c = threadIdx.x + (int64_t)BS * m;
         const int64_t ly = c / N, x = c - ly * N, y = y0 + ly;
         const bool rowok = c < cells && y >= 0 && y < N;
         const int64_t za = z0 - 1, zb = z0 - 2;
-        s_c[m] = rowok && za >= 0 ? sm1[x + N * (y + N * za)] : (T)0;
-        s_m[m] = rowok && zb >= 0 ? sm1[x + N * (y + N * zb)] : (T)0;
-        u3p[m] = rowok && zb >= 0 ? dv[3 * ds + x + N * (y + N * zb)] : (T)0;
-        v0p[m] = rp[m] = sjp[m] = part[m] = (T)0;
-        if constexpr (SL)
-            if (c < cells) ((T *)s2_lds + 2 * cells)[c + N] = s_c[m];
+        const int64_t ia = rowok && za >= 0 ? x + N * (y + N * za) : 0;
+        const int64_t ib = rowok && zb >= 0 ? x + N * (y + N * zb) : 0;
+        s_c[m] = sm1[ia];
+        s_m[m] = sm1[ib];
+        u3p[m] = dv[3 * ds + ib];
     }
     // s_{j-1} planes in LDS (SL): rows -1 .. S2_RY of the tile, two buffers
     T *const sl0 = (T *)s2_lds + 2 * cells;
     const int64_t scells = cells + 2 * N;
+    static_assert(2 * S2_NMAX <= BS, "one halo cell per thread");
+    T hx0 = (T)0;
     if constexpr (SL) {
-        for (int64_t e = threadIdx.x; e < 2 * N; e += BS) {
-            const int64_t row = e < N ? -1 : S2_RY, x = e < N ? e : e - N, y = y0 + row, za = z0 - 1;
-            sl0[(row + 1) * N + x] = y >= 0 && y < N && za >= 0 ? sm1[x + N * (y + N * za)] : (T)0;
-        }
+        const int64_t e = threadIdx.x, row = e < N ? -1 : S2_RY, x = e < N ? e : e - N, y = y0 + row;
+        const int64_t za = z0 - 1;
+        hx0 = sm1[e < 2 * N && y >= 0 && y < N && za >= 0 ? x + N * (y + N * za) : 0];
+    }
+#pragma unroll
+    for (int m = 0; m < MM; ++m) {
+        const int64_t c = threadIdx.x + (int64_t)BS * m;
+        const int64_t ly = c / N, y = y0 + ly;
+        const bool rowok = c < cells && y >= 0 && y < N;
+        s_c[m] = rowok && z0 - 1 >= 0 ? s_c[m] : (T)0;
+        s_m[m] = rowok && z0 - 2 >= 0 ? s_m[m] : (T)0;
+        u3p[m] = rowok && z0 - 2 >= 0 ? u3p[m] : (T)0;
+        v0p[m] = rp[m] = sjp[m] = part[m] = (T)0;
+        if constexpr (SL)
+            if (c < cells) sl0[c + N] = s_c[m];
+    }
+    if constexpr (SL) {
+        const int64_t e = threadIdx.x, row = e < N ? -1 : S2_RY, x = e < N ? e : e - N, y = y0 + row;
+        if (e < 2 * N) sl0[(row + 1) * N + x] = y >= 0 && y < N && z0 - 1 >= 0 ? hx0 : (T)0;
         __syncthreads();
     }
     int buf = 0;
@@ -99,56 +119,83 @@ static __global__ __launch_bounds__(BS) void k_cheb2_stencil(Stencil2 g, const T
         const bool zin = zz >= 0 && zz < NZ;
         const bool fin2 = zz - 1 >= z0 && zz - 1 < z1;  // finish s_{j+1} on plane zz-1
         const bool part_now = zz >= z0 && zz < z1;      // partial sums for plane zz
+        const bool zl = zz > 0, zu = zz + 1 < NZ;
         T *pl = (T *)s2_lds + buf * cells;
-        T cur[MM], xp[MM], nl1[MM], nu1[MM], nl2[MM], nu2[MM], nv0[MM], nu3[MM], nr[MM];
+        // the plane's global loads: operator row, r, s_{j-2} on plane zz, s_{j-1} on plane zz+1
+        T v0[MM], u1[MM], u2[MM], u3[MM], l1[MM], l2[MM], ri[MM], so[MM], xp[MM];
+#pragma unroll
+        for (int m = 0; m < MM; ++m) {
+            const int64_t c = threadIdx.x + (int64_t)BS * m;
+            const int64_t ly = c / N, x = c - ly * N, y = y0 + ly;
+            const bool rowok = c < cells && y >= 0 && y < N;
+            const bool ok = rowok && zin;
+            const int64_t i = ok ? x + N * (y + N * zz) : 0;
+            v0[m] = dv[i];
+            u1[m] = dv[ds + i];
+            u2[m] = dv[2 * ds + i];
+            u3[m] = dv[3 * ds + i];
+            l1[m] = dv[ds + (ok && x > 0 ? i - 1 : i)];
+            l2[m] = dv[2 * ds + (ok && y > 0 ? i - N : i)];
+            ri[m] = r[i];
+            so[m] = ldm<NT>(sm2 + i);
+            xp[m] = sm1[rowok && zu ? x + N * (y + N * (zz + 1)) : 0];
+        }
+        T hx = (T)0;  // s_{j-1} on the halo rows -1 and S2_RY of plane zz+1 (SL)
+        if constexpr (SL) {
+            const int64_t e = threadIdx.x, row = e < N ? -1 : S2_RY, x = e < N ? e : e - N, y = y0 + row;
+            hx = sm1[e < 2 * N && y >= 0 && y < N && zu ? x + N * (y + N * (zz + 1)) : 0];
+        }
+        // s_j on plane zz for every owned cell (branch-free, so that the LDS
+        // reads of all cells are in flight together; absent cells give 0)
+        T cur[MM];
+#pragma unroll
+        for (int m = 0; m < MM; ++m) {
+            const int64_t c = threadIdx.x + (int64_t)BS * m;
+            const int64_t ly = c / N, x = c - ly * N, y = y0 + ly;
+            const bool rowok = c < cells && y >= 0 && y < N;
+            const bool ok = rowok && zin;
+            const int64_t i = ok ? x + N * (y + N * zz) : 0;
+            const bool xl = x > 0, xu = x + 1 < N, yl = y > 0, yu = y + 1 < N;
+            T x1m, x1p, x2m, x2p;
+            if constexpr (SL) {
+                const T *sp = sl0 + buf * scells + (ok ? c : 0) + N;
+                x1m = sp[ok && xl ? -1 : 0];
+                x1p = sp[ok && xu ? 1 : 0];
+                x2m = sp[-N];
+                x2p = sp[N];
+            } else {
+                x1m = sm1[ok && xl ? i - 1 : i];
+                x1p = sm1[ok && xu ? i + 1 : i];
+                x2m = sm1[ok && yl ? i - N : i];
+                x2p = sm1[ok && yu ? i + N : i];
+            }
+            const T xs = s_c[m];
+            const T xpm = rowok && zu ? xp[m] : (T)0;
+            T acc = (T)0;
+            acc += (xl ? l1[m] : (T)0) * x1m;
+            acc += (xu ? u1[m] : (T)0) * x1p;
+            acc += (yl ? l2[m] : (T)0) * x2m;
+            acc += (yu ? u2[m] : (T)0) * x2p;
+            acc += (zl ? u3p[m] : (T)0) * s_m[m];
+            acc += (zu ? u3[m] : (T)0) * xpm;
+            const T a = acc + v0[m] * xs;
+            T o = a1A * a + a1r * ri[m];
+            o += a1x * xs;
+            o += a1o * so[m];
+            cur[m] = ok ? o : (T)0;
+        }
+        // stores of s_j (plane zz) and s_{j+1} (plane zz-1); LDS copies for the next phase
 #pragma unroll
         for (int m = 0; m < MM; ++m) {
             const int64_t c = threadIdx.x + (int64_t)BS * m;
             const int64_t ly = c / N, x = c - ly * N, y = y0 + ly;
             const bool rowok = c < cells && y >= 0 && y < N;
             const bool interior = ly >= 1 && ly <= S2_TY && rowok;
-            T sj = (T)0;
-            xp[m] = rowok && zz + 1 < NZ ? sm1[x + N * (y + N * (zz + 1))] : (T)0;
-            nl1[m] = nu1[m] = nl2[m] = nu2[m] = nv0[m] = nu3[m] = nr[m] = (T)0;
-            if (rowok && zin) {
+            const T sj = cur[m];
+            if (interior && zz >= z0 && zz < z1) {
                 const int64_t i = x + N * (y + N * zz);
-                const bool xl = x > 0, xu = x + 1 < N, yl = y > 0, yu = y + 1 < N, zl = zz > 0, zu = zz + 1 < NZ;
-                const T v0 = dv[i];
-                const T u1 = dv[ds + i], u2 = dv[2 * ds + i], u3 = dv[3 * ds + i];
-                const T l1 = dv[ds + (xl ? i - 1 : i)], l2 = dv[2 * ds + (yl ? i - N : i)];
-                const T ri = r[i];
-                const T so = ldm<NT>(sm2 + i);
-                T x1m, x1p, x2m, x2p;
-                if constexpr (SL) {
-                    const T *sp = sl0 + buf * scells + c + N;
-                    x1m = sp[xl ? -1 : 0];
-                    x1p = sp[xu ? 1 : 0];
-                    x2m = sp[-N];
-                    x2p = sp[N];
-                } else {
-                    x1m = sm1[xl ? i - 1 : i];
-                    x1p = sm1[xu ? i + 1 : i];
-                    x2m = sm1[yl ? i - N : i];
-                    x2p = sm1[yu ? i + N : i];
-                }
-                const T xs = s_c[m];
-                T acc = (T)0;
-                acc += (xl ? l1 : (T)0) * x1m;
-                acc += (xu ? u1 : (T)0) * x1p;
-                acc += (yl ? l2 : (T)0) * x2m;
-                acc += (yu ? u2 : (T)0) * x2p;
-                acc += (zl ? u3p[m] : (T)0) * s_m[m];
-                acc += (zu ? u3 : (T)0) * xp[m];
-                const T a = acc + v0 * xs;
-                T o = a1A * a + a1r * ri;
-                o += a1x * xs;
-                o += a1o * so;
-                sj = o;
-                if (interior && zz >= z0 && zz < z1) {
-                    if constexpr (NT) __builtin_nontemporal_store(sj, out1 + i);
-                    else out1[i] = sj;
-                }
-                nl1[m] = l1; nu1[m] = u1; nl2[m] = l2; nu2[m] = u2; nv0[m] = v0; nu3[m] = u3; nr[m] = ri;
+                if constexpr (NT) __builtin_nontemporal_store(sj, out1 + i);
+                else out1[i] = sj;
             }
             if (fin2 && interior) {
                 const int64_t i2 = x + N * (y + N * (zz - 1));
@@ -161,39 +208,38 @@ static __global__ __launch_bounds__(BS) void k_cheb2_stencil(Stencil2 g, const T
                 else out2[i2] = o2;
                 if constexpr (DOT) dotp += (double)rp[m] * (double)o2;
             }
-            cur[m] = sj;
             if (c < cells) pl[c] = sj;
             if constexpr (SL)
-                if (c < cells) sl0[(buf ^ 1) * scells + c + N] = xp[m];
+                if (c < cells) sl0[(buf ^ 1) * scells + c + N] = rowok && zu ? xp[m] : (T)0;
         }
         if constexpr (SL) {
-            for (int64_t e = threadIdx.x; e < 2 * N; e += BS) {
-                const int64_t row = e < N ? -1 : S2_RY, x = e < N ? e : e - N, y = y0 + row;
-                sl0[(buf ^ 1) * scells + (row + 1) * N + x] =
-                    y >= 0 && y < N && zz + 1 < NZ ? sm1[x + N * (y + N * (zz + 1))] : (T)0;
-            }
+            const int64_t e = threadIdx.x, row = e < N ? -1 : S2_RY, x = e < N ? e : e - N, y = y0 + row;
+            if (e < 2 * N) sl0[(buf ^ 1) * scells + (row + 1) * N + x] = y >= 0 && y < N && zu ? hx : (T)0;
         }
         __syncthreads();
+        // partial sums of (A s_j) on plane zz (branch-free; cells outside give 0)
 #pragma unroll
         for (int m = 0; m < MM; ++m) {
             const int64_t c = threadIdx.x + (int64_t)BS * m;
             const int64_t ly = c / N, x = c - ly * N, y = y0 + ly;
+            const bool rowok = c < cells && y >= 0 && y < N;
+            const bool ok = rowok && zin;
+            const bool pc = part_now && ly >= 1 && ly <= S2_TY && c < cells && y < N;
+            const int64_t cc = pc ? c : N;  // rows 1 .. S2_TY: c - N and c + N stay inside the plane
+            const bool xl = x > 0, xu = x + 1 < N, yl = y > 0, yu = y + 1 < N;
             T pn = (T)0;
-            if (part_now && ly >= 1 && ly <= S2_TY && c < cells && y < N) {
-                const bool xl = x > 0, xu = x + 1 < N, yl = y > 0, yu = y + 1 < N, zl = zz > 0;
-                pn += (xl ? nl1[m] : (T)0) * pl[xl ? c - 1 : c];
-                pn += (xu ? nu1[m] : (T)0) * pl[xu ? c + 1 : c];
-                pn += (yl ? nl2[m] : (T)0) * pl[c - N];
-                pn += (yu ? nu2[m] : (T)0) * pl[c + N];
-                pn += (zl ? u3p[m] : (T)0) * sjp[m];
-            }
-            part[m] = pn;
-            v0p[m] = nv0[m];
-            rp[m] = nr[m];
+            pn += (xl ? l1[m] : (T)0) * pl[pc && xl ? cc - 1 : cc];
+            pn += (xu ? u1[m] : (T)0) * pl[pc && xu ? cc + 1 : cc];
+            pn += (yl ? l2[m] : (T)0) * pl[cc - N];
+            pn += (yu ? u2[m] : (T)0) * pl[cc + N];
+            pn += (zl ? u3p[m] : (T)0) * sjp[m];
+            part[m] = pc ? pn : (T)0;
+            v0p[m] = ok ? v0[m] : (T)0;
+            rp[m] = ok ? ri[m] : (T)0;
             sjp[m] = cur[m];
-            u3p[m] = nu3[m];
+            u3p[m] = ok ? u3[m] : (T)0;
             s_m[m] = s_c[m];
-            s_c[m] = xp[m];
+            s_c[m] = rowok && zu ? xp[m] : (T)0;
         }
         buf ^= 1;
     }
