@@ -74,6 +74,7 @@ struct pp_op_s {
     int cus = 256;     // compute units of the device (pair launches want one workgroup per CU)
     int64_t s2N = 0, s2NZ = 0;
     double *sC = nullptr, *sD = nullptr;
+    float *sC32 = nullptr, *sD32 = nullptr;  // the same in mixed mode
     double *partials = nullptr;  // (1 + LR_MAX) * 8192 doubles
     // spectral low-rank correction: V (n x lr_p, column-major), (V^T A V)^{-1}
     int lr_p = 0;
@@ -207,6 +208,7 @@ struct pp_op_s {
         ppc::dfree(xh); ppc::dfree(r); ppc::dfree(p); ppc::dfree(q); ppc::dfree(z); ppc::dfree(bh); ppc::dfree(sA); ppc::dfree(sB);
         ppc::dfree(r32); ppc::dfree(sA32); ppc::dfree(sB32);
         ppc::dfree(sC); ppc::dfree(sD);
+        ppc::dfree(sC32); ppc::dfree(sD32);
         ppc::dfree(partials); ppc::dfree(coef_d); ppc::dfree(st);
         ppc::dfree(lr_v); ppc::dfree(lr_hinv); ppc::dfree(nbuf);
         if (hst) (void)hipHostFree(hst);

@@ -534,9 +534,14 @@ pp_status create_common(pp_op *out, int kind, int64_t n, int64_t nnz, const int6
             HIPCHK(hipMemcpyAsync(&h, bad, sizeof(int), hipMemcpyDeviceToHost, op->stream));
             HIPCHK(hipStreamSynchronize(op->stream));
             dfree(bad);
-            if (!h && !op->mixed()) {
-                op->sC = dalloc<double>(n);
-                op->sD = dalloc<double>(n);
+            if (!h) {
+                if (op->mixed()) {
+                    op->sC32 = dalloc<float>(n);
+                    op->sD32 = dalloc<float>(n);
+                } else {
+                    op->sC = dalloc<double>(n);
+                    op->sD = dalloc<double>(n);
+                }
                 op->s2 = true;
                 op->s2N = op->doff[2];
                 op->s2NZ = n / op->doff[3];
@@ -788,7 +793,7 @@ ppk::Stencil2 pair_shape(const pp_op_s *op)
 // a 3-D 7-point box large enough, or forced)
 bool use_pairs(const pp_op_s *op)
 {
-    return op->s2 && op->two_step != 0 && op->form == 0 && !op->mixed() && pair_shape(op).zc > 0;
+    return op->s2 && op->two_step != 0 && op->form == 0 && pair_shape(op).zc > 0;
 }
 
 template <typename T>
@@ -843,7 +848,9 @@ void enqueue_poly_pairs(pp_op_s *op, const double *rr, const T *rT, T *const (&b
                         bool scale)
 {
     const int k = op->k;
-    const bool last_pair = !scale && k % 2 == 0 && pair_grid(op) <= 8192;  // partials hold 8192 per column
+    // the last pair writes z only in FP64 (in mixed mode the last step is single:
+    // it reads r and writes z in FP64); partials hold 8192 per column
+    const bool last_pair = sizeof(T) == 8 && !scale && k % 2 == 0 && pair_grid(op) <= 8192;
     int ic = -1, io = -1;  // buffers of s_{j-1} and s_{j-2} (-1: r)
     int j = 1;
     const bool timed = op->time_pairs;
@@ -888,9 +895,7 @@ void enqueue_poly(pp_op_s *op, const double *rr, double *zout, int fin, bool sca
         return;
     }
     const int k = op->k;
-    // fused pairs in FP64 only: in FP32 the bytes saved do not pay for the halo
-    // rows and the lower occupancy (measured)
-    if (k >= 4 && use_pairs(op)) {
+    if (k >= 4 && use_pairs(op) && !op->mixed()) {
         double *const buf[4] = {op->sA, op->sB, op->sC, op->sD};
         enqueue_poly_pairs<double>(op, rr, rr, buf, zout, fin, scale);
         return;
@@ -930,6 +935,11 @@ void enqueue_poly(pp_op_s *op, const double *rr, double *zout, int fin, bool sca
     // mixed: r32 = (float) rr, steps in FP32, last step writes FP64 z
     hipLaunchKernelGGL((ppk::k_scale<double, float>), dim3(op->grid_elems(op->n)), dim3(BLOCK), 0, op->stream,
                        op->n, rr, (const double *)nullptr, 1.0, op->r32);
+    if (k >= 4 && use_pairs(op)) {
+        float *const buf[4] = {op->sA32, op->sB32, op->sC32, op->sD32};
+        enqueue_poly_pairs<float>(op, rr, op->r32, buf, zout, fin, scale);
+        return;
+    }
     for (int j = 1; j <= k; ++j) {
         const StepCoef c = step_coef(op, j);
         const bool last = (j == k);

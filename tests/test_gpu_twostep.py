@@ -1,9 +1,9 @@
 """GPU checks of the fused pairs of Chebyshev steps on 3-D 7-point operators.
 
 The pair kernel computes the same terms per row as the one-step kernels, so
-p_k(A) r with pairs and without them agree to a few ulps (relative 1e-14,
-FP64; the FP32 mixed mode keeps one pass per step), and both match the oracle's Algorithm 2
-to 1e-12.  Box shapes cover ragged y-tiles (tiles of 8 lines: remainders of
+p_k(A) r with pairs and without them agree to a few ulps (relative 1e-14
+in FP64), and both match the oracle's Algorithm 2 to 1e-12; in the FP32 mixed
+mode they agree within FP32 rounding.  Box shapes cover ragged y-tiles (tiles of 8 lines: remainders of
 5 and 7), z-ranges that are not whole chunks of 32 planes (37 planes; 33,
 so that the last chunk holds one plane), and boxes that are not cubes
 (principal blocks of the first z-planes).
@@ -79,11 +79,43 @@ def test_pairs_match_single_steps_and_oracle(B, name, k, xi):
     op.close()
 
 
-def test_mixed_mode_keeps_single_steps(B):
-    """The FP32 polynomial runs one pass per step (fused pairs are FP64 only)."""
-    a = W.hetero_diffusion(21, 2.0, 5)
-    op = B.Operator(a=a, flags=B.PP_JACOBI | B.PP_MIXED)
-    assert B.pp_get_stats(op.handle)["two_step"] == 0
+@pytest.mark.parametrize("k", [4, 7, 20])
+@pytest.mark.parametrize("name", ["hetero37", "box40x40x33"])
+def test_mixed_pairs(B, name, k):
+    """Mixed mode runs the pairs in FP32 too; its last step stays single (it reads
+    r and writes z in FP64).  p_k(A) r with FP32 pairs against the FP32 single
+    steps and against the oracle within FP32 rounding (the bound of the mixed
+    pp_apply test, 1e-4; the two FP32 forms differ only in rounding, 1e-5);
+    PCG: FP64 true scaled residual <= 1e-8, iterations within 2 of the FP64 oracle."""
+    build, jac = CASES[name]
+    a = build()
+    op = B.Operator(a=a, flags=(B.PP_JACOBI if jac else 0) | B.PP_MIXED)
+    B.pp_set_option(op.handle, B.PP_OPT_TWO_STEP, 2)
+    assert B.pp_get_stats(op.handle)["two_step"] == 1
+    orc = O.Operator(a, jacobi=jac)
+    lmin, lmax = O.lanczos_bounds(orc, 20)
+    B.pp_setup(op.handle, k, lmin, lmax, 1e-3)
+    r = W.rhs_uniform(a.n_rows, 7)
+    z2 = torch.empty(a.n_rows, dtype=torch.float64, device="cuda")
+    z1 = torch.empty_like(z2)
+    B.pp_apply(op.handle, dev(r), z2)
+    B.pp_set_option(op.handle, B.PP_OPT_TWO_STEP, 0)
+    B.pp_apply(op.handle, dev(r), z1)
+    g2, g1 = host(z2), host(z1)
+    ref = O.cheb_apply(orc, k, lmin, lmax, 1e-3, r)
+    assert np.linalg.norm(g2 - g1) <= 1e-5 * np.linalg.norm(g1)
+    assert np.linalg.norm(g2 - ref) <= 1e-4 * np.linalg.norm(ref)
+    B.pp_set_option(op.handle, B.PP_OPT_TWO_STEP, 2)
+    b = W.rhs_uniform(a.n_rows, 1)
+    xo, sto = O.pcg(orc, k, lmin, lmax, 1e-3, b, tol=1e-8, maxit=2000)
+    x = torch.zeros(a.n_rows, dtype=torch.float64, device="cuda")
+    s, it, rel = B.pcg_solve(op.handle, dev(b), x, 1e-8, 2000)
+    assert s == B.PP_OK and abs(it - sto["iters"]) <= 2, (it, sto["iters"])
+    res = orc.apply_raw(host(x)) - b
+    bb = b
+    if jac:
+        res, bb = res * orc.dis, b * orc.dis
+    assert np.linalg.norm(res) / np.linalg.norm(bb) <= 1e-8
     op.close()
 
 
