@@ -864,13 +864,17 @@ def main():
             % (tol_u, itu, tu, tru))
 
     bps = cheb_bytes_per_step(n, nnz, kh)
-    storage = "%d symmetric stored diagonals + %d sliced entries" % (st0["diagonals"], st0["nnz_stored"])
+    storage = "%d symmetric stored diagonals%s + %d sliced entries" % (
+        st0["diagonals"], " (the main one exactly 1 after Jacobi scaling, not read by the pairs)"
+        if st0["unit_diagonal"] else "", st0["nnz_stored"])
     if best["pair_launch_us"]:
         # two steps per launch; the operator (stored diagonals) is read once for both
         launch_us = best["pair_launch_us"]
         lb = 2 * bps
         npad = -(-n // 64) * 64
-        sb = 8 * st0["diagonals"] * npad + 5 * 8 * n  # reads r, s_{j-1}, s_{j-2}; writes s_j, s_{j+1}
+        # the stored diagonals once (a unit main diagonal is not read), r, s_{j-1}, s_{j-2}
+        # read, s_j and s_{j+1} written
+        sb = 8 * (st0["diagonals"] - st0["unit_diagonal"]) * npad + 5 * 8 * n
         kern = "k_cheb2_stencil (two fused Chebyshev steps per launch, FP64, symmetric stored diagonals)"
         traffic = committed_traffic(args, n, kh)
     else:

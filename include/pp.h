@@ -332,7 +332,9 @@ typedef struct {
     double gather_spread;   /* distinct 64-byte lines of x per stored entry that a   */
                             /* slice of 64 rows gathers (sampled; after renumbering) */
     int32_t lds_tiles;      /* 1 when the FP64 steps stage x in LDS per tile         */
-    int32_t pad1;
+    int32_t unit_diagonal;  /* 1 when the Jacobi-scaled main diagonal is stored as   */
+                            /* exactly 1 (stored diagonals of a CSR matrix) and the   */
+                            /* fused pairs skip reading it                            */
 } pp_stats;
 
 PP_API pp_status pp_get_stats(pp_op op, pp_stats *st);

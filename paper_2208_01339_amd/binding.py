@@ -48,7 +48,7 @@ class pp_stats(C.Structure):
         ("nnz_stored", C.c_int64), ("nnz_matrix", C.c_int64), ("driver", C.c_int32),
         ("grid", C.c_int32), ("diagonals", C.c_int32), ("two_step", C.c_int32),
         ("pair_ms", C.c_double), ("pair_launches", C.c_int64), ("restarts", C.c_int32), ("reordered", C.c_int32),
-        ("true_relres", C.c_double), ("gather_spread", C.c_double), ("lds_tiles", C.c_int32), ("pad1", C.c_int32),
+        ("true_relres", C.c_double), ("gather_spread", C.c_double), ("lds_tiles", C.c_int32), ("unit_diagonal", C.c_int32),
     ]
 
 

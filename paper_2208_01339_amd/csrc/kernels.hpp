@@ -1204,10 +1204,13 @@ static __global__ __launch_bounds__(BLOCK) void k_dia_check(int64_t n, int64_t r
 }
 
 // Scale the stored diagonals to the Jacobi-scaled operator:
-// dv[d][i] = (a_{i,i+o} dis_i) dis_{i+o}, and write the FP32 copy.
+// dv[d][i] = (a_{i,i+o} dis_i) dis_{i+o}, and write the FP32 copy.  unit_d0:
+// the stored diagonals hold the whole diagonal of the operator (a CSR
+// matrix), so the scaled diagonal is one by definition and is stored as
+// exactly 1 (the product above rounds to within two ulps of it).
 static __global__ __launch_bounds__(BLOCK) void k_dia_scale(int64_t n, DiaSet D, const double *__restrict__ dis,
                                                             double *__restrict__ dv, float *__restrict__ dv32,
-                                                            int64_t ds)
+                                                            int64_t ds, int unit_d0)
 {
     const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (i >= n) return;
@@ -1215,6 +1218,7 @@ static __global__ __launch_bounds__(BLOCK) void k_dia_scale(int64_t n, DiaSet D,
         const int64_t j = i + D.off[d];
         double v = dv[(int64_t)d * ds + i];
         if (dis) v = j < n ? v * dis[i] * dis[j] : 0.0;
+        if (dis && unit_d0 && D.off[d] == 0) v = 1.0;
         dv[(int64_t)d * ds + i] = v;
         if (dv32) dv32[(int64_t)d * ds + i] = (float)v;
     }

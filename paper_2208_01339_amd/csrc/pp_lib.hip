@@ -166,7 +166,7 @@ ppk::DiaSet build_diagonals(pp_op_s *op, const int64_t *rp, const int32_t *col, 
     if (op->mixed()) op->dval32 = dalloc<float>((size_t)D.nd * ds);
     if (op->dval32) HIPCHK(hipMemsetAsync(op->dval32, 0, sizeof(float) * D.nd * ds, op->stream));
     hipLaunchKernelGGL(ppk::k_dia_scale, dim3(gr), dim3(BLOCK), 0, op->stream, n, D, (const double *)op->dis,
-                       op->dval, op->dval32, ds);
+                       op->dval, op->dval32, ds, op->kind == 0 ? 1 : 0);
     HIPCHK(hipGetLastError());
     op->nd = D.nd;
     op->dstride = ds;
@@ -805,17 +805,25 @@ void launch_pair(pp_op_s *op, const T *sm1, const T *sm2, const T *r, T *o1, T *
     const T *dv = sizeof(T) == 4 ? (const T *)op->dval32 : (const T *)op->dval;
     const size_t lds = sizeof(T) * (2 * ppk::S2_RY + (ppk::S2_SL ? 2 * (ppk::S2_RY + 2) : 0)) * (size_t)g.N;
     const ppk::State *st = (const ppk::State *)op->st;
-#define PP_PAIR(NTV, DOTV)                                                                                          \
-    hipLaunchKernelGGL((ppk::k_cheb2_stencil<T, NTV, ppk::S2_BS, ppk::S2_SL, DOTV>), grid, dim3(ppk::S2_BS), lds,   \
-                       op->stream, g, dv, op->dstride, sm1, sm2, r, o1, o2, c1.cx, c1.cold, c1.cr, c1.cA, c2.cx,      \
+#define PP_PAIR(NTV, DOTV, UNITV)                                                                                   \
+    hipLaunchKernelGGL((ppk::k_cheb2_stencil<T, NTV, ppk::S2_BS, ppk::S2_SL, DOTV, UNITV>), grid, dim3(ppk::S2_BS),   \
+                       lds, op->stream, g, dv, op->dstride, sm1, sm2, r, o1, o2, c1.cx, c1.cold, c1.cr, c1.cA, c2.cx, \
                        c2.cold, c2.cr, c2.cA, st, op->partials)
+#define PP_PAIR_U(NTV, DOTV)                  \
+    do {                                      \
+        if (unit) PP_PAIR(NTV, DOTV, true);   \
+        else PP_PAIR(NTV, DOTV, false);       \
+    } while (0)
+    // Jacobi scaling: the stored main diagonal is exactly 1 (k_dia_scale), not read
+    const bool unit = op->dis != nullptr && op->kind == 0;
     if (op->ntload) {
-        if (dot) PP_PAIR(true, true);
-        else PP_PAIR(true, false);
+        if (dot) PP_PAIR_U(true, true);
+        else PP_PAIR_U(true, false);
     } else {
-        if (dot) PP_PAIR(false, true);
-        else PP_PAIR(false, false);
+        if (dot) PP_PAIR_U(false, true);
+        else PP_PAIR_U(false, false);
     }
+#undef PP_PAIR_U
 #undef PP_PAIR
 }
 
@@ -1588,6 +1596,7 @@ pp_status pp_get_stats(pp_op op, pp_stats *st)
     if (!op || !st) return fail(PP_ERR_ARG, "NULL argument");
     *st = op->stats;
     st->two_step = use_pairs(op) ? 1 : 0;
+    st->unit_diagonal = op->dis != nullptr && op->kind == 0 && op->nd > 0 ? 1 : 0;
     return PP_OK;
 }
 

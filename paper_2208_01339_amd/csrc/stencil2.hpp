@@ -45,8 +45,8 @@ constexpr int s2_cells_per_thread() { return (S2_RY * (int)S2_NMAX + BS - 1) / B
 // s_{j-1} (cache hits).  LDS: two planes of s_j (double buffer, one barrier
 // per plane).  DOT: the pair ends the polynomial; partials[L] receives this
 // workgroup's part of r . s_{j+1} (the dot product of the CG step).  Absent neighbours enter as zero couplings times a clamped
-// (in-range) value.
-template <typename T, bool NT, int BS, bool SL, bool DOT>
+// (in-range) value.  UNITD: the main diagonal is 1 (Jacobi-scaled operators) and is not read.
+template <typename T, bool NT, int BS, bool SL, bool DOT, bool UNITD>
 static __global__ __launch_bounds__(BS) void k_cheb2_stencil(Stencil2 g, const T *__restrict__ dv, int64_t ds,
                                                          const T *__restrict__ sm1, const T *__restrict__ sm2,
                                                          const T *__restrict__ r, T *__restrict__ out1,
@@ -130,7 +130,8 @@ static __global__ __launch_bounds__(BS) void k_cheb2_stencil(Stencil2 g, const T
             const bool rowok = c < cells && y >= 0 && y < N;
             const bool ok = rowok && zin;
             const int64_t i = ok ? x + N * (y + N * zz) : 0;
-            v0[m] = dv[i];
+            if constexpr (UNITD) v0[m] = (T)1;  // unit diagonal (Jacobi-scaled): not stored data to read
+            else v0[m] = dv[i];
             u1[m] = dv[ds + i];
             u2[m] = dv[2 * ds + i];
             u3[m] = dv[3 * ds + i];

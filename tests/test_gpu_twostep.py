@@ -211,3 +211,27 @@ def test_automatic_rule(B):
     with pytest.raises(B.PPError):
         B.pp_set_option(op.handle, B.PP_OPT_TWO_STEP, 3)
     op.close()
+
+
+def test_unit_diagonal_flag(B):
+    """Under Jacobi scaling the stored main diagonal of a CSR operator is exactly 1
+    (reported as unit_diagonal, and the pairs do not read it); without scaling,
+    and for the Schur shape (whose stored A_ff diagonal is not the operator's), it
+    is the stored data.  Operator application stays within the per-row bound."""
+    a = W.hetero_diffusion(12, 2.0, 3)
+    orc = O.Operator(a, jacobi=True)
+    for flags, want in ((B.PP_JACOBI, 1), (0, 0), (B.PP_JACOBI | B.PP_SLICED, 0)):
+        op = B.Operator(a=a, flags=flags)
+        assert B.pp_get_stats(op.handle)["unit_diagonal"] == want, flags
+        op.close()
+    s = W.dfn_schur(n_frac=13, G=16, n_traces=30, L_lo=3, L_hi=12, seed=2)
+    op = B.Operator(schur=s, flags=B.PP_JACOBI)
+    assert B.pp_get_stats(op.handle)["unit_diagonal"] == 0
+    op.close()
+    op = B.Operator(a=a, flags=B.PP_JACOBI)
+    x = W.rhs_uniform(a.n_rows, 4)
+    y = torch.empty(a.n_rows, dtype=torch.float64, device="cuda")
+    B.pp_operator_apply(op.handle, dev(x), y)
+    bound = abs(a.to_scipy()) @ np.abs(x)
+    assert np.all(np.abs(host(y) - orc.apply_raw(x)) <= 32 * np.finfo(np.float64).eps * bound)
+    op.close()
