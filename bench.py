@@ -911,13 +911,15 @@ def main():
         B.pcg_solve(hm, bd, x, args.tol, args.maxit)
         torch.cuda.synchronize()
         tt0 = time.perf_counter()
-        cms, csteps = 0.0, 0
+        cms, csteps, pms, npairs = 0.0, 0, 0.0, 0
         for _ in range(args.steps):
             x.zero_()
             status_m, it_m, rel_m = B.pcg_solve(hm, bd, x, args.tol, args.maxit)
             stm = B.pp_get_stats(hm)
             cms += stm["cheb_ms"]
             csteps += stm["cheb_steps"]
+            pms += stm["pair_ms"]
+            npairs += stm["pair_launches"]
         torch.cuda.synchronize()
         tm = (time.perf_counter() - tt0) / max(1, args.steps)
         y = torch.empty_like(x)
@@ -935,8 +937,16 @@ def main():
                      true_relres_scaled_lib=stm["true_relres"], restarts=stm["restarts"], true_relres=tr,
                      err_vs_fp64=err64, status=B.pp_status_str(status_m), speedup_vs_fp64=best["s_per_solve"] / tm,
                      cheb_step_us=us32,
-                     cheb_step_csr_equiv_gbs=cheb_bytes_per_step(n, nnz, kh, fp32=True) / (us32 * 1e-6) / 1e9,
-                     cheb_step_stored_gbs=stored_bytes_per_step(n, stm, kh, fp32=True) / (us32 * 1e-6) / 1e9)
+                     cheb_step_csr_equiv_gbs=cheb_bytes_per_step(n, nnz, kh, fp32=True) / (us32 * 1e-6) / 1e9)
+        if npairs:
+            # FP32 pairs: the stored diagonals once (a unit main one not read), r, s_{j-1}, s_{j-2}
+            # read and s_j, s_{j+1} written, per launch
+            pus = 1000.0 * pms / npairs
+            pb = 4 * (stm["diagonals"] - stm["unit_diagonal"]) * (-(-n // 64) * 64) + 5 * 4 * n
+            mixed.update(pair_launch_us=pus, pair_launches=npairs // max(1, args.steps), pair_bytes=pb,
+                         pair_stored_gbs=pb / (pus * 1e-6) / 1e9)
+        else:
+            mixed["cheb_step_stored_gbs"] = stored_bytes_per_step(n, stm, kh, fp32=True) / (us32 * 1e-6) / 1e9
         log("mixed k=%d: %.3f s/solve, iters %d, FP64 true relres scaled %.2e (unscaled %.2e), "
             "x vs FP64 solve %.1e, speedup %.2fx" % (kh, tm, it_m, trs, tr, err64, mixed["speedup_vs_fp64"]))
         del x64
