@@ -354,7 +354,7 @@ enum {
     PP_OPT_TWO_STEP = 6,    /* on 3-D 7-point operators (stored diagonals at offsets 0, 1,  */
                             /* N, N^2, no coupling across the box's x- and y-faces,        */
                             /* N <= 256) fuse pairs of Chebyshev steps into one pass (in   */
-                            /* PP_MIXED mode FP32 pairs, the last step single in FP64)   */
+                            /* PP_MIXED mode FP32 pairs, the last one writing z in FP64) */
                             /* (tiles of whole x-lines with one recomputed halo line each  */
                             /* side, marching up z): 1 (default) = when the box's tiles    */
                             /* fill whole rounds of compute units (one tile per CU) at     */

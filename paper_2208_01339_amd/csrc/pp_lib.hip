@@ -796,9 +796,9 @@ bool use_pairs(const pp_op_s *op)
     return op->s2 && op->two_step != 0 && op->form == 0 && pair_shape(op).zc > 0;
 }
 
-template <typename T>
-void launch_pair(pp_op_s *op, const T *sm1, const T *sm2, const T *r, T *o1, T *o2, const StepCoef &c1,
-                 const StepCoef &c2, bool dot)
+template <typename T, typename O2 = T>
+void launch_pair(pp_op_s *op, const T *sm1, const T *sm2, const T *r, T *o1, O2 *o2, const StepCoef &c1,
+                 const StepCoef &c2, bool dot, const double *r64 = nullptr)
 {
     const ppk::Stencil2 g = pair_shape(op);
     const dim3 grid((unsigned)(g.nty * g.nzc));
@@ -806,9 +806,9 @@ void launch_pair(pp_op_s *op, const T *sm1, const T *sm2, const T *r, T *o1, T *
     const size_t lds = sizeof(T) * (2 * ppk::S2_RY + (ppk::S2_SL ? 2 * (ppk::S2_RY + 2) : 0)) * (size_t)g.N;
     const ppk::State *st = (const ppk::State *)op->st;
 #define PP_PAIR(NTV, DOTV, UNITV)                                                                                   \
-    hipLaunchKernelGGL((ppk::k_cheb2_stencil<T, NTV, ppk::S2_BS, ppk::S2_SL, DOTV, UNITV>), grid, dim3(ppk::S2_BS),   \
-                       lds, op->stream, g, dv, op->dstride, sm1, sm2, r, o1, o2, c1.cx, c1.cold, c1.cr, c1.cA, c2.cx, \
-                       c2.cold, c2.cr, c2.cA, st, op->partials)
+    hipLaunchKernelGGL((ppk::k_cheb2_stencil<T, NTV, ppk::S2_BS, ppk::S2_SL, DOTV, UNITV, O2>), grid,              \
+                       dim3(ppk::S2_BS), lds, op->stream, g, dv, op->dstride, sm1, sm2, r, r64, o1, o2, c1.cx,      \
+                       c1.cold, c1.cr, c1.cA, c2.cx, c2.cold, c2.cr, c2.cA, st, op->partials)
 #define PP_PAIR_U(NTV, DOTV)                  \
     do {                                      \
         if (unit) PP_PAIR(NTV, DOTV, true);   \
@@ -856,9 +856,9 @@ void enqueue_poly_pairs(pp_op_s *op, const double *rr, const T *rT, T *const (&b
                         bool scale)
 {
     const int k = op->k;
-    // the last pair writes z only in FP64 (in mixed mode the last step is single:
-    // it reads r and writes z in FP64); partials hold 8192 per column
-    const bool last_pair = sizeof(T) == 8 && !scale && k % 2 == 0 && pair_grid(op) <= 8192;
+    // the last pair writes z in FP64 (in mixed mode its second step reads r in
+    // FP64 for the dot product); partials hold 8192 per column
+    const bool last_pair = !scale && k % 2 == 0 && pair_grid(op) <= 8192;
     int ic = -1, io = -1;  // buffers of s_{j-1} and s_{j-2} (-1: r)
     int j = 1;
     const bool timed = op->time_pairs;
@@ -870,8 +870,11 @@ void enqueue_poly_pairs(pp_op_s *op, const double *rr, const T *rT, T *const (&b
         for (int q = 0; q < 4; ++q)
             if (q != ic && q != io) (a < 0 ? a : b) = q;
         const T *sm1 = ic < 0 ? rT : buf[ic], *sm2 = io < 0 ? rT : buf[io];
-        launch_pair<T>(op, sm1, sm2, rT, buf[a], ends ? (T *)zout : buf[b], step_coef(op, j), step_coef(op, j + 1),
-                       ends && fin != ppk::FIN_NONE);
+        if (!ends)
+            launch_pair<T>(op, sm1, sm2, rT, buf[a], buf[b], step_coef(op, j), step_coef(op, j + 1), false);
+        else
+            launch_pair<T, double>(op, sm1, sm2, rT, buf[a], zout, step_coef(op, j), step_coef(op, j + 1),
+                                   fin != ppk::FIN_NONE, sizeof(T) == 8 ? nullptr : rr);
         ++pairs;
         io = a;
         ic = b;

@@ -14,6 +14,8 @@
 // are identical.  s_j and s_{j+1} go to two fresh buffers: no input may be
 // overwritten while neighbours still read it.
 #pragma once
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace ppk {
@@ -46,14 +48,18 @@ constexpr int s2_cells_per_thread() { return (S2_RY * (int)S2_NMAX + BS - 1) / B
 // per plane).  DOT: the pair ends the polynomial; partials[L] receives this
 // workgroup's part of r . s_{j+1} (the dot product of the CG step).  Absent neighbours enter as zero couplings times a clamped
 // (in-range) value.  UNITD: the main diagonal is 1 (Jacobi-scaled operators) and is not read.
-template <typename T, bool NT, int BS, bool SL, bool DOT, bool UNITD>
+// O2 = double with T = float: the last pair of the mixed-precision polynomial,
+// whose second step writes z in FP64 and reduces r . z with r in FP64 (r64);
+// it computes in FP32 with r rounded to FP32, as the single FP32 step does.
+template <typename T, bool NT, int BS, bool SL, bool DOT, bool UNITD, typename O2 = T>
 static __global__ __launch_bounds__(BS) void k_cheb2_stencil(Stencil2 g, const T *__restrict__ dv, int64_t ds,
                                                          const T *__restrict__ sm1, const T *__restrict__ sm2,
-                                                         const T *__restrict__ r, T *__restrict__ out1,
-                                                         T *__restrict__ out2, double c1x, double c1o, double c1r,
-                                                         double c1A, double c2x, double c2o, double c2r,
-                                                         double c2A, const State *st, double *partials)
+                                                         const T *__restrict__ r, const double *__restrict__ r64,
+                                                         T *__restrict__ out1, O2 *__restrict__ out2, double c1x,
+                                                         double c1o, double c1r, double c1A, double c2x, double c2o,
+                                                         double c2r, double c2A, const State *st, double *partials)
 {
+    constexpr bool R64 = !std::is_same_v<O2, T>;
     if (st != nullptr && st->done) return;
     double dotp = 0.0;  // r . s_{j+1} over this workgroup (DOT)
     constexpr int MM = s2_cells_per_thread<BS>();
@@ -71,6 +77,7 @@ static __global__ __launch_bounds__(BS) void k_cheb2_stencil(Stencil2 g, const T
     T s_c[MM], s_m[MM];  // s_{j-1} on planes z and z-1
     T u3p[MM];           // coupling of plane z-1 to plane z (= the -z coupling of plane z)
     T v0p[MM], rp[MM], sjp[MM], part[MM];  // plane z-1: diagonal, r, s_j, partial (A s_j)
+    double rp64[R64 ? MM : 1];             // plane z-1: r in FP64 (R64)
     // Every global load of a plane is issued before the first use of any of
     // them: indices are clamped to a valid row (0) where a cell is absent and
     // the values are masked where they are used, so the loads form one
@@ -106,6 +113,7 @@ static __global__ __launch_bounds__(BS) void k_cheb2_stencil(Stencil2 g, const T
         s_m[m] = rowok && z0 - 2 >= 0 ? s_m[m] : (T)0;
         u3p[m] = rowok && z0 - 2 >= 0 ? u3p[m] : (T)0;
         v0p[m] = rp[m] = sjp[m] = part[m] = (T)0;
+        if constexpr (R64) rp64[m] = 0.0;
         if constexpr (SL)
             if (c < cells) sl0[c + N] = s_c[m];
     }
@@ -123,6 +131,7 @@ static __global__ __launch_bounds__(BS) void k_cheb2_stencil(Stencil2 g, const T
         T *pl = (T *)s2_lds + buf * cells;
         // the plane's global loads: operator row, r, s_{j-2} on plane zz, s_{j-1} on plane zz+1
         T v0[MM], u1[MM], u2[MM], u3[MM], l1[MM], l2[MM], ri[MM], so[MM], xp[MM];
+        double r64v[R64 ? MM : 1];
 #pragma unroll
         for (int m = 0; m < MM; ++m) {
             const int64_t c = threadIdx.x + (int64_t)BS * m;
@@ -138,6 +147,7 @@ static __global__ __launch_bounds__(BS) void k_cheb2_stencil(Stencil2 g, const T
             l1[m] = dv[ds + (ok && x > 0 ? i - 1 : i)];
             l2[m] = dv[2 * ds + (ok && y > 0 ? i - N : i)];
             ri[m] = r[i];
+            if constexpr (R64) r64v[m] = r64[i];
             so[m] = ldm<NT>(sm2 + i);
             xp[m] = sm1[rowok && zu ? x + N * (y + N * (zz + 1)) : 0];
         }
@@ -205,9 +215,13 @@ static __global__ __launch_bounds__(BS) void k_cheb2_stencil(Stencil2 g, const T
                 T o2 = a2A * a2 + a2r * rp[m];
                 o2 += a2x * sjp[m];
                 o2 += a2o * s_m[m];
-                if constexpr (NT) __builtin_nontemporal_store(o2, out2 + i2);
-                else out2[i2] = o2;
-                if constexpr (DOT) dotp += (double)rp[m] * (double)o2;
+                const O2 ov = (O2)o2;
+                if constexpr (NT) __builtin_nontemporal_store(ov, out2 + i2);
+                else out2[i2] = ov;
+                if constexpr (DOT) {
+                    if constexpr (R64) dotp += rp64[m] * (double)ov;
+                    else dotp += (double)rp[m] * (double)ov;
+                }
             }
             if (c < cells) pl[c] = sj;
             if constexpr (SL)
@@ -237,6 +251,7 @@ static __global__ __launch_bounds__(BS) void k_cheb2_stencil(Stencil2 g, const T
             part[m] = pc ? pn : (T)0;
             v0p[m] = ok ? v0[m] : (T)0;
             rp[m] = ok ? ri[m] : (T)0;
+            if constexpr (R64) rp64[m] = ok ? r64v[m] : 0.0;
             sjp[m] = cur[m];
             u3p[m] = ok ? u3[m] : (T)0;
             s_m[m] = s_c[m];

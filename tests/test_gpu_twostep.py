@@ -80,12 +80,15 @@ def test_pairs_match_single_steps_and_oracle(B, name, k, xi):
 
 
 @pytest.mark.parametrize("k", [4, 7, 20])
-@pytest.mark.parametrize("name", ["hetero37", "box40x40x33"])
+@pytest.mark.parametrize("name", ["hetero37", "box40x40x33", "poisson32"])
 def test_mixed_pairs(B, name, k):
-    """Mixed mode runs the pairs in FP32 too; its last step stays single (it reads
-    r and writes z in FP64).  p_k(A) r with FP32 pairs against the FP32 single
-    steps and against the oracle within FP32 rounding (the bound of the mixed
-    pp_apply test, 1e-4; the two FP32 forms differ only in rounding, 1e-5);
+    """Mixed mode runs the pairs in FP32 too; at even k the last pair's second step
+    reads r in FP64 for the dot product and writes z in FP64 (odd k: the last step
+    runs alone, FP32 in, FP64 out; pp_apply under Jacobi scaling, whose output is
+    scaled, ends with a single step too, so the unscaled poisson32 covers the last
+    pair in pp_apply).  p_k(A) r with FP32 pairs against the FP32
+    single steps and against the oracle within FP32 rounding (the bound of the
+    mixed pp_apply test, 1e-4; the two FP32 forms differ only in rounding, 1e-5);
     PCG: FP64 true scaled residual <= 1e-8, iterations within 2 of the FP64 oracle."""
     build, jac = CASES[name]
     a = build()
