@@ -337,7 +337,9 @@ __device__ __forceinline__ T op_row(const SellView &A, const XT *__restrict__ x,
 // off-diagonal offsets in one straight-line chunk (DK = 0: no diagonal part,
 // DK < 0: the runtime form above), SP: slice part present.  With no branch
 // between them, every load of the row is issued before the first product.
-template <int DK, bool SP, typename T, typename XT, bool SCHUR, bool NT>
+// UNITD: the stored main diagonal is exactly 1 (Jacobi-scaled CSR operator)
+// and is not read (1 * x_i = x_i, so the sum is the same bit for bit).
+template <int DK, bool SP, typename T, typename XT, bool SCHUR, bool NT, bool UNITD = false>
 __device__ __forceinline__ T op_row_fixed(const SellView &A, const XT *__restrict__ x, const T *__restrict__ w,
                                           int64_t row, int64_t s, int lane)
 {
@@ -350,7 +352,8 @@ __device__ __forceinline__ T op_row_fixed(const SellView &A, const XT *__restric
         T acc = (T)0;
         if constexpr (DK > 0) {
             const int64_t i = row < A.n ? row : A.n - 1;
-            acc = dia_chunk<T, XT, DK>(A, x, i, 1) + ((const T *)A.dv)[i] * (T)x[i];
+            if constexpr (UNITD) acc = dia_chunk<T, XT, DK>(A, x, i, 1) + (T)x[i];
+            else acc = dia_chunk<T, XT, DK>(A, x, i, 1) + ((const T *)A.dv)[i] * (T)x[i];
         } else if constexpr (!SP) {
             // diagonal only (nd == 1)
             const int64_t i = row < A.n ? row : A.n - 1;
@@ -512,7 +515,7 @@ __device__ __forceinline__ double ph_init_resid(const SellView &A, const double 
 }
 
 // q = A p; returns the share of p.q
-template <bool SCHUR, bool NT>
+template <bool SCHUR, bool NT, bool UNITD = false>
 __device__ __forceinline__ double ph_pq(const SellView &A, const double *__restrict__ p,
                                         const double *__restrict__ w, double *__restrict__ q, int L, int G)
 {
@@ -523,7 +526,7 @@ __device__ __forceinline__ double ph_pq(const SellView &A, const double *__restr
         for_my_slices(A.nslices, L, G, [&](int64_t row, int64_t s, int lane) {
             const int64_t rc = row < A.n ? row : A.n - 1;
             const double pi = p[rc];
-            double a = op_row_fixed<DK, SP, double, double, SCHUR, NT>(A, p, w, row, s, lane);
+            double a = op_row_fixed<DK, SP, double, double, SCHUR, NT, UNITD>(A, p, w, row, s, lane);
             if (row < A.n) {
                 q[row] = a;
                 part += pi * a;
@@ -658,13 +661,15 @@ __global__ __launch_bounds__(BLOCK) void k_init_resid(SellView A, const double *
     store_partial(part, partials, L);
 }
 
-template <bool SCHUR>
+// q = A-hat p and this workgroup's share of p.q.  UNITD: unit main diagonal, not read.
+template <bool SCHUR, bool UNITD = false>
 __global__ __launch_bounds__(BLOCK) void k_pq(SellView A, const double *__restrict__ p,
                                               const double *__restrict__ w, double *__restrict__ q,
                                               double *partials, State *st, int nt)
 {
     PPK_PROLOGUE(st)
-    const double part = nt ? ph_pq<SCHUR, true>(A, p, w, q, L, G) : ph_pq<SCHUR, false>(A, p, w, q, L, G);
+    const double part = nt ? ph_pq<SCHUR, true, UNITD>(A, p, w, q, L, G)
+                           : ph_pq<SCHUR, false, UNITD>(A, p, w, q, L, G);
     store_partial(part, partials, L);
 }
 

@@ -1028,6 +1028,9 @@ void enqueue_iteration(pp_op_s *op, hipEvent_t e0, hipEvent_t e1)
     if (op->schur())
         hipLaunchKernelGGL(ppk::k_pq<true>, dim3(gs), dim3(BLOCK), 0, op->stream, op->view(false), op->p,
                            (const double *)op->tw, op->q, op->partials, op->st, op->ntload);
+    else if (op->dis != nullptr && op->kind == 0 && op->nd > 0)  // unit main diagonal (k_dia_scale): not read
+        hipLaunchKernelGGL((ppk::k_pq<false, true>), dim3(gs), dim3(BLOCK), 0, op->stream, op->view(false), op->p,
+                           (const double *)nullptr, op->q, op->partials, op->st, op->ntload);
     else
         hipLaunchKernelGGL(ppk::k_pq<false>, dim3(gs), dim3(BLOCK), 0, op->stream, op->view(false), op->p,
                            (const double *)nullptr, op->q, op->partials, op->st, op->ntload);
