@@ -435,7 +435,7 @@ __device__ __forceinline__ void ph_trace(const CsrView &Cm, const XT *__restrict
 // SCALE: out *= dis_i (pp_apply with Jacobi returns D^{-1/2} s_k).
 // out may alias sold (each thread reads sold_i before writing out_i).
 template <typename T, typename XT, typename RT, typename OT, int MODE, bool SCHUR, bool DOT, bool SCALE,
-          bool NT>
+          bool NT, bool UNITD = false>
 __device__ __forceinline__ double ph_cheb(const SellView &A, const XT *__restrict__ xg,
                                           const T *__restrict__ w, const RT *__restrict__ r,
                                           const T *sold, OT *out, T ax, T aold, T ar, T aA,
@@ -459,7 +459,7 @@ __device__ __forceinline__ double ph_cheb(const SellView &A, const XT *__restric
             const T xs = (MODE >= 2) ? (T)xg[rc] : (T)0;
             const T so = (MODE == 3) ? ldm<NTV>(sold + rc) : (T)0;
             const double ds = SCALE ? dis[rc] : 1.0;
-            T a = op_row_fixed<DK, SP, T, XT, SCHUR, NT>(A, xg, w, row, s, lane);
+            T a = op_row_fixed<DK, SP, T, XT, SCHUR, NT, UNITD>(A, xg, w, row, s, lane);
             if (row < A.n) {
                 T o = aA * a + ar * (T)ri;
                 if (MODE >= 2) o += ax * xs;
@@ -609,7 +609,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmv(SellView A, const T *__restrict_
 }
 
 template <typename T, typename XT, typename RT, typename OT, int MODE, bool SCHUR, bool DOT, bool SCALE,
-          bool NT>
+          bool NT, bool UNITD = false>
 static __global__ __launch_bounds__(BLOCK) void k_cheb(SellView A, const XT *__restrict__ xg,
                                                 const T *__restrict__ w, const RT *__restrict__ r,
                                                 const T *sold, OT *out, double cx, double cold,
@@ -617,7 +617,7 @@ static __global__ __launch_bounds__(BLOCK) void k_cheb(SellView A, const XT *__r
                                                 double *partials, State *st, int fin, int nt)
 {
     PPK_PROLOGUE(st)
-    const double part = ph_cheb<T, XT, RT, OT, MODE, SCHUR, DOT, SCALE, NT>(
+    const double part = ph_cheb<T, XT, RT, OT, MODE, SCHUR, DOT, SCALE, NT, UNITD>(
         A, xg, w, r, sold, out, (T)cx, (T)cold, (T)cr, (T)cA, dis, L, G);
     if (DOT) store_partial(part, partials, L);
 }

@@ -618,14 +618,21 @@ void launch_cheb(pp_op_s *op, const XT *xg, const T *w, const RT *r, const T *so
             if (DOT && fin != ppk::FIN_NONE) enqueue_fin(op, op->grid_slices(), fin);
         }
     } after{op, fin};
-    if (op->ntload)
-        hipLaunchKernelGGL((ppk::k_cheb<T, XT, RT, OT, MODE, SCHUR, DOT, SCALE, true>), dim3(op->grid_slices()),
-                           dim3(BLOCK), 0, op->stream, op->view(f32), xg, w, r, sold, out, c.cx, c.cold, c.cr,
-                           c.cA, (const double *)op->dis, op->partials, op->st, fin, 0);
-    else
-        hipLaunchKernelGGL((ppk::k_cheb<T, XT, RT, OT, MODE, SCHUR, DOT, SCALE, false>), dim3(op->grid_slices()),
-                           dim3(BLOCK), 0, op->stream, op->view(f32), xg, w, r, sold, out, c.cx, c.cold, c.cr,
-                           c.cA, (const double *)op->dis, op->partials, op->st, fin, 0);
+#define PP_CHEB(NTV, UNITV)                                                                                    \
+    hipLaunchKernelGGL((ppk::k_cheb<T, XT, RT, OT, MODE, SCHUR, DOT, SCALE, NTV, UNITV>), dim3(op->grid_slices()), \
+                       dim3(BLOCK), 0, op->stream, op->view(f32), xg, w, r, sold, out, c.cx, c.cold, c.cr, c.cA,    \
+                       (const double *)op->dis, op->partials, op->st, fin, 0)
+    // Jacobi-scaled CSR operator with stored diagonals: the main one is exactly 1, not read
+    if constexpr (!SCHUR) {
+        if (op->dis != nullptr && op->kind == 0 && op->nd > 0) {
+            if (op->ntload) PP_CHEB(true, true);
+            else PP_CHEB(false, true);
+            return;
+        }
+    }
+    if (op->ntload) PP_CHEB(true, false);
+    else PP_CHEB(false, false);
+#undef PP_CHEB
 }
 
 template <typename T, typename XT, typename RT, typename OT, int MODE, bool SCHUR>
