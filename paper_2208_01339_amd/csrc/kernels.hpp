@@ -536,16 +536,18 @@ __device__ __forceinline__ double ph_pq(const SellView &A, const double *__restr
     return part;
 }
 
-// x += alpha p; r -= alpha q; returns the share of r.r
+// x += alpha p; r -= alpha q; returns the share of r.r.  r32 (mixed mode, or
+// NULL): the FP32 copy of the new r the polynomial reads.
 __device__ __forceinline__ double ph_xr(int64_t n, const double *__restrict__ p, const double *__restrict__ q,
                                         double *__restrict__ x, double *__restrict__ r, double alpha, int L,
-                                        int G)
+                                        int G, float *__restrict__ r32 = nullptr)
 {
     double part = 0.0;
     for_my_elems(n, L, G, [&](int64_t i) {
         x[i] = x[i] + alpha * p[i];
         const double ri = r[i] - alpha * q[i];
         r[i] = ri;
+        if (r32) r32[i] = (float)ri;
         part += ri * ri;
     });
     return part;
@@ -675,10 +677,11 @@ __global__ __launch_bounds__(BLOCK) void k_pq(SellView A, const double *__restri
 
 static __global__ __launch_bounds__(BLOCK) void k_xr(int64_t n, const double *__restrict__ p,
                                               const double *__restrict__ q, double *__restrict__ x,
-                                              double *__restrict__ r, double *partials, State *st)
+                                              double *__restrict__ r, double *partials, State *st,
+                                              float *__restrict__ r32)
 {
     PPK_PROLOGUE(st)
-    const double part = ph_xr(n, p, q, x, r, st->alpha, L, G);
+    const double part = ph_xr(n, p, q, x, r, st->alpha, L, G, r32);
     store_partial(part, partials, L);
 }
 

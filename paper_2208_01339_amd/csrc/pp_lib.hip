@@ -906,7 +906,7 @@ void enqueue_poly_pairs(pp_op_s *op, const double *rr, const T *rT, T *const (&b
 // z = p_k(A-hat) rr, rr in the scaled space (double).  fin: FIN_NONE,
 // FIN_RHO0 or FIN_RHO (reduce rr.z).  scale: multiply the output by dis
 // (pp_apply under Jacobi).  r32src: FP32 copy of rr already made (mixed).
-void enqueue_poly(pp_op_s *op, const double *rr, double *zout, int fin, bool scale)
+void enqueue_poly(pp_op_s *op, const double *rr, double *zout, int fin, bool scale, bool r32_ready = false)
 {
     if (op->form == 1) {
         enqueue_newton(op, rr, zout, fin, scale);
@@ -950,9 +950,11 @@ void enqueue_poly(pp_op_s *op, const double *rr, double *zout, int fin, bool sca
         }
         return;
     }
-    // mixed: r32 = (float) rr, steps in FP32, last step writes FP64 z
-    hipLaunchKernelGGL((ppk::k_scale<double, float>), dim3(op->grid_elems(op->n)), dim3(BLOCK), 0, op->stream,
-                       op->n, rr, (const double *)nullptr, 1.0, op->r32);
+    // mixed: r32 = (float) rr (unless the r update wrote it), steps in FP32,
+    // last step writes FP64 z
+    if (!r32_ready)
+        hipLaunchKernelGGL((ppk::k_scale<double, float>), dim3(op->grid_elems(op->n)), dim3(BLOCK), 0, op->stream,
+                           op->n, rr, (const double *)nullptr, 1.0, op->r32);
     if (k >= 4 && use_pairs(op)) {
         float *const buf[4] = {op->sA32, op->sB32, op->sC32, op->sD32};
         enqueue_poly_pairs<float>(op, rr, op->r32, buf, zout, fin, scale);
@@ -1050,12 +1052,13 @@ void enqueue_iteration(pp_op_s *op, hipEvent_t e0, hipEvent_t e1)
         hipLaunchKernelGGL(ppk::k_fin_lr, dim3(1), dim3(BLOCK), 0, op->stream, (const double *)op->partials, ge,
                            1 + lp, op->st, (int)ppk::LR_FIN_RR, lp, (const double *)op->lr_hinv);
     } else {
+        // mixed mode: the FP32 copy of r for the polynomial in the same pass
         hipLaunchKernelGGL(ppk::k_xr, dim3(ge), dim3(BLOCK), 0, op->stream, op->n, op->p, op->q, op->xh, op->r,
-                           op->partials, op->st);
+                           op->partials, op->st, op->mixed() ? op->r32 : (float *)nullptr);
         enqueue_fin(op, ge, ppk::FIN_RR);
     }
     if (e0) (void)hipEventRecord(e0, op->stream);
-    enqueue_poly(op, op->r, op->z, ppk::FIN_RHO, false);
+    enqueue_poly(op, op->r, op->z, ppk::FIN_RHO, false, op->mixed() && lp == 0);
     if (e1) (void)hipEventRecord(e1, op->stream);
     enqueue_p(op, false);
 }

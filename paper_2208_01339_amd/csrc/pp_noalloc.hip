@@ -364,7 +364,7 @@ pp_status pcg_solve_csr_noalloc(int64_t n, int64_t nnz, const int64_t *rowptr, c
                 na_csr<NA_PQ, true>(c, p, nullptr, nullptr, q, none);
                 na_fin(c, ppk::FIN_GAMMA);
                 hipLaunchKernelGGL(ppk::k_xr, dim3(ge), dim3(BLOCK), 0, c.s, n, (const double *)p, (const double *)q,
-                                   xh, r, c.partials, c.st);
+                                   xh, r, c.partials, c.st, (float *)nullptr);
                 na_fin(c, ppk::FIN_RR);
                 na_poly(c, steps, theta, r, z, sa, sb, ppk::FIN_RHO);
                 hipLaunchKernelGGL(ppk::k_p, dim3(ge), dim3(BLOCK), 0, c.s, n, (const double *)z, p,
