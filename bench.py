@@ -367,6 +367,36 @@ def run_batch256(args, B, W, torch, dev):
     return out
 
 
+def stream_probes(torch, dev, nbytes=1 << 30, reps=5):
+    """Achievable HBM rates on this GPU, measured in this run with plain PyTorch
+    kernels on 1 GiB arrays (best of reps): a device copy (one read, one write)
+    and addcmul (three reads, one write, the read/write mix of the fused pair)."""
+    n = nbytes // 8
+    a = torch.empty(n, dtype=torch.float64, device=dev).fill_(1.0)
+    b = torch.empty_like(a).fill_(2.0)
+    c = torch.empty_like(a).fill_(3.0)
+    d = torch.empty_like(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def best(fn, moved):
+        t = []
+        for _ in range(reps):
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            t.append(e0.elapsed_time(e1) * 1e-3)
+        return round(moved / min(t) / 1e9, 1)
+
+    out = {"copy_gbs": best(lambda: d.copy_(a), 2 * 8 * n),
+           "read3_write1_gbs": best(lambda: torch.addcmul(a, b, c, out=d), 4 * 8 * n),
+           "note": "plain PyTorch kernels on 1 GiB FP64 arrays, best of %d: the streaming rates a kernel reaches "
+                   "on this part, against the 8 TB/s peak" % reps}
+    del a, b, c, d
+    torch.cuda.synchronize()
+    return out
+
+
 def timed_solves(B, torch, h, bd, x, tol, maxit, warmup, runs):
     """warmup + runs solves from x0 = 0; returns (median s, status, iters, relres, stats of the last)."""
     for _ in range(warmup):
@@ -897,6 +927,12 @@ def main():
                 "note": ("bytes_per_launch: what the kernel must move in the storage held (operator once per "
                          "launch, the step vectors); csr_equiv_*: the same launch time against one plain CSR "
                          "pass per step, a rate of the method's work that can pass the HBM peak")}
+    probes = stream_probes(torch, dev)
+    roofline["probes"] = probes
+    roofline["frac_of_read3_write1"] = round(achieved / probes["read3_write1_gbs"], 4)
+    log("roofline: %.0f GB/s stored bytes (frac %.3f of 8 TB/s); this GPU streams copy %.0f GB/s, "
+        "3 reads + 1 write %.0f GB/s" % (achieved, achieved / HBM_PEAK_GBS, probes["copy_gbs"],
+                                          probes["read3_write1_gbs"]))
 
     mixed = None
     if not args.no_mixed:
