@@ -49,6 +49,7 @@ struct Batch {
     const double *dv64;
     const float *dv32;
     int64_t dstride;
+    int32_t unit_d0;          // 1: the stored main diagonals are exactly 1 (Jacobi), not read
 };
 
 // Per-(segment, column) CG state, arrays of S * NB (index s * NB + c).
@@ -304,10 +305,12 @@ __device__ __forceinline__ const T *dv_of(const Batch &bt)
 // zero value; their indices are redirected to the row itself.
 template <typename T, int CPL, int DK>
 __device__ __forceinline__ void spmm_dia(const T *__restrict__ dv, int64_t ds, const SegDia<DK> &g,
-                                         const T *__restrict__ X, int NB, int64_t row, int c0, T (&acc)[CPL])
+                                         const T *__restrict__ X, int NB, int64_t row, int c0, T (&acc)[CPL],
+                                         bool unit)
 {
     const Vec<T, CPL> x0 = ldv<T, CPL>(X + row * NB + c0);
-    const T v0 = dv[row];
+    T v0 = (T)1;  // a unit main diagonal (Jacobi-scaled) is not read
+    if (!unit) v0 = dv[row];
     T vu[DK], vl[DK];
     Vec<T, CPL> xu[DK], xl[DK];
 #pragma unroll
@@ -354,7 +357,7 @@ __device__ __forceinline__ void spmm_any(const ppk::SellView &A, const Batch &bt
                                          int rin, int c0, T (&acc)[CPL])
 {
     if constexpr (DK > 0) {
-        spmm_dia<T, CPL, DK>(dv_of<T>(bt), bt.dstride, g, X, NB, row, c0, acc);
+        spmm_dia<T, CPL, DK>(dv_of<T>(bt), bt.dstride, g, X, NB, row, c0, acc, bt.unit_d0 != 0);
         if constexpr (SP) {
             T more[CPL];
             spmm_row<T, W, CPL, NT>(A, X, NB, base, width, rin, c0, more);

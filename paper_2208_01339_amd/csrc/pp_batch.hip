@@ -103,6 +103,7 @@ struct pp_batch_s {
         b.dv64 = dv64;
         b.dv32 = dv32;
         b.dstride = n_int;
+        b.unit_d0 = (flags & PP_JACOBI) != 0 ? 1 : 0;
         return b;
     }
     ppb::BState bst(double tol, int maxit) const
@@ -275,7 +276,7 @@ void build_diagonals(pp_batch_s *op, const int64_t *rowptr, const int32_t *colin
                 const int64_t n = op->seg_n_h[s], r0 = op->seg_row0_h[s];
                 hipLaunchKernelGGL(ppk::k_dia_scale, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0,
                                    op->stream, n, D[s], jac ? (const double *)op->dis + r0 : (const double *)nullptr,
-                                   op->dv64 + r0, op->dv32 ? op->dv32 + r0 : (float *)nullptr, ds, 0);
+                                   op->dv64 + r0, op->dv32 ? op->dv32 + r0 : (float *)nullptr, ds, jac ? 1 : 0);
                 nd[s] = D[s].nd;
                 for (int d = 0; d < ppk::DMAX; ++d) off[(size_t)s * ppk::DMAX + d] = D[s].off[d];
             }
