@@ -25,8 +25,8 @@ import statistics
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DIGEST_FILES = ("csrc/kernels.hpp", "csrc/op.hpp", "csrc/dfn.hpp", "csrc/common.hpp", "csrc/dia_plan.hpp",
-                "csrc/stencil2.hpp", "csrc/lowrank.hpp", "csrc/ltile.hpp", "csrc/reorder.hpp", "csrc/pp_lib.hip",
-                "build.py")
+                "csrc/stencil2.hpp", "csrc/lowrank.hpp", "csrc/ltile.hpp", "csrc/reorder.hpp", "csrc/persistent.hpp",
+                "csrc/sym_eig.hpp", "csrc/pp_lib.hip", "csrc/batch.hpp", "csrc/pp_batch.hip", "build.py")
 
 
 def _code_only(text: str) -> str:
@@ -42,7 +42,7 @@ def _code_only(text: str) -> str:
 
 
 def source_digest(root: str = HERE) -> str:
-    """Digest of the code (not the comments) of the fused-step kernel sources."""
+    """Digest of the code (not the comments) of the solver and batch kernel sources."""
     h = hashlib.sha256()
     for rel in DIGEST_FILES:
         with open(os.path.join(root, rel), encoding="utf-8") as f:
