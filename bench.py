@@ -929,6 +929,7 @@ def main():
                          "pass per step, a rate of the method's work that can pass the HBM peak")}
     probes = stream_probes(torch, dev)
     roofline["probes"] = probes
+    roofline["frac_of_copy"] = round(achieved / probes["copy_gbs"], 4)
     roofline["frac_of_read3_write1"] = round(achieved / probes["read3_write1_gbs"], 4)
     log("roofline: %.0f GB/s stored bytes (frac %.3f of 8 TB/s); this GPU streams copy %.0f GB/s, "
         "3 reads + 1 write %.0f GB/s" % (achieved, achieved / HBM_PEAK_GBS, probes["copy_gbs"],
