@@ -127,7 +127,7 @@ static __global__ __launch_bounds__(BS) void k_cheb2_stencil(Stencil2 g, const T
         const bool zin = zz >= 0 && zz < NZ;
         const bool fin2 = zz - 1 >= z0 && zz - 1 < z1;  // finish s_{j+1} on plane zz-1
         const bool part_now = zz >= z0 && zz < z1;      // partial sums for plane zz
-        const bool zl = zz > 0, zu = zz + 1 < NZ;
+        const bool zu = zz + 1 < NZ;
         T *pl = (T *)s2_lds + buf * cells;
         // the plane's global loads: operator row, r, s_{j-2} on plane zz, s_{j-1} on plane zz+1
         T v0[MM], u1[MM], u2[MM], u3[MM], l1[MM], l2[MM], ri[MM], so[MM], xp[MM];
@@ -144,8 +144,11 @@ static __global__ __launch_bounds__(BS) void k_cheb2_stencil(Stencil2 g, const T
             u1[m] = dv[ds + i];
             u2[m] = dv[2 * ds + i];
             u3[m] = dv[3 * ds + i];
-            l1[m] = dv[ds + (ok && x > 0 ? i - 1 : i)];
-            l2[m] = dv[2 * ds + (ok && y > 0 ? i - N : i)];
+            // the mirrored couplings a_{i,i-1} and a_{i,i-N}; at the box's x- and
+            // y-faces they read a stored zero of the face row (the pair kernel
+            // runs only on operators without couplings across those faces)
+            l1[m] = dv[ds + (ok ? (i > 0 ? i - 1 : N - 1) : 0)];
+            l2[m] = dv[2 * ds + (ok ? (i >= N ? i - N : i + (N - 1) * N) : 0)];
             ri[m] = r[i];
             if constexpr (R64) r64v[m] = r64[i];
             so[m] = ldm<NT>(sm2 + i);
@@ -166,15 +169,18 @@ static __global__ __launch_bounds__(BS) void k_cheb2_stencil(Stencil2 g, const T
             const bool rowok = c < cells && y >= 0 && y < N;
             const bool ok = rowok && zin;
             const int64_t i = ok ? x + N * (y + N * zz) : 0;
-            const bool xl = x > 0, xu = x + 1 < N, yl = y > 0, yu = y + 1 < N;
+            // Neighbour values: a neighbour outside the box has a zero coupling
+            // (stored zeros at the faces; 0 above the last plane and below the
+            // first), so its value only has to be finite, read at a valid index.
             T x1m, x1p, x2m, x2p;
             if constexpr (SL) {
                 const T *sp = sl0 + buf * scells + (ok ? c : 0) + N;
-                x1m = sp[ok && xl ? -1 : 0];
-                x1p = sp[ok && xu ? 1 : 0];
+                x1m = sp[-1];
+                x1p = sp[1];
                 x2m = sp[-N];
                 x2p = sp[N];
             } else {
+                const bool xl = x > 0, xu = x + 1 < N, yl = y > 0, yu = y + 1 < N;
                 x1m = sm1[ok && xl ? i - 1 : i];
                 x1p = sm1[ok && xu ? i + 1 : i];
                 x2m = sm1[ok && yl ? i - N : i];
@@ -183,12 +189,12 @@ static __global__ __launch_bounds__(BS) void k_cheb2_stencil(Stencil2 g, const T
             const T xs = s_c[m];
             const T xpm = rowok && zu ? xp[m] : (T)0;
             T acc = (T)0;
-            acc += (xl ? l1[m] : (T)0) * x1m;
-            acc += (xu ? u1[m] : (T)0) * x1p;
-            acc += (yl ? l2[m] : (T)0) * x2m;
-            acc += (yu ? u2[m] : (T)0) * x2p;
-            acc += (zl ? u3p[m] : (T)0) * s_m[m];
-            acc += (zu ? u3[m] : (T)0) * xpm;
+            acc += l1[m] * x1m;
+            acc += u1[m] * x1p;
+            acc += l2[m] * x2m;
+            acc += u2[m] * x2p;
+            acc += u3p[m] * s_m[m];
+            acc += u3[m] * xpm;
             const T a = acc + v0[m] * xs;
             T o = a1A * a + a1r * ri[m];
             o += a1x * xs;
@@ -210,7 +216,7 @@ static __global__ __launch_bounds__(BS) void k_cheb2_stencil(Stencil2 g, const T
             }
             if (fin2 && interior) {
                 const int64_t i2 = x + N * (y + N * (zz - 1));
-                const T acc2 = part[m] + (zz < NZ ? u3p[m] : (T)0) * sj;
+                const T acc2 = part[m] + u3p[m] * sj;
                 const T a2 = acc2 + v0p[m] * sjp[m];
                 T o2 = a2A * a2 + a2r * rp[m];
                 o2 += a2x * sjp[m];
@@ -236,18 +242,17 @@ static __global__ __launch_bounds__(BS) void k_cheb2_stencil(Stencil2 g, const T
 #pragma unroll
         for (int m = 0; m < MM; ++m) {
             const int64_t c = threadIdx.x + (int64_t)BS * m;
-            const int64_t ly = c / N, x = c - ly * N, y = y0 + ly;
+            const int64_t ly = c / N, y = y0 + ly;
             const bool rowok = c < cells && y >= 0 && y < N;
             const bool ok = rowok && zin;
             const bool pc = part_now && ly >= 1 && ly <= S2_TY && c < cells && y < N;
-            const int64_t cc = pc ? c : N;  // rows 1 .. S2_TY: c - N and c + N stay inside the plane
-            const bool xl = x > 0, xu = x + 1 < N, yl = y > 0, yu = y + 1 < N;
+            const int64_t cc = pc ? c : N;  // rows 1 .. S2_TY: c +- 1 and c +- N stay inside the plane
             T pn = (T)0;
-            pn += (xl ? l1[m] : (T)0) * pl[pc && xl ? cc - 1 : cc];
-            pn += (xu ? u1[m] : (T)0) * pl[pc && xu ? cc + 1 : cc];
-            pn += (yl ? l2[m] : (T)0) * pl[cc - N];
-            pn += (yu ? u2[m] : (T)0) * pl[cc + N];
-            pn += (zl ? u3p[m] : (T)0) * sjp[m];
+            pn += l1[m] * pl[cc - 1];
+            pn += u1[m] * pl[cc + 1];
+            pn += l2[m] * pl[cc - N];
+            pn += u2[m] * pl[cc + N];
+            pn += u3p[m] * sjp[m];
             part[m] = pc ? pn : (T)0;
             v0p[m] = ok ? v0[m] : (T)0;
             rp[m] = ok ? ri[m] : (T)0;
