@@ -18,6 +18,8 @@ holds only the kernels of that workload:
                    1100 traces), k = 31, scaling 1e-3
   batch256         256 uneven heterogeneous systems in one batched solve
                    (FP32 polynomial, FP64 CG), k = 60
+  poisson32        Poisson 32^3, no scaling, k = 10, the default driver (one
+                   persistent launch per solve at this size)
 
 --calib-copy first runs one plain device copy of 1 GiB (the reference of the
 HBM byte counters).  Prints one line per solve (iterations, seconds).
@@ -30,7 +32,7 @@ import time
 
 import numpy as np
 
-CASES = ("sliced256", "sliced256_plain", "irregular160", "dfn", "dfn_su", "batch256")
+CASES = ("sliced256", "sliced256_plain", "irregular160", "dfn", "dfn_su", "batch256", "poisson32")
 
 
 def _log(*a):
@@ -93,6 +95,10 @@ def main(argv=None):
         a = W.irregular_fe(160)
         b = W.rhs_uniform(a.n_rows, 1)
         op = B.Operator(a=a, flags=B.PP_JACOBI)
+    elif args.case == "poisson32":
+        a, b = W.config_poisson32()
+        op = B.Operator(a=a, flags=0)
+        k = 10
     elif args.case == "dfn":
         s, b = W.config_dfn()
         op = B.Operator(schur=s, flags=B.PP_JACOBI)
