@@ -522,11 +522,29 @@ def run_poisson32(args, B, W, torch, dev):
     out = dict(workload="poisson3d_32^3_k10", n=a.n_rows, nnz=a.nnz, bounds=[lo, hi], k=10, s_per_solve=ts,
                iters=it, relres=rel, status=B.pp_status_str(status),
                driver="persistent" if st["driver"] == 1 else "stream", grid=st["grid"],
+               barrier={0: "runtime", 1: "flat", 2: "two-level"}.get(st["barrier"], None),
                stream_driver=dict(s_per_solve=ts0, iters=it0, step_us=st0["step_us"],
                                   effective_gbs_cache_resident=eff))
-    log("poisson32 k=10: %.2f ms/solve (%s driver, %d workgroups), %d iters; stream-driven %.2f ms, step %.1f us "
-        "(%.0f GB/s effective, cache-resident)" % (1000 * ts, out["driver"], st["grid"], it, 1000 * ts0,
-                                                   st0["step_us"], eff))
+    log("poisson32 k=10: %.2f ms/solve (%s driver, %d workgroups, %s barrier), %d iters; stream-driven %.2f ms, "
+        "step %.1f us (%.0f GB/s effective, cache-resident)" % (1000 * ts, out["driver"], st["grid"], out["barrier"],
+                                                              it, 1000 * ts0, st0["step_us"], eff))
+    # 64^3: past the default driver's size limit; both drivers, same bounds recipe
+    a6 = W.poisson3d(64)
+    b6 = W.rhs_uniform(a6.n_rows, 0)
+    h = B.pp_create_csr(a6.n_rows, a6.nnz, up(a6.rowptr), up(a6.col), up(a6.val), 0)
+    lo6, hi6 = B.pp_estimate_bounds(h, 20)
+    B.pp_setup(h, 10, lo6, hi6, 0.0)
+    x6 = torch.zeros(a6.n_rows, dtype=torch.float64, device=dev)
+    rec = {}
+    for name, drv in (("stream", 0), ("persistent", 1)):
+        B.pp_set_option(h, B.PP_OPT_DRIVER, drv)
+        t6, s6, it6, _, st6 = timed_solves(B, torch, h, up(b6), x6, args.tol, args.maxit, 3, 10)
+        rec[name] = dict(s_per_solve=t6, iters=it6, status=B.pp_status_str(s6), grid=st6["grid"])
+    B.pp_destroy(h)
+    out["poisson64"] = dict(workload="poisson3d_64^3_k10", n=a6.n_rows, **rec)
+    log("poisson64 k=10: stream-driven %.2f ms/solve, persistent %.2f ms (%d workgroups), %d iters"
+        % (1000 * rec["stream"]["s_per_solve"], 1000 * rec["persistent"]["s_per_solve"], rec["persistent"]["grid"],
+           rec["stream"]["iters"]))
     return out
 
 

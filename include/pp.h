@@ -56,7 +56,9 @@ typedef enum {
     PP_ERR_ARG = -1,      /* invalid argument (null pointer, size, bounds, flags)  */
     PP_ERR_OOM = -2,      /* device allocation failed                              */
     PP_ERR_HIP = -3,      /* a HIP runtime call failed                             */
-    PP_ERR_STATE = -4     /* call out of order (apply/solve before pp_setup)       */
+    PP_ERR_STATE = -4,    /* call out of order (apply/solve before pp_setup)       */
+    PP_ERR_TIMEOUT = -5   /* a grid-barrier wait of the persistent driver gave up  */
+                          /* (PP_OPT_SPIN_LIMIT); x is undefined                   */
 } pp_status;
 
 /* create flags */
@@ -335,6 +337,9 @@ typedef struct {
     int32_t unit_diagonal;  /* 1 when the Jacobi-scaled main diagonal is stored as   */
                             /* exactly 1 (stored diagonals of a CSR matrix) and the   */
                             /* fused pairs skip reading it                            */
+    int32_t barrier;        /* grid barrier of the last persistent solve: 0 the      */
+                            /* runtime's cooperative barrier, 1 flat, 2 two-level    */
+                            /* (PP_OPT_BARRIER); -1 after a stream-driven solve      */
 } pp_stats;
 
 PP_API pp_status pp_get_stats(pp_op op, pp_stats *st);
@@ -346,8 +351,8 @@ enum {
     PP_OPT_TIMING = 3,      /* 1 = record events around the polynomial steps              */
     PP_OPT_DRIVER = 4,      /* 0 = stream-driven, 1 = persistent cooperative kernel, -1 = auto */
                             /* (default: persistent for operators of at most 65536 rows   */
-                            /* whose polynomial runs single steps, on 8 to 32 workgroups, */
-                            /* stream-driven otherwise)                                   */
+                            /* whose polynomial runs single steps, one 64-row slice per   */
+                            /* wave up to 128 workgroups; stream-driven otherwise)        */
     PP_OPT_NT_LOADS = 5,    /* 1 = non-temporal accesses for the streams read once per step */
                             /* (the sliced matrix; r, s_{j-2} and the output with stored */
                             /* diagonals), 0 = plain; default 1 from 2^22 rows on       */
@@ -367,11 +372,19 @@ enum {
                             /* Costs one operator application when the check passes.       */
     PP_OPT_RITZ = 8,        /* pp_lowrank_ritz: 0 (default) Lanczos on A-hat, 1 Lanczos on   */
                             /* p_k(A-hat) with full reorthogonalisation                    */
-    PP_OPT_LDS_TILES = 9    /* FP64 CSR operators held in slices only: 1 (default) = the    */
+    PP_OPT_LDS_TILES = 9,   /* FP64 CSR operators held in slices only: 1 (default) = the    */
                             /* Chebyshev steps stage the x segments of each tile of 1024  */
                             /* rows in LDS and gather from there (tiles touching more     */
                             /* than 6144 values of x gather from memory; create plans     */
                             /* no tiles when over a tenth would), 0 = gather from memory  */
+    PP_OPT_BARRIER = 10,    /* grid barrier of the persistent driver: 0 = the runtime's   */
+                            /* cooperative barrier, 1 = flat (every workgroup writes back */
+                            /* its L2 and arrives on one counter), 2 = two-level (one L2  */
+                            /* writeback and one global arrival per XCD), -1 (default) =  */
+                            /* flat below 32 workgroups, two-level from 32                */
+    PP_OPT_SPIN_LIMIT = 11  /* polls (each about a microsecond) before a wait in a hand-  */
+                            /* written grid barrier gives up and the solve returns        */
+                            /* PP_ERR_TIMEOUT; 1 .. 2^31, default 2^21                    */
 };
 PP_API pp_status pp_set_option(pp_op op, int key, int64_t value);
 

@@ -14,10 +14,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libppcg.so")
 
 PP_OK, PP_NOT_CONVERGED, PP_BREAKDOWN = 0, 1, 2
-PP_ERR_ARG, PP_ERR_OOM, PP_ERR_HIP, PP_ERR_STATE = -1, -2, -3, -4
+PP_ERR_ARG, PP_ERR_OOM, PP_ERR_HIP, PP_ERR_STATE, PP_ERR_TIMEOUT = -1, -2, -3, -4, -5
 PP_JACOBI, PP_MIXED, PP_SLICED, PP_NO_REORDER = 1, 2, 4, 8
 PP_OPT_GRID, PP_OPT_CHUNK, PP_OPT_TIMING, PP_OPT_DRIVER, PP_OPT_NT_LOADS, PP_OPT_TWO_STEP, PP_OPT_VERIFY = 1, 2, 3, 4, 5, 6, 7
-PP_OPT_RITZ, PP_OPT_LDS_TILES = 8, 9
+PP_OPT_RITZ, PP_OPT_LDS_TILES, PP_OPT_BARRIER, PP_OPT_SPIN_LIMIT = 8, 9, 10, 11
 
 PP_BOPT_GRAPH = 100
 
@@ -49,6 +49,7 @@ class pp_stats(C.Structure):
         ("grid", C.c_int32), ("diagonals", C.c_int32), ("two_step", C.c_int32),
         ("pair_ms", C.c_double), ("pair_launches", C.c_int64), ("restarts", C.c_int32), ("reordered", C.c_int32),
         ("true_relres", C.c_double), ("gather_spread", C.c_double), ("lds_tiles", C.c_int32), ("unit_diagonal", C.c_int32),
+        ("barrier", C.c_int32),
     ]
 
 

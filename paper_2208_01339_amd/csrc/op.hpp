@@ -112,6 +112,9 @@ struct pp_op_s {
     int chunk = 0;  // 0 = auto
     int timing = 0;
     int driver = -1;  // -1 auto, 0 stream-driven, 1 persistent
+    int bar_mode = -1;           // persistent grid barrier: -1 auto, 0 runtime, 1 flat, 2 two-level
+    unsigned int spin = 1u << 21;  // polls before a barrier wait gives up
+    unsigned long long *bw = nullptr;  // barrier words of the persistent driver
     int ritz_poly = 0;  // pp_lowrank_ritz: 0 Lanczos on A-hat, 1 on p_k(A-hat) with full reorthogonalisation
     std::vector<double> lr_theta, lr_res;  // v^T A-hat v and ||A-hat v - theta v|| of the installed V
     int verify = -1;  // true-residual check at convergence: -1 auto (mixed mode), 0 off, 1 on
@@ -209,7 +212,7 @@ struct pp_op_s {
         ppc::dfree(r32); ppc::dfree(sA32); ppc::dfree(sB32);
         ppc::dfree(sC); ppc::dfree(sD);
         ppc::dfree(sC32); ppc::dfree(sD32);
-        ppc::dfree(partials); ppc::dfree(coef_d); ppc::dfree(st);
+        ppc::dfree(partials); ppc::dfree(coef_d); ppc::dfree(bw); ppc::dfree(st);
         ppc::dfree(lr_v); ppc::dfree(lr_hinv); ppc::dfree(nbuf);
         if (hst) (void)hipHostFree(hst);
         if (hflag) (void)hipHostFree(hflag);

@@ -1116,12 +1116,12 @@ bool persistent_solve(pp_op_s *op, const double *b, double *x, double tol, int m
     }
     int G = (int)std::min<int64_t>({(int64_t)op->persist_occ[slot], (op->nslices + WPB - 1) / WPB, 8192,
                                     (int64_t)op->grid_max});
-    // A grid barrier costs about 0.1 us per workgroup (a same-address atomic
-    // each), so small operators run on few workgroups: 16 slices per
-    // workgroup, 8 to 32 of them (measured: Poisson 32^3 1.46 ms at 32
-    // workgroups, 2.85 ms at 128; 24^3 1.38 ms at 16).
+    // Small operators: one slice per wave, at most 128 workgroups (the
+    // two-level barrier costs ~3 us at 128 workgroups, ~4 us at 256; measured
+    // Poisson k = 10: 32^3 1.04 ms at 128 workgroups, 1.27 at 32, 1.56 at 16;
+    // 40^3 1.35 ms at 128, 1.43 at 250).
     if (op->nslices <= PERSIST_SMALL_SLICES && op->grid_max == op->grid_auto)
-        G = (int)std::min<int64_t>(G, std::max<int64_t>(8, std::min<int64_t>(32, op->nslices / 16)));
+        G = (int)std::min<int64_t>(G, 128);
     if (G < 1) return false;
     const int k = op->k;
     if (op->coef_k != k) {
@@ -1140,6 +1140,9 @@ bool persistent_solve(pp_op_s *op, const double *b, double *x, double tol, int m
         HIPCHK(hipStreamSynchronize(op->stream));
         op->coef_k = k;
     }
+    if (!op->bw) op->bw = dalloc<unsigned long long>((size_t)ppk::GB_LINES * ppk::GB_LINE);
+    hipLaunchKernelGGL(ppk::k_zero_u64, dim3(1), dim3(BLOCK), 0, op->stream, op->bw,
+                       (int64_t)ppk::GB_LINES * ppk::GB_LINE);
     ppk::PersistArgs a;
     a.A = op->view(false);
     a.A32 = op->view(op->mixed());
@@ -1158,6 +1161,14 @@ bool persistent_solve(pp_op_s *op, const double *b, double *x, double tol, int m
     a.tol = tol;
     a.k = k;
     a.maxit = maxit;
+    a.bw = op->bw;
+    // the runtime's barrier costs ~0.1 us per workgroup, the flat one about a
+    // third of that, the two-level one grows far more slowly (alone in a
+    // cooperative launch: 8 workgroups 2.5 / 1.1 / 1.6 us, 32: 5.1 / 1.8 /
+    // 2.2 us, 256: 26.8 / 9.5 / 4.2 us, 1024: 104 / 74 / 11 us); inside the
+    // solve the two-level one is ahead from 32 workgroups
+    a.bar_mode = op->bar_mode >= 0 ? op->bar_mode : (G < 32 ? 1 : 2);
+    a.spin = op->spin;
     void *args[] = {&a};
     hipError_t e = hipLaunchCooperativeKernel(fn, dim3(G), dim3(BLOCK), args, 0, op->stream);
     if (e != hipSuccess) {
@@ -1165,6 +1176,7 @@ bool persistent_solve(pp_op_s *op, const double *b, double *x, double tol, int m
         return false;
     }
     op->stats.grid = G;
+    op->stats.barrier = a.bar_mode;
     return true;
 }
 
@@ -1186,6 +1198,7 @@ const char *pp_status_str(pp_status s)
     case PP_ERR_OOM: return "PP_ERR_OOM";
     case PP_ERR_HIP: return "PP_ERR_HIP";
     case PP_ERR_STATE: return "PP_ERR_STATE";
+    case PP_ERR_TIMEOUT: return "PP_ERR_TIMEOUT";
     }
     return "PP_UNKNOWN";
 }
@@ -1603,6 +1616,14 @@ pp_status pp_set_option(pp_op op, int key, int64_t value)
         if (value < 0 || value > 1) return fail(PP_ERR_ARG, "PP_OPT_LDS_TILES must be 0 or 1");
         op->lt_use = (int)value;
         return PP_OK;
+    case PP_OPT_BARRIER:
+        if (value < -1 || value > 2) return fail(PP_ERR_ARG, "PP_OPT_BARRIER must be -1, 0, 1 or 2");
+        op->bar_mode = (int)value;
+        return PP_OK;
+    case PP_OPT_SPIN_LIMIT:
+        if (value < 1 || value > (int64_t)1 << 31) return fail(PP_ERR_ARG, "PP_OPT_SPIN_LIMIT must be in [1, 2^31]");
+        op->spin = (unsigned int)value;
+        return PP_OK;
     default: return fail(PP_ERR_ARG, "unknown option");
     }
 }
@@ -1839,6 +1860,8 @@ pp_status pcg_solve(pp_op op, const double *b, double *x, double tol, int maxit,
         op->stats.pair_launches = 0;
         op->stats.driver = persisted ? 1 : 0;
         if (!persisted) op->stats.grid = op->grid_slices();
+        if (!persisted) op->stats.barrier = -1;
+        if (ret == PP_ERR_TIMEOUT) ppc::last_error() = "a grid-barrier wait of the persistent driver gave up (PP_OPT_SPIN_LIMIT)";
         if (op->timing && !zero_b && !persisted) {
             // first pass only: pairs 0 .. polys-1 ran (the initial one and one per iteration but the last)
             const int64_t polys = first_it > 0 ? first_it : 1;

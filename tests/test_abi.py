@@ -44,7 +44,8 @@ def test_every_declared_symbol_is_exported(B):
 
 def test_status_strings(B):
     for code, name in [(0, "PP_OK"), (1, "PP_NOT_CONVERGED"), (2, "PP_BREAKDOWN"), (-1, "PP_ERR_ARG"),
-                       (-2, "PP_ERR_OOM"), (-3, "PP_ERR_HIP"), (-4, "PP_ERR_STATE")]:
+                       (-2, "PP_ERR_OOM"), (-3, "PP_ERR_HIP"), (-4, "PP_ERR_STATE"),
+                       (-5, "PP_ERR_TIMEOUT")]:
         assert B.pp_status_str(code) == name
 
 
