@@ -342,6 +342,20 @@ def run_batch256(args, B, W, torch, dev):
         times.append(time.perf_counter() - t1)
     tb = float(np.median(times))
     bst = B.pp_batch_get_stats(h)
+    # the same solve as one persistent launch (no host round trip, workgroup map fixed)
+    B.pp_batch_set_option(h, B.PP_BOPT_DRIVER, 1)
+    B.pcg_solve_batch(h, len(systems), 1, bd, X, args.tol, args.maxit)
+    ptimes = []
+    for _ in range(max(1, min(args.steps, 3))):
+        X.zero_()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        sp_, itp, relp, _ = B.pcg_solve_batch(h, len(systems), 1, bd, X, args.tol, args.maxit)
+        ptimes.append(time.perf_counter() - t1)
+    pst = B.pp_batch_get_stats(h)
+    persistent = dict(s_per_solve=float(np.median(ptimes)), iters_max=int(itp.max()), relres_max=float(relp.max()),
+                      verified=pst["verified"], status=B.pp_status_str(sp_), grid=pst["grid"],
+                      map_entries=bst["grid"])
     B.pp_destroy_batch(h)
     # plain FP64, one system at a time, same bounds and degree
     tseq = 0.0
@@ -362,8 +376,57 @@ def run_batch256(args, B, W, torch, dev):
                graph=bst["graph"], status=B.pp_status_str(s), fp64_sequential_s=tseq,
                speedup_vs_fp64_sequential=tseq / tb,
                driver="chunks of CG iterations captured once as a hipGraph and replayed; the host polls the "
-                      "done counter one chunk behind and redistributes workgroups of finished systems")
-    log("batch256: %.2f s batched vs %.2f s sequential FP64 (%.2fx)" % (tb, tseq, tseq / tb))
+                      "done counter one chunk behind and redistributes workgroups of finished systems",
+               persistent=persistent)
+    log("batch256: %.2f s batched vs %.2f s sequential FP64 (%.2fx); one persistent launch %.2f s (%d workgroups "
+        "over %d map entries)" % (tb, tseq, tseq / tb, persistent["s_per_solve"], persistent["grid"],
+                                  persistent["map_entries"]))
+    out["small_systems"] = run_batch_small(args, B, W, torch, dev)
+    return out
+
+
+def run_batch_small(args, B, W, torch, dev):
+    """Batches of 256 small heterogeneous systems (the uneven batch's generator), sides 4..8
+    (68 k rows: every phase a few microseconds of work) and 8..24 (1.3 M rows: bandwidth
+    bound again); host-driven chunks against one persistent launch, FP64, k = 20."""
+    return [batch_small_case(args, B, W, torch, dev, lo, hi, seed) for lo, hi, seed in ((4, 8, 7), (8, 24, 5))]
+
+
+def batch_small_case(args, B, W, torch, dev, smin, smax, seed):
+    sides = np.random.default_rng(seed).integers(smin, smax + 1, 256)
+    systems, rhs = [], []
+    for i, N in enumerate(sides):
+        a_i, b_i = W.batch_system(i, int(N))
+        systems.append(a_i)
+        rhs.append(b_i)
+    full, sp = W.block_diag(systems)
+    h = B.pp_create_batch(len(systems), sp, full.nnz, torch.from_numpy(full.rowptr).to(dev),
+                          torch.from_numpy(full.col).to(dev), torch.from_numpy(full.val).to(dev), 1, B.PP_JACOBI)
+    lo, hi = B.pp_batch_estimate_bounds(h, len(systems), 20)
+    k = 20
+    B.pp_batch_setup(h, k, lo, hi, 0.0)
+    bd = torch.from_numpy(np.concatenate(rhs)).to(dev).reshape(-1, 1)
+    X = torch.zeros_like(bd)
+    rec = {}
+    for name, drv in (("chunks", 0), ("persistent", 1)):
+        B.pp_batch_set_option(h, B.PP_BOPT_DRIVER, drv)
+        B.pcg_solve_batch(h, len(systems), 1, bd, X, args.tol, args.maxit)
+        ts = []
+        for _ in range(5):
+            X.zero_()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            s, it, rel, _ = B.pcg_solve_batch(h, len(systems), 1, bd, X, args.tol, args.maxit)
+            ts.append(time.perf_counter() - t1)
+        st = B.pp_batch_get_stats(h)
+        rec[name] = dict(s_per_solve=float(np.median(ts)), iters_max=int(it.max()), status=B.pp_status_str(s),
+                         grid=st["grid"])
+    B.pp_destroy_batch(h)
+    out = dict(workload="batch256_hetero_sides%d-%d" % (smin, smax), nsys=len(systems), n=int(sp[-1]), k=k,
+               dtype="f64", **rec)
+    log("batch256 sides %d..%d (n=%d): chunks %.2f ms, one persistent launch %.2f ms (%d workgroups), %d iterations "
+        "at most" % (smin, smax, int(sp[-1]), 1e3 * rec["chunks"]["s_per_solve"], 1e3 * rec["persistent"]["s_per_solve"],
+                     rec["persistent"]["grid"], rec["persistent"]["iters_max"]))
     return out
 
 

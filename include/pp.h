@@ -450,16 +450,26 @@ PP_API pp_status pp_batch_autotune(pp_batch op, int *best_w, double *best_us);
 /* Batch options: PP_OPT_CHUNK (iterations per graph), PP_OPT_NT_LOADS,
  * PP_OPT_VERIFY (as for pcg_solve: once every column has converged, the true
  * residuals are formed in FP64 and the columns that miss tol restart from
- * their iterates; -1 default = in PP_MIXED mode only), and
- * PP_BOPT_GRAPH (1 = replay captured iteration chunks, 0 = launch eagerly). */
-enum { PP_BOPT_GRAPH = 100 };
+ * their iterates; -1 default = in PP_MIXED mode only),
+ * PP_BOPT_GRAPH (1 = replay captured iteration chunks, 0 = launch eagerly),
+ * PP_BOPT_DRIVER (0 = iteration chunks driven from the host, which polls
+ * convergence one chunk behind and moves the workgroups of finished systems
+ * to the others; 1 = the whole solve in one persistent cooperative launch,
+ * with no host round trip, convergence decided on the device and the
+ * workgroup map fixed, for batches with one right-hand side per system --
+ * blocks of right-hand sides keep the host-driven chunks; PP_OPT_GRID caps
+ * its workgroups, 0 default = the resident ones, at most max(256, slices/8);
+ * PP_OPT_BARRIER and PP_OPT_SPIN_LIMIT as for a single operator, a timeout
+ * returning PP_ERR_TIMEOUT). */
+enum { PP_BOPT_GRAPH = 100, PP_BOPT_DRIVER = 101 };
 PP_API pp_status pp_batch_set_option(pp_batch op, int key, int64_t value);
 
 /* Sizes and last-solve timing: n rows, internal block width, entries in the
  * slice layout, workgroups per launch, solve device time (ms), the most
  * iterations of any (system, column), systems held as stored diagonals, CG
- * restarts after a failed true-residual check, and 1 when the check ran and
- * every column passed it (relres then holds the true residuals). */
+ * restarts after a failed true-residual check, 1 when the check ran and
+ * every column passed it (relres then holds the true residuals), and the
+ * driver of the last solve (grid: its workgroups). */
 typedef struct {
     int64_t n;
     int32_t nsys;
@@ -474,6 +484,7 @@ typedef struct {
     int32_t diag_systems;
     int32_t restarts;
     int32_t verified;
+    int32_t driver;  /* 1 when the last solve ran as one persistent launch */
 } pp_batch_stats;
 PP_API pp_status pp_batch_get_stats(pp_batch op, pp_batch_stats *st);
 

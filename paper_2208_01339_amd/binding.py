@@ -19,7 +19,7 @@ PP_JACOBI, PP_MIXED, PP_SLICED, PP_NO_REORDER = 1, 2, 4, 8
 PP_OPT_GRID, PP_OPT_CHUNK, PP_OPT_TIMING, PP_OPT_DRIVER, PP_OPT_NT_LOADS, PP_OPT_TWO_STEP, PP_OPT_VERIFY = 1, 2, 3, 4, 5, 6, 7
 PP_OPT_RITZ, PP_OPT_LDS_TILES, PP_OPT_BARRIER, PP_OPT_SPIN_LIMIT = 8, 9, 10, 11
 
-PP_BOPT_GRAPH = 100
+PP_BOPT_GRAPH, PP_BOPT_DRIVER = 100, 101
 
 ABI_FUNCTIONS = (
     "pp_create_csr", "pp_create_schur", "pp_setup", "pp_apply", "pcg_solve", "pp_estimate_bounds",
@@ -58,6 +58,7 @@ class pp_batch_stats(C.Structure):
         ("n", C.c_int64), ("nsys", C.c_int32), ("nb", C.c_int32), ("nrhs", C.c_int32), ("w", C.c_int32),
         ("nnz_stored", C.c_int64), ("grid", C.c_int32), ("graph", C.c_int32), ("solve_ms", C.c_double),
         ("max_iters", C.c_int32), ("diag_systems", C.c_int32), ("restarts", C.c_int32), ("verified", C.c_int32),
+        ("driver", C.c_int32),
     ]
 
 

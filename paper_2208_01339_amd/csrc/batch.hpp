@@ -131,18 +131,23 @@ __device__ __forceinline__ int logical_block() { return ppk::xcd_remap((int)bloc
 
 // Publish this workgroup's NB column partials (plain stores); kb_fin reduces them.
 template <int NB>
+__device__ __forceinline__ void store_seg(double *partials, const double *mine, int b)
+{
+    if (threadIdx.x < NB) partials[(size_t)b * NB + threadIdx.x] = mine[threadIdx.x];
+}
+
+template <int NB>
 __device__ __forceinline__ void store_seg(double *partials, const double *mine)
 {
-    if (threadIdx.x < NB) partials[(size_t)logical_block() * NB + threadIdx.x] = mine[threadIdx.x];
+    store_seg<NB>(partials, mine, logical_block());
 }
 
 // One workgroup per segment: sum the segment's workgroup partials per column
 // in workgroup order and run the scalar logic for its columns.
 template <int NB>
-__global__ __launch_bounds__(BLOCK) void kb_fin(Batch bt, BState st, const double *__restrict__ partials, int fin,
-                                                int idx)
+__device__ __forceinline__ void kbd_fin(int s, Batch bt, BState st, const double *__restrict__ partials, int fin,
+                                        int idx)
 {
-    const int s = blockIdx.x;
     if (fin < BF_LZN && st.seg_done[s]) return;
     __shared__ double lds[BLOCK + NB_MAX];
     constexpr int M = BLOCK / NB;
@@ -162,6 +167,13 @@ __global__ __launch_bounds__(BLOCK) void kb_fin(Batch bt, BState st, const doubl
         for (int cc = 0; cc < NB; ++cc)
             if (fin >= BF_LZN || cc < bt.nrhs) bfinalize(bt, st, fin, s, cc, lds[BLOCK + cc], idx);
     }
+}
+
+template <int NB>
+__global__ __launch_bounds__(BLOCK) void kb_fin(Batch bt, BState st, const double *__restrict__ partials, int fin,
+                                                int idx)
+{
+    kbd_fin<NB>(blockIdx.x, bt, st, partials, fin, idx);
 }
 
 // Workgroup sum of per-thread column partials: part[q] belongs to column
@@ -195,16 +207,17 @@ struct BlockRange {
     int64_t s0, s1, row_end;  // slice range and end of the segment's real rows
 };
 
-__device__ __forceinline__ BlockRange my_range(const Batch &bt)
+__device__ __forceinline__ BlockRange my_range(const Batch &bt, int b)
 {
     BlockRange r;
-    const int b = logical_block();
     r.seg = bt.blk_seg[b];
     r.s0 = bt.blk_s0[b];
     r.s1 = bt.blk_s1[b];
     r.row_end = bt.seg_row0[r.seg] + bt.seg_n[r.seg];
     return r;
 }
+
+__device__ __forceinline__ BlockRange my_range(const Batch &bt) { return my_range(bt, logical_block()); }
 
 template <typename T, int CPL>
 struct Vec {
@@ -369,8 +382,8 @@ __device__ __forceinline__ void spmm_any(const ppk::SellView &A, const Batch &bt
     }
 }
 
-#define PPB_PROLOGUE()                                  \
-    const BlockRange br = my_range(bt);                 \
+#define PPB_PROLOGUE_B(b)                               \
+    const BlockRange br = my_range(bt, b);              \
     if (st.seg_done[br.seg]) return;                    \
     const int lane = threadIdx.x & (WAVE - 1);          \
     const int c0 = (lane % W) * CPL;                    \
@@ -383,14 +396,14 @@ __device__ __forceinline__ void spmm_any(const ppk::SellView &A, const Batch &bt
 // Bh = dis .* B (caller layout [n_ext][nrhs] -> internal [rows][NB]), Xh = X ./ dis;
 // column sums of Bh.Bh -> BF_BNORM.  Padding rows and columns >= nrhs are zero.
 template <int W, int CPL>
-__global__ __launch_bounds__(BLOCK) void kb_init_scale(Batch bt, BState st, ppk::SellView A,
-                                                       const double *__restrict__ B, const double *__restrict__ X,
-                                                       const double *__restrict__ dis, double *__restrict__ Bh,
-                                                       double *__restrict__ Xh, double *partials)
+__device__ __forceinline__ void kbd_init_scale(int b, Batch bt, BState st, ppk::SellView A,
+                                               const double *__restrict__ B, const double *__restrict__ X,
+                                               const double *__restrict__ dis, double *__restrict__ Bh,
+                                               double *__restrict__ Xh, double *partials)
 {
     constexpr int NB = W * CPL;
     __shared__ double lds[BLOCK + NB_MAX * 2 + NB * WPB];
-    PPB_PROLOGUE()
+    PPB_PROLOGUE_B(b)
     double part[CPL] = {};
     const int64_t ext0 = bt.ext_row0[br.seg], row0 = bt.seg_row0[br.seg];
     for_rows<W, false>(A, br, [&](int64_t row, int rin, int64_t base, int width) {
@@ -409,18 +422,27 @@ __global__ __launch_bounds__(BLOCK) void kb_init_scale(Batch bt, BState st, ppk:
         }
     });
     block_colsum<W, CPL>(part, lds, lds + BLOCK + NB_MAX);
-    store_seg<NB>(partials, lds + BLOCK + NB_MAX);
+    store_seg<NB>(partials, lds + BLOCK + NB_MAX, b);
+}
+
+template <int W, int CPL>
+__global__ __launch_bounds__(BLOCK) void kb_init_scale(Batch bt, BState st, ppk::SellView A,
+                                                       const double *__restrict__ B, const double *__restrict__ X,
+                                                       const double *__restrict__ dis, double *__restrict__ Bh,
+                                                       double *__restrict__ Xh, double *partials)
+{
+    kbd_init_scale<W, CPL>(logical_block(), bt, st, A, B, X, dis, Bh, Xh, partials);
 }
 
 // R = Bh - A Xh -> BF_RR0 ; Q = A P -> BF_GAMMA (p.q) ; both FP64
 template <int W, int CPL, int WHICH, bool NT>
-__global__ __launch_bounds__(BLOCK) void kb_apply64(Batch bt, BState st, ppk::SellView A,
-                                                    const double *__restrict__ X, const double *__restrict__ Bh,
-                                                    double *__restrict__ Y, double *partials)
+__device__ __forceinline__ void kbd_apply64(int b, Batch bt, BState st, ppk::SellView A,
+                                            const double *__restrict__ X, const double *__restrict__ Bh,
+                                            double *__restrict__ Y, double *partials)
 {
     constexpr int NB = W * CPL;
     __shared__ double lds[BLOCK + NB_MAX * 2 + NB * WPB];
-    PPB_PROLOGUE()
+    PPB_PROLOGUE_B(b)
     double part[CPL] = {};
     with_seg_storage(bt, br.seg, [&](auto dk, auto spc) {
         constexpr int DK = decltype(dk)::value;
@@ -446,20 +468,28 @@ __global__ __launch_bounds__(BLOCK) void kb_apply64(Batch bt, BState st, ppk::Se
         });
     });
     block_colsum<W, CPL>(part, lds, lds + BLOCK + NB_MAX);
-    store_seg<NB>(partials, lds + BLOCK + NB_MAX);
+    store_seg<NB>(partials, lds + BLOCK + NB_MAX, b);
+}
+
+template <int W, int CPL, int WHICH, bool NT>
+__global__ __launch_bounds__(BLOCK) void kb_apply64(Batch bt, BState st, ppk::SellView A,
+                                                    const double *__restrict__ X, const double *__restrict__ Bh,
+                                                    double *__restrict__ Y, double *partials)
+{
+    kbd_apply64<W, CPL, WHICH, NT>(logical_block(), bt, st, A, X, Bh, Y, partials);
 }
 
 // One Chebyshev step on all columns (coefficients of the row's segment):
 //   OUT = cx X + cold SOLD + cr R + cA (A X).  LAST: R read in FP64, OUT FP64,
 //   column sums of R.OUT -> fin.  OUT may alias SOLD.
 template <typename T, typename RT, typename OT, int W, int CPL, int MODE, bool LAST, bool NT>
-__global__ __launch_bounds__(BLOCK) void kb_cheb(Batch bt, BState st, ppk::SellView A, const T *__restrict__ X,
-                                                 const RT *__restrict__ Rv, const T *SOLD, OT *OUT,
-                                                 const double *__restrict__ coef, int j, double *partials, int fin)
+__device__ __forceinline__ void kbd_cheb(int b, Batch bt, BState st, ppk::SellView A, const T *__restrict__ X,
+                                         const RT *__restrict__ Rv, const T *SOLD, OT *OUT,
+                                         const double *__restrict__ coef, int j, double *partials, int fin)
 {
     constexpr int NB = W * CPL;
     __shared__ double lds[BLOCK + NB_MAX * 2 + NB * WPB];
-    PPB_PROLOGUE()
+    PPB_PROLOGUE_B(b)
     const double *cf = coef + ((size_t)br.seg * bt.k + (j - 1)) * 4;
     const T ax = (T)cf[0], aold = (T)cf[1], ar = (T)cf[2], aA = (T)cf[3];
     double part[CPL] = {};
@@ -492,19 +522,27 @@ __global__ __launch_bounds__(BLOCK) void kb_cheb(Batch bt, BState st, ppk::SellV
     });
     if (LAST) {
         block_colsum<W, CPL>(part, lds, lds + BLOCK + NB_MAX);
-        store_seg<NB>(partials, lds + BLOCK + NB_MAX);
+        store_seg<NB>(partials, lds + BLOCK + NB_MAX, b);
     }
+}
+
+template <typename T, typename RT, typename OT, int W, int CPL, int MODE, bool LAST, bool NT>
+__global__ __launch_bounds__(BLOCK) void kb_cheb(Batch bt, BState st, ppk::SellView A, const T *__restrict__ X,
+                                                 const RT *__restrict__ Rv, const T *SOLD, OT *OUT,
+                                                 const double *__restrict__ coef, int j, double *partials, int fin)
+{
+    kbd_cheb<T, RT, OT, W, CPL, MODE, LAST, NT>(logical_block(), bt, st, A, X, Rv, SOLD, OUT, coef, j, partials, fin);
 }
 
 // Z = theta^-1 R (degree 0) with column sums of R.Z -> fin
 template <int W, int CPL>
-__global__ __launch_bounds__(BLOCK) void kb_deg0(Batch bt, BState st, ppk::SellView A, const double *__restrict__ Rv,
-                                                 double *__restrict__ Z, const double *__restrict__ thinv,
-                                                 double *partials, int fin)
+__device__ __forceinline__ void kbd_deg0(int b, Batch bt, BState st, ppk::SellView A, const double *__restrict__ Rv,
+                                         double *__restrict__ Z, const double *__restrict__ thinv,
+                                         double *partials, int fin)
 {
     constexpr int NB = W * CPL;
     __shared__ double lds[BLOCK + NB_MAX * 2 + NB * WPB];
-    PPB_PROLOGUE()
+    PPB_PROLOGUE_B(b)
     const double ti = thinv[br.seg];
     double part[CPL] = {};
     for_rows<W, false>(A, br, [&](int64_t row, int rin, int64_t base, int width) {
@@ -517,18 +555,26 @@ __global__ __launch_bounds__(BLOCK) void kb_deg0(Batch bt, BState st, ppk::SellV
         }
     });
     block_colsum<W, CPL>(part, lds, lds + BLOCK + NB_MAX);
-    store_seg<NB>(partials, lds + BLOCK + NB_MAX);
+    store_seg<NB>(partials, lds + BLOCK + NB_MAX, b);
+}
+
+template <int W, int CPL>
+__global__ __launch_bounds__(BLOCK) void kb_deg0(Batch bt, BState st, ppk::SellView A, const double *__restrict__ Rv,
+                                                 double *__restrict__ Z, const double *__restrict__ thinv,
+                                                 double *partials, int fin)
+{
+    kbd_deg0<W, CPL>(logical_block(), bt, st, A, Rv, Z, thinv, partials, fin);
 }
 
 // Xh += alpha P ; R -= alpha Q (frozen columns keep their values) -> BF_RR
 template <int W, int CPL>
-__global__ __launch_bounds__(BLOCK) void kb_xr(Batch bt, BState st, ppk::SellView A, const double *__restrict__ P,
-                                               const double *__restrict__ Q, double *__restrict__ Xh,
-                                               double *__restrict__ Rv, double *partials)
+__device__ __forceinline__ void kbd_xr(int b, Batch bt, BState st, ppk::SellView A, const double *__restrict__ P,
+                                       const double *__restrict__ Q, double *__restrict__ Xh,
+                                       double *__restrict__ Rv, double *partials)
 {
     constexpr int NB = W * CPL;
     __shared__ double lds[BLOCK + NB_MAX * 2 + NB * WPB];
-    PPB_PROLOGUE()
+    PPB_PROLOGUE_B(b)
     double al[CPL];
 #pragma unroll
     for (int q = 0; q < CPL; ++q) {
@@ -547,16 +593,24 @@ __global__ __launch_bounds__(BLOCK) void kb_xr(Batch bt, BState st, ppk::SellVie
         }
     });
     block_colsum<W, CPL>(part, lds, lds + BLOCK + NB_MAX);
-    store_seg<NB>(partials, lds + BLOCK + NB_MAX);
+    store_seg<NB>(partials, lds + BLOCK + NB_MAX, b);
+}
+
+template <int W, int CPL>
+__global__ __launch_bounds__(BLOCK) void kb_xr(Batch bt, BState st, ppk::SellView A, const double *__restrict__ P,
+                                               const double *__restrict__ Q, double *__restrict__ Xh,
+                                               double *__restrict__ Rv, double *partials)
+{
+    kbd_xr<W, CPL>(logical_block(), bt, st, A, P, Q, Xh, Rv, partials);
 }
 
 // P = Z + beta P (first: P = Z); frozen columns keep P
 template <int W, int CPL>
-__global__ __launch_bounds__(BLOCK) void kb_p(Batch bt, BState st, ppk::SellView A, const double *__restrict__ Z,
-                                              double *__restrict__ P, int first)
+__device__ __forceinline__ void kbd_p(int b, Batch bt, BState st, ppk::SellView A, const double *__restrict__ Z,
+                                      double *__restrict__ P, int first)
 {
     constexpr int NB = W * CPL;
-    PPB_PROLOGUE()
+    PPB_PROLOGUE_B(b)
     double be[CPL];
     bool fr[CPL];
 #pragma unroll
@@ -574,12 +628,19 @@ __global__ __launch_bounds__(BLOCK) void kb_p(Batch bt, BState st, ppk::SellView
     });
 }
 
+template <int W, int CPL>
+__global__ __launch_bounds__(BLOCK) void kb_p(Batch bt, BState st, ppk::SellView A, const double *__restrict__ Z,
+                                              double *__restrict__ P, int first)
+{
+    kbd_p<W, CPL>(logical_block(), bt, st, A, Z, P, first);
+}
+
 // R32 = (float) R
 template <int W, int CPL>
-__global__ __launch_bounds__(BLOCK) void kb_conv(Batch bt, BState st, ppk::SellView A, const double *__restrict__ Rv,
-                                                 float *__restrict__ R32)
+__device__ __forceinline__ void kbd_conv(int b, Batch bt, BState st, ppk::SellView A, const double *__restrict__ Rv,
+                                         float *__restrict__ R32)
 {
-    PPB_PROLOGUE()
+    PPB_PROLOGUE_B(b)
     constexpr int NB = W * CPL;
     for_rows<W, false>(A, br, [&](int64_t row, int rin, int64_t base, int width) {
 #pragma unroll
@@ -587,13 +648,20 @@ __global__ __launch_bounds__(BLOCK) void kb_conv(Batch bt, BState st, ppk::SellV
     });
 }
 
+template <int W, int CPL>
+__global__ __launch_bounds__(BLOCK) void kb_conv(Batch bt, BState st, ppk::SellView A, const double *__restrict__ Rv,
+                                                 float *__restrict__ R32)
+{
+    kbd_conv<W, CPL>(logical_block(), bt, st, A, Rv, R32);
+}
+
 // X (caller layout) = dis .* Xh (zero where b_hat == 0); runs for every segment
 template <int W, int CPL>
-__global__ __launch_bounds__(BLOCK) void kb_final(Batch bt, BState st, ppk::SellView A, const double *__restrict__ Xh,
-                                                  const double *__restrict__ dis, double *__restrict__ X)
+__device__ __forceinline__ void kbd_final(int b, Batch bt, BState st, ppk::SellView A, const double *__restrict__ Xh,
+                                          const double *__restrict__ dis, double *__restrict__ X)
 {
     constexpr int NB = W * CPL;
-    const BlockRange br = my_range(bt);
+    const BlockRange br = my_range(bt, b);
     const int lane = threadIdx.x & (WAVE - 1);
     const int c0 = (lane % W) * CPL;
     const int64_t ext0 = bt.ext_row0[br.seg], row0 = bt.seg_row0[br.seg];
@@ -607,6 +675,13 @@ __global__ __launch_bounds__(BLOCK) void kb_final(Batch bt, BState st, ppk::Sell
             if (c < bt.nrhs) X[er * bt.nrhs + c] = st.zero_b[br.seg * NB + c] ? 0.0 : d * Xh[row * NB + c];
         }
     });
+}
+
+template <int W, int CPL>
+__global__ __launch_bounds__(BLOCK) void kb_final(Batch bt, BState st, ppk::SellView A, const double *__restrict__ Xh,
+                                                  const double *__restrict__ dis, double *__restrict__ X)
+{
+    kbd_final<W, CPL>(logical_block(), bt, st, A, Xh, dis, X);
 }
 
 // reset the per-(segment, column) state before a solve or a Lanczos run

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "batch.hpp"
+#include "batch_persist.hpp"
 #include "common.hpp"
 #include "dia_plan.hpp"
 #include "sym_eig.hpp"
@@ -74,6 +75,13 @@ struct pp_batch_s {
     std::vector<double> lmin, lmax;
     // options
     int chunk = 0, ntload = 1, use_graph = 1;
+    int driver = 0;                    // 0: captured iteration chunks, host one chunk behind; 1: one persistent launch
+    int pgrid = 0;                     // workgroups of the persistent launch, 0 = all resident ones
+    int bar_mode = -1;                 // grid barrier of the persistent launch (PP_OPT_BARRIER)
+    unsigned int spin = 1u << 21;      // polls before a barrier wait gives up
+    unsigned long long *bw = nullptr;  // barrier words
+    unsigned long long h_abort = 0;
+    bool timed_out = false;
     int verify = -1;  // true-residual check at convergence: -1 auto (mixed mode), 0 off, 1 on
     // captured iteration chunk
     hipGraphExec_t gexec = nullptr;
@@ -138,7 +146,7 @@ struct pp_batch_s {
         dfree(sp); dfree(scol); dfree(sval); dfree(sval32); dfree(dis);
         dfree(seg_nd); dfree(seg_sell); dfree(seg_off); dfree(dv64); dfree(dv32);
         dfree(Xh); dfree(R); dfree(P); dfree(Q); dfree(Z); dfree(Bh); dfree(SA64); dfree(SB64);
-        dfree(R32); dfree(SA); dfree(SB); dfree(partials); dfree(coef_d); dfree(thinv_d);
+        dfree(R32); dfree(SA); dfree(SB); dfree(partials); dfree(coef_d); dfree(thinv_d); dfree(bw);
         dfree(d_rho); dfree(d_alpha); dfree(d_beta); dfree(d_rr); dfree(d_bn2); dfree(d_tol2); dfree(d_lz);
         dfree(d_it); dfree(d_status); dfree(d_done); dfree(d_zero_b); dfree(d_seg_ndone); dfree(d_seg_done);
         dfree(d_ndone); dfree(d_ticket);
@@ -742,6 +750,22 @@ pp_status pp_batch_set_option(pp_batch op, int key, int64_t value)
         return PP_OK;
     case PP_OPT_NT_LOADS: op->ntload = value != 0; op->g_k = -1; return PP_OK;
     case PP_BOPT_GRAPH: op->use_graph = value != 0; return PP_OK;
+    case PP_BOPT_DRIVER:
+        if (value < 0 || value > 1) return fail(PP_ERR_ARG, "PP_BOPT_DRIVER must be 0 or 1");
+        op->driver = (int)value;
+        return PP_OK;
+    case PP_OPT_GRID:
+        if (value < 0 || value > 8192) return fail(PP_ERR_ARG, "grid must be in [0, 8192]");
+        op->pgrid = (int)value;
+        return PP_OK;
+    case PP_OPT_BARRIER:
+        if (value < -1 || value > 2) return fail(PP_ERR_ARG, "PP_OPT_BARRIER must be -1, 0, 1 or 2");
+        op->bar_mode = (int)value;
+        return PP_OK;
+    case PP_OPT_SPIN_LIMIT:
+        if (value < 1 || value > (int64_t)1 << 31) return fail(PP_ERR_ARG, "PP_OPT_SPIN_LIMIT must be in [1, 2^31]");
+        op->spin = (unsigned int)value;
+        return PP_OK;
     case PP_OPT_VERIFY:
         if (value < -1 || value > 1) return fail(PP_ERR_ARG, "PP_OPT_VERIFY must be -1, 0 or 1");
         op->verify = (int)value;
@@ -865,8 +889,75 @@ namespace {
 // then chunks of iterations (a captured graph) until every column is done,
 // and X = D^{-1/2} X-hat.  check_only: stop after the initial test when it
 // ends every column (the true-residual check of a converged batch).
+// The whole pass in one cooperative launch (ppb::kbp_solve).  Returns false,
+// with nothing queued but the barrier reset, when the runtime refuses the
+// cooperative grid; the caller then drives the pass from the host.
+bool persistent_pass(pp_batch_s *op, const double *B, double *X, double tol, int maxit)
+{
+    // one right-hand side per system (internal block width 1) only: the
+    // multi-column layouts, inlined into one kernel, would spill
+    if (op->NB != 1 || op->W != 1 || op->CPL != 1) return false;
+    const void *fn = op->mixed() ? (const void *)ppb::kbp_solve<1, 1, true> : (const void *)ppb::kbp_solve<1, 1, false>;
+    int occ = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, BLOCK, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, op->device) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    // all resident workgroups while a phase has work for them (a slice per
+    // wave and more), else 256: the barrier's cost grows with the grid
+    // (256 systems of sides 4..8: 0.97 ms on 256 workgroups, 1.10 ms on 363;
+    // sides 8..24: 6.2 ms on 768, 8.6 ms on 256)
+    int G = std::min(op->G, std::max(0, occ) * std::max(0, cus));
+    G = (int)std::min<int64_t>(G, std::max<int64_t>(256, op->nslices / 8));
+    if (op->pgrid > 0) G = std::min(G, op->pgrid);
+    if (G < 1) return false;
+    if (!op->bw) op->bw = dalloc<unsigned long long>((size_t)ppk::GB_LINES * ppk::GB_LINE);
+    hipLaunchKernelGGL(ppk::k_zero_u64, dim3(1), dim3(BLOCK), 0, op->stream, op->bw,
+                       (int64_t)ppk::GB_LINES * ppk::GB_LINE);
+    ppb::BPArgs a;
+    a.bt = op->bt();
+    a.st = op->bst(tol, maxit);
+    a.A = op->view(false);
+    a.A32 = op->view(op->mixed());
+    a.B = B;
+    a.X = X;
+    a.dis = op->dis;
+    a.Bh = op->Bh; a.Xh = op->Xh; a.R = op->R; a.P = op->P; a.Q = op->Q; a.Z = op->Z;
+    a.SA64 = op->SA64; a.SB64 = op->SB64;
+    a.R32 = op->R32; a.SA = op->SA; a.SB = op->SB;
+    a.partials = op->partials;
+    a.coef = op->coef_d;
+    a.thinv = op->thinv_d;
+    a.nblk = op->G;
+    a.k = op->k;
+    a.maxit = maxit;
+    a.total = op->S * op->NB;
+    a.bw = op->bw;
+    a.bar_mode = op->bar_mode >= 0 ? op->bar_mode : (G < 32 ? 1 : 2);
+    a.spin = op->spin;
+    void *args[] = {&a};
+    if (hipLaunchCooperativeKernel(fn, dim3(G), dim3(BLOCK), args, 0, op->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    HIPCHK(hipMemcpyAsync(&op->h_abort, op->bw + (size_t)ppk::GB_ABORT * ppk::GB_LINE, sizeof(op->h_abort),
+                          hipMemcpyDeviceToHost, op->stream));
+    HIPCHK(hipStreamSynchronize(op->stream));
+    if (op->h_abort != 0) op->timed_out = true;
+    op->stats.grid = G;
+    op->stats.driver = 1;
+    return true;
+}
+
 void batch_pass(pp_batch_s *op, const double *B, double *X, double tol, int maxit, bool check_only)
 {
+    if (op->driver == 1) {
+        launch_state_init(op, tol, maxit);
+        if (persistent_pass(op, B, X, tol, maxit)) return;
+    }
+    op->stats.grid = op->G;
+    op->stats.driver = 0;
     const ppb::BState st = op->bst(tol, maxit);
     const ppb::Batch bt = op->bt();
     const dim3 g(op->G), b(BLOCK);
@@ -963,6 +1054,7 @@ pp_status pcg_solve_batch(pp_batch op, const double *B, double *X, double tol, i
     if (!op->setup_done) return fail(PP_ERR_STATE, "pp_batch_setup must be called before pcg_solve_batch");
     try {
         begin_call(op);
+        op->timed_out = false;
         HIPCHK(hipEventRecord(op->solve_ev[0], op->stream));
         // true-residual check at convergence (default: mixed mode only)
         const bool verify = op->verify > 0 || (op->verify < 0 && op->mixed());
@@ -995,6 +1087,7 @@ pp_status pcg_solve_batch(pp_batch op, const double *B, double *X, double tol, i
                     if (!zb[i] && stt[i] != PP_OK) all_ok = false;
                     if (!zb[i] && it[i] > 0) iterated = true;
                 }
+            if (op->timed_out) break;
             if (pass > 0 && !iterated) { verified = all_ok; break; }
             if (pass > 0) ++restarts;
             if (!(verify && all_ok && iterated && pass < 3)) break;
@@ -1021,6 +1114,8 @@ pp_status pcg_solve_batch(pp_batch op, const double *B, double *X, double tol, i
                 if (relres) relres[o] = zb[i] ? 0.0 : (bn[i] > 0 ? std::sqrt(rr[i] / bn[i]) : 0.0);
             }
         op->stats.max_iters = maxits;
+        if (op->timed_out)
+            return fail(PP_ERR_TIMEOUT, "a grid-barrier wait of the persistent batched solve gave up (PP_OPT_SPIN_LIMIT)");
         return worst;
     } catch (std::bad_alloc &) {
         return fail(PP_ERR_OOM, "device allocation failed");

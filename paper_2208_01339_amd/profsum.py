@@ -26,7 +26,8 @@ import statistics
 HERE = os.path.dirname(os.path.abspath(__file__))
 DIGEST_FILES = ("csrc/kernels.hpp", "csrc/op.hpp", "csrc/dfn.hpp", "csrc/common.hpp", "csrc/dia_plan.hpp",
                 "csrc/stencil2.hpp", "csrc/lowrank.hpp", "csrc/ltile.hpp", "csrc/reorder.hpp", "csrc/persistent.hpp",
-                "csrc/sym_eig.hpp", "csrc/pp_lib.hip", "csrc/batch.hpp", "csrc/pp_batch.hip", "build.py")
+                "csrc/sym_eig.hpp", "csrc/pp_lib.hip", "csrc/batch.hpp", "csrc/batch_persist.hpp", "csrc/pp_batch.hip",
+                "build.py")
 
 
 def _code_only(text: str) -> str:
