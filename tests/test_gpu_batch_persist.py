@@ -3,7 +3,9 @@
 The whole batched solve runs in one cooperative launch that sweeps the same
 workgroup map as the host-driven chunks, so with every member running the
 same number of iterations (no redistribution of workgroups on the host
-side) its iterates equal the host-driven ones bit for bit.  Against the
+side) its iterates equal the host-driven ones bit for bit; after tol-driven
+solves, where the host side redistributes, that still holds (the map is
+restored).  Against the
 oracle, as for the other batch tests: every system's iterate after m
 iterations within 1e-10 of its own oracle solve; tol-driven iteration
 counts within 2; mixed precision to an FP64 true residual <= 1e-8.  Eight
@@ -88,6 +90,10 @@ def test_persistent_batch_equal_iterations(B, small, layout):
 
 
 def test_persistent_batch_tol_driven(B, small):
+    """Members converge at different iterations (the host-driven solve then moves the
+    workgroups of finished systems to the others; the persistent launch keeps its map):
+    both within one iteration of each other, and a later equal-iteration solve on both
+    drivers still gives the same bits."""
     systems, ops, lo, hi = small
     k = 10
     bo = B.BatchOperator(systems, nrhs=1, flags=B.PP_JACOBI)
@@ -95,11 +101,20 @@ def test_persistent_batch_tol_driven(B, small):
     b = W.block_rhs(int(bo.sys_ptr[-1]), 1, 7)
     s, it, rel, stt, Xp, st = solve(B, bo, len(systems), 1, b, 1e-9, 500, 1)
     assert st["driver"] == 1 and s == B.PP_OK and np.all(stt == B.PP_OK) and np.all(rel <= 1e-9)
+    assert len(set(int(v) for v in it[:, 0])) > 1
     for i, o in enumerate(ops):
         r0, r1 = bo.sys_ptr[i], bo.sys_ptr[i + 1]
         xo, sto = O.pcg(o, k, lo[i], hi[i], 0.0, b[r0:r1, 0], tol=1e-9, maxit=500)
         assert abs(int(it[i, 0]) - sto["iters"]) <= 2
         assert np.linalg.norm(Xp[r0:r1, 0] - xo) / np.linalg.norm(xo) <= 1e-6
+    # the same tol-driven solve host-driven: the same iteration counts within one
+    s0, it0, rel0, stt0, Xg, st0 = solve(B, bo, len(systems), 1, b, 1e-9, 500, 0)
+    assert st0["driver"] == 0 and np.all(np.abs(it0 - it) <= 1) and np.all(rel0 <= 1e-9)
+    # map restored: equal-iteration solves agree bit for bit again
+    m = 6
+    _, itp, _, _, Xpm, _ = solve(B, bo, len(systems), 1, b, 0.0, m, 1)
+    _, itg, _, _, Xgm, _ = solve(B, bo, len(systems), 1, b, 0.0, m, 0)
+    assert np.all(itp == m) and np.array_equal(itp, itg) and np.array_equal(Xpm, Xgm)
     bo.close()
 
 
@@ -216,3 +231,17 @@ def test_persistent_batch_benchmark_subset(B):
     assert st0["driver"] == 0 and st0["grid"] > st["grid"]  # several map entries per workgroup
     assert np.array_equal(Xg, Xp)
     bo.close()
+    # mixed, tol-driven, as in the benchmark: members finish at different iterations
+    bm = B.BatchOperator(systems, nrhs=1, flags=B.PP_JACOBI | B.PP_MIXED)
+    B.pp_batch_setup(bm.handle, k, lo, hi, 0.0)
+    s, it, rel, stt, Xp, st = solve(B, bm, len(systems), 1, bvec, 1e-8, 500, 1)
+    assert st["driver"] == 1 and s == B.PP_OK and st["verified"] == 1
+    assert len(set(int(v) for v in it[:, 0])) > 1
+    for j, o in enumerate(ops):
+        r0, r1 = bm.sys_ptr[j], bm.sys_ptr[j + 1]
+        res = (o.apply_raw(Xp[r0:r1, 0]) - rhs[j]) * o.dis
+        true = np.linalg.norm(res) / np.linalg.norm(rhs[j] * o.dis)
+        assert true <= 1e-8, (pick[j], true)
+    s0, it0, _, _, _, _ = solve(B, bm, len(systems), 1, bvec, 1e-8, 500, 0)
+    assert np.all(np.abs(it0 - it) <= 1)
+    bm.close()
