@@ -12,10 +12,10 @@
 // The launch is cooperative, so the runtime refuses a grid that cannot be
 // co-resident instead of letting a barrier wait forever.
 //
-// Grid barriers.  The runtime's cooperative barrier makes every workgroup
-// write back its XCD's L2 and arrive on one counter that all of them poll;
-// its cost grows by about 0.1 us per workgroup.  Two hand-written barriers
-// replace it (the runtime's stays selectable, mode 0):
+// Grid barriers.  The runtime's cooperative barrier costs about 0.1 us per
+// workgroup (measured in a cooperative launch: 5.1 us at 32 workgroups, 104
+// us at 1024).  Two hand-written barriers replace it (the runtime's stays
+// selectable, mode 0):
 //   flat (mode 1): every workgroup writes back the L2 (agent-scope release),
 //     arrives on one counter and polls it until all G have arrived, then
 //     acquires (invalidates L2 and L1);
