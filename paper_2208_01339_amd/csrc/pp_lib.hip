@@ -770,10 +770,12 @@ void enqueue_newton(pp_op_s *op, const double *rr, double *zout, int fin, bool s
 
 // Steps j and j+1 (both three-term steps) in one pass of k_cheb2_stencil.
 // Tiles of a pair launch: y-tiles of S2_TY lines; z-chunks of 32 planes, or
-// 16 or 8.  A pair workgroup holds a whole CU, so the chunk is taken only if
-// the tiles fill whole rounds of CUs at least 90 % (256^3: 256 tiles of 32
+// 16.  A pair workgroup holds a whole CU, so the chunk is taken only if the
+// tiles fill whole rounds of CUs at least 90 % (256^3: 256 tiles of 32
 // planes); zc = 0 when none does (the one-step kernels are then faster:
-// 160^3 and 192^3 measured 25-30 % slower with a part-filled last round).
+// 160^3 and 192^3 measured 25-30 % slower with a part-filled last round, and
+// 128^3 on 8-plane chunks, whose recomputed halo planes add a quarter, 7-10 %
+// slower with full rounds).  Forced pairs (PP_OPT_TWO_STEP = 2) take 32.
 ppk::Stencil2 pair_shape(const pp_op_s *op)
 {
     ppk::Stencil2 g;
@@ -783,7 +785,7 @@ ppk::Stencil2 pair_shape(const pp_op_s *op)
     g.nty = (int)((g.N + ppk::S2_TY - 1) / ppk::S2_TY);
     g.zc = 0;
     const int64_t cus = op->cus;
-    for (int zc = ppk::S2_ZC_MAX; zc >= 8; zc /= 2) {
+    for (int zc = ppk::S2_ZC_MAX; zc >= 16; zc /= 2) {
         const int64_t nwg = (int64_t)g.nty * ((g.NZ + zc - 1) / zc);
         const int64_t rounds = (nwg + cus - 1) / cus;
         if (nwg >= cus && 10 * nwg >= 9 * rounds * cus) {

@@ -22,7 +22,7 @@ namespace ppk {
 
 constexpr int S2_TY = 8;              // y-rows per tile (full x-lines, one halo row each side)
 constexpr int S2_RY = S2_TY + 2;
-constexpr int S2_ZC_MAX = 32;         // z-planes per workgroup: 32, else 16 or 8 (enough workgroups)
+constexpr int S2_ZC_MAX = 32;         // z-planes per workgroup: 32, else 16 (enough workgroups)
 constexpr int64_t S2_NMAX = 256;      // widest x-line (sizes the per-thread register arrays)
 constexpr int S2_BS = 512;            // threads per workgroup
 constexpr bool S2_SL = true;          // in-plane neighbours of s_{j-1} from LDS
