@@ -18,6 +18,8 @@ holds only the kernels of that workload:
                    1100 traces), k = 31, scaling 1e-3
   batch256         256 uneven heterogeneous systems in one batched solve
                    (FP32 polynomial, FP64 CG), k = 60
+  batch256_persistent  the same batch, the whole solve in one persistent
+                   launch (PP_BOPT_DRIVER = 1)
   poisson32        Poisson 32^3, no scaling, k = 10, the default driver (one
                    persistent launch per solve at this size)
 
@@ -32,7 +34,8 @@ import time
 
 import numpy as np
 
-CASES = ("sliced256", "sliced256_plain", "irregular160", "dfn", "dfn_su", "batch256", "poisson32")
+CASES = ("sliced256", "sliced256_plain", "irregular160", "dfn", "dfn_su", "batch256", "batch256_persistent",
+         "poisson32")
 
 
 def _log(*a):
@@ -64,7 +67,7 @@ def main(argv=None):
         torch.cuda.synchronize()
         del src, dst
 
-    if args.case == "batch256":
+    if args.case in ("batch256", "batch256_persistent"):
         sides = W.batch_sizes()
         systems, rhs = zip(*(W.batch_system(i, int(N)) for i, N in enumerate(sides)))
         full, sp = W.block_diag(list(systems))
@@ -74,6 +77,8 @@ def main(argv=None):
         del full
         lo, hi = B.pp_batch_estimate_bounds(h, nsys, 20)
         B.pp_batch_setup(h, 60, lo, hi, 0.0)
+        if args.case == "batch256_persistent":
+            B.pp_batch_set_option(h, B.PP_BOPT_DRIVER, 1)
         bd = up(np.concatenate(rhs)).reshape(-1, 1)
         X = torch.zeros_like(bd)
         for i in range(args.solves):
@@ -81,8 +86,9 @@ def main(argv=None):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             s, it, _, _ = B.pcg_solve_batch(h, nsys, 1, bd, X, 1e-8, 5000)
-            _log("solve %d: status %s, iterations %d..%d, %.3f s" % (i, B.pp_status_str(s), it.min(), it.max(),
-                                                                     time.perf_counter() - t0))
+            _log("solve %d: status %s, iterations %d..%d, %.3f s, driver %d" % (
+                i, B.pp_status_str(s), it.min(), it.max(), time.perf_counter() - t0,
+                B.pp_batch_get_stats(h)["driver"]))
         B.pp_destroy_batch(h)
         return 0
 
